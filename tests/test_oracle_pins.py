@@ -1,0 +1,490 @@
+"""Pins of the FP64 oracle against closed forms, invariants, brute force,
+library routines and finite differences (CPU only).
+
+Nothing here calls the HIP path.  Each test names the passage of the paper
+whose statement it checks.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.linalg import expm
+from scipy.spatial.transform import Rotation
+
+import oracle
+from oracle import brute
+from paper_2601_00705_amd import scenes
+
+CFG = oracle.Config()
+SMOOTH = oracle.Config(alpha_min=0.0, T_min=0.0, alpha_max=1.0, dilation=0.3)
+
+
+def _one(mean, quat=(1, 0, 0, 0), log_scale=(0, 0, 0), logit=0.0, colour=(1, 0.5, 0.25)):
+    return {
+        "mean": np.array(mean, float).reshape(3, 1),
+        "quat": np.array(quat, float).reshape(4, 1),
+        "log_scale": np.array(log_scale, float).reshape(3, 1),
+        "opacity_logit": np.array([logit], float),
+        "colour": np.array(colour, float).reshape(3, 1),
+    }
+
+
+def _cat(*ps):
+    return {k: np.concatenate([p[k] for p in ps], axis=-1) for k in ps[0]}
+
+
+def _sig(x):
+    return 1.0 / (1.0 + math.exp(-x))
+
+
+CAM = {"width": 40, "height": 30, "fx": 50.0, "fy": 45.0, "cx": 20.0, "cy": 15.0}
+I12 = scenes.identity_pose()[None, :]
+
+
+# ---------------------------------------------------------------- P1 ----
+def test_single_on_axis_gaussian_closed_form():
+    """Eq. (proj) + Eq. (alpha) for one axis-aligned Gaussian on the optical
+    axis: C(p) = c o exp(-dx^2/(2 sx^2) - dy^2/(2 sy^2)), sx^2 = (fx s_x/z)^2 + eps."""
+    z, ls, lam = 3.0, (math.log(0.05), math.log(0.08), math.log(0.02)), 0.3
+    p = _one((0, 0, z), log_scale=ls, logit=lam)
+    out = oracle.render(p, [CAM], I12, CFG)
+    o = _sig(lam)
+    sx2 = (CAM["fx"] * math.exp(ls[0]) / z) ** 2 + CFG.dilation
+    sy2 = (CAM["fy"] * math.exp(ls[1]) / z) ** 2 + CFG.dilation
+    py, px = np.mgrid[0:30, 0:40] + 0.5
+    dx, dy = px - CAM["cx"], py - CAM["cy"]
+    G = np.exp(-0.5 * dx ** 2 / sx2 - 0.5 * dy ** 2 / sy2)
+    a = o * G
+    a = np.where(a >= CFG.alpha_min, a, 0.0)
+    rgb = oracle.split_views(out["rgb"], [CAM], 3)[0]
+    for c, col in enumerate((1, 0.5, 0.25)):
+        np.testing.assert_allclose(rgb[c], col * a, atol=1e-13)
+    np.testing.assert_allclose(out["T_final"].reshape(30, 40), 1 - a, atol=1e-13)
+
+    # analytic gradients of L = sum w * C_red
+    w = np.random.default_rng(0).normal(size=(30, 40))
+    dL = np.zeros((3, 30, 40))
+    dL[0] = w
+    g = oracle.backward(p, [CAM], I12, CFG, dL.ravel())
+    live = a > 0
+    np.testing.assert_allclose(g["colour"][0, 0], np.sum(w * a), rtol=1e-12)
+    np.testing.assert_allclose(g["opacity_logit"][0], np.sum(w * G * live) * o * (1 - o), rtol=1e-10)
+    fs = (CAM["fx"] * math.exp(ls[0]) / z) ** 2
+    np.testing.assert_allclose(g["log_scale"][0, 0], np.sum(w * a * dx ** 2 * fs / sx2 ** 2), rtol=1e-10)
+    # d u / d mu_x = fx / z; the EWA covariance is stationary on the axis
+    np.testing.assert_allclose(g["mean"][0, 0], np.sum(w * a * dx / sx2) * CAM["fx"] / z, rtol=1e-10)
+
+
+# ---------------------------------------------------------------- P2 ----
+def test_ewa_offaxis_isotropic_closed_form():
+    """Eq. (proj) for an isotropic Gaussian at (x, y, z) with equal focal
+    lengths: Sigma_I = (s f / z)^2 [[1 + x^2/z^2, x y/z^2], [x y/z^2, 1 + y^2/z^2]] + eps I."""
+    cam = dict(CAM, fy=CAM["fx"])
+    s = 0.07
+    for (x, y, z) in [(0.4, -0.3, 2.0), (-1.0, 0.7, 3.5), (0.0, 0.9, 1.1)]:
+        p = _one((x, y, z), log_scale=(math.log(s),) * 3, quat=(0.3, -0.5, 0.2, 0.7))
+        r = oracle.project(p, cam, I12[0], CFG)
+        k = (s * cam["fx"] / z) ** 2
+        np.testing.assert_allclose(r["cov_a"][0], k * (1 + x * x / z ** 2) + CFG.dilation, rtol=1e-12)
+        np.testing.assert_allclose(r["cov_b"][0], k * x * y / z ** 2, rtol=1e-12, atol=1e-12 * k)
+        np.testing.assert_allclose(r["cov_c"][0], k * (1 + y * y / z ** 2) + CFG.dilation, rtol=1e-12)
+        np.testing.assert_allclose(r["u"][0], cam["fx"] * x / z + cam["cx"], rtol=1e-14)
+
+
+def test_ewa_anisotropic_matches_linearised_projection():
+    """Eq. (proj) under a general pose: Sigma_I = J R Sigma_W R^T J^T with J the
+    first-order linearisation of the pinhole at mu_C (here by central
+    differences) and Sigma_W from scipy's quaternion rotation."""
+    rng = np.random.default_rng(3)
+    pose = scenes.left_perturb(scenes.identity_pose(), np.array([0.1, -0.2, 0.05, 0.3, -0.2, 0.1]))
+    R, t = pose[:9].reshape(3, 3), pose[9:]
+    for _ in range(5):
+        mw = rng.uniform([-0.5, -0.5, 2.0], [0.5, 0.5, 3.0])
+        q = rng.normal(size=4)
+        ls = rng.uniform(math.log(0.02), math.log(0.2), 3)
+        r = oracle.project(_one(mw, quat=q, log_scale=ls), CAM, pose, CFG)
+        mc = R @ mw + t
+
+        def pi(X):
+            return np.array([CAM["fx"] * X[0] / X[2] + CAM["cx"], CAM["fy"] * X[1] / X[2] + CAM["cy"]])
+
+        h = 1e-6
+        J = np.stack([(pi(mc + h * e) - pi(mc - h * e)) / (2 * h) for e in np.eye(3)], axis=1)
+        Rq = Rotation.from_quat(np.r_[q[1:], q[0]]).as_matrix()
+        Sw = Rq @ np.diag(np.exp(2 * ls)) @ Rq.T
+        S = J @ R @ Sw @ R.T @ J.T + CFG.dilation * np.eye(2)
+        np.testing.assert_allclose([r["cov_a"][0], r["cov_b"][0], r["cov_c"][0]],
+                                   [S[0, 0], S[0, 1], S[1, 1]], rtol=1e-7)
+        np.testing.assert_allclose(r["depth"][0], mc[2], rtol=1e-14)
+        np.testing.assert_allclose([r["u"][0], r["v"][0]], pi(mc), rtol=1e-13)
+        Sinv = np.linalg.inv(S)
+        np.testing.assert_allclose([r["A"][0], r["B"][0], r["C"][0]], [Sinv[0, 0], Sinv[0, 1], Sinv[1, 1]],
+                                   rtol=1e-7)
+
+
+# ---------------------------------------------------------------- P3 ----
+def _iso_alpha(p, i, cam, px, py):
+    z = p["mean"][2, i]
+    s = math.exp(p["log_scale"][0, i])
+    u = cam["fx"] * p["mean"][0, i] / z + cam["cx"]
+    v = cam["fy"] * p["mean"][1, i] / z + cam["cy"]
+    sx2 = (cam["fx"] * s / z) ** 2 + CFG.dilation
+    sy2 = (cam["fy"] * s / z) ** 2 + CFG.dilation
+    # exact only on the axis or for the off-diagonal-free case used below
+    a = _sig(p["opacity_logit"][i]) * np.exp(-0.5 * (px - u) ** 2 / sx2 - 0.5 * (py - v) ** 2 / sy2)
+    return np.where(a >= CFG.alpha_min, np.minimum(a, CFG.alpha_max), 0.0)
+
+
+def test_two_gaussians_compositing_closed_form():
+    """Eq. (alpha) with two Gaussians at distinct depths:
+    C = c1 a1 + c2 a2 (1 - a1), T = (1 - a1)(1 - a2); near one in front."""
+    near = _one((0, 0, 2.0), log_scale=(math.log(0.1),) * 3, logit=0.5, colour=(1, 0, 0))
+    far = _one((0, 0, 3.0), log_scale=(math.log(0.2),) * 3, logit=1.0, colour=(0, 1, 0.5))
+    py, px = np.mgrid[0:30, 0:40] + 0.5
+    a1 = _iso_alpha(near, 0, CAM, px, py)
+    a2 = _iso_alpha(far, 0, CAM, px, py)
+    for p in (_cat(near, far), _cat(far, near)):  # index order must not matter
+        out = oracle.render(p, [CAM], I12, CFG)
+        rgb = oracle.split_views(out["rgb"], [CAM], 3)[0]
+        np.testing.assert_allclose(rgb[0], a1, atol=1e-13)
+        np.testing.assert_allclose(rgb[1], a2 * (1 - a1), atol=1e-13)
+        np.testing.assert_allclose(rgb[2], 0.5 * a2 * (1 - a1), atol=1e-13)
+        np.testing.assert_allclose(out["T_final"].reshape(30, 40), (1 - a1) * (1 - a2), atol=1e-13)
+
+
+def test_equal_depth_ties_broken_by_index():
+    """Front-to-back order N(p) with equal depths: lower index composited first."""
+    g0 = _one((0, 0, 2.5), log_scale=(math.log(0.1),) * 3, logit=0.5, colour=(1, 0, 0))
+    g1 = _one((0, 0, 2.5), log_scale=(math.log(0.15),) * 3, logit=1.5, colour=(0, 1, 0))
+    py, px = np.mgrid[0:30, 0:40] + 0.5
+    for first, second in ((g0, g1), (g1, g0)):
+        out = oracle.render(_cat(first, second), [CAM], I12, CFG)
+        rgb = oracle.split_views(out["rgb"], [CAM], 3)[0]
+        a0 = _iso_alpha(first, 0, CAM, px, py)
+        a1 = _iso_alpha(second, 0, CAM, px, py)
+        c0 = first["colour"][:, 0]
+        c1 = second["colour"][:, 0]
+        for c in range(3):
+            np.testing.assert_allclose(rgb[c], c0[c] * a0 + c1[c] * a1 * (1 - a0), atol=1e-13)
+
+
+# ---------------------------------------------------------------- P4 ----
+def _small_scene(seed, n=12, sh_degree=-1, w=24, h=20):
+    p, cam = scenes.cloud(seed, n, w, h, 30.0, sh_degree=sh_degree)
+    p = {k: v.astype(np.float64) for k, v in p.items()}
+    return p, cam
+
+
+def test_compositing_invariants():
+    """Eq. (alpha): weights a_i T_i telescope to 1 - T_final (white colours,
+    black background give exactly 1 - T_final); T in [0, 1]; image linear in
+    colour; permutation of indices with distinct depths changes nothing."""
+    p, cam = _small_scene(5, n=40)
+    cams = [cam]
+    white = dict(p, colour=np.ones_like(p["colour"]))
+    out = oracle.render(white, cams, I12, CFG)
+    T = out["T_final"]
+    assert np.all(T >= 0) and np.all(T <= 1)
+    for c in range(3):
+        np.testing.assert_allclose(out["rgb"][c * T.size:(c + 1) * T.size], 1 - T, atol=1e-12)
+    assert np.all(out["rgb"] <= 1 + 1e-12)
+    # linearity in colour
+    rng = np.random.default_rng(1)
+    c1, c2 = rng.uniform(size=p["colour"].shape), rng.uniform(size=p["colour"].shape)
+    r1 = oracle.render(dict(p, colour=c1), cams, I12, CFG)["rgb"]
+    r2 = oracle.render(dict(p, colour=c2), cams, I12, CFG)["rgb"]
+    r12 = oracle.render(dict(p, colour=c1 + 2 * c2), cams, I12, CFG)["rgb"]
+    np.testing.assert_allclose(r12, r1 + 2 * r2, atol=1e-12)
+    # permutation invariance
+    perm = rng.permutation(p["opacity_logit"].shape[0])
+    pp = {k: v[..., perm] for k, v in p.items()}
+    a = oracle.render(p, cams, I12, CFG)
+    b = oracle.render(pp, cams, I12, CFG)
+    np.testing.assert_allclose(a["rgb"], b["rgb"], atol=1e-14)
+    np.testing.assert_array_equal(a["n_blend"], b["n_blend"])
+
+
+def test_transmittance_monotone_along_list():
+    """Each blended Gaussian multiplies T by (1 - alpha) in (0, 1]: rendering
+    with the first k Gaussians (by depth) gives a non-increasing T sequence."""
+    p, cam = _small_scene(8, n=25)
+    order = np.argsort(p["mean"][2])
+    prev = np.ones(cam["width"] * cam["height"])
+    cfg = oracle.Config(T_min=0.0)
+    for k in range(1, len(order) + 1):
+        sub = {kk: v[..., np.sort(order[:k])] for kk, v in p.items()}
+        T = oracle.render(sub, [cam], I12, cfg)["T_final"]
+        assert np.all(T <= prev + 1e-15)
+        prev = T
+
+
+# ---------------------------------------------------------------- P5 ----
+def _compose_quat(a, b):
+    w1, x1, y1, z1 = a
+    w2, x2, y2, z2 = b
+    return np.array([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                     w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+def test_rigid_motion_and_scale_invariance():
+    """Eq. (proj): moving Gaussians by G and the camera by T G^-1 leaves the
+    image unchanged; so does scaling means, translation, z_near by lam and
+    log-scales by + ln lam."""
+    p, cam = _small_scene(11, n=30)
+    cams = [cam]
+    pose = scenes.left_perturb(scenes.identity_pose(), np.array([0.05, 0.02, -0.1, 0.02, -0.03, 0.01]))
+    base = oracle.render(p, cams, pose[None], CFG)
+    qg = np.array([0.9, 0.2, -0.3, 0.1])
+    qg /= np.linalg.norm(qg)
+    Rg = Rotation.from_quat(np.r_[qg[1:], qg[0]]).as_matrix()
+    tg = np.array([0.3, -1.0, 2.0])
+    moved = dict(p)
+    moved["mean"] = Rg @ p["mean"] + tg[:, None]
+    moved["quat"] = np.stack([_compose_quat(qg, p["quat"][:, i]) for i in range(p["quat"].shape[1])], axis=1)
+    T = np.eye(4)
+    T[:3, :3] = pose[:9].reshape(3, 3)
+    T[:3, 3] = pose[9:]
+    G = np.eye(4)
+    G[:3, :3], G[:3, 3] = Rg, tg
+    T2 = T @ np.linalg.inv(G)
+    pose2 = np.concatenate([T2[:3, :3].ravel(), T2[:3, 3]])
+    out = oracle.render(moved, cams, pose2[None], CFG)
+    np.testing.assert_allclose(out["rgb"], base["rgb"], atol=1e-10)
+    np.testing.assert_array_equal(out["n_blend"], base["n_blend"])
+    lam = 2.7
+    scaled = dict(p, mean=p["mean"] * lam, log_scale=p["log_scale"] + math.log(lam))
+    pose3 = np.concatenate([pose[:9], pose[9:] * lam])
+    cfg3 = oracle.Config(z_near=CFG.z_near * lam)
+    out3 = oracle.render(scaled, cams, pose3[None], cfg3)
+    np.testing.assert_allclose(out3["rgb"], base["rgb"], atol=1e-10)
+
+
+def test_translation_gradient_identity():
+    """Eq. (muCjac), rho part: translating every Gaussian by d equals moving
+    the camera by R d, so sum_i dL/dmu_W,i = R^T dL/drho (RGB, one view)."""
+    p, cam = _small_scene(12, n=30)
+    pose = scenes.left_perturb(scenes.identity_pose(), np.array([0.0, 0.1, 0.0, 0.1, 0.0, -0.05]))
+    dL = scenes.upstream_grad(3, 3 * cam["width"] * cam["height"]).astype(np.float64)
+    g = oracle.backward(p, [cam], pose[None], CFG, dL)
+    R = pose[:9].reshape(3, 3)
+    np.testing.assert_allclose(g["mean"].sum(axis=1), R.T @ g["xi"][0, :3], rtol=1e-10, atol=1e-14)
+
+
+# ---------------------------------------------------------------- P6 ----
+@pytest.mark.parametrize("seed", [21, 22, 23])
+def test_tiled_equals_brute_force(seed):
+    """The tile lists are a pure acceleration of Eq. (alpha): an independent
+    per-pixel brute force over all Gaussians gives the same image, and the
+    image is the same for every tile size."""
+    p, cam = _small_scene(seed, n=16, w=24, h=20)
+    rgb_b, T_b, nb_b = brute.render(p, cam, I12[0], CFG)
+    outs = []
+    for tw, th in ((16, 16), (8, 8), (32, 8), (8, 16)):
+        cfg = oracle.Config(tile_w=tw, tile_h=th)
+        out = oracle.render(p, [cam], I12, cfg)
+        outs.append(out)
+        rgb = oracle.split_views(out["rgb"], [cam], 3)[0]
+        np.testing.assert_allclose(rgb, rgb_b, atol=1e-12)
+        np.testing.assert_allclose(out["T_final"].reshape(T_b.shape), T_b, atol=1e-12)
+        np.testing.assert_array_equal(out["n_blend"].reshape(nb_b.shape), nb_b)
+    for o in outs[1:]:
+        np.testing.assert_array_equal(o["rgb"], outs[0]["rgb"])
+
+
+def _bin_reference(cams, n, u, v, rx, ry, depth, tw, th):
+    """Python restatement of the binning contract on float32 values."""
+    f32 = np.float32
+    pairs = []
+    base = 0
+    for w, cam in enumerate(cams):
+        tx_n = (cam["width"] + tw - 1) // tw
+        ty_n = (cam["height"] + th - 1) // th
+        for i in range(n):
+            s = w * n + i
+            uu, vv, a, b, d = f32(u[s]), f32(v[s]), f32(rx[s]), f32(ry[s]), f32(depth[s])
+            if not (a >= 0 and b >= 0 and uu == uu and vv == vv and d > 0):
+                continue
+            x0 = np.floor(f32(uu - a) / f32(tw))
+            x1 = np.floor(f32(uu + a) / f32(tw))
+            y0 = np.floor(f32(vv - b) / f32(th))
+            y1 = np.floor(f32(vv + b) / f32(th))
+            if x1 < 0 or y1 < 0 or x0 > tx_n - 1 or y0 > ty_n - 1:
+                continue
+            bits = int(np.array([d], dtype=np.float32).view(np.uint32)[0])
+            for ty in range(int(max(y0, 0)), int(min(y1, ty_n - 1)) + 1):
+                for tx in range(int(max(x0, 0)), int(min(x1, tx_n - 1)) + 1):
+                    pairs.append((((base + ty * tx_n + tx) << 32) | bits, s))
+        base += tx_n * ty_n
+    pairs.sort()
+    return pairs, base
+
+
+def test_bin_contract_adversarial():
+    """Depth ordering of N(p) (Sec. Alpha Compositing for Color) as (tile,
+    depth-bits, slot) order on float32 records: equal depths, border rects,
+    empty and culled slots, NaN, a slot covering every tile, two views."""
+    cams = [{"width": 50, "height": 33}, {"width": 17, "height": 40}]
+    n = 60
+    rng = np.random.default_rng(0)
+    u = rng.uniform(-10, 60, 2 * n).astype(np.float32)
+    v = rng.uniform(-10, 45, 2 * n).astype(np.float32)
+    rx = rng.uniform(0, 12, 2 * n).astype(np.float32)
+    ry = rng.uniform(0, 12, 2 * n).astype(np.float32)
+    depth = rng.choice(np.array([1.0, 2.0, 2.5], np.float32), 2 * n)
+    u[0], rx[0] = 16.0, 0.0          # exactly on a tile edge
+    u[1], rx[1] = 25.0, 1e9           # covers every tile column
+    ry[1] = 1e9
+    rx[2] = -1.0                       # culled
+    u[3] = np.nan                      # invalid
+    depth[4] = 0.0                     # invalid
+    u[5], rx[5] = -5.0, 1.0            # entirely left of the image
+    u[6], v[6], rx[6], ry[6] = 49.99, 32.99, 0.0, 0.0  # last pixel
+    keys, vals, ranges = oracle.bin_f32(cams, n, u, v, rx, ry, depth, 16, 16)
+    ref, n_tiles = _bin_reference(cams, n, u, v, rx, ry, depth, 16, 16)
+    assert len(ref) == len(keys)
+    np.testing.assert_array_equal(keys, np.array([k for k, _ in ref], dtype=np.uint64))
+    np.testing.assert_array_equal(vals, np.array([s for _, s in ref], dtype=np.uint32))
+    assert ranges.shape == (n_tiles, 2)
+    tiles = keys >> np.uint64(32)
+    for t in range(n_tiles):
+        idx = np.nonzero(tiles == t)[0]
+        if idx.size:
+            assert ranges[t, 0] == idx[0] and ranges[t, 1] == idx[-1] + 1
+        else:
+            assert ranges[t, 0] == 0 and ranges[t, 1] == 0
+
+
+# ---------------------------------------------------------------- P7 ----
+def _loss(p, cams, poses, cfg, w_rgb, w_T):
+    out = oracle.render(p, cams, poses, cfg, want_margin=False)
+    return float(np.dot(out["rgb"], w_rgb) + np.dot(out["T_final"], w_T))
+
+
+def _fd_check(p, cams, poses, cfg, seed, pose_only=None, h=1e-6):
+    rng = np.random.default_rng(seed)
+    P = oracle.n_pixels(cams)
+    w_rgb = rng.normal(size=3 * P)
+    w_T = rng.normal(size=P)
+    g = oracle.backward(p, cams, poses, cfg, w_rgb, w_T, pose_only=pose_only)
+    for key in ("mean", "quat", "log_scale", "opacity_logit", "colour"):
+        flat = p[key].reshape(-1)
+        an = g[key].reshape(-1)
+        fd = np.zeros_like(an)
+        for j in range(flat.size):
+            pp = {k: v.copy() for k, v in p.items()}
+            pf = pp[key].reshape(-1)
+            pf[j] += h
+            lp = _loss(pp, cams, poses, cfg, w_rgb, w_T)
+            pf[j] -= 2 * h
+            lm = _loss(pp, cams, poses, cfg, w_rgb, w_T)
+            fd[j] = (lp - lm) / (2 * h)
+        scale = max(np.max(np.abs(an)), 1e-300)
+        err = np.max(np.abs(fd - an)) / scale
+        assert err < 1e-6, (key, err)
+    for v in range(len(cams)):
+        for k in range(6):
+            xs = []
+            for sgn in (1, -1):
+                xi = np.zeros(6)
+                xi[k] = sgn * h
+                P2 = np.array(poses, dtype=np.float64).copy()
+                P2[v] = scenes.left_perturb(P2[v], xi)
+                xs.append(_loss(p, cams, P2, cfg, w_rgb, w_T))
+            fd = (xs[0] - xs[1]) / (2 * h)
+            scale = max(np.max(np.abs(g["xi"][v])), 1e-300)
+            assert abs(fd - g["xi"][v, k]) / scale < 1e-6, (v, k, fd, g["xi"][v, k])
+
+
+def test_backward_matches_central_differences_rgb():
+    """Differentiability claim after Eq. (alpha) and Eqs. (muCjac)-(sigmaIjac):
+    the analytic gradient of every parameter and of the left twist equals
+    FP64 central differences in the smooth setting."""
+    p, cam = _small_scene(31, n=6, w=16, h=12)
+    pose = scenes.left_perturb(scenes.identity_pose(), np.array([0.02, -0.03, 0.1, 0.05, 0.02, -0.04]))
+    _fd_check(p, [cam], pose[None], SMOOTH, seed=1)
+
+
+def test_backward_matches_central_differences_sh3_two_views():
+    """Same, with degree-3 SH colour (Eq. app-sh; direction from the camera
+    centre) and two views, the second pose-only (no parameter gradient)."""
+    p, cam = _small_scene(32, n=4, w=12, h=10, sh_degree=3)
+    cams = [cam, dict(cam)]
+    poses = np.stack([
+        scenes.left_perturb(scenes.identity_pose(), np.array([0.02, -0.03, 0.1, 0.05, 0.02, -0.04])),
+        scenes.left_perturb(scenes.identity_pose(), np.array([-0.1, 0.05, 0.0, -0.02, 0.06, 0.03])),
+    ])
+    cfg = oracle.Config(alpha_min=0.0, T_min=0.0, alpha_max=1.0, sh_degree=3, bg=(0.1, 0.2, 0.3))
+    rng = np.random.default_rng(2)
+    P = oracle.n_pixels(cams)
+    w_rgb, w_T = rng.normal(size=3 * P), rng.normal(size=P)
+    # pose-only second view: parameter gradient equals that of view 0 alone
+    g_both = oracle.backward(p, cams, poses, cfg, w_rgb, w_T, pose_only=np.array([0, 1], np.uint8))
+    P0 = cam["width"] * cam["height"]
+    w_rgb0 = w_rgb[: 3 * P0]
+    g0 = oracle.backward(p, [cam], poses[:1], cfg, w_rgb0, w_T[:P0])
+    for k in ("mean", "quat", "log_scale", "opacity_logit", "colour"):
+        np.testing.assert_allclose(g_both[k], g0[k], rtol=1e-12, atol=1e-15)
+    _fd_check(p, cams, poses, cfg, seed=2)
+
+
+def test_backward_with_clamp_and_threshold_settings():
+    """With the default alpha_min / alpha_max / T_min decisions fixed, the
+    gradient still equals central differences away from the decision
+    boundaries (the decisions are piecewise constant)."""
+    p, cam = _small_scene(45, n=8, w=16, h=12)
+    p["opacity_logit"][:3] = 7.0          # opacity 0.9991: alpha clamps at alpha_max
+    p["log_scale"][:, :3] = math.log(0.3)
+    p["mean"][:2, :3] *= 0.3
+    cfg = oracle.Config(dilation=0.3)
+    out = oracle.render(p, [cam], I12, cfg)
+    assert np.sum(out["T_final"] < 0.0101) > 5, "some pixels must see a clamped alpha"
+    assert np.min(out["margin"]) > 1e-3, "choose a seed away from decision boundaries"
+    _fd_check(p, [cam], I12, cfg, seed=3, h=1e-6)
+
+
+# ---------------------------------------------------------------- P8 ----
+def _real_sh_scipy(l, m, d):
+    from scipy.special import sph_harm_y
+    theta = math.acos(max(-1.0, min(1.0, d[2])))
+    phi = math.atan2(d[1], d[0])
+    if m == 0:
+        return sph_harm_y(l, 0, theta, phi).real
+    Y = sph_harm_y(l, abs(m), theta, phi)
+    sgn = (-1) ** m
+    return math.sqrt(2) * sgn * (Y.real if m > 0 else Y.imag)
+
+
+def test_sh_basis_against_scipy_and_orthonormal():
+    """Eq. (app-sh): real spherical harmonics; the basis equals scipy's
+    (Condon-Shortley phase removed) and is orthonormal on the sphere."""
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        Y = oracle.sh_basis(3, d)
+        k = 0
+        for l in range(4):
+            for m in range(-l, l + 1):
+                assert abs(Y[k] - _real_sh_scipy(l, m, d)) < 1e-12, (l, m)
+                k += 1
+    # Gauss-Legendre in cos(theta) x uniform phi
+    xs, ws = np.polynomial.legendre.leggauss(12)
+    nphi = 24
+    G = np.zeros((16, 16))
+    for x, w in zip(xs, ws):
+        for j in range(nphi):
+            phi = 2 * math.pi * j / nphi
+            s = math.sqrt(1 - x * x)
+            Y = oracle.sh_basis(3, np.array([s * math.cos(phi), s * math.sin(phi), x]))
+            G += np.outer(Y, Y) * w * 2 * math.pi / nphi
+    np.testing.assert_allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_degree0_reduces_to_rgb():
+    """Eq. (app-sh) at degree 0: colour = k00 * Y00 for every view direction."""
+    p, cam = _small_scene(40, n=20)
+    y00 = 0.5 / math.sqrt(math.pi)
+    sh = dict(p, colour=(p["colour"] / y00)[None, :, :])
+    a = oracle.render(p, [cam], I12, CFG)
+    b = oracle.render(sh, [cam], I12, oracle.Config(sh_degree=0))
+    np.testing.assert_allclose(b["rgb"], a["rgb"], atol=1e-13)
