@@ -1,0 +1,186 @@
+/*
+ * gsr.h -- C ABI of libgsr, an MI355X (gfx950) differentiable tile-based
+ * 3D Gaussian-splatting rasterizer: the renderer that RGS-SLAM
+ * (arXiv 2601.00705) optimises during tracking and mapping.
+ *
+ * The operations follow the paper:
+ *   - gsr_project: Eq. (proj) of Sec. "Gaussian Splatting Representation":
+ *     mu_I = pi(R mu_W + t), Sigma_I = J R Sigma_W R^T J^T (J the pinhole
+ *     Jacobian at mu_C), with Sigma_W = R_q diag(s^2) R_q^T from a unit
+ *     quaternion and log-scales (appendix, Gaussian Splatting
+ *     Representation) and colour as RGB or real SH, Eq. (app-sh).
+ *   - gsr_bin: the front-to-back ordered sets N(p) of Eq. (alpha) ("sorted
+ *     from near to far", Sec. Alpha Compositing for Color), built per tile.
+ *   - gsr_render_fwd: alpha compositing, Eq. (alpha).
+ *   - gsr_loss_l1: the gradient seed of the L1 photometric residual,
+ *     Eq. (photometric).
+ *   - gsr_render_bwd: gradients for colour, opacity, mean, covariance
+ *     parameters (the differentiability statement after Eq. (alpha)) and for
+ *     the pose twist of Eq. (leftupdate), via Eqs. (muCjac), (muIjac),
+ *     (sigmaIjac).
+ *
+ * Conventions (readings where the paper is silent):
+ *   - pose: world-to-camera [R | t], 12 floats per view, R row-major then t;
+ *     x_c = R x_w + t.
+ *   - pose tangent xi = (rho, omega): T(xi) = exp(xi^) T, xi^ = [[omega]x rho;
+ *     0 0]; gradients are taken at xi = 0.
+ *   - pixel (px, py) is sampled at (px + 1/2, py + 1/2); the 2-D Gaussian is
+ *     unnormalised (peak 1); Sigma_I gets + dilation * I.
+ *   - alpha = min(alpha_max, o exp(-d^T Sigma_I^-1 d / 2)), o = sigmoid(logit);
+ *     entries with alpha < alpha_min are skipped; compositing stops before an
+ *     entry that would take the transmittance below T_min; output colour is
+ *     C + T_final * bg.
+ *   - ordering: camera-space depth z ascending, ties by Gaussian index.
+ *   - SH: real basis without Condon-Shortley phase, index l*l + l + m, at the
+ *     unit direction from the camera centre (-R^T t) to the world mean.
+ *
+ * Memory: every array argument is a DEVICE pointer owned by the caller
+ * unless stated otherwise.  Parameter planes are structure-of-arrays:
+ * mean [3][n], quat [4][n] (w, x, y, z, any non-zero norm), log_scale [3][n],
+ * opacity_logit [n], colour [3][n] (RGB) or [K][3][n] (SH, K = (d+1)^2).
+ * Images of the views are concatenated in view order; view v occupies
+ * 3 * H_v * W_v floats laid out [3][H_v][W_v] (rgb, dL_drgb) or H_v * W_v
+ * values [H_v][W_v] (T_final, n_contrib, n_blend, dL_dT).
+ *
+ * The library allocates no device memory and never synchronises, except
+ * gsr_plan_bind and gsr_pair_count, which say so.  All work is enqueued on the
+ * given stream (a hipStream_t; NULL = the null stream).  Calls on different
+ * plans are independent; calls on one plan must be ordered by the caller.
+ */
+#ifndef GSR_H
+#define GSR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GSR_MAX_VIEWS 64
+
+typedef enum {
+    GSR_OK = 0,
+    GSR_EINVAL = -1,       /* invalid argument; nothing was enqueued */
+    GSR_ECAPACITY = -2,    /* pair capacity exceeded (see gsr_pair_count) */
+    GSR_EHIP = -3,         /* a HIP runtime call or kernel launch failed */
+    GSR_EUNSUPPORTED = -4, /* valid but unsupported configuration */
+    GSR_ESTATE = -5        /* plan not bound to a workspace */
+} gsr_status;
+
+/* Pinhole camera of one view (host struct). */
+typedef struct {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+} gsr_camera;
+
+/* Renderer settings (host struct). */
+typedef struct {
+    int32_t tile_w, tile_h; /* powers of two; tile_w * tile_h in {64, 128, 256} */
+    int32_t batch;          /* reserved, 0 (the LDS batch equals the tile pixel count) */
+    int32_t sh_degree;      /* -1: RGB colour; 0..3: SH degree */
+    float z_near;           /* cull mu_C.z <= z_near */
+    float dilation;         /* eps added to the diagonal of Sigma_I (px^2) */
+    float alpha_min;        /* skip threshold (0 disables it and the extent cull) */
+    float alpha_max;        /* upper clamp, in (0, 1] */
+    float T_min;            /* early-stop transmittance (0 disables it) */
+    float bg[3];            /* background colour weighted by T_final */
+} gsr_config;
+
+/* Gaussian parameters (device planes, see above). */
+typedef struct {
+    int64_t n;
+    const float *mean, *quat, *log_scale, *opacity_logit, *colour;
+} gsr_gaussians;
+
+/* Parameter gradients (device planes with the shapes of gsr_gaussians).
+ * Written, not accumulated; summed over the views that are not pose-only. */
+typedef struct {
+    float *d_mean, *d_quat, *d_log_scale, *d_opacity_logit, *d_colour;
+} gsr_grads;
+
+/* Byte offsets of the planes inside a bound workspace. */
+typedef struct {
+    size_t counters;  /* struct { uint64 pairs; uint32 overflow; ... } */
+    size_t geom;      /* float4 [V*n]: (u, v, rx, ry); rx < 0 = culled */
+    size_t conic_o;   /* float4 [V*n]: (A, B, C, o), A = (Sigma_I^-1)_00 ... */
+    size_t rgb_d;     /* float4 [V*n]: (r, g, b, depth) */
+    size_t grad2d;    /* float [9][V*n]: d(u, v, A, B, C, o, r, g, b) */
+    size_t keys;      /* uint64 [capacity]: sorted (tile << 32 | depth bits) */
+    size_t vals;      /* uint32 [capacity]: sorted slot = view * n + index */
+    size_t ranges;    /* uint32 [tiles][2]: [first, last + 1) per global tile */
+    size_t total;     /* workspace bytes */
+} gsr_layout;
+
+/* Sizes derived by a plan (host struct). */
+typedef struct {
+    int64_t n, slots, capacity, total_pixels;
+    int32_t n_views, total_tiles, sort_passes, tile_bits;
+} gsr_plan_info;
+
+typedef struct gsr_plan gsr_plan; /* opaque host object */
+
+/* Creates a plan for n Gaussians rendered into n_views (1..GSR_MAX_VIEWS)
+ * views.  cams: host array [n_views].  pair_capacity: maximum number of
+ * (tile, Gaussian) pairs one binning may produce (< 2^32); the workspace
+ * holds two key/value buffers of that size.  Requires n * n_views < 2^32.
+ * Returns GSR_EINVAL on invalid arguments. */
+gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_camera *cams, const gsr_config *cfg,
+                           int64_t pair_capacity, gsr_plan **out);
+void gsr_plan_destroy(gsr_plan *plan);
+
+/* Workspace bytes the plan needs (256-byte aligned device memory). */
+size_t gsr_plan_workspace_bytes(const gsr_plan *plan);
+
+/* Binds a caller-owned device workspace of at least gsr_plan_workspace_bytes
+ * bytes, uploads the view table and capacity into it, and synchronises
+ * `stream` once.  The workspace must stay alive while the plan is used. */
+gsr_status gsr_plan_bind(gsr_plan *plan, void *workspace, size_t bytes, void *stream);
+
+gsr_status gsr_plan_layout(const gsr_plan *plan, gsr_layout *out);
+gsr_status gsr_plan_get_info(const gsr_plan *plan, gsr_plan_info *out);
+
+/* Eq. (proj): projects every Gaussian into every view (poses: device
+ * [n_views][12]).  Writes the geom / conic_o / rgb_d records and clears the
+ * screen-space gradient accumulators of live slots. */
+gsr_status gsr_project(gsr_plan *plan, const gsr_gaussians *g, const float *poses, void *stream);
+
+/* Builds the depth-ordered per-tile lists from the geom / rgb_d records:
+ * pair emission, stable LSD radix sort of (tile | depth) keys with slot
+ * values, tile ranges.  When the pair count exceeds the capacity, a device
+ * flag is set, no pair is written, gsr_render_fwd writes NaN images and
+ * gsr_render_bwd writes NaN gradients; gsr_pair_count reports it. */
+gsr_status gsr_bin(gsr_plan *plan, void *stream);
+
+/* Eq. (alpha) for every view.  rgb, T_final, n_contrib required; n_blend
+ * (number of blended entries per pixel) may be NULL.  n_contrib is the list
+ * position + 1 of the last blended entry of the pixel's tile list; it is
+ * what gsr_render_bwd replays. */
+gsr_status gsr_render_fwd(gsr_plan *plan, float *rgb, float *T_final, int32_t *n_contrib, int32_t *n_blend,
+                          void *stream);
+
+/* Gradient of the mean absolute photometric error, Eq. (photometric):
+ * dL_drgb = sign(rgb - target) / (3 * total pixels), sign(0) = 0. */
+gsr_status gsr_loss_l1(gsr_plan *plan, const float *rgb, const float *target, float *dL_drgb, void *stream);
+
+/* Backward of gsr_render_fwd (call after it, on the same plan, without an
+ * intervening gsr_project).  dL_dT may be NULL (zero).  pose_only: HOST array
+ * [n_views] of 0/1 or NULL; views flagged 1 contribute to d_xi only.  grads
+ * may be NULL (pose gradients only); d_xi: device [n_views][6] or NULL.
+ * g and poses must be the values given to gsr_project. */
+gsr_status gsr_render_bwd(gsr_plan *plan, const gsr_gaussians *g, const float *poses, const float *dL_drgb,
+                          const float *dL_dT, const uint8_t *pose_only, gsr_grads *grads, float *d_xi,
+                          void *stream);
+
+/* Synchronises `stream`, then reports the pair count of the last binning
+ * and whether it exceeded the capacity. */
+gsr_status gsr_pair_count(gsr_plan *plan, int64_t *required, int32_t *overflow, void *stream);
+
+const char *gsr_status_str(gsr_status s);
+/* Detail of the last failure on the calling thread ("" if none). */
+const char *gsr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSR_H */

@@ -677,7 +677,8 @@ int or_backward(const or_scene *sc, int32_t n_views, const or_camera *cams, cons
 /* binning contract in float32                                               */
 
 /* Binning of already-projected float32 records into (tile | depth) keys.
- * A slot is live iff rx >= 0, ry >= 0, u and v are not NaN and depth > 0.
+ * A slot is live iff rx >= 0, ry >= 0 and u and v are not NaN; the depth is
+ * only a sort key (its raw float32 bit pattern).
  * Its rectangle is computed with single-precision IEEE operations only:
  *   x0 = floor((u - rx) / tile_w), x1 = floor((u + rx) / tile_w)  (same in y),
  * empty if x1 < 0, y1 < 0, x0 > tiles_x - 1 or y0 > tiles_y - 1, otherwise
@@ -712,8 +713,8 @@ int64_t or_bin_f32(int32_t n_views, const int32_t *widths, const int32_t *height
         int tiles_x = (widths[w] + tile_w - 1) / tile_w, tiles_y = (heights[w] + tile_h - 1) / tile_h;
         for (int64_t i = 0; i < n; ++i) {
             int64_t s = (int64_t)w * n + i;
-            float uu = u[s], vv = v[s], rxx = rx[s], ryy = ry[s], dd = depth[s];
-            if (!(rxx >= 0.0f) || !(ryy >= 0.0f) || uu != uu || vv != vv || !(dd > 0.0f)) continue;
+            float uu = u[s], vv = v[s], rxx = rx[s], ryy = ry[s];
+            if (!(rxx >= 0.0f) || !(ryy >= 0.0f) || uu != uu || vv != vv) continue;
             float x0 = floorf((uu - rxx) / (float)tile_w), x1 = floorf((uu + rxx) / (float)tile_w);
             float y0 = floorf((vv - ryy) / (float)tile_h), y1 = floorf((vv + ryy) / (float)tile_h);
             if (x1 < 0.0f || y1 < 0.0f || x0 > (float)(tiles_x - 1) || y0 > (float)(tiles_y - 1)) continue;
@@ -732,7 +733,7 @@ int64_t or_bin_f32(int32_t n_views, const int32_t *widths, const int32_t *height
         for (int64_t i = 0; i < n; ++i) {
             int64_t s = (int64_t)w * n + i;
             float uu = u[s], vv = v[s], rxx = rx[s], ryy = ry[s], dd = depth[s];
-            if (!(rxx >= 0.0f) || !(ryy >= 0.0f) || uu != uu || vv != vv || !(dd > 0.0f)) continue;
+            if (!(rxx >= 0.0f) || !(ryy >= 0.0f) || uu != uu || vv != vv) continue;
             float x0 = floorf((uu - rxx) / (float)tile_w), x1 = floorf((uu + rxx) / (float)tile_w);
             float y0 = floorf((vv - ryy) / (float)tile_h), y1 = floorf((vv + ryy) / (float)tile_h);
             if (x1 < 0.0f || y1 < 0.0f || x0 > (float)(tiles_x - 1) || y0 > (float)(tiles_y - 1)) continue;

@@ -1,0 +1,449 @@
+// gsr_api.cpp -- host side of the C ABI declared in include/gsr.h.
+//
+// A plan carries the host-known sizes (views, tiles, capacity, sort passes)
+// and the layout of the caller's workspace; launches are enqueued on the
+// caller's stream.  Kernel launch shapes depend only on the plan, never on
+// device-side counts, so a call sequence can be captured into a HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "gsr.h"
+#include "kernels.h"
+
+using namespace gsr;
+
+static thread_local std::string g_err;
+
+static gsr_status fail(gsr_status s, const char* what)
+{
+    g_err = what;
+    return s;
+}
+
+static gsr_status hip_fail(hipError_t e, const char* where)
+{
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return GSR_EHIP;
+}
+
+struct gsr_plan {
+    int64_t n = 0;
+    int32_t V = 0;
+    gsr_config cfg{};
+    DevCfg dcfg{};
+    ViewTable vt{};
+    int64_t capacity = 0;
+    int64_t total_pixels = 0;
+    int32_t total_tiles = 0, tile_bits = 0, passes = 0, chunks = 0;
+    int32_t sort_max_blocks = 0, sort_grid = 0, bwd_blocks = 0;
+    size_t off_counters = 0, off_views = 0, off_geom = 0, off_conic = 0, off_rgbd = 0, off_grad2d = 0;
+    size_t off_keys0 = 0, off_keys1 = 0, off_vals0 = 0, off_vals1 = 0, off_ranges = 0, off_hist = 0;
+    size_t off_dtotal = 0, off_bsums = 0, off_boffs = 0, off_xip = 0, total = 0;
+    char* ws = nullptr;
+    Counters host_counters{};
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static bool pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+static int ilog2(int x)
+{
+    int r = 0;
+    while ((1 << r) < x) ++r;
+    return r;
+}
+
+extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_camera* cams, const gsr_config* cfg,
+                                      int64_t pair_capacity, gsr_plan** out)
+{
+    g_err.clear();
+    if (!out || !cams || !cfg) return fail(GSR_EINVAL, "null argument");
+    *out = nullptr;
+    if (n < 0) return fail(GSR_EINVAL, "n < 0");
+    if (n_views < 1 || n_views > GSR_MAX_VIEWS) return fail(GSR_EINVAL, "n_views out of range");
+    if ((uint64_t)n * (uint64_t)n_views >= (1ull << 32)) return fail(GSR_EINVAL, "n * n_views >= 2^32");
+    if (pair_capacity < 0 || pair_capacity >= (int64_t)(1ull << 32))
+        return fail(GSR_EINVAL, "pair_capacity out of range");
+    if (!pow2(cfg->tile_w) || !pow2(cfg->tile_h)) return fail(GSR_EINVAL, "tile sizes must be powers of two");
+    int tpx = cfg->tile_w * cfg->tile_h;
+    if (tpx != 64 && tpx != 128 && tpx != 256) return fail(GSR_EUNSUPPORTED, "tile pixel count not in {64,128,256}");
+    if (cfg->batch != 0 && cfg->batch != tpx) return fail(GSR_EUNSUPPORTED, "batch must be 0 or the tile pixel count");
+    if (cfg->sh_degree < -1 || cfg->sh_degree > 3) return fail(GSR_EINVAL, "sh_degree not in -1..3");
+    if (!(cfg->alpha_min >= 0.0f) || !(cfg->alpha_max > 0.0f) || !(cfg->alpha_max <= 1.0f) ||
+        !(cfg->alpha_min <= cfg->alpha_max))
+        return fail(GSR_EINVAL, "alpha bounds");
+    if (!(cfg->T_min >= 0.0f) || !(cfg->T_min < 1.0f)) return fail(GSR_EINVAL, "T_min");
+    if (!(cfg->dilation >= 0.0f) || !std::isfinite(cfg->z_near)) return fail(GSR_EINVAL, "dilation / z_near");
+
+    gsr_plan* p = new (std::nothrow) gsr_plan();
+    if (!p) return fail(GSR_EINVAL, "out of host memory");
+    p->n = n;
+    p->V = n_views;
+    p->cfg = *cfg;
+    p->capacity = pair_capacity;
+    p->dcfg.tile_w = cfg->tile_w;
+    p->dcfg.tile_h = cfg->tile_h;
+    p->dcfg.log2_tw = ilog2(cfg->tile_w);
+    p->dcfg.log2_th = ilog2(cfg->tile_h);
+    p->dcfg.sh_degree = cfg->sh_degree;
+    p->dcfg.z_near = cfg->z_near;
+    p->dcfg.dilation = cfg->dilation;
+    p->dcfg.alpha_min = cfg->alpha_min;
+    p->dcfg.alpha_max = cfg->alpha_max;
+    p->dcfg.T_min = cfg->T_min;
+    p->dcfg.bg0 = cfg->bg[0];
+    p->dcfg.bg1 = cfg->bg[1];
+    p->dcfg.bg2 = cfg->bg[2];
+    int64_t tiles = 0, pix = 0;
+    p->vt.n = n_views;
+    for (int v = 0; v < n_views; ++v) {
+        const gsr_camera& c = cams[v];
+        if (c.width <= 0 || c.height <= 0 || c.width > 65536 || c.height > 65536 ||
+            !std::isfinite(c.fx) || !std::isfinite(c.fy) || !std::isfinite(c.cx) || !std::isfinite(c.cy)) {
+            delete p;
+            return fail(GSR_EINVAL, "camera");
+        }
+        ViewInfo& vi = p->vt.v[v];
+        vi.width = c.width;
+        vi.height = c.height;
+        vi.tiles_x = (c.width + cfg->tile_w - 1) / cfg->tile_w;
+        vi.tiles_y = (c.height + cfg->tile_h - 1) / cfg->tile_h;
+        vi.tile_base = (int32_t)tiles;
+        vi.pix_base = (int32_t)pix;
+        vi.fx = c.fx;
+        vi.fy = c.fy;
+        vi.cx = c.cx;
+        vi.cy = c.cy;
+        tiles += (int64_t)vi.tiles_x * vi.tiles_y;
+        pix += (int64_t)c.width * c.height;
+        if (tiles >= (1ll << 31) || 3 * pix >= (1ll << 31)) {
+            delete p;
+            return fail(GSR_EINVAL, "too many tiles or pixels");
+        }
+    }
+    p->vt.total_tiles = (int32_t)tiles;
+    p->total_tiles = (int32_t)tiles;
+    p->total_pixels = pix;
+    p->tile_bits = tiles > 1 ? ilog2((int)tiles) : 0;
+    p->passes = (32 + p->tile_bits + 7) / 8;
+    p->chunks = (int32_t)((n + GSR_BIN_CHUNK - 1) / GSR_BIN_CHUNK);
+    if (p->chunks == 0) p->chunks = 1;
+    p->sort_max_blocks = (int32_t)((pair_capacity + GSR_SORT_ITEMS - 1) / GSR_SORT_ITEMS);
+    if (p->sort_max_blocks == 0) p->sort_max_blocks = 1;
+    p->sort_grid = p->sort_max_blocks < 2048 ? p->sort_max_blocks : 2048;
+    p->bwd_blocks = (int32_t)((n + 255) / 256);
+    if (p->bwd_blocks == 0) p->bwd_blocks = 1;
+
+    const int64_t S = n * n_views;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + (bytes ? bytes : 1));
+        return at;
+    };
+    p->off_counters = take(sizeof(Counters));
+    p->off_views = take(sizeof(ViewTable));
+    p->off_geom = take(sizeof(float4) * S);
+    p->off_conic = take(sizeof(float4) * S);
+    p->off_rgbd = take(sizeof(float4) * S);
+    p->off_grad2d = take(sizeof(float) * GSR_G2 * S);
+    p->off_keys0 = take(sizeof(unsigned long long) * pair_capacity);
+    p->off_keys1 = take(sizeof(unsigned long long) * pair_capacity);
+    p->off_vals0 = take(sizeof(uint32_t) * pair_capacity);
+    p->off_vals1 = take(sizeof(uint32_t) * pair_capacity);
+    p->off_ranges = take(sizeof(uint2) * tiles);
+    p->off_hist = take(sizeof(uint32_t) * 256 * (size_t)p->sort_max_blocks);
+    p->off_dtotal = take(sizeof(uint32_t) * 256);
+    p->off_bsums = take(sizeof(uint32_t) * (size_t)n_views * p->chunks);
+    p->off_boffs = take(sizeof(unsigned long long) * (size_t)n_views * p->chunks);
+    p->off_xip = take(sizeof(float) * 6 * (size_t)n_views * p->bwd_blocks);
+    p->total = o;
+    p->host_counters = Counters{};
+    p->host_counters.capacity = (unsigned long long)pair_capacity;
+    *out = p;
+    return GSR_OK;
+}
+
+extern "C" void gsr_plan_destroy(gsr_plan* plan) { delete plan; }
+
+extern "C" size_t gsr_plan_workspace_bytes(const gsr_plan* plan) { return plan ? plan->total : 0; }
+
+extern "C" gsr_status gsr_plan_bind(gsr_plan* plan, void* workspace, size_t bytes, void* stream)
+{
+    g_err.clear();
+    if (!plan || !workspace) return fail(GSR_EINVAL, "null argument");
+    if (bytes < plan->total) return fail(GSR_EINVAL, "workspace too small");
+    if (((uintptr_t)workspace & 255) != 0) return fail(GSR_EINVAL, "workspace not 256-byte aligned");
+    plan->ws = (char*)workspace;
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(plan->ws + plan->off_counters, &plan->host_counters, sizeof(Counters),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(plan->ws + plan->off_views, &plan->vt, sizeof(ViewTable), hipMemcpyHostToDevice, s);
+    // empty tile ranges until the first binning
+    if (e == hipSuccess)
+        e = hipMemsetAsync(plan->ws + plan->off_ranges, 0, sizeof(uint2) * (size_t)plan->total_tiles, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        plan->ws = nullptr;
+        return hip_fail(e, "gsr_plan_bind");
+    }
+    return GSR_OK;
+}
+
+static int final_buffer(const gsr_plan* p) { return p->passes & 1; }
+
+extern "C" gsr_status gsr_plan_layout(const gsr_plan* plan, gsr_layout* out)
+{
+    if (!plan || !out) return fail(GSR_EINVAL, "null argument");
+    out->counters = plan->off_counters;
+    out->geom = plan->off_geom;
+    out->conic_o = plan->off_conic;
+    out->rgb_d = plan->off_rgbd;
+    out->grad2d = plan->off_grad2d;
+    out->keys = final_buffer(plan) ? plan->off_keys1 : plan->off_keys0;
+    out->vals = final_buffer(plan) ? plan->off_vals1 : plan->off_vals0;
+    out->ranges = plan->off_ranges;
+    out->total = plan->total;
+    return GSR_OK;
+}
+
+extern "C" gsr_status gsr_plan_get_info(const gsr_plan* plan, gsr_plan_info* out)
+{
+    if (!plan || !out) return fail(GSR_EINVAL, "null argument");
+    out->n = plan->n;
+    out->slots = plan->n * plan->V;
+    out->capacity = plan->capacity;
+    out->total_pixels = plan->total_pixels;
+    out->n_views = plan->V;
+    out->total_tiles = plan->total_tiles;
+    out->sort_passes = plan->passes;
+    out->tile_bits = plan->tile_bits;
+    return GSR_OK;
+}
+
+template <class T>
+static T* at(const gsr_plan* p, size_t off)
+{
+    return reinterpret_cast<T*>(p->ws + off);
+}
+
+static gsr_status check_bound(const gsr_plan* p)
+{
+    if (!p) return fail(GSR_EINVAL, "null plan");
+    if (!p->ws) return fail(GSR_ESTATE, "plan not bound to a workspace");
+    return GSR_OK;
+}
+
+static gsr_status check_gaussians(const gsr_plan* p, const gsr_gaussians* g)
+{
+    if (!g) return fail(GSR_EINVAL, "null gaussians");
+    if (g->n != p->n) return fail(GSR_EINVAL, "gaussian count differs from the plan");
+    if (p->n > 0 && (!g->mean || !g->quat || !g->log_scale || !g->opacity_logit || !g->colour))
+        return fail(GSR_EINVAL, "null parameter plane");
+    return GSR_OK;
+}
+
+extern "C" gsr_status gsr_project(gsr_plan* plan, const gsr_gaussians* g, const float* poses, void* stream)
+{
+    g_err.clear();
+    gsr_status st = check_bound(plan);
+    if (st != GSR_OK) return st;
+    if ((st = check_gaussians(plan, g)) != GSR_OK) return st;
+    if (!poses) return fail(GSR_EINVAL, "null poses");
+    ProjectArgs a{};
+    a.n = plan->n;
+    a.mean = g->mean;
+    a.quat = g->quat;
+    a.log_scale = g->log_scale;
+    a.opacity_logit = g->opacity_logit;
+    a.colour = g->colour;
+    a.poses = poses;
+    a.views = at<ViewTable>(plan, plan->off_views);
+    a.cfg = plan->dcfg;
+    a.geom = at<float4>(plan, plan->off_geom);
+    a.conic_o = at<float4>(plan, plan->off_conic);
+    a.rgb_d = at<float4>(plan, plan->off_rgbd);
+    a.grad2d = at<float>(plan, plan->off_grad2d);
+    a.clear_grad = 1;
+    hipError_t e = launch_project(a, plan->cfg.sh_degree, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_project");
+}
+
+extern "C" gsr_status gsr_bin(gsr_plan* plan, void* stream)
+{
+    g_err.clear();
+    gsr_status st = check_bound(plan);
+    if (st != GSR_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    BinArgs b{};
+    b.n = plan->n;
+    b.n_views = plan->V;
+    b.views = at<ViewTable>(plan, plan->off_views);
+    b.cfg = plan->dcfg;
+    b.geom = at<float4>(plan, plan->off_geom);
+    b.rgb_d = at<float4>(plan, plan->off_rgbd);
+    b.block_sums = at<uint32_t>(plan, plan->off_bsums);
+    b.block_offs = at<unsigned long long>(plan, plan->off_boffs);
+    b.chunks = plan->chunks;
+    b.counters = at<Counters>(plan, plan->off_counters);
+    b.keys = at<unsigned long long>(plan, plan->off_keys0);
+    b.vals = at<uint32_t>(plan, plan->off_vals0);
+    hipError_t e = launch_bin(b, s);
+    if (e != hipSuccess) return hip_fail(e, "gsr_bin: emit");
+    for (int pass = 0; pass < plan->passes; ++pass) {
+        SortArgs a{};
+        a.counters = b.counters;
+        bool odd = pass & 1;
+        a.keys_in = at<unsigned long long>(plan, odd ? plan->off_keys1 : plan->off_keys0);
+        a.vals_in = at<uint32_t>(plan, odd ? plan->off_vals1 : plan->off_vals0);
+        a.keys_out = at<unsigned long long>(plan, odd ? plan->off_keys0 : plan->off_keys1);
+        a.vals_out = at<uint32_t>(plan, odd ? plan->off_vals0 : plan->off_vals1);
+        a.hist = at<uint32_t>(plan, plan->off_hist);
+        a.digit_total = at<uint32_t>(plan, plan->off_dtotal);
+        a.max_blocks = plan->sort_max_blocks;
+        a.shift = 8 * pass;
+        e = launch_sort_pass(a, plan->sort_grid, s);
+        if (e != hipSuccess) return hip_fail(e, "gsr_bin: sort");
+    }
+    RangeArgs r{};
+    r.counters = b.counters;
+    r.keys = at<unsigned long long>(plan, final_buffer(plan) ? plan->off_keys1 : plan->off_keys0);
+    r.ranges = at<uint2>(plan, plan->off_ranges);
+    r.total_tiles = plan->total_tiles;
+    e = launch_ranges(r, plan->sort_grid < 1024 ? plan->sort_grid * 4 : 4096, s);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_bin: ranges");
+}
+
+static RasterArgs raster_args(const gsr_plan* plan)
+{
+    RasterArgs a{};
+    a.views = at<ViewTable>(plan, plan->off_views);
+    a.cfg = plan->dcfg;
+    a.counters = at<Counters>(plan, plan->off_counters);
+    a.ranges = at<uint2>(plan, plan->off_ranges);
+    a.vals = at<uint32_t>(plan, final_buffer(plan) ? plan->off_vals1 : plan->off_vals0);
+    a.geom = at<float4>(plan, plan->off_geom);
+    a.conic_o = at<float4>(plan, plan->off_conic);
+    a.rgb_d = at<float4>(plan, plan->off_rgbd);
+    a.grad2d = at<float>(plan, plan->off_grad2d);
+    a.slots = plan->n * plan->V;
+    return a;
+}
+
+extern "C" gsr_status gsr_render_fwd(gsr_plan* plan, float* rgb, float* T_final, int32_t* n_contrib,
+                                     int32_t* n_blend, void* stream)
+{
+    g_err.clear();
+    gsr_status st = check_bound(plan);
+    if (st != GSR_OK) return st;
+    if (!rgb || !T_final || !n_contrib) return fail(GSR_EINVAL, "null output");
+    RasterArgs a = raster_args(plan);
+    a.rgb = rgb;
+    a.T_final = T_final;
+    a.n_contrib = n_contrib;
+    a.n_blend = n_blend;
+    hipError_t e = launch_raster_fwd(a, plan->total_tiles, plan->cfg.tile_w * plan->cfg.tile_h,
+                                     (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_render_fwd");
+}
+
+extern "C" gsr_status gsr_loss_l1(gsr_plan* plan, const float* rgb, const float* target, float* dL_drgb,
+                                  void* stream)
+{
+    g_err.clear();
+    if (!plan) return fail(GSR_EINVAL, "null plan");
+    if (!rgb || !target || !dL_drgb) return fail(GSR_EINVAL, "null buffer");
+    LossArgs a{};
+    a.rgb = rgb;
+    a.target = target;
+    a.dL_drgb = dL_drgb;
+    a.count = 3 * plan->total_pixels;
+    a.scale = a.count ? 1.0f / (float)a.count : 0.0f;
+    hipError_t e = launch_loss_l1(a, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_loss_l1");
+}
+
+extern "C" gsr_status gsr_render_bwd(gsr_plan* plan, const gsr_gaussians* g, const float* poses,
+                                     const float* dL_drgb, const float* dL_dT, const uint8_t* pose_only,
+                                     gsr_grads* grads, float* d_xi, void* stream)
+{
+    g_err.clear();
+    gsr_status st = check_bound(plan);
+    if (st != GSR_OK) return st;
+    if ((st = check_gaussians(plan, g)) != GSR_OK) return st;
+    if (!poses || !dL_drgb) return fail(GSR_EINVAL, "null poses or dL_drgb");
+    if (grads && plan->n > 0 &&
+        (!grads->d_mean || !grads->d_quat || !grads->d_log_scale || !grads->d_opacity_logit || !grads->d_colour))
+        return fail(GSR_EINVAL, "null gradient plane");
+    hipStream_t s = (hipStream_t)stream;
+    RasterArgs a = raster_args(plan);
+    a.dL_drgb = dL_drgb;
+    a.dL_dT = dL_dT;
+    hipError_t e = launch_raster_bwd(a, plan->total_tiles, plan->cfg.tile_w * plan->cfg.tile_h, s);
+    if (e != hipSuccess) return hip_fail(e, "gsr_render_bwd: raster");
+    ProjectBwdArgs b{};
+    b.n = plan->n;
+    b.mean = g->mean;
+    b.quat = g->quat;
+    b.log_scale = g->log_scale;
+    b.opacity_logit = g->opacity_logit;
+    b.colour = g->colour;
+    b.poses = poses;
+    b.views = a.views;
+    b.cfg = plan->dcfg;
+    b.geom = a.geom;
+    b.grad2d = a.grad2d;
+    unsigned long long mask = 0;
+    for (int v = 0; v < plan->V; ++v)
+        if (pose_only && pose_only[v]) mask |= 1ull << v;
+    if (!grads) mask = ~0ull;
+    b.pose_only = mask;
+    // without gradient planes every view is pose-only and no parameter store happens
+    b.d_mean = grads ? grads->d_mean : nullptr;
+    b.d_quat = grads ? grads->d_quat : nullptr;
+    b.d_log_scale = grads ? grads->d_log_scale : nullptr;
+    b.d_opacity_logit = grads ? grads->d_opacity_logit : nullptr;
+    b.d_colour = grads ? grads->d_colour : nullptr;
+    b.xi_partial = at<float>(plan, plan->off_xip);
+    b.blocks = plan->bwd_blocks;
+    e = launch_project_bwd(b, plan->cfg.sh_degree, d_xi, plan->V, s);
+    if (e != hipSuccess) return hip_fail(e, "gsr_render_bwd: projection");
+    return GSR_OK;
+}
+
+extern "C" gsr_status gsr_pair_count(gsr_plan* plan, int64_t* required, int32_t* overflow, void* stream)
+{
+    g_err.clear();
+    gsr_status st = check_bound(plan);
+    if (st != GSR_OK) return st;
+    Counters c{};
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(&c, plan->ws + plan->off_counters, sizeof(Counters), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "gsr_pair_count");
+    if (required) *required = (int64_t)c.pairs;
+    if (overflow) *overflow = (int32_t)c.overflow;
+    return c.overflow ? GSR_ECAPACITY : GSR_OK;
+}
+
+extern "C" const char* gsr_status_str(gsr_status s)
+{
+    switch (s) {
+    case GSR_OK: return "ok";
+    case GSR_EINVAL: return "invalid argument";
+    case GSR_ECAPACITY: return "pair capacity exceeded";
+    case GSR_EHIP: return "HIP error";
+    case GSR_EUNSUPPORTED: return "unsupported configuration";
+    case GSR_ESTATE: return "plan not bound";
+    }
+    return "unknown status";
+}
+
+extern "C" const char* gsr_last_error(void) { return g_err.c_str(); }

@@ -1,0 +1,204 @@
+"""ctypes binding of libgsr.so (the C ABI in include/gsr.h).
+
+Argument marshalling only: every step of the renderer runs in the library's
+HIP kernels.  Importing this module loads the library and raises if it has
+not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgsr.so")
+MAX_VIEWS = 64
+
+OK, EINVAL, ECAPACITY, EHIP, EUNSUPPORTED, ESTATE = 0, -1, -2, -3, -4, -5
+
+
+class GsrError(RuntimeError):
+    def __init__(self, status, where, detail=""):
+        self.status = status
+        super().__init__(f"{where}: {_lib.gsr_status_str(status).decode()} (status {status})"
+                         + (f": {detail}" if detail else ""))
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("sh_degree", ctypes.c_int32), ("z_near", ctypes.c_float), ("dilation", ctypes.c_float),
+                ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("T_min", ctypes.c_float),
+                ("bg", ctypes.c_float * 3)]
+
+
+class Gaussians(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("mean", ctypes.c_void_p), ("quat", ctypes.c_void_p),
+                ("log_scale", ctypes.c_void_p), ("opacity_logit", ctypes.c_void_p),
+                ("colour", ctypes.c_void_p)]
+
+
+class Grads(ctypes.Structure):
+    _fields_ = [("d_mean", ctypes.c_void_p), ("d_quat", ctypes.c_void_p), ("d_log_scale", ctypes.c_void_p),
+                ("d_opacity_logit", ctypes.c_void_p), ("d_colour", ctypes.c_void_p)]
+
+
+class Layout(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_size_t) for k in
+                ("counters", "geom", "conic_o", "rgb_d", "grad2d", "keys", "vals", "ranges", "total")]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("slots", ctypes.c_int64), ("capacity", ctypes.c_int64),
+                ("total_pixels", ctypes.c_int64), ("n_views", ctypes.c_int32),
+                ("total_tiles", ctypes.c_int32), ("sort_passes", ctypes.c_int32),
+                ("tile_bits", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_2601_00705_amd.build.build() "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    st = ctypes.c_int
+    sigs = {
+        "gsr_plan_create": (st, [ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_int64, P]),
+        "gsr_plan_destroy": (None, [P]),
+        "gsr_plan_workspace_bytes": (ctypes.c_size_t, [P]),
+        "gsr_plan_bind": (st, [P, P, ctypes.c_size_t, P]),
+        "gsr_plan_layout": (st, [P, P]),
+        "gsr_plan_get_info": (st, [P, P]),
+        "gsr_project": (st, [P, P, P, P]),
+        "gsr_bin": (st, [P, P]),
+        "gsr_render_fwd": (st, [P, P, P, P, P, P]),
+        "gsr_loss_l1": (st, [P, P, P, P, P]),
+        "gsr_render_bwd": (st, [P, P, P, P, P, P, P, P, P]),
+        "gsr_pair_count": (st, [P, P, P, P]),
+        "gsr_status_str": (ctypes.c_char_p, [st]),
+        "gsr_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+EXPORTS = ("gsr_plan_create", "gsr_plan_destroy", "gsr_plan_workspace_bytes", "gsr_plan_bind",
+           "gsr_plan_layout", "gsr_plan_get_info", "gsr_project", "gsr_bin", "gsr_render_fwd",
+           "gsr_loss_l1", "gsr_render_bwd", "gsr_pair_count", "gsr_status_str", "gsr_last_error")
+
+
+def raw():
+    """The loaded ctypes library."""
+    return _lib
+
+
+def check(status, where):
+    if status != OK:
+        raise GsrError(status, where, _lib.gsr_last_error().decode())
+    return status
+
+
+def _p(x):
+    """Device pointer of a tensor (or None)."""
+    return None if x is None else ctypes.c_void_p(x.data_ptr())
+
+
+def make_cameras(cams):
+    arr = (Camera * len(cams))()
+    for k, c in enumerate(cams):
+        arr[k] = Camera(int(c["width"]), int(c["height"]), float(c["fx"]), float(c["fy"]),
+                        float(c["cx"]), float(c["cy"]))
+    return arr
+
+
+def make_config(cfg):
+    c = Config()
+    c.tile_w, c.tile_h, c.batch, c.sh_degree = cfg.tile_w, cfg.tile_h, 0, cfg.sh_degree
+    c.z_near, c.dilation = cfg.z_near, cfg.dilation
+    c.alpha_min, c.alpha_max, c.T_min = cfg.alpha_min, cfg.alpha_max, cfg.T_min
+    for k in range(3):
+        c.bg[k] = float(cfg.bg[k])
+    return c
+
+
+def make_gaussians(n, mean, quat, log_scale, opacity_logit, colour):
+    return Gaussians(int(n), _p(mean), _p(quat), _p(log_scale), _p(opacity_logit), _p(colour))
+
+
+def gsr_plan_create(n, cams, cfg, pair_capacity):
+    plan = ctypes.c_void_p()
+    cam_arr = make_cameras(cams)
+    ccfg = make_config(cfg)
+    check(_lib.gsr_plan_create(int(n), len(cams), ctypes.cast(cam_arr, ctypes.c_void_p),
+                               ctypes.byref(ccfg), int(pair_capacity), ctypes.byref(plan)),
+          "gsr_plan_create")
+    return plan
+
+
+def gsr_plan_destroy(plan):
+    _lib.gsr_plan_destroy(plan)
+
+
+def gsr_plan_workspace_bytes(plan):
+    return int(_lib.gsr_plan_workspace_bytes(plan))
+
+
+def gsr_plan_bind(plan, workspace, stream):
+    check(_lib.gsr_plan_bind(plan, _p(workspace), workspace.numel() * workspace.element_size(),
+                             ctypes.c_void_p(stream)), "gsr_plan_bind")
+
+
+def gsr_plan_layout(plan):
+    lay = Layout()
+    check(_lib.gsr_plan_layout(plan, ctypes.byref(lay)), "gsr_plan_layout")
+    return lay
+
+
+def gsr_plan_get_info(plan):
+    info = PlanInfo()
+    check(_lib.gsr_plan_get_info(plan, ctypes.byref(info)), "gsr_plan_get_info")
+    return info
+
+
+def gsr_project(plan, g: Gaussians, poses, stream):
+    return check(_lib.gsr_project(plan, ctypes.byref(g), _p(poses), ctypes.c_void_p(stream)), "gsr_project")
+
+
+def gsr_bin(plan, stream):
+    return check(_lib.gsr_bin(plan, ctypes.c_void_p(stream)), "gsr_bin")
+
+
+def gsr_render_fwd(plan, rgb, T_final, n_contrib, n_blend, stream):
+    return check(_lib.gsr_render_fwd(plan, _p(rgb), _p(T_final), _p(n_contrib), _p(n_blend),
+                                     ctypes.c_void_p(stream)), "gsr_render_fwd")
+
+
+def gsr_loss_l1(plan, rgb, target, dL_drgb, stream):
+    return check(_lib.gsr_loss_l1(plan, _p(rgb), _p(target), _p(dL_drgb), ctypes.c_void_p(stream)),
+                 "gsr_loss_l1")
+
+
+def gsr_render_bwd(plan, g: Gaussians, poses, dL_drgb, dL_dT, pose_only, grads, d_xi, stream):
+    po = None
+    if pose_only is not None:
+        po = (ctypes.c_uint8 * len(pose_only))(*[int(x) for x in pose_only])
+    gp = ctypes.byref(grads) if grads is not None else None
+    return check(_lib.gsr_render_bwd(plan, ctypes.byref(g), _p(poses), _p(dL_drgb), _p(dL_dT),
+                                     ctypes.cast(po, ctypes.c_void_p) if po is not None else None,
+                                     gp, _p(d_xi), ctypes.c_void_p(stream)), "gsr_render_bwd")
+
+
+def gsr_pair_count(plan, stream):
+    req = ctypes.c_int64()
+    ovf = ctypes.c_int32()
+    s = _lib.gsr_pair_count(plan, ctypes.byref(req), ctypes.byref(ovf), ctypes.c_void_p(stream))
+    if s not in (OK, ECAPACITY):
+        check(s, "gsr_pair_count")
+    return int(req.value), bool(ovf.value)

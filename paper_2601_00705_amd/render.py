@@ -1,0 +1,184 @@
+"""Torch-facing renderer: plans, workspaces and a torch.autograd.Function.
+
+PyTorch provides device memory and streams; every computation is a call into
+libgsr (see include/gsr.h).  ``Renderer`` owns one plan (host object) and its
+workspace (a uint8 CUDA tensor); ``render`` is differentiable w.r.t. every
+Gaussian parameter and the pose twists xi (the left update T <- exp(xi^) T of
+Eq. (leftupdate), gradient at xi = 0).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import torch
+
+from . import lib
+
+PARAM_KEYS = ("mean", "quat", "log_scale", "opacity_logit", "colour")
+
+
+@dataclass
+class Config:
+    """Renderer settings.  Defaults: 16x16 tiles, near plane 0.2, screen
+    covariance dilation 0.3 px^2, alpha in [1/255, 0.99], early stop at
+    T < 1e-4, black background, RGB colour."""
+    tile_w: int = 16
+    tile_h: int = 16
+    sh_degree: int = -1
+    z_near: float = 0.2
+    dilation: float = 0.3
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    bg: tuple = (0.0, 0.0, 0.0)
+
+
+def _stream(device):
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Renderer:
+    """One plan + workspace for n Gaussians and a fixed set of cameras."""
+
+    def __init__(self, n, cams, cfg: Config = Config(), pair_capacity=None, device="cuda"):
+        self.n = int(n)
+        self.cams = [dict(c) for c in cams]
+        self.cfg = cfg
+        self.device = torch.device(device)
+        self.total_pixels = sum(int(c["width"]) * int(c["height"]) for c in cams)
+        if pair_capacity is None:
+            pair_capacity = max(1 << 16, 8 * self.n * len(cams))
+        self.plan = None
+        self._make(int(min(pair_capacity, (1 << 32) - 1)))
+
+    def _make(self, capacity):
+        if self.plan is not None:
+            lib.gsr_plan_destroy(self.plan)
+        self.plan = lib.gsr_plan_create(self.n, self.cams, self.cfg, capacity)
+        self.capacity = capacity
+        nbytes = lib.gsr_plan_workspace_bytes(self.plan)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        lib.gsr_plan_bind(self.plan, self.workspace, _stream(self.device))
+        self.layout = lib.gsr_plan_layout(self.plan)
+        self.info = lib.gsr_plan_get_info(self.plan)
+
+    def __del__(self):
+        if getattr(self, "plan", None) is not None:
+            lib.gsr_plan_destroy(self.plan)
+            self.plan = None
+
+    # -- views into the workspace (for tests and diagnostics) -------------
+    def _view(self, off, count, dtype):
+        nbytes = count * torch.empty((), dtype=dtype).element_size()
+        return self.workspace[off:off + nbytes].view(dtype)
+
+    def records(self):
+        S = self.info.slots
+        L = self.layout
+        return {
+            "geom": self._view(L.geom, 4 * S, torch.float32).view(S, 4),
+            "conic_o": self._view(L.conic_o, 4 * S, torch.float32).view(S, 4),
+            "rgb_d": self._view(L.rgb_d, 4 * S, torch.float32).view(S, 4),
+            "grad2d": self._view(L.grad2d, 9 * S, torch.float32).view(9, S),
+        }
+
+    def sorted_pairs(self, count):
+        L = self.layout
+        return (self._view(L.keys, count, torch.int64), self._view(L.vals, count, torch.int32),
+                self._view(L.ranges, 2 * self.info.total_tiles, torch.int32).view(-1, 2))
+
+    # -- the C ABI calls ---------------------------------------------------
+    def gaussians(self, params):
+        return lib.make_gaussians(self.n, *(params[k] for k in PARAM_KEYS))
+
+    def project(self, params, poses):
+        lib.gsr_project(self.plan, self.gaussians(params), poses, _stream(self.device))
+
+    def bin(self):
+        lib.gsr_bin(self.plan, _stream(self.device))
+
+    def pair_count(self):
+        return lib.gsr_pair_count(self.plan, _stream(self.device))
+
+    def new_image_buffers(self, want_blend=False):
+        P = self.total_pixels
+        dev = self.device
+        return (torch.empty(3 * P, device=dev), torch.empty(P, device=dev),
+                torch.empty(P, dtype=torch.int32, device=dev),
+                torch.empty(P, dtype=torch.int32, device=dev) if want_blend else None)
+
+    def render_fwd(self, rgb, T_final, n_contrib, n_blend=None):
+        lib.gsr_render_fwd(self.plan, rgb, T_final, n_contrib, n_blend, _stream(self.device))
+
+    def loss_l1(self, rgb, target, dL_drgb):
+        lib.gsr_loss_l1(self.plan, rgb, target, dL_drgb, _stream(self.device))
+
+    def render_bwd(self, params, poses, dL_drgb, dL_dT=None, pose_only=None, grads=None, d_xi=None):
+        g = None if grads is None else lib.Grads(*(lib._p(grads[k]) for k in PARAM_KEYS))
+        lib.gsr_render_bwd(self.plan, self.gaussians(params), poses, dL_drgb, dL_dT, pose_only, g, d_xi,
+                           _stream(self.device))
+
+    def forward_all(self, params, poses, want_blend=False, grow=True):
+        """project + bin (+ capacity growth) + render_fwd; returns buffers."""
+        self.project(params, poses)
+        self.bin()
+        if grow:
+            need, ovf = self.pair_count()
+            if ovf:
+                self._make(int(min(need * 5 // 4 + 4096, (1 << 32) - 1)))
+                self.project(params, poses)
+                self.bin()
+        out = self.new_image_buffers(want_blend)
+        self.render_fwd(*out)
+        return out
+
+
+def split_views(flat, cams, channels):
+    """Concatenated per-view buffer -> list of [C, H, W] (or [H, W]) views."""
+    out, off = [], 0
+    for c in cams:
+        hw = int(c["width"]) * int(c["height"])
+        chunk = flat[off * channels:(off + hw) * channels]
+        out.append(chunk.view(channels, int(c["height"]), int(c["width"])) if channels > 1
+                   else chunk.view(int(c["height"]), int(c["width"])))
+        off += hw
+    return out
+
+
+class _RenderFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, renderer, poses, pose_only, xi, mean, quat, log_scale, opacity_logit, colour):
+        params = dict(zip(PARAM_KEYS, (mean, quat, log_scale, opacity_logit, colour)))
+        params = {k: v.contiguous() for k, v in params.items()}
+        poses = poses.contiguous()
+        rgb, T, nc, _ = renderer.forward_all(params, poses)
+        ctx.renderer = renderer
+        ctx.pose_only = pose_only
+        ctx.save_for_backward(poses, *(params[k] for k in PARAM_KEYS))
+        ctx.mark_non_differentiable(nc)
+        return rgb, T, nc
+
+    @staticmethod
+    def backward(ctx, d_rgb, d_T, _d_nc):
+        r = ctx.renderer
+        poses, *tensors = ctx.saved_tensors
+        params = dict(zip(PARAM_KEYS, tensors))
+        grads = {k: torch.empty_like(v) for k, v in params.items()}
+        d_xi = torch.empty(len(r.cams), 6, device=poses.device)
+        d_rgb = torch.zeros(3 * r.total_pixels, device=poses.device) if d_rgb is None else d_rgb.contiguous()
+        d_T = None if d_T is None else d_T.contiguous()
+        r.render_bwd(params, poses, d_rgb, d_T, ctx.pose_only, grads, d_xi)
+        return (None, None, None, d_xi, grads["mean"], grads["quat"], grads["log_scale"],
+                grads["opacity_logit"], grads["colour"])
+
+
+def render(renderer: Renderer, params, poses, xi=None, pose_only=None):
+    """Differentiable render of all views of ``renderer``.
+
+    params: dict of CUDA float32 planes; poses: [V, 12] world-to-camera;
+    xi: optional [V, 6] twist placeholder (zeros, requires_grad) whose
+    gradient is dL/dxi at xi = 0.  Returns (rgb [sum 3HW], T_final [sum HW],
+    n_contrib [sum HW]); use split_views for per-view images."""
+    if xi is None:
+        xi = torch.zeros(len(renderer.cams), 6, device=poses.device)
+    return _RenderFn.apply(renderer, poses, pose_only, xi, *(params[k] for k in PARAM_KEYS))

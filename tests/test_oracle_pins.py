@@ -302,7 +302,7 @@ def _bin_reference(cams, n, u, v, rx, ry, depth, tw, th):
         for i in range(n):
             s = w * n + i
             uu, vv, a, b, d = f32(u[s]), f32(v[s]), f32(rx[s]), f32(ry[s]), f32(depth[s])
-            if not (a >= 0 and b >= 0 and uu == uu and vv == vv and d > 0):
+            if not (a >= 0 and b >= 0 and uu == uu and vv == vv):
                 continue
             x0 = np.floor(f32(uu - a) / f32(tw))
             x1 = np.floor(f32(uu + a) / f32(tw))
@@ -336,7 +336,7 @@ def test_bin_contract_adversarial():
     ry[1] = 1e9
     rx[2] = -1.0                       # culled
     u[3] = np.nan                      # invalid
-    depth[4] = 0.0                     # invalid
+    depth[4] = 0.0                     # zero depth still sorts by its bits
     u[5], rx[5] = -5.0, 1.0            # entirely left of the image
     u[6], v[6], rx[6], ry[6] = 49.99, 32.99, 0.0, 0.0  # last pixel
     keys, vals, ranges = oracle.bin_f32(cams, n, u, v, rx, ry, depth, 16, 16)
