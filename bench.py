@@ -1,0 +1,333 @@
+#!/usr/bin/env python
+"""Throughput of the differentiable Gaussian-splatting renderer on one MI355X.
+
+A step is one pass of the whole path over one batch of views: projection,
+binning (pair emission + LDS radix sort + tile ranges), compositing forward,
+the L1 photometric gradient seed, compositing backward and projection
+backward (all parameters and the pose twists).  Inputs are synthetic and
+seeded (paper_2601_00705_amd.scenes) and resident in HBM before timing.
+
+Batched mode: all views of the workload in one plan, the step captured once
+in a HIP graph (torch.cuda.CUDAGraph over the library's stream) and
+replayed.  Plain mode: one plan per view, launched view after view on one
+stream without a graph.  Prints one JSON line on stdout; details on stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+
+# Algorithmic FP32 work per blended (pixel, Gaussian) pair, FMA = 2 flops,
+# a transcendental = 1 (see the design notes for the derivation).
+FLOPS_FWD_PER_BLEND = 21
+FLOPS_BWD_PER_BLEND = 48
+# Algorithmic HBM bytes of the projection backward per live slot / Gaussian
+BYTES_PBWD_PER_SLOT = 16 + 36       # geom record + screen-space gradient
+BYTES_PBWD_PER_GAUSSIAN_RGB = 56 + 56
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=3, help="workload index 0..4")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-views", type=str, default=None, help="comma list of views for the oracle sample")
+    ap.add_argument("--tile", type=str, default=None, help="WxH tile size (default: autotuned or 16x16)")
+    ap.add_argument("--copy-probe", action="store_true", help="run a plain device copy of known size first")
+    return ap.parse_args()
+
+
+def target_images(w, params_d, poses_d, cfg, Renderer, torch):
+    """Target images of the workload, rendered once on the GPU (untimed) or
+    taken from the workload's own images."""
+    import numpy as np
+    cams = w["cams"]
+    if "targets" in w:
+        return torch.from_numpy(np.concatenate([t.reshape(-1) for t in w["targets"]])).cuda()
+    R = Renderer(w["params"]["opacity_logit"].shape[0], cams, cfg)
+    if "target_params" in w:
+        P = {k: torch.from_numpy(v).cuda() for k, v in w["target_params"].items()}
+        rgb, _, _, _ = R.forward_all(P, poses_d)
+    else:
+        tp = torch.from_numpy(w["target_poses"].astype(np.float32)).cuda()
+        rgb, _, _, _ = R.forward_all(params_d, tp)
+    torch.cuda.synchronize()
+    out = rgb.clone()
+    del R
+    return out
+
+
+class Step:
+    """Buffers and the C-ABI call sequence of one step for one plan."""
+
+    def __init__(self, R, params, poses, target, pose_only, torch):
+        self.R, self.params, self.poses, self.target, self.pose_only = R, params, poses, target, pose_only
+        P = R.total_pixels
+        dev = poses.device
+        self.rgb = torch.empty(3 * P, device=dev)
+        self.T = torch.empty(P, device=dev)
+        self.nc = torch.empty(P, dtype=torch.int32, device=dev)
+        self.dL = torch.empty(3 * P, device=dev)
+        self.grads = {k: torch.empty_like(v) for k, v in params.items()}
+        self.d_xi = torch.empty(len(R.cams), 6, device=dev)
+
+    def stages(self):
+        R = self.R
+        return [
+            ("project", lambda: R.project(self.params, self.poses)),
+            ("bin", lambda: R.bin()),
+            ("raster_fwd", lambda: R.render_fwd(self.rgb, self.T, self.nc)),
+            ("loss_l1", lambda: R.loss_l1(self.rgb, self.target, self.dL)),
+            ("raster_bwd", lambda: R.raster_bwd(self.T, self.nc, self.dL)),
+            ("project_bwd", lambda: R.project_bwd(self.params, self.poses, self.pose_only, self.grads, self.d_xi)),
+        ]
+
+    def run(self):
+        for _, f in self.stages():
+            f()
+
+
+def sized_renderer(Renderer, n, cams, cfg, params, poses, torch, slack=1.15):
+    R = Renderer(n, cams, cfg)
+    R.project(params, poses)
+    R.bin()
+    need, _ = R.pair_count()
+    R._make(int(need * slack) + 4096)
+    return R, need
+
+
+def oracle_sample(w, views, cfg):
+    """The FP64 CPU oracle on a bounded sample of the workload: forward +
+    backward of the given views with the full Gaussian set."""
+    import numpy as np
+    import oracle
+    from paper_2601_00705_amd import scenes
+    cams = [w["cams"][v] for v in views]
+    poses = w["poses"][views]
+    ocfg = oracle.Config(tile_w=cfg.tile_w, tile_h=cfg.tile_h, sh_degree=cfg.sh_degree, z_near=cfg.z_near,
+                         dilation=cfg.dilation, alpha_min=cfg.alpha_min, alpha_max=cfg.alpha_max,
+                         T_min=cfg.T_min, bg=cfg.bg)
+    P = sum(c["width"] * c["height"] for c in cams)
+    dL = scenes.upstream_grad(5, 3 * P).astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.render(w["params"], cams, poses, ocfg, want_margin=False)
+    oracle.backward(w["params"], cams, poses, ocfg, dL)
+    dt = time.perf_counter() - t0
+    return P, dt
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the renderer is benchmarked on a single MI355X "
+              "(multi-GPU view sharding is a design note, not built); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2601_00705_amd import scenes
+    from paper_2601_00705_amd.render import Config, Renderer
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    t_gen = time.time()
+    w = scenes.workload(args.config)
+    log(f"workload {w['name']}: generated in {time.time() - t_gen:.1f}s")
+    cams = w["cams"]
+    n = int(w["params"]["opacity_logit"].shape[0])
+    V = len(cams)
+    pose_only = [int(x) for x in w["pose_only"]]
+    tile = (16, 16)
+    if args.tile:
+        tile = tuple(int(x) for x in args.tile.lower().split("x"))
+    else:
+        try:
+            from paper_2601_00705_amd import autotune
+            tile = autotune.lookup(cams, n, w["sh_degree"]) or tile
+        except Exception:  # no cache yet
+            pass
+    cfg = Config(tile_w=tile[0], tile_h=tile[1], sh_degree=w["sh_degree"])
+    params = {k: torch.from_numpy(v).to(dev) for k, v in w["params"].items()}
+    poses = torch.from_numpy(w["poses"].astype(np.float32)).to(dev)
+    target = target_images(w, params, poses, cfg, Renderer, torch)
+    total_px = sum(c["width"] * c["height"] for c in cams)
+
+    if args.copy_probe:
+        # plain device copy of a known size (scales the HBM byte counters)
+        a = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: 3 x 256 MiB device copies")
+
+    # ---------------- batched: one plan, one graph --------------------
+    R, need = sized_renderer(Renderer, n, cams, cfg, params, poses, torch)
+    st = Step(R, params, poses, target, pose_only, torch)
+    for _ in range(2):
+        st.run()
+    torch.cuda.synchronize()
+    _, ovf = R.pair_count()
+    assert not ovf
+    graph = torch.cuda.CUDAGraph()
+    cap = torch.cuda.Stream()
+    cap.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(cap):
+        st.run()  # warm the capture stream
+        torch.cuda.synchronize()
+        with torch.cuda.graph(graph, stream=cap):
+            st.run()
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    _, ovf = R.pair_count()
+    assert not ovf, "pair capacity exceeded during replay"
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    log(f"batched (graph): {ms_step:.3f} ms/step, pairs {need}")
+
+    # ---------------- per-stage HIP-event timing (eager) ---------------
+    stages = st.stages()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in stages]
+    acc = [0.0] * len(stages)
+    K = max(3, args.steps // 2)
+    stream = torch.cuda.current_stream()
+    for _ in range(K):
+        for k, (_, f) in enumerate(stages):
+            ev[k][0].record(stream)
+            f()
+            ev[k][1].record(stream)
+        torch.cuda.synchronize()
+        for k in range(len(stages)):
+            acc[k] += ev[k][0].elapsed_time(ev[k][1])
+    stage_ms = {name: acc[k] / K for k, (name, _) in enumerate(stages)}
+    log("stage ms: " + ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()))
+
+    # ---------------- blends / evaluations (untimed counting pass) -----
+    nb = torch.empty(total_px, dtype=torch.int32, device=dev)
+    R.render_fwd(st.rgb, st.T, st.nc, nb)
+    torch.cuda.synchronize()
+    blends = int(nb.sum(dtype=torch.int64))
+    contrib_entries = int(st.nc.sum(dtype=torch.int64))
+    slots_live = int((R.records()["geom"][:, 2] >= 0).sum())
+    log(f"blends {blends}, list entries up to last contributor {contrib_entries}, live slots {slots_live}")
+
+    # ---------------- plain: one plan per view, no graph ---------------
+    plain = None
+    if not args.no_plain and V > 1:
+        steps_plain = []
+        off = 0
+        for v in range(V):
+            hw = cams[v]["width"] * cams[v]["height"]
+            Rv, _ = sized_renderer(Renderer, n, [cams[v]], cfg, params, poses[v:v + 1], torch)
+            steps_plain.append(Step(Rv, params, poses[v:v + 1].contiguous(), target[3 * off:3 * (off + hw)],
+                                    [pose_only[v]], torch))
+            off += hw
+        for _ in range(2):
+            for s in steps_plain:
+                s.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            for s in steps_plain:
+                s.run()
+        torch.cuda.synchronize()
+        plain = (time.perf_counter() - t0) * 1e3 / args.steps
+        log(f"plain ({V} per-view launch sequences): {plain:.3f} ms/step; speedup {plain / ms_step:.2f}x")
+
+    # ---------------- roofline of the dominant kernel ------------------
+    dom = max(stage_ms, key=stage_ms.get)
+    dom_ms = stage_ms[dom]
+    if dom == "raster_bwd":
+        roof = {"bound": "alu", "achieved": blends * FLOPS_BWD_PER_BLEND / (dom_ms * 1e-3) / 1e12,
+                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    elif dom == "raster_fwd":
+        roof = {"bound": "alu", "achieved": blends * FLOPS_FWD_PER_BLEND / (dom_ms * 1e-3) / 1e12,
+                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s"}
+    elif dom == "bin":
+        passes = R.info.sort_passes
+        algo = need * (12 + passes * 32 + 8)
+        roof = {"bound": "hbm", "achieved": algo / (dom_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    else:
+        algo = slots_live * BYTES_PBWD_PER_SLOT + n * BYTES_PBWD_PER_GAUSSIAN_RGB
+        roof = {"bound": "hbm", "achieved": algo / (dom_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    roof["kernel"] = dom
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof["traffic"] = None
+
+    # ---------------- CPU baseline: the oracle on a bounded sample -----
+    cpu = None
+    if not args.no_cpu_baseline:
+        if args.cpu_views:
+            views = [int(x) for x in args.cpu_views.split(",")]
+        else:
+            # smallest views first, about 0.1-0.2 Mpix of work
+            order = sorted(range(V), key=lambda v: cams[v]["width"] * cams[v]["height"])
+            views, px = [], 0
+            for v in order:
+                if px >= 100_000:
+                    break
+                views.append(v)
+                px += cams[v]["width"] * cams[v]["height"]
+        P_cpu, dt = oracle_sample(w, views, cfg)
+        cpu = {"value": P_cpu / dt / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+               "sample": f"views {views} ({P_cpu} px) of {w['name']}, fwd+bwd, full Gaussian set, "
+                         f"{dt:.1f} s single-threaded FP64"}
+        log(f"cpu oracle: {cpu['value']:.4f} Mpix/s over {dt:.1f}s")
+
+    mpix = total_px / (ms_step * 1e-3) / 1e6
+    out = {
+        "metric": "fwd+bwd Mpix/s and Gaussian-pixel blends/s, batched vs plain, 1 MI355X",
+        "value": mpix,
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "gaussians": n, "views": V, "pixels": total_px,
+                   "tile": f"{cfg.tile_w}x{cfg.tile_h}", "sh_degree": cfg.sh_degree, "mode": "batched-graph"},
+        "blends_per_s": blends / (ms_step * 1e-3),
+        "blends_per_step": blends,
+        "pairs_per_step": need,
+        "plain_ms_per_step": plain,
+        "plain_mpix_per_s": None if plain is None else total_px / (plain * 1e-3) / 1e6,
+        "batched_speedup": None if plain is None else plain / ms_step,
+        "stage_ms": stage_ms,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -164,13 +164,24 @@ gsr_status gsr_render_fwd(gsr_plan *plan, float *rgb, float *T_final, int32_t *n
 gsr_status gsr_loss_l1(gsr_plan *plan, const float *rgb, const float *target, float *dL_drgb, void *stream);
 
 /* Backward of gsr_render_fwd (call after it, on the same plan, without an
- * intervening gsr_project).  dL_dT may be NULL (zero).  pose_only: HOST array
+ * intervening gsr_project or gsr_bin).  T_final and n_contrib are the buffers
+ * the forward wrote (read only).  dL_dT may be NULL (zero).  pose_only: HOST array
  * [n_views] of 0/1 or NULL; views flagged 1 contribute to d_xi only.  grads
  * may be NULL (pose gradients only); d_xi: device [n_views][6] or NULL.
  * g and poses must be the values given to gsr_project. */
-gsr_status gsr_render_bwd(gsr_plan *plan, const gsr_gaussians *g, const float *poses, const float *dL_drgb,
-                          const float *dL_dT, const uint8_t *pose_only, gsr_grads *grads, float *d_xi,
-                          void *stream);
+gsr_status gsr_render_bwd(gsr_plan *plan, const gsr_gaussians *g, const float *poses, const float *T_final,
+                          const int32_t *n_contrib, const float *dL_drgb, const float *dL_dT,
+                          const uint8_t *pose_only, gsr_grads *grads, float *d_xi, void *stream);
+
+/* The two stages of gsr_render_bwd, callable separately (same arguments and
+ * rules).  gsr_raster_bwd: backward of Eq. (alpha) into per-slot
+ * screen-space gradient accumulators (grad2d in the layout).
+ * gsr_project_bwd: backward of Eq. (proj) and of the pose twist, Eqs.
+ * (muCjac)-(sigmaIjac), from those accumulators to grads and d_xi. */
+gsr_status gsr_raster_bwd(gsr_plan *plan, const float *T_final, const int32_t *n_contrib, const float *dL_drgb,
+                          const float *dL_dT, void *stream);
+gsr_status gsr_project_bwd(gsr_plan *plan, const gsr_gaussians *g, const float *poses, const uint8_t *pose_only,
+                           gsr_grads *grads, float *d_xi, void *stream);
 
 /* Synchronises `stream`, then reports the pair count of the last binning
  * and whether it exceeded the capacity. */

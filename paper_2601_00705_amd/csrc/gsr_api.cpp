@@ -370,24 +370,33 @@ extern "C" gsr_status gsr_loss_l1(gsr_plan* plan, const float* rgb, const float*
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_loss_l1");
 }
 
-extern "C" gsr_status gsr_render_bwd(gsr_plan* plan, const gsr_gaussians* g, const float* poses,
-                                     const float* dL_drgb, const float* dL_dT, const uint8_t* pose_only,
-                                     gsr_grads* grads, float* d_xi, void* stream)
+extern "C" gsr_status gsr_raster_bwd(gsr_plan* plan, const float* T_final, const int32_t* n_contrib,
+                                     const float* dL_drgb, const float* dL_dT, void* stream)
+{
+    g_err.clear();
+    gsr_status st = check_bound(plan);
+    if (st != GSR_OK) return st;
+    if (!dL_drgb || !T_final || !n_contrib) return fail(GSR_EINVAL, "null T_final, n_contrib or dL_drgb");
+    RasterArgs a = raster_args(plan);
+    a.T_final_in = T_final;
+    a.n_contrib_in = n_contrib;
+    a.dL_drgb = dL_drgb;
+    a.dL_dT = dL_dT;
+    hipError_t e = launch_raster_bwd(a, plan->total_tiles, plan->cfg.tile_w * plan->cfg.tile_h, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_raster_bwd");
+}
+
+extern "C" gsr_status gsr_project_bwd(gsr_plan* plan, const gsr_gaussians* g, const float* poses,
+                                      const uint8_t* pose_only, gsr_grads* grads, float* d_xi, void* stream)
 {
     g_err.clear();
     gsr_status st = check_bound(plan);
     if (st != GSR_OK) return st;
     if ((st = check_gaussians(plan, g)) != GSR_OK) return st;
-    if (!poses || !dL_drgb) return fail(GSR_EINVAL, "null poses or dL_drgb");
+    if (!poses) return fail(GSR_EINVAL, "null poses");
     if (grads && plan->n > 0 &&
         (!grads->d_mean || !grads->d_quat || !grads->d_log_scale || !grads->d_opacity_logit || !grads->d_colour))
         return fail(GSR_EINVAL, "null gradient plane");
-    hipStream_t s = (hipStream_t)stream;
-    RasterArgs a = raster_args(plan);
-    a.dL_drgb = dL_drgb;
-    a.dL_dT = dL_dT;
-    hipError_t e = launch_raster_bwd(a, plan->total_tiles, plan->cfg.tile_w * plan->cfg.tile_h, s);
-    if (e != hipSuccess) return hip_fail(e, "gsr_render_bwd: raster");
     ProjectBwdArgs b{};
     b.n = plan->n;
     b.mean = g->mean;
@@ -396,16 +405,16 @@ extern "C" gsr_status gsr_render_bwd(gsr_plan* plan, const gsr_gaussians* g, con
     b.opacity_logit = g->opacity_logit;
     b.colour = g->colour;
     b.poses = poses;
-    b.views = a.views;
+    b.views = at<ViewTable>(plan, plan->off_views);
     b.cfg = plan->dcfg;
-    b.geom = a.geom;
-    b.grad2d = a.grad2d;
+    b.geom = at<float4>(plan, plan->off_geom);
+    b.grad2d = at<float>(plan, plan->off_grad2d);
     unsigned long long mask = 0;
     for (int v = 0; v < plan->V; ++v)
         if (pose_only && pose_only[v]) mask |= 1ull << v;
+    // without gradient planes every view is pose-only and no parameter store happens
     if (!grads) mask = ~0ull;
     b.pose_only = mask;
-    // without gradient planes every view is pose-only and no parameter store happens
     b.d_mean = grads ? grads->d_mean : nullptr;
     b.d_quat = grads ? grads->d_quat : nullptr;
     b.d_log_scale = grads ? grads->d_log_scale : nullptr;
@@ -413,9 +422,22 @@ extern "C" gsr_status gsr_render_bwd(gsr_plan* plan, const gsr_gaussians* g, con
     b.d_colour = grads ? grads->d_colour : nullptr;
     b.xi_partial = at<float>(plan, plan->off_xip);
     b.blocks = plan->bwd_blocks;
-    e = launch_project_bwd(b, plan->cfg.sh_degree, d_xi, plan->V, s);
-    if (e != hipSuccess) return hip_fail(e, "gsr_render_bwd: projection");
-    return GSR_OK;
+    hipError_t e = launch_project_bwd(b, plan->cfg.sh_degree, d_xi, plan->V, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_project_bwd");
+}
+
+extern "C" gsr_status gsr_render_bwd(gsr_plan* plan, const gsr_gaussians* g, const float* poses,
+                                     const float* T_final, const int32_t* n_contrib, const float* dL_drgb,
+                                     const float* dL_dT, const uint8_t* pose_only, gsr_grads* grads, float* d_xi,
+                                     void* stream)
+{
+    gsr_status st = check_bound(plan);
+    if (st != GSR_OK) return st;
+    if ((st = check_gaussians(plan, g)) != GSR_OK) return st;
+    if (!poses) return fail(GSR_EINVAL, "null poses");
+    st = gsr_raster_bwd(plan, T_final, n_contrib, dL_drgb, dL_dT, stream);
+    if (st != GSR_OK) return st;
+    return gsr_project_bwd(plan, g, poses, pose_only, grads, d_xi, stream);
 }
 
 extern "C" gsr_status gsr_pair_count(gsr_plan* plan, int64_t* required, int32_t* overflow, void* stream)

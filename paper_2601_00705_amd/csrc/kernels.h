@@ -61,6 +61,8 @@ struct RasterArgs {
     int32_t* n_contrib;        // [sum H W]
     int32_t* n_blend;          // nullable
     // backward only
+    const float* T_final_in;   // forward outputs, read by the backward
+    const int32_t* n_contrib_in;
     const float* dL_drgb;
     const float* dL_dT;        // nullable
     float* grad2d;             // [9][slots]

@@ -166,8 +166,8 @@ __global__ __launch_bounds__(BLOCK) void k_raster_bwd(RasterArgs a)
     float Tf = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, gT = 0.0f;
     uint32_t my_n = 0;
     if (c.inside) {
-        Tf = a.T_final[c.pix];
-        my_n = (uint32_t)a.n_contrib[c.pix];
+        Tf = a.T_final_in[c.pix];
+        my_n = (uint32_t)a.n_contrib_in[c.pix];
         g0 = a.dL_drgb[c.rgb0];
         g1 = a.dL_drgb[c.rgb0 + c.plane];
         g2 = a.dL_drgb[c.rgb0 + 2 * c.plane];

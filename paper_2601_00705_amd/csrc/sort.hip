@@ -132,6 +132,9 @@ __global__ __launch_bounds__(GSR_SORT_THREADS) void k_sort_scatter(SortArgs a)
             unsigned long long m = match_digit(d, valid);
             uint32_t below = (uint32_t)__popcll(m & lt);
             uint32_t start = valid ? wcnt[w][d] : 0u;
+            // every lane of the wave has read its counter before a leader
+            // updates it (lockstep; the barrier keeps the order explicit)
+            __builtin_amdgcn_wave_barrier();
             rank[r] = start + below;
             if (valid && below == 0u) wcnt[w][d] = start + (uint32_t)__popcll(m);
         }

@@ -76,7 +76,9 @@ def _load():
         "gsr_bin": (st, [P, P]),
         "gsr_render_fwd": (st, [P, P, P, P, P, P]),
         "gsr_loss_l1": (st, [P, P, P, P, P]),
-        "gsr_render_bwd": (st, [P, P, P, P, P, P, P, P, P]),
+        "gsr_render_bwd": (st, [P, P, P, P, P, P, P, P, P, P, P]),
+        "gsr_raster_bwd": (st, [P, P, P, P, P, P]),
+        "gsr_project_bwd": (st, [P, P, P, P, P, P, P]),
         "gsr_pair_count": (st, [P, P, P, P]),
         "gsr_status_str": (ctypes.c_char_p, [st]),
         "gsr_last_error": (ctypes.c_char_p, []),
@@ -91,7 +93,8 @@ def _load():
 _lib = _load()
 EXPORTS = ("gsr_plan_create", "gsr_plan_destroy", "gsr_plan_workspace_bytes", "gsr_plan_bind",
            "gsr_plan_layout", "gsr_plan_get_info", "gsr_project", "gsr_bin", "gsr_render_fwd",
-           "gsr_loss_l1", "gsr_render_bwd", "gsr_pair_count", "gsr_status_str", "gsr_last_error")
+           "gsr_loss_l1", "gsr_render_bwd", "gsr_raster_bwd", "gsr_project_bwd", "gsr_pair_count",
+           "gsr_status_str", "gsr_last_error")
 
 
 def raw():
@@ -185,14 +188,36 @@ def gsr_loss_l1(plan, rgb, target, dL_drgb, stream):
                  "gsr_loss_l1")
 
 
-def gsr_render_bwd(plan, g: Gaussians, poses, dL_drgb, dL_dT, pose_only, grads, d_xi, stream):
+def gsr_render_bwd(plan, g: Gaussians, poses, T_final, n_contrib, dL_drgb, dL_dT, pose_only, grads, d_xi,
+                   stream):
     po = None
     if pose_only is not None:
         po = (ctypes.c_uint8 * len(pose_only))(*[int(x) for x in pose_only])
     gp = ctypes.byref(grads) if grads is not None else None
-    return check(_lib.gsr_render_bwd(plan, ctypes.byref(g), _p(poses), _p(dL_drgb), _p(dL_dT),
+    return check(_lib.gsr_render_bwd(plan, ctypes.byref(g), _p(poses), _p(T_final), _p(n_contrib),
+                                     _p(dL_drgb), _p(dL_dT),
                                      ctypes.cast(po, ctypes.c_void_p) if po is not None else None,
                                      gp, _p(d_xi), ctypes.c_void_p(stream)), "gsr_render_bwd")
+
+
+def _pose_only_arg(pose_only):
+    if pose_only is None:
+        return None
+    po = (ctypes.c_uint8 * len(pose_only))(*[int(x) for x in pose_only])
+    return po
+
+
+def gsr_raster_bwd(plan, T_final, n_contrib, dL_drgb, dL_dT, stream):
+    return check(_lib.gsr_raster_bwd(plan, _p(T_final), _p(n_contrib), _p(dL_drgb), _p(dL_dT),
+                                     ctypes.c_void_p(stream)), "gsr_raster_bwd")
+
+
+def gsr_project_bwd(plan, g: Gaussians, poses, pose_only, grads, d_xi, stream):
+    po = _pose_only_arg(pose_only)
+    return check(_lib.gsr_project_bwd(plan, ctypes.byref(g), _p(poses),
+                                      ctypes.cast(po, ctypes.c_void_p) if po is not None else None,
+                                      ctypes.byref(grads) if grads is not None else None, _p(d_xi),
+                                      ctypes.c_void_p(stream)), "gsr_project_bwd")
 
 
 def gsr_pair_count(plan, stream):

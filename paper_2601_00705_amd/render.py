@@ -113,10 +113,18 @@ class Renderer:
     def loss_l1(self, rgb, target, dL_drgb):
         lib.gsr_loss_l1(self.plan, rgb, target, dL_drgb, _stream(self.device))
 
-    def render_bwd(self, params, poses, dL_drgb, dL_dT=None, pose_only=None, grads=None, d_xi=None):
+    def render_bwd(self, params, poses, T_final, n_contrib, dL_drgb, dL_dT=None, pose_only=None, grads=None,
+                   d_xi=None):
         g = None if grads is None else lib.Grads(*(lib._p(grads[k]) for k in PARAM_KEYS))
-        lib.gsr_render_bwd(self.plan, self.gaussians(params), poses, dL_drgb, dL_dT, pose_only, g, d_xi,
-                           _stream(self.device))
+        lib.gsr_render_bwd(self.plan, self.gaussians(params), poses, T_final, n_contrib, dL_drgb, dL_dT,
+                           pose_only, g, d_xi, _stream(self.device))
+
+    def raster_bwd(self, T_final, n_contrib, dL_drgb, dL_dT=None):
+        lib.gsr_raster_bwd(self.plan, T_final, n_contrib, dL_drgb, dL_dT, _stream(self.device))
+
+    def project_bwd(self, params, poses, pose_only=None, grads=None, d_xi=None):
+        g = None if grads is None else lib.Grads(*(lib._p(grads[k]) for k in PARAM_KEYS))
+        lib.gsr_project_bwd(self.plan, self.gaussians(params), poses, pose_only, g, d_xi, _stream(self.device))
 
     def forward_all(self, params, poses, want_blend=False, grow=True):
         """project + bin (+ capacity growth) + render_fwd; returns buffers."""
@@ -154,20 +162,20 @@ class _RenderFn(torch.autograd.Function):
         rgb, T, nc, _ = renderer.forward_all(params, poses)
         ctx.renderer = renderer
         ctx.pose_only = pose_only
-        ctx.save_for_backward(poses, *(params[k] for k in PARAM_KEYS))
+        ctx.save_for_backward(poses, T, nc, *(params[k] for k in PARAM_KEYS))
         ctx.mark_non_differentiable(nc)
         return rgb, T, nc
 
     @staticmethod
     def backward(ctx, d_rgb, d_T, _d_nc):
         r = ctx.renderer
-        poses, *tensors = ctx.saved_tensors
+        poses, T, nc, *tensors = ctx.saved_tensors
         params = dict(zip(PARAM_KEYS, tensors))
         grads = {k: torch.empty_like(v) for k, v in params.items()}
         d_xi = torch.empty(len(r.cams), 6, device=poses.device)
         d_rgb = torch.zeros(3 * r.total_pixels, device=poses.device) if d_rgb is None else d_rgb.contiguous()
         d_T = None if d_T is None else d_T.contiguous()
-        r.render_bwd(params, poses, d_rgb, d_T, ctx.pose_only, grads, d_xi)
+        r.render_bwd(params, poses, T, nc, d_rgb, d_T, ctx.pose_only, grads, d_xi)
         return (None, None, None, d_xi, grads["mean"], grads["quat"], grads["log_scale"],
                 grads["opacity_logit"], grads["colour"])
 

@@ -269,8 +269,8 @@ def _check_backward(name, params, cams, poses, cfg, seed, pose_only=None, with_d
     dT = scenes.upstream_grad(seed + 1, Ptot) if with_dT else None
     grads = {k: torch.empty_like(v) for k, v in P.items()}
     d_xi = torch.empty(len(cams), 6, device="cuda")
-    R.render_bwd(P, poses_d, torch.from_numpy(dL).cuda(), None if dT is None else torch.from_numpy(dT).cuda(),
-                 pose_only, grads, d_xi)
+    R.render_bwd(P, poses_d, T, nc, torch.from_numpy(dL).cuda(),
+                 None if dT is None else torch.from_numpy(dT).cuda(), pose_only, grads, d_xi)
     torch.cuda.synchronize()
     ref = oracle.backward(params, cams, poses, oracle_cfg(cfg), dL.astype(np.float64),
                           None if dT is None else dT.astype(np.float64), pose_only=pose_only)
