@@ -105,7 +105,7 @@ typedef struct {
     size_t geom;      /* float4 [V*n]: (u, v, rx, ry); rx < 0 = culled */
     size_t conic_o;   /* float4 [V*n]: (A, B, C, o), A = (Sigma_I^-1)_00 ... */
     size_t rgb_d;     /* float4 [V*n]: (r, g, b, depth) */
-    size_t grad2d;    /* float [9][V*n]: d(u, v, A, B, C, o, r, g, b) */
+    size_t grad2d;    /* double [9][V*n]: d(u, v, A, B, C, o, r, g, b) */
     size_t keys;      /* uint64 [capacity]: sorted (tile << 32 | depth bits) */
     size_t vals;      /* uint32 [capacity]: sorted slot = view * n + index */
     size_t ranges;    /* uint32 [tiles][2]: [first, last + 1) per global tile */

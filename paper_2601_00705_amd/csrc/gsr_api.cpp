@@ -152,7 +152,7 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->off_geom = take(sizeof(float4) * S);
     p->off_conic = take(sizeof(float4) * S);
     p->off_rgbd = take(sizeof(float4) * S);
-    p->off_grad2d = take(sizeof(float) * GSR_G2 * S);
+    p->off_grad2d = take(sizeof(double) * GSR_G2 * S);
     p->off_keys0 = take(sizeof(unsigned long long) * pair_capacity);
     p->off_keys1 = take(sizeof(unsigned long long) * pair_capacity);
     p->off_vals0 = take(sizeof(uint32_t) * pair_capacity);
@@ -162,7 +162,7 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->off_dtotal = take(sizeof(uint32_t) * 256);
     p->off_bsums = take(sizeof(uint32_t) * (size_t)n_views * p->chunks);
     p->off_boffs = take(sizeof(unsigned long long) * (size_t)n_views * p->chunks);
-    p->off_xip = take(sizeof(float) * 6 * (size_t)n_views * p->bwd_blocks);
+    p->off_xip = take(sizeof(double) * 6 * (size_t)n_views * p->bwd_blocks);
     p->total = o;
     p->host_counters = Counters{};
     p->host_counters.capacity = (unsigned long long)pair_capacity;
@@ -270,8 +270,6 @@ extern "C" gsr_status gsr_project(gsr_plan* plan, const gsr_gaussians* g, const 
     a.geom = at<float4>(plan, plan->off_geom);
     a.conic_o = at<float4>(plan, plan->off_conic);
     a.rgb_d = at<float4>(plan, plan->off_rgbd);
-    a.grad2d = at<float>(plan, plan->off_grad2d);
-    a.clear_grad = 1;
     hipError_t e = launch_project(a, plan->cfg.sh_degree, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_project");
 }
@@ -332,7 +330,7 @@ static RasterArgs raster_args(const gsr_plan* plan)
     a.geom = at<float4>(plan, plan->off_geom);
     a.conic_o = at<float4>(plan, plan->off_conic);
     a.rgb_d = at<float4>(plan, plan->off_rgbd);
-    a.grad2d = at<float>(plan, plan->off_grad2d);
+    a.grad2d = at<double>(plan, plan->off_grad2d);
     a.slots = plan->n * plan->V;
     return a;
 }
@@ -408,7 +406,7 @@ extern "C" gsr_status gsr_project_bwd(gsr_plan* plan, const gsr_gaussians* g, co
     b.views = at<ViewTable>(plan, plan->off_views);
     b.cfg = plan->dcfg;
     b.geom = at<float4>(plan, plan->off_geom);
-    b.grad2d = at<float>(plan, plan->off_grad2d);
+    b.grad2d = at<double>(plan, plan->off_grad2d);
     unsigned long long mask = 0;
     for (int v = 0; v < plan->V; ++v)
         if (pose_only && pose_only[v]) mask |= 1ull << v;
@@ -420,7 +418,7 @@ extern "C" gsr_status gsr_project_bwd(gsr_plan* plan, const gsr_gaussians* g, co
     b.d_log_scale = grads ? grads->d_log_scale : nullptr;
     b.d_opacity_logit = grads ? grads->d_opacity_logit : nullptr;
     b.d_colour = grads ? grads->d_colour : nullptr;
-    b.xi_partial = at<float>(plan, plan->off_xip);
+    b.xi_partial = at<double>(plan, plan->off_xip);
     b.blocks = plan->bwd_blocks;
     hipError_t e = launch_project_bwd(b, plan->cfg.sh_degree, d_xi, plan->V, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_project_bwd");

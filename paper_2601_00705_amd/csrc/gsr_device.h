@@ -6,7 +6,7 @@
 //                                      rx < 0 marks a culled slot
 //   conic_o float4 (A, B, C, o)       inverse screen covariance, opacity
 //   rgb_d   float4 (r, g, b, depth)   colour in this view, camera depth z
-//   grad2d  float [9][slots]          screen-space gradient accumulators
+//   grad2d  double [9][slots]         screen-space gradient accumulators
 //                                      (du, dv, dA, dB, dC, do, dr, dg, db)
 // The rectangle function below is the binning contract: a pure function of
 // the float32 (u, v, rx, ry) of a slot, single IEEE operations only, so the
@@ -89,7 +89,7 @@ __device__ __forceinline__ float wave_sum(float x)
     return x;
 }
 
-__device__ __forceinline__ void atomic_add_f32(float* p, float v)
+__device__ __forceinline__ void atomic_add_f64(double* p, double v)
 {
     unsafeAtomicAdd(p, v);
 }

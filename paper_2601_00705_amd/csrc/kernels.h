@@ -11,8 +11,6 @@ struct ProjectArgs {
     const ViewTable* views;    // device copy
     DevCfg cfg;
     float4 *geom, *conic_o, *rgb_d;
-    float* grad2d;             // [9][V*n]
-    int clear_grad;
 };
 
 struct BinArgs {
@@ -65,7 +63,7 @@ struct RasterArgs {
     const int32_t* n_contrib_in;
     const float* dL_drgb;
     const float* dL_dT;        // nullable
-    float* grad2d;             // [9][slots]
+    double* grad2d;            // [9][slots]
     int64_t slots;
 };
 
@@ -76,10 +74,10 @@ struct ProjectBwdArgs {
     const ViewTable* views;
     DevCfg cfg;
     const float4* geom;
-    const float* grad2d;
+    const double* grad2d;
     unsigned long long pose_only;   // bit v set: view v updates the pose only
     float *d_mean, *d_quat, *d_log_scale, *d_opacity_logit, *d_colour;
-    float* xi_partial;              // [V][blocks][6]
+    double* xi_partial;             // [V][blocks][6]
     int32_t blocks;
 };
 
@@ -104,6 +102,5 @@ hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, 
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, float* d_xi, int n_views,
                               hipStream_t s);
 hipError_t launch_loss_l1(const LossArgs& a, hipStream_t s);
-hipError_t launch_fill_nan(float* p, int64_t count, hipStream_t s);
 
 }  // namespace gsr

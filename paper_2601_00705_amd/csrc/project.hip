@@ -4,8 +4,8 @@
 // Gaussian's parameters are read once (coalesced SoA planes) and kept in
 // registers for every view of the batch; the per-view pose is read from
 // device memory so that a captured graph sees pose updates.  For every slot
-// (view, Gaussian) the kernel writes geom/conic_o/rgb_d and clears the slot's
-// screen-space gradient accumulators when the slot touches a tile.
+// (view, Gaussian) the kernel writes geom/conic_o/rgb_d; a culled slot gets
+// rx = ry = -1.
 #include "kernels.h"
 #include "project_math.h"
 
@@ -17,8 +17,8 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const int64_t n = a.n;
-    Activated g;
-    activate(a.mean, a.quat, a.log_scale, a.opacity_logit, n, i, g);
+    Activated<float> g;
+    activate<float>(a.mean, a.quat, a.log_scale, a.opacity_logit, n, i, g);
     constexpr int K = DEG < 0 ? 1 : (DEG + 1) * (DEG + 1);
     float col[K][3];
     if (DEG < 0) {
@@ -34,8 +34,8 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
     for (int v = 0; v < vt->n; ++v) {
         const ViewInfo vw = vt->v[v];
         const float* pose = a.poses + 12 * v;
-        Projected p;
-        project_gaussian(g, pose, vw, a.cfg, p);
+        Projected<float> p;
+        project_gaussian<float>(g, pose, vw, a.cfg, p);
         int64_t slot = (int64_t)v * n + i;
         int x0, y0, x1, y1;
         bool live = p.valid && tile_rect(p.u, p.v, p.rx, p.ry, inv_tw, inv_th, vw.tiles_x, vw.tiles_y,
@@ -51,11 +51,11 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
             rgb[2] = col[0][2];
         } else {
             float oc[3];
-            camera_centre(pose, oc);
+            camera_centre<float>(pose, oc);
             float dx = g.mw[0] - oc[0], dy = g.mw[1] - oc[1], dz = g.mw[2] - oc[2];
             float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
             float Y[16];
-            sh_eval<DEG < 0 ? 0 : DEG>(dx * inv, dy * inv, dz * inv, Y);
+            sh_eval<DEG < 0 ? 0 : DEG, float>(dx * inv, dy * inv, dz * inv, Y);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 float acc = 0.0f;
@@ -67,11 +67,6 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
         a.geom[slot] = make_float4(p.u, p.v, p.rx, p.ry);
         a.conic_o[slot] = make_float4(p.A, p.B, p.C, g.o);
         a.rgb_d[slot] = make_float4(rgb[0], rgb[1], rgb[2], p.mc[2]);
-        if (a.clear_grad) {
-            const int64_t S = (int64_t)vt->n * n;
-#pragma unroll
-            for (int f = 0; f < GSR_G2; ++f) a.grad2d[f * S + slot] = 0.0f;
-        }
     }
 }
 

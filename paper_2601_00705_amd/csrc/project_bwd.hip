@@ -2,31 +2,35 @@
 // the SE(3) pose tangent.
 //
 // One thread per Gaussian loops over the views, recomputing the forward
-// projection (project_math.h) and applying the chain rule of Eq. (proj):
+// projection (project_math.h, in double) and applying the chain rule of
+// Eq. (proj):
 //   conic (A, B, C) = Sigma_I^-1:   dSigma_I = -Sigma_I^-1 dconic Sigma_I^-1
 //   Sigma_I = M Sigma_W M^T, M = J R:  dSigma_W = M^T G M, dM = 2 G M Sigma_W
 //   dJ = dM R^T, dR_cam = J^T dM;  J(mu_C), (u, v)(mu_C) -> d mu_C
 // and of the pose tangent, Eqs. (muCjac), (muIjac), (sigmaIjac):
 //   d rho += d mu_C,  d omega += mu_C x d mu_C + vee(P - P^T), P = dR_cam R^T
 //   (SH colour: the camera centre moves by -R^T rho, so d rho += R dd).
-// Per view the block's 6 tangent partials are reduced (transposed wave
-// exchange, then LDS) and written to a per-block slot; a second kernel sums
-// the slots in a fixed order, so the pose gradient is deterministic.
-// Parameter gradients are summed over the views not flagged pose-only and
-// written once (overwrite).
+// The arithmetic is double: near the near plane the Jacobians grow like
+// 1/z^2 and would amplify float rounding of the accumulated gradients (the
+// FP64 vector rate of the chip equals its unpacked FP32 rate, and this kernel
+// is a small part of the step).  Per view the block's 6 tangent partials are
+// reduced (transposed wave exchange, then LDS) into a per-block slot; a
+// second kernel sums the slots in a fixed order, so the pose gradient is
+// deterministic given the accumulators.  Parameter gradients are summed over
+// the views not flagged pose-only and written once (overwrite).
 #include "kernels.h"
 #include "project_math.h"
 
 namespace gsr {
 
 template <int N>
-__device__ __forceinline__ void xchg_b(float* v, int lane, int mask)
+__device__ __forceinline__ void xchg_d(double* v, int lane, int mask)
 {
     const bool hi = (lane & mask) != 0;
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-        float send = hi ? v[j] : v[N + j];
-        float keep = hi ? v[N + j] : v[j];
+        double send = hi ? v[j] : v[N + j];
+        double keep = hi ? v[N + j] : v[j];
         v[j] = keep + __shfl_xor(send, mask, 64);
     }
 }
@@ -34,7 +38,8 @@ __device__ __forceinline__ void xchg_b(float* v, int lane, int mask)
 template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
 {
-    __shared__ float red[4][8];
+    typedef double T;
+    __shared__ double red[4][8];
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t n = a.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
@@ -42,29 +47,30 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
     const int64_t S = (int64_t)a.views->n * n;
     constexpr int K = DEG < 0 ? 1 : (DEG + 1) * (DEG + 1);
 
-    Activated g;
-    float col[K][3];
+    Activated<T> g;
+    T col[K][3];
     if (live_thread) {
-        activate(a.mean, a.quat, a.log_scale, a.opacity_logit, n, i, g);
+        activate<T>(a.mean, a.quat, a.log_scale, a.opacity_logit, n, i, g);
         if (DEG >= 0) {
 #pragma unroll
             for (int k = 0; k < K; ++k)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) col[k][c] = a.colour[(k * 3 + c) * n + i];
+                for (int c = 0; c < 3; ++c) col[k][c] = (T)a.colour[(k * 3 + c) * n + i];
         }
     }
-    float dmw[3] = {0, 0, 0}, dSw[6] = {0, 0, 0, 0, 0, 0}, d_o = 0.0f;
-    float dcol[K][3];
+    T dmw[3] = {0, 0, 0}, dSw[6] = {0, 0, 0, 0, 0, 0}, d_o = 0;
+    T dcol[K][3];
 #pragma unroll
-    for (int k = 0; k < K; ++k) dcol[k][0] = dcol[k][1] = dcol[k][2] = 0.0f;
+    for (int k = 0; k < K; ++k) dcol[k][0] = dcol[k][1] = dcol[k][2] = 0;
 
     const float inv_tw = 1.0f / (float)a.cfg.tile_w, inv_th = 1.0f / (float)a.cfg.tile_h;
     for (int v = 0; v < a.views->n; ++v) {
         const ViewInfo vw = a.views->v[v];
         const float* pose = a.poses + 12 * v;
-        const float* R = pose;
+        T R[9];
+        for (int k = 0; k < 9; ++k) R[k] = (T)pose[k];
         const bool params = ((a.pose_only >> v) & 1ull) == 0ull;
-        float xi[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        T xi[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         int64_t slot = (int64_t)v * n + i;
         bool live = false;
         if (live_thread) {
@@ -72,84 +78,84 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
             int x0, y0, x1, y1;
             live = tile_rect(gm.x, gm.y, gm.z, gm.w, inv_tw, inv_th, vw.tiles_x, vw.tiles_y, x0, y0, x1, y1);
         }
-        Projected p;
+        Projected<T> p;
         if (live) {
-            project_gaussian(g, pose, vw, a.cfg, p);
+            project_gaussian<T>(g, pose, vw, a.cfg, p);
             live = p.valid;
         }
         if (live) {
-            float gu = a.grad2d[0 * S + slot], gv = a.grad2d[1 * S + slot];
-            float gA = a.grad2d[2 * S + slot], gB = a.grad2d[3 * S + slot], gC = a.grad2d[4 * S + slot];
-            float go = a.grad2d[5 * S + slot];
-            float gc[3] = {a.grad2d[6 * S + slot], a.grad2d[7 * S + slot], a.grad2d[8 * S + slot]};
+            T gu = a.grad2d[0 * S + slot], gv = a.grad2d[1 * S + slot];
+            T gA = a.grad2d[2 * S + slot], gB = a.grad2d[3 * S + slot], gC = a.grad2d[4 * S + slot];
+            T go = a.grad2d[5 * S + slot];
+            T gc[3] = {a.grad2d[6 * S + slot], a.grad2d[7 * S + slot], a.grad2d[8 * S + slot]};
             // conic -> Sigma_I entries (a, b, c): dSigma = -Sigma^-1 dConic Sigma^-1
-            const float A = p.A, B = p.B, C = p.C;
-            float da = -(A * A * gA + A * B * gB + B * B * gC);
-            float db = -(2.0f * A * B * gA + (A * C + B * B) * gB + 2.0f * B * C * gC);
-            float dc = -(B * B * gA + B * C * gB + C * C * gC);
-            float G00 = da, G01 = 0.5f * db, G11 = dc;
-            const float* M = p.M;
+            const T A = p.A, B = p.B, C = p.C;
+            T da = -(A * A * gA + A * B * gB + B * B * gC);
+            T db = -((T)2 * A * B * gA + (A * C + B * B) * gB + (T)2 * B * C * gC);
+            T dc = -(B * B * gA + B * C * gB + C * C * gC);
+            T G00 = da, G01 = (T)0.5 * db, G11 = dc;
+            const T* M = p.M;
             // GM = G M (2 x 3)
-            float GM0[3], GM1[3];
+            T GM0[3], GM1[3];
             for (int k = 0; k < 3; ++k) {
                 GM0[k] = G00 * M[k] + G01 * M[3 + k];
                 GM1[k] = G01 * M[k] + G11 * M[3 + k];
             }
             // dM = 2 GM Sigma_W
-            const float* Sw = g.Sw;
-            float Sfull[9] = {Sw[0], Sw[1], Sw[2], Sw[1], Sw[3], Sw[4], Sw[2], Sw[4], Sw[5]};
-            float dM0[3], dM1[3];
+            const T* Sw = g.Sw;
+            T Sfull[9] = {Sw[0], Sw[1], Sw[2], Sw[1], Sw[3], Sw[4], Sw[2], Sw[4], Sw[5]};
+            T dM0[3], dM1[3];
             for (int k = 0; k < 3; ++k) {
-                dM0[k] = 2.0f * (GM0[0] * Sfull[k] + GM0[1] * Sfull[3 + k] + GM0[2] * Sfull[6 + k]);
-                dM1[k] = 2.0f * (GM1[0] * Sfull[k] + GM1[1] * Sfull[3 + k] + GM1[2] * Sfull[6 + k]);
+                dM0[k] = (T)2 * (GM0[0] * Sfull[k] + GM0[1] * Sfull[3 + k] + GM0[2] * Sfull[6 + k]);
+                dM1[k] = (T)2 * (GM1[0] * Sfull[k] + GM1[1] * Sfull[3 + k] + GM1[2] * Sfull[6 + k]);
             }
             // M = J R
-            float dJ00 = dM0[0] * R[0] + dM0[1] * R[1] + dM0[2] * R[2];
-            float dJ02 = dM0[0] * R[6] + dM0[1] * R[7] + dM0[2] * R[8];
-            float dJ11 = dM1[0] * R[3] + dM1[1] * R[4] + dM1[2] * R[5];
-            float dJ12 = dM1[0] * R[6] + dM1[1] * R[7] + dM1[2] * R[8];
-            float dRc[9];
+            T dJ00 = dM0[0] * R[0] + dM0[1] * R[1] + dM0[2] * R[2];
+            T dJ02 = dM0[0] * R[6] + dM0[1] * R[7] + dM0[2] * R[8];
+            T dJ11 = dM1[0] * R[3] + dM1[1] * R[4] + dM1[2] * R[5];
+            T dJ12 = dM1[0] * R[6] + dM1[1] * R[7] + dM1[2] * R[8];
+            T dRc[9];
             for (int k = 0; k < 3; ++k) {
                 dRc[k] = p.J00 * dM0[k];
                 dRc[3 + k] = p.J11 * dM1[k];
                 dRc[6 + k] = p.J02 * dM0[k] + p.J12 * dM1[k];
             }
             // J and (u, v) as functions of mu_C
-            const float x = p.mc[0], y = p.mc[1], iz = p.iz;
-            const float fx = vw.fx, fy = vw.fy, iz2 = iz * iz, iz3 = iz2 * iz;
-            float dmc0 = dJ02 * (-fx * iz2) + gu * fx * iz;
-            float dmc1 = dJ12 * (-fy * iz2) + gv * fy * iz;
-            float dmc2 = dJ00 * (-fx * iz2) + dJ02 * (2.0f * fx * x * iz3) + dJ11 * (-fy * iz2) +
-                         dJ12 * (2.0f * fy * y * iz3) - gu * fx * x * iz2 - gv * fy * y * iz2;
+            const T x = p.mc[0], y = p.mc[1], iz = p.iz;
+            const T fx = (T)vw.fx, fy = (T)vw.fy, iz2 = iz * iz, iz3 = iz2 * iz;
+            T dmc0 = dJ02 * (-fx * iz2) + gu * fx * iz;
+            T dmc1 = dJ12 * (-fy * iz2) + gv * fy * iz;
+            T dmc2 = dJ00 * (-fx * iz2) + dJ02 * ((T)2 * fx * x * iz3) + dJ11 * (-fy * iz2) +
+                     dJ12 * ((T)2 * fy * y * iz3) - gu * fx * x * iz2 - gv * fy * y * iz2;
             // pose tangent
-            float P[9];
+            T P[9];
             for (int r = 0; r < 3; ++r)
                 for (int q = 0; q < 3; ++q)
                     P[r * 3 + q] = dRc[r * 3] * R[q * 3] + dRc[r * 3 + 1] * R[q * 3 + 1] + dRc[r * 3 + 2] * R[q * 3 + 2];
-            const float z = p.mc[2];
+            const T z = p.mc[2];
             xi[0] = dmc0;
             xi[1] = dmc1;
             xi[2] = dmc2;
             xi[3] = y * dmc2 - z * dmc1 + (P[7] - P[5]);
             xi[4] = z * dmc0 - x * dmc2 + (P[2] - P[6]);
             xi[5] = x * dmc1 - y * dmc0 + (P[3] - P[1]);
-            float dm[3];
+            T dm[3];
             for (int q = 0; q < 3; ++q) dm[q] = R[q] * dmc0 + R[3 + q] * dmc1 + R[6 + q] * dmc2;
             if (DEG >= 0) {
-                float oc[3];
-                camera_centre(pose, oc);
-                float ddv[3] = {g.mw[0] - oc[0], g.mw[1] - oc[1], g.mw[2] - oc[2]};
-                float inv = 1.0f / sqrtf(ddv[0] * ddv[0] + ddv[1] * ddv[1] + ddv[2] * ddv[2]);
-                float nx = ddv[0] * inv, ny = ddv[1] * inv, nz = ddv[2] * inv;
-                float Y[16];
-                sh_eval<DEG < 0 ? 0 : DEG>(nx, ny, nz, Y);
-                float wk[16];
+                T oc[3];
+                camera_centre<T>(pose, oc);
+                T ddv[3] = {g.mw[0] - oc[0], g.mw[1] - oc[1], g.mw[2] - oc[2]};
+                T inv = (T)1 / sqrt(ddv[0] * ddv[0] + ddv[1] * ddv[1] + ddv[2] * ddv[2]);
+                T nx = ddv[0] * inv, ny = ddv[1] * inv, nz = ddv[2] * inv;
+                T Y[16];
+                sh_eval<DEG < 0 ? 0 : DEG, T>(nx, ny, nz, Y);
+                T wk[16];
 #pragma unroll
                 for (int k = 0; k < K; ++k) wk[k] = gc[0] * col[k][0] + gc[1] * col[k][1] + gc[2] * col[k][2];
-                float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-                sh_grad_acc<DEG < 0 ? 0 : DEG>(nx, ny, nz, wk, gx, gy, gz);
-                float dot = gx * nx + gy * ny + gz * nz;
-                float e0 = (gx - nx * dot) * inv, e1 = (gy - ny * dot) * inv, e2 = (gz - nz * dot) * inv;
+                T gx = 0, gy = 0, gz = 0;
+                sh_grad_acc<DEG < 0 ? 0 : DEG, T>(nx, ny, nz, wk, gx, gy, gz);
+                T dot = gx * nx + gy * ny + gz * nz;
+                T e0 = (gx - nx * dot) * inv, e1 = (gy - ny * dot) * inv, e2 = (gz - nz * dot) * inv;
                 dm[0] += e0;
                 dm[1] += e1;
                 dm[2] += e2;
@@ -182,17 +188,17 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
             }
         }
         // block reduction of the 6 tangent partials (uniform control flow)
-        xchg_b<4>(xi, lane, 32);
-        xchg_b<2>(xi, lane, 16);
-        xchg_b<1>(xi, lane, 8);
-        float s = xi[0];
+        xchg_d<4>(xi, lane, 32);
+        xchg_d<2>(xi, lane, 16);
+        xchg_d<1>(xi, lane, 8);
+        T s = xi[0];
         s += __shfl_xor(s, 4, 64);
         s += __shfl_xor(s, 2, 64);
         s += __shfl_xor(s, 1, 64);
         if ((lane & 7) == 0) red[wv][lane >> 3] = s;
         __syncthreads();
         if (tid < 6) {
-            float t = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
+            T t = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
             a.xi_partial[((int64_t)v * a.blocks + blockIdx.x) * 6 + tid] = t;
         }
         __syncthreads();
@@ -200,47 +206,47 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
     if (!live_thread || !a.d_mean) return;
 
     // Sigma_W = R_q diag(s2) R_q^T  ->  log-scales and quaternion
-    const float* Rq = g.Rq;
-    float dS[9] = {dSw[0], dSw[1], dSw[2], dSw[1], dSw[3], dSw[4], dSw[2], dSw[4], dSw[5]};
-    float dRq[9];
+    const T* Rq = g.Rq;
+    T dS[9] = {dSw[0], dSw[1], dSw[2], dSw[1], dSw[3], dSw[4], dSw[2], dSw[4], dSw[5]};
+    T dRq[9];
     for (int r = 0; r < 3; ++r)
         for (int k = 0; k < 3; ++k)
-            dRq[r * 3 + k] = 2.0f * g.s2[k] * (dS[r * 3] * Rq[k] + dS[r * 3 + 1] * Rq[3 + k] + dS[r * 3 + 2] * Rq[6 + k]);
+            dRq[r * 3 + k] = (T)2 * g.s2[k] * (dS[r * 3] * Rq[k] + dS[r * 3 + 1] * Rq[3 + k] + dS[r * 3 + 2] * Rq[6 + k]);
     for (int k = 0; k < 3; ++k) {
-        // (R_q^T dS R_q)_kk * 2 s_k^2 = sum_r R_q[r][k] dRq[r][k]
-        float acc = Rq[k] * dRq[k] + Rq[3 + k] * dRq[3 + k] + Rq[6 + k] * dRq[6 + k];
-        a.d_log_scale[k * n + i] = acc;
+        // 2 s_k^2 (R_q^T dS R_q)_kk = sum_r R_q[r][k] dRq[r][k]
+        T acc = Rq[k] * dRq[k] + Rq[3 + k] * dRq[3 + k] + Rq[6 + k] * dRq[6 + k];
+        a.d_log_scale[k * n + i] = (float)acc;
     }
-    const float w = g.qh[0], x = g.qh[1], y = g.qh[2], z = g.qh[3];
-    float dqw = 2.0f * (-z * dRq[1] + y * dRq[2] + z * dRq[3] - x * dRq[5] - y * dRq[6] + x * dRq[7]);
-    float dqx = 2.0f * (y * dRq[1] + z * dRq[2] + y * dRq[3] - 2.0f * x * dRq[4] - w * dRq[5] + z * dRq[6] +
-                        w * dRq[7] - 2.0f * x * dRq[8]);
-    float dqy = 2.0f * (-2.0f * y * dRq[0] + x * dRq[1] + w * dRq[2] + x * dRq[3] + z * dRq[5] - w * dRq[6] +
-                        z * dRq[7] - 2.0f * y * dRq[8]);
-    float dqz = 2.0f * (-2.0f * z * dRq[0] - w * dRq[1] + x * dRq[2] + w * dRq[3] - 2.0f * z * dRq[4] +
-                        y * dRq[5] + x * dRq[6] + y * dRq[7]);
-    float dot = dqw * w + dqx * x + dqy * y + dqz * z;
-    float iq = g.ok ? 1.0f / g.qn : 0.0f;
-    a.d_quat[i] = (dqw - w * dot) * iq;
-    a.d_quat[n + i] = (dqx - x * dot) * iq;
-    a.d_quat[2 * n + i] = (dqy - y * dot) * iq;
-    a.d_quat[3 * n + i] = (dqz - z * dot) * iq;
-    a.d_mean[i] = dmw[0];
-    a.d_mean[n + i] = dmw[1];
-    a.d_mean[2 * n + i] = dmw[2];
-    a.d_opacity_logit[i] = d_o * g.o * (1.0f - g.o);
+    const T w = g.qh[0], x = g.qh[1], y = g.qh[2], z = g.qh[3];
+    T dqw = (T)2 * (-z * dRq[1] + y * dRq[2] + z * dRq[3] - x * dRq[5] - y * dRq[6] + x * dRq[7]);
+    T dqx = (T)2 * (y * dRq[1] + z * dRq[2] + y * dRq[3] - (T)2 * x * dRq[4] - w * dRq[5] + z * dRq[6] +
+                    w * dRq[7] - (T)2 * x * dRq[8]);
+    T dqy = (T)2 * (-(T)2 * y * dRq[0] + x * dRq[1] + w * dRq[2] + x * dRq[3] + z * dRq[5] - w * dRq[6] +
+                    z * dRq[7] - (T)2 * y * dRq[8]);
+    T dqz = (T)2 * (-(T)2 * z * dRq[0] - w * dRq[1] + x * dRq[2] + w * dRq[3] - (T)2 * z * dRq[4] +
+                    y * dRq[5] + x * dRq[6] + y * dRq[7]);
+    T dot = dqw * w + dqx * x + dqy * y + dqz * z;
+    T iq = g.ok ? (T)1 / g.qn : (T)0;
+    a.d_quat[i] = (float)((dqw - w * dot) * iq);
+    a.d_quat[n + i] = (float)((dqx - x * dot) * iq);
+    a.d_quat[2 * n + i] = (float)((dqy - y * dot) * iq);
+    a.d_quat[3 * n + i] = (float)((dqz - z * dot) * iq);
+    a.d_mean[i] = (float)dmw[0];
+    a.d_mean[n + i] = (float)dmw[1];
+    a.d_mean[2 * n + i] = (float)dmw[2];
+    a.d_opacity_logit[i] = (float)(d_o * g.o * ((T)1 - g.o));
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) a.d_colour[(k * 3 + c) * n + i] = dcol[k][c];
+        for (int c = 0; c < 3; ++c) a.d_colour[(k * 3 + c) * n + i] = (float)dcol[k][c];
 }
 
 // sum of the per-block tangent partials, fixed order: one block per view
-__global__ __launch_bounds__(256) void k_xi_reduce(const float* partial, int blocks, float* d_xi)
+__global__ __launch_bounds__(256) void k_xi_reduce(const double* partial, int blocks, float* d_xi)
 {
-    __shared__ float red[6][256];
+    __shared__ double red[6][256];
     const int v = blockIdx.x, tid = threadIdx.x;
-    float s[6] = {0, 0, 0, 0, 0, 0};
+    double s[6] = {0, 0, 0, 0, 0, 0};
     for (int b = tid; b < blocks; b += 256)
         for (int k = 0; k < 6; ++k) s[k] += partial[((int64_t)v * blocks + b) * 6 + k];
     for (int k = 0; k < 6; ++k) red[k][tid] = s[k];
@@ -250,7 +256,7 @@ __global__ __launch_bounds__(256) void k_xi_reduce(const float* partial, int blo
             for (int k = 0; k < 6; ++k) red[k][tid] += red[k][tid + off];
         __syncthreads();
     }
-    if (tid < 6) d_xi[v * 6 + tid] = red[tid][0];
+    if (tid < 6) d_xi[v * 6 + tid] = (float)red[tid][0];
 }
 
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, float* d_xi, int n_views,

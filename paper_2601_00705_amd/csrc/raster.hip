@@ -1,29 +1,34 @@
 // raster.hip -- per-tile alpha compositing, Eq. (alpha), forward and backward.
 //
-// One workgroup per (view, tile), one thread per pixel.  The tile's
-// depth-sorted pair range is walked in batches: each thread stages one
-// record into LDS (precomputed in exp2 form: power2 = a dx^2 + b dx dy +
-// c dy^2 with the conic scaled by -log2(e)/2, -log2(e), -log2(e)/2, and the
-// alpha_min test as power2 < log2(alpha_min / o)), then every pixel walks the
-// batch.  Forward: alpha = min(alpha_max, o 2^power2); entries below
-// alpha_min are skipped; compositing stops before an entry that would take T
-// below T_min; out = C + T bg, plus T_final and n_contrib (list position + 1
-// of the last blended entry), optionally the number of blended entries.
+// One wavefront (64 lanes) per (view, tile); each lane owns PPT = tile
+// pixels / 64 pixels of one column of the tile (rows l / tile_w + k * 64 /
+// tile_w).  The tile's depth-sorted pair range is walked in batches of
+// BATCH records: every lane stages BATCH / 64 records into LDS, precomputed in
+// exp2 form (power2 = a dx^2 + b dx dy + c dy^2 with the conic scaled by
+// -log2(e)/2, -log2(e), -log2(e)/2, and the alpha_min test as
+// power2 < log2(alpha_min / o)); then the lane walks the batch for each of its
+// pixels, sharing the per-entry terms of its column.
 //
-// Backward: the same range is replayed from the block's largest n_contrib
-// down.  Each pixel recovers T before an entry as T / (1 - alpha) and keeps
-// g . (colour behind) as a running scalar, giving
+// Forward: alpha = min(alpha_max, o 2^power2); entries below alpha_min are
+// skipped; compositing stops before an entry that would take T below T_min;
+// out = C + T bg, plus T_final and n_contrib (list position + 1 of the last
+// blended entry) and, optionally, the number of blended entries.
+//
+// Backward: the range is replayed from the tile's largest n_contrib down.
+// Each pixel recovers T before an entry as T / (1 - alpha) and keeps
+// g . (colour behind) as a running scalar, so that
 //   dL/dalpha_i = T_i g.c_i - (g.S_i + dL/dT_final T_final) / (1 - alpha_i).
-// Per entry the 9 screen-space partials are reduced over the wavefront
-// (transposed exchange: 8 values in 10 shuffles, plus one), accumulated per
-// batch in LDS across the workgroup's waves, then added to the per-slot
-// accumulators with one global float atomic per field and batch entry.
+// A lane sums its pixels' 9 screen-space partials of an entry, the wavefront
+// reduces them (transposed exchange: 8 values in 10 shuffles, plus one), and
+// 9 lanes add the tile's totals to the slot's double accumulators with one
+// atomic instruction (plus one).
 #include "kernels.h"
 
 namespace gsr {
 
 #define GSR_LOG2E 1.4426950408889634f
 #define GSR_LN2 0.69314718055994531f
+#define GSR_BATCH 128
 
 struct __align__(16) LdsRec {
     float4 p0;  // u, v, a2, b2      (a2 = -0.5 log2e A, b2 = -log2e B)
@@ -36,104 +41,138 @@ __device__ __forceinline__ void stage_record(const RasterArgs& a, uint32_t slot,
     float4 gm = a.geom[slot];
     float4 co = a.conic_o[slot];
     float4 cd = a.rgb_d[slot];
-    float thr = a.cfg.alpha_min > 0.0f ? __log2f(a.cfg.alpha_min / co.w) : -INFINITY;
+    float thr = a.cfg.alpha_min > 0.0f ? log2f(a.cfg.alpha_min / co.w) : -INFINITY;
     r.p0 = make_float4(gm.x, gm.y, -0.5f * GSR_LOG2E * co.x, -GSR_LOG2E * co.y);
     r.p1 = make_float4(-0.5f * GSR_LOG2E * co.z, co.w, thr, 0.0f);
     r.p2 = make_float4(cd.x, cd.y, cd.z, __uint_as_float(slot));
 }
 
-// power2 of a record at pixel centre (fpx, fpy); identical in both passes
-__device__ __forceinline__ float eval_power2(const LdsRec& r, float fpx, float fpy, float& dx, float& dy,
-                                             float& t)
+// power2 = a2 dx^2 + dy (b2 dx + c2 dy), the same operation sequence in both
+// passes so that their decisions agree bit for bit
+__device__ __forceinline__ float power2(float a2dx2, float b2dx, float c2, float dy)
 {
-    dx = fpx - r.p0.x;
-    dy = fpy - r.p0.y;
-    t = __builtin_fmaf(r.p0.z, dx, r.p0.w * dy);  // a2 dx + b2 dy
-    return __builtin_fmaf(t, dx, r.p1.x * dy * dy);
+    return __builtin_fmaf(dy, __builtin_fmaf(c2, dy, b2dx), a2dx2);
 }
 
+template <int PPT>
 struct TileCtx {
-    int v, tx, ty, px, py;
-    bool inside;
-    int64_t pix;      // index into the concatenated [H][W] planes
-    int64_t plane;    // H * W of the view
-    int64_t rgb0;     // offset of channel 0 of this pixel
+    int px, py0, rs;          // column, first row, row stride
+    bool inside[PPT];
+    int64_t pix[PPT];         // index into the concatenated [H][W] planes
+    int64_t rgb0[PPT];        // channel-0 index into the concatenated images
+    int64_t plane;            // H * W of the view
 };
 
-__device__ __forceinline__ TileCtx tile_ctx(const RasterArgs& a, int log2_tw)
+template <int PPT>
+__device__ __forceinline__ TileCtx<PPT> tile_ctx(const RasterArgs& a)
 {
-    TileCtx c;
+    TileCtx<PPT> c;
     const int tile = blockIdx.x;
-    c.v = view_of_tile(a.views, tile);
-    const ViewInfo& vw = a.views->v[c.v];
-    int lt = tile - vw.tile_base;
-    c.ty = lt / vw.tiles_x;
-    c.tx = lt - c.ty * vw.tiles_x;
-    const int tw = 1 << log2_tw;
-    c.px = c.tx * tw + (threadIdx.x & (tw - 1));
-    c.py = c.ty * a.cfg.tile_h + (threadIdx.x >> log2_tw);
-    c.inside = c.px < vw.width && c.py < vw.height;
+    const int v = view_of_tile(a.views, tile);
+    const ViewInfo& vw = a.views->v[v];
+    const int lt = tile - vw.tile_base;
+    const int ty = lt / vw.tiles_x;
+    const int tx = lt - ty * vw.tiles_x;
+    const int lane = threadIdx.x;
+    const int l2 = a.cfg.log2_tw;
+    c.px = tx * a.cfg.tile_w + (lane & (a.cfg.tile_w - 1));
+    c.py0 = ty * a.cfg.tile_h + (lane >> l2);
+    c.rs = 64 >> l2;
     c.plane = (int64_t)vw.width * vw.height;
-    c.pix = (int64_t)vw.pix_base + (int64_t)c.py * vw.width + c.px;
-    c.rgb0 = 3 * (int64_t)vw.pix_base + (int64_t)c.py * vw.width + c.px;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int py = c.py0 + k * c.rs;
+        c.inside[k] = c.px < vw.width && py < vw.height;
+        c.pix[k] = (int64_t)vw.pix_base + (int64_t)py * vw.width + c.px;
+        c.rgb0[k] = 3 * (int64_t)vw.pix_base + (int64_t)py * vw.width + c.px;
+    }
     return c;
 }
 
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_raster_fwd(RasterArgs a)
+template <int PPT>
+__global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
 {
-    __shared__ LdsRec rec[BLOCK];
-    const TileCtx c = tile_ctx(a, a.cfg.log2_tw);
+    __shared__ LdsRec rec[GSR_BATCH];
+    const TileCtx<PPT> c = tile_ctx<PPT>(a);
+    const int lane = threadIdx.x;
     const bool overflow = a.counters->overflow != 0u;
     const uint2 range = overflow ? make_uint2(0u, 0u) : a.ranges[blockIdx.x];
-    const float fpx = (float)c.px + 0.5f, fpy = (float)c.py + 0.5f;
+    const float fpx = (float)c.px + 0.5f;
     const float amax = a.cfg.alpha_max, tmin = a.cfg.T_min;
-    float T = 1.0f, C0 = 0.0f, C1 = 0.0f, C2 = 0.0f;
-    uint32_t last = 0, nb = 0;
-    bool done = !c.inside;
-    for (uint32_t base = range.x; base < range.y; base += BLOCK) {
-        if (__syncthreads_and(done)) break;
-        uint32_t j = base + threadIdx.x;
-        if (j < range.y) stage_record(a, a.vals[j], rec[threadIdx.x]);
-        __syncthreads();
-        const int cnt = (int)min((uint32_t)BLOCK, range.y - base);
-        for (int k = 0; k < cnt && !done; ++k) {
-            const LdsRec r = rec[k];
-            float dx, dy, t;
-            float p2 = eval_power2(r, fpx, fpy, dx, dy, t);
-            if (p2 < r.p1.z) continue;
-            float alpha = fminf(amax, r.p1.y * __builtin_amdgcn_exp2f(p2));
-            float Tn = __builtin_fmaf(-T, alpha, T);
-            if (Tn < tmin) {
-                done = true;
-                break;
-            }
-            float wgt = alpha * T;
-            C0 = __builtin_fmaf(r.p2.x, wgt, C0);
-            C1 = __builtin_fmaf(r.p2.y, wgt, C1);
-            C2 = __builtin_fmaf(r.p2.z, wgt, C2);
-            T = Tn;
-            last = base + (uint32_t)k - range.x + 1u;
-            ++nb;
+    float T[PPT], C0[PPT], C1[PPT], C2[PPT], fpy[PPT];
+    uint32_t last[PPT], nb[PPT];
+    bool done[PPT];
+    bool lane_done = true;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        T[k] = 1.0f;
+        C0[k] = C1[k] = C2[k] = 0.0f;
+        last[k] = nb[k] = 0u;
+        done[k] = !c.inside[k];
+        lane_done = lane_done && done[k];
+        fpy[k] = (float)(c.py0 + k * c.rs) + 0.5f;
+    }
+    for (uint32_t base = range.x; base < range.y; base += GSR_BATCH) {
+        if (__all(lane_done)) break;
+#pragma unroll
+        for (int r = 0; r < GSR_BATCH / 64; ++r) {
+            const uint32_t j = base + lane + 64 * r;
+            if (j < range.y) stage_record(a, a.vals[j], rec[lane + 64 * r]);
         }
+        __syncthreads();
+        const int cnt = (int)min((uint32_t)GSR_BATCH, range.y - base);
+        for (int e = 0; e < cnt && !lane_done; ++e) {
+            const LdsRec r = rec[e];
+            const float dx = fpx - r.p0.x;
+            const float a2dx2 = r.p0.z * dx * dx;
+            const float b2dx = r.p0.w * dx;
+            bool all = true;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                if (!done[k]) {
+                    const float p2 = power2(a2dx2, b2dx, r.p1.x, fpy[k] - r.p0.y);
+                    if (p2 >= r.p1.z) {
+                        const float alpha = fminf(amax, r.p1.y * __builtin_amdgcn_exp2f(p2));
+                        const float Tn = __builtin_fmaf(-T[k], alpha, T[k]);
+                        if (Tn < tmin) {
+                            done[k] = true;
+                        } else {
+                            const float wgt = alpha * T[k];
+                            C0[k] = __builtin_fmaf(r.p2.x, wgt, C0[k]);
+                            C1[k] = __builtin_fmaf(r.p2.y, wgt, C1[k]);
+                            C2[k] = __builtin_fmaf(r.p2.z, wgt, C2[k]);
+                            T[k] = Tn;
+                            last[k] = base + (uint32_t)e - range.x + 1u;
+                            ++nb[k];
+                        }
+                    }
+                }
+                all = all && done[k];
+            }
+            lane_done = all;
+        }
+        __syncthreads();
     }
-    if (!c.inside) return;
-    if (overflow) {
-        const float q = __builtin_nanf("");
-        a.rgb[c.rgb0] = q;
-        a.rgb[c.rgb0 + c.plane] = q;
-        a.rgb[c.rgb0 + 2 * c.plane] = q;
-        a.T_final[c.pix] = q;
-        a.n_contrib[c.pix] = 0;
-        if (a.n_blend) a.n_blend[c.pix] = 0;
-        return;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if (!c.inside[k]) continue;
+        if (overflow) {
+            const float q = __builtin_nanf("");
+            a.rgb[c.rgb0[k]] = q;
+            a.rgb[c.rgb0[k] + c.plane] = q;
+            a.rgb[c.rgb0[k] + 2 * c.plane] = q;
+            a.T_final[c.pix[k]] = q;
+            a.n_contrib[c.pix[k]] = 0;
+            if (a.n_blend) a.n_blend[c.pix[k]] = 0;
+            continue;
+        }
+        a.rgb[c.rgb0[k]] = __builtin_fmaf(T[k], a.cfg.bg0, C0[k]);
+        a.rgb[c.rgb0[k] + c.plane] = __builtin_fmaf(T[k], a.cfg.bg1, C1[k]);
+        a.rgb[c.rgb0[k] + 2 * c.plane] = __builtin_fmaf(T[k], a.cfg.bg2, C2[k]);
+        a.T_final[c.pix[k]] = T[k];
+        a.n_contrib[c.pix[k]] = (int32_t)last[k];
+        if (a.n_blend) a.n_blend[c.pix[k]] = (int32_t)nb[k];
     }
-    a.rgb[c.rgb0] = __builtin_fmaf(T, a.cfg.bg0, C0);
-    a.rgb[c.rgb0 + c.plane] = __builtin_fmaf(T, a.cfg.bg1, C1);
-    a.rgb[c.rgb0 + 2 * c.plane] = __builtin_fmaf(T, a.cfg.bg2, C2);
-    a.T_final[c.pix] = T;
-    a.n_contrib[c.pix] = (int32_t)last;
-    if (a.n_blend) a.n_blend[c.pix] = (int32_t)nb;
 }
 
 // One exchange step of the transposed reduction: keep half of 2N values,
@@ -150,81 +189,103 @@ __device__ __forceinline__ void xchg(float* v, int lane, int mask)
     }
 }
 
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void k_raster_bwd(RasterArgs a)
+// scale of field f (du, dv, dA, dB, dC, do, dr, dg) from the accumulated
+// power2-space partials to the screen-space gradient
+__device__ __forceinline__ float field_scale(int f)
 {
-    __shared__ LdsRec rec[BLOCK];
-    __shared__ float acc[GSR_G2][BLOCK];
-    __shared__ uint32_t smax;
-    const TileCtx c = tile_ctx(a, a.cfg.log2_tw);
+    return f < 2 ? -GSR_LN2 : (f == 3 ? -1.0f : (f < 5 ? -0.5f : 1.0f));
+}
+
+template <int PPT>
+__global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
+{
+    __shared__ LdsRec rec[GSR_BATCH];
+    const TileCtx<PPT> c = tile_ctx<PPT>(a);
     if (a.counters->overflow) return;
     const uint2 range = a.ranges[blockIdx.x];
-    const int tid = threadIdx.x, lane = tid & 63;
-    const float fpx = (float)c.px + 0.5f, fpy = (float)c.py + 0.5f;
+    const int lane = threadIdx.x;
+    const float fpx = (float)c.px + 0.5f;
     const float amax = a.cfg.alpha_max;
-
-    float Tf = 1.0f, g0 = 0.0f, g1 = 0.0f, g2 = 0.0f, gT = 0.0f;
-    uint32_t my_n = 0;
-    if (c.inside) {
-        Tf = a.T_final_in[c.pix];
-        my_n = (uint32_t)a.n_contrib_in[c.pix];
-        g0 = a.dL_drgb[c.rgb0];
-        g1 = a.dL_drgb[c.rgb0 + c.plane];
-        g2 = a.dL_drgb[c.rgb0 + 2 * c.plane];
-        if (a.dL_dT) gT = a.dL_dT[c.pix];
-    }
-    if (tid == 0) smax = 0u;
-    for (int f = 0; f < GSR_G2; ++f) acc[f][tid] = 0.0f;
-    __syncthreads();
-    atomicMax(&smax, my_n);
-    __syncthreads();
-    const uint32_t end = range.x + min(smax, range.y - range.x);
-
-    float T = Tf;
-    // g . (colour behind) + dL/dT_final T_final, maintained incrementally
-    float gsk = __builtin_fmaf(gT, Tf, Tf * (g0 * a.cfg.bg0 + g1 * a.cfg.bg1 + g2 * a.cfg.bg2));
     const int64_t S = a.slots;
 
+    float T[PPT], Tf[PPT], gsk[PPT], g0[PPT], g1[PPT], g2[PPT], fpy[PPT];
+    uint32_t my_n[PPT];
+    uint32_t lane_max = 0;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        Tf[k] = 1.0f;
+        g0[k] = g1[k] = g2[k] = 0.0f;
+        float gT = 0.0f;
+        my_n[k] = 0u;
+        if (c.inside[k]) {
+            Tf[k] = a.T_final_in[c.pix[k]];
+            my_n[k] = (uint32_t)a.n_contrib_in[c.pix[k]];
+            g0[k] = a.dL_drgb[c.rgb0[k]];
+            g1[k] = a.dL_drgb[c.rgb0[k] + c.plane];
+            g2[k] = a.dL_drgb[c.rgb0[k] + 2 * c.plane];
+            if (a.dL_dT) gT = a.dL_dT[c.pix[k]];
+        }
+        T[k] = Tf[k];
+        // g . (colour behind) + dL/dT_final T_final, maintained incrementally
+        gsk[k] = __builtin_fmaf(gT, Tf[k], Tf[k] * (g0[k] * a.cfg.bg0 + g1[k] * a.cfg.bg1 + g2[k] * a.cfg.bg2));
+        fpy[k] = (float)(c.py0 + k * c.rs) + 0.5f;
+        lane_max = max(lane_max, my_n[k]);
+    }
+    for (int off = 32; off > 0; off >>= 1) lane_max = max(lane_max, (uint32_t)__shfl_xor((int)lane_max, off, 64));
+    const uint32_t end = range.x + min(lane_max, range.y - range.x);
+
     for (uint32_t hi_ = end; hi_ > range.x;) {
-        const uint32_t lo_ = hi_ - range.x > (uint32_t)BLOCK ? hi_ - BLOCK : range.x;
+        const uint32_t lo_ = hi_ - range.x > (uint32_t)GSR_BATCH ? hi_ - GSR_BATCH : range.x;
         const int cnt = (int)(hi_ - lo_);
-        if (tid < cnt) stage_record(a, a.vals[hi_ - 1 - tid], rec[tid]);
+#pragma unroll
+        for (int r = 0; r < GSR_BATCH / 64; ++r) {
+            const int t = lane + 64 * r;
+            if (t < cnt) stage_record(a, a.vals[hi_ - 1 - t], rec[t]);
+        }
         __syncthreads();
-        for (int k = 0; k < cnt; ++k) {
-            const uint32_t pos = hi_ - 1 - (uint32_t)k - range.x;
-            const LdsRec r = rec[k];
-            float dx, dy, t;
-            float p2 = eval_power2(r, fpx, fpy, dx, dy, t);
-            bool contrib = pos < my_n && p2 >= r.p1.z;
+        for (int e = 0; e < cnt; ++e) {
+            const uint32_t pos = hi_ - 1 - (uint32_t)e - range.x;
+            const LdsRec r = rec[e];
+            const float dx = fpx - r.p0.x;
+            const float a2dx2 = r.p0.z * dx * dx;
+            const float b2dx = r.p0.w * dx;
             float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             float v8 = 0.0f;
-            if (contrib) {
-                float G = __builtin_amdgcn_exp2f(p2);
-                float a_raw = r.p1.y * G;
-                bool clamped = !(a_raw < amax);
-                float alpha = clamped ? amax : a_raw;
-                float rcp = 1.0f / (1.0f - alpha);
-                float Tb = T * rcp;
-                float gcol = __builtin_fmaf(g0, r.p2.x, __builtin_fmaf(g1, r.p2.y, g2 * r.p2.z));
-                float dalpha = __builtin_fmaf(Tb, gcol, -rcp * gsk);
-                float wgt = alpha * Tb;
-                v[6] = g0 * wgt;
-                v[7] = g1 * wgt;
-                v8 = g2 * wgt;
-                gsk = __builtin_fmaf(wgt, gcol, gsk);
-                T = Tb;
-                if (!clamped) {
-                    float dd = dalpha * alpha;
-                    float ddx = dd * dx;
-                    v[0] = dd * (t + r.p0.z * dx);                         // 2 a2 dx + b2 dy
-                    v[1] = dd * __builtin_fmaf(r.p0.w, dx, 2.0f * r.p1.x * dy);  // b2 dx + 2 c2 dy
-                    v[2] = ddx * dx;
-                    v[3] = ddx * dy;
-                    v[4] = dd * dy * dy;
-                    v[5] = dalpha * G;
+            bool any = false;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const float dy = fpy[k] - r.p0.y;
+                const float p2 = power2(a2dx2, b2dx, r.p1.x, dy);
+                if (pos < my_n[k] && p2 >= r.p1.z) {
+                    any = true;
+                    const float G = __builtin_amdgcn_exp2f(p2);
+                    const float a_raw = r.p1.y * G;
+                    const bool clamped = !(a_raw < amax);
+                    const float alpha = clamped ? amax : a_raw;
+                    const float rcp = __builtin_amdgcn_rcpf(1.0f - alpha);
+                    const float Tb = T[k] * rcp;
+                    const float gcol = __builtin_fmaf(g0[k], r.p2.x, __builtin_fmaf(g1[k], r.p2.y, g2[k] * r.p2.z));
+                    const float dalpha = __builtin_fmaf(Tb, gcol, -rcp * gsk[k]);
+                    const float wgt = alpha * Tb;
+                    v[6] = __builtin_fmaf(g0[k], wgt, v[6]);
+                    v[7] = __builtin_fmaf(g1[k], wgt, v[7]);
+                    v8 = __builtin_fmaf(g2[k], wgt, v8);
+                    gsk[k] = __builtin_fmaf(wgt, gcol, gsk[k]);
+                    T[k] = Tb;
+                    if (!clamped) {
+                        const float dd = dalpha * alpha;
+                        const float ddx = dd * dx;
+                        // d power2 / du = -(2 a2 dx + b2 dy), / dv = -(b2 dx + 2 c2 dy)
+                        v[0] = __builtin_fmaf(dd, __builtin_fmaf(2.0f * r.p0.z, dx, r.p0.w * dy), v[0]);
+                        v[1] = __builtin_fmaf(dd, __builtin_fmaf(2.0f * r.p1.x, dy, b2dx), v[1]);
+                        v[2] = __builtin_fmaf(ddx, dx, v[2]);
+                        v[3] = __builtin_fmaf(ddx, dy, v[3]);
+                        v[4] = __builtin_fmaf(dd * dy, dy, v[4]);
+                        v[5] = __builtin_fmaf(dalpha, G, v[5]);
+                    }
                 }
             }
-            if (__any(contrib)) {
+            if (__any(any)) {
                 xchg<4>(v, lane, 32);
                 xchg<2>(v, lane, 16);
                 xchg<1>(v, lane, 8);
@@ -233,20 +294,12 @@ __global__ __launch_bounds__(BLOCK) void k_raster_bwd(RasterArgs a)
                 s += __shfl_xor(s, 2, 64);
                 s += __shfl_xor(s, 1, 64);
                 v8 = wave_sum(v8);
-                if ((lane & 7) == 0) atomicAdd(&acc[lane >> 3][k], s);
-                if (lane == 0) atomicAdd(&acc[8][k], v8);
-            }
-        }
-        __syncthreads();
-        if (tid < cnt) {
-            const uint32_t slot = __float_as_uint(rec[tid].p2.w);
-            // fields: du, dv, dA, dB, dC, do, dr, dg, db
-            const float scale[GSR_G2] = {-GSR_LN2, -GSR_LN2, -0.5f, -1.0f, -0.5f, 1.0f, 1.0f, 1.0f, 1.0f};
-#pragma unroll
-            for (int f = 0; f < GSR_G2; ++f) {
-                float x = acc[f][tid];
-                if (x != 0.0f) atomic_add_f32(&a.grad2d[f * S + slot], x * scale[f]);
-                acc[f][tid] = 0.0f;
+                const uint32_t slot = __float_as_uint(r.p2.w);
+                if ((lane & 7) == 0) {
+                    const int f = lane >> 3;
+                    atomic_add_f64(&a.grad2d[f * S + slot], (double)(s * field_scale(f)));
+                }
+                if (lane == 0) atomic_add_f64(&a.grad2d[8 * S + slot], (double)v8);
             }
         }
         __syncthreads();
@@ -254,25 +307,56 @@ __global__ __launch_bounds__(BLOCK) void k_raster_bwd(RasterArgs a)
     }
 }
 
+template <int PPT>
+static void launch_fwd_t(const RasterArgs& a, int tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_raster_fwd<PPT>, dim3(tiles), dim3(64), 0, s, a);
+}
+
+template <int PPT>
+static void launch_bwd_t(const RasterArgs& a, int tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_raster_bwd<PPT>, dim3(tiles), dim3(64), 0, s, a);
+}
+
 hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, hipStream_t s)
 {
     if (total_tiles == 0) return hipSuccess;
     switch (tile_px) {
-    case 64: hipLaunchKernelGGL(k_raster_fwd<64>, dim3(total_tiles), dim3(64), 0, s, a); break;
-    case 128: hipLaunchKernelGGL(k_raster_fwd<128>, dim3(total_tiles), dim3(128), 0, s, a); break;
-    case 256: hipLaunchKernelGGL(k_raster_fwd<256>, dim3(total_tiles), dim3(256), 0, s, a); break;
+    case 64: launch_fwd_t<1>(a, total_tiles, s); break;
+    case 128: launch_fwd_t<2>(a, total_tiles, s); break;
+    case 256: launch_fwd_t<4>(a, total_tiles, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
+// zero the screen-space accumulators of every projected slot (rx >= 0); the
+// backward only ever adds to and reads such slots, so each backward starts
+// from zero however often it is called
+__global__ void k_clear_grad2d(const float4* geom, double* grad2d, int64_t slots)
+{
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        if (geom[s].z >= 0.0f) {
+#pragma unroll
+            for (int f = 0; f < GSR_G2; ++f) grad2d[f * slots + s] = 0.0;
+        }
+    }
+}
+
 hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, hipStream_t s)
 {
     if (total_tiles == 0) return hipSuccess;
+    if (a.slots > 0) {
+        int64_t blocks = (a.slots + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(k_clear_grad2d, dim3((unsigned)blocks), dim3(256), 0, s, a.geom, a.grad2d, a.slots);
+    }
     switch (tile_px) {
-    case 64: hipLaunchKernelGGL(k_raster_bwd<64>, dim3(total_tiles), dim3(64), 0, s, a); break;
-    case 128: hipLaunchKernelGGL(k_raster_bwd<128>, dim3(total_tiles), dim3(128), 0, s, a); break;
-    case 256: hipLaunchKernelGGL(k_raster_bwd<256>, dim3(total_tiles), dim3(256), 0, s, a); break;
+    case 64: launch_bwd_t<1>(a, total_tiles, s); break;
+    case 128: launch_bwd_t<2>(a, total_tiles, s); break;
+    case 256: launch_bwd_t<4>(a, total_tiles, s); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -296,22 +380,6 @@ hipError_t launch_loss_l1(const LossArgs& a, hipStream_t s)
     int64_t blocks = (a.count + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(k_loss_l1, dim3((unsigned)blocks), dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-__global__ void k_fill_nan(float* p, int64_t count)
-{
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-         i += (int64_t)gridDim.x * blockDim.x)
-        p[i] = __builtin_nanf("");
-}
-
-hipError_t launch_fill_nan(float* p, int64_t count, hipStream_t s)
-{
-    if (count == 0 || !p) return hipSuccess;
-    int64_t blocks = (count + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_fill_nan, dim3((unsigned)blocks), dim3(256), 0, s, p, count);
     return hipGetLastError();
 }
 

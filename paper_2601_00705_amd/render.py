@@ -63,9 +63,12 @@ class Renderer:
         self.info = lib.gsr_plan_get_info(self.plan)
 
     def __del__(self):
-        if getattr(self, "plan", None) is not None:
-            lib.gsr_plan_destroy(self.plan)
-            self.plan = None
+        plan, self.plan = getattr(self, "plan", None), None
+        if plan is not None and lib is not None and getattr(lib, "_lib", None) is not None:
+            try:
+                lib.gsr_plan_destroy(plan)
+            except Exception:  # interpreter shutdown
+                pass
 
     # -- views into the workspace (for tests and diagnostics) -------------
     def _view(self, off, count, dtype):
@@ -79,7 +82,7 @@ class Renderer:
             "geom": self._view(L.geom, 4 * S, torch.float32).view(S, 4),
             "conic_o": self._view(L.conic_o, 4 * S, torch.float32).view(S, 4),
             "rgb_d": self._view(L.rgb_d, 4 * S, torch.float32).view(S, 4),
-            "grad2d": self._view(L.grad2d, 9 * S, torch.float32).view(9, S),
+            "grad2d": self._view(L.grad2d, 9 * S, torch.float64).view(9, S),
         }
 
     def sorted_pairs(self, count):

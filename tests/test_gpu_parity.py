@@ -36,24 +36,30 @@ def _gpu_fwd(params, cams, poses, cfg, capacity=None, want_blend=True):
 
 
 def _check_forward(name, params, cams, poses, cfg, capacity=None):
+    """Strict 1e-4 on pixels whose FP64 decisions are clear of their
+    thresholds; elsewhere a pixel may differ only if the oracle records a
+    near-threshold decision for it, and such pixels stay rare."""
     say(f"[fwd] {name}: n={params['opacity_logit'].shape[0]} views={len(cams)}")
     R, P, poses_d, rgb, T, nc, nb = _gpu_fwd(params, cams, poses, cfg, capacity)
     ref = oracle.render(params, cams, poses, oracle_cfg(cfg))
     ok = pixel_mask(ref["margin"], cams)
-    ok3 = pixel_mask(ref["margin"], cams, 3)
     rgb_g = rgb.cpu().numpy().astype(np.float64)
     T_g = T.cpu().numpy().astype(np.float64)
-    err_img = np.abs(rgb_g - ref["rgb"])[ok3]
-    err_T = np.abs(T_g - ref["T_final"])[ok]
-    excluded = 1.0 - ok.mean()
-    say(f"  max|d rgb|={err_img.max() if err_img.size else 0:.3g} max|d T|={err_T.max() if err_T.size else 0:.3g}"
-        f" excluded={excluded:.2%}")
-    assert np.all(np.isfinite(rgb_g)) and np.all(np.isfinite(T_g))
-    assert err_img.size == 0 or err_img.max() <= IMG_ATOL
-    assert err_T.size == 0 or err_T.max() <= IMG_ATOL
     nb_g = nb.cpu().numpy()
-    np.testing.assert_array_equal(nb_g[ok], ref["n_blend"][ok])
-    assert excluded < 0.01
+    assert np.all(np.isfinite(rgb_g)) and np.all(np.isfinite(T_g))
+    d_rgb = np.abs(rgb_g - ref["rgb"])
+    per_px = np.zeros_like(T_g)
+    off = 0
+    for c in cams:
+        hw = c["width"] * c["height"]
+        per_px[off:off + hw] = d_rgb[3 * off:3 * off + 3 * hw].reshape(3, hw).max(axis=0)
+        off += hw
+    per_px = np.maximum(per_px, np.abs(T_g - ref["T_final"]))
+    flipped = (per_px > IMG_ATOL) | (nb_g != ref["n_blend"])
+    say(f"  max|d| on clear pixels={per_px[ok].max() if ok.any() else 0:.3g}; near-threshold pixels "
+        f"{1 - ok.mean():.2%}; pixels differing {flipped.mean():.4%} (max {per_px.max():.3g})")
+    assert not np.any(flipped & ok), "a pixel with clear decisions differs"
+    assert flipped.mean() <= 1e-3
     return R, P, poses_d, rgb, T, nc, ref, ok
 
 
@@ -112,14 +118,15 @@ def test_bin_bitexact_shared_records(tile):
 
 
 def test_bin_bitexact_many_pairs():
-    """Several sort blocks per digit and a ragged last block: 1.3M pairs over
-    a 1200x680 view with 16x16 tiles (15 key bits for the tile)."""
+    """Many sort blocks per digit and a ragged last block: over a million
+    pairs over a 1200x680 and a 640x480 view with 16x16 tiles."""
     cams = [{"width": 1200, "height": 680, "fx": 1, "fy": 1, "cx": 0, "cy": 0},
             {"width": 640, "height": 480, "fx": 1, "fy": 1, "cx": 0, "cy": 0}]
-    n = 60_000
+    n = 120_000
     rng = np.random.default_rng(11)
     u, v, rx, ry, depth = _records(cams, n, rng)
-    rx *= 2
+    rx *= 3
+    ry *= 2
     say("[bin] many pairs")
     R = Renderer(n, cams, Config(), pair_capacity=4_000_000)
     rec = R.records()
@@ -269,9 +276,18 @@ def _check_backward(name, params, cams, poses, cfg, seed, pose_only=None, with_d
     dT = scenes.upstream_grad(seed + 1, Ptot) if with_dT else None
     grads = {k: torch.empty_like(v) for k, v in P.items()}
     d_xi = torch.empty(len(cams), 6, device="cuda")
-    R.render_bwd(P, poses_d, T, nc, torch.from_numpy(dL).cuda(),
-                 None if dT is None else torch.from_numpy(dT).cuda(), pose_only, grads, d_xi)
+    dL_d = torch.from_numpy(dL).cuda()
+    dT_d = None if dT is None else torch.from_numpy(dT).cuda()
+    R.render_bwd(P, poses_d, T, nc, dL_d, dT_d, pose_only, grads, d_xi)
+    # a second backward of the same forward returns the same gradients
+    grads2 = {k: torch.empty_like(v) for k, v in P.items()}
+    d_xi2 = torch.empty_like(d_xi)
+    R.render_bwd(P, poses_d, T, nc, dL_d, dT_d, pose_only, grads2, d_xi2)
     torch.cuda.synchronize()
+    for k in grads:
+        scale = float(grads[k].abs().max()) + 1e-30
+        assert float((grads2[k] - grads[k]).abs().max()) <= 1e-5 * scale, k
+    assert float((d_xi2 - d_xi).abs().max()) <= 1e-5 * (float(d_xi.abs().max()) + 1e-30)
     ref = oracle.backward(params, cams, poses, oracle_cfg(cfg), dL.astype(np.float64),
                           None if dT is None else dT.astype(np.float64), pose_only=pose_only)
     worst = {}
