@@ -81,12 +81,82 @@ __device__ __forceinline__ int view_of_tile(const ViewTable* vt, int tile)
 }
 
 // ---------------------------------------------------------------------------
-// wave64 helpers
+// wave64 cross-lane helpers on VALU instructions (no LDS round trip):
+// v_permlane32_swap / v_permlane16_swap exchange lane i with lane i ^ 32 /
+// i ^ 16 between their two operands; DPP row_mirror pairs lane i with
+// 15 - i of its row, row_half_mirror with 7 - i of its half-row, quad_perm
+// permutes within quads.
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+}
+#define GSR_DPP_QUAD_XOR1 0xB1
+#define GSR_DPP_QUAD_XOR2 0x4E
+#define GSR_DPP_ROW_MIRROR 0x140
+#define GSR_DPP_ROW_HALF_MIRROR 0x141
+
+// value of the same register in lane ^ 32 (MASK 32) or lane ^ 16 (MASK 16)
+template <int MASK>
+__device__ __forceinline__ float swap_partner(float x, int lane)
+{
+    unsigned u = __float_as_uint(x);
+    if (MASK == 32) {
+        auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+        return __uint_as_float((lane & 32) ? r[0] : r[1]);
+    } else {
+        auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        return __uint_as_float((lane & 16) ? r[0] : r[1]);
+    }
+}
+
+// sum over all 64 lanes (every lane gets the total)
 __device__ __forceinline__ float wave_sum(float x)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    const int lane = threadIdx.x & 63;
+    x += dpp<GSR_DPP_QUAD_XOR1>(x);
+    x += dpp<GSR_DPP_QUAD_XOR2>(x);
+    x += dpp<GSR_DPP_ROW_HALF_MIRROR>(x);
+    x += dpp<GSR_DPP_ROW_MIRROR>(x);
+    x += swap_partner<16>(x, lane);
+    x += swap_partner<32>(x, lane);
     return x;
+}
+
+// Transposed reduction of 8 values over the wave: afterwards lane 8k holds
+// the 64-lane total of v[k] (in v[0]).  Each exchange keeps half of the
+// values and adds the partner lane's copy of that half.
+__device__ __forceinline__ float wave_sum8_transposed(float* v)
+{
+    const int lane = threadIdx.x & 63;
+    {  // lane ^ 32: permlane32 swap of (v[j], v[4 + j])
+        const bool hi = lane & 32;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[j]), __float_as_uint(v[4 + j]), false, false);
+            v[j] = hi ? v[4 + j] + __uint_as_float(r[0]) : v[j] + __uint_as_float(r[1]);
+        }
+    }
+    {  // lane ^ 16
+        const bool hi = lane & 16;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[j]), __float_as_uint(v[2 + j]), false, false);
+            v[j] = hi ? v[2 + j] + __uint_as_float(r[0]) : v[j] + __uint_as_float(r[1]);
+        }
+    }
+    {  // mirror partner in the row (bit 3 complemented)
+        const bool hi = lane & 8;
+        float send = hi ? v[0] : v[1];
+        float keep = hi ? v[1] : v[0];
+        v[0] = keep + dpp<GSR_DPP_ROW_MIRROR>(send);
+    }
+    float s = v[0];
+    s += dpp<GSR_DPP_ROW_HALF_MIRROR>(s);
+    s += dpp<GSR_DPP_QUAD_XOR2>(s);
+    s += dpp<GSR_DPP_QUAD_XOR1>(s);
+    return s;
 }
 
 __device__ __forceinline__ void atomic_add_f64(double* p, double v)

@@ -19,9 +19,11 @@
 // g . (colour behind) as a running scalar, so that
 //   dL/dalpha_i = T_i g.c_i - (g.S_i + dL/dT_final T_final) / (1 - alpha_i).
 // A lane sums its pixels' 9 screen-space partials of an entry, the wavefront
-// reduces them (transposed exchange: 8 values in 10 shuffles, plus one), and
-// 9 lanes add the tile's totals to the slot's double accumulators with one
-// atomic instruction (plus one).
+// reduces them on VALU cross-lane instructions (a transposed exchange of 8
+// values in 7 swaps plus 3 DPP adds, and one full sum), and 9 lanes add the
+// tile's totals to the slot's double accumulators with one atomic
+// instruction (plus one).  Per-pixel work is branch-free (selects); an entry
+// no lane of the wave needs is skipped as a whole.
 #include "kernels.h"
 
 namespace gsr {
@@ -121,33 +123,38 @@ __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)GSR_BATCH, range.y - base);
-        for (int e = 0; e < cnt && !lane_done; ++e) {
+        for (int e = 0; e < cnt; ++e) {
+            if ((e & 15) == 0 && __all(lane_done)) break;
             const LdsRec r = rec[e];
             const float dx = fpx - r.p0.x;
             const float a2dx2 = r.p0.z * dx * dx;
             const float b2dx = r.p0.w * dx;
+            float p2[PPT];
+            bool pass[PPT], any = false;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                p2[k] = power2(a2dx2, b2dx, r.p1.x, fpy[k] - r.p0.y);
+                pass[k] = (p2[k] >= r.p1.z) & !done[k];
+                any |= pass[k];
+            }
+            if (!__any(any)) continue;
+            const uint32_t pos1 = base + (uint32_t)e - range.x + 1u;
             bool all = true;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                if (!done[k]) {
-                    const float p2 = power2(a2dx2, b2dx, r.p1.x, fpy[k] - r.p0.y);
-                    if (p2 >= r.p1.z) {
-                        const float alpha = fminf(amax, r.p1.y * __builtin_amdgcn_exp2f(p2));
-                        const float Tn = __builtin_fmaf(-T[k], alpha, T[k]);
-                        if (Tn < tmin) {
-                            done[k] = true;
-                        } else {
-                            const float wgt = alpha * T[k];
-                            C0[k] = __builtin_fmaf(r.p2.x, wgt, C0[k]);
-                            C1[k] = __builtin_fmaf(r.p2.y, wgt, C1[k]);
-                            C2[k] = __builtin_fmaf(r.p2.z, wgt, C2[k]);
-                            T[k] = Tn;
-                            last[k] = base + (uint32_t)e - range.x + 1u;
-                            ++nb[k];
-                        }
-                    }
-                }
-                all = all && done[k];
+                const float alpha = fminf(amax, r.p1.y * __builtin_amdgcn_exp2f(p2[k]));
+                const float Tn = __builtin_fmaf(-T[k], alpha, T[k]);
+                const bool stop = pass[k] & (Tn < tmin);
+                const bool blend = pass[k] & !stop;
+                done[k] = done[k] | stop;
+                const float wgt = blend ? alpha * T[k] : 0.0f;
+                C0[k] = __builtin_fmaf(r.p2.x, wgt, C0[k]);
+                C1[k] = __builtin_fmaf(r.p2.y, wgt, C1[k]);
+                C2[k] = __builtin_fmaf(r.p2.z, wgt, C2[k]);
+                T[k] = blend ? Tn : T[k];
+                last[k] = blend ? pos1 : last[k];
+                nb[k] += blend ? 1u : 0u;
+                all = all & done[k];
             }
             lane_done = all;
         }
@@ -172,20 +179,6 @@ __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
         a.T_final[c.pix[k]] = T[k];
         a.n_contrib[c.pix[k]] = (int32_t)last[k];
         if (a.n_blend) a.n_blend[c.pix[k]] = (int32_t)nb[k];
-    }
-}
-
-// One exchange step of the transposed reduction: keep half of 2N values,
-// add the partner's copy of the kept half.
-template <int N>
-__device__ __forceinline__ void xchg(float* v, int lane, int mask)
-{
-    const bool hi = (lane & mask) != 0;
-#pragma unroll
-    for (int j = 0; j < N; ++j) {
-        float send = hi ? v[j] : v[N + j];
-        float keep = hi ? v[N + j] : v[j];
-        v[j] = keep + __shfl_xor(send, mask, 64);
     }
 }
 
@@ -249,58 +242,53 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
             const float dx = fpx - r.p0.x;
             const float a2dx2 = r.p0.z * dx * dx;
             const float b2dx = r.p0.w * dx;
-            float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            float v8 = 0.0f;
-            bool any = false;
+            float p2[PPT], dy[PPT];
+            bool on[PPT], any = false;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                const float dy = fpy[k] - r.p0.y;
-                const float p2 = power2(a2dx2, b2dx, r.p1.x, dy);
-                if (pos < my_n[k] && p2 >= r.p1.z) {
-                    any = true;
-                    const float G = __builtin_amdgcn_exp2f(p2);
-                    const float a_raw = r.p1.y * G;
-                    const bool clamped = !(a_raw < amax);
-                    const float alpha = clamped ? amax : a_raw;
-                    const float rcp = __builtin_amdgcn_rcpf(1.0f - alpha);
-                    const float Tb = T[k] * rcp;
-                    const float gcol = __builtin_fmaf(g0[k], r.p2.x, __builtin_fmaf(g1[k], r.p2.y, g2[k] * r.p2.z));
-                    const float dalpha = __builtin_fmaf(Tb, gcol, -rcp * gsk[k]);
-                    const float wgt = alpha * Tb;
-                    v[6] = __builtin_fmaf(g0[k], wgt, v[6]);
-                    v[7] = __builtin_fmaf(g1[k], wgt, v[7]);
-                    v8 = __builtin_fmaf(g2[k], wgt, v8);
-                    gsk[k] = __builtin_fmaf(wgt, gcol, gsk[k]);
-                    T[k] = Tb;
-                    if (!clamped) {
-                        const float dd = dalpha * alpha;
-                        const float ddx = dd * dx;
-                        // d power2 / du = -(2 a2 dx + b2 dy), / dv = -(b2 dx + 2 c2 dy)
-                        v[0] = __builtin_fmaf(dd, __builtin_fmaf(2.0f * r.p0.z, dx, r.p0.w * dy), v[0]);
-                        v[1] = __builtin_fmaf(dd, __builtin_fmaf(2.0f * r.p1.x, dy, b2dx), v[1]);
-                        v[2] = __builtin_fmaf(ddx, dx, v[2]);
-                        v[3] = __builtin_fmaf(ddx, dy, v[3]);
-                        v[4] = __builtin_fmaf(dd * dy, dy, v[4]);
-                        v[5] = __builtin_fmaf(dalpha, G, v[5]);
-                    }
-                }
+                dy[k] = fpy[k] - r.p0.y;
+                p2[k] = power2(a2dx2, b2dx, r.p1.x, dy[k]);
+                on[k] = (pos < my_n[k]) & (p2[k] >= r.p1.z);
+                any |= on[k];
             }
-            if (__any(any)) {
-                xchg<4>(v, lane, 32);
-                xchg<2>(v, lane, 16);
-                xchg<1>(v, lane, 8);
-                float s = v[0];
-                s += __shfl_xor(s, 4, 64);
-                s += __shfl_xor(s, 2, 64);
-                s += __shfl_xor(s, 1, 64);
-                v8 = wave_sum(v8);
-                const uint32_t slot = __float_as_uint(r.p2.w);
-                if ((lane & 7) == 0) {
-                    const int f = lane >> 3;
-                    atomic_add_f64(&a.grad2d[f * S + slot], (double)(s * field_scale(f)));
-                }
-                if (lane == 0) atomic_add_f64(&a.grad2d[8 * S + slot], (double)v8);
+            if (!__any(any)) continue;
+            float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+            float v8 = 0.0f;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const float G = __builtin_amdgcn_exp2f(p2[k]);
+                const float a_raw = r.p1.y * G;
+                const bool clamped = !(a_raw < amax);
+                const float alpha = clamped ? amax : a_raw;
+                const float rcp = __builtin_amdgcn_rcpf(1.0f - alpha);
+                const float Tb = T[k] * rcp;
+                const float gcol = __builtin_fmaf(g0[k], r.p2.x, __builtin_fmaf(g1[k], r.p2.y, g2[k] * r.p2.z));
+                const float dalpha = __builtin_fmaf(Tb, gcol, -rcp * gsk[k]);
+                const float wgt = on[k] ? alpha * Tb : 0.0f;
+                v[6] = __builtin_fmaf(g0[k], wgt, v[6]);
+                v[7] = __builtin_fmaf(g1[k], wgt, v[7]);
+                v8 = __builtin_fmaf(g2[k], wgt, v8);
+                gsk[k] = __builtin_fmaf(wgt, gcol, gsk[k]);
+                T[k] = on[k] ? Tb : T[k];
+                const bool live = on[k] & !clamped;
+                const float dd = live ? dalpha * alpha : 0.0f;
+                const float ddx = dd * dx;
+                // d power2 / du = -(2 a2 dx + b2 dy), / dv = -(b2 dx + 2 c2 dy)
+                v[0] = __builtin_fmaf(dd, __builtin_fmaf(2.0f * r.p0.z, dx, r.p0.w * dy[k]), v[0]);
+                v[1] = __builtin_fmaf(dd, __builtin_fmaf(2.0f * r.p1.x, dy[k], b2dx), v[1]);
+                v[2] = __builtin_fmaf(ddx, dx, v[2]);
+                v[3] = __builtin_fmaf(ddx, dy[k], v[3]);
+                v[4] = __builtin_fmaf(dd * dy[k], dy[k], v[4]);
+                v[5] = __builtin_fmaf(live ? dalpha : 0.0f, G, v[5]);
             }
+            const float s8 = wave_sum8_transposed(v);
+            v8 = wave_sum(v8);
+            const uint32_t slot = __float_as_uint(r.p2.w);
+            if ((lane & 7) == 0) {
+                const int f = lane >> 3;
+                atomic_add_f64(&a.grad2d[f * S + slot], (double)(s8 * field_scale(f)));
+            }
+            if (lane == 0) atomic_add_f64(&a.grad2d[8 * S + slot], (double)v8);
         }
         __syncthreads();
         hi_ = lo_;
