@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-views", type=str, default=None, help="comma list of views for the oracle sample")
-    ap.add_argument("--tile", type=str, default=None, help="WxH tile size (default: autotuned or 16x16)")
+    ap.add_argument("--tile", type=str, default=None, help="WxH[/batch] (default: autotuned)")
+    ap.add_argument("--autotune", action="store_true", help="re-run the tile/batch autotuner")
     ap.add_argument("--copy-probe", action="store_true", help="run a plain device copy of known size first")
     return ap.parse_args()
 
@@ -157,19 +158,21 @@ def main():
     n = int(w["params"]["opacity_logit"].shape[0])
     V = len(cams)
     pose_only = [int(x) for x in w["pose_only"]]
-    tile = (16, 16)
-    if args.tile:
-        tile = tuple(int(x) for x in args.tile.lower().split("x"))
-    else:
-        try:
-            from paper_2601_00705_amd import autotune
-            tile = autotune.lookup(cams, n, w["sh_degree"]) or tile
-        except Exception:  # no cache yet
-            pass
-    cfg = Config(tile_w=tile[0], tile_h=tile[1], sh_degree=w["sh_degree"])
     params = {k: torch.from_numpy(v).to(dev) for k, v in w["params"].items()}
     poses = torch.from_numpy(w["poses"].astype(np.float32)).to(dev)
-    target = target_images(w, params, poses, cfg, Renderer, torch)
+    target = target_images(w, params, poses, Config(sh_degree=w["sh_degree"]), Renderer, torch)
+    tuned = None
+    if args.tile:
+        t, _, b = args.tile.lower().partition("/")
+        tile = (int(t.split("x")[0]), int(t.split("x")[1]), int(b) if b else 128)
+    else:
+        from paper_2601_00705_amd import autotune
+        tile = None if args.autotune else autotune.lookup(cams, n, w["sh_degree"])
+        if tile is None:
+            tuned = autotune.tune(params, cams, poses, target, w["sh_degree"], pose_only, log=log)
+            tile = tuned["best"]
+    cfg = Config(tile_w=tile[0], tile_h=tile[1], batch=tile[2], sh_degree=w["sh_degree"])
+    log(f"tile {tile[0]}x{tile[1]}, LDS batch {tile[2]}")
     total_px = sum(c["width"] * c["height"] for c in cams)
 
     if args.copy_probe:
@@ -315,7 +318,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w["name"], "gaussians": n, "views": V, "pixels": total_px,
-                   "tile": f"{cfg.tile_w}x{cfg.tile_h}", "sh_degree": cfg.sh_degree, "mode": "batched-graph"},
+                   "tile": f"{cfg.tile_w}x{cfg.tile_h}", "batch": cfg.batch, "sh_degree": cfg.sh_degree,
+                   "mode": "batched-graph"},
+        "autotune_ms": None if tuned is None else tuned["ms"],
         "blends_per_s": blends / (ms_step * 1e-3),
         "blends_per_step": blends,
         "pairs_per_step": need,

@@ -77,7 +77,7 @@ typedef struct {
 /* Renderer settings (host struct). */
 typedef struct {
     int32_t tile_w, tile_h; /* powers of two; tile_w * tile_h in {64, 128, 256} */
-    int32_t batch;          /* reserved, 0 (the LDS batch equals the tile pixel count) */
+    int32_t batch;          /* records staged in LDS per step: 64, 128 or 256 (0 = 128) */
     int32_t sh_degree;      /* -1: RGB colour; 0..3: SH degree */
     float z_near;           /* cull mu_C.z <= z_near */
     float dilation;         /* eps added to the diagonal of Sigma_I (px^2) */
@@ -105,6 +105,7 @@ typedef struct {
     size_t geom;      /* float4 [V*n]: (u, v, rx, ry); rx < 0 = culled */
     size_t conic_o;   /* float4 [V*n]: (A, B, C, o), A = (Sigma_I^-1)_00 ... */
     size_t rgb_d;     /* float4 [V*n]: (r, g, b, depth) */
+    size_t qthr;      /* float [V*n]: binning level of d^T conic d per slot */
     size_t grad2d;    /* double [9][V*n]: d(u, v, A, B, C, o, r, g, b) */
     size_t keys;      /* uint64 [capacity]: sorted (tile << 32 | depth bits) */
     size_t vals;      /* uint32 [capacity]: sorted slot = view * n + index */
@@ -145,7 +146,9 @@ gsr_status gsr_plan_get_info(const gsr_plan *plan, gsr_plan_info *out);
  * screen-space gradient accumulators of live slots. */
 gsr_status gsr_project(gsr_plan *plan, const gsr_gaussians *g, const float *poses, void *stream);
 
-/* Builds the depth-ordered per-tile lists from the geom / rgb_d records:
+/* Builds the depth-ordered per-tile lists from the geom / conic_o / qthr /
+ * rgb_d records (candidate tiles: the slot's rectangle; kept: the tiles whose
+ * pixel-centre box reaches d^T conic d <= qthr):
  * pair emission, stable LSD radix sort of (tile | depth) keys with slot
  * values, tile ranges.  When the pair count exceeds the capacity, a device
  * flag is set, no pair is written, gsr_render_fwd writes NaN images and

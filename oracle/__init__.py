@@ -203,24 +203,24 @@ def project(params, cam, pose, cfg: Config):
     return {k: out[:, j] for j, k in enumerate(PROJ_FIELDS)}
 
 
-def bin_f32(cams, n, u, v, rx, ry, depth, tile_w, tile_h):
+def bin_f32(cams, n, u, v, rx, ry, A, B, C, qthr, depth, tile_w, tile_h):
     """Reference binning of float32 records (slot = view * n + i) into sorted
     (tile | depth-bits) keys, slot values and per-tile ranges."""
     lib = _load()
-    u, v, rx, ry, depth = (np.ascontiguousarray(a, dtype=np.float32) for a in (u, v, rx, ry, depth))
+    arrs = [np.ascontiguousarray(a, dtype=np.float32) for a in (u, v, rx, ry, A, B, C, qthr, depth)]
     V = len(cams)
     W = np.array([c["width"] for c in cams], dtype=np.int32)
     H = np.array([c["height"] for c in cams], dtype=np.int32)
     tiles = int(sum(((w + tile_w - 1) // tile_w) * ((h + tile_h - 1) // tile_h) for w, h in zip(W, H)))
     ranges = np.zeros(2 * tiles, dtype=np.uint32)
-    M = lib.or_bin_f32(ctypes.c_int32(V), _ptr(W), _ptr(H), ctypes.c_int64(n), _ptr(u), _ptr(v),
-                       _ptr(rx), _ptr(ry), _ptr(depth), ctypes.c_int32(tile_w),
-                       ctypes.c_int32(tile_h), ctypes.c_int64(0), None, None, _ptr(ranges))
+    M = lib.or_bin_f32(ctypes.c_int32(V), _ptr(W), _ptr(H), ctypes.c_int64(n), *(_ptr(a) for a in arrs),
+                       ctypes.c_int32(tile_w), ctypes.c_int32(tile_h), ctypes.c_int64(0), None, None,
+                       _ptr(ranges))
     keys = np.zeros(max(M, 1), dtype=np.uint64)
     vals = np.zeros(max(M, 1), dtype=np.uint32)
-    lib.or_bin_f32(ctypes.c_int32(V), _ptr(W), _ptr(H), ctypes.c_int64(n), _ptr(u), _ptr(v),
-                   _ptr(rx), _ptr(ry), _ptr(depth), ctypes.c_int32(tile_w), ctypes.c_int32(tile_h),
-                   ctypes.c_int64(M), _ptr(keys), _ptr(vals), _ptr(ranges))
+    lib.or_bin_f32(ctypes.c_int32(V), _ptr(W), _ptr(H), ctypes.c_int64(n), *(_ptr(a) for a in arrs),
+                   ctypes.c_int32(tile_w), ctypes.c_int32(tile_h), ctypes.c_int64(M), _ptr(keys), _ptr(vals),
+                   _ptr(ranges))
     return keys[:M], vals[:M], ranges.reshape(tiles, 2)
 
 

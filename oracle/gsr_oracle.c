@@ -679,13 +679,17 @@ int or_backward(const or_scene *sc, int32_t n_views, const or_camera *cams, cons
 /* Binning of already-projected float32 records into (tile | depth) keys.
  * A slot is live iff rx >= 0, ry >= 0 and u and v are not NaN; the depth is
  * only a sort key (its raw float32 bit pattern).
- * Its rectangle is computed with single-precision IEEE operations only:
+ * Candidate tiles are those of the slot's rectangle, computed with
+ * single-precision IEEE operations only:
  *   x0 = floor((u - rx) / tile_w), x1 = floor((u + rx) / tile_w)  (same in y),
  * empty if x1 < 0, y1 < 0, x0 > tiles_x - 1 or y0 > tiles_y - 1, otherwise
- * clipped to the view's tile grid.  Key = (global tile << 32) | bits(depth),
- * value = slot index (view * n + Gaussian); pairs ordered by key, then slot.
- * ranges[2 t], ranges[2 t + 1] = [first, last + 1) of global tile t, or 0, 0.
- * Returns the number of pairs; writes at most `capacity` of them. */
+ * clipped to the view's tile grid.  A candidate tile is kept iff tile_hit()
+ * finds the slot's quadratic form at or below its threshold qthr somewhere on
+ * the box spanned by the tile's pixel centres.
+ * Key = (global tile << 32) | bits(depth), value = slot index (view * n +
+ * Gaussian); pairs are ordered by key, then slot; rectangle tiles are visited
+ * row by row.  ranges[2 t], ranges[2 t + 1] = [first, last + 1) of global
+ * tile t, or 0, 0.  Returns the number of pairs; writes at most `capacity`. */
 static const uint64_t *g_bin_keys;
 static int cmp_pair(const void *a, const void *b)
 {
@@ -695,8 +699,41 @@ static int cmp_pair(const void *a, const void *b)
     return ia < ib ? -1 : (ia > ib ? 1 : 0);
 }
 
+/* q(dx, dy) = A dx^2 + 2 B dx dy + C dy^2, d = pixel centre - (u, v): is its
+ * minimum over the box of the tile's pixel centres <= qthr?  Inside the box
+ * the minimum is 0; otherwise it lies on an edge, where the minimiser along
+ * the edge is clamped to the edge.  Float32 operations in this exact order. */
+static int tile_hit(float u, float v, float A, float B, float C, float qthr, int64_t tx, int64_t ty,
+                    int32_t tw, int32_t th)
+{
+    float x0 = ((float)(tx * tw) + 0.5f) - u;
+    float x1 = ((float)(tx * tw + tw - 1) + 0.5f) - u;
+    float y0 = ((float)(ty * th) + 0.5f) - v;
+    float y1 = ((float)(ty * th + th - 1) + 0.5f) - v;
+    if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return 1;
+    float iA = 1.0f / A, iC = 1.0f / C, B2 = 2.0f * B;
+    float m = INFINITY;
+    float ex[2] = { x0, x1 }, ey[2] = { y0, y1 };
+    for (int e = 0; e < 2; ++e) {
+        float X = ex[e];
+        float ys = -(B * X) * iC;
+        ys = ys < y0 ? y0 : (ys > y1 ? y1 : ys);
+        float q = (A * X) * X + (B2 * X) * ys + (C * ys) * ys;
+        m = q < m ? q : m;
+    }
+    for (int e = 0; e < 2; ++e) {
+        float Y = ey[e];
+        float xs = -(B * Y) * iA;
+        xs = xs < x0 ? x0 : (xs > x1 ? x1 : xs);
+        float q = (A * xs) * xs + (B2 * xs) * Y + (C * Y) * Y;
+        m = q < m ? q : m;
+    }
+    return m <= qthr;
+}
+
 int64_t or_bin_f32(int32_t n_views, const int32_t *widths, const int32_t *heights, int64_t n,
                    const float *u, const float *v, const float *rx, const float *ry,
+                   const float *A, const float *B, const float *C, const float *qthr,
                    const float *depth, int32_t tile_w, int32_t tile_h, int64_t capacity,
                    uint64_t *keys, uint32_t *vals, uint32_t *ranges)
 {
@@ -721,7 +758,9 @@ int64_t or_bin_f32(int32_t n_views, const int32_t *widths, const int32_t *height
             int64_t tx0 = x0 < 0.0f ? 0 : (int64_t)x0, ty0 = y0 < 0.0f ? 0 : (int64_t)y0;
             int64_t tx1 = x1 > (float)(tiles_x - 1) ? tiles_x - 1 : (int64_t)x1;
             int64_t ty1 = y1 > (float)(tiles_y - 1) ? tiles_y - 1 : (int64_t)y1;
-            M += (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+            for (int64_t ty = ty0; ty <= ty1; ++ty)
+                for (int64_t tx = tx0; tx <= tx1; ++tx)
+                    M += tile_hit(uu, vv, A[s], B[s], C[s], qthr[s], tx, ty, tile_w, tile_h);
         }
     }
     uint64_t *k_all = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(M + 1));
@@ -744,6 +783,7 @@ int64_t or_bin_f32(int32_t n_views, const int32_t *widths, const int32_t *height
             memcpy(&bits, &dd, 4);
             for (int64_t ty = ty0; ty <= ty1; ++ty)
                 for (int64_t tx = tx0; tx <= tx1; ++tx) {
+                    if (!tile_hit(uu, vv, A[s], B[s], C[s], qthr[s], tx, ty, tile_w, tile_h)) continue;
                     uint64_t tile = (uint64_t)(base[w] + ty * tiles_x + tx);
                     k_all[m] = (tile << 32) | bits;
                     v_all[m] = (uint32_t)s;

@@ -1,65 +1,123 @@
 // bin.hip -- pair emission for the depth-ordered sets N(p) of Eq. (alpha).
 //
-// For every live slot the conservative tile rectangle (tile_rect, the
-// binning contract) is expanded into one (key, value) pair per covered tile:
-// key = (global tile << 32) | float bits of the camera depth (positive floats
-// order like their bit patterns), value = slot.  Emission is in slot order so
-// that a stable sort breaks depth ties by slot, i.e. by Gaussian index.
+// For every live slot the conservative tile rectangle (tile_rect) gives the
+// candidate tiles; a candidate is kept when the slot's ellipse reaches the
+// tile's pixel-centre box (tile_hit).  Each kept tile yields one
+// (key, value) pair: key = (global tile << 32) | float bits of the camera
+// depth (positive floats order like their bit patterns), value = slot.
+// Emission is in slot order, rectangle tiles row by row, so that a stable
+// sort breaks depth ties by slot, i.e. by Gaussian index.
 //
-//   k_bin_count : per chunk of BIN_CHUNK Gaussians of one view, the pair count
+//   k_bin_count : per chunk of BIN_CHUNK Gaussians of one view, the number of
+//                 kept tiles (the chunk's rectangles are expanded
+//                 cooperatively: one candidate per thread and step, owner
+//                 found by binary search over the rectangle-area prefix)
 //   k_bin_scan  : exclusive scan of the chunk counts, total, capacity check
-//   k_bin_emit  : per chunk, a block scan of per-slot counts, then a
-//                 cooperative expansion (one output pair per thread and step,
-//                 owner found by binary search) so that stores are coalesced.
+//   k_bin_emit  : the same expansion; kept candidates are compacted in order
+//                 (wave ballots + a block prefix) so that stores are coalesced
 #include "kernels.h"
 
 namespace gsr {
 
-struct SlotRect {
-    int x0, y0, w, h;
+struct ChunkLds {
+    uint32_t excl[GSR_BIN_CHUNK + 1];  // prefix of rectangle areas
+    int rx0[GSR_BIN_CHUNK], ry0[GSR_BIN_CHUNK], rw[GSR_BIN_CHUNK];
+    float u[GSR_BIN_CHUNK], v[GSR_BIN_CHUNK], A[GSR_BIN_CHUNK], B[GSR_BIN_CHUNK], C[GSR_BIN_CHUNK];
+    float q[GSR_BIN_CHUNK];
+    uint32_t dbits[GSR_BIN_CHUNK];
+    uint32_t wsum[4];
 };
 
-__device__ __forceinline__ uint32_t slot_count(const BinArgs& a, const ViewInfo& vw, int64_t i,
-                                               int v, SlotRect& r, float inv_tw, float inv_th)
+// Loads the chunk's slots (thread t owns chunk items 4t .. 4t+3, which keeps
+// slot order), their rectangles and ellipse data, and scans the areas.
+// Returns the chunk's total rectangle area.
+__device__ uint32_t load_chunk(const BinArgs& a, const ViewInfo& vw, int v, int64_t base, bool want_depth,
+                               ChunkLds& L)
 {
-    if (i >= a.n) return 0;
-    float4 gm = a.geom[(int64_t)v * a.n + i];
-    int x0, y0, x1, y1;
-    if (!tile_rect(gm.x, gm.y, gm.z, gm.w, inv_tw, inv_th, vw.tiles_x, vw.tiles_y, x0, y0, x1, y1))
-        return 0;
-    r.x0 = x0;
-    r.y0 = y0;
-    r.w = x1 - x0 + 1;
-    r.h = y1 - y0 + 1;
-    return (uint32_t)(r.w * r.h);
+    const float inv_tw = 1.0f / (float)a.cfg.tile_w, inv_th = 1.0f / (float)a.cfg.tile_h;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t area[4], tsum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int li = tid * 4 + k;
+        const int64_t i = base + li;
+        area[k] = 0;
+        int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
+        if (i < a.n) {
+            const int64_t slot = (int64_t)v * a.n + i;
+            const float4 gm = a.geom[slot];
+            if (tile_rect(gm.x, gm.y, gm.z, gm.w, inv_tw, inv_th, vw.tiles_x, vw.tiles_y, x0, y0, x1, y1)) {
+                area[k] = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+                const float4 co = a.conic_o[slot];
+                L.u[li] = gm.x;
+                L.v[li] = gm.y;
+                L.A[li] = co.x;
+                L.B[li] = co.y;
+                L.C[li] = co.z;
+                L.q[li] = a.qthr[slot];
+                if (want_depth) L.dbits[li] = __float_as_uint(a.rgb_d[slot].w);
+            }
+        }
+        L.rx0[li] = x0;
+        L.ry0[li] = y0;
+        L.rw[li] = x1 - x0 + 1;
+        tsum += area[k];
+    }
+    uint32_t incl = tsum;
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) L.wsum[w] = incl;
+    __syncthreads();
+    uint32_t wofs = 0;
+    for (int k = 0; k < w; ++k) wofs += L.wsum[k];
+    uint32_t run = wofs + incl - tsum;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        L.excl[tid * 4 + k] = run;
+        run += area[k];
+    }
+    const uint32_t total = L.wsum[0] + L.wsum[1] + L.wsum[2] + L.wsum[3];
+    if (tid == 0) L.excl[GSR_BIN_CHUNK] = total;
+    __syncthreads();
+    return total;
 }
 
-__device__ __forceinline__ uint32_t block_sum_u32(uint32_t x, uint32_t* red)
+// candidate j of the chunk: owner slot (largest s with excl[s] <= j) and tile
+__device__ __forceinline__ bool candidate(const ChunkLds& L, uint32_t j, const BinArgs& a, int& s, int& tx,
+                                          int& ty)
 {
-    // 256 threads = 4 waves
-    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
-    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (lane == 0) red[w] = x;
-    __syncthreads();
-    uint32_t t = red[0] + red[1] + red[2] + red[3];
-    __syncthreads();
-    return t;
+    int lo = 0, hi = GSR_BIN_CHUNK - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.excl[mid] <= j) lo = mid; else hi = mid - 1;
+    }
+    s = lo;
+    const uint32_t r = j - L.excl[lo];
+    const uint32_t wdt = (uint32_t)L.rw[lo];
+    ty = L.ry0[lo] + (int)(r / wdt);
+    tx = L.rx0[lo] + (int)(r % wdt);
+    return tile_hit(L.u[lo], L.v[lo], L.A[lo], L.B[lo], L.C[lo], L.q[lo], tx, ty, a.cfg.tile_w, a.cfg.tile_h);
 }
 
 __global__ __launch_bounds__(256) void k_bin_count(BinArgs a)
 {
+    __shared__ ChunkLds L;
     __shared__ uint32_t red[4];
     const int v = blockIdx.y;
     const ViewInfo vw = a.views->v[v];
-    const float inv_tw = 1.0f / (float)a.cfg.tile_w, inv_th = 1.0f / (float)a.cfg.tile_h;
-    int64_t base = (int64_t)blockIdx.x * GSR_BIN_CHUNK;
+    const int64_t base = (int64_t)blockIdx.x * GSR_BIN_CHUNK;
+    const uint32_t total = load_chunk(a, vw, v, base, false, L);
     uint32_t c = 0;
-    for (int k = 0; k < GSR_BIN_CHUNK / 256; ++k) {
-        SlotRect r;
-        c += slot_count(a, vw, base + k * 256 + threadIdx.x, v, r, inv_tw, inv_th);
+    for (uint32_t j = threadIdx.x; j < total; j += 256) {
+        int s, tx, ty;
+        c += candidate(L, j, a, s, tx, ty) ? 1u : 0u;
     }
-    uint32_t t = block_sum_u32(c, red);
-    if (threadIdx.x == 0) a.block_sums[v * a.chunks + blockIdx.x] = t;
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) a.block_sums[v * a.chunks + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
 }
 
 __global__ __launch_bounds__(1024) void k_bin_scan(BinArgs a)
@@ -93,64 +151,33 @@ __global__ __launch_bounds__(1024) void k_bin_scan(BinArgs a)
 
 __global__ __launch_bounds__(256) void k_bin_emit(BinArgs a)
 {
-    __shared__ uint32_t excl[GSR_BIN_CHUNK + 1];
-    __shared__ int rx0[GSR_BIN_CHUNK], ry0[GSR_BIN_CHUNK], rw[GSR_BIN_CHUNK];
-    __shared__ uint32_t dbits[GSR_BIN_CHUNK];
-    __shared__ uint32_t wsum[4];
+    __shared__ ChunkLds L;
+    __shared__ uint32_t wcount[4];
     if (a.counters->overflow) return;
     const int v = blockIdx.y;
     const ViewInfo vw = a.views->v[v];
-    const float inv_tw = 1.0f / (float)a.cfg.tile_w, inv_th = 1.0f / (float)a.cfg.tile_h;
     const int64_t base = (int64_t)blockIdx.x * GSR_BIN_CHUNK;
+    const uint32_t total = load_chunk(a, vw, v, base, true, L);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    // blocked layout: thread t owns chunk items 4t .. 4t+3 (keeps slot order)
-    uint32_t cnt[4], tsum = 0;
-    for (int k = 0; k < 4; ++k) {
-        int li = tid * 4 + k;
-        SlotRect r{0, 0, 0, 0};
-        cnt[k] = slot_count(a, vw, base + li, v, r, inv_tw, inv_th);
-        rx0[li] = r.x0;
-        ry0[li] = r.y0;
-        rw[li] = r.w;
-        if (cnt[k]) {
-            float d = a.rgb_d[(int64_t)v * a.n + base + li].w;
-            dbits[li] = __float_as_uint(d);
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    unsigned long long out = a.block_offs[v * a.chunks + blockIdx.x];
+    for (uint32_t j0 = 0; j0 < total; j0 += 256) {
+        const uint32_t j = j0 + tid;
+        int s = 0, tx = 0, ty = 0;
+        const bool hit = j < total && candidate(L, j, a, s, tx, ty);
+        const unsigned long long m = __ballot(hit);
+        if (lane == 0) wcount[w] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t before = 0;
+        for (int k = 0; k < w; ++k) before += wcount[k];
+        if (hit) {
+            const unsigned long long pos = out + before + (uint32_t)__popcll(m & lt);
+            const unsigned long long tile = (unsigned long long)(vw.tile_base + ty * vw.tiles_x + tx);
+            a.keys[pos] = (tile << 32) | L.dbits[s];
+            a.vals[pos] = (uint32_t)((int64_t)v * a.n + base + s);
         }
-        tsum += cnt[k];
-    }
-    // block exclusive scan of the per-thread sums
-    uint32_t incl = tsum;
-    for (int off = 1; off < 64; off <<= 1) {
-        uint32_t y = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += y;
-    }
-    if (lane == 63) wsum[w] = incl;
-    __syncthreads();
-    uint32_t wofs = 0;
-    for (int k = 0; k < w; ++k) wofs += wsum[k];
-    uint32_t run = wofs + incl - tsum;
-    for (int k = 0; k < 4; ++k) {
-        excl[tid * 4 + k] = run;
-        run += cnt[k];
-    }
-    const uint32_t total = wsum[0] + wsum[1] + wsum[2] + wsum[3];
-    if (tid == 0) excl[GSR_BIN_CHUNK] = total;
-    __syncthreads();
-    const unsigned long long out0 = a.block_offs[v * a.chunks + blockIdx.x];
-    for (uint32_t j = tid; j < total; j += 256) {
-        // owner: largest s with excl[s] <= j
-        int lo = 0, hi = GSR_BIN_CHUNK - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (excl[mid] <= j) lo = mid; else hi = mid - 1;
-        }
-        uint32_t r = j - excl[lo];
-        int wdt = rw[lo];
-        int ty = ry0[lo] + (int)(r / (uint32_t)wdt);
-        int tx = rx0[lo] + (int)(r % (uint32_t)wdt);
-        unsigned long long tile = (unsigned long long)(vw.tile_base + ty * vw.tiles_x + tx);
-        a.keys[out0 + j] = (tile << 32) | dbits[lo];
-        a.vals[out0 + j] = (uint32_t)((int64_t)v * a.n + base + lo);
+        out += wcount[0] + wcount[1] + wcount[2] + wcount[3];
+        __syncthreads();
     }
 }
 

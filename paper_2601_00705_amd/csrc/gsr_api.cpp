@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "gsr.h"
 #include "kernels.h"
@@ -41,11 +42,12 @@ struct gsr_plan {
     int64_t total_pixels = 0;
     int32_t total_tiles = 0, tile_bits = 0, passes = 0, chunks = 0;
     int32_t sort_max_blocks = 0, sort_grid = 0, bwd_blocks = 0;
-    size_t off_counters = 0, off_views = 0, off_geom = 0, off_conic = 0, off_rgbd = 0, off_grad2d = 0;
+    size_t off_counters = 0, off_views = 0, off_geom = 0, off_conic = 0, off_rgbd = 0, off_qthr = 0, off_grad2d = 0;
     size_t off_keys0 = 0, off_keys1 = 0, off_vals0 = 0, off_vals1 = 0, off_ranges = 0, off_hist = 0;
-    size_t off_dtotal = 0, off_bsums = 0, off_boffs = 0, off_xip = 0, total = 0;
+    size_t off_dtotal = 0, off_bsums = 0, off_boffs = 0, off_xip = 0, off_order = 0, off_buckets = 0, total = 0;
     char* ws = nullptr;
     Counters host_counters{};
+    std::vector<uint32_t> identity_order;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -73,7 +75,8 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     if (!pow2(cfg->tile_w) || !pow2(cfg->tile_h)) return fail(GSR_EINVAL, "tile sizes must be powers of two");
     int tpx = cfg->tile_w * cfg->tile_h;
     if (tpx != 64 && tpx != 128 && tpx != 256) return fail(GSR_EUNSUPPORTED, "tile pixel count not in {64,128,256}");
-    if (cfg->batch != 0 && cfg->batch != tpx) return fail(GSR_EUNSUPPORTED, "batch must be 0 or the tile pixel count");
+    if (cfg->batch != 0 && cfg->batch != 64 && cfg->batch != 128 && cfg->batch != 256)
+        return fail(GSR_EUNSUPPORTED, "batch must be 0 (default 128), 64, 128 or 256");
     if (cfg->sh_degree < -1 || cfg->sh_degree > 3) return fail(GSR_EINVAL, "sh_degree not in -1..3");
     if (!(cfg->alpha_min >= 0.0f) || !(cfg->alpha_max > 0.0f) || !(cfg->alpha_max <= 1.0f) ||
         !(cfg->alpha_min <= cfg->alpha_max))
@@ -86,6 +89,7 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->n = n;
     p->V = n_views;
     p->cfg = *cfg;
+    if (p->cfg.batch == 0) p->cfg.batch = 128;
     p->capacity = pair_capacity;
     p->dcfg.tile_w = cfg->tile_w;
     p->dcfg.tile_h = cfg->tile_h;
@@ -152,12 +156,15 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->off_geom = take(sizeof(float4) * S);
     p->off_conic = take(sizeof(float4) * S);
     p->off_rgbd = take(sizeof(float4) * S);
+    p->off_qthr = take(sizeof(float) * S);
     p->off_grad2d = take(sizeof(double) * GSR_G2 * S);
     p->off_keys0 = take(sizeof(unsigned long long) * pair_capacity);
     p->off_keys1 = take(sizeof(unsigned long long) * pair_capacity);
     p->off_vals0 = take(sizeof(uint32_t) * pair_capacity);
     p->off_vals1 = take(sizeof(uint32_t) * pair_capacity);
     p->off_ranges = take(sizeof(uint2) * tiles);
+    p->off_order = take(sizeof(uint32_t) * tiles);
+    p->off_buckets = take(sizeof(uint32_t) * 64);
     p->off_hist = take(sizeof(uint32_t) * 256 * (size_t)p->sort_max_blocks);
     p->off_dtotal = take(sizeof(uint32_t) * 256);
     p->off_bsums = take(sizeof(uint32_t) * (size_t)n_views * p->chunks);
@@ -186,9 +193,15 @@ extern "C" gsr_status gsr_plan_bind(gsr_plan* plan, void* workspace, size_t byte
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
         e = hipMemcpyAsync(plan->ws + plan->off_views, &plan->vt, sizeof(ViewTable), hipMemcpyHostToDevice, s);
-    // empty tile ranges until the first binning
+    // empty tile ranges and an identity tile order until the first binning
     if (e == hipSuccess)
         e = hipMemsetAsync(plan->ws + plan->off_ranges, 0, sizeof(uint2) * (size_t)plan->total_tiles, s);
+    if (e == hipSuccess) {
+        plan->identity_order.resize((size_t)plan->total_tiles);
+        for (int32_t t = 0; t < plan->total_tiles; ++t) plan->identity_order[(size_t)t] = (uint32_t)t;
+        e = hipMemcpyAsync(plan->ws + plan->off_order, plan->identity_order.data(),
+                           sizeof(uint32_t) * (size_t)plan->total_tiles, hipMemcpyHostToDevice, s);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         plan->ws = nullptr;
@@ -206,6 +219,7 @@ extern "C" gsr_status gsr_plan_layout(const gsr_plan* plan, gsr_layout* out)
     out->geom = plan->off_geom;
     out->conic_o = plan->off_conic;
     out->rgb_d = plan->off_rgbd;
+    out->qthr = plan->off_qthr;
     out->grad2d = plan->off_grad2d;
     out->keys = final_buffer(plan) ? plan->off_keys1 : plan->off_keys0;
     out->vals = final_buffer(plan) ? plan->off_vals1 : plan->off_vals0;
@@ -270,6 +284,7 @@ extern "C" gsr_status gsr_project(gsr_plan* plan, const gsr_gaussians* g, const 
     a.geom = at<float4>(plan, plan->off_geom);
     a.conic_o = at<float4>(plan, plan->off_conic);
     a.rgb_d = at<float4>(plan, plan->off_rgbd);
+    a.qthr = at<float>(plan, plan->off_qthr);
     hipError_t e = launch_project(a, plan->cfg.sh_degree, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_project");
 }
@@ -287,6 +302,8 @@ extern "C" gsr_status gsr_bin(gsr_plan* plan, void* stream)
     b.cfg = plan->dcfg;
     b.geom = at<float4>(plan, plan->off_geom);
     b.rgb_d = at<float4>(plan, plan->off_rgbd);
+    b.conic_o = at<float4>(plan, plan->off_conic);
+    b.qthr = at<float>(plan, plan->off_qthr);
     b.block_sums = at<uint32_t>(plan, plan->off_bsums);
     b.block_offs = at<unsigned long long>(plan, plan->off_boffs);
     b.chunks = plan->chunks;
@@ -315,6 +332,8 @@ extern "C" gsr_status gsr_bin(gsr_plan* plan, void* stream)
     r.keys = at<unsigned long long>(plan, final_buffer(plan) ? plan->off_keys1 : plan->off_keys0);
     r.ranges = at<uint2>(plan, plan->off_ranges);
     r.total_tiles = plan->total_tiles;
+    r.order = at<uint32_t>(plan, plan->off_order);
+    r.buckets = at<uint32_t>(plan, plan->off_buckets);
     e = launch_ranges(r, plan->sort_grid < 1024 ? plan->sort_grid * 4 : 4096, s);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_bin: ranges");
 }
@@ -326,6 +345,7 @@ static RasterArgs raster_args(const gsr_plan* plan)
     a.cfg = plan->dcfg;
     a.counters = at<Counters>(plan, plan->off_counters);
     a.ranges = at<uint2>(plan, plan->off_ranges);
+    a.order = at<uint32_t>(plan, plan->off_order);
     a.vals = at<uint32_t>(plan, final_buffer(plan) ? plan->off_vals1 : plan->off_vals0);
     a.geom = at<float4>(plan, plan->off_geom);
     a.conic_o = at<float4>(plan, plan->off_conic);
@@ -347,7 +367,7 @@ extern "C" gsr_status gsr_render_fwd(gsr_plan* plan, float* rgb, float* T_final,
     a.T_final = T_final;
     a.n_contrib = n_contrib;
     a.n_blend = n_blend;
-    hipError_t e = launch_raster_fwd(a, plan->total_tiles, plan->cfg.tile_w * plan->cfg.tile_h,
+    hipError_t e = launch_raster_fwd(a, plan->total_tiles, plan->cfg.tile_w * plan->cfg.tile_h, plan->cfg.batch,
                                      (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_render_fwd");
 }
@@ -380,7 +400,8 @@ extern "C" gsr_status gsr_raster_bwd(gsr_plan* plan, const float* T_final, const
     a.n_contrib_in = n_contrib;
     a.dL_drgb = dL_drgb;
     a.dL_dT = dL_dT;
-    hipError_t e = launch_raster_bwd(a, plan->total_tiles, plan->cfg.tile_w * plan->cfg.tile_h, (hipStream_t)stream);
+    hipError_t e = launch_raster_bwd(a, plan->total_tiles, plan->cfg.tile_w * plan->cfg.tile_h, plan->cfg.batch,
+                                     (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_raster_bwd");
 }
 

@@ -6,6 +6,8 @@
 //                                      rx < 0 marks a culled slot
 //   conic_o float4 (A, B, C, o)       inverse screen covariance, opacity
 //   rgb_d   float4 (r, g, b, depth)   colour in this view, camera depth z
+//   qthr    float                     level of the quadratic form d^T conic d
+//                                      below which a tile is binned
 //   grad2d  double [9][slots]         screen-space gradient accumulators
 //                                      (du, dv, dA, dB, dC, do, dr, dg, db)
 // The rectangle function below is the binning contract: a pure function of
@@ -69,6 +71,40 @@ __device__ __forceinline__ bool tile_rect(float u, float v, float rx, float ry, 
     x1 = fx1 > mx ? tiles_x - 1 : (int)fx1;
     y1 = fy1 > my ? tiles_y - 1 : (int)fy1;
     return true;
+}
+
+// Second half of the binning contract: candidate tile (tx, ty) of a slot is
+// kept iff q(d) = A dx^2 + 2 B dx dy + C dy^2 (d = pixel centre - (u, v))
+// reaches qthr on the box spanned by the tile's pixel centres.  Inside the
+// box the minimum is 0; otherwise it lies on an edge, at the edge's
+// unconstrained minimiser clamped to the edge.  Float32, this exact order.
+__device__ __forceinline__ bool tile_hit(float u, float v, float A, float B, float C, float qthr, int tx, int ty,
+                                         int tw, int th)
+{
+    const float x0 = ((float)(tx * tw) + 0.5f) - u;
+    const float x1 = ((float)(tx * tw + tw - 1) + 0.5f) - u;
+    const float y0 = ((float)(ty * th) + 0.5f) - v;
+    const float y1 = ((float)(ty * th + th - 1) + 0.5f) - v;
+    if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return true;
+    const float iA = 1.0f / A, iC = 1.0f / C, B2 = 2.0f * B;
+    float m = INFINITY;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float X = e ? x1 : x0;
+        float ys = -(B * X) * iC;
+        ys = ys < y0 ? y0 : (ys > y1 ? y1 : ys);
+        const float q = (A * X) * X + (B2 * X) * ys + (C * ys) * ys;
+        m = q < m ? q : m;
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const float Y = e ? y1 : y0;
+        float xs = -(B * Y) * iA;
+        xs = xs < x0 ? x0 : (xs > x1 ? x1 : xs);
+        const float q = (A * xs) * xs + (B2 * xs) * Y + (C * Y) * Y;
+        m = q < m ? q : m;
+    }
+    return m <= qthr;
 }
 
 // view owning a global tile (views are few; a uniform linear scan)

@@ -11,6 +11,7 @@ struct ProjectArgs {
     const ViewTable* views;    // device copy
     DevCfg cfg;
     float4 *geom, *conic_o, *rgb_d;
+    float* qthr;
 };
 
 struct BinArgs {
@@ -19,6 +20,8 @@ struct BinArgs {
     const ViewTable* views;
     DevCfg cfg;
     const float4* geom;
+    const float4* conic_o;
+    const float* qthr;
     const float4* rgb_d;
     uint32_t* block_sums;      // [n_views * chunks]
     unsigned long long* block_offs;
@@ -45,6 +48,8 @@ struct RangeArgs {
     const unsigned long long* keys;
     uint2* ranges;
     int32_t total_tiles;
+    uint32_t* order;           // [tiles]: tiles by pair count, descending
+    uint32_t* buckets;         // [64]: per log2-bucket counts, then cursors
 };
 
 struct RasterArgs {
@@ -52,6 +57,7 @@ struct RasterArgs {
     DevCfg cfg;
     const Counters* counters;
     const uint2* ranges;
+    const uint32_t* order;     // processing order of the tiles
     const uint32_t* vals;
     const float4 *geom, *conic_o, *rgb_d;
     float* rgb;                // [sum 3 H W]
@@ -97,8 +103,8 @@ hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t s);
 hipError_t launch_bin(const BinArgs& a, hipStream_t s);
 hipError_t launch_sort_pass(const SortArgs& a, int grid_blocks, hipStream_t s);
 hipError_t launch_ranges(const RangeArgs& a, int grid_blocks, hipStream_t s);
-hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, hipStream_t s);
-hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, hipStream_t s);
+hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s);
+hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s);
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, float* d_xi, int n_views,
                               hipStream_t s);
 hipError_t launch_loss_l1(const LossArgs& a, hipStream_t s);

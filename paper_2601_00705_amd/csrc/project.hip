@@ -67,6 +67,10 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
         a.geom[slot] = make_float4(p.u, p.v, p.rx, p.ry);
         a.conic_o[slot] = make_float4(p.A, p.B, p.C, g.o);
         a.rgb_d[slot] = make_float4(rgb[0], rgb[1], rgb[2], p.mc[2]);
+        // binning level of d^T conic d: the alpha_min ellipse 2 ln(o / alpha_min)
+        // widened by 5% + 0.01 so that rounding never drops a tile the
+        // compositing would reach
+        a.qthr[slot] = a.cfg.alpha_min > 0.0f ? 1.05f * (2.0f * logf(g.o / a.cfg.alpha_min)) + 0.01f : INFINITY;
     }
 }
 

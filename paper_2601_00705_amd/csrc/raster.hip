@@ -3,7 +3,7 @@
 // One wavefront (64 lanes) per (view, tile); each lane owns PPT = tile
 // pixels / 64 pixels of one column of the tile (rows l / tile_w + k * 64 /
 // tile_w).  The tile's depth-sorted pair range is walked in batches of
-// BATCH records: every lane stages BATCH / 64 records into LDS, precomputed in
+// BATCH (64, 128 or 256) records: every lane stages BATCH / 64 records into LDS, precomputed in
 // exp2 form (power2 = a dx^2 + b dx dy + c dy^2 with the conic scaled by
 // -log2(e)/2, -log2(e), -log2(e)/2, and the alpha_min test as
 // power2 < log2(alpha_min / o)); then the lane walks the batch for each of its
@@ -30,7 +30,6 @@ namespace gsr {
 
 #define GSR_LOG2E 1.4426950408889634f
 #define GSR_LN2 0.69314718055994531f
-#define GSR_BATCH 128
 
 struct __align__(16) LdsRec {
     float4 p0;  // u, v, a2, b2      (a2 = -0.5 log2e A, b2 = -log2e B)
@@ -58,6 +57,7 @@ __device__ __forceinline__ float power2(float a2dx2, float b2dx, float c2, float
 
 template <int PPT>
 struct TileCtx {
+    int tile;                 // global tile of this workgroup
     int px, py0, rs;          // column, first row, row stride
     bool inside[PPT];
     int64_t pix[PPT];         // index into the concatenated [H][W] planes
@@ -69,7 +69,8 @@ template <int PPT>
 __device__ __forceinline__ TileCtx<PPT> tile_ctx(const RasterArgs& a)
 {
     TileCtx<PPT> c;
-    const int tile = blockIdx.x;
+    c.tile = (int)a.order[blockIdx.x];
+    const int tile = c.tile;
     const int v = view_of_tile(a.views, tile);
     const ViewInfo& vw = a.views->v[v];
     const int lt = tile - vw.tile_base;
@@ -91,14 +92,14 @@ __device__ __forceinline__ TileCtx<PPT> tile_ctx(const RasterArgs& a)
     return c;
 }
 
-template <int PPT>
+template <int PPT, int GSR_BATCH>
 __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
 {
     __shared__ LdsRec rec[GSR_BATCH];
     const TileCtx<PPT> c = tile_ctx<PPT>(a);
     const int lane = threadIdx.x;
     const bool overflow = a.counters->overflow != 0u;
-    const uint2 range = overflow ? make_uint2(0u, 0u) : a.ranges[blockIdx.x];
+    const uint2 range = overflow ? make_uint2(0u, 0u) : a.ranges[c.tile];
     const float fpx = (float)c.px + 0.5f;
     const float amax = a.cfg.alpha_max, tmin = a.cfg.T_min;
     float T[PPT], C0[PPT], C1[PPT], C2[PPT], fpy[PPT];
@@ -189,13 +190,13 @@ __device__ __forceinline__ float field_scale(int f)
     return f < 2 ? -GSR_LN2 : (f == 3 ? -1.0f : (f < 5 ? -0.5f : 1.0f));
 }
 
-template <int PPT>
+template <int PPT, int GSR_BATCH>
 __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
 {
     __shared__ LdsRec rec[GSR_BATCH];
     const TileCtx<PPT> c = tile_ctx<PPT>(a);
     if (a.counters->overflow) return;
-    const uint2 range = a.ranges[blockIdx.x];
+    const uint2 range = a.ranges[c.tile];
     const int lane = threadIdx.x;
     const float fpx = (float)c.px + 0.5f;
     const float amax = a.cfg.alpha_max;
@@ -296,27 +297,40 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
 }
 
 template <int PPT>
-static void launch_fwd_t(const RasterArgs& a, int tiles, hipStream_t s)
+static hipError_t launch_fwd_t(const RasterArgs& a, int tiles, int batch, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_raster_fwd<PPT>, dim3(tiles), dim3(64), 0, s, a);
+    switch (batch) {
+    case 64: hipLaunchKernelGGL((k_raster_fwd<PPT, 64>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 128: hipLaunchKernelGGL((k_raster_fwd<PPT, 128>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 256: hipLaunchKernelGGL((k_raster_fwd<PPT, 256>), dim3(tiles), dim3(64), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipSuccess;
 }
 
 template <int PPT>
-static void launch_bwd_t(const RasterArgs& a, int tiles, hipStream_t s)
+static hipError_t launch_bwd_t(const RasterArgs& a, int tiles, int batch, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_raster_bwd<PPT>, dim3(tiles), dim3(64), 0, s, a);
-}
-
-hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, hipStream_t s)
-{
-    if (total_tiles == 0) return hipSuccess;
-    switch (tile_px) {
-    case 64: launch_fwd_t<1>(a, total_tiles, s); break;
-    case 128: launch_fwd_t<2>(a, total_tiles, s); break;
-    case 256: launch_fwd_t<4>(a, total_tiles, s); break;
+    switch (batch) {
+    case 64: hipLaunchKernelGGL((k_raster_bwd<PPT, 64>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 128: hipLaunchKernelGGL((k_raster_bwd<PPT, 128>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 256: hipLaunchKernelGGL((k_raster_bwd<PPT, 256>), dim3(tiles), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    return hipSuccess;
+}
+
+hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s)
+{
+    if (total_tiles == 0) return hipSuccess;
+    hipError_t e;
+    switch (tile_px) {
+    case 64: e = launch_fwd_t<1>(a, total_tiles, batch, s); break;
+    case 128: e = launch_fwd_t<2>(a, total_tiles, batch, s); break;
+    case 256: e = launch_fwd_t<4>(a, total_tiles, batch, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 // zero the screen-space accumulators of every projected slot (rx >= 0); the
@@ -333,7 +347,7 @@ __global__ void k_clear_grad2d(const float4* geom, double* grad2d, int64_t slots
     }
 }
 
-hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, hipStream_t s)
+hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s)
 {
     if (total_tiles == 0) return hipSuccess;
     if (a.slots > 0) {
@@ -341,13 +355,14 @@ hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, 
         if (blocks > 8192) blocks = 8192;
         hipLaunchKernelGGL(k_clear_grad2d, dim3((unsigned)blocks), dim3(256), 0, s, a.geom, a.grad2d, a.slots);
     }
+    hipError_t e;
     switch (tile_px) {
-    case 64: launch_bwd_t<1>(a, total_tiles, s); break;
-    case 128: launch_bwd_t<2>(a, total_tiles, s); break;
-    case 256: launch_bwd_t<4>(a, total_tiles, s); break;
+    case 64: e = launch_bwd_t<1>(a, total_tiles, batch, s); break;
+    case 128: e = launch_bwd_t<2>(a, total_tiles, batch, s); break;
+    case 256: e = launch_bwd_t<4>(a, total_tiles, batch, s); break;
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    return e != hipSuccess ? e : hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

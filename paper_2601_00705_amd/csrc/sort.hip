@@ -196,6 +196,7 @@ __global__ void k_ranges_zero(RangeArgs a)
 {
     int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < a.total_tiles) a.ranges[t] = make_uint2(0u, 0u);
+    if (t < 64) a.buckets[t] = 0u;
 }
 
 __global__ void k_ranges(RangeArgs a)
@@ -209,10 +210,53 @@ __global__ void k_ranges(RangeArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// processing order of the tiles: descending pair count, bucketed by
+// floor(log2(count)) (bucket 0 holds the longest lists); the compositing
+// kernels take their tile from this order so that long lists start first
+
+__device__ __forceinline__ uint32_t count_bucket(uint2 r)
+{
+    uint32_t c = r.y - r.x;
+    return c == 0u ? 31u : (uint32_t)__clz(c);  // 31 - floor(log2 c)
+}
+
+__global__ void k_order_count(RangeArgs a)
+{
+    __shared__ uint32_t h[32];
+    if (threadIdx.x < 32) h[threadIdx.x] = 0u;
+    __syncthreads();
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < a.total_tiles) atomicAdd(&h[count_bucket(a.ranges[t])], 1u);
+    __syncthreads();
+    if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(&a.buckets[threadIdx.x], h[threadIdx.x]);
+}
+
+__global__ void k_order_place(RangeArgs a)
+{
+    __shared__ uint32_t base[32];
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int b = 0; b < 32; ++b) {
+            base[b] = run;
+            run += a.buckets[b];
+        }
+    }
+    __syncthreads();
+    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < a.total_tiles) {
+        uint32_t b = count_bucket(a.ranges[t]);
+        a.order[base[b] + atomicAdd(&a.buckets[32 + b], 1u)] = (uint32_t)t;
+    }
+}
+
 hipError_t launch_ranges(const RangeArgs& a, int grid_blocks, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ranges_zero, dim3((a.total_tiles + 255) / 256), dim3(256), 0, s, a);
+    const int tb = (a.total_tiles + 255) / 256;
+    hipLaunchKernelGGL(k_ranges_zero, dim3(tb > 0 ? tb : 1), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_ranges, dim3(grid_blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_order_count, dim3(tb), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_order_place, dim3(tb), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

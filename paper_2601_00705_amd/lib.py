@@ -48,7 +48,7 @@ class Grads(ctypes.Structure):
 
 class Layout(ctypes.Structure):
     _fields_ = [(k, ctypes.c_size_t) for k in
-                ("counters", "geom", "conic_o", "rgb_d", "grad2d", "keys", "vals", "ranges", "total")]
+                ("counters", "geom", "conic_o", "rgb_d", "qthr", "grad2d", "keys", "vals", "ranges", "total")]
 
 
 class PlanInfo(ctypes.Structure):
@@ -123,7 +123,7 @@ def make_cameras(cams):
 
 def make_config(cfg):
     c = Config()
-    c.tile_w, c.tile_h, c.batch, c.sh_degree = cfg.tile_w, cfg.tile_h, 0, cfg.sh_degree
+    c.tile_w, c.tile_h, c.batch, c.sh_degree = cfg.tile_w, cfg.tile_h, getattr(cfg, "batch", 0), cfg.sh_degree
     c.z_near, c.dilation = cfg.z_near, cfg.dilation
     c.alpha_min, c.alpha_max, c.T_min = cfg.alpha_min, cfg.alpha_max, cfg.T_min
     for k in range(3):

@@ -24,6 +24,7 @@ class Config:
     T < 1e-4, black background, RGB colour."""
     tile_w: int = 16
     tile_h: int = 16
+    batch: int = 128
     sh_degree: int = -1
     z_near: float = 0.2
     dilation: float = 0.3
@@ -47,7 +48,8 @@ class Renderer:
         self.device = torch.device(device)
         self.total_pixels = sum(int(c["width"]) * int(c["height"]) for c in cams)
         if pair_capacity is None:
-            pair_capacity = max(1 << 16, 8 * self.n * len(cams))
+            # a first guess; forward_all grows it to the measured need
+            pair_capacity = min(max(1 << 16, 8 * self.n * len(cams)), 1 << 26)
         self.plan = None
         self._make(int(min(pair_capacity, (1 << 32) - 1)))
 
@@ -82,6 +84,7 @@ class Renderer:
             "geom": self._view(L.geom, 4 * S, torch.float32).view(S, 4),
             "conic_o": self._view(L.conic_o, 4 * S, torch.float32).view(S, 4),
             "rgb_d": self._view(L.rgb_d, 4 * S, torch.float32).view(S, 4),
+            "qthr": self._view(L.qthr, S, torch.float32),
             "grad2d": self._view(L.grad2d, 9 * S, torch.float64).view(9, S),
         }
 

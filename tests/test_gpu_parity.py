@@ -72,13 +72,20 @@ def _records(cams, n, rng):
     for w, c in enumerate(cams):
         u[w * n:(w + 1) * n] = rng.uniform(-20, c["width"] + 20, n)
         v[w * n:(w + 1) * n] = rng.uniform(-20, c["height"] + 20, n)
-    rx = rng.exponential(6.0, S).astype(np.float32)
-    ry = rng.exponential(6.0, S).astype(np.float32)
+    sa = rng.uniform(0.5, 15.0, S)
+    sc = rng.uniform(0.5, 15.0, S)
+    corr = rng.uniform(-0.95, 0.95, S)
+    a, c2, b = sa ** 2, sc ** 2, corr * sa * sc
+    det = a * c2 - b * b
+    q = rng.uniform(1.0, 12.0, S)
+    A, B, C = (c2 / det).astype(np.float32), (-b / det).astype(np.float32), (a / det).astype(np.float32)
+    qthr = q.astype(np.float32)
+    rx, ry = np.sqrt(q * a).astype(np.float32), np.sqrt(q * c2).astype(np.float32)
     depth = rng.choice(np.array([0.5, 1.0, 1.0000001, 2.0, 7.25], np.float32), S)
     depth[: S // 2] = rng.uniform(0.2, 9.0, S // 2).astype(np.float32)
     # adversarial slots
     u[0], rx[0] = 16.0, 0.0
-    u[1], v[1], rx[1], ry[1] = 10.0, 10.0, 1e9, 1e9
+    u[1], v[1], rx[1], ry[1], qthr[1] = 10.0, 10.0, 1e9, 1e9, np.inf
     rx[2] = -1.0
     u[3] = np.nan
     u[4], rx[4] = -5.0, 1.0
@@ -86,7 +93,18 @@ def _records(cams, n, rng):
     depth[6:20] = 3.0
     u[6:20] = 30.0
     v[6:20] = 20.0
-    return u, v, rx, ry, depth
+    return u, v, rx, ry, A, B, C, qthr, depth
+
+
+def _fill_and_bin(R, rec_arrays):
+    u, v, rx, ry, A, B, C, qthr, depth = rec_arrays
+    rec = R.records()
+    rec["geom"].copy_(torch.from_numpy(np.stack([u, v, rx, ry], 1)))
+    rec["conic_o"][:, :3].copy_(torch.from_numpy(np.stack([A, B, C], 1)))
+    rec["qthr"].copy_(torch.from_numpy(qthr))
+    rec["rgb_d"][:, 3].copy_(torch.from_numpy(depth))
+    R.bin()
+    return R.pair_count()
 
 
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8), (16, 8)])
@@ -98,18 +116,14 @@ def test_bin_bitexact_shared_records(tile):
             {"width": 130, "height": 70, "fx": 1, "fy": 1, "cx": 0, "cy": 0}]
     n = 3000
     rng = np.random.default_rng(7)
-    u, v, rx, ry, depth = _records(cams, n, rng)
     cfg = Config(tile_w=tile[0], tile_h=tile[1])
     say(f"[bin] tile={tile}")
     R = Renderer(n, cams, cfg, pair_capacity=400_000)
-    rec = R.records()
-    rec["geom"].copy_(torch.from_numpy(np.stack([u, v, rx, ry], 1)))
-    rec["rgb_d"][:, 3].copy_(torch.from_numpy(depth))
-    R.bin()
-    M, ovf = R.pair_count()
+    recs = _records(cams, n, rng)
+    M, ovf = _fill_and_bin(R, recs)
     assert not ovf
     keys, vals, ranges = R.sorted_pairs(M)
-    ok_, ov_, or_ = oracle.bin_f32(cams, n, u, v, rx, ry, depth, tile[0], tile[1])
+    ok_, ov_, or_ = oracle.bin_f32(cams, n, *recs, tile[0], tile[1])
     say(f"  pairs={M} passes={R.info.sort_passes}")
     assert M == len(ok_)
     np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint64), ok_)
@@ -124,18 +138,16 @@ def test_bin_bitexact_many_pairs():
             {"width": 640, "height": 480, "fx": 1, "fy": 1, "cx": 0, "cy": 0}]
     n = 120_000
     rng = np.random.default_rng(11)
-    u, v, rx, ry, depth = _records(cams, n, rng)
-    rx *= 3
-    ry *= 2
+    recs = list(_records(cams, n, rng))
+    recs[2] = recs[2] * 3   # rx
+    recs[3] = recs[3] * 2   # ry
+    recs[7] = recs[7] * 9   # qthr: ellipses 3x wider
     say("[bin] many pairs")
-    R = Renderer(n, cams, Config(), pair_capacity=4_000_000)
-    rec = R.records()
-    rec["geom"].copy_(torch.from_numpy(np.stack([u, v, rx, ry], 1)))
-    rec["rgb_d"][:, 3].copy_(torch.from_numpy(depth))
-    R.bin()
-    M, ovf = R.pair_count()
+    R = Renderer(n, cams, Config(), pair_capacity=12_000_000)
+    M, ovf = _fill_and_bin(R, recs)
+    assert not ovf
     keys, vals, ranges = R.sorted_pairs(M)
-    ok_, ov_, or_ = oracle.bin_f32(cams, n, u, v, rx, ry, depth, 16, 16)
+    ok_, ov_, or_ = oracle.bin_f32(cams, n, *recs, 16, 16)
     say(f"  pairs={M}")
     assert M == len(ok_) and M > 1_000_000
     np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint64), ok_)

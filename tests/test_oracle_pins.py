@@ -291,7 +291,32 @@ def test_tiled_equals_brute_force(seed):
         np.testing.assert_array_equal(o["rgb"], outs[0]["rgb"])
 
 
-def _bin_reference(cams, n, u, v, rx, ry, depth, tw, th):
+def _tile_hit_ref(u, v, A, B, C, q, tx, ty, tw, th):
+    """Restatement of the tile test in NumPy float32 (same operation order)."""
+    f = np.float32
+    x0 = (f(tx * tw) + f(0.5)) - u
+    x1 = (f(tx * tw + tw - 1) + f(0.5)) - u
+    y0 = (f(ty * th) + f(0.5)) - v
+    y1 = (f(ty * th + th - 1) + f(0.5)) - v
+    if x0 <= 0 and x1 >= 0 and y0 <= 0 and y1 >= 0:
+        return True
+    with np.errstate(all="ignore"):
+        iA, iC, B2 = f(1) / A, f(1) / C, f(2) * B
+        m = f(np.inf)
+        for X in (x0, x1):
+            ys = -(B * X) * iC
+            ys = y0 if ys < y0 else (y1 if ys > y1 else ys)
+            qq = (A * X) * X + (B2 * X) * ys + (C * ys) * ys
+            m = qq if qq < m else m
+        for Y in (y0, y1):
+            xs = -(B * Y) * iA
+            xs = x0 if xs < x0 else (x1 if xs > x1 else xs)
+            qq = (A * xs) * xs + (B2 * xs) * Y + (C * Y) * Y
+            m = qq if qq < m else m
+    return bool(m <= q)
+
+
+def _bin_reference(cams, n, u, v, rx, ry, A, B, C, q, depth, tw, th):
     """Python restatement of the binning contract on float32 values."""
     f32 = np.float32
     pairs = []
@@ -313,34 +338,48 @@ def _bin_reference(cams, n, u, v, rx, ry, depth, tw, th):
             bits = int(np.array([d], dtype=np.float32).view(np.uint32)[0])
             for ty in range(int(max(y0, 0)), int(min(y1, ty_n - 1)) + 1):
                 for tx in range(int(max(x0, 0)), int(min(x1, tx_n - 1)) + 1):
-                    pairs.append((((base + ty * tx_n + tx) << 32) | bits, s))
+                    if _tile_hit_ref(uu, vv, f32(A[s]), f32(B[s]), f32(C[s]), f32(q[s]), tx, ty, tw, th):
+                        pairs.append((((base + ty * tx_n + tx) << 32) | bits, s))
         base += tx_n * ty_n
     pairs.sort()
     return pairs, base
 
 
+def _random_conics(rng, S):
+    """Random SPD 2x2 inverse covariances (A, B, C) and thresholds."""
+    sa = rng.uniform(0.5, 30.0, S)
+    sc = rng.uniform(0.5, 30.0, S)
+    corr = rng.uniform(-0.95, 0.95, S)
+    a, c = sa ** 2, sc ** 2
+    b = corr * sa * sc
+    det = a * c - b * b
+    q = rng.uniform(1.0, 12.0, S)
+    return (c / det).astype(np.float32), (-b / det).astype(np.float32), (a / det).astype(np.float32), \
+        q.astype(np.float32), np.sqrt(q * a).astype(np.float32), np.sqrt(q * c).astype(np.float32)
+
+
 def test_bin_contract_adversarial():
     """Depth ordering of N(p) (Sec. Alpha Compositing for Color) as (tile,
-    depth-bits, slot) order on float32 records: equal depths, border rects,
-    empty and culled slots, NaN, a slot covering every tile, two views."""
+    depth-bits, slot) order on float32 records, tiles kept by the ellipse
+    test: equal depths, border rects, empty and culled slots, NaN, a slot
+    covering every tile, two views."""
     cams = [{"width": 50, "height": 33}, {"width": 17, "height": 40}]
     n = 60
     rng = np.random.default_rng(0)
     u = rng.uniform(-10, 60, 2 * n).astype(np.float32)
     v = rng.uniform(-10, 45, 2 * n).astype(np.float32)
-    rx = rng.uniform(0, 12, 2 * n).astype(np.float32)
-    ry = rng.uniform(0, 12, 2 * n).astype(np.float32)
+    A, B, C, q, rx, ry = _random_conics(rng, 2 * n)
     depth = rng.choice(np.array([1.0, 2.0, 2.5], np.float32), 2 * n)
     u[0], rx[0] = 16.0, 0.0          # exactly on a tile edge
-    u[1], rx[1] = 25.0, 1e9           # covers every tile column
-    ry[1] = 1e9
+    u[1], rx[1] = 25.0, 1e9           # covers every tile
+    ry[1], q[1] = 1e9, np.inf
     rx[2] = -1.0                       # culled
     u[3] = np.nan                      # invalid
     depth[4] = 0.0                     # zero depth still sorts by its bits
     u[5], rx[5] = -5.0, 1.0            # entirely left of the image
     u[6], v[6], rx[6], ry[6] = 49.99, 32.99, 0.0, 0.0  # last pixel
-    keys, vals, ranges = oracle.bin_f32(cams, n, u, v, rx, ry, depth, 16, 16)
-    ref, n_tiles = _bin_reference(cams, n, u, v, rx, ry, depth, 16, 16)
+    keys, vals, ranges = oracle.bin_f32(cams, n, u, v, rx, ry, A, B, C, q, depth, 16, 16)
+    ref, n_tiles = _bin_reference(cams, n, u, v, rx, ry, A, B, C, q, depth, 16, 16)
     assert len(ref) == len(keys)
     np.testing.assert_array_equal(keys, np.array([k for k, _ in ref], dtype=np.uint64))
     np.testing.assert_array_equal(vals, np.array([s for _, s in ref], dtype=np.uint32))
@@ -352,6 +391,33 @@ def test_bin_contract_adversarial():
             assert ranges[t, 0] == idx[0] and ranges[t, 1] == idx[-1] + 1
         else:
             assert ranges[t, 0] == 0 and ranges[t, 1] == 0
+
+
+def test_bin_tile_test_is_conservative():
+    """Every pixel centre whose quadratic form (FP64) lies below the
+    threshold keeps its tile, and the test prunes tiles of the rectangle
+    (it is not vacuous)."""
+    cams = [{"width": 96, "height": 80}]
+    n = 400
+    rng = np.random.default_rng(4)
+    u = rng.uniform(0, 96, n).astype(np.float32)
+    v = rng.uniform(0, 80, n).astype(np.float32)
+    A, B, C, q, rx, ry = _random_conics(rng, n)
+    depth = np.ones(n, np.float32)
+    keys, vals, _ = oracle.bin_f32(cams, n, u, v, rx, ry, A, B, C, q, depth, 8, 8)
+    kept = set(zip(vals.tolist(), (keys >> np.uint64(32)).astype(np.int64).tolist()))
+    py, px = np.mgrid[0:80, 0:96] + 0.5
+    rect_pairs = 0
+    for s in range(n):
+        dx, dy = px - float(u[s]), py - float(v[s])
+        qq = float(A[s]) * dx * dx + 2 * float(B[s]) * dx * dy + float(C[s]) * dy * dy
+        inside = qq <= float(q[s]) * (1 - 1e-6)
+        for (yy, xx) in zip(*np.nonzero(inside)):
+            assert (s, (yy // 8) * 12 + xx // 8) in kept
+        x0, x1 = max(0, int((u[s] - rx[s]) // 8)), min(11, int((u[s] + rx[s]) // 8))
+        y0, y1 = max(0, int((v[s] - ry[s]) // 8)), min(9, int((v[s] + ry[s]) // 8))
+        rect_pairs += max(0, x1 - x0 + 1) * max(0, y1 - y0 + 1)
+    assert len(keys) < 0.9 * rect_pairs
 
 
 # ---------------------------------------------------------------- P7 ----
