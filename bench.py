@@ -24,17 +24,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# MI355X published peaks
+# MI355X peaks.  HBM: published 8 TB/s.  VALU issue: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz = 39.3e12 lane-operations/s for unpacked FP32 (the published
+# 157.3 TFLOP/s counts packed FMAs as 4 flops per lane; packed FP32 is not
+# generated here), a transcendental taking 4 issue slots (quarter rate).
 HBM_PEAK_GBS = 8000.0
-FP32_VECTOR_PEAK_TFLOPS = 157.3
+VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
 
-# Algorithmic FP32 work per blended (pixel, Gaussian) pair, FMA = 2 flops,
-# a transcendental = 1 (see the design notes for the derivation).
-FLOPS_FWD_PER_BLEND = 21
-FLOPS_BWD_PER_BLEND = 48
-# Algorithmic HBM bytes of the projection backward per live slot / Gaussian
-BYTES_PBWD_PER_SLOT = 16 + 36       # geom record + screen-space gradient
+# Algorithmic VALU issue slots per evaluation (one pixel against one list
+# entry up to the pixel's last contributor), counted from the per-pixel
+# formulas of the forward and backward compositing (design notes):
+# forward 17 operations + exp2 (4 slots); backward 46 operations + exp2 + rcp.
+SLOTS_FWD_PER_EVAL = 17 + 4
+SLOTS_BWD_PER_EVAL = 46 + 4 + 4
+# Algorithmic HBM bytes of one sort pass per pair: key + value read and written
+BYTES_SORT_PASS_PER_PAIR = 2 * (8 + 4)
+# Projection backward: per live slot the geom record and the nine FP64
+# screen-space gradients; per Gaussian the parameters read and gradients written
+BYTES_PBWD_PER_SLOT = 16 + 9 * 8
 BYTES_PBWD_PER_GAUSSIAN_RGB = 56 + 56
+
+# files whose text defines the compositing kernels (a counter summary is only
+# used while they are unchanged)
+KERNEL_SOURCES = ("paper_2601_00705_amd/csrc/raster.hip", "paper_2601_00705_amd/csrc/gsr_device.h",
+                  "paper_2601_00705_amd/csrc/kernels.h")
 
 
 def log(*a):
@@ -113,6 +126,38 @@ def sized_renderer(Renderer, n, cams, cfg, params, poses, torch, slack=1.15):
     need, _ = R.pair_count()
     R._make(int(need * slack) + 4096)
     return R, need
+
+
+def sources_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, cfg):
+    """HBM bytes per launch of `kernel` from a committed rocprofv3 counter
+    summary (profiles/<kernel>.<workload>.md), or None when there is none
+    for this workload and tile setting or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}.{workload}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            k, sep, v = line.strip().lstrip("-* ").partition(":")
+            if sep:
+                fields[k.strip()] = v.strip().strip("`")
+    if fields.get("sources_sha256") != sources_digest():
+        return None
+    if fields.get("tile") != f"{cfg.tile_w}x{cfg.tile_h}/{cfg.batch}":
+        return None
+    try:
+        return float(fields["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def oracle_sample(w, views, cfg):
@@ -206,39 +251,49 @@ def main():
     torch.cuda.synchronize()
     _, ovf = R.pair_count()
     assert not ovf, "pair capacity exceeded during replay"
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    marks[0].record()
+    for k in range(args.steps):
         graph.replay()
+        marks[k + 1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
-    log(f"batched (graph): {ms_step:.3f} ms/step, pairs {need}")
+    per_step = sorted(marks[k].elapsed_time(marks[k + 1]) for k in range(args.steps))
+    pct = {q: float(np.percentile(per_step, q)) for q in (10, 50, 90)}
+    log(f"batched (graph): {ms_step:.3f} ms/step (p10 {pct[10]:.3f}, p50 {pct[50]:.3f}, p90 {pct[90]:.3f}), "
+        f"pairs {need}")
 
-    # ---------------- per-stage HIP-event timing (eager) ---------------
-    stages = st.stages()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in stages]
-    acc = [0.0] * len(stages)
+    # ---------------- per-kernel device time: library HIP events ----------
+    # (eager launches of the same step on the same inputs, right after the
+    # timed replays; every group is bracketed on the stream it runs on)
     K = max(3, args.steps // 2)
-    stream = torch.cuda.current_stream()
+    R.set_timing(True)
     for _ in range(K):
-        for k, (_, f) in enumerate(stages):
-            ev[k][0].record(stream)
-            f()
-            ev[k][1].record(stream)
-        torch.cuda.synchronize()
-        for k in range(len(stages)):
-            acc[k] += ev[k][0].elapsed_time(ev[k][1])
-    stage_ms = {name: acc[k] / K for k, (name, _) in enumerate(stages)}
-    log("stage ms: " + ", ".join(f"{k}={v:.3f}" for k, v in stage_ms.items()))
+        st.run()
+    timing = R.read_timing()
+    R.set_timing(False)
+    kernel_ms = {g: (ms / cnt if cnt else 0.0) for g, (ms, cnt) in timing.items()}
+    stage_ms = {
+        "project": kernel_ms["project"],
+        "bin": kernel_ms["bin_emit"] + kernel_ms["bin_sort"] + kernel_ms["bin_ranges"],
+        "raster_fwd": kernel_ms["raster_fwd"],
+        "loss_l1": kernel_ms["loss_l1"],
+        "raster_bwd": kernel_ms["clear_grad2d"] + kernel_ms["raster_bwd"],
+        "project_bwd": kernel_ms["project_bwd"],
+    }
+    log("kernel ms: " + ", ".join(f"{k}={v:.3f}" for k, v in kernel_ms.items()))
 
     # ---------------- blends / evaluations (untimed counting pass) -----
     nb = torch.empty(total_px, dtype=torch.int32, device=dev)
     R.render_fwd(st.rgb, st.T, st.nc, nb)
     torch.cuda.synchronize()
     blends = int(nb.sum(dtype=torch.int64))
-    contrib_entries = int(st.nc.sum(dtype=torch.int64))
+    evals = int(st.nc.sum(dtype=torch.int64))
     slots_live = int((R.records()["geom"][:, 2] >= 0).sum())
-    log(f"blends {blends}, list entries up to last contributor {contrib_entries}, live slots {slots_live}")
+    log(f"blends {blends}, evaluations (list entries up to the last contributor) {evals}, "
+        f"live slots {slots_live}")
 
     # ---------------- plain: one plan per view, no graph ---------------
     plain = None
@@ -264,24 +319,24 @@ def main():
         log(f"plain ({V} per-view launch sequences): {plain:.3f} ms/step; speedup {plain / ms_step:.2f}x")
 
     # ---------------- roofline of the dominant kernel ------------------
-    dom = max(stage_ms, key=stage_ms.get)
-    dom_ms = stage_ms[dom]
-    if dom == "raster_bwd":
-        roof = {"bound": "alu", "achieved": blends * FLOPS_BWD_PER_BLEND / (dom_ms * 1e-3) / 1e12,
-                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s"}
-    elif dom == "raster_fwd":
-        roof = {"bound": "alu", "achieved": blends * FLOPS_FWD_PER_BLEND / (dom_ms * 1e-3) / 1e12,
-                "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s"}
-    elif dom == "bin":
+    dom = max(kernel_ms, key=kernel_ms.get)
+    dom_ms = kernel_ms[dom]
+    if dom in ("raster_bwd", "raster_fwd"):
+        per = SLOTS_BWD_PER_EVAL if dom == "raster_bwd" else SLOTS_FWD_PER_EVAL
+        roof = {"bound": "alu", "achieved": evals * per / (dom_ms * 1e-3) / 1e12, "peak": VALU_PEAK_TSLOTS,
+                "unit": "Tslot/s", "work": f"{per} VALU slots x {evals} evaluations"}
+    elif dom == "bin_sort":
         passes = R.info.sort_passes
-        algo = need * (12 + passes * 32 + 8)
-        roof = {"bound": "hbm", "achieved": algo / (dom_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        algo = need * passes * BYTES_SORT_PASS_PER_PAIR
+        roof = {"bound": "hbm", "achieved": algo / (dom_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "work": f"{BYTES_SORT_PASS_PER_PAIR} B x {passes} passes x {need} pairs"}
     else:
         algo = slots_live * BYTES_PBWD_PER_SLOT + n * BYTES_PBWD_PER_GAUSSIAN_RGB
-        roof = {"bound": "hbm", "achieved": algo / (dom_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        roof = {"bound": "hbm", "achieved": algo / (dom_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "work": f"{algo} B"}
     roof["kernel"] = dom
     roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
+    roof["traffic"] = measured_traffic(dom, w["name"], cfg)
 
     # ---------------- CPU baseline: the oracle on a bounded sample -----
     cpu = None
@@ -289,11 +344,11 @@ def main():
         if args.cpu_views:
             views = [int(x) for x in args.cpu_views.split(",")]
         else:
-            # smallest views first, about 0.1-0.2 Mpix of work
+            # smallest views first, about 0.4-0.5 Mpix of work (10-30 s)
             order = sorted(range(V), key=lambda v: cams[v]["width"] * cams[v]["height"])
             views, px = [], 0
             for v in order:
-                if px >= 100_000:
+                if px >= 400_000:
                     break
                 views.append(v)
                 px += cams[v]["width"] * cams[v]["height"]
@@ -321,13 +376,16 @@ def main():
                    "tile": f"{cfg.tile_w}x{cfg.tile_h}", "batch": cfg.batch, "sh_degree": cfg.sh_degree,
                    "mode": "batched-graph"},
         "autotune_ms": None if tuned is None else tuned["ms"],
+        "ms_per_step_p10_p50_p90": [pct[10], pct[50], pct[90]],
         "blends_per_s": blends / (ms_step * 1e-3),
         "blends_per_step": blends,
+        "evaluations_per_step": evals,
         "pairs_per_step": need,
         "plain_ms_per_step": plain,
         "plain_mpix_per_s": None if plain is None else total_px / (plain * 1e-3) / 1e6,
         "batched_speedup": None if plain is None else plain / ms_step,
         "stage_ms": stage_ms,
+        "kernel_ms": kernel_ms,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

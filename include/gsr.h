@@ -142,8 +142,7 @@ gsr_status gsr_plan_layout(const gsr_plan *plan, gsr_layout *out);
 gsr_status gsr_plan_get_info(const gsr_plan *plan, gsr_plan_info *out);
 
 /* Eq. (proj): projects every Gaussian into every view (poses: device
- * [n_views][12]).  Writes the geom / conic_o / rgb_d records and clears the
- * screen-space gradient accumulators of live slots. */
+ * [n_views][12]).  Writes the geom / conic_o / rgb_d / qthr records. */
 gsr_status gsr_project(gsr_plan *plan, const gsr_gaussians *g, const float *poses, void *stream);
 
 /* Builds the depth-ordered per-tile lists from the geom / conic_o / qthr /
@@ -189,6 +188,31 @@ gsr_status gsr_project_bwd(gsr_plan *plan, const gsr_gaussians *g, const float *
 /* Synchronises `stream`, then reports the pair count of the last binning
  * and whether it exceeded the capacity. */
 gsr_status gsr_pair_count(gsr_plan *plan, int64_t *required, int32_t *overflow, void *stream);
+
+/* Device time of the library's kernels, for benchmarks and profiling.
+ * While timing is on, each launch group below is bracketed by two HIP events
+ * recorded on the launch stream (not while that stream is being captured
+ * into a graph, where nothing is recorded).  The events are host objects of
+ * the plan; no device memory is allocated.  Switching timing on clears the
+ * totals.  gsr_plan_read_timing waits for the events recorded so far (it
+ * synchronises with them) and reports, for one group, the summed
+ * milliseconds and the number of timed launches since timing was switched
+ * on.  Returns GSR_EINVAL for an unknown group. */
+typedef enum {
+    GSR_T_PROJECT = 0,  /* gsr_project's kernel */
+    GSR_T_BIN_EMIT,     /* pair counting, offsets and emission */
+    GSR_T_BIN_SORT,     /* ordering of the pairs */
+    GSR_T_BIN_RANGES,   /* tile ranges and the tiles' processing order */
+    GSR_T_RASTER_FWD,   /* compositing forward kernel */
+    GSR_T_LOSS_L1,      /* gsr_loss_l1's kernel */
+    GSR_T_CLEAR_GRAD2D, /* zeroing of the screen-space gradient accumulators */
+    GSR_T_RASTER_BWD,   /* compositing backward kernel */
+    GSR_T_PROJECT_BWD,  /* projection backward and the pose reduction */
+    GSR_T_COUNT
+} gsr_timer;
+
+gsr_status gsr_plan_set_timing(gsr_plan *plan, int32_t enable);
+gsr_status gsr_plan_read_timing(gsr_plan *plan, int32_t timer, double *total_ms, int64_t *launches);
 
 const char *gsr_status_str(gsr_status s);
 /* Detail of the last failure on the calling thread ("" if none). */

@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "gsr.h"
@@ -48,6 +49,69 @@ struct gsr_plan {
     char* ws = nullptr;
     Counters host_counters{};
     std::vector<uint32_t> identity_order;
+    // optional per-group device timing (host event objects only)
+    bool timing = false;
+    std::vector<hipEvent_t> event_pool;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[GSR_T_COUNT];
+    double timed_ms[GSR_T_COUNT] = {};
+    int64_t timed_launches[GSR_T_COUNT] = {};
+
+    ~gsr_plan()
+    {
+        for (auto& v : pending)
+            for (auto& pr : v) {
+                (void)hipEventDestroy(pr.first);
+                (void)hipEventDestroy(pr.second);
+            }
+        for (hipEvent_t e : event_pool) (void)hipEventDestroy(e);
+    }
+};
+
+static hipEvent_t take_event(gsr_plan* p)
+{
+    if (!p->event_pool.empty()) {
+        hipEvent_t e = p->event_pool.back();
+        p->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+// Brackets one launch group with events on its stream while timing is on and
+// the stream is not being captured.
+class Timed {
+public:
+    Timed(gsr_plan* p, int group, hipStream_t s) : p_(p), group_(group), s_(s)
+    {
+        if (!p->timing) return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+        e0_ = take_event(p);
+        if (e0_ && hipEventRecord(e0_, s) != hipSuccess) {
+            p->event_pool.push_back(e0_);
+            e0_ = nullptr;
+        }
+    }
+    ~Timed()
+    {
+        if (!e0_) return;
+        hipEvent_t e1 = take_event(p_);
+        if (e1 && hipEventRecord(e1, s_) == hipSuccess) {
+            p_->pending[group_].push_back({e0_, e1});
+            return;
+        }
+        p_->event_pool.push_back(e0_);
+        if (e1) p_->event_pool.push_back(e1);
+    }
+    Timed(const Timed&) = delete;
+    Timed& operator=(const Timed&) = delete;
+
+private:
+    gsr_plan* p_;
+    int group_;
+    hipStream_t s_;
+    hipEvent_t e0_ = nullptr;
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -285,6 +349,7 @@ extern "C" gsr_status gsr_project(gsr_plan* plan, const gsr_gaussians* g, const 
     a.conic_o = at<float4>(plan, plan->off_conic);
     a.rgb_d = at<float4>(plan, plan->off_rgbd);
     a.qthr = at<float>(plan, plan->off_qthr);
+    Timed t(plan, GSR_T_PROJECT, (hipStream_t)stream);
     hipError_t e = launch_project(a, plan->cfg.sh_degree, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_project");
 }
@@ -310,23 +375,30 @@ extern "C" gsr_status gsr_bin(gsr_plan* plan, void* stream)
     b.counters = at<Counters>(plan, plan->off_counters);
     b.keys = at<unsigned long long>(plan, plan->off_keys0);
     b.vals = at<uint32_t>(plan, plan->off_vals0);
-    hipError_t e = launch_bin(b, s);
-    if (e != hipSuccess) return hip_fail(e, "gsr_bin: emit");
-    for (int pass = 0; pass < plan->passes; ++pass) {
-        SortArgs a{};
-        a.counters = b.counters;
-        bool odd = pass & 1;
-        a.keys_in = at<unsigned long long>(plan, odd ? plan->off_keys1 : plan->off_keys0);
-        a.vals_in = at<uint32_t>(plan, odd ? plan->off_vals1 : plan->off_vals0);
-        a.keys_out = at<unsigned long long>(plan, odd ? plan->off_keys0 : plan->off_keys1);
-        a.vals_out = at<uint32_t>(plan, odd ? plan->off_vals0 : plan->off_vals1);
-        a.hist = at<uint32_t>(plan, plan->off_hist);
-        a.digit_total = at<uint32_t>(plan, plan->off_dtotal);
-        a.max_blocks = plan->sort_max_blocks;
-        a.shift = 8 * pass;
-        e = launch_sort_pass(a, plan->sort_grid, s);
-        if (e != hipSuccess) return hip_fail(e, "gsr_bin: sort");
+    hipError_t e;
+    {
+        Timed t(plan, GSR_T_BIN_EMIT, s);
+        e = launch_bin(b, s);
     }
+    if (e != hipSuccess) return hip_fail(e, "gsr_bin: emit");
+    {
+        Timed t(plan, GSR_T_BIN_SORT, s);
+        for (int pass = 0; pass < plan->passes && e == hipSuccess; ++pass) {
+            SortArgs a{};
+            a.counters = b.counters;
+            bool odd = pass & 1;
+            a.keys_in = at<unsigned long long>(plan, odd ? plan->off_keys1 : plan->off_keys0);
+            a.vals_in = at<uint32_t>(plan, odd ? plan->off_vals1 : plan->off_vals0);
+            a.keys_out = at<unsigned long long>(plan, odd ? plan->off_keys0 : plan->off_keys1);
+            a.vals_out = at<uint32_t>(plan, odd ? plan->off_vals0 : plan->off_vals1);
+            a.hist = at<uint32_t>(plan, plan->off_hist);
+            a.digit_total = at<uint32_t>(plan, plan->off_dtotal);
+            a.max_blocks = plan->sort_max_blocks;
+            a.shift = 8 * pass;
+            e = launch_sort_pass(a, plan->sort_grid, s);
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, "gsr_bin: sort");
     RangeArgs r{};
     r.counters = b.counters;
     r.keys = at<unsigned long long>(plan, final_buffer(plan) ? plan->off_keys1 : plan->off_keys0);
@@ -334,7 +406,10 @@ extern "C" gsr_status gsr_bin(gsr_plan* plan, void* stream)
     r.total_tiles = plan->total_tiles;
     r.order = at<uint32_t>(plan, plan->off_order);
     r.buckets = at<uint32_t>(plan, plan->off_buckets);
-    e = launch_ranges(r, plan->sort_grid < 1024 ? plan->sort_grid * 4 : 4096, s);
+    {
+        Timed t(plan, GSR_T_BIN_RANGES, s);
+        e = launch_ranges(r, plan->sort_grid < 1024 ? plan->sort_grid * 4 : 4096, s);
+    }
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_bin: ranges");
 }
 
@@ -367,6 +442,7 @@ extern "C" gsr_status gsr_render_fwd(gsr_plan* plan, float* rgb, float* T_final,
     a.T_final = T_final;
     a.n_contrib = n_contrib;
     a.n_blend = n_blend;
+    Timed t(plan, GSR_T_RASTER_FWD, (hipStream_t)stream);
     hipError_t e = launch_raster_fwd(a, plan->total_tiles, plan->cfg.tile_w * plan->cfg.tile_h, plan->cfg.batch,
                                      (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_render_fwd");
@@ -384,6 +460,7 @@ extern "C" gsr_status gsr_loss_l1(gsr_plan* plan, const float* rgb, const float*
     a.dL_drgb = dL_drgb;
     a.count = 3 * plan->total_pixels;
     a.scale = a.count ? 1.0f / (float)a.count : 0.0f;
+    Timed t(plan, GSR_T_LOSS_L1, (hipStream_t)stream);
     hipError_t e = launch_loss_l1(a, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_loss_l1");
 }
@@ -400,8 +477,15 @@ extern "C" gsr_status gsr_raster_bwd(gsr_plan* plan, const float* T_final, const
     a.n_contrib_in = n_contrib;
     a.dL_drgb = dL_drgb;
     a.dL_dT = dL_dT;
-    hipError_t e = launch_raster_bwd(a, plan->total_tiles, plan->cfg.tile_w * plan->cfg.tile_h, plan->cfg.batch,
-                                     (hipStream_t)stream);
+    hipError_t e;
+    {
+        Timed t(plan, GSR_T_CLEAR_GRAD2D, (hipStream_t)stream);
+        e = launch_clear_grad2d(a, (hipStream_t)stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "gsr_raster_bwd: clear");
+    Timed t(plan, GSR_T_RASTER_BWD, (hipStream_t)stream);
+    e = launch_raster_bwd(a, plan->total_tiles, plan->cfg.tile_w * plan->cfg.tile_h, plan->cfg.batch,
+                          (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_raster_bwd");
 }
 
@@ -441,6 +525,7 @@ extern "C" gsr_status gsr_project_bwd(gsr_plan* plan, const gsr_gaussians* g, co
     b.d_colour = grads ? grads->d_colour : nullptr;
     b.xi_partial = at<double>(plan, plan->off_xip);
     b.blocks = plan->bwd_blocks;
+    Timed t(plan, GSR_T_PROJECT_BWD, (hipStream_t)stream);
     hipError_t e = launch_project_bwd(b, plan->cfg.sh_degree, d_xi, plan->V, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_project_bwd");
 }
@@ -472,6 +557,50 @@ extern "C" gsr_status gsr_pair_count(gsr_plan* plan, int64_t* required, int32_t*
     if (required) *required = (int64_t)c.pairs;
     if (overflow) *overflow = (int32_t)c.overflow;
     return c.overflow ? GSR_ECAPACITY : GSR_OK;
+}
+
+extern "C" gsr_status gsr_plan_set_timing(gsr_plan* plan, int32_t enable)
+{
+    g_err.clear();
+    if (!plan) return fail(GSR_EINVAL, "null plan");
+    for (auto& v : plan->pending) {
+        for (auto& pr : v) {
+            plan->event_pool.push_back(pr.first);
+            plan->event_pool.push_back(pr.second);
+        }
+        v.clear();
+    }
+    for (int k = 0; k < GSR_T_COUNT; ++k) {
+        plan->timed_ms[k] = 0.0;
+        plan->timed_launches[k] = 0;
+    }
+    plan->timing = enable != 0;
+    return GSR_OK;
+}
+
+extern "C" gsr_status gsr_plan_read_timing(gsr_plan* plan, int32_t timer, double* total_ms, int64_t* launches)
+{
+    g_err.clear();
+    if (!plan) return fail(GSR_EINVAL, "null plan");
+    if (timer < 0 || timer >= GSR_T_COUNT) return fail(GSR_EINVAL, "unknown timer");
+    auto& v = plan->pending[timer];
+    size_t done = 0;
+    hipError_t e = hipSuccess;
+    for (; done < v.size(); ++done) {
+        e = hipEventSynchronize(v[done].second);
+        float ms = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, v[done].first, v[done].second);
+        if (e != hipSuccess) break;
+        plan->timed_ms[timer] += ms;
+        plan->timed_launches[timer] += 1;
+        plan->event_pool.push_back(v[done].first);
+        plan->event_pool.push_back(v[done].second);
+    }
+    v.erase(v.begin(), v.begin() + (std::ptrdiff_t)done);
+    if (e != hipSuccess) return hip_fail(e, "gsr_plan_read_timing");
+    if (total_ms) *total_ms = plan->timed_ms[timer];
+    if (launches) *launches = plan->timed_launches[timer];
+    return GSR_OK;
 }
 
 extern "C" const char* gsr_status_str(gsr_status s)

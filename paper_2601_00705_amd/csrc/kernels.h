@@ -104,6 +104,7 @@ hipError_t launch_bin(const BinArgs& a, hipStream_t s);
 hipError_t launch_sort_pass(const SortArgs& a, int grid_blocks, hipStream_t s);
 hipError_t launch_ranges(const RangeArgs& a, int grid_blocks, hipStream_t s);
 hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s);
+hipError_t launch_clear_grad2d(const RasterArgs& a, hipStream_t s);
 hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s);
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, float* d_xi, int n_views,
                               hipStream_t s);

@@ -347,14 +347,18 @@ __global__ void k_clear_grad2d(const float4* geom, double* grad2d, int64_t slots
     }
 }
 
+hipError_t launch_clear_grad2d(const RasterArgs& a, hipStream_t s)
+{
+    if (a.slots <= 0) return hipSuccess;
+    int64_t blocks = (a.slots + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    hipLaunchKernelGGL(k_clear_grad2d, dim3((unsigned)blocks), dim3(256), 0, s, a.geom, a.grad2d, a.slots);
+    return hipGetLastError();
+}
+
 hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s)
 {
     if (total_tiles == 0) return hipSuccess;
-    if (a.slots > 0) {
-        int64_t blocks = (a.slots + 255) / 256;
-        if (blocks > 8192) blocks = 8192;
-        hipLaunchKernelGGL(k_clear_grad2d, dim3((unsigned)blocks), dim3(256), 0, s, a.geom, a.grad2d, a.slots);
-    }
     hipError_t e;
     switch (tile_px) {
     case 64: e = launch_bwd_t<1>(a, total_tiles, batch, s); break;

@@ -80,6 +80,8 @@ def _load():
         "gsr_raster_bwd": (st, [P, P, P, P, P, P]),
         "gsr_project_bwd": (st, [P, P, P, P, P, P, P]),
         "gsr_pair_count": (st, [P, P, P, P]),
+        "gsr_plan_set_timing": (st, [P, ctypes.c_int32]),
+        "gsr_plan_read_timing": (st, [P, ctypes.c_int32, P, P]),
         "gsr_status_str": (ctypes.c_char_p, [st]),
         "gsr_last_error": (ctypes.c_char_p, []),
     }
@@ -94,7 +96,11 @@ _lib = _load()
 EXPORTS = ("gsr_plan_create", "gsr_plan_destroy", "gsr_plan_workspace_bytes", "gsr_plan_bind",
            "gsr_plan_layout", "gsr_plan_get_info", "gsr_project", "gsr_bin", "gsr_render_fwd",
            "gsr_loss_l1", "gsr_render_bwd", "gsr_raster_bwd", "gsr_project_bwd", "gsr_pair_count",
-           "gsr_status_str", "gsr_last_error")
+           "gsr_plan_set_timing", "gsr_plan_read_timing", "gsr_status_str", "gsr_last_error")
+
+# launch groups of gsr_plan_read_timing (gsr_timer)
+TIMERS = ("project", "bin_emit", "bin_sort", "bin_ranges", "raster_fwd", "loss_l1", "clear_grad2d",
+          "raster_bwd", "project_bwd")
 
 
 def raw():
@@ -227,3 +233,19 @@ def gsr_pair_count(plan, stream):
     if s not in (OK, ECAPACITY):
         check(s, "gsr_pair_count")
     return int(req.value), bool(ovf.value)
+
+
+def gsr_plan_set_timing(plan, enable):
+    check(_lib.gsr_plan_set_timing(plan, 1 if enable else 0), "gsr_plan_set_timing")
+
+
+def gsr_plan_read_timing(plan):
+    """{group: (total ms, launches)} for every launch group (waits for the
+    recorded events)."""
+    out = {}
+    for k, name in enumerate(TIMERS):
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        check(_lib.gsr_plan_read_timing(plan, k, ctypes.byref(ms), ctypes.byref(cnt)), "gsr_plan_read_timing")
+        out[name] = (ms.value, cnt.value)
+    return out

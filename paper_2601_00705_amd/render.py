@@ -132,6 +132,14 @@ class Renderer:
         g = None if grads is None else lib.Grads(*(lib._p(grads[k]) for k in PARAM_KEYS))
         lib.gsr_project_bwd(self.plan, self.gaussians(params), poses, pose_only, g, d_xi, _stream(self.device))
 
+    def set_timing(self, enable):
+        """Per-launch-group HIP-event timing inside the library (eager launches only)."""
+        lib.gsr_plan_set_timing(self.plan, enable)
+
+    def read_timing(self):
+        """{group: (total ms, launches)} since timing was switched on."""
+        return lib.gsr_plan_read_timing(self.plan)
+
     def forward_all(self, params, poses, want_blend=False, grow=True):
         """project + bin (+ capacity growth) + render_fwd; returns buffers."""
         self.project(params, poses)

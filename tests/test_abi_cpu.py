@@ -72,3 +72,21 @@ def test_plan_info_and_layout():
         assert e.value.status == lib.ESTATE
     finally:
         lib.gsr_plan_destroy(plan)
+
+
+def test_timing_switch_without_device_work():
+    """Timing can be switched on and read on a fresh plan: no launch was
+    timed, so every group reads zero; an unknown group is an argument error."""
+    from paper_2601_00705_amd import lib
+    plan = lib.gsr_plan_create(100, CAM, _cfg(), 10000)
+    try:
+        lib.gsr_plan_set_timing(plan, True)
+        t = lib.gsr_plan_read_timing(plan)
+        assert set(t) == set(lib.TIMERS) and all(v == (0.0, 0) for v in t.values())
+        ms = ctypes.c_double()
+        cnt = ctypes.c_int64()
+        assert lib.raw().gsr_plan_read_timing(plan, len(lib.TIMERS), ctypes.byref(ms),
+                                              ctypes.byref(cnt)) == lib.EINVAL
+        lib.gsr_plan_set_timing(plan, False)
+    finally:
+        lib.gsr_plan_destroy(plan)

@@ -88,3 +88,41 @@ def test_graph_replays_match_eager():
     assert not torch.equal(replayed[0], eager[0])
     _, ovf = R.pair_count()
     assert not ovf
+
+
+def test_kernel_timing_eager_only():
+    """The library's event timer brackets every launch group of an eager
+    step once, with positive device time, and records nothing while the
+    stream is captured into a graph."""
+    from paper_2601_00705_amd import lib
+    w = scenes.workload(0)
+    cfg = Config()
+    P = {k: torch.from_numpy(v).cuda() for k, v in w["params"].items()}
+    poses = torch.from_numpy(w["poses"].astype(np.float32)).cuda()
+    print("[timing] setup", flush=True)
+    R = Renderer(P["opacity_logit"].shape[0], w["cams"], cfg)
+    rgb0, _, _, _ = R.forward_all(P, poses)
+    target = (rgb0 * 0.5).contiguous()
+    Pt = R.total_pixels
+    bufs = (torch.empty(3 * Pt, device="cuda"), torch.empty(Pt, device="cuda"),
+            torch.empty(Pt, dtype=torch.int32, device="cuda"), torch.empty(3 * Pt, device="cuda"),
+            {k: torch.empty_like(v) for k, v in P.items()}, torch.empty(1, 6, device="cuda"))
+    R.set_timing(True)
+    _step(R, P, poses, target, bufs)
+    t = R.read_timing()
+    assert set(t) == set(lib.TIMERS)
+    for name, (ms, cnt) in t.items():
+        assert cnt == 1 and ms > 0.0, name
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            _step(R, P, poses, target, bufs)
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    t2 = R.read_timing()
+    assert all(t2[k][1] == 1 for k in t2), t2
+    R.set_timing(False)
+    assert all(v == (0.0, 0) for v in R.read_timing().values())
