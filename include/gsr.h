@@ -106,6 +106,8 @@ typedef struct {
     size_t conic_o;   /* float4 [V*n]: (A, B, C, o), A = (Sigma_I^-1)_00 ... */
     size_t rgb_d;     /* float4 [V*n]: (r, g, b, depth) */
     size_t qthr;      /* float [V*n]: binning level of d^T conic d per slot */
+    size_t stage;     /* 64-byte records [V*n]: double u, v, A, B, C; float o, r, g, b
+                         (unrounded centre and conic the compositing stages from) */
     size_t grad2d;    /* double [9][V*n]: d(u, v, A, B, C, o, r, g, b) */
     size_t keys;      /* uint64 [capacity]: sorted (tile << 32 | depth bits) */
     size_t vals;      /* uint32 [capacity]: sorted slot = view * n + index */
@@ -142,7 +144,8 @@ gsr_status gsr_plan_layout(const gsr_plan *plan, gsr_layout *out);
 gsr_status gsr_plan_get_info(const gsr_plan *plan, gsr_plan_info *out);
 
 /* Eq. (proj): projects every Gaussian into every view (poses: device
- * [n_views][12]).  Writes the geom / conic_o / rgb_d / qthr records. */
+ * [n_views][12]), in double precision.  Writes the float geom / conic_o /
+ * rgb_d / qthr records (correctly rounded) and the staging records. */
 gsr_status gsr_project(gsr_plan *plan, const gsr_gaussians *g, const float *poses, void *stream);
 
 /* Builds the depth-ordered per-tile lists from the geom / conic_o / qthr /

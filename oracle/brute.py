@@ -3,7 +3,7 @@
 A second forward written independently of ``gsr_oracle.c`` and used to pin
 it on tiny inputs: no tiles and no rectangles; for every pixel every live
 Gaussian is evaluated, the ones whose alpha clears alpha_min are ordered by
-(camera depth, index) and composited with Eq. (alpha).  The rotation of a
+(camera depth rounded to float32, index) and composited with Eq. (alpha).  The rotation of a
 Gaussian is built by rotating the basis vectors with the Hamilton product
 q v q*, not from the closed-form matrix the C code uses.
 
@@ -79,7 +79,8 @@ def render(params, cam, pose, cfg):
         rgb += np.asarray(cfg.bg, dtype=np.float64)[:, None, None]
         return rgb, T_out, nb
     u, v, inv, opac, depth = map(np.asarray, (u, v, inv, opac, depth))
-    order = np.lexsort((live, depth))  # by depth, then index
+    # by the float32-rounded depth (the precision of the ordering key), then index
+    order = np.lexsort((live, depth.astype(np.float32)))
     for py in range(H):
         for px in range(W):
             d = np.stack([px + 0.5 - u, py + 0.5 - v], axis=1)

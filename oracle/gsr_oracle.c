@@ -27,7 +27,8 @@
  * centre in world frame.
  *
  * Forward: per tile, the Gaussians whose conservative bounding rectangle covers
- * the tile, sorted by (depth, index); per pixel the plain compositing sum.
+ * the tile, sorted by (float32-rounded depth, index); per pixel the plain
+ * compositing sum.
  * Backward: per pixel, the blended list is stored and the colour "behind" each
  * entry and the transmittance product after it are built by suffix recursion
  * (no division by 1-alpha), then the chain rule is written out scalar by scalar.
@@ -294,10 +295,14 @@ typedef struct {
 
 static const proj_t *g_sort_proj; /* comparator context (single-threaded) */
 
+/* Front-to-back order of a tile list (Eq. (alpha): N(p) sorted near to far).
+ * The order is an integer decision; it is taken on the float32 key the
+ * renderer's records carry (FP32 throughout): the camera depth rounded once
+ * to float32, ties broken by Gaussian index. */
 static int cmp_depth_id(const void *a, const void *b)
 {
     int64_t ia = *(const int64_t *)a, ib = *(const int64_t *)b;
-    double da = g_sort_proj[ia].mc[2], db = g_sort_proj[ib].mc[2];
+    float da = (float)g_sort_proj[ia].mc[2], db = (float)g_sort_proj[ib].mc[2];
     if (da < db) return -1;
     if (da > db) return 1;
     return ia < ib ? -1 : (ia > ib ? 1 : 0);

@@ -44,6 +44,7 @@ struct gsr_plan {
     int32_t total_tiles = 0, tile_bits = 0, passes = 0, chunks = 0;
     int32_t sort_max_blocks = 0, sort_grid = 0, bwd_blocks = 0;
     size_t off_counters = 0, off_views = 0, off_geom = 0, off_conic = 0, off_rgbd = 0, off_qthr = 0, off_grad2d = 0;
+    size_t off_stage = 0;
     size_t off_keys0 = 0, off_keys1 = 0, off_vals0 = 0, off_vals1 = 0, off_ranges = 0, off_hist = 0;
     size_t off_dtotal = 0, off_bsums = 0, off_boffs = 0, off_xip = 0, off_order = 0, off_buckets = 0, total = 0;
     char* ws = nullptr;
@@ -221,6 +222,7 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->off_conic = take(sizeof(float4) * S);
     p->off_rgbd = take(sizeof(float4) * S);
     p->off_qthr = take(sizeof(float) * S);
+    p->off_stage = take(sizeof(StageRec) * S);
     p->off_grad2d = take(sizeof(double) * GSR_G2 * S);
     p->off_keys0 = take(sizeof(unsigned long long) * pair_capacity);
     p->off_keys1 = take(sizeof(unsigned long long) * pair_capacity);
@@ -284,6 +286,7 @@ extern "C" gsr_status gsr_plan_layout(const gsr_plan* plan, gsr_layout* out)
     out->conic_o = plan->off_conic;
     out->rgb_d = plan->off_rgbd;
     out->qthr = plan->off_qthr;
+    out->stage = plan->off_stage;
     out->grad2d = plan->off_grad2d;
     out->keys = final_buffer(plan) ? plan->off_keys1 : plan->off_keys0;
     out->vals = final_buffer(plan) ? plan->off_vals1 : plan->off_vals0;
@@ -349,6 +352,7 @@ extern "C" gsr_status gsr_project(gsr_plan* plan, const gsr_gaussians* g, const 
     a.conic_o = at<float4>(plan, plan->off_conic);
     a.rgb_d = at<float4>(plan, plan->off_rgbd);
     a.qthr = at<float>(plan, plan->off_qthr);
+    a.stage = at<StageRec>(plan, plan->off_stage);
     Timed t(plan, GSR_T_PROJECT, (hipStream_t)stream);
     hipError_t e = launch_project(a, plan->cfg.sh_degree, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_project");
@@ -423,8 +427,7 @@ static RasterArgs raster_args(const gsr_plan* plan)
     a.order = at<uint32_t>(plan, plan->off_order);
     a.vals = at<uint32_t>(plan, final_buffer(plan) ? plan->off_vals1 : plan->off_vals0);
     a.geom = at<float4>(plan, plan->off_geom);
-    a.conic_o = at<float4>(plan, plan->off_conic);
-    a.rgb_d = at<float4>(plan, plan->off_rgbd);
+    a.stage = at<StageRec>(plan, plan->off_stage);
     a.grad2d = at<double>(plan, plan->off_grad2d);
     a.slots = plan->n * plan->V;
     return a;

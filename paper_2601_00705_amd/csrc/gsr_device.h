@@ -51,6 +51,17 @@ struct Counters {
     uint32_t pad[10];
 };
 
+// Per live slot, the record the compositing kernels stage from: the projected
+// centre and conic in double (each tile expands the quadratic form around its
+// own centre, so that a Gaussian far from the pixels it reaches keeps its
+// accuracy) and the opacity and colour.
+struct __align__(16) StageRec {
+    double u, v, A, B, C;
+    float o, r, g, b;
+    float pad[2];
+};
+static_assert(sizeof(StageRec) == 64, "StageRec is 64 bytes");
+
 // ---------------------------------------------------------------------------
 // binning contract: tile rectangle of a projected record.
 // Returns false when the slot touches no tile.  Tile sizes are powers of two,

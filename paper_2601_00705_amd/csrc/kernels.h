@@ -12,6 +12,7 @@ struct ProjectArgs {
     DevCfg cfg;
     float4 *geom, *conic_o, *rgb_d;
     float* qthr;
+    StageRec* stage;
 };
 
 struct BinArgs {
@@ -59,7 +60,8 @@ struct RasterArgs {
     const uint2* ranges;
     const uint32_t* order;     // processing order of the tiles
     const uint32_t* vals;
-    const float4 *geom, *conic_o, *rgb_d;
+    const float4* geom;        // liveness of a slot (rx >= 0)
+    const StageRec* stage;     // per-slot staging records
     float* rgb;                // [sum 3 H W]
     float* T_final;            // [sum H W]
     int32_t* n_contrib;        // [sum H W]

@@ -3,8 +3,9 @@
 // Eq. (proj) with the appendix's parameterisation (see project_math.h).  The
 // Gaussian's parameters are read once (coalesced SoA planes) and kept in
 // registers for every view of the batch; the per-view pose is read from
-// device memory so that a captured graph sees pose updates.  For every slot
-// (view, Gaussian) the kernel writes geom/conic_o/rgb_d; a culled slot gets
+// device memory so that a captured graph sees pose updates.  For every live
+// slot (view, Gaussian) the kernel writes geom/conic_o/rgb_d/qthr (float) and
+// the staging record (double centre and conic); a culled slot gets
 // rx = ry = -1.
 #include "kernels.h"
 #include "project_math.h"
@@ -17,8 +18,11 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= a.n) return;
     const int64_t n = a.n;
-    Activated<float> g;
-    activate<float>(a.mean, a.quat, a.log_scale, a.opacity_logit, n, i, g);
+    // the geometry is computed in double (the chip's FP64 vector rate equals
+    // its FP32 rate and this kernel is bound by memory), so that every float
+    // record below is the correctly rounded value of the exact projection
+    Activated<double> g;
+    activate<double>(a.mean, a.quat, a.log_scale, a.opacity_logit, n, i, g);
     constexpr int K = DEG < 0 ? 1 : (DEG + 1) * (DEG + 1);
     float col[K][3];
     if (DEG < 0) {
@@ -31,15 +35,16 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
     }
     const ViewTable* vt = a.views;
     const float inv_tw = 1.0f / (float)a.cfg.tile_w, inv_th = 1.0f / (float)a.cfg.tile_h;
+    const float o = (float)g.o;
     for (int v = 0; v < vt->n; ++v) {
         const ViewInfo vw = vt->v[v];
         const float* pose = a.poses + 12 * v;
-        Projected<float> p;
-        project_gaussian<float>(g, pose, vw, a.cfg, p);
+        Projected<double> p;
+        project_gaussian<double>(g, pose, vw, a.cfg, p);
         int64_t slot = (int64_t)v * n + i;
+        const float u = (float)p.u, vv = (float)p.v, rx = (float)p.rx, ry = (float)p.ry;
         int x0, y0, x1, y1;
-        bool live = p.valid && tile_rect(p.u, p.v, p.rx, p.ry, inv_tw, inv_th, vw.tiles_x, vw.tiles_y,
-                                         x0, y0, x1, y1);
+        bool live = p.valid && tile_rect(u, vv, rx, ry, inv_tw, inv_th, vw.tiles_x, vw.tiles_y, x0, y0, x1, y1);
         if (!live) {
             a.geom[slot] = make_float4(0.0f, 0.0f, -1.0f, -1.0f);
             continue;
@@ -50,12 +55,12 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
             rgb[1] = col[0][1];
             rgb[2] = col[0][2];
         } else {
-            float oc[3];
-            camera_centre<float>(pose, oc);
-            float dx = g.mw[0] - oc[0], dy = g.mw[1] - oc[1], dz = g.mw[2] - oc[2];
-            float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+            double oc[3];
+            camera_centre<double>(pose, oc);
+            double dx = g.mw[0] - oc[0], dy = g.mw[1] - oc[1], dz = g.mw[2] - oc[2];
+            double inv = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
             float Y[16];
-            sh_eval<DEG < 0 ? 0 : DEG, float>(dx * inv, dy * inv, dz * inv, Y);
+            sh_eval<DEG < 0 ? 0 : DEG, float>((float)(dx * inv), (float)(dy * inv), (float)(dz * inv), Y);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
                 float acc = 0.0f;
@@ -64,13 +69,25 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
                 rgb[c] = acc;
             }
         }
-        a.geom[slot] = make_float4(p.u, p.v, p.rx, p.ry);
-        a.conic_o[slot] = make_float4(p.A, p.B, p.C, g.o);
-        a.rgb_d[slot] = make_float4(rgb[0], rgb[1], rgb[2], p.mc[2]);
+        a.geom[slot] = make_float4(u, vv, rx, ry);
+        a.conic_o[slot] = make_float4((float)p.A, (float)p.B, (float)p.C, o);
+        a.rgb_d[slot] = make_float4(rgb[0], rgb[1], rgb[2], (float)p.mc[2]);
+        StageRec sr;
+        sr.u = p.u;
+        sr.v = p.v;
+        sr.A = p.A;
+        sr.B = p.B;
+        sr.C = p.C;
+        sr.o = o;
+        sr.r = rgb[0];
+        sr.g = rgb[1];
+        sr.b = rgb[2];
+        sr.pad[0] = sr.pad[1] = 0.0f;
+        a.stage[slot] = sr;
         // binning level of d^T conic d: the alpha_min ellipse 2 ln(o / alpha_min)
         // widened by 5% + 0.01 so that rounding never drops a tile the
         // compositing would reach
-        a.qthr[slot] = a.cfg.alpha_min > 0.0f ? 1.05f * (2.0f * logf(g.o / a.cfg.alpha_min)) + 0.01f : INFINITY;
+        a.qthr[slot] = a.cfg.alpha_min > 0.0f ? 1.05f * (2.0f * logf(o / a.cfg.alpha_min)) + 0.01f : INFINITY;
     }
 }
 

@@ -158,9 +158,16 @@ __device__ __forceinline__ void project_gaussian(const Activated<T>& g, const fl
     for (int k = 0; k < 9; ++k) R[k] = (T)pose[k];
     for (int k = 0; k < 3; ++k) t[k] = (T)pose[9 + k];
     p.valid = false;
-    p.mc[0] = R[0] * g.mw[0] + R[1] * g.mw[1] + R[2] * g.mw[2] + t[0];
-    p.mc[1] = R[3] * g.mw[0] + R[4] * g.mw[1] + R[5] * g.mw[2] + t[1];
-    p.mc[2] = R[6] * g.mw[0] + R[7] * g.mw[1] + R[8] * g.mw[2] + t[2];
+    // Camera-space mean from double products (a float32 product is exact in
+    // double), rounded once: R mu + t cancels when the camera is close to the
+    // Gaussian, and the rounded depth is the key that orders the tile lists.
+    for (int r = 0; r < 3; ++r) {
+        double acc = (double)pose[9 + r];
+        acc = fma((double)pose[3 * r], (double)g.mw[0], acc);
+        acc = fma((double)pose[3 * r + 1], (double)g.mw[1], acc);
+        acc = fma((double)pose[3 * r + 2], (double)g.mw[2], acc);
+        p.mc[r] = (T)acc;
+    }
     T x = p.mc[0], y = p.mc[1], z = p.mc[2];
     if (!g.ok || !(z > (T)cfg.z_near) || !(z < (T)INFINITY)) return;
     const T fx = (T)vw.fx, fy = (T)vw.fy;

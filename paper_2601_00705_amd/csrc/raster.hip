@@ -3,11 +3,12 @@
 // One wavefront (64 lanes) per (view, tile); each lane owns PPT = tile
 // pixels / 64 pixels of one column of the tile (rows l / tile_w + k * 64 /
 // tile_w).  The tile's depth-sorted pair range is walked in batches of
-// BATCH (64, 128 or 256) records: every lane stages BATCH / 64 records into LDS, precomputed in
-// exp2 form (power2 = a dx^2 + b dx dy + c dy^2 with the conic scaled by
-// -log2(e)/2, -log2(e), -log2(e)/2, and the alpha_min test as
-// power2 < log2(alpha_min / o)); then the lane walks the batch for each of its
-// pixels, sharing the per-entry terms of its column.
+// BATCH (64, 128 or 256) records: every lane stages BATCH / 64 records into
+// LDS in exp2 form, the quadratic form expanded around the tile centre in
+// double (power2 = c0 + g . d + a2 dx^2 + b2 dx dy + c2 dy^2 for the offset d
+// of a pixel from the tile centre, the conic scaled by -log2(e)/2, and the
+// alpha_min test as power2 < log2(alpha_min / o)); then the lane walks the
+// batch for each of its pixels, sharing the per-entry terms of its column.
 //
 // Forward: alpha = min(alpha_max, o 2^power2); entries below alpha_min are
 // skipped; compositing stops before an entry that would take T below T_min;
@@ -32,27 +33,54 @@ namespace gsr {
 #define GSR_LN2 0.69314718055994531f
 
 struct __align__(16) LdsRec {
-    float4 p0;  // u, v, a2, b2      (a2 = -0.5 log2e A, b2 = -log2e B)
-    float4 p1;  // c2, o, thr, -     (c2 = -0.5 log2e C, thr = log2(alpha_min / o))
+    float4 p0;  // c0, gx, gy, a2   (power2 at the tile centre and its gradient; a2 = k A)
+    float4 p1;  // b2, c2, o, thr   (b2 = 2 k B, c2 = k C, thr = log2(alpha_min / o))
     float4 p2;  // r, g, b, slot bits
+    float4 p3;  // ox, oy, -, -     (tile centre - projected centre)
 };
 
-__device__ __forceinline__ void stage_record(const RasterArgs& a, uint32_t slot, LdsRec& r)
+// Stages the record of `slot` for the tile centred at (xc, yc).  With
+// k = -log2(e) / 2 and o = (xc, yc) - (u, v), the exp2-space power at a pixel
+// offset d from the tile centre is
+//   power2(d) = k (o + d)^T conic (o + d)
+//             = c0 + gx dx + gy dy + a2 dx^2 + b2 dx dy + c2 dy^2,
+// c0 = k o^T conic o, (gx, gy) = 2 k conic o, formed here in double: the
+// quadratic form of a Gaussian whose centre lies far from the tile cancels
+// heavily, and |d| is at most half a tile.
+__device__ __forceinline__ void stage_record(const RasterArgs& a, uint32_t slot, double xc, double yc,
+                                             LdsRec& r)
 {
-    float4 gm = a.geom[slot];
-    float4 co = a.conic_o[slot];
-    float4 cd = a.rgb_d[slot];
-    float thr = a.cfg.alpha_min > 0.0f ? log2f(a.cfg.alpha_min / co.w) : -INFINITY;
-    r.p0 = make_float4(gm.x, gm.y, -0.5f * GSR_LOG2E * co.x, -GSR_LOG2E * co.y);
-    r.p1 = make_float4(-0.5f * GSR_LOG2E * co.z, co.w, thr, 0.0f);
-    r.p2 = make_float4(cd.x, cd.y, cd.z, __uint_as_float(slot));
+    const StageRec sr = a.stage[slot];
+    const double k = -0.5 * 1.4426950408889634;
+    const double ox = xc - sr.u, oy = yc - sr.v;
+    const double qx = sr.A * ox + sr.B * oy, qy = sr.B * ox + sr.C * oy;
+    const float thr = a.cfg.alpha_min > 0.0f ? log2f(a.cfg.alpha_min / sr.o) : -INFINITY;
+    r.p0 = make_float4((float)(k * (ox * qx + oy * qy)), (float)(2.0 * k * qx), (float)(2.0 * k * qy),
+                       (float)(k * sr.A));
+    r.p1 = make_float4((float)(2.0 * k * sr.B), (float)(k * sr.C), sr.o, thr);
+    r.p2 = make_float4(sr.r, sr.g, sr.b, __uint_as_float(slot));
+    r.p3 = make_float4((float)ox, (float)oy, 0.0f, 0.0f);
 }
 
-// power2 = a2 dx^2 + dy (b2 dx + c2 dy), the same operation sequence in both
-// passes so that their decisions agree bit for bit
-__device__ __forceinline__ float power2(float a2dx2, float b2dx, float c2, float dy)
+// The terms of power2 shared by the pixels of one lane (same column offset
+// dx), and power2 at row offset dy; the same operation sequence in both
+// passes, so that their decisions agree bit for bit.
+struct ColTerms {
+    float s0;  // c0 + gx dx + a2 dx^2
+    float s1;  // gy + b2 dx
+};
+
+__device__ __forceinline__ ColTerms col_terms(const LdsRec& r, float dx)
 {
-    return __builtin_fmaf(dy, __builtin_fmaf(c2, dy, b2dx), a2dx2);
+    ColTerms t;
+    t.s0 = __builtin_fmaf(__builtin_fmaf(r.p0.w, dx, r.p0.y), dx, r.p0.x);
+    t.s1 = __builtin_fmaf(r.p1.x, dx, r.p0.z);
+    return t;
+}
+
+__device__ __forceinline__ float power2(const ColTerms& t, float c2, float dy)
+{
+    return __builtin_fmaf(__builtin_fmaf(c2, dy, t.s1), dy, t.s0);
 }
 
 template <int PPT>
@@ -63,6 +91,9 @@ struct TileCtx {
     int64_t pix[PPT];         // index into the concatenated [H][W] planes
     int64_t rgb0[PPT];        // channel-0 index into the concatenated images
     int64_t plane;            // H * W of the view
+    double xc, yc;            // tile centre in view pixel coordinates
+    float dx;                 // this lane's pixel-centre offset from it (column)
+    float dy[PPT];            // and its rows'
 };
 
 template <int PPT>
@@ -82,10 +113,14 @@ __device__ __forceinline__ TileCtx<PPT> tile_ctx(const RasterArgs& a)
     c.py0 = ty * a.cfg.tile_h + (lane >> l2);
     c.rs = 64 >> l2;
     c.plane = (int64_t)vw.width * vw.height;
+    c.xc = (double)(tx * a.cfg.tile_w) + 0.5 * a.cfg.tile_w;
+    c.yc = (double)(ty * a.cfg.tile_h) + 0.5 * a.cfg.tile_h;
+    c.dx = (float)(lane & (a.cfg.tile_w - 1)) + 0.5f - 0.5f * (float)a.cfg.tile_w;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int py = c.py0 + k * c.rs;
         c.inside[k] = c.px < vw.width && py < vw.height;
+        c.dy[k] = (float)((lane >> l2) + k * c.rs) + 0.5f - 0.5f * (float)a.cfg.tile_h;
         c.pix[k] = (int64_t)vw.pix_base + (int64_t)py * vw.width + c.px;
         c.rgb0[k] = 3 * (int64_t)vw.pix_base + (int64_t)py * vw.width + c.px;
     }
@@ -100,9 +135,8 @@ __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
     const int lane = threadIdx.x;
     const bool overflow = a.counters->overflow != 0u;
     const uint2 range = overflow ? make_uint2(0u, 0u) : a.ranges[c.tile];
-    const float fpx = (float)c.px + 0.5f;
     const float amax = a.cfg.alpha_max, tmin = a.cfg.T_min;
-    float T[PPT], C0[PPT], C1[PPT], C2[PPT], fpy[PPT];
+    float T[PPT], C0[PPT], C1[PPT], C2[PPT];
     uint32_t last[PPT], nb[PPT];
     bool done[PPT];
     bool lane_done = true;
@@ -113,29 +147,26 @@ __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
         last[k] = nb[k] = 0u;
         done[k] = !c.inside[k];
         lane_done = lane_done && done[k];
-        fpy[k] = (float)(c.py0 + k * c.rs) + 0.5f;
     }
     for (uint32_t base = range.x; base < range.y; base += GSR_BATCH) {
         if (__all(lane_done)) break;
 #pragma unroll
         for (int r = 0; r < GSR_BATCH / 64; ++r) {
             const uint32_t j = base + lane + 64 * r;
-            if (j < range.y) stage_record(a, a.vals[j], rec[lane + 64 * r]);
+            if (j < range.y) stage_record(a, a.vals[j], c.xc, c.yc, rec[lane + 64 * r]);
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)GSR_BATCH, range.y - base);
         for (int e = 0; e < cnt; ++e) {
             if ((e & 15) == 0 && __all(lane_done)) break;
             const LdsRec r = rec[e];
-            const float dx = fpx - r.p0.x;
-            const float a2dx2 = r.p0.z * dx * dx;
-            const float b2dx = r.p0.w * dx;
+            const ColTerms ct = col_terms(r, c.dx);
             float p2[PPT];
             bool pass[PPT], any = false;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                p2[k] = power2(a2dx2, b2dx, r.p1.x, fpy[k] - r.p0.y);
-                pass[k] = (p2[k] >= r.p1.z) & !done[k];
+                p2[k] = power2(ct, r.p1.y, c.dy[k]);
+                pass[k] = (p2[k] >= r.p1.w) & !done[k];
                 any |= pass[k];
             }
             if (!__any(any)) continue;
@@ -143,7 +174,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
             bool all = true;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                const float alpha = fminf(amax, r.p1.y * __builtin_amdgcn_exp2f(p2[k]));
+                const float alpha = fminf(amax, r.p1.z * __builtin_amdgcn_exp2f(p2[k]));
                 const float Tn = __builtin_fmaf(-T[k], alpha, T[k]);
                 const bool stop = pass[k] & (Tn < tmin);
                 const bool blend = pass[k] & !stop;
@@ -198,11 +229,10 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
     if (a.counters->overflow) return;
     const uint2 range = a.ranges[c.tile];
     const int lane = threadIdx.x;
-    const float fpx = (float)c.px + 0.5f;
     const float amax = a.cfg.alpha_max;
     const int64_t S = a.slots;
 
-    float T[PPT], Tf[PPT], gsk[PPT], g0[PPT], g1[PPT], g2[PPT], fpy[PPT];
+    float T[PPT], Tf[PPT], gsk[PPT], g0[PPT], g1[PPT], g2[PPT];
     uint32_t my_n[PPT];
     uint32_t lane_max = 0;
 #pragma unroll
@@ -222,7 +252,6 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
         T[k] = Tf[k];
         // g . (colour behind) + dL/dT_final T_final, maintained incrementally
         gsk[k] = __builtin_fmaf(gT, Tf[k], Tf[k] * (g0[k] * a.cfg.bg0 + g1[k] * a.cfg.bg1 + g2[k] * a.cfg.bg2));
-        fpy[k] = (float)(c.py0 + k * c.rs) + 0.5f;
         lane_max = max(lane_max, my_n[k]);
     }
     for (int off = 32; off > 0; off >>= 1) lane_max = max(lane_max, (uint32_t)__shfl_xor((int)lane_max, off, 64));
@@ -234,31 +263,33 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
 #pragma unroll
         for (int r = 0; r < GSR_BATCH / 64; ++r) {
             const int t = lane + 64 * r;
-            if (t < cnt) stage_record(a, a.vals[hi_ - 1 - t], rec[t]);
+            if (t < cnt) stage_record(a, a.vals[hi_ - 1 - t], c.xc, c.yc, rec[t]);
         }
         __syncthreads();
         for (int e = 0; e < cnt; ++e) {
             const uint32_t pos = hi_ - 1 - (uint32_t)e - range.x;
             const LdsRec r = rec[e];
-            const float dx = fpx - r.p0.x;
-            const float a2dx2 = r.p0.z * dx * dx;
-            const float b2dx = r.p0.w * dx;
-            float p2[PPT], dy[PPT];
+            const ColTerms ct = col_terms(r, c.dx);
+            float p2[PPT];
             bool on[PPT], any = false;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
-                dy[k] = fpy[k] - r.p0.y;
-                p2[k] = power2(a2dx2, b2dx, r.p1.x, dy[k]);
-                on[k] = (pos < my_n[k]) & (p2[k] >= r.p1.z);
+                p2[k] = power2(ct, r.p1.y, c.dy[k]);
+                on[k] = (pos < my_n[k]) & (p2[k] >= r.p1.w);
                 any |= on[k];
             }
             if (!__any(any)) continue;
             float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             float v8 = 0.0f;
+            // power2 partials: d/du = -(2 a2 dx + b2 dy + gx), d/dv = -(b2 dx + 2 c2 dy + gy)
+            // (d = pixel - tile centre); d/d(A, B, C) = k (fx^2, 2 fx fy, fy^2) with
+            // (fx, fy) = pixel - projected centre = d + o
+            const float tu = __builtin_fmaf(2.0f * r.p0.w, c.dx, r.p0.y);
+            const float fx = c.dx + r.p3.x;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const float G = __builtin_amdgcn_exp2f(p2[k]);
-                const float a_raw = r.p1.y * G;
+                const float a_raw = r.p1.z * G;
                 const bool clamped = !(a_raw < amax);
                 const float alpha = clamped ? amax : a_raw;
                 const float rcp = __builtin_amdgcn_rcpf(1.0f - alpha);
@@ -273,13 +304,13 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
                 T[k] = on[k] ? Tb : T[k];
                 const bool live = on[k] & !clamped;
                 const float dd = live ? dalpha * alpha : 0.0f;
-                const float ddx = dd * dx;
-                // d power2 / du = -(2 a2 dx + b2 dy), / dv = -(b2 dx + 2 c2 dy)
-                v[0] = __builtin_fmaf(dd, __builtin_fmaf(2.0f * r.p0.z, dx, r.p0.w * dy[k]), v[0]);
-                v[1] = __builtin_fmaf(dd, __builtin_fmaf(2.0f * r.p1.x, dy[k], b2dx), v[1]);
-                v[2] = __builtin_fmaf(ddx, dx, v[2]);
-                v[3] = __builtin_fmaf(ddx, dy[k], v[3]);
-                v[4] = __builtin_fmaf(dd * dy[k], dy[k], v[4]);
+                const float fy = c.dy[k] + r.p3.y;
+                const float ddx = dd * fx;
+                v[0] = __builtin_fmaf(dd, __builtin_fmaf(r.p1.x, c.dy[k], tu), v[0]);
+                v[1] = __builtin_fmaf(dd, __builtin_fmaf(2.0f * r.p1.y, c.dy[k], ct.s1), v[1]);
+                v[2] = __builtin_fmaf(ddx, fx, v[2]);
+                v[3] = __builtin_fmaf(ddx, fy, v[3]);
+                v[4] = __builtin_fmaf(dd * fy, fy, v[4]);
                 v[5] = __builtin_fmaf(live ? dalpha : 0.0f, G, v[5]);
             }
             const float s8 = wave_sum8_transposed(v);

@@ -48,7 +48,8 @@ class Grads(ctypes.Structure):
 
 class Layout(ctypes.Structure):
     _fields_ = [(k, ctypes.c_size_t) for k in
-                ("counters", "geom", "conic_o", "rgb_d", "qthr", "grad2d", "keys", "vals", "ranges", "total")]
+                ("counters", "geom", "conic_o", "rgb_d", "qthr", "stage", "grad2d", "keys", "vals", "ranges",
+                 "total")]
 
 
 class PlanInfo(ctypes.Structure):

@@ -402,7 +402,20 @@ def seeded_keyframes(seed, n_target, n_views=5, width=1200, height=680, f=600.0,
 
 def workload(index, seed=None):
     """Returns dict(params, cams, poses, targets or target_poses, pose_only,
-    sh_degree, name).  Sizes follow the five benchmark configurations."""
+    sh_degree, name).  Sizes follow the five benchmark configurations.
+    Parameters and poses are float32 (the renderer's input precision), so
+    that every consumer sees the same inputs."""
+    return _pose_f32(_workload(index, seed))
+
+
+def _pose_f32(w):
+    for k in ("poses", "target_poses"):
+        if k in w:
+            w[k] = np.ascontiguousarray(w[k], dtype=np.float32)
+    return w
+
+
+def _workload(index, seed=None):
     if index == 0:
         s = 1000 if seed is None else seed
         params, cam = cloud(s, 2000, 64, 48, 50.0)

@@ -27,6 +27,7 @@ def say(msg):
 
 
 def _gpu_fwd(params, cams, poses, cfg, capacity=None, want_blend=True):
+    poses = np.asarray(poses, dtype=np.float32)
     R = Renderer(params["opacity_logit"].shape[0], cams, cfg, pair_capacity=capacity)
     P = to_dev(params)
     poses_d = torch.from_numpy(np.ascontiguousarray(poses, dtype=np.float32)).cuda()
@@ -40,6 +41,7 @@ def _check_forward(name, params, cams, poses, cfg, capacity=None):
     thresholds; elsewhere a pixel may differ only if the oracle records a
     near-threshold decision for it, and such pixels stay rare."""
     say(f"[fwd] {name}: n={params['opacity_logit'].shape[0]} views={len(cams)}")
+    poses = np.asarray(poses, dtype=np.float32)  # the oracle sees the poses the GPU sees
     R, P, poses_d, rgb, T, nc, nb = _gpu_fwd(params, cams, poses, cfg, capacity)
     ref = oracle.render(params, cams, poses, oracle_cfg(cfg))
     ok = pixel_mask(ref["margin"], cams)
@@ -279,9 +281,40 @@ def test_forward_deterministic_and_batched_equals_plain():
         assert torch.equal(tparts[v].reshape(-1), T_v), v
 
 
+def test_forward_identical_across_batches_and_tiles():
+    """Binning is conservative and every pixel composites the same
+    depth-ordered entries whatever the tile shape or the LDS batch.  For one
+    tile shape, rgb, T_final and blend counts are bitwise identical over the
+    LDS batches.  Across tile shapes only the rounding of the tile-centred
+    expansion differs: images agree within 1e-5 where the blend counts agree,
+    and those differ on at most 1e-4 of the pixels (640x480 room view, 100k
+    Gaussians)."""
+    from paper_2601_00705_amd import autotune
+    w = scenes.workload(1)
+    base = None
+    per_tile = {}
+    for tw, th, batch in [(16, 16, 64), (16, 16, 128), (16, 16, 256)] + list(autotune.CANDIDATES):
+        say(f"[tiles] {tw}x{th}/{batch}")
+        _, _, _, rgb, T, _, nb = _gpu_fwd(w["params"], w["cams"], w["poses"],
+                                          Config(tile_w=tw, tile_h=th, batch=batch))
+        if (tw, th) in per_tile:
+            r0, T0, n0 = per_tile[(tw, th)]
+            assert torch.equal(rgb, r0) and torch.equal(T, T0) and torch.equal(nb, n0), (tw, th, batch)
+        else:
+            per_tile[(tw, th)] = (rgb.clone(), T.clone(), nb.clone())
+        if base is None:
+            base = (rgb.clone(), T.clone(), nb.clone())
+            continue
+        same = (nb == base[2])
+        assert float((~same).float().mean()) <= 1e-4, (tw, th)
+        d = (rgb - base[0]).abs().view(3, -1).max(dim=0).values
+        assert float(d[same].max()) <= 1e-5 and float((T - base[1]).abs()[same].max()) <= 1e-5, (tw, th)
+
+
 # --------------------------------------------------------------------------
 def _check_backward(name, params, cams, poses, cfg, seed, pose_only=None, with_dT=False, frac_max=0.0):
     say(f"[bwd] {name}")
+    poses = np.asarray(poses, dtype=np.float32)  # the oracle sees the poses the GPU sees
     R, P, poses_d, rgb, T, nc, nb = _gpu_fwd(params, cams, poses, cfg)
     Ptot = sum(c["width"] * c["height"] for c in cams)
     dL = scenes.upstream_grad(seed, 3 * Ptot)
@@ -315,6 +348,7 @@ def _check_backward(name, params, cams, poses, cfg, seed, pose_only=None, with_d
 
 
 def _min_margin(params, cams, poses, cfg):
+    poses = np.asarray(poses, dtype=np.float32)
     return float(np.min(oracle.render(params, cams, poses, oracle_cfg(cfg))["margin"]))
 
 
@@ -378,7 +412,7 @@ def test_autograd_function_matches_oracle():
     wT = torch.from_numpy(scenes.upstream_grad(2, T.numel())).cuda()
     loss = (rgb * w).sum() + (T * wT).sum()
     loss.backward()
-    ref = oracle.backward(params, [cam], pose[None], oracle_cfg(cfg), w.cpu().double().numpy(),
+    ref = oracle.backward(params, [cam], pose[None].astype(np.float32), oracle_cfg(cfg), w.cpu().double().numpy(),
                           wT.cpu().double().numpy())
     for k in ("mean", "quat", "log_scale", "opacity_logit", "colour"):
         frac, ratio = grad_violations(P[k].grad.cpu().numpy(), ref[k])

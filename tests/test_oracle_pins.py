@@ -168,6 +168,26 @@ def test_equal_depth_ties_broken_by_index():
             np.testing.assert_allclose(rgb[c], c0[c] * a0 + c1[c] * a1 * (1 - a0), atol=1e-13)
 
 
+def test_depths_equal_in_float32_keep_index_order():
+    """The order of N(p) is decided on the float32 depth key: two depths that
+    differ in double but round to the same float32 composite in index order,
+    in the tiled oracle and in the brute force alike."""
+    z = 2.5
+    assert np.float32(z) == np.float32(z + 1e-8) and z + 1e-8 > z
+    g0 = _one((0, 0, z + 1e-8), log_scale=(math.log(0.1),) * 3, logit=0.5, colour=(1, 0, 0))
+    g1 = _one((0, 0, z), log_scale=(math.log(0.15),) * 3, logit=1.5, colour=(0, 1, 0))
+    py, px = np.mgrid[0:30, 0:40] + 0.5
+    a0 = _iso_alpha(g0, 0, CAM, px, py)
+    a1 = _iso_alpha(g1, 0, CAM, px, py)
+    p = _cat(g0, g1)
+    out = oracle.render(p, [CAM], I12, CFG)
+    rgb = oracle.split_views(out["rgb"], [CAM], 3)[0]
+    rgb_b, _, _ = brute.render(p, CAM, I12[0], CFG)
+    np.testing.assert_allclose(rgb[0], a0, atol=1e-12)
+    np.testing.assert_allclose(rgb[1], a1 * (1 - a0), atol=1e-12)
+    np.testing.assert_allclose(rgb_b, rgb, atol=1e-12)
+
+
 # ---------------------------------------------------------------- P4 ----
 def _small_scene(seed, n=12, sh_degree=-1, w=24, h=20):
     p, cam = scenes.cloud(seed, n, w, h, 30.0, sh_degree=sh_degree)
