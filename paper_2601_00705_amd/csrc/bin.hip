@@ -1,20 +1,29 @@
-// bin.hip -- pair emission for the depth-ordered sets N(p) of Eq. (alpha).
+// bin.hip -- the depth-ordered sets N(p) of Eq. (alpha), grouped by tile.
 //
 // For every live slot the conservative tile rectangle (tile_rect) gives the
 // candidate tiles; a candidate is kept when the slot's ellipse reaches the
-// tile's pixel-centre box (tile_hit).  Each kept tile yields one
-// (key, value) pair: key = (global tile << 32) | float bits of the camera
-// depth (positive floats order like their bit patterns), value = slot.
-// Emission is in slot order, rectangle tiles row by row, so that a stable
-// sort breaks depth ties by slot, i.e. by Gaussian index.
+// tile's pixel-centre box (tile_hit).  Each kept (tile, slot) pair goes into
+// the tile's segment of the pair array as one 64-bit key
+//   (float bits of the camera depth << 32) | Gaussian index,
+// which orders a segment by depth and breaks ties by index (positive floats
+// order like their bit patterns).  The tile is the most significant part of
+// the order, so it is resolved by counting instead of sorting:
 //
-//   k_bin_count : per chunk of BIN_CHUNK Gaussians of one view, the number of
-//                 kept tiles (the chunk's rectangles are expanded
-//                 cooperatively: one candidate per thread and step, owner
-//                 found by binary search over the rectangle-area prefix)
-//   k_bin_scan  : exclusive scan of the chunk counts, total, capacity check
-//   k_bin_emit  : the same expansion; kept candidates are compacted in order
-//                 (wave ballots + a block prefix) so that stores are coalesced
+//   k_bin_count   per chunk of one view (chunk_mult * GSR_BIN_CHUNK Gaussians):
+//                 pairs per tile of the view, one row of the view's
+//                 [chunk][tile] count matrix (LDS histogram; views with more
+//                 than GSR_BIN_LDS_TILES tiles add straight into the row)
+//   k_bin_colscan per tile: exclusive prefix of its column (the chunk's offset
+//                 inside the tile's segment) and the tile's total
+//   k_bin_tiles   exclusive scan of the tile totals: the tile ranges, the pair
+//                 count and the capacity flag
+//   k_bin_emit    the chunk's pairs, each at its tile's cursor (LDS atomics:
+//                 the order inside a chunk's group is arbitrary, and the
+//                 per-tile sort of the unique keys makes it exact)
+//
+// Candidates of a staged group of Gaussians are expanded cooperatively: one
+// candidate per thread and step, its owner found by binary search over the
+// rectangle-area prefix.
 #include "kernels.h"
 
 namespace gsr {
@@ -28,18 +37,22 @@ struct ChunkLds {
     uint32_t wsum[4];
 };
 
-// Loads the chunk's slots (thread t owns chunk items 4t .. 4t+3, which keeps
-// slot order), their rectangles and ellipse data, and scans the areas.
-// Returns the chunk's total rectangle area.
+// Stages Gaussians base .. base + GSR_BIN_CHUNK - 1 of view v (thread t owns
+// items IPT t .. IPT t + IPT - 1, which keeps index order): rectangles,
+// ellipse data and the scan of the rectangle areas.  Returns the total area.
+// Starts and ends with a block barrier.
+constexpr int IPT = GSR_BIN_CHUNK / 256;
+
 __device__ uint32_t load_chunk(const BinArgs& a, const ViewInfo& vw, int v, int64_t base, bool want_depth,
                                ChunkLds& L)
 {
     const float inv_tw = 1.0f / (float)a.cfg.tile_w, inv_th = 1.0f / (float)a.cfg.tile_h;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    uint32_t area[4], tsum = 0;
+    __syncthreads();
+    uint32_t area[IPT], tsum = 0;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int li = tid * 4 + k;
+    for (int k = 0; k < IPT; ++k) {
+        const int li = tid * IPT + k;
         const int64_t i = base + li;
         area[k] = 0;
         int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
@@ -74,8 +87,8 @@ __device__ uint32_t load_chunk(const BinArgs& a, const ViewInfo& vw, int v, int6
     for (int k = 0; k < w; ++k) wofs += L.wsum[k];
     uint32_t run = wofs + incl - tsum;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        L.excl[tid * 4 + k] = run;
+    for (int k = 0; k < IPT; ++k) {
+        L.excl[tid * IPT + k] = run;
         run += area[k];
     }
     const uint32_t total = L.wsum[0] + L.wsum[1] + L.wsum[2] + L.wsum[3];
@@ -84,7 +97,7 @@ __device__ uint32_t load_chunk(const BinArgs& a, const ViewInfo& vw, int v, int6
     return total;
 }
 
-// candidate j of the chunk: owner slot (largest s with excl[s] <= j) and tile
+// candidate j of the staged group: owner (largest s with excl[s] <= j) and tile
 __device__ __forceinline__ bool candidate(const ChunkLds& L, uint32_t j, const BinArgs& a, int& s, int& tx,
                                           int& ty)
 {
@@ -101,36 +114,91 @@ __device__ __forceinline__ bool candidate(const ChunkLds& L, uint32_t j, const B
     return tile_hit(L.u[lo], L.v[lo], L.A[lo], L.B[lo], L.C[lo], L.q[lo], tx, ty, a.cfg.tile_w, a.cfg.tile_h);
 }
 
-__global__ __launch_bounds__(256) void k_bin_count(BinArgs a)
+// row of the count matrix of (view, chunk)
+__device__ __forceinline__ uint32_t* count_row(const BinArgs& a, const ViewInfo& vw, int chunk)
 {
-    __shared__ ChunkLds L;
-    __shared__ uint32_t red[4];
-    const int v = blockIdx.y;
-    const ViewInfo vw = a.views->v[v];
-    const int64_t base = (int64_t)blockIdx.x * GSR_BIN_CHUNK;
-    const uint32_t total = load_chunk(a, vw, v, base, false, L);
-    uint32_t c = 0;
-    for (uint32_t j = threadIdx.x; j < total; j += 256) {
-        int s, tx, ty;
-        c += candidate(L, j, a, s, tx, ty) ? 1u : 0u;
-    }
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
-    __syncthreads();
-    if (threadIdx.x == 0) a.block_sums[v * a.chunks + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+    const int64_t tiles_v = (int64_t)vw.tiles_x * vw.tiles_y;
+    return a.cnt + (int64_t)a.chunks * vw.tile_base + (int64_t)chunk * tiles_v;
 }
 
-__global__ __launch_bounds__(1024) void k_bin_scan(BinArgs a)
+template <bool LDS_HIST>
+__global__ __launch_bounds__(256) void k_bin_count(BinArgs a)
+{
+    HIP_DYNAMIC_SHARED(uint32_t, hist)  // [tiles of the view] when LDS_HIST
+    __shared__ ChunkLds L;
+    const int v = blockIdx.y;
+    const ViewInfo vw = a.views->v[v];
+    const int tiles_v = vw.tiles_x * vw.tiles_y;
+    uint32_t* row = count_row(a, vw, blockIdx.x);
+    if (LDS_HIST)
+        for (int t = threadIdx.x; t < tiles_v; t += 256) hist[t] = 0u;
+    for (int sub = 0; sub < a.chunk_mult; ++sub) {
+        const int64_t base = ((int64_t)blockIdx.x * a.chunk_mult + sub) * GSR_BIN_CHUNK;
+        if (base >= a.n) break;
+        const uint32_t total = load_chunk(a, vw, v, base, false, L);
+        for (uint32_t j = threadIdx.x; j < total; j += 256) {
+            int s, tx, ty;
+            if (candidate(L, j, a, s, tx, ty)) {
+                const int tt = ty * vw.tiles_x + tx;
+                if (LDS_HIST) atomicAdd(&hist[tt], 1u);
+                else atomicAdd(&row[tt], 1u);
+            }
+        }
+    }
+    if (LDS_HIST) {
+        __syncthreads();
+        for (int t = threadIdx.x; t < tiles_v; t += 256) row[t] = hist[t];
+    }
+}
+
+__global__ void k_zero_u32(uint32_t* p, int64_t count)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0u;
+}
+
+// thread per global tile: the column of the tile in its view's count matrix
+// becomes the exclusive prefix over chunks; the total goes to ranges[].y
+__global__ __launch_bounds__(256) void k_bin_colscan(BinArgs a)
+{
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.total_tiles) return;
+    const int v = view_of_tile(a.views, g);
+    const ViewInfo& vw = a.views->v[v];
+    const int64_t tiles_v = (int64_t)vw.tiles_x * vw.tiles_y;
+    uint32_t* col = a.cnt + (int64_t)a.chunks * vw.tile_base + (g - vw.tile_base);
+    uint32_t run = 0;
+    int c = 0;
+    for (; c + 8 <= a.chunks; c += 8) {
+        uint32_t x[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) x[k] = col[(int64_t)(c + k) * tiles_v];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            col[(int64_t)(c + k) * tiles_v] = run;
+            run += x[k];
+        }
+    }
+    for (; c < a.chunks; ++c) {
+        const uint32_t x = col[(int64_t)c * tiles_v];
+        col[(int64_t)c * tiles_v] = run;
+        run += x;
+    }
+    a.ranges[g] = make_uint2(0u, run);
+}
+
+// one block: exclusive scan of the tile totals into the ranges; pair count
+// and capacity flag
+__global__ __launch_bounds__(1024) void k_bin_tiles(BinArgs a)
 {
     __shared__ unsigned long long part[1024];
-    const int nb = a.n_views * a.chunks;
-    const int per = (nb + 1023) / 1024;
+    const int nt = a.total_tiles;
+    const int per = (nt + 1023) / 1024;
     const int lo = threadIdx.x * per;
     unsigned long long s = 0;
-    for (int k = 0; k < per && lo + k < nb; ++k) s += a.block_sums[lo + k];
+    for (int k = 0; k < per && lo + k < nt; ++k) s += a.ranges[lo + k].y;
     part[threadIdx.x] = s;
     __syncthreads();
-    // inclusive Hillis-Steele scan of the 1024 partial sums
     for (int off = 1; off < 1024; off <<= 1) {
         unsigned long long x = threadIdx.x >= off ? part[threadIdx.x - off] : 0ull;
         __syncthreads();
@@ -138,55 +206,66 @@ __global__ __launch_bounds__(1024) void k_bin_scan(BinArgs a)
         __syncthreads();
     }
     unsigned long long run = threadIdx.x ? part[threadIdx.x - 1] : 0ull;
-    for (int k = 0; k < per && lo + k < nb; ++k) {
-        a.block_offs[lo + k] = run;
-        run += a.block_sums[lo + k];
+    const unsigned long long total = part[1023];
+    const bool over = total > a.counters->capacity;
+    for (int k = 0; k < per && lo + k < nt; ++k) {
+        const uint32_t c = a.ranges[lo + k].y;
+        // empty tiles get [0, 0); on overflow every range is empty, so that
+        // no kernel reads past the capacity
+        a.ranges[lo + k] = (over || c == 0u) ? make_uint2(0u, 0u) : make_uint2((uint32_t)run, (uint32_t)(run + c));
+        run += c;
     }
     if (threadIdx.x == 1023) {
-        unsigned long long total = part[1023];
         a.counters->pairs = total;
-        a.counters->overflow = total > a.counters->capacity ? 1u : 0u;
+        a.counters->overflow = over ? 1u : 0u;
     }
 }
 
+template <bool LDS_HIST>
 __global__ __launch_bounds__(256) void k_bin_emit(BinArgs a)
 {
+    HIP_DYNAMIC_SHARED(uint32_t, cursor)  // [tiles of the view] when LDS_HIST
     __shared__ ChunkLds L;
-    __shared__ uint32_t wcount[4];
     if (a.counters->overflow) return;
     const int v = blockIdx.y;
     const ViewInfo vw = a.views->v[v];
-    const int64_t base = (int64_t)blockIdx.x * GSR_BIN_CHUNK;
-    const uint32_t total = load_chunk(a, vw, v, base, true, L);
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const unsigned long long lt = (1ull << lane) - 1ull;
-    unsigned long long out = a.block_offs[v * a.chunks + blockIdx.x];
-    for (uint32_t j0 = 0; j0 < total; j0 += 256) {
-        const uint32_t j = j0 + tid;
-        int s = 0, tx = 0, ty = 0;
-        const bool hit = j < total && candidate(L, j, a, s, tx, ty);
-        const unsigned long long m = __ballot(hit);
-        if (lane == 0) wcount[w] = (uint32_t)__popcll(m);
-        __syncthreads();
-        uint32_t before = 0;
-        for (int k = 0; k < w; ++k) before += wcount[k];
-        if (hit) {
-            const unsigned long long pos = out + before + (uint32_t)__popcll(m & lt);
-            const unsigned long long tile = (unsigned long long)(vw.tile_base + ty * vw.tiles_x + tx);
-            a.keys[pos] = (tile << 32) | L.dbits[s];
-            a.vals[pos] = (uint32_t)((int64_t)v * a.n + base + s);
+    const int tiles_v = vw.tiles_x * vw.tiles_y;
+    uint32_t* row = count_row(a, vw, blockIdx.x);
+    const uint2* rng = a.ranges + vw.tile_base;
+    if (LDS_HIST)
+        for (int t = threadIdx.x; t < tiles_v; t += 256) cursor[t] = rng[t].x + row[t];
+    for (int sub = 0; sub < a.chunk_mult; ++sub) {
+        const int64_t base = ((int64_t)blockIdx.x * a.chunk_mult + sub) * GSR_BIN_CHUNK;
+        if (base >= a.n) break;
+        const uint32_t total = load_chunk(a, vw, v, base, true, L);
+        for (uint32_t j = threadIdx.x; j < total; j += 256) {
+            int s, tx, ty;
+            if (candidate(L, j, a, s, tx, ty)) {
+                const int tt = ty * vw.tiles_x + tx;
+                const uint32_t pos = LDS_HIST ? atomicAdd(&cursor[tt], 1u) : rng[tt].x + atomicAdd(&row[tt], 1u);
+                a.seg[pos] = ((unsigned long long)L.dbits[s] << 32) | (unsigned long long)(base + s);
+            }
         }
-        out += wcount[0] + wcount[1] + wcount[2] + wcount[3];
-        __syncthreads();
     }
 }
 
-hipError_t launch_bin(const BinArgs& a, hipStream_t s)
+hipError_t launch_bin(const BinArgs& a, int max_tiles_view, hipStream_t s)
 {
+    if (a.total_tiles == 0) return hipSuccess;
     dim3 grid((unsigned)a.chunks, (unsigned)a.n_views);
-    hipLaunchKernelGGL(k_bin_count, grid, dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, a);
-    hipLaunchKernelGGL(k_bin_emit, grid, dim3(256), 0, s, a);
+    const bool lds = max_tiles_view <= GSR_BIN_LDS_TILES;
+    const size_t dyn = lds ? sizeof(uint32_t) * (size_t)max_tiles_view : 0;
+    if (lds) {
+        hipLaunchKernelGGL(k_bin_count<true>, grid, dim3(256), dyn, s, a);
+    } else {
+        const int64_t entries = (int64_t)a.chunks * a.total_tiles;
+        hipLaunchKernelGGL(k_zero_u32, dim3(2048), dim3(256), 0, s, a.cnt, entries);
+        hipLaunchKernelGGL(k_bin_count<false>, grid, dim3(256), 0, s, a);
+    }
+    hipLaunchKernelGGL(k_bin_colscan, dim3((unsigned)((a.total_tiles + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_bin_tiles, dim3(1), dim3(1024), 0, s, a);
+    if (lds) hipLaunchKernelGGL(k_bin_emit<true>, grid, dim3(256), dyn, s, a);
+    else hipLaunchKernelGGL(k_bin_emit<false>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

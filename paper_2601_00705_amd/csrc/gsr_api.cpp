@@ -6,6 +6,7 @@
 // device-side counts, so a call sequence can be captured into a HIP graph.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -41,12 +42,12 @@ struct gsr_plan {
     ViewTable vt{};
     int64_t capacity = 0;
     int64_t total_pixels = 0;
-    int32_t total_tiles = 0, tile_bits = 0, passes = 0, chunks = 0;
-    int32_t sort_max_blocks = 0, sort_grid = 0, bwd_blocks = 0;
+    int32_t total_tiles = 0, tile_bits = 0, passes = 0, chunks = 0, chunk_mult = 1, max_tiles_view = 0;
+    int32_t bwd_blocks = 0;
     size_t off_counters = 0, off_views = 0, off_geom = 0, off_conic = 0, off_rgbd = 0, off_qthr = 0, off_grad2d = 0;
     size_t off_stage = 0;
-    size_t off_keys0 = 0, off_keys1 = 0, off_vals0 = 0, off_vals1 = 0, off_ranges = 0, off_hist = 0;
-    size_t off_dtotal = 0, off_bsums = 0, off_boffs = 0, off_xip = 0, off_order = 0, off_buckets = 0, total = 0;
+    size_t off_keys = 0, off_vals = 0, off_seg = 0, off_ranges = 0, off_cnt = 0;
+    size_t off_xip = 0, off_order = 0, off_buckets = 0, total = 0;
     char* ws = nullptr;
     Counters host_counters{};
     std::vector<uint32_t> identity_order;
@@ -200,12 +201,20 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->total_tiles = (int32_t)tiles;
     p->total_pixels = pix;
     p->tile_bits = tiles > 1 ? ilog2((int)tiles) : 0;
-    p->passes = (32 + p->tile_bits + 7) / 8;
-    p->chunks = (int32_t)((n + GSR_BIN_CHUNK - 1) / GSR_BIN_CHUNK);
-    if (p->chunks == 0) p->chunks = 1;
-    p->sort_max_blocks = (int32_t)((pair_capacity + GSR_SORT_ITEMS - 1) / GSR_SORT_ITEMS);
-    if (p->sort_max_blocks == 0) p->sort_max_blocks = 1;
-    p->sort_grid = p->sort_max_blocks < 2048 ? p->sort_max_blocks : 2048;
+    // per-tile sort of (depth bits << 32 | index): at most 4 depth digits plus
+    // the digits of the Gaussian index
+    p->passes = 4 + (n > 1 ? (ilog2((int)std::min<int64_t>(n, 1ll << 30)) + 7) / 8 : 0);
+    for (int v = 0; v < n_views; ++v)
+        p->max_tiles_view = std::max(p->max_tiles_view, p->vt.v[v].tiles_x * p->vt.v[v].tiles_y);
+    // binning chunks of GSR_BIN_CHUNK * chunk_mult Gaussians: larger chunks
+    // while at least 2048 (chunk, view) blocks remain, so the count matrix
+    // stays small
+    auto chunks_for = [&](int m) {
+        return (int64_t)((n + (int64_t)GSR_BIN_CHUNK * m - 1) / ((int64_t)GSR_BIN_CHUNK * m));
+    };
+    p->chunk_mult = 1;
+    while (p->chunk_mult < 32 && chunks_for(2 * p->chunk_mult) * n_views >= 2048) p->chunk_mult *= 2;
+    p->chunks = (int32_t)std::max<int64_t>(1, chunks_for(p->chunk_mult));
     p->bwd_blocks = (int32_t)((n + 255) / 256);
     if (p->bwd_blocks == 0) p->bwd_blocks = 1;
 
@@ -224,17 +233,13 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->off_qthr = take(sizeof(float) * S);
     p->off_stage = take(sizeof(StageRec) * S);
     p->off_grad2d = take(sizeof(double) * GSR_G2 * S);
-    p->off_keys0 = take(sizeof(unsigned long long) * pair_capacity);
-    p->off_keys1 = take(sizeof(unsigned long long) * pair_capacity);
-    p->off_vals0 = take(sizeof(uint32_t) * pair_capacity);
-    p->off_vals1 = take(sizeof(uint32_t) * pair_capacity);
+    p->off_keys = take(sizeof(unsigned long long) * pair_capacity);
+    p->off_vals = take(sizeof(uint32_t) * pair_capacity);
+    p->off_seg = take(sizeof(unsigned long long) * pair_capacity);
     p->off_ranges = take(sizeof(uint2) * tiles);
     p->off_order = take(sizeof(uint32_t) * tiles);
     p->off_buckets = take(sizeof(uint32_t) * 64);
-    p->off_hist = take(sizeof(uint32_t) * 256 * (size_t)p->sort_max_blocks);
-    p->off_dtotal = take(sizeof(uint32_t) * 256);
-    p->off_bsums = take(sizeof(uint32_t) * (size_t)n_views * p->chunks);
-    p->off_boffs = take(sizeof(unsigned long long) * (size_t)n_views * p->chunks);
+    p->off_cnt = take(sizeof(uint32_t) * (size_t)p->chunks * (size_t)tiles);
     p->off_xip = take(sizeof(double) * 6 * (size_t)n_views * p->bwd_blocks);
     p->total = o;
     p->host_counters = Counters{};
@@ -276,7 +281,6 @@ extern "C" gsr_status gsr_plan_bind(gsr_plan* plan, void* workspace, size_t byte
     return GSR_OK;
 }
 
-static int final_buffer(const gsr_plan* p) { return p->passes & 1; }
 
 extern "C" gsr_status gsr_plan_layout(const gsr_plan* plan, gsr_layout* out)
 {
@@ -288,8 +292,8 @@ extern "C" gsr_status gsr_plan_layout(const gsr_plan* plan, gsr_layout* out)
     out->qthr = plan->off_qthr;
     out->stage = plan->off_stage;
     out->grad2d = plan->off_grad2d;
-    out->keys = final_buffer(plan) ? plan->off_keys1 : plan->off_keys0;
-    out->vals = final_buffer(plan) ? plan->off_vals1 : plan->off_vals0;
+    out->keys = plan->off_keys;
+    out->vals = plan->off_vals;
     out->ranges = plan->off_ranges;
     out->total = plan->total;
     return GSR_OK;
@@ -373,48 +377,44 @@ extern "C" gsr_status gsr_bin(gsr_plan* plan, void* stream)
     b.rgb_d = at<float4>(plan, plan->off_rgbd);
     b.conic_o = at<float4>(plan, plan->off_conic);
     b.qthr = at<float>(plan, plan->off_qthr);
-    b.block_sums = at<uint32_t>(plan, plan->off_bsums);
-    b.block_offs = at<unsigned long long>(plan, plan->off_boffs);
     b.chunks = plan->chunks;
+    b.chunk_mult = plan->chunk_mult;
+    b.total_tiles = plan->total_tiles;
+    b.cnt = at<uint32_t>(plan, plan->off_cnt);
     b.counters = at<Counters>(plan, plan->off_counters);
-    b.keys = at<unsigned long long>(plan, plan->off_keys0);
-    b.vals = at<uint32_t>(plan, plan->off_vals0);
-    hipError_t e;
-    {
-        Timed t(plan, GSR_T_BIN_EMIT, s);
-        e = launch_bin(b, s);
-    }
-    if (e != hipSuccess) return hip_fail(e, "gsr_bin: emit");
-    {
-        Timed t(plan, GSR_T_BIN_SORT, s);
-        for (int pass = 0; pass < plan->passes && e == hipSuccess; ++pass) {
-            SortArgs a{};
-            a.counters = b.counters;
-            bool odd = pass & 1;
-            a.keys_in = at<unsigned long long>(plan, odd ? plan->off_keys1 : plan->off_keys0);
-            a.vals_in = at<uint32_t>(plan, odd ? plan->off_vals1 : plan->off_vals0);
-            a.keys_out = at<unsigned long long>(plan, odd ? plan->off_keys0 : plan->off_keys1);
-            a.vals_out = at<uint32_t>(plan, odd ? plan->off_vals0 : plan->off_vals1);
-            a.hist = at<uint32_t>(plan, plan->off_hist);
-            a.digit_total = at<uint32_t>(plan, plan->off_dtotal);
-            a.max_blocks = plan->sort_max_blocks;
-            a.shift = 8 * pass;
-            e = launch_sort_pass(a, plan->sort_grid, s);
-        }
-    }
-    if (e != hipSuccess) return hip_fail(e, "gsr_bin: sort");
+    b.ranges = at<uint2>(plan, plan->off_ranges);
+    b.seg = at<unsigned long long>(plan, plan->off_seg);
     RangeArgs r{};
     r.counters = b.counters;
-    r.keys = at<unsigned long long>(plan, final_buffer(plan) ? plan->off_keys1 : plan->off_keys0);
-    r.ranges = at<uint2>(plan, plan->off_ranges);
+    r.ranges = b.ranges;
     r.total_tiles = plan->total_tiles;
     r.order = at<uint32_t>(plan, plan->off_order);
     r.buckets = at<uint32_t>(plan, plan->off_buckets);
+    SegArgs g{};
+    g.counters = b.counters;
+    g.views = b.views;
+    g.ranges = b.ranges;
+    g.order = r.order;
+    g.seg = b.seg;
+    g.keys = at<unsigned long long>(plan, plan->off_keys);
+    g.vals = at<uint32_t>(plan, plan->off_vals);
+    g.n = plan->n;
+    hipError_t e;
+    {
+        Timed t(plan, GSR_T_BIN_EMIT, s);
+        e = launch_bin(b, plan->max_tiles_view, s);
+    }
+    if (e != hipSuccess) return hip_fail(e, "gsr_bin: emit");
     {
         Timed t(plan, GSR_T_BIN_RANGES, s);
-        e = launch_ranges(r, plan->sort_grid < 1024 ? plan->sort_grid * 4 : 4096, s);
+        e = launch_order(r, s);
     }
-    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_bin: ranges");
+    if (e != hipSuccess) return hip_fail(e, "gsr_bin: order");
+    {
+        Timed t(plan, GSR_T_BIN_SORT, s);
+        e = launch_seg_sort(g, plan->total_tiles, s);
+    }
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_bin: sort");
 }
 
 static RasterArgs raster_args(const gsr_plan* plan)
@@ -425,7 +425,7 @@ static RasterArgs raster_args(const gsr_plan* plan)
     a.counters = at<Counters>(plan, plan->off_counters);
     a.ranges = at<uint2>(plan, plan->off_ranges);
     a.order = at<uint32_t>(plan, plan->off_order);
-    a.vals = at<uint32_t>(plan, final_buffer(plan) ? plan->off_vals1 : plan->off_vals0);
+    a.vals = at<uint32_t>(plan, plan->off_vals);
     a.geom = at<float4>(plan, plan->off_geom);
     a.stage = at<StageRec>(plan, plan->off_stage);
     a.grad2d = at<double>(plan, plan->off_grad2d);

@@ -24,30 +24,29 @@ struct BinArgs {
     const float4* conic_o;
     const float* qthr;
     const float4* rgb_d;
-    uint32_t* block_sums;      // [n_views * chunks]
-    unsigned long long* block_offs;
-    int32_t chunks;            // chunks of BIN_CHUNK Gaussians per view
+    int32_t chunks;            // chunks of GSR_BIN_CHUNK * chunk_mult Gaussians per view
+    int32_t chunk_mult;
+    int32_t total_tiles;
+    uint32_t* cnt;             // per view: [chunks][tiles of the view] pair counts, then offsets
     Counters* counters;
-    unsigned long long* keys;  // [capacity]
-    uint32_t* vals;
+    uint2* ranges;             // [total_tiles]: [first, last + 1) of each tile's pairs
+    unsigned long long* seg;   // [capacity]: (depth bits << 32 | Gaussian index), grouped by tile
 };
 
-struct SortArgs {
+struct SegArgs {
     const Counters* counters;
-    const unsigned long long* keys_in;
-    const uint32_t* vals_in;
-    unsigned long long* keys_out;
-    uint32_t* vals_out;
-    uint32_t* hist;            // [256][max_blocks]
-    uint32_t* digit_total;     // [256]
-    int32_t max_blocks;
-    int32_t shift;
+    const ViewTable* views;
+    const uint2* ranges;
+    const uint32_t* order;     // tiles by pair count, descending
+    unsigned long long* seg;   // [capacity]: emitted keys, sorted in place per tile (scratch)
+    unsigned long long* keys;  // [capacity]: sorted (tile << 32 | depth bits)
+    uint32_t* vals;            // [capacity]: sorted slots
+    int64_t n;
 };
 
 struct RangeArgs {
     const Counters* counters;
-    const unsigned long long* keys;
-    uint2* ranges;
+    const uint2* ranges;
     int32_t total_tiles;
     uint32_t* order;           // [tiles]: tiles by pair count, descending
     uint32_t* buckets;         // [64]: per log2-bucket counts, then cursors
@@ -97,14 +96,17 @@ struct LossArgs {
     float scale;        // 1 / count
 };
 
-#define GSR_BIN_CHUNK 1024
-#define GSR_SORT_ITEMS 4096
-#define GSR_SORT_THREADS 256
+#define GSR_BIN_CHUNK 512           // Gaussians staged in LDS at a time by the binning blocks (x256)
+#define GSR_BIN_LDS_TILES 16384     // views with more tiles count and place with global atomics
+#define GSR_SEG_THREADS 256
+#define GSR_SEG_ITEMS 4096          // segments up to this size are sorted in LDS
 
 hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t s);
-hipError_t launch_bin(const BinArgs& a, hipStream_t s);
-hipError_t launch_sort_pass(const SortArgs& a, int grid_blocks, hipStream_t s);
-hipError_t launch_ranges(const RangeArgs& a, int grid_blocks, hipStream_t s);
+// pair counting, offsets, emission into per-tile segments; max_tiles_view is
+// the largest tile count of one view
+hipError_t launch_bin(const BinArgs& a, int max_tiles_view, hipStream_t s);
+hipError_t launch_order(const RangeArgs& a, hipStream_t s);
+hipError_t launch_seg_sort(const SegArgs& a, int total_tiles, hipStream_t s);
 hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s);
 hipError_t launch_clear_grad2d(const RasterArgs& a, hipStream_t s);
 hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s);

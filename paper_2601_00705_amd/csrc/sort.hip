@@ -1,15 +1,20 @@
-// sort.hip -- stable LSD radix sort of (key u64, value u32) pairs, 8-bit digits.
+// sort.hip -- per-tile ordering of the emitted pairs, and the tiles' order.
 //
-// One pass = three kernels over virtual blocks of SORT_ITEMS pairs:
-//   k_sort_hist    per-block digit histogram (wave64 match: each distinct
-//                  digit of a 64-key round costs one LDS atomic)
-//   k_sort_scan    one block per digit scans that digit's row of block counts
-//   k_sort_scatter per block: stable local ranking (wave match + per-wave
-//                  running counters), staging in LDS in digit order, then a
-//                  coalesced store at the digit's global offset.
-// Pair count and overflow flag are read from device memory, so the launch
-// configuration depends only on the capacity (graph-capturable).  Items are
-// ranked in index order (wave, round, lane), which makes every pass stable.
+// k_seg_sort   one block per tile (largest segments first): sorts the
+//              segment's unique 64-bit keys (depth bits << 32 | Gaussian
+//              index) ascending with a stable LSD radix sort of 8-bit digits,
+//              skipping every digit that is the same for all keys of the
+//              segment, then writes the final pairs: key (tile << 32 | depth
+//              bits), value slot = view * n + index.  Segments of up to
+//              GSR_SEG_ITEMS keys are sorted in LDS; longer ones by the block
+//              in global memory, GSR_SEG_ITEMS keys at a time, ping-ponging
+//              between the segment and the output key array.
+// k_order_*    processing order of the tiles: descending pair count, bucketed
+//              by floor(log2(count)), for the segment sort and compositing.
+//
+// Ranking inside the block is stable: items are ranked in index order (wave,
+// round, lane) with wave-private digit counters; equal digits inside a round
+// are found with 8 ballots.
 #include "kernels.h"
 
 namespace gsr {
@@ -26,199 +31,244 @@ __device__ __forceinline__ unsigned long long match_digit(uint32_t d, bool valid
     return m;
 }
 
-__device__ __forceinline__ unsigned long long live_pairs(const Counters* c)
-{
-    return c->overflow ? 0ull : c->pairs;
-}
+struct SegLds {
+    unsigned long long sk[GSR_SEG_ITEMS];  // keys in digit order (LDS path)
+    uint32_t wcnt[4][256];                 // per-wave digit counters, then wave offsets
+    uint32_t dstart[256];                  // block-local start of each digit
+    uint32_t run[256];                     // global path: running output offset per digit
+    uint32_t hist[256];
+    uint32_t wsum[4];
+    unsigned long long red[2][4];
+};
 
-__global__ __launch_bounds__(GSR_SORT_THREADS) void k_sort_hist(SortArgs a)
+// Stable ranking of the block's items by digit (key >> shift) & 255.  Item
+// (r, lane) of wave w has index w * R * 64 + r * 64 + lane; on return
+// pos[r] is its position in digit order (digit-major, index order within a
+// digit) and L.dstart[] holds the first position of each digit.
+template <int MAXR>
+__device__ __forceinline__ void rank_items(const unsigned long long* key, int R, int m, int shift, uint32_t* pos,
+                                           SegLds& L)
 {
-    __shared__ uint32_t hist[256];
-    const unsigned long long M = live_pairs(a.counters);
-    const int nvb = (int)((M + GSR_SORT_ITEMS - 1) / GSR_SORT_ITEMS);
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-        hist[tid] = 0;
-        __syncthreads();
-        const unsigned long long base = (unsigned long long)vb * GSR_SORT_ITEMS + w * 1024;
-        for (int r = 0; r < 16; ++r) {
-            unsigned long long idx = base + r * 64 + lane;
-            bool valid = idx < M;
-            uint32_t d = valid ? (uint32_t)(a.keys_in[idx] >> a.shift) & 255u : 0u;
-            unsigned long long m = match_digit(d, valid);
-            unsigned long long lt = (1ull << lane) - 1ull;
-            if (valid && (m & lt) == 0ull) atomicAdd(&hist[d], (uint32_t)__popcll(m));
-        }
-        __syncthreads();
-        a.hist[tid * a.max_blocks + vb] = hist[tid];
-        __syncthreads();
-    }
-}
-
-__global__ __launch_bounds__(256) void k_sort_scan(SortArgs a)
-{
-    __shared__ uint32_t wsum[4];
-    const unsigned long long M = live_pairs(a.counters);
-    const int nvb = (int)((M + GSR_SORT_ITEMS - 1) / GSR_SORT_ITEMS);
-    const int d = blockIdx.x, tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    uint32_t* row = a.hist + (size_t)d * a.max_blocks;
-    uint32_t carry = 0;
-    for (int b0 = 0; b0 < nvb; b0 += 256) {
-        int b = b0 + tid;
-        uint32_t x = b < nvb ? row[b] : 0u;
-        uint32_t incl = x;
-        for (int off = 1; off < 64; off <<= 1) {
-            uint32_t y = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += y;
-        }
-        if (lane == 63) wsum[w] = incl;
-        __syncthreads();
-        uint32_t wofs = 0;
-        for (int k = 0; k < w; ++k) wofs += wsum[k];
-        if (b < nvb) row[b] = carry + wofs + incl - x;
-        carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
-        __syncthreads();
-    }
-    if (tid == 0) a.digit_total[d] = carry;
-}
-
-__global__ __launch_bounds__(GSR_SORT_THREADS) void k_sort_scatter(SortArgs a)
-{
-    __shared__ unsigned long long sk[GSR_SORT_ITEMS];
-    __shared__ uint32_t sv[GSR_SORT_ITEMS];
-    __shared__ uint32_t wcnt[4][256];
-    __shared__ uint32_t dstart[256];
-    __shared__ uint32_t gbase[256];
-    __shared__ uint32_t gdig[256];
-    __shared__ uint32_t wsum[4];
-    const unsigned long long M = live_pairs(a.counters);
-    const int nvb = (int)((M + GSR_SORT_ITEMS - 1) / GSR_SORT_ITEMS);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
-
-    // exclusive scan of the digit totals: global start of each digit
+    for (int k = tid; k < 4 * 256; k += GSR_SEG_THREADS) (&L.wcnt[0][0])[k] = 0u;
+    __syncthreads();
+    uint32_t dig[MAXR];
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) {
+        if (r >= R) break;
+        const int li = w * R * 64 + r * 64 + lane;
+        const bool valid = li < m;
+        const uint32_t d = valid ? (uint32_t)(key[r] >> shift) & 255u : 0u;
+        const unsigned long long mk = match_digit(d, valid);
+        const uint32_t below = (uint32_t)__popcll(mk & lt);
+        const uint32_t start = valid ? L.wcnt[w][d] : 0u;
+        // every lane has read its counter before a leader updates it
+        __builtin_amdgcn_wave_barrier();
+        pos[r] = start + below;
+        dig[r] = valid ? d : 256u;
+        if (valid && below == 0u) L.wcnt[w][d] = start + (uint32_t)__popcll(mk);
+    }
+    __syncthreads();
     {
-        uint32_t x = a.digit_total[tid];
-        uint32_t incl = x;
+        // thread = digit: offsets of the waves inside the digit, block digit starts
+        const uint32_t c0 = L.wcnt[0][tid], c1 = L.wcnt[1][tid], c2 = L.wcnt[2][tid], c3 = L.wcnt[3][tid];
+        const uint32_t tot = c0 + c1 + c2 + c3;
+        uint32_t incl = tot;
         for (int off = 1; off < 64; off <<= 1) {
-            uint32_t y = __shfl_up(incl, off, 64);
+            const uint32_t y = __shfl_up(incl, off, 64);
             if (lane >= off) incl += y;
         }
-        if (lane == 63) wsum[w] = incl;
+        if (lane == 63) L.wsum[w] = incl;
         __syncthreads();
         uint32_t wofs = 0;
-        for (int k = 0; k < w; ++k) wofs += wsum[k];
-        gdig[tid] = wofs + incl - x;
-        __syncthreads();
+        for (int k = 0; k < w; ++k) wofs += L.wsum[k];
+        const uint32_t ds = wofs + incl - tot;
+        L.dstart[tid] = ds;
+        L.wcnt[0][tid] = ds;
+        L.wcnt[1][tid] = ds + c0;
+        L.wcnt[2][tid] = ds + c0 + c1;
+        L.wcnt[3][tid] = ds + c0 + c1 + c2;
     }
-
-    for (int vb = blockIdx.x; vb < nvb; vb += gridDim.x) {
-        const unsigned long long base = (unsigned long long)vb * GSR_SORT_ITEMS;
-        const int cnt = (int)min((unsigned long long)GSR_SORT_ITEMS, M - base);
-        for (int k = tid; k < 4 * 256; k += GSR_SORT_THREADS) (&wcnt[0][0])[k] = 0;
-        __syncthreads();
-        unsigned long long key[16];
-        uint32_t val[16];
-        uint32_t rank[16];
-        uint32_t dig[16];
+    __syncthreads();
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            int li = w * 1024 + r * 64 + lane;
-            bool valid = li < cnt;
-            key[r] = valid ? a.keys_in[base + li] : 0ull;
-            val[r] = valid ? a.vals_in[base + li] : 0u;
-            uint32_t d = (uint32_t)(key[r] >> a.shift) & 255u;
-            dig[r] = valid ? d : 256u;
-            unsigned long long m = match_digit(d, valid);
-            uint32_t below = (uint32_t)__popcll(m & lt);
-            uint32_t start = valid ? wcnt[w][d] : 0u;
-            // every lane of the wave has read its counter before a leader
-            // updates it (lockstep; the barrier keeps the order explicit)
-            __builtin_amdgcn_wave_barrier();
-            rank[r] = start + below;
-            if (valid && below == 0u) wcnt[w][d] = start + (uint32_t)__popcll(m);
-        }
-        __syncthreads();
-        // per digit (thread = digit): wave prefixes and the block's digit starts
-        {
-            uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
-            uint32_t tot = c0 + c1 + c2 + c3;
-            uint32_t incl = tot;
-            for (int off = 1; off < 64; off <<= 1) {
-                uint32_t y = __shfl_up(incl, off, 64);
-                if (lane >= off) incl += y;
-            }
-            if (lane == 63) wsum[w] = incl;
-            __syncthreads();
-            uint32_t wofs = 0;
-            for (int k = 0; k < w; ++k) wofs += wsum[k];
-            uint32_t ds = wofs + incl - tot;
-            dstart[tid] = ds;
-            wcnt[0][tid] = ds;
-            wcnt[1][tid] = ds + c0;
-            wcnt[2][tid] = ds + c0 + c1;
-            wcnt[3][tid] = ds + c0 + c1 + c2;
-            gbase[tid] = gdig[tid] + a.hist[tid * a.max_blocks + vb];
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            if (dig[r] < 256u) {
-                uint32_t pos = wcnt[w][dig[r]] + rank[r];
-                sk[pos] = key[r];
-                sv[pos] = val[r];
-            }
-        }
-        __syncthreads();
-        for (int i = tid; i < cnt; i += GSR_SORT_THREADS) {
-            unsigned long long k = sk[i];
-            uint32_t d = (uint32_t)(k >> a.shift) & 255u;
-            uint32_t out = gbase[d] + (uint32_t)i - dstart[d];
-            a.keys_out[out] = k;
-            a.vals_out[out] = sv[i];
-        }
-        __syncthreads();
+    for (int r = 0; r < MAXR; ++r) {
+        if (r >= R) break;
+        pos[r] = dig[r] < 256u ? L.wcnt[w][dig[r]] + pos[r] : 0xffffffffu;
     }
 }
 
-hipError_t launch_sort_pass(const SortArgs& a, int grid_blocks, hipStream_t s)
+// OR and AND of the block's keys (identity for no key)
+__device__ __forceinline__ void block_or_and(unsigned long long o, unsigned long long a, SegLds& L,
+                                             unsigned long long& bor, unsigned long long& band)
 {
-    hipLaunchKernelGGL(k_sort_hist, dim3(grid_blocks), dim3(GSR_SORT_THREADS), 0, s, a);
-    hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_sort_scatter, dim3(grid_blocks), dim3(GSR_SORT_THREADS), 0, s, a);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int off = 32; off > 0; off >>= 1) {
+        o |= __shfl_xor(o, off, 64);
+        a &= __shfl_xor(a, off, 64);
+    }
+    if (lane == 0) {
+        L.red[0][w] = o;
+        L.red[1][w] = a;
+    }
+    __syncthreads();
+    bor = L.red[0][0] | L.red[0][1] | L.red[0][2] | L.red[0][3];
+    band = L.red[1][0] & L.red[1][1] & L.red[1][2] & L.red[1][3];
+    __syncthreads();
+}
+
+__device__ __forceinline__ void write_pair(const SegArgs& a, uint32_t at, unsigned long long k, unsigned long long tile,
+                                           uint32_t vbase)
+{
+    a.keys[at] = (tile << 32) | (k >> 32);
+    a.vals[at] = vbase + (uint32_t)k;
+}
+
+__global__ __launch_bounds__(GSR_SEG_THREADS) void k_seg_sort(SegArgs a)
+{
+    __shared__ SegLds L;
+    if (a.counters->overflow) return;
+    const uint32_t tile = a.order[blockIdx.x];
+    const uint2 rg = a.ranges[tile];
+    const int m = (int)(rg.y - rg.x);
+    if (m == 0) return;
+    const int v = view_of_tile(a.views, (int)tile);
+    const uint32_t vbase = (uint32_t)((int64_t)v * a.n);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    constexpr int MAXR = GSR_SEG_ITEMS / GSR_SEG_THREADS;
+
+    if (m <= GSR_SEG_ITEMS) {
+        const int R = (m + GSR_SEG_THREADS - 1) / GSR_SEG_THREADS;
+        unsigned long long key[MAXR];
+        uint32_t pos[MAXR];
+        unsigned long long o = 0ull, an = ~0ull;
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r) {
+            if (r >= R) break;
+            const int li = w * R * 64 + r * 64 + lane;
+            key[r] = li < m ? a.seg[rg.x + li] : 0ull;
+            if (li < m) {
+                o |= key[r];
+                an &= key[r];
+            }
+        }
+        unsigned long long bor, band;
+        block_or_and(o, an, L, bor, band);
+        const unsigned long long diff = bor ^ band;
+        for (int d = 0; d < 8; ++d) {
+            if (((diff >> (8 * d)) & 255ull) == 0ull) continue;
+            rank_items<MAXR>(key, R, m, 8 * d, pos, L);
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+                if (r >= R) break;
+                if (pos[r] != 0xffffffffu) L.sk[pos[r]] = key[r];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+                if (r >= R) break;
+                const int li = w * R * 64 + r * 64 + lane;
+                if (li < m) key[r] = L.sk[li];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r) {
+            if (r >= R) break;
+            const int li = w * R * 64 + r * 64 + lane;
+            if (li < m) write_pair(a, rg.x + (uint32_t)li, key[r], tile, vbase);
+        }
+        return;
+    }
+
+    // long segment: LSD passes through global memory
+    unsigned long long* bufA = a.seg + rg.x;
+    unsigned long long* bufB = a.keys + rg.x;  // output keys double as scratch
+    unsigned long long o = 0ull, an = ~0ull;
+    for (int i = tid; i < m; i += GSR_SEG_THREADS) {
+        const unsigned long long k = bufA[i];
+        o |= k;
+        an &= k;
+    }
+    unsigned long long bor, band;
+    block_or_and(o, an, L, bor, band);
+    const unsigned long long diff = bor ^ band;
+    unsigned long long* src = bufA;
+    unsigned long long* dst = bufB;
+    for (int d = 0; d < 8; ++d) {
+        if (((diff >> (8 * d)) & 255ull) == 0ull) continue;
+        const int shift = 8 * d;
+        L.hist[tid] = 0u;
+        __syncthreads();
+        for (int i = tid; i < m; i += GSR_SEG_THREADS) atomicAdd(&L.hist[(uint32_t)(src[i] >> shift) & 255u], 1u);
+        __syncthreads();
+        {
+            const uint32_t x = L.hist[tid];
+            uint32_t incl = x;
+            for (int off = 1; off < 64; off <<= 1) {
+                const uint32_t y = __shfl_up(incl, off, 64);
+                if (lane >= off) incl += y;
+            }
+            if (lane == 63) L.wsum[w] = incl;
+            __syncthreads();
+            uint32_t wofs = 0;
+            for (int k = 0; k < w; ++k) wofs += L.wsum[k];
+            L.run[tid] = wofs + incl - x;
+        }
+        for (int cb = 0; cb < m; cb += GSR_SEG_ITEMS) {
+            const int cm = min(GSR_SEG_ITEMS, m - cb);
+            const int R = (cm + GSR_SEG_THREADS - 1) / GSR_SEG_THREADS;
+            unsigned long long key[MAXR];
+            uint32_t pos[MAXR];
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+                if (r >= R) break;
+                const int li = w * R * 64 + r * 64 + lane;
+                key[r] = li < cm ? src[cb + li] : 0ull;
+            }
+            rank_items<MAXR>(key, R, cm, shift, pos, L);
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+                if (r >= R) break;
+                if (pos[r] != 0xffffffffu) {
+                    const uint32_t dg = (uint32_t)(key[r] >> shift) & 255u;
+                    dst[L.run[dg] + (pos[r] - L.dstart[dg])] = key[r];
+                }
+            }
+            __syncthreads();
+            // advance the running offsets by this chunk's digit counts
+            const uint32_t next = tid < 255 ? L.dstart[tid + 1] : (uint32_t)cm;
+            L.run[tid] += next - L.dstart[tid];
+            __syncthreads();
+        }
+        unsigned long long* t = src;
+        src = dst;
+        dst = t;
+    }
+    // src holds the sorted keys (in place when it is the output array)
+    for (int i = tid; i < m; i += GSR_SEG_THREADS) write_pair(a, rg.x + (uint32_t)i, src[i], tile, vbase);
+}
+
+hipError_t launch_seg_sort(const SegArgs& a, int total_tiles, hipStream_t s)
+{
+    if (total_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_sort, dim3((unsigned)total_tiles), dim3(GSR_SEG_THREADS), 0, s, a);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// tile ranges of the sorted keys
-
-__global__ void k_ranges_zero(RangeArgs a)
-{
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < a.total_tiles) a.ranges[t] = make_uint2(0u, 0u);
-    if (t < 64) a.buckets[t] = 0u;
-}
-
-__global__ void k_ranges(RangeArgs a)
-{
-    const unsigned long long M = live_pairs(a.counters);
-    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < M;
-         i += (unsigned long long)gridDim.x * blockDim.x) {
-        uint32_t t = (uint32_t)(a.keys[i] >> 32);
-        if (i == 0 || (uint32_t)(a.keys[i - 1] >> 32) != t) a.ranges[t].x = (uint32_t)i;
-        if (i == M - 1 || (uint32_t)(a.keys[i + 1] >> 32) != t) a.ranges[t].y = (uint32_t)(i + 1);
-    }
-}
-
-// ---------------------------------------------------------------------------
 // processing order of the tiles: descending pair count, bucketed by
-// floor(log2(count)) (bucket 0 holds the longest lists); the compositing
-// kernels take their tile from this order so that long lists start first
+// floor(log2(count)) (bucket 0 holds the longest lists)
 
 __device__ __forceinline__ uint32_t count_bucket(uint2 r)
 {
     uint32_t c = r.y - r.x;
     return c == 0u ? 31u : (uint32_t)__clz(c);  // 31 - floor(log2 c)
+}
+
+__global__ void k_order_zero(RangeArgs a)
+{
+    if (threadIdx.x < 64) a.buckets[threadIdx.x] = 0u;
 }
 
 __global__ void k_order_count(RangeArgs a)
@@ -232,9 +282,12 @@ __global__ void k_order_count(RangeArgs a)
     if (threadIdx.x < 32 && h[threadIdx.x]) atomicAdd(&a.buckets[threadIdx.x], h[threadIdx.x]);
 }
 
+// places each tile at its bucket's base plus a block-aggregated cursor: one
+// global atomic per (block, bucket)
 __global__ void k_order_place(RangeArgs a)
 {
-    __shared__ uint32_t base[32];
+    __shared__ uint32_t base[32], cnt[32], blk[32];
+    if (threadIdx.x < 32) cnt[threadIdx.x] = 0u;
     if (threadIdx.x == 0) {
         uint32_t run = 0;
         for (int b = 0; b < 32; ++b) {
@@ -243,18 +296,23 @@ __global__ void k_order_place(RangeArgs a)
         }
     }
     __syncthreads();
-    int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t b = 0, local = 0;
     if (t < a.total_tiles) {
-        uint32_t b = count_bucket(a.ranges[t]);
-        a.order[base[b] + atomicAdd(&a.buckets[32 + b], 1u)] = (uint32_t)t;
+        b = count_bucket(a.ranges[t]);
+        local = atomicAdd(&cnt[b], 1u);
     }
+    __syncthreads();
+    if (threadIdx.x < 32) blk[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&a.buckets[32 + threadIdx.x], cnt[threadIdx.x]) : 0u;
+    __syncthreads();
+    if (t < a.total_tiles) a.order[base[b] + blk[b] + local] = (uint32_t)t;
 }
 
-hipError_t launch_ranges(const RangeArgs& a, int grid_blocks, hipStream_t s)
+hipError_t launch_order(const RangeArgs& a, hipStream_t s)
 {
+    if (a.total_tiles == 0) return hipSuccess;
     const int tb = (a.total_tiles + 255) / 256;
-    hipLaunchKernelGGL(k_ranges_zero, dim3(tb > 0 ? tb : 1), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_ranges, dim3(grid_blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_order_zero, dim3(1), dim3(64), 0, s, a);
     hipLaunchKernelGGL(k_order_count, dim3(tb), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_order_place, dim3(tb), dim3(256), 0, s, a);
     return hipGetLastError();

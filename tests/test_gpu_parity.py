@@ -157,6 +157,62 @@ def test_bin_bitexact_many_pairs():
     np.testing.assert_array_equal(ranges.cpu().numpy().view(np.uint32), or_)
 
 
+def _disc_records(rng, S, w, h, scale):
+    u = rng.uniform(-5, w + 5, S).astype(np.float32)
+    v = rng.uniform(-5, h + 5, S).astype(np.float32)
+    s = rng.uniform(0.5, 6.0, S) * scale
+    A = (1 / s ** 2).astype(np.float32)
+    q = np.full(S, 9.0, np.float32)
+    rx = (3 * s).astype(np.float32)
+    d = rng.uniform(0.5, 3.0, S).astype(np.float32)
+    d[::7] = np.float32(1.5)  # many equal depths
+    return [u, v, rx, rx.copy(), A, np.zeros(S, np.float32), A.copy(), q, d]
+
+
+def test_bin_bitexact_long_segments():
+    """Tiles whose lists exceed what one block sorts in LDS (9,000 and
+    20,000 pairs in one tile, one seventh of them at one depth)."""
+    for n in (9000, 20000):
+        cams = [{"width": 16, "height": 16, "fx": 1, "fy": 1, "cx": 0, "cy": 0}]
+        rng = np.random.default_rng(n)
+        recs = _disc_records(rng, n, 16, 16, 1.0)
+        recs[0][:] = 8.0
+        recs[1][:] = 8.0
+        say(f"[bin] long segment {n}")
+        R = Renderer(n, cams, Config(), pair_capacity=n + 16)
+        M, ovf = _fill_and_bin(R, recs)
+        assert not ovf and M == n
+        keys, vals, ranges = R.sorted_pairs(M)
+        ok_, ov_, or_ = oracle.bin_f32(cams, n, *recs, 16, 16)
+        np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint64), ok_)
+        np.testing.assert_array_equal(vals.cpu().numpy().view(np.uint32), ov_)
+        np.testing.assert_array_equal(ranges.cpu().numpy().view(np.uint32), or_)
+
+
+def test_bin_bitexact_view_with_many_tiles():
+    """A view with more tiles than the LDS histogram holds (1100x1000 with
+    8x8 tiles, 17,250 tiles) next to a small one: counting and placement
+    through global atomics."""
+    cams = [{"width": 48, "height": 32, "fx": 1, "fy": 1, "cx": 0, "cy": 0},
+            {"width": 1100, "height": 1000, "fx": 1, "fy": 1, "cx": 0, "cy": 0}]
+    n = 3000
+    rng = np.random.default_rng(21)
+    a = _disc_records(rng, n, 48, 32, 1.0)
+    b = _disc_records(rng, n, 1100, 1000, 8.0)
+    recs = [np.concatenate([x, y]) for x, y in zip(a, b)]
+    say("[bin] many tiles")
+    R = Renderer(n, cams, Config(tile_w=8, tile_h=8), pair_capacity=3_000_000)
+    M, ovf = _fill_and_bin(R, recs)
+    assert not ovf
+    keys, vals, ranges = R.sorted_pairs(M)
+    ok_, ov_, or_ = oracle.bin_f32(cams, n, *recs, 8, 8)
+    say(f"  pairs={M}")
+    assert M == len(ok_) and R.info.total_tiles == 6 * 4 + 138 * 125
+    np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint64), ok_)
+    np.testing.assert_array_equal(vals.cpu().numpy().view(np.uint32), ov_)
+    np.testing.assert_array_equal(ranges.cpu().numpy().view(np.uint32), or_)
+
+
 def test_capacity_overflow_reports_and_recovers():
     """A binning that exceeds the pair capacity sets the device flag, the
     forward writes NaN, gsr_pair_count reports the required count, and a
