@@ -108,7 +108,7 @@ typedef struct {
     size_t qthr;      /* float [V*n]: binning level of d^T conic d per slot */
     size_t stage;     /* 64-byte records [V*n]: double u, v, A, B, C; float o, r, g, b
                          (unrounded centre and conic the compositing stages from) */
-    size_t grad2d;    /* double [9][V*n]: d(u, v, A, B, C, o, r, g, b) */
+    size_t grad2d;    /* double [V*n][9]: d(u, v, A, B, C, o, r, g, b) per slot */
     size_t keys;      /* uint64 [capacity]: sorted (tile << 32 | depth bits) */
     size_t vals;      /* uint32 [capacity]: sorted slot = view * n + index */
     size_t ranges;    /* uint32 [tiles][2]: [first, last + 1) per global tile */
@@ -145,7 +145,8 @@ gsr_status gsr_plan_get_info(const gsr_plan *plan, gsr_plan_info *out);
 
 /* Eq. (proj): projects every Gaussian into every view (poses: device
  * [n_views][12]), in double precision.  Writes the float geom / conic_o /
- * rgb_d / qthr records (correctly rounded) and the staging records. */
+ * rgb_d / qthr records (correctly rounded) and the staging records, and zeroes
+ * the screen-space gradient accumulators of the live slots. */
 gsr_status gsr_project(gsr_plan *plan, const gsr_gaussians *g, const float *poses, void *stream);
 
 /* Builds the depth-ordered per-tile lists from the geom / conic_o / qthr /

@@ -357,6 +357,8 @@ extern "C" gsr_status gsr_project(gsr_plan* plan, const gsr_gaussians* g, const 
     a.rgb_d = at<float4>(plan, plan->off_rgbd);
     a.qthr = at<float>(plan, plan->off_qthr);
     a.stage = at<StageRec>(plan, plan->off_stage);
+    a.grad2d = at<double>(plan, plan->off_grad2d);
+    a.counters = at<Counters>(plan, plan->off_counters);
     Timed t(plan, GSR_T_PROJECT, (hipStream_t)stream);
     hipError_t e = launch_project(a, plan->cfg.sh_degree, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_project");

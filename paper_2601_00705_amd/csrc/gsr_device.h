@@ -46,7 +46,8 @@ struct DevCfg {
 struct Counters {
     unsigned long long pairs;   // required pair count of the last binning
     uint32_t overflow;          // 1 when pairs > capacity
-    uint32_t pad0;
+    uint32_t grad_dirty;        // 1 once a backward has added to the accumulators
+                                // since the last projection zeroed them
     unsigned long long capacity;
     uint32_t pad[10];
 };

@@ -13,6 +13,8 @@ struct ProjectArgs {
     float4 *geom, *conic_o, *rgb_d;
     float* qthr;
     StageRec* stage;
+    double* grad2d;            // [slots][9], zeroed for live slots
+    Counters* counters;
 };
 
 struct BinArgs {
@@ -55,7 +57,7 @@ struct RangeArgs {
 struct RasterArgs {
     const ViewTable* views;
     DevCfg cfg;
-    const Counters* counters;
+    Counters* counters;         // overflow flag (read), accumulator flag (written)
     const uint2* ranges;
     const uint32_t* order;     // processing order of the tiles
     const uint32_t* vals;
@@ -70,7 +72,7 @@ struct RasterArgs {
     const int32_t* n_contrib_in;
     const float* dL_drgb;
     const float* dL_dT;        // nullable
-    double* grad2d;            // [9][slots]
+    double* grad2d;            // [slots][9]
     int64_t slots;
 };
 

@@ -4,9 +4,9 @@
 // Gaussian's parameters are read once (coalesced SoA planes) and kept in
 // registers for every view of the batch; the per-view pose is read from
 // device memory so that a captured graph sees pose updates.  For every live
-// slot (view, Gaussian) the kernel writes geom/conic_o/rgb_d/qthr (float) and
-// the staging record (double centre and conic); a culled slot gets
-// rx = ry = -1.
+// slot (view, Gaussian) the kernel writes geom/conic_o/rgb_d/qthr (float),
+// the staging record (double centre and conic) and zeroes the slot's
+// screen-space gradient accumulators; a culled slot gets rx = ry = -1.
 #include "kernels.h"
 #include "project_math.h"
 
@@ -16,6 +16,9 @@ template <int DEG>
 __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // the accumulators of the live slots are zeroed below: the next backward
+    // needs no clearing pass
+    if (i == 0) a.counters->grad_dirty = 0u;
     if (i >= a.n) return;
     const int64_t n = a.n;
     // the geometry is computed in double (the chip's FP64 vector rate equals
@@ -84,6 +87,8 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
         sr.b = rgb[2];
         sr.pad[0] = sr.pad[1] = 0.0f;
         a.stage[slot] = sr;
+#pragma unroll
+        for (int f = 0; f < GSR_G2; ++f) a.grad2d[GSR_G2 * slot + f] = 0.0;
         // binning level of d^T conic d: the alpha_min ellipse 2 ln(o / alpha_min)
         // widened by 5% + 0.01 so that rounding never drops a tile the
         // compositing would reach

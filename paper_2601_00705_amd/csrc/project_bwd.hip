@@ -84,10 +84,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
             live = p.valid;
         }
         if (live) {
-            T gu = a.grad2d[0 * S + slot], gv = a.grad2d[1 * S + slot];
-            T gA = a.grad2d[2 * S + slot], gB = a.grad2d[3 * S + slot], gC = a.grad2d[4 * S + slot];
-            T go = a.grad2d[5 * S + slot];
-            T gc[3] = {a.grad2d[6 * S + slot], a.grad2d[7 * S + slot], a.grad2d[8 * S + slot]};
+            const double* g2 = a.grad2d + GSR_G2 * slot;
+            T gu = g2[0], gv = g2[1];
+            T gA = g2[2], gB = g2[3], gC = g2[4];
+            T go = g2[5];
+            T gc[3] = {g2[6], g2[7], g2[8]};
             // conic -> Sigma_I entries (a, b, c): dSigma = -Sigma^-1 dConic Sigma^-1
             const T A = p.A, B = p.B, C = p.C;
             T da = -(A * A * gA + A * B * gB + B * B * gC);

@@ -226,11 +226,13 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
 {
     __shared__ LdsRec rec[GSR_BATCH];
     const TileCtx<PPT> c = tile_ctx<PPT>(a);
+    // the accumulators are in use from here on (the clearing kernel, which
+    // reads the flag, has completed before this kernel starts)
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.counters->grad_dirty = 1u;
     if (a.counters->overflow) return;
     const uint2 range = a.ranges[c.tile];
     const int lane = threadIdx.x;
     const float amax = a.cfg.alpha_max;
-    const int64_t S = a.slots;
 
     float T[PPT], Tf[PPT], gsk[PPT], g0[PPT], g1[PPT], g2[PPT];
     uint32_t my_n[PPT];
@@ -318,9 +320,9 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
             const uint32_t slot = __float_as_uint(r.p2.w);
             if ((lane & 7) == 0) {
                 const int f = lane >> 3;
-                atomic_add_f64(&a.grad2d[f * S + slot], (double)(s8 * field_scale(f)));
+                atomic_add_f64(&a.grad2d[GSR_G2 * (int64_t)slot + f], (double)(s8 * field_scale(f)));
             }
-            if (lane == 0) atomic_add_f64(&a.grad2d[8 * S + slot], (double)v8);
+            if (lane == 0) atomic_add_f64(&a.grad2d[GSR_G2 * (int64_t)slot + 8], (double)v8);
         }
         __syncthreads();
         hi_ = lo_;
@@ -364,16 +366,18 @@ hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, 
     return e != hipSuccess ? e : hipGetLastError();
 }
 
-// zero the screen-space accumulators of every projected slot (rx >= 0); the
+// zero the screen-space accumulators of every projected slot (rx >= 0) when
+// a backward has added to them since the projection zeroed them; the
 // backward only ever adds to and reads such slots, so each backward starts
 // from zero however often it is called
-__global__ void k_clear_grad2d(const float4* geom, double* grad2d, int64_t slots)
+__global__ void k_clear_grad2d(const Counters* counters, const float4* geom, double* grad2d, int64_t slots)
 {
+    if (!counters->grad_dirty) return;
     for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
          s += (int64_t)gridDim.x * blockDim.x) {
         if (geom[s].z >= 0.0f) {
 #pragma unroll
-            for (int f = 0; f < GSR_G2; ++f) grad2d[f * slots + s] = 0.0;
+            for (int f = 0; f < GSR_G2; ++f) grad2d[GSR_G2 * s + f] = 0.0;
         }
     }
 }
@@ -383,7 +387,8 @@ hipError_t launch_clear_grad2d(const RasterArgs& a, hipStream_t s)
     if (a.slots <= 0) return hipSuccess;
     int64_t blocks = (a.slots + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_clear_grad2d, dim3((unsigned)blocks), dim3(256), 0, s, a.geom, a.grad2d, a.slots);
+    hipLaunchKernelGGL(k_clear_grad2d, dim3((unsigned)blocks), dim3(256), 0, s, a.counters, a.geom, a.grad2d,
+                       a.slots);
     return hipGetLastError();
 }
 

@@ -1,14 +1,14 @@
 // sort.hip -- per-tile ordering of the emitted pairs, and the tiles' order.
 //
-// k_seg_sort   one block per tile (largest segments first): sorts the
+// k_seg_sort   one 256-thread block per tile (longest first): sorts the
 //              segment's unique 64-bit keys (depth bits << 32 | Gaussian
 //              index) ascending with a stable LSD radix sort of 8-bit digits,
 //              skipping every digit that is the same for all keys of the
 //              segment, then writes the final pairs: key (tile << 32 | depth
 //              bits), value slot = view * n + index.  Segments of up to
 //              GSR_SEG_ITEMS keys are sorted in LDS; longer ones by the block
-//              in global memory, GSR_SEG_ITEMS keys at a time, ping-ponging
-//              between the segment and the output key array.
+//              through global memory, GSR_SEG_ITEMS keys at a time,
+//              ping-ponging between the segment and the output key array.
 // k_order_*    processing order of the tiles: descending pair count, bucketed
 //              by floor(log2(count)), for the segment sort and compositing.
 //
@@ -31,27 +31,29 @@ __device__ __forceinline__ unsigned long long match_digit(uint32_t d, bool valid
     return m;
 }
 
+template <int WAVES, int ITEMS>
 struct SegLds {
-    unsigned long long sk[GSR_SEG_ITEMS];  // keys in digit order (LDS path)
-    uint32_t wcnt[4][256];                 // per-wave digit counters, then wave offsets
+    unsigned long long sk[ITEMS];          // keys in digit order (LDS path)
+    uint32_t wcnt[WAVES][256];             // per-wave digit counters, then wave offsets
     uint32_t dstart[256];                  // block-local start of each digit
     uint32_t run[256];                     // global path: running output offset per digit
     uint32_t hist[256];
     uint32_t wsum[4];
-    unsigned long long red[2][4];
+    unsigned long long red[2][WAVES];
 };
 
 // Stable ranking of the block's items by digit (key >> shift) & 255.  Item
 // (r, lane) of wave w has index w * R * 64 + r * 64 + lane; on return
 // pos[r] is its position in digit order (digit-major, index order within a
-// digit) and L.dstart[] holds the first position of each digit.
-template <int MAXR>
+// digit) or ~0 for an item past m, and L.dstart[] holds the first position
+// of each digit.
+template <int WAVES, int ITEMS, int MAXR>
 __device__ __forceinline__ void rank_items(const unsigned long long* key, int R, int m, int shift, uint32_t* pos,
-                                           SegLds& L)
+                                           SegLds<WAVES, ITEMS>& L)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const unsigned long long lt = (1ull << lane) - 1ull;
-    for (int k = tid; k < 4 * 256; k += GSR_SEG_THREADS) (&L.wcnt[0][0])[k] = 0u;
+    for (int k = tid; k < WAVES * 256; k += WAVES * 64) (&L.wcnt[0][0])[k] = 0u;
     __syncthreads();
     uint32_t dig[MAXR];
 #pragma unroll
@@ -70,25 +72,28 @@ __device__ __forceinline__ void rank_items(const unsigned long long* key, int R,
         if (valid && below == 0u) L.wcnt[w][d] = start + (uint32_t)__popcll(mk);
     }
     __syncthreads();
-    {
-        // thread = digit: offsets of the waves inside the digit, block digit starts
-        const uint32_t c0 = L.wcnt[0][tid], c1 = L.wcnt[1][tid], c2 = L.wcnt[2][tid], c3 = L.wcnt[3][tid];
-        const uint32_t tot = c0 + c1 + c2 + c3;
-        uint32_t incl = tot;
+    // threads 0..255 (one per digit): wave offsets inside the digit and the
+    // block's digit starts
+    uint32_t tot = 0, incl = 0;
+    if (tid < 256) {
+        for (int k = 0; k < WAVES; ++k) tot += L.wcnt[k][tid];
+        incl = tot;
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(incl, off, 64);
             if (lane >= off) incl += y;
         }
         if (lane == 63) L.wsum[w] = incl;
-        __syncthreads();
-        uint32_t wofs = 0;
-        for (int k = 0; k < w; ++k) wofs += L.wsum[k];
-        const uint32_t ds = wofs + incl - tot;
+    }
+    __syncthreads();
+    if (tid < 256) {
+        uint32_t ds = incl - tot;
+        for (int k = 0; k < w; ++k) ds += L.wsum[k];
         L.dstart[tid] = ds;
-        L.wcnt[0][tid] = ds;
-        L.wcnt[1][tid] = ds + c0;
-        L.wcnt[2][tid] = ds + c0 + c1;
-        L.wcnt[3][tid] = ds + c0 + c1 + c2;
+        for (int k = 0; k < WAVES; ++k) {
+            const uint32_t c = L.wcnt[k][tid];
+            L.wcnt[k][tid] = ds;
+            ds += c;
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -99,7 +104,8 @@ __device__ __forceinline__ void rank_items(const unsigned long long* key, int R,
 }
 
 // OR and AND of the block's keys (identity for no key)
-__device__ __forceinline__ void block_or_and(unsigned long long o, unsigned long long a, SegLds& L,
+template <int WAVES, int ITEMS>
+__device__ __forceinline__ void block_or_and(unsigned long long o, unsigned long long a, SegLds<WAVES, ITEMS>& L,
                                              unsigned long long& bor, unsigned long long& band)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -112,8 +118,12 @@ __device__ __forceinline__ void block_or_and(unsigned long long o, unsigned long
         L.red[1][w] = a;
     }
     __syncthreads();
-    bor = L.red[0][0] | L.red[0][1] | L.red[0][2] | L.red[0][3];
-    band = L.red[1][0] & L.red[1][1] & L.red[1][2] & L.red[1][3];
+    bor = 0ull;
+    band = ~0ull;
+    for (int k = 0; k < WAVES; ++k) {
+        bor |= L.red[0][k];
+        band &= L.red[1][k];
+    }
     __syncthreads();
 }
 
@@ -124,21 +134,20 @@ __device__ __forceinline__ void write_pair(const SegArgs& a, uint32_t at, unsign
     a.vals[at] = vbase + (uint32_t)k;
 }
 
-__global__ __launch_bounds__(GSR_SEG_THREADS) void k_seg_sort(SegArgs a)
+// Sorts the segment of one tile with the whole block (WAVES * 64 threads,
+// ITEMS = 16 keys per thread fit in LDS).
+template <int WAVES, int ITEMS>
+__device__ void sort_segment(const SegArgs& a, uint32_t tile, uint2 rg, SegLds<WAVES, ITEMS>& L)
 {
-    __shared__ SegLds L;
-    if (a.counters->overflow) return;
-    const uint32_t tile = a.order[blockIdx.x];
-    const uint2 rg = a.ranges[tile];
+    constexpr int THREADS = WAVES * 64;
+    constexpr int MAXR = ITEMS / THREADS;
     const int m = (int)(rg.y - rg.x);
-    if (m == 0) return;
     const int v = view_of_tile(a.views, (int)tile);
     const uint32_t vbase = (uint32_t)((int64_t)v * a.n);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    constexpr int MAXR = GSR_SEG_ITEMS / GSR_SEG_THREADS;
 
-    if (m <= GSR_SEG_ITEMS) {
-        const int R = (m + GSR_SEG_THREADS - 1) / GSR_SEG_THREADS;
+    if (m <= ITEMS) {
+        const int R = (m + THREADS - 1) / THREADS;
         unsigned long long key[MAXR];
         uint32_t pos[MAXR];
         unsigned long long o = 0ull, an = ~0ull;
@@ -157,7 +166,7 @@ __global__ __launch_bounds__(GSR_SEG_THREADS) void k_seg_sort(SegArgs a)
         const unsigned long long diff = bor ^ band;
         for (int d = 0; d < 8; ++d) {
             if (((diff >> (8 * d)) & 255ull) == 0ull) continue;
-            rank_items<MAXR>(key, R, m, 8 * d, pos, L);
+            rank_items<WAVES, ITEMS, MAXR>(key, R, m, 8 * d, pos, L);
 #pragma unroll
             for (int r = 0; r < MAXR; ++r) {
                 if (r >= R) break;
@@ -181,11 +190,11 @@ __global__ __launch_bounds__(GSR_SEG_THREADS) void k_seg_sort(SegArgs a)
         return;
     }
 
-    // long segment: LSD passes through global memory
+    // longer segment: LSD passes through global memory, ITEMS keys at a time
     unsigned long long* bufA = a.seg + rg.x;
     unsigned long long* bufB = a.keys + rg.x;  // output keys double as scratch
     unsigned long long o = 0ull, an = ~0ull;
-    for (int i = tid; i < m; i += GSR_SEG_THREADS) {
+    for (int i = tid; i < m; i += THREADS) {
         const unsigned long long k = bufA[i];
         o |= k;
         an &= k;
@@ -198,26 +207,29 @@ __global__ __launch_bounds__(GSR_SEG_THREADS) void k_seg_sort(SegArgs a)
     for (int d = 0; d < 8; ++d) {
         if (((diff >> (8 * d)) & 255ull) == 0ull) continue;
         const int shift = 8 * d;
-        L.hist[tid] = 0u;
+        if (tid < 256) L.hist[tid] = 0u;
         __syncthreads();
-        for (int i = tid; i < m; i += GSR_SEG_THREADS) atomicAdd(&L.hist[(uint32_t)(src[i] >> shift) & 255u], 1u);
+        for (int i = tid; i < m; i += THREADS) atomicAdd(&L.hist[(uint32_t)(src[i] >> shift) & 255u], 1u);
         __syncthreads();
-        {
-            const uint32_t x = L.hist[tid];
-            uint32_t incl = x;
+        uint32_t x = 0, incl = 0;
+        if (tid < 256) {
+            x = L.hist[tid];
+            incl = x;
             for (int off = 1; off < 64; off <<= 1) {
                 const uint32_t y = __shfl_up(incl, off, 64);
                 if (lane >= off) incl += y;
             }
             if (lane == 63) L.wsum[w] = incl;
-            __syncthreads();
+        }
+        __syncthreads();
+        if (tid < 256) {
             uint32_t wofs = 0;
             for (int k = 0; k < w; ++k) wofs += L.wsum[k];
             L.run[tid] = wofs + incl - x;
         }
-        for (int cb = 0; cb < m; cb += GSR_SEG_ITEMS) {
-            const int cm = min(GSR_SEG_ITEMS, m - cb);
-            const int R = (cm + GSR_SEG_THREADS - 1) / GSR_SEG_THREADS;
+        for (int cb = 0; cb < m; cb += ITEMS) {
+            const int cm = min(ITEMS, m - cb);
+            const int R = (cm + THREADS - 1) / THREADS;
             unsigned long long key[MAXR];
             uint32_t pos[MAXR];
 #pragma unroll
@@ -226,7 +238,7 @@ __global__ __launch_bounds__(GSR_SEG_THREADS) void k_seg_sort(SegArgs a)
                 const int li = w * R * 64 + r * 64 + lane;
                 key[r] = li < cm ? src[cb + li] : 0ull;
             }
-            rank_items<MAXR>(key, R, cm, shift, pos, L);
+            rank_items<WAVES, ITEMS, MAXR>(key, R, cm, shift, pos, L);
 #pragma unroll
             for (int r = 0; r < MAXR; ++r) {
                 if (r >= R) break;
@@ -237,8 +249,10 @@ __global__ __launch_bounds__(GSR_SEG_THREADS) void k_seg_sort(SegArgs a)
             }
             __syncthreads();
             // advance the running offsets by this chunk's digit counts
-            const uint32_t next = tid < 255 ? L.dstart[tid + 1] : (uint32_t)cm;
-            L.run[tid] += next - L.dstart[tid];
+            if (tid < 256) {
+                const uint32_t next = tid < 255 ? L.dstart[tid + 1] : (uint32_t)cm;
+                L.run[tid] += next - L.dstart[tid];
+            }
             __syncthreads();
         }
         unsigned long long* t = src;
@@ -246,7 +260,18 @@ __global__ __launch_bounds__(GSR_SEG_THREADS) void k_seg_sort(SegArgs a)
         dst = t;
     }
     // src holds the sorted keys (in place when it is the output array)
-    for (int i = tid; i < m; i += GSR_SEG_THREADS) write_pair(a, rg.x + (uint32_t)i, src[i], tile, vbase);
+    for (int i = tid; i < m; i += THREADS) write_pair(a, rg.x + (uint32_t)i, src[i], tile, vbase);
+}
+
+// one 256-thread block per tile, in the tiles' processing order (longest first)
+__global__ __launch_bounds__(GSR_SEG_THREADS) void k_seg_sort(SegArgs a)
+{
+    __shared__ SegLds<GSR_SEG_THREADS / 64, GSR_SEG_ITEMS> L;
+    if (a.counters->overflow) return;
+    const uint32_t tile = a.order[blockIdx.x];
+    const uint2 rg = a.ranges[tile];
+    if (rg.y == rg.x) return;
+    sort_segment(a, tile, rg, L);
 }
 
 hipError_t launch_seg_sort(const SegArgs& a, int total_tiles, hipStream_t s)

@@ -85,7 +85,7 @@ class Renderer:
             "conic_o": self._view(L.conic_o, 4 * S, torch.float32).view(S, 4),
             "rgb_d": self._view(L.rgb_d, 4 * S, torch.float32).view(S, 4),
             "qthr": self._view(L.qthr, S, torch.float32),
-            "grad2d": self._view(L.grad2d, 9 * S, torch.float64).view(9, S),
+            "grad2d": self._view(L.grad2d, 9 * S, torch.float64).view(S, 9),
         }
 
     def sorted_pairs(self, count):
