@@ -4,7 +4,10 @@
 //              segment's unique 64-bit keys (depth bits << 32 | Gaussian
 //              index) ascending with a stable LSD radix sort of 8-bit digits,
 //              skipping every digit that is the same for all keys of the
-//              segment, then writes the final pairs: key (tile << 32 | depth
+//              segment.  In LDS the depth digits go first and the runs of
+//              equal depth are then put in index order by odd-even
+//              transposition (falling back to every digit when a run does
+//              not settle in 8 rounds).  Then it writes the final pairs: key (tile << 32 | depth
 //              bits), value slot = view * n + index.  Segments of up to
 //              GSR_SEG_ITEMS keys are sorted in LDS; longer ones by the block
 //              through global memory, GSR_SEG_ITEMS keys at a time,
@@ -164,7 +167,12 @@ __device__ void sort_segment(const SegArgs& a, uint32_t tile, uint2 rg, SegLds<W
         unsigned long long bor, band;
         block_or_and(o, an, L, bor, band);
         const unsigned long long diff = bor ^ band;
-        for (int d = 0; d < 8; ++d) {
+        // depth digits first.  Keys that share a depth then stand in runs in
+        // emission order; odd-even transposition inside those runs puts them in
+        // index order (a few rounds: runs are short).  Runs that do not settle
+        // within 8 rounds fall back to sorting every digit, LSD from the index.
+        bool sorted = false, in_lds = false;
+        for (int d = 4; d < 8; ++d) {
             if (((diff >> (8 * d)) & 255ull) == 0ull) continue;
             rank_items<WAVES, ITEMS, MAXR>(key, R, m, 8 * d, pos, L);
 #pragma unroll
@@ -173,6 +181,7 @@ __device__ void sort_segment(const SegArgs& a, uint32_t tile, uint2 rg, SegLds<W
                 if (pos[r] != 0xffffffffu) L.sk[pos[r]] = key[r];
             }
             __syncthreads();
+            in_lds = true;
 #pragma unroll
             for (int r = 0; r < MAXR; ++r) {
                 if (r >= R) break;
@@ -180,6 +189,60 @@ __device__ void sort_segment(const SegArgs& a, uint32_t tile, uint2 rg, SegLds<W
                 if (li < m) key[r] = L.sk[li];
             }
             __syncthreads();
+        }
+        if ((diff & 0xffffffffull) == 0ull) {
+            sorted = true;  // a single key
+        } else if (diff >> 32) {
+            if (!in_lds) {
+#pragma unroll
+                for (int r = 0; r < MAXR; ++r) {
+                    if (r >= R) break;
+                    const int li = w * R * 64 + r * 64 + lane;
+                    if (li < m) L.sk[li] = key[r];
+                }
+                __syncthreads();
+            }
+            for (int round = 0; round < 8 && !sorted; ++round) {
+                bool swapped = false;
+                for (int par = 0; par < 2; ++par) {
+                    for (int i = par + 2 * tid; i + 1 < m; i += 2 * THREADS) {
+                        const unsigned long long x = L.sk[i], y = L.sk[i + 1];
+                        if ((x >> 32) == (y >> 32) && x > y) {
+                            L.sk[i] = y;
+                            L.sk[i + 1] = x;
+                            swapped = true;
+                        }
+                    }
+                    __syncthreads();
+                }
+                sorted = __syncthreads_or(swapped) == 0;
+            }
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+                if (r >= R) break;
+                const int li = w * R * 64 + r * 64 + lane;
+                if (li < m) key[r] = L.sk[li];
+            }
+            __syncthreads();
+        }
+        if (!sorted) {
+            for (int d = 0; d < 8; ++d) {
+                if (((diff >> (8 * d)) & 255ull) == 0ull) continue;
+                rank_items<WAVES, ITEMS, MAXR>(key, R, m, 8 * d, pos, L);
+#pragma unroll
+                for (int r = 0; r < MAXR; ++r) {
+                    if (r >= R) break;
+                    if (pos[r] != 0xffffffffu) L.sk[pos[r]] = key[r];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < MAXR; ++r) {
+                    if (r >= R) break;
+                    const int li = w * R * 64 + r * 64 + lane;
+                    if (li < m) key[r] = L.sk[li];
+                }
+                __syncthreads();
+            }
         }
 #pragma unroll
         for (int r = 0; r < MAXR; ++r) {

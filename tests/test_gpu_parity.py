@@ -190,6 +190,33 @@ def test_bin_bitexact_long_segments():
         np.testing.assert_array_equal(ranges.cpu().numpy().view(np.uint32), or_)
 
 
+@pytest.mark.parametrize("mode", ["seventh", "all", "run"])
+def test_bin_bitexact_equal_depth_runs(mode):
+    """3,000 pairs in one tile (sorted in LDS) with equal depths: one seventh
+    of the keys at one depth, all keys at one depth, one run of 100 equal
+    depths among distinct ones; equal depths end in index order."""
+    n = 3000
+    cams = [{"width": 16, "height": 16, "fx": 1, "fy": 1, "cx": 0, "cy": 0}]
+    rng = np.random.default_rng(5)
+    recs = _disc_records(rng, n, 16, 16, 1.0)
+    recs[0][:] = 8.0
+    recs[1][:] = 8.0
+    if mode == "all":
+        recs[8][:] = np.float32(2.0)
+    elif mode == "run":
+        recs[8][:] = rng.uniform(0.5, 3.0, n).astype(np.float32)
+        recs[8][rng.permutation(n)[:100]] = np.float32(1.25)
+    say(f"[bin] equal depths: {mode}")
+    R = Renderer(n, cams, Config(), pair_capacity=n + 16)
+    M, ovf = _fill_and_bin(R, recs)
+    assert not ovf and M == n
+    keys, vals, ranges = R.sorted_pairs(M)
+    ok_, ov_, or_ = oracle.bin_f32(cams, n, *recs, 16, 16)
+    np.testing.assert_array_equal(keys.cpu().numpy().view(np.uint64), ok_)
+    np.testing.assert_array_equal(vals.cpu().numpy().view(np.uint32), ov_)
+    np.testing.assert_array_equal(ranges.cpu().numpy().view(np.uint32), or_)
+
+
 def test_bin_bitexact_view_with_many_tiles():
     """A view with more tiles than the LDS histogram holds (1100x1000 with
     8x8 tiles, 17,250 tiles) next to a small one: counting and placement
