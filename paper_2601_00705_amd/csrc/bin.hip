@@ -37,14 +37,39 @@ struct ChunkLds {
     uint32_t wsum[4];
 };
 
-// Stages Gaussians base .. base + GSR_BIN_CHUNK - 1 of view v (thread t owns
-// items IPT t .. IPT t + IPT - 1, which keeps index order): rectangles,
-// ellipse data and the scan of the rectangle areas.  Returns the total area.
-// Starts and ends with a block barrier.
+// The records of one staged group, fetched into registers (thread t owns
+// items IPT t .. IPT t + IPT - 1).  All fields are loaded at once, live or
+// not, so that one memory round trip serves the group; the next group's
+// fetch is issued before the current group is expanded.
 constexpr int IPT = GSR_BIN_CHUNK / 256;
 
-__device__ uint32_t load_chunk(const BinArgs& a, const ViewInfo& vw, int v, int64_t base, bool want_depth,
-                               ChunkLds& L)
+struct ChunkRegs {
+    float4 gm[IPT], co[IPT];
+    float q[IPT];
+    uint32_t dbits[IPT];
+    bool in[IPT];
+};
+
+__device__ __forceinline__ void fetch_chunk(const BinArgs& a, int v, int64_t base, bool want_depth, ChunkRegs& R)
+{
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+        const int64_t i = base + threadIdx.x * IPT + k;
+        R.in[k] = i < a.n;
+        if (R.in[k]) {
+            const int64_t slot = (int64_t)v * a.n + i;
+            R.gm[k] = a.geom[slot];
+            R.co[k] = a.conic_o[slot];
+            R.q[k] = a.qthr[slot];
+            R.dbits[k] = want_depth ? __float_as_uint(a.rgb_d[slot].w) : 0u;
+        }
+    }
+}
+
+// Stages a fetched group: rectangles, ellipse data and the scan of the
+// rectangle areas.  Returns the total area.  Starts and ends with a block
+// barrier.
+__device__ uint32_t stage_chunk(const BinArgs& a, const ViewInfo& vw, const ChunkRegs& R, ChunkLds& L)
 {
     const float inv_tw = 1.0f / (float)a.cfg.tile_w, inv_th = 1.0f / (float)a.cfg.tile_h;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -53,23 +78,18 @@ __device__ uint32_t load_chunk(const BinArgs& a, const ViewInfo& vw, int v, int6
 #pragma unroll
     for (int k = 0; k < IPT; ++k) {
         const int li = tid * IPT + k;
-        const int64_t i = base + li;
         area[k] = 0;
         int x0 = 0, y0 = 0, x1 = -1, y1 = -1;
-        if (i < a.n) {
-            const int64_t slot = (int64_t)v * a.n + i;
-            const float4 gm = a.geom[slot];
-            if (tile_rect(gm.x, gm.y, gm.z, gm.w, inv_tw, inv_th, vw.tiles_x, vw.tiles_y, x0, y0, x1, y1)) {
-                area[k] = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
-                const float4 co = a.conic_o[slot];
-                L.u[li] = gm.x;
-                L.v[li] = gm.y;
-                L.A[li] = co.x;
-                L.B[li] = co.y;
-                L.C[li] = co.z;
-                L.q[li] = a.qthr[slot];
-                if (want_depth) L.dbits[li] = __float_as_uint(a.rgb_d[slot].w);
-            }
+        if (R.in[k] && tile_rect(R.gm[k].x, R.gm[k].y, R.gm[k].z, R.gm[k].w, inv_tw, inv_th, vw.tiles_x,
+                                 vw.tiles_y, x0, y0, x1, y1)) {
+            area[k] = (uint32_t)((x1 - x0 + 1) * (y1 - y0 + 1));
+            L.u[li] = R.gm[k].x;
+            L.v[li] = R.gm[k].y;
+            L.A[li] = R.co[k].x;
+            L.B[li] = R.co[k].y;
+            L.C[li] = R.co[k].z;
+            L.q[li] = R.q[k];
+            L.dbits[li] = R.dbits[k];
         }
         L.rx0[li] = x0;
         L.ry0[li] = y0;
@@ -132,10 +152,14 @@ __global__ __launch_bounds__(256) void k_bin_count(BinArgs a)
     uint32_t* row = count_row(a, vw, blockIdx.x);
     if (LDS_HIST)
         for (int t = threadIdx.x; t < tiles_v; t += 256) hist[t] = 0u;
-    for (int sub = 0; sub < a.chunk_mult; ++sub) {
-        const int64_t base = ((int64_t)blockIdx.x * a.chunk_mult + sub) * GSR_BIN_CHUNK;
+    ChunkRegs cur, nxt;
+    int64_t base = (int64_t)blockIdx.x * a.chunk_mult * GSR_BIN_CHUNK;
+    fetch_chunk(a, v, base, false, nxt);
+    for (int sub = 0; sub < a.chunk_mult; ++sub, base += GSR_BIN_CHUNK) {
         if (base >= a.n) break;
-        const uint32_t total = load_chunk(a, vw, v, base, false, L);
+        cur = nxt;
+        if (sub + 1 < a.chunk_mult) fetch_chunk(a, v, base + GSR_BIN_CHUNK, false, nxt);
+        const uint32_t total = stage_chunk(a, vw, cur, L);
         for (uint32_t j = threadIdx.x; j < total; j += 256) {
             int s, tx, ty;
             if (candidate(L, j, a, s, tx, ty)) {
@@ -234,10 +258,14 @@ __global__ __launch_bounds__(256) void k_bin_emit(BinArgs a)
     const uint2* rng = a.ranges + vw.tile_base;
     if (LDS_HIST)
         for (int t = threadIdx.x; t < tiles_v; t += 256) cursor[t] = rng[t].x + row[t];
-    for (int sub = 0; sub < a.chunk_mult; ++sub) {
-        const int64_t base = ((int64_t)blockIdx.x * a.chunk_mult + sub) * GSR_BIN_CHUNK;
+    ChunkRegs cur, nxt;
+    int64_t base = (int64_t)blockIdx.x * a.chunk_mult * GSR_BIN_CHUNK;
+    fetch_chunk(a, v, base, true, nxt);
+    for (int sub = 0; sub < a.chunk_mult; ++sub, base += GSR_BIN_CHUNK) {
         if (base >= a.n) break;
-        const uint32_t total = load_chunk(a, vw, v, base, true, L);
+        cur = nxt;
+        if (sub + 1 < a.chunk_mult) fetch_chunk(a, v, base + GSR_BIN_CHUNK, true, nxt);
+        const uint32_t total = stage_chunk(a, vw, cur, L);
         for (uint32_t j = threadIdx.x; j < total; j += 256) {
             int s, tx, ty;
             if (candidate(L, j, a, s, tx, ty)) {
