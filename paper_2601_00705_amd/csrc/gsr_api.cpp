@@ -206,14 +206,17 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->passes = 4 + (n > 1 ? (ilog2((int)std::min<int64_t>(n, 1ll << 30)) + 7) / 8 : 0);
     for (int v = 0; v < n_views; ++v)
         p->max_tiles_view = std::max(p->max_tiles_view, p->vt.v[v].tiles_x * p->vt.v[v].tiles_y);
-    // binning chunks of GSR_BIN_CHUNK * chunk_mult Gaussians: larger chunks
-    // while at least 2048 (chunk, view) blocks remain, so the count matrix
-    // stays small
+    // binning chunks of GSR_BIN_CHUNK * chunk_mult Gaussians per block: each
+    // block writes a count row of its view's tiles, so views with many tiles
+    // want larger chunks, while enough blocks must remain to keep every CU
+    // busy (measured on MI355X: 1024 Gaussians per block for views of up to
+    // 4096 tiles, 2048 beyond; smaller chunks while fewer than 4096 blocks
+    // would exist)
     auto chunks_for = [&](int m) {
         return (int64_t)((n + (int64_t)GSR_BIN_CHUNK * m - 1) / ((int64_t)GSR_BIN_CHUNK * m));
     };
-    p->chunk_mult = 1;
-    while (p->chunk_mult < 32 && chunks_for(2 * p->chunk_mult) * n_views >= 2048) p->chunk_mult *= 2;
+    p->chunk_mult = (p->max_tiles_view <= 4096 ? 1024 : 2048) / GSR_BIN_CHUNK;
+    while (p->chunk_mult > 1 && chunks_for(p->chunk_mult) * n_views < 4096) p->chunk_mult /= 2;
     p->chunks = (int32_t)std::max<int64_t>(1, chunks_for(p->chunk_mult));
     p->bwd_blocks = (int32_t)((n + 255) / 256);
     if (p->bwd_blocks == 0) p->bwd_blocks = 1;

@@ -98,7 +98,7 @@ struct LossArgs {
     float scale;        // 1 / count
 };
 
-#define GSR_BIN_CHUNK 512           // Gaussians staged in LDS at a time by the binning blocks (x256)
+#define GSR_BIN_CHUNK 256           // Gaussians staged in LDS at a time by the binning blocks (x256)
 #define GSR_BIN_LDS_TILES 16384     // views with more tiles count and place with global atomics
 #define GSR_SEG_THREADS 256
 #define GSR_SEG_ITEMS 4096          // segments up to this size are sorted in LDS
