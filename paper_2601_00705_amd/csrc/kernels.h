@@ -100,8 +100,8 @@ struct LossArgs {
 
 #define GSR_BIN_CHUNK 256           // Gaussians staged in LDS at a time by the binning blocks (x256)
 #define GSR_BIN_LDS_TILES 16384     // views with more tiles count and place with global atomics
-#define GSR_SEG_THREADS 256
-#define GSR_SEG_ITEMS 4096          // segments up to this size are sorted in LDS
+#define GSR_SEG_THREADS 512
+#define GSR_SEG_ITEMS 8192          // segments up to this size are sorted in LDS
 
 hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t s);
 // pair counting, offsets, emission into per-tile segments; max_tiles_view is

@@ -1,6 +1,6 @@
 // sort.hip -- per-tile ordering of the emitted pairs, and the tiles' order.
 //
-// k_seg_sort   one 256-thread block per tile (longest first): sorts the
+// k_seg_sort   one 512-thread block per tile (longest first): sorts the
 //              segment's unique 64-bit keys (depth bits << 32 | Gaussian
 //              index) ascending with a stable LSD radix sort of 8-bit digits,
 //              skipping every digit that is the same for all keys of the
@@ -36,6 +36,8 @@ __device__ __forceinline__ unsigned long long match_digit(uint32_t d, bool valid
 
 template <int WAVES, int ITEMS>
 struct SegLds {
+    // the digit scans give one thread to each of the 256 digits
+    static_assert(WAVES * 64 >= 256, "a sorting block needs at least 256 threads");
     unsigned long long sk[ITEMS];          // keys in digit order (LDS path)
     uint32_t wcnt[WAVES][256];             // per-wave digit counters, then wave offsets
     uint32_t dstart[256];                  // block-local start of each digit
@@ -326,7 +328,7 @@ __device__ void sort_segment(const SegArgs& a, uint32_t tile, uint2 rg, SegLds<W
     for (int i = tid; i < m; i += THREADS) write_pair(a, rg.x + (uint32_t)i, src[i], tile, vbase);
 }
 
-// one 256-thread block per tile, in the tiles' processing order (longest first)
+// one block per tile, in the tiles' processing order (longest first)
 __global__ __launch_bounds__(GSR_SEG_THREADS) void k_seg_sort(SegArgs a)
 {
     __shared__ SegLds<GSR_SEG_THREADS / 64, GSR_SEG_ITEMS> L;

@@ -170,8 +170,8 @@ def _disc_records(rng, S, w, h, scale):
 
 
 def test_bin_bitexact_long_segments():
-    """Tiles whose lists exceed what one block sorts in LDS (6,000, 9,000
-    and 20,000 pairs in one tile: sorted through global memory), one seventh
+    """Long tile lists: 6,000 pairs (sorted in LDS) and 9,000 and 20,000
+    (beyond what one block holds: sorted through global memory), one seventh
     of the keys at one depth."""
     for n in (6000, 9000, 20000):
         cams = [{"width": 16, "height": 16, "fx": 1, "fy": 1, "cx": 0, "cy": 0}]
