@@ -127,6 +127,70 @@ __device__ __forceinline__ TileCtx<PPT> tile_ctx(const RasterArgs& a)
     return c;
 }
 
+// Walks the batch in LDS for the lane's pixels.  A pixel that has stopped
+// (or lies outside the view) carries a NaN row offset, so every later test
+// power2 >= thr fails for it without a per-pixel flag.  Reaching T_min is
+// rare (once per pixel at most), so the common step applies every passing
+// entry and a wave-uniform branch undoes the blend of stopping pixels.
+template <int PPT, bool COUNT>
+__device__ __forceinline__ void fwd_batch(const LdsRec* rec, int cnt, uint32_t pos0, float amax, float tmin,
+                                          float dx, float (&dy)[PPT], float (&T)[PPT], float (&C0)[PPT],
+                                          float (&C1)[PPT], float (&C2)[PPT], uint32_t (&last)[PPT],
+                                          uint32_t (&nb)[PPT])
+{
+    for (int e = 0; e < cnt; ++e) {
+        if ((e & 15) == 0) {
+            uint64_t live = 0;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) live |= __builtin_amdgcn_ballot_w64(dy[k] == dy[k]);
+            if (live == 0) break;
+        }
+        const LdsRec r = rec[e];
+        const ColTerms ct = col_terms(r, dx);
+        float p2[PPT];
+        bool pass[PPT];
+        uint64_t any = 0;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            p2[k] = power2(ct, r.p1.y, dy[k]);
+            pass[k] = p2[k] >= r.p1.w;
+            any |= __builtin_amdgcn_ballot_w64(pass[k]);
+        }
+        if (any == 0) continue;
+        float ab[PPT], Tn[PPT];
+        bool stop[PPT];
+        uint64_t any_stop = 0;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const float alpha = fminf(amax, r.p1.z * __builtin_amdgcn_exp2f(p2[k]));
+            ab[k] = pass[k] ? alpha : 0.0f;
+            Tn[k] = __builtin_fmaf(-T[k], ab[k], T[k]);
+            stop[k] = Tn[k] < tmin;
+            any_stop |= __builtin_amdgcn_ballot_w64(stop[k]);
+        }
+        if (any_stop != 0) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                ab[k] = stop[k] ? 0.0f : ab[k];
+                Tn[k] = stop[k] ? T[k] : Tn[k];
+                dy[k] = stop[k] ? __builtin_nanf("") : dy[k];
+            }
+        }
+        const uint32_t pos1 = pos0 + (uint32_t)e + 1u;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const bool blend = pass[k] & !stop[k];
+            const float wgt = ab[k] * T[k];
+            C0[k] = __builtin_fmaf(r.p2.x, wgt, C0[k]);
+            C1[k] = __builtin_fmaf(r.p2.y, wgt, C1[k]);
+            C2[k] = __builtin_fmaf(r.p2.z, wgt, C2[k]);
+            T[k] = Tn[k];
+            last[k] = blend ? pos1 : last[k];
+            if (COUNT) nb[k] += blend ? 1u : 0u;
+        }
+    }
+}
+
 template <int PPT, int GSR_BATCH>
 __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
 {
@@ -136,20 +200,21 @@ __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
     const bool overflow = a.counters->overflow != 0u;
     const uint2 range = overflow ? make_uint2(0u, 0u) : a.ranges[c.tile];
     const float amax = a.cfg.alpha_max, tmin = a.cfg.T_min;
-    float T[PPT], C0[PPT], C1[PPT], C2[PPT];
+    const bool count = a.n_blend != nullptr;
+    float T[PPT], C0[PPT], C1[PPT], C2[PPT], dy[PPT];
     uint32_t last[PPT], nb[PPT];
-    bool done[PPT];
-    bool lane_done = true;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         T[k] = 1.0f;
         C0[k] = C1[k] = C2[k] = 0.0f;
         last[k] = nb[k] = 0u;
-        done[k] = !c.inside[k];
-        lane_done = lane_done && done[k];
+        dy[k] = c.inside[k] ? c.dy[k] : __builtin_nanf("");
     }
     for (uint32_t base = range.x; base < range.y; base += GSR_BATCH) {
-        if (__all(lane_done)) break;
+        uint64_t live = 0;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) live |= __builtin_amdgcn_ballot_w64(dy[k] == dy[k]);
+        if (live == 0) break;
 #pragma unroll
         for (int r = 0; r < GSR_BATCH / 64; ++r) {
             const uint32_t j = base + lane + 64 * r;
@@ -157,39 +222,10 @@ __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)GSR_BATCH, range.y - base);
-        for (int e = 0; e < cnt; ++e) {
-            if ((e & 15) == 0 && __all(lane_done)) break;
-            const LdsRec r = rec[e];
-            const ColTerms ct = col_terms(r, c.dx);
-            float p2[PPT];
-            bool pass[PPT], any = false;
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                p2[k] = power2(ct, r.p1.y, c.dy[k]);
-                pass[k] = (p2[k] >= r.p1.w) & !done[k];
-                any |= pass[k];
-            }
-            if (!__any(any)) continue;
-            const uint32_t pos1 = base + (uint32_t)e - range.x + 1u;
-            bool all = true;
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                const float alpha = fminf(amax, r.p1.z * __builtin_amdgcn_exp2f(p2[k]));
-                const float Tn = __builtin_fmaf(-T[k], alpha, T[k]);
-                const bool stop = pass[k] & (Tn < tmin);
-                const bool blend = pass[k] & !stop;
-                done[k] = done[k] | stop;
-                const float wgt = blend ? alpha * T[k] : 0.0f;
-                C0[k] = __builtin_fmaf(r.p2.x, wgt, C0[k]);
-                C1[k] = __builtin_fmaf(r.p2.y, wgt, C1[k]);
-                C2[k] = __builtin_fmaf(r.p2.z, wgt, C2[k]);
-                T[k] = blend ? Tn : T[k];
-                last[k] = blend ? pos1 : last[k];
-                nb[k] += blend ? 1u : 0u;
-                all = all & done[k];
-            }
-            lane_done = all;
-        }
+        if (count)
+            fwd_batch<PPT, true>(rec, cnt, base - range.x, amax, tmin, c.dx, dy, T, C0, C1, C2, last, nb);
+        else
+            fwd_batch<PPT, false>(rec, cnt, base - range.x, amax, tmin, c.dx, dy, T, C0, C1, C2, last, nb);
         __syncthreads();
     }
 #pragma unroll
