@@ -32,11 +32,18 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 # Algorithmic VALU issue slots per evaluation (one pixel against one list
-# entry up to the pixel's last contributor), counted from the per-pixel
-# formulas of the forward and backward compositing (design notes):
-# forward 17 operations + exp2 (4 slots); backward 46 operations + exp2 + rcp.
-SLOTS_FWD_PER_EVAL = 17 + 4
-SLOTS_BWD_PER_EVAL = 46 + 4 + 4
+# entry up to the pixel's last contributor), counted operation by operation
+# from the per-pixel formulas, a transcendental at 4 slots:
+#   forward: power2 (2 FMA), alpha_min test, exp2, o * G and the alpha_max
+#     clamp (2), pass select, T (1 - alpha) (FMA), T_min test, weight alpha T,
+#     colour (3 FMA), last-contributor select = 13 operations + exp2
+#   backward: power2 (2 FMA), alpha_min and list-position tests (2), exp2,
+#     o * G and clamp (2), 1 - alpha, rcp, T / (1 - alpha), g . c (3),
+#     dL/dalpha (2), weight (1), colour gradients (3 FMA), running g . S (1),
+#     alpha dL/dalpha (1), moments sum dd, dd dy, dd dy^2 (3), selects of the
+#     weight, T and dd (3) = 25 operations + exp2 + rcp
+SLOTS_FWD_PER_EVAL = 13 + 4
+SLOTS_BWD_PER_EVAL = 25 + 4 + 4
 # Algorithmic HBM bytes of one sort pass per pair: key + value read and written
 BYTES_SORT_PASS_PER_PAIR = 2 * (8 + 4)
 # Projection backward: per live slot the geom record and the nine FP64

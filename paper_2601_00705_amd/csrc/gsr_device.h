@@ -145,66 +145,45 @@ __device__ __forceinline__ float dpp(float x)
 #define GSR_DPP_ROW_MIRROR 0x140
 #define GSR_DPP_ROW_HALF_MIRROR 0x141
 
-// value of the same register in lane ^ 32 (MASK 32) or lane ^ 16 (MASK 16)
-template <int MASK>
-__device__ __forceinline__ float swap_partner(float x, int lane)
+// Sum of a and b after exchanging the upper 32 lanes of a with the lower 32
+// lanes of b: lanes 0-31 get a + a(lane + 32), lanes 32-63 get
+// b(lane - 32) + b.  permlane16 does the same between rows 0/1 and 2/3.
+__device__ __forceinline__ float swap_sum32(float a, float b)
 {
-    unsigned u = __float_as_uint(x);
-    if (MASK == 32) {
-        auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
-        return __uint_as_float((lane & 32) ? r[0] : r[1]);
-    } else {
-        auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
-        return __uint_as_float((lane & 16) ? r[0] : r[1]);
-    }
+    auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// sum over all 64 lanes (every lane gets the total)
-__device__ __forceinline__ float wave_sum(float x)
+__device__ __forceinline__ float swap_sum16(float a, float b)
 {
-    const int lane = threadIdx.x & 63;
-    x += dpp<GSR_DPP_QUAD_XOR1>(x);
-    x += dpp<GSR_DPP_QUAD_XOR2>(x);
-    x += dpp<GSR_DPP_ROW_HALF_MIRROR>(x);
-    x += dpp<GSR_DPP_ROW_MIRROR>(x);
-    x += swap_partner<16>(x, lane);
-    x += swap_partner<32>(x, lane);
-    return x;
+    auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a), __float_as_uint(b), false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Transposed reduction of 8 values over the wave: afterwards lane 8k holds
-// the 64-lane total of v[k] (in v[0]).  Each exchange keeps half of the
-// values and adds the partner lane's copy of that half.
-__device__ __forceinline__ float wave_sum8_transposed(float* v)
+// Transposed reduction of 9 values over the wave.  Afterwards lane 8k
+// (k < 8) holds the 64-lane total of v[k] and lane 1 the total of v[8].
+// Each exchange keeps half of the values and adds the partner lane's copy
+// of that half; v[8] rides along paired with zeros into lanes 0-15 and is
+// finished inside row 0.
+__device__ __forceinline__ float wave_sum9_transposed(const float (&v)[9], int lane)
 {
-    const int lane = threadIdx.x & 63;
-    {  // lane ^ 32: permlane32 swap of (v[j], v[4 + j])
-        const bool hi = lane & 32;
+    float a[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[j]), __float_as_uint(v[4 + j]), false, false);
-            v[j] = hi ? v[4 + j] + __uint_as_float(r[0]) : v[j] + __uint_as_float(r[1]);
-        }
-    }
-    {  // lane ^ 16
-        const bool hi = lane & 16;
-#pragma unroll
-        for (int j = 0; j < 2; ++j) {
-            auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[j]), __float_as_uint(v[2 + j]), false, false);
-            v[j] = hi ? v[2 + j] + __uint_as_float(r[0]) : v[j] + __uint_as_float(r[1]);
-        }
-    }
-    {  // mirror partner in the row (bit 3 complemented)
-        const bool hi = lane & 8;
-        float send = hi ? v[0] : v[1];
-        float keep = hi ? v[1] : v[0];
-        v[0] = keep + dpp<GSR_DPP_ROW_MIRROR>(send);
-    }
-    float s = v[0];
+    for (int j = 0; j < 4; ++j) a[j] = swap_sum32(v[j], v[4 + j]);  // lane ^ 32
+    float w = swap_sum32(v[8], 0.0f);
+    float b0 = swap_sum16(a[0], a[2]), b1 = swap_sum16(a[1], a[3]);  // lane ^ 16
+    w = swap_sum16(w, 0.0f);
+    // mirror partner in the row (bit 3 complemented)
+    const bool hi = lane & 8;
+    float s = (hi ? b1 : b0) + dpp<GSR_DPP_ROW_MIRROR>(hi ? b0 : b1);
     s += dpp<GSR_DPP_ROW_HALF_MIRROR>(s);
     s += dpp<GSR_DPP_QUAD_XOR2>(s);
     s += dpp<GSR_DPP_QUAD_XOR1>(s);
-    return s;
+    w += dpp<GSR_DPP_QUAD_XOR1>(w);
+    w += dpp<GSR_DPP_QUAD_XOR2>(w);
+    w += dpp<GSR_DPP_ROW_HALF_MIRROR>(w);
+    w += dpp<GSR_DPP_ROW_MIRROR>(w);
+    return lane == 1 ? w : s;
 }
 
 __device__ __forceinline__ void atomic_add_f64(double* p, double v)

@@ -36,7 +36,7 @@ struct __align__(16) LdsRec {
     float4 p0;  // c0, gx, gy, a2   (power2 at the tile centre and its gradient; a2 = k A)
     float4 p1;  // b2, c2, o, thr   (b2 = 2 k B, c2 = k C, thr = log2(alpha_min / o))
     float4 p2;  // r, g, b, slot bits
-    float4 p3;  // ox, oy, -, -     (tile centre - projected centre)
+    float4 p3;  // ox, oy, 1/o, -   (tile centre - projected centre)
 };
 
 // Stages the record of `slot` for the tile centred at (xc, yc).  With
@@ -59,7 +59,7 @@ __device__ __forceinline__ void stage_record(const RasterArgs& a, uint32_t slot,
                        (float)(k * sr.A));
     r.p1 = make_float4((float)(2.0 * k * sr.B), (float)(k * sr.C), sr.o, thr);
     r.p2 = make_float4(sr.r, sr.g, sr.b, __uint_as_float(slot));
-    r.p3 = make_float4((float)ox, (float)oy, 0.0f, 0.0f);
+    r.p3 = make_float4((float)ox, (float)oy, 1.0f / sr.o, 0.0f);
 }
 
 // The terms of power2 shared by the pixels of one lane (same column offset
@@ -250,8 +250,9 @@ __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
     }
 }
 
-// scale of field f (du, dv, dA, dB, dC, do, dr, dg) from the accumulated
-// power2-space partials to the screen-space gradient
+// scale of field f (du, dv, dA, dB, dC, -, dr, dg, db) from the reduced
+// power2-space partials to the screen-space gradient (the opacity field is
+// scaled by the record's 1/o)
 __device__ __forceinline__ float field_scale(int f)
 {
     return f < 2 ? -GSR_LN2 : (f == 3 ? -1.0f : (f < 5 ? -0.5f : 1.0f));
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
     const int lane = threadIdx.x;
     const float amax = a.cfg.alpha_max;
 
-    float T[PPT], Tf[PPT], gsk[PPT], g0[PPT], g1[PPT], g2[PPT];
+    float T[PPT], Tf[PPT], gsk[PPT], g0[PPT], g1[PPT], g2[PPT], dy2[PPT];
     uint32_t my_n[PPT];
     uint32_t lane_max = 0;
 #pragma unroll
@@ -288,6 +289,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
             if (a.dL_dT) gT = a.dL_dT[c.pix[k]];
         }
         T[k] = Tf[k];
+        dy2[k] = c.dy[k] * c.dy[k];
         // g . (colour behind) + dL/dT_final T_final, maintained incrementally
         gsk[k] = __builtin_fmaf(gT, Tf[k], Tf[k] * (g0[k] * a.cfg.bg0 + g1[k] * a.cfg.bg1 + g2[k] * a.cfg.bg2));
         lane_max = max(lane_max, my_n[k]);
@@ -317,13 +319,10 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
                 any |= on[k];
             }
             if (!__any(any)) continue;
-            float v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-            float v8 = 0.0f;
-            // power2 partials: d/du = -(2 a2 dx + b2 dy + gx), d/dv = -(b2 dx + 2 c2 dy + gy)
-            // (d = pixel - tile centre); d/d(A, B, C) = k (fx^2, 2 fx fy, fy^2) with
-            // (fx, fy) = pixel - projected centre = d + o
-            const float tu = __builtin_fmaf(2.0f * r.p0.w, c.dx, r.p0.y);
-            const float fx = c.dx + r.p3.x;
+            // colour partials, and the pixel moments of dd = alpha dL/dalpha
+            // (zero where alpha is clamped): D = sum dd, Dy = sum dd dy,
+            // Dyy = sum dd dy^2 over the lane's pixels (dx is common to them)
+            float c0s = 0.0f, c1s = 0.0f, c2s = 0.0f, D = 0.0f, Dy = 0.0f, Dyy = 0.0f;
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 const float G = __builtin_amdgcn_exp2f(p2[k]);
@@ -335,30 +334,39 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
                 const float gcol = __builtin_fmaf(g0[k], r.p2.x, __builtin_fmaf(g1[k], r.p2.y, g2[k] * r.p2.z));
                 const float dalpha = __builtin_fmaf(Tb, gcol, -rcp * gsk[k]);
                 const float wgt = on[k] ? alpha * Tb : 0.0f;
-                v[6] = __builtin_fmaf(g0[k], wgt, v[6]);
-                v[7] = __builtin_fmaf(g1[k], wgt, v[7]);
-                v8 = __builtin_fmaf(g2[k], wgt, v8);
+                c0s = __builtin_fmaf(g0[k], wgt, c0s);
+                c1s = __builtin_fmaf(g1[k], wgt, c1s);
+                c2s = __builtin_fmaf(g2[k], wgt, c2s);
                 gsk[k] = __builtin_fmaf(wgt, gcol, gsk[k]);
                 T[k] = on[k] ? Tb : T[k];
-                const bool live = on[k] & !clamped;
-                const float dd = live ? dalpha * alpha : 0.0f;
-                const float fy = c.dy[k] + r.p3.y;
-                const float ddx = dd * fx;
-                v[0] = __builtin_fmaf(dd, __builtin_fmaf(r.p1.x, c.dy[k], tu), v[0]);
-                v[1] = __builtin_fmaf(dd, __builtin_fmaf(2.0f * r.p1.y, c.dy[k], ct.s1), v[1]);
-                v[2] = __builtin_fmaf(ddx, fx, v[2]);
-                v[3] = __builtin_fmaf(ddx, fy, v[3]);
-                v[4] = __builtin_fmaf(dd * fy, fy, v[4]);
-                v[5] = __builtin_fmaf(live ? dalpha : 0.0f, G, v[5]);
+                const float dd = (on[k] & !clamped) ? dalpha * alpha : 0.0f;
+                D += dd;
+                Dy = __builtin_fmaf(dd, c.dy[k], Dy);
+                Dyy = __builtin_fmaf(dd, dy2[k], Dyy);
             }
-            const float s8 = wave_sum8_transposed(v);
-            v8 = wave_sum(v8);
+            // power2 partials per pixel: d/du = -(2 a2 dx + b2 dy + gx),
+            // d/dv = -(b2 dx + 2 c2 dy + gy) (d = pixel - tile centre), and
+            // d/d(A, B, C) = k (fx^2, 2 fx fy, fy^2) with (fx, fy) = d + o the
+            // offset from the projected centre; d alpha / d o = alpha / o
+            const float fx = c.dx + r.p3.x;
+            const float Fy = __builtin_fmaf(r.p3.y, D, Dy);  // sum dd fy
+            float v[9];
+            v[0] = __builtin_fmaf(__builtin_fmaf(2.0f * r.p0.w, c.dx, r.p0.y), D, r.p1.x * Dy);
+            v[1] = __builtin_fmaf(ct.s1, D, 2.0f * r.p1.y * Dy);
+            v[2] = fx * (fx * D);
+            v[3] = fx * Fy;
+            v[4] = __builtin_fmaf(r.p3.y, Fy + Dy, Dyy);
+            v[5] = D;
+            v[6] = c0s;
+            v[7] = c1s;
+            v[8] = c2s;
+            const float s = wave_sum9_transposed(v, lane);
             const uint32_t slot = __float_as_uint(r.p2.w);
-            if ((lane & 7) == 0) {
-                const int f = lane >> 3;
-                atomic_add_f64(&a.grad2d[GSR_G2 * (int64_t)slot + f], (double)(s8 * field_scale(f)));
+            if ((lane & 7) == 0 || lane == 1) {
+                const int f = lane == 1 ? 8 : lane >> 3;
+                const float scale = f == 5 ? r.p3.z : field_scale(f);
+                atomic_add_f64(&a.grad2d[GSR_G2 * (int64_t)slot + f], (double)(s * scale));
             }
-            if (lane == 0) atomic_add_f64(&a.grad2d[GSR_G2 * (int64_t)slot + 8], (double)v8);
         }
         __syncthreads();
         hi_ = lo_;
