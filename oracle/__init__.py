@@ -231,3 +231,6 @@ def sh_basis(deg, direction):
     Y = np.zeros(16)
     lib.or_sh_basis(ctypes.c_int32(deg), _ptr(d), _ptr(Y))
     return Y[: (deg + 1) ** 2]
+
+
+from .track import track_loss, track_view, grad_norm as track_grad_norm, exposure as track_exposure  # noqa: E402

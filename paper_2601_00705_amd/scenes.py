@@ -122,6 +122,28 @@ def upstream_grad(seed, n_values, scale=None):
     return (s * (scale if scale is not None else 1.0 / n_values)).astype(np.float32)
 
 
+def track_inputs(seed, cams):
+    """Inputs of the tracking loss for concatenated views (float32): a render
+    rgb [sum 3 H W] in [0, 1], its final transmittance [sum H W] (a quarter
+    of the pixels empty, T = 1), and an observation [sum 3 H W] that is a
+    brightness-shifted, noisy copy of the render with one flat (textureless)
+    rectangle per view."""
+    rng = np.random.default_rng(seed)
+    rgb, T, target = [], [], []
+    for c in cams:
+        H, W = int(c["height"]), int(c["width"])
+        img = rng.uniform(0.0, 1.0, (3, H, W))
+        t = np.where(rng.uniform(size=(H, W)) < 0.25, 1.0, rng.uniform(0.0, 1.0, (H, W)))
+        obs = 0.85 * img + 0.06 + rng.normal(0.0, 0.05, (3, H, W))
+        y0, x0 = int(rng.integers(0, H)), int(rng.integers(0, W))
+        obs[:, y0:y0 + max(1, H // 3), x0:x0 + max(1, W // 3)] = rng.uniform(0.2, 0.8, (3, 1, 1))
+        rgb.append(img.ravel())
+        T.append(t.ravel())
+        target.append(obs.ravel())
+    return (np.concatenate(rgb).astype(np.float32), np.concatenate(T).astype(np.float32),
+            np.concatenate(target).astype(np.float32))
+
+
 # --------------------------------------------------------------------------
 # textured room: 6 walls + spheres
 
