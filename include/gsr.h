@@ -14,6 +14,9 @@
  *   - gsr_render_fwd: alpha compositing, Eq. (alpha).
  *   - gsr_loss_l1: the gradient seed of the L1 photometric residual,
  *     Eq. (photometric).
+ *   - gsr_loss_track: the tracking loss of the appendix (Tracking and Camera
+ *     Pose Optimization), Eqs. (app-bright), (app-ls), (app-trackloss),
+ *     (app-weight), and its gradient seed for gsr_render_bwd.
  *   - gsr_render_bwd: gradients for colour, opacity, mean, covariance
  *     parameters (the differentiability statement after Eq. (alpha)) and for
  *     the pose twist of Eq. (leftupdate), via Eqs. (muCjac), (muIjac),
@@ -169,6 +172,29 @@ gsr_status gsr_render_fwd(gsr_plan *plan, float *rgb, float *T_final, int32_t *n
  * dL_drgb = sign(rgb - target) / (3 * total pixels), sign(0) = 0. */
 gsr_status gsr_loss_l1(gsr_plan *plan, const float *rgb, const float *target, float *dL_drgb, void *stream);
 
+/* Tracking loss of every view, appendix (Tracking and Camera Pose
+ * Optimization).  With I_hat the render (rgb), I the observation (target),
+ * both [3][H][W] per view, and the sums running over the view's pixels and
+ * channels:
+ *   (g, b) = argmin_{g,b} sum (I - g I_hat - b)^2               Eq. (app-ls)
+ *   loss   = sum_pixels w sum_channels |I - (g I_hat + b)|      Eqs. (app-bright), (app-trackloss)
+ *   w      = clip((1 - T_final) / tau_alpha, 0, 1)
+ *            * clip(||grad I||_2 / tau_grad, 0, 1)              Eq. (app-weight)
+ * ||grad I||_2: Frobenius norm over the channels of the observation's
+ * central differences (one-sided at the border, zero along an axis of
+ * extent 1).  (g, b) is the least-squares solution as a function of the
+ * render; a render without variance takes g = 1, b = mean(I) - mean(I_hat).
+ * Outputs (device): loss [n_views] and exposure [n_views][2] = (g, b) in
+ * double; dL_drgb (like rgb) = d(sum of the losses)/d rgb, including the
+ * dependence of (g, b) on the render (d|r|/dr = 0 at r = 0); dL_dT (like
+ * T_final, may be NULL) = the gradient through the opacity weight (the
+ * clip's derivative taken as 0 outside the open interval (0, 1)).  Both feed
+ * gsr_render_bwd.  tau_alpha, tau_grad: positive and finite, else
+ * GSR_EINVAL.  Uses the plan's workspace; deterministic (fixed-order sums). */
+gsr_status gsr_loss_track(gsr_plan *plan, const float *rgb, const float *T_final, const float *target,
+                          double tau_alpha, double tau_grad, double *loss, double *exposure, float *dL_drgb,
+                          float *dL_dT, void *stream);
+
 /* Backward of gsr_render_fwd (call after it, on the same plan, without an
  * intervening gsr_project or gsr_bin).  T_final and n_contrib are the buffers
  * the forward wrote (read only).  dL_dT may be NULL (zero).  pose_only: HOST array
@@ -212,6 +238,7 @@ typedef enum {
     GSR_T_CLEAR_GRAD2D, /* zeroing of the screen-space gradient accumulators */
     GSR_T_RASTER_BWD,   /* compositing backward kernel */
     GSR_T_PROJECT_BWD,  /* projection backward and the pose reduction */
+    GSR_T_LOSS_TRACK,   /* gsr_loss_track's kernels */
     GSR_T_COUNT
 } gsr_timer;
 

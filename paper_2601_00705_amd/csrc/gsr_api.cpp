@@ -47,7 +47,7 @@ struct gsr_plan {
     size_t off_counters = 0, off_views = 0, off_geom = 0, off_conic = 0, off_rgbd = 0, off_qthr = 0, off_grad2d = 0;
     size_t off_stage = 0;
     size_t off_keys = 0, off_vals = 0, off_seg = 0, off_ranges = 0, off_cnt = 0;
-    size_t off_xip = 0, off_order = 0, off_buckets = 0, total = 0;
+    size_t off_xip = 0, off_order = 0, off_buckets = 0, off_track = 0, total = 0;
     char* ws = nullptr;
     Counters host_counters{};
     std::vector<uint32_t> identity_order;
@@ -244,6 +244,7 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->off_buckets = take(sizeof(uint32_t) * 64);
     p->off_cnt = take(sizeof(uint32_t) * (size_t)p->chunks * (size_t)tiles);
     p->off_xip = take(sizeof(double) * 6 * (size_t)n_views * p->bwd_blocks);
+    p->off_track = take(sizeof(double) * GSR_TRACK_SLOTS * GSR_TRACK_BLOCKS * (size_t)n_views);
     p->total = o;
     p->host_counters = Counters{};
     p->host_counters.capacity = (unsigned long long)pair_capacity;
@@ -471,6 +472,34 @@ extern "C" gsr_status gsr_loss_l1(gsr_plan* plan, const float* rgb, const float*
     Timed t(plan, GSR_T_LOSS_L1, (hipStream_t)stream);
     hipError_t e = launch_loss_l1(a, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_loss_l1");
+}
+
+extern "C" gsr_status gsr_loss_track(gsr_plan* plan, const float* rgb, const float* T_final, const float* target,
+                                     double tau_alpha, double tau_grad, double* loss, double* exposure,
+                                     float* dL_drgb, float* dL_dT, void* stream)
+{
+    g_err.clear();
+    if (!plan) return fail(GSR_EINVAL, "null plan");
+    if (!rgb || !T_final || !target || !loss || !exposure || !dL_drgb) return fail(GSR_EINVAL, "null buffer");
+    if (!(tau_alpha > 0.0) || !(tau_grad > 0.0) || !std::isfinite(tau_alpha) || !std::isfinite(tau_grad))
+        return fail(GSR_EINVAL, "tau_alpha and tau_grad must be positive and finite");
+    gsr_status st = check_bound(plan);
+    if (st != GSR_OK) return st;
+    TrackArgs a{};
+    a.views = at<ViewTable>(plan, plan->off_views);
+    a.rgb = rgb;
+    a.T_final = T_final;
+    a.target = target;
+    a.tau_alpha = tau_alpha;
+    a.tau_grad = tau_grad;
+    a.part = at<double>(plan, plan->off_track);
+    a.loss = loss;
+    a.exposure = exposure;
+    a.dL_drgb = dL_drgb;
+    a.dL_dT = dL_dT;
+    Timed t(plan, GSR_T_LOSS_TRACK, (hipStream_t)stream);
+    hipError_t e = launch_loss_track(a, plan->V, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_loss_track");
 }
 
 extern "C" gsr_status gsr_raster_bwd(gsr_plan* plan, const float* T_final, const int32_t* n_contrib,

@@ -98,6 +98,21 @@ struct LossArgs {
     float scale;        // 1 / count
 };
 
+struct TrackArgs {
+    const ViewTable* views;
+    const float* rgb;          // render [3][H][W] per view, concatenated
+    const float* T_final;      // [H][W] per view
+    const float* target;       // observation, like rgb
+    double tau_alpha, tau_grad;
+    double* part;              // [views][GSR_TRACK_BLOCKS][GSR_TRACK_SLOTS] partial sums
+    double* loss;              // [views]
+    double* exposure;          // [views][2]: g, b
+    float* dL_drgb;            // like rgb
+    float* dL_dT;              // like T_final, nullable
+};
+
+#define GSR_TRACK_BLOCKS 64         // blocks per view of the tracking-loss kernels
+#define GSR_TRACK_SLOTS 8           // partial sums per block (4 exposure sums, 3 loss/sign sums)
 #define GSR_BIN_CHUNK 256           // Gaussians staged in LDS at a time by the binning blocks (x256)
 #define GSR_BIN_LDS_TILES 16384     // views with more tiles count and place with global atomics
 #define GSR_SEG_THREADS 512
@@ -115,5 +130,6 @@ hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, 
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, float* d_xi, int n_views,
                               hipStream_t s);
 hipError_t launch_loss_l1(const LossArgs& a, hipStream_t s);
+hipError_t launch_loss_track(const TrackArgs& a, int n_views, hipStream_t s);
 
 }  // namespace gsr

@@ -77,6 +77,7 @@ def _load():
         "gsr_bin": (st, [P, P]),
         "gsr_render_fwd": (st, [P, P, P, P, P, P]),
         "gsr_loss_l1": (st, [P, P, P, P, P]),
+        "gsr_loss_track": (st, [P, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P, P, P]),
         "gsr_render_bwd": (st, [P, P, P, P, P, P, P, P, P, P, P]),
         "gsr_raster_bwd": (st, [P, P, P, P, P, P]),
         "gsr_project_bwd": (st, [P, P, P, P, P, P, P]),
@@ -96,12 +97,12 @@ def _load():
 _lib = _load()
 EXPORTS = ("gsr_plan_create", "gsr_plan_destroy", "gsr_plan_workspace_bytes", "gsr_plan_bind",
            "gsr_plan_layout", "gsr_plan_get_info", "gsr_project", "gsr_bin", "gsr_render_fwd",
-           "gsr_loss_l1", "gsr_render_bwd", "gsr_raster_bwd", "gsr_project_bwd", "gsr_pair_count",
+           "gsr_loss_l1", "gsr_loss_track", "gsr_render_bwd", "gsr_raster_bwd", "gsr_project_bwd", "gsr_pair_count",
            "gsr_plan_set_timing", "gsr_plan_read_timing", "gsr_status_str", "gsr_last_error")
 
 # launch groups of gsr_plan_read_timing (gsr_timer)
 TIMERS = ("project", "bin_emit", "bin_sort", "bin_ranges", "raster_fwd", "loss_l1", "clear_grad2d",
-          "raster_bwd", "project_bwd")
+          "raster_bwd", "project_bwd", "loss_track")
 
 
 def raw():
@@ -193,6 +194,12 @@ def gsr_render_fwd(plan, rgb, T_final, n_contrib, n_blend, stream):
 def gsr_loss_l1(plan, rgb, target, dL_drgb, stream):
     return check(_lib.gsr_loss_l1(plan, _p(rgb), _p(target), _p(dL_drgb), ctypes.c_void_p(stream)),
                  "gsr_loss_l1")
+
+
+def gsr_loss_track(plan, rgb, T_final, target, tau_alpha, tau_grad, loss, exposure, dL_drgb, dL_dT, stream):
+    return check(_lib.gsr_loss_track(plan, _p(rgb), _p(T_final), _p(target), ctypes.c_double(tau_alpha),
+                                     ctypes.c_double(tau_grad), _p(loss), _p(exposure), _p(dL_drgb), _p(dL_dT),
+                                     ctypes.c_void_p(stream)), "gsr_loss_track")
 
 
 def gsr_render_bwd(plan, g: Gaussians, poses, T_final, n_contrib, dL_drgb, dL_dT, pose_only, grads, d_xi,

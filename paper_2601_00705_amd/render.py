@@ -119,6 +119,12 @@ class Renderer:
     def loss_l1(self, rgb, target, dL_drgb):
         lib.gsr_loss_l1(self.plan, rgb, target, dL_drgb, _stream(self.device))
 
+    def loss_track(self, rgb, T_final, target, tau_alpha, tau_grad, loss, exposure, dL_drgb, dL_dT=None):
+        """Tracking loss per view (loss [V] and exposure [V][2] float64) and
+        its gradient seed dL_drgb / dL_dT for render_bwd."""
+        lib.gsr_loss_track(self.plan, rgb, T_final, target, tau_alpha, tau_grad, loss, exposure, dL_drgb, dL_dT,
+                           _stream(self.device))
+
     def render_bwd(self, params, poses, T_final, n_contrib, dL_drgb, dL_dT=None, pose_only=None, grads=None,
                    d_xi=None):
         g = None if grads is None else lib.Grads(*(lib._p(grads[k]) for k in PARAM_KEYS))

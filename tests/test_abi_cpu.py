@@ -90,3 +90,19 @@ def test_timing_switch_without_device_work():
         lib.gsr_plan_set_timing(plan, False)
     finally:
         lib.gsr_plan_destroy(plan)
+
+
+def test_track_loss_argument_errors():
+    """gsr_loss_track rejects non-positive or non-finite thresholds and null
+    buffers before touching the device (the pointers are never read)."""
+    from paper_2601_00705_amd import lib
+    raw = lib.raw()
+    plan = lib.gsr_plan_create(100, CAM, _cfg(), 10000)
+    fake = ctypes.c_void_p(16)
+    try:
+        for ta, tg in ((0.0, 0.1), (0.5, -1.0), (float("nan"), 0.1), (0.5, float("inf"))):
+            assert raw.gsr_loss_track(plan, fake, fake, fake, ta, tg, fake, fake, fake, None, None) == lib.EINVAL
+        assert raw.gsr_loss_track(plan, None, fake, fake, 0.5, 0.1, fake, fake, fake, None, None) == lib.EINVAL
+        assert raw.gsr_loss_track(None, fake, fake, fake, 0.5, 0.1, fake, fake, fake, None, None) == lib.EINVAL
+    finally:
+        lib.gsr_plan_destroy(plan)
