@@ -44,6 +44,15 @@ VALU_PEAK_TSLOTS = 256 * 4 * 16 * 2.4e9 / 1e12
 #     weight, T and dd (3) = 25 operations + exp2 + rcp
 SLOTS_FWD_PER_EVAL = 13 + 4
 SLOTS_BWD_PER_EVAL = 25 + 4 + 4
+# Tracking loss: weight thresholds (the paper gives none; accumulated opacity
+# saturates the weight from 0.5, an observed gradient norm from 0.05 per
+# pixel), and its algorithmic HBM bytes per pixel over its three passes: the
+# exposure sums read render and observation (24 B); the sign sums read them
+# and T_final (28 B); the gradient reads the same and writes dL/drgb and
+# dL/dT_final (28 + 16 B)
+TRACK_TAU_ALPHA = 0.5
+TRACK_TAU_GRAD = 0.05
+BYTES_TRACK_PER_PIXEL = 24 + 28 + 28 + 16
 # Algorithmic HBM bytes of one sort pass per pair: key + value read and written
 BYTES_SORT_PASS_PER_PAIR = 2 * (8 + 4)
 # Projection backward: per live slot the geom record and the nine FP64
@@ -73,6 +82,8 @@ def parse():
     ap.add_argument("--tile", type=str, default=None, help="WxH[/batch] (default: autotuned)")
     ap.add_argument("--autotune", action="store_true", help="re-run the tile/batch autotuner")
     ap.add_argument("--copy-probe", action="store_true", help="run a plain device copy of known size first")
+    ap.add_argument("--loss", choices=("l1", "track"), default="l1",
+                    help="gradient seed of the step: L1 (default) or the tracking loss")
     return ap.parse_args()
 
 
@@ -99,14 +110,18 @@ def target_images(w, params_d, poses_d, cfg, Renderer, torch):
 class Step:
     """Buffers and the C-ABI call sequence of one step for one plan."""
 
-    def __init__(self, R, params, poses, target, pose_only, torch):
+    def __init__(self, R, params, poses, target, pose_only, torch, loss="l1"):
         self.R, self.params, self.poses, self.target, self.pose_only = R, params, poses, target, pose_only
+        self.loss = loss
         P = R.total_pixels
         dev = poses.device
         self.rgb = torch.empty(3 * P, device=dev)
         self.T = torch.empty(P, device=dev)
         self.nc = torch.empty(P, dtype=torch.int32, device=dev)
         self.dL = torch.empty(3 * P, device=dev)
+        self.dT = torch.empty(P, device=dev)
+        self.loss_v = torch.empty(len(R.cams), dtype=torch.float64, device=dev)
+        self.expo = torch.empty(len(R.cams), 2, dtype=torch.float64, device=dev)
         self.grads = {k: torch.empty_like(v) for k, v in params.items()}
         self.d_xi = torch.empty(len(R.cams), 6, device=dev)
 
@@ -116,10 +131,20 @@ class Step:
             ("project", lambda: R.project(self.params, self.poses)),
             ("bin", lambda: R.bin()),
             ("raster_fwd", lambda: R.render_fwd(self.rgb, self.T, self.nc)),
-            ("loss_l1", lambda: R.loss_l1(self.rgb, self.target, self.dL)),
-            ("raster_bwd", lambda: R.raster_bwd(self.T, self.nc, self.dL)),
+            ("loss", self.seed),
+            ("raster_bwd", lambda: R.raster_bwd(self.T, self.nc, self.dL, self.dT if self.loss == "track" else None)),
             ("project_bwd", lambda: R.project_bwd(self.params, self.poses, self.pose_only, self.grads, self.d_xi)),
         ]
+
+    def seed(self):
+        if self.loss == "track":
+            self.track()
+        else:
+            self.R.loss_l1(self.rgb, self.target, self.dL)
+
+    def track(self):
+        self.R.loss_track(self.rgb, self.T, self.target, TRACK_TAU_ALPHA, TRACK_TAU_GRAD, self.loss_v, self.expo,
+                          self.dL, self.dT)
 
     def run(self):
         for _, f in self.stages():
@@ -238,7 +263,7 @@ def main():
 
     # ---------------- batched: one plan, one graph --------------------
     R, need = sized_renderer(Renderer, n, cams, cfg, params, poses, torch)
-    st = Step(R, params, poses, target, pose_only, torch)
+    st = Step(R, params, poses, target, pose_only, torch, loss=args.loss)
     for _ in range(2):
         st.run()
     torch.cuda.synchronize()
@@ -281,16 +306,31 @@ def main():
         st.run()
     timing = R.read_timing()
     R.set_timing(False)
-    kernel_ms = {g: (ms / cnt if cnt else 0.0) for g, (ms, cnt) in timing.items()}
+    kernel_ms = {g: ms / cnt for g, (ms, cnt) in timing.items() if cnt}
+    loss_group = "loss_track" if args.loss == "track" else "loss_l1"
     stage_ms = {
         "project": kernel_ms["project"],
         "bin": kernel_ms["bin_emit"] + kernel_ms["bin_sort"] + kernel_ms["bin_ranges"],
         "raster_fwd": kernel_ms["raster_fwd"],
-        "loss_l1": kernel_ms["loss_l1"],
+        loss_group: kernel_ms[loss_group],
         "raster_bwd": kernel_ms["clear_grad2d"] + kernel_ms["raster_bwd"],
         "project_bwd": kernel_ms["project_bwd"],
     }
     log("kernel ms: " + ", ".join(f"{k}={v:.3f}" for k, v in kernel_ms.items()))
+
+    # ---------------- tracking loss: its three kernels, eager, HBM bound -----
+    R.set_timing(True)
+    for _ in range(K):
+        st.track()
+    t_ms, t_cnt = R.read_timing()["loss_track"]
+    R.set_timing(False)
+    t_ms /= max(t_cnt, 1)
+    t_bytes = BYTES_TRACK_PER_PIXEL * total_px
+    track = {"ms": t_ms, "bound": "hbm", "achieved": t_bytes / (t_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "work": f"{BYTES_TRACK_PER_PIXEL} B x {total_px} px",
+             "tau_alpha": TRACK_TAU_ALPHA, "tau_grad": TRACK_TAU_GRAD}
+    track["frac"] = track["achieved"] / track["peak"]
+    log(f"tracking loss: {t_ms:.4f} ms, {track['achieved']:.0f} GB/s ({track['frac']:.2f} of HBM)")
 
     # ---------------- blends / evaluations (untimed counting pass) -----
     nb = torch.empty(total_px, dtype=torch.int32, device=dev)
@@ -311,7 +351,7 @@ def main():
             hw = cams[v]["width"] * cams[v]["height"]
             Rv, _ = sized_renderer(Renderer, n, [cams[v]], cfg, params, poses[v:v + 1], torch)
             steps_plain.append(Step(Rv, params, poses[v:v + 1].contiguous(), target[3 * off:3 * (off + hw)],
-                                    [pose_only[v]], torch))
+                                    [pose_only[v]], torch, loss=args.loss))
             off += hw
         for _ in range(2):
             for s in steps_plain:
@@ -381,7 +421,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "gaussians": n, "views": V, "pixels": total_px,
                    "tile": f"{cfg.tile_w}x{cfg.tile_h}", "batch": cfg.batch, "sh_degree": cfg.sh_degree,
-                   "mode": "batched-graph"},
+                   "mode": "batched-graph", "loss": args.loss},
         "autotune_ms": None if tuned is None else tuned["ms"],
         "ms_per_step_p10_p50_p90": [pct[10], pct[50], pct[90]],
         "blends_per_s": blends / (ms_step * 1e-3),
@@ -394,6 +434,7 @@ def main():
         "stage_ms": stage_ms,
         "kernel_ms": kernel_ms,
         "roofline": roof,
+        "tracking_loss": track,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -111,7 +111,7 @@ struct TrackArgs {
     float* dL_dT;              // like T_final, nullable
 };
 
-#define GSR_TRACK_BLOCKS 64         // blocks per view of the tracking-loss kernels
+#define GSR_TRACK_BLOCKS 256        // blocks per view of the tracking-loss kernels
 #define GSR_TRACK_SLOTS 8           // partial sums per block (4 exposure sums, 3 loss/sign sums)
 #define GSR_BIN_CHUNK 256           // Gaussians staged in LDS at a time by the binning blocks (x256)
 #define GSR_BIN_LDS_TILES 16384     // views with more tiles count and place with global atomics

@@ -60,7 +60,8 @@ __device__ __forceinline__ void block_sum(double (&v)[K], double (*lds)[GSR_TRAC
 }
 
 // the sums of the view's partial slots [first, first + K) over its blocks,
-// in a fixed order: one wave adds one slot per lane, then a shuffle tree
+// in a fixed order: lane j of one wave adds the slots of blocks j, j + 64,
+// ..., then a shuffle tree
 template <int K>
 __device__ __forceinline__ void view_totals(const double* part, int v, int first, double (&tot)[K],
                                             double (*lds)[GSR_TRACK_THREADS / 64])
@@ -114,8 +115,8 @@ __device__ __forceinline__ Exposure exposure_of(const double (&s)[4], double N)
 // the observation's gradient norm at (x, y) of a [3][H][W] image
 __device__ __forceinline__ double grad_norm_at(const float* img, int W, int H, int x, int y)
 {
-    const int64_t plane = (int64_t)W * H;
-    const int64_t at = (int64_t)y * W + x;
+    const int plane = W * H;
+    const int at = y * W + x;
     const int xl = x > 0 ? x - 1 : x, xr = x < W - 1 ? x + 1 : x;
     const int yu = y > 0 ? y - 1 : y, yd = y < H - 1 ? y + 1 : y;
     const double hx = (xr - xl) == 2 ? 0.5 : 1.0, hy = (yd - yu) == 2 ? 0.5 : 1.0;
@@ -124,7 +125,7 @@ __device__ __forceinline__ double grad_norm_at(const float* img, int W, int H, i
     for (int c = 0; c < 3; ++c) {
         const float* p = img + c * plane;
         const double gx = W > 1 ? ((double)p[at - x + xr] - (double)p[at - x + xl]) * hx : 0.0;
-        const double gy = H > 1 ? ((double)p[(int64_t)yd * W + x] - (double)p[(int64_t)yu * W + x]) * hy : 0.0;
+        const double gy = H > 1 ? ((double)p[yd * W + x] - (double)p[yu * W + x]) * hy : 0.0;
         s += gx * gx + gy * gy;
     }
     return sqrt(s);
@@ -143,8 +144,8 @@ __global__ __launch_bounds__(GSR_TRACK_THREADS) void k_track_sums(TrackArgs a)
     const float* Ih = a.rgb + 3 * (int64_t)vw.pix_base;
     const float* I = a.target + 3 * (int64_t)vw.pix_base;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t i = (int64_t)blockIdx.x * GSR_TRACK_THREADS + threadIdx.x; i < hw;
-         i += (int64_t)GSR_TRACK_BLOCKS * GSR_TRACK_THREADS) {
+    for (int i = (int)blockIdx.x * GSR_TRACK_THREADS + (int)threadIdx.x; i < (int)hw;
+         i += GSR_TRACK_BLOCKS * GSR_TRACK_THREADS) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double x = Ih[c * hw + i], y = I[c * hw + i];
@@ -173,9 +174,9 @@ __global__ __launch_bounds__(GSR_TRACK_THREADS) void k_track_signs(TrackArgs a)
     const float* I = a.target + 3 * (int64_t)vw.pix_base;
     const float* T = a.T_final + vw.pix_base;
     double q[3] = {0.0, 0.0, 0.0};  // sum w |r|, sum w s, sum w s I_hat
-    for (int64_t i = (int64_t)blockIdx.x * GSR_TRACK_THREADS + threadIdx.x; i < hw;
-         i += (int64_t)GSR_TRACK_BLOCKS * GSR_TRACK_THREADS) {
-        const int y = (int)(i / W), x = (int)(i - (int64_t)y * W);
+    for (int i = (int)blockIdx.x * GSR_TRACK_THREADS + (int)threadIdx.x; i < (int)hw;
+         i += GSR_TRACK_BLOCKS * GSR_TRACK_THREADS) {
+        const int y = i / W, x = i - y * W;
         const double w = clip01((1.0 - (double)T[i]) / a.tau_alpha) *
                          clip01(grad_norm_at(I, W, H, x, y) / a.tau_grad);
 #pragma unroll
@@ -219,9 +220,9 @@ __global__ __launch_bounds__(GSR_TRACK_THREADS) void k_track_grad(TrackArgs a)
     const float* T = a.T_final + vw.pix_base;
     float* dI = a.dL_drgb + 3 * (int64_t)vw.pix_base;
     float* dT = a.dL_dT ? a.dL_dT + vw.pix_base : nullptr;
-    for (int64_t i = (int64_t)blockIdx.x * GSR_TRACK_THREADS + threadIdx.x; i < hw;
-         i += (int64_t)GSR_TRACK_BLOCKS * GSR_TRACK_THREADS) {
-        const int y = (int)(i / W), x = (int)(i - (int64_t)y * W);
+    for (int i = (int)blockIdx.x * GSR_TRACK_THREADS + (int)threadIdx.x; i < (int)hw;
+         i += GSR_TRACK_BLOCKS * GSR_TRACK_THREADS) {
+        const int y = i / W, x = i - y * W;
         const double za = (1.0 - (double)T[i]) / a.tau_alpha;
         const double wg = clip01(grad_norm_at(I, W, H, x, y) / a.tau_grad);
         const double w = clip01(za) * wg;
