@@ -331,6 +331,53 @@ def _bilinear(img, x, y):
             img[:, y1, x0] * (1 - fx) * fy + img[:, y1, x1] * fx * fy)
 
 
+def seed_inputs(seed, n_points, n_views=5, width=160, height=120, f=100.0, noise_px=0.5, outlier_frac=0.1):
+    """Inputs of the one-shot seeding for one reference keyframe (view 0) and
+    n_views - 1 neighbours: a keyframe path looking at the +z wall of the
+    analytic room (baselines ~ U[5, 15] cm, +-5 deg jitter), the keyframe
+    images, a per-view exposure (g, b) ~ (U[0.9, 1.1], U[-0.05, 0.05]) applied
+    to the neighbours' images (the reference keeps (1, 0)), and per reference
+    pixel: its position, the raycast point seen there, and per neighbour the
+    point's projection perturbed by N(0, noise_px^2) (for outlier_frac of the
+    matches a uniform pixel instead) with a confidence ~ U[0.6, 1] for
+    inliers and U[0, 0.4] for outliers.  No triangulation happens here."""
+    rng = np.random.default_rng(seed)
+    cam = camera(width, height, f)
+    poses, centre = [], np.array([-0.3, 0.0, 0.0])
+    for k in range(n_views):
+        if k:
+            step = rng.normal(size=3)
+            step[2] *= 0.2
+            centre = centre + step / np.linalg.norm(step) * rng.uniform(0.05, 0.15)
+        yaw, pitch = np.radians(rng.uniform(-5, 5)), np.radians(rng.uniform(-5, 5))
+        poses.append(pose_from_centre(centre, yaw, pitch))
+    centres = np.stack([-(p[:9].reshape(3, 3).T @ p[9:]) for p in poses])
+    spheres = _spheres(rng, 20, list(centres))
+    expo = np.stack([[1.0, 0.0]] + [[rng.uniform(0.9, 1.1), rng.uniform(-0.05, 0.05)] for _ in range(n_views - 1)])
+    images = [(expo[v, 0] * raycast_image(p, cam, spheres) + expo[v, 1]).astype(np.float32)
+              for v, p in enumerate(poses)]
+    Ps = np.stack([_projection_matrix(p, cam) for p in poses])
+    px = rng.uniform(0, width, n_points)
+    py = rng.uniform(0, height, n_points)
+    oc, d = _pixel_rays(poses[0], cam, px, py)
+    X, _ = raycast(oc, d, spheres)
+    K = n_views - 1
+    xn = np.zeros((K, 2, n_points))
+    kappa = np.zeros((K, n_points))
+    for k in range(K):
+        x2, _ = _project_pts(poses[1 + k], cam, X)
+        x2 = x2 + rng.normal(0, noise_px, size=x2.shape)
+        out = rng.uniform(size=n_points) < outlier_frac
+        x2[0, out] = rng.uniform(0, width, out.sum())
+        x2[1, out] = rng.uniform(0, height, out.sum())
+        xn[k] = x2
+        kappa[k] = np.where(out, rng.uniform(0.0, 0.4, n_points), rng.uniform(0.6, 1.0, n_points))
+    xr = np.stack([px, py]) + rng.normal(0, noise_px, size=(2, n_points))
+    return {"cams": [dict(cam) for _ in range(n_views)], "poses": np.stack(poses), "Ps": Ps, "centres": centres,
+            "images": images, "expo": expo, "X_true": X, "xr": xr.astype(np.float32),
+            "xn": xn.astype(np.float32), "kappa": kappa.astype(np.float32)}
+
+
 def seeded_keyframes(seed, n_target, n_views=5, width=1200, height=680, f=600.0,
                      noise_px=0.5, outlier_frac=0.1, max_reproj=2.0, batch=200_000):
     """Gaussians triangulated from synthetic dense correspondences across a
