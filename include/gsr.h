@@ -17,6 +17,11 @@
  *   - gsr_loss_track: the tracking loss of the appendix (Tracking and Camera
  *     Pose Optimization), Eqs. (app-bright), (app-ls), (app-trackloss),
  *     (app-weight), and its gradient seed for gsr_render_bwd.
+ *   - gsr_seed_triangulate, gsr_seed_scale: the one-shot Gaussian seeding of
+ *     Sec. "Dense Feature Matching" (Eq. (conf), two-view linear
+ *     triangulation) and the appendix's initialisation (Eq.
+ *     (app-alpha-init), colour median), producing Gaussians in the layout
+ *     gsr_project reads.
  *   - gsr_render_bwd: gradients for colour, opacity, mean, covariance
  *     parameters (the differentiability statement after Eq. (alpha)) and for
  *     the pose twist of Eq. (leftupdate), via Eqs. (muCjac), (muIjac),
@@ -214,6 +219,66 @@ gsr_status gsr_raster_bwd(gsr_plan *plan, const float *T_final, const int32_t *n
                           const float *dL_dT, void *stream);
 gsr_status gsr_project_bwd(gsr_plan *plan, const gsr_gaussians *g, const float *poses, const uint8_t *pose_only,
                            gsr_grads *grads, float *d_xi, void *stream);
+
+/* ---- one-shot seeding (independent of any plan) ---------------------- */
+
+#define GSR_SEED_MAX_NEIGHBOURS 8
+
+/* One keyframe of a seeding call (host struct; image is a device pointer). */
+typedef struct {
+    double P[12];          /* 3x4 projection matrix K [R | t], row-major; pixel
+                              positions with pixel centres at +1/2 */
+    double centre[3];      /* camera centre, world coordinates */
+    int32_t width, height; /* image size */
+    const float *image;    /* device [3][height][width]: the observed keyframe */
+    double gain, bias;     /* its exposure (observed = gain * radiance + bias) */
+} gsr_seed_view;
+
+typedef struct {
+    double max_reproj;     /* px; a kept point's reprojection error is below it */
+    double min_parallax;   /* radians; a kept point's baseline angle is at least it */
+    double alpha_lo, alpha_hi; /* Eq. (app-alpha-init) bounds, 0 < lo <= hi < 1 */
+} gsr_seed_config;
+
+/* Seeds one Gaussian candidate per reference pixel of keyframe views[0] from
+ * its correspondences in the n_neighbours keyframes views[1..] (Sec. "Dense
+ * Feature Matching", Multi-view Triangulation, and the appendix's
+ * initialisation).  For every neighbour the two-view linear system
+ * (rows x P^3 - P^1, y P^3 - P^2 of both views) is solved in double for the
+ * right singular vector of its smallest singular value; the hypothesis with
+ * the lowest reprojection error (RMS of the two reprojection distances, in
+ * front of both cameras) is kept, ties going to the larger baseline angle
+ * (the angle at X between the rays to both camera centres).  It is valid
+ * when that error is below max_reproj and the angle at least min_parallax.
+ * Inputs (device): x_ref [2][n] reference pixel positions, x_nb [K][2][n]
+ * matched positions, kappa [K][n] per-neighbour confidences in [0, 1].
+ * Outputs (device): mean [3][n] (the kept hypothesis, also for an invalid
+ * one; 0 if there is none), colour [3][n] (median over the supporting views
+ * -- the reference and every neighbour whose match lies within max_reproj of
+ * the point's projection -- of the bilinear samples corrected by
+ * (sample - bias) / gain; the mean of the middle two for an even count; 0
+ * when invalid), opacity_logit [n] (logit of alpha_lo + (alpha_hi -
+ * alpha_lo) kappa_bar, Eq. (app-alpha-init)), valid [n] (0/1); optional
+ * (NULL allowed): best [n] (neighbour index or -1), err [n] (px, +inf if no
+ * hypothesis), angle [n] (radians), kappa_bar [n] (Eq. (conf), the mean of
+ * kappa over the neighbours).  n < 2^31, 1 <= n_neighbours <=
+ * GSR_SEED_MAX_NEIGHBOURS; bad arguments give GSR_EINVAL. */
+gsr_status gsr_seed_triangulate(int64_t n, int32_t n_neighbours, const gsr_seed_view *views,
+                                const gsr_seed_config *cfg, const float *x_ref, const float *x_nb,
+                                const float *kappa, float *mean, float *colour, float *opacity_logit,
+                                int32_t *valid, int32_t *best, float *err, float *angle, float *kappa_bar,
+                                void *stream);
+
+/* Isotropic initial scale of the valid seeds: log_scale [3][n] (device) =
+ * log(max(d, floor_scale)) on every axis, d the mean distance to the 3
+ * nearest other valid seeds (all of them when fewer exist; floor_scale when
+ * none); 0 for invalid seeds.  mean [3][n], valid [n] as written by
+ * gsr_seed_triangulate.  workspace: caller-owned device memory of
+ * gsr_seed_scale_workspace_bytes(n) bytes (0 for n out of range), reused
+ * freely between calls; calls that share it must be ordered. */
+size_t gsr_seed_scale_workspace_bytes(int64_t n);
+gsr_status gsr_seed_scale(int64_t n, const float *mean, const int32_t *valid, float floor_scale, void *workspace,
+                          size_t workspace_bytes, float *log_scale, void *stream);
 
 /* Synchronises `stream`, then reports the pair count of the last binning
  * and whether it exceeded the capacity. */

@@ -24,7 +24,8 @@ Readings where the paper is silent:
     homogeneous coordinate is no candidate;
   - the baseline angle is the angle at X between the rays to the two camera
     centres; a kept point needs error < max_reproj and angle >= min_parallax
-    (the rejection is applied to the selected hypothesis);
+    (the rejection is applied to the selected hypothesis), and a position
+    representable in float32 (the Gaussian layout);
   - supporting views: the reference view and every neighbour whose matched
     pixel lies within max_reproj of the kept point's projection;
   - a sample is bilinear between pixel centres (pixel (i, j) holds the value
@@ -107,7 +108,7 @@ def seed_point(Ps, centres, images, expo, xr, xn, kappa, max_reproj, min_paralla
         return out
     err, ang, k, X = best
     out.update(best=k, err=err, angle=ang, mean=X)
-    if not (err < max_reproj and ang >= min_parallax):
+    if not (err < max_reproj and ang >= min_parallax and np.all(np.isfinite(X.astype(np.float32)))):
         return out
     out["valid"] = True
     samples = []

@@ -654,3 +654,121 @@ extern "C" const char* gsr_status_str(gsr_status s)
 }
 
 extern "C" const char* gsr_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// one-shot seeding
+
+extern "C" gsr_status gsr_seed_triangulate(int64_t n, int32_t n_neighbours, const gsr_seed_view* views,
+                                           const gsr_seed_config* cfg, const float* x_ref, const float* x_nb,
+                                           const float* kappa, float* mean, float* colour, float* opacity_logit,
+                                           int32_t* valid, int32_t* best, float* err, float* angle, float* kappa_bar,
+                                           void* stream)
+{
+    g_err.clear();
+    if (n < 0 || n >= (1ll << 31)) return fail(GSR_EINVAL, "n out of range");
+    if (n_neighbours < 1 || n_neighbours > GSR_SEED_MAX_NEIGHBOURS) return fail(GSR_EINVAL, "n_neighbours out of range");
+    if (!views || !cfg) return fail(GSR_EINVAL, "null views or config");
+    if (!(cfg->max_reproj > 0.0) || !(cfg->min_parallax >= 0.0) || !(cfg->alpha_lo > 0.0) ||
+        !(cfg->alpha_lo <= cfg->alpha_hi) || !(cfg->alpha_hi < 1.0))
+        return fail(GSR_EINVAL, "config: need max_reproj > 0, min_parallax >= 0, 0 < alpha_lo <= alpha_hi < 1");
+    SeedArgs a{};
+    for (int v = 0; v <= n_neighbours; ++v) {
+        const gsr_seed_view& s = views[v];
+        if (s.width < 1 || s.height < 1 || !s.image) return fail(GSR_EINVAL, "view without an image");
+        if (!(s.gain != 0.0) || !std::isfinite(s.gain) || !std::isfinite(s.bias))
+            return fail(GSR_EINVAL, "view exposure: gain must be finite and non-zero");
+        SeedView& d = a.views[v];
+        for (int k = 0; k < 12; ++k) d.P[k] = s.P[k];
+        for (int k = 0; k < 3; ++k) d.centre[k] = s.centre[k];
+        d.width = s.width;
+        d.height = s.height;
+        d.image = s.image;
+        d.gain = s.gain;
+        d.bias = s.bias;
+    }
+    if (n == 0) return GSR_OK;
+    if (!x_ref || !x_nb || !kappa || !mean || !colour || !opacity_logit || !valid)
+        return fail(GSR_EINVAL, "null buffer");
+    a.n = n;
+    a.K = n_neighbours;
+    a.max_reproj = cfg->max_reproj;
+    a.min_parallax = cfg->min_parallax;
+    a.alpha_lo = cfg->alpha_lo;
+    a.alpha_hi = cfg->alpha_hi;
+    a.x_ref = x_ref;
+    a.x_nb = x_nb;
+    a.kappa = kappa;
+    a.mean = mean;
+    a.colour = colour;
+    a.opacity_logit = opacity_logit;
+    a.valid = valid;
+    a.best = best;
+    a.err = err;
+    a.angle = angle;
+    a.kappa_bar = kappa_bar;
+    hipError_t e = launch_seed_triangulate(a, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_seed_triangulate");
+}
+
+namespace {
+struct KnnLayout {
+    size_t bpart, grid, cell_count, cell_start, cell_of, rank, sorted, total;
+    int64_t max_cells;
+};
+
+KnnLayout knn_layout(int64_t n)
+{
+    KnnLayout L{};
+    L.max_cells = 4 * n + 64;
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + (bytes ? bytes : 1));
+        return at;
+    };
+    L.bpart = take(sizeof(float) * 8 * GSR_KNN_BLOCKS);
+    L.grid = take(sizeof(KnnGrid));
+    L.cell_count = take(sizeof(uint32_t) * (size_t)(L.max_cells + 1));
+    L.cell_start = take(sizeof(uint32_t) * (size_t)(L.max_cells + 1));
+    L.cell_of = take(sizeof(uint32_t) * (size_t)n);
+    L.rank = take(sizeof(uint32_t) * (size_t)n);
+    L.sorted = take(sizeof(uint32_t) * (size_t)n);
+    L.total = o;
+    return L;
+}
+}  // namespace
+
+extern "C" size_t gsr_seed_scale_workspace_bytes(int64_t n)
+{
+    if (n < 0 || n >= (1ll << 31)) return 0;
+    return knn_layout(n).total;
+}
+
+extern "C" gsr_status gsr_seed_scale(int64_t n, const float* mean, const int32_t* valid, float floor_scale,
+                                     void* workspace, size_t workspace_bytes, float* log_scale, void* stream)
+{
+    g_err.clear();
+    if (n < 0 || n >= (1ll << 31)) return fail(GSR_EINVAL, "n out of range");
+    if (!(floor_scale > 0.0f) || !std::isfinite(floor_scale)) return fail(GSR_EINVAL, "floor_scale must be positive");
+    if (n == 0) return GSR_OK;
+    if (!mean || !valid || !log_scale || !workspace) return fail(GSR_EINVAL, "null buffer");
+    const KnnLayout L = knn_layout(n);
+    if (workspace_bytes < L.total) return fail(GSR_EINVAL, "workspace too small");
+    char* ws = (char*)workspace;
+    KnnArgs a{};
+    a.n = n;
+    a.mean = mean;
+    a.valid = valid;
+    a.floor_scale = floor_scale;
+    a.max_cells = L.max_cells;
+    a.bpart = (float*)(ws + L.bpart);
+    a.grid = (KnnGrid*)(ws + L.grid);
+    a.cell_count = (uint32_t*)(ws + L.cell_count);
+    a.cell_start = (uint32_t*)(ws + L.cell_start);
+    a.cell_of = (uint32_t*)(ws + L.cell_of);
+    a.rank = (uint32_t*)(ws + L.rank);
+    a.sorted = (uint32_t*)(ws + L.sorted);
+    a.log_scale = log_scale;
+    hipError_t e = launch_seed_scale(a, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_seed_scale");
+}

@@ -111,6 +111,59 @@ struct TrackArgs {
     float* dL_dT;              // like T_final, nullable
 };
 
+#define GSR_SEED_MAX_NEIGHBOURS 8
+#define GSR_KNN_BLOCKS 256          // blocks of the seeds' bounding-box pass
+
+struct SeedView {
+    double P[12];              // 3x4 projection matrix K [R | t], row-major
+    double centre[3];          // camera centre, world
+    int32_t width, height;
+    const float* image;        // [3][H][W]
+    double gain, bias;         // exposure: observed = gain * radiance + bias
+};
+
+struct SeedArgs {
+    SeedView views[GSR_SEED_MAX_NEIGHBOURS + 1];  // reference, then neighbours
+    int64_t n;
+    int32_t K;
+    double max_reproj, min_parallax, alpha_lo, alpha_hi;
+    const float* x_ref;        // [2][n]
+    const float* x_nb;         // [K][2][n]
+    const float* kappa;        // [K][n]
+    float* mean;               // [3][n]
+    float* colour;             // [3][n]
+    float* opacity_logit;      // [n]
+    int32_t* valid;            // [n]
+    int32_t* best;             // [n]
+    float* err;                // [n]
+    float* angle;              // [n]
+    float* kappa_bar;          // [n]
+};
+
+struct KnnGrid {
+    double origin[3];
+    double h;
+    int32_t dims[3];
+    int64_t cells;
+    int64_t count;
+};
+
+struct KnnArgs {
+    int64_t n;
+    const float* mean;         // [3][n]
+    const int32_t* valid;      // [n]
+    float floor_scale;
+    int64_t max_cells;
+    float* bpart;              // [GSR_KNN_BLOCKS][8]
+    KnnGrid* grid;
+    uint32_t* cell_count;      // [max_cells + 1]
+    uint32_t* cell_start;      // [max_cells + 1]
+    uint32_t* cell_of;         // [n]
+    uint32_t* rank;            // [n]
+    uint32_t* sorted;          // [n]
+    float* log_scale;          // [3][n]
+};
+
 #define GSR_TRACK_BLOCKS 256        // blocks per view of the tracking-loss kernels
 #define GSR_TRACK_SLOTS 8           // partial sums per block (4 exposure sums, 3 loss/sign sums)
 #define GSR_BIN_CHUNK 256           // Gaussians staged in LDS at a time by the binning blocks (x256)
@@ -131,5 +184,7 @@ hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, float* d_x
                               hipStream_t s);
 hipError_t launch_loss_l1(const LossArgs& a, hipStream_t s);
 hipError_t launch_loss_track(const TrackArgs& a, int n_views, hipStream_t s);
+hipError_t launch_seed_triangulate(const SeedArgs& a, hipStream_t s);
+hipError_t launch_seed_scale(const KnnArgs& a, hipStream_t s);
 
 }  // namespace gsr

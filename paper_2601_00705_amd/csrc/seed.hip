@@ -1,0 +1,481 @@
+// seed.hip -- the one-shot Gaussian seeding from dense correspondences (Sec.
+// "Dense Feature Matching" and the appendix's initialisation), one thread per
+// reference pixel.
+//
+// k_seed_triangulate: for every neighbour n of the reference keyframe, the
+//   two-view linear system A X = 0 (rows x P^3 - P^1, y P^3 - P^2 of both
+//   views) is solved in double by a one-sided Jacobi SVD of the 4x4 A: plane
+//   rotations orthogonalise A's columns and accumulate V; the column of V
+//   whose rotated column of A has the smallest norm is the right singular
+//   vector of the smallest singular value.  Among the neighbours the
+//   hypothesis with the smallest reprojection error (RMS of the two
+//   reprojection distances, in front of both cameras) is kept, ties going to
+//   the larger baseline angle; it is rejected when its error reaches
+//   max_reproj or its angle is below min_parallax.  Eq. (conf) gives
+//   kappa_bar, Eq. (app-alpha-init) the opacity; the colour is the median of
+//   the exposure-corrected bilinear samples over the supporting views (the
+//   reference, and every neighbour whose match lies within max_reproj of the
+//   kept point's projection).
+//
+// k_seed_bbox .. k_seed_knn: isotropic scale from the mean distance to the 3
+//   nearest other kept seeds, through a uniform grid: per-block bounds, the
+//   grid (cell size from the bounding volume and the seed count, at most
+//   ~4 cells per seed), a counting sort of the seeds by cell, then for every
+//   seed a search over cubic shells of cells around its own until the third
+//   distance found cannot be beaten by a farther shell.
+#include "kernels.h"
+
+namespace gsr {
+
+#define GSR_SEED_THREADS 256
+
+// ---------------------------------------------------------------------------
+// triangulation
+
+// right singular vector of the smallest singular value of the 4x4 A (rows)
+__device__ void smallest_right_singular(double A[4][4], double out[4])
+{
+    double V[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 40; ++sweep) {
+        bool rotated = false;
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+#pragma unroll
+            for (int q = p + 1; q < 4; ++q) {
+                double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    al += A[i][p] * A[i][p];
+                    be += A[i][q] * A[i][q];
+                    ga += A[i][p] * A[i][q];
+                }
+                if (ga == 0.0 || fabs(ga) <= 1e-17 * sqrt(al * be)) continue;
+                rotated = true;
+                const double zeta = (be - al) / (2.0 * ga);
+                const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const double ap = A[i][p], aq = A[i][q];
+                    A[i][p] = c * ap - s * aq;
+                    A[i][q] = s * ap + c * aq;
+                    const double vp = V[i][p], vq = V[i][q];
+                    V[i][p] = c * vp - s * vq;
+                    V[i][q] = s * vp + c * vq;
+                }
+            }
+        }
+        if (!rotated) break;
+    }
+    int best = 0;
+    double bn = 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        double nrm = 0.0;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) nrm += A[i][j] * A[i][j];
+        if (j == 0 || nrm < bn) {
+            bn = nrm;
+            best = j;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) out[i] = V[i][best];
+}
+
+__device__ __forceinline__ void project_px(const double* P, const double X[3], double& u, double& v, double& z)
+{
+    const double y0 = P[0] * X[0] + P[1] * X[1] + P[2] * X[2] + P[3];
+    const double y1 = P[4] * X[0] + P[5] * X[1] + P[6] * X[2] + P[7];
+    z = P[8] * X[0] + P[9] * X[1] + P[10] * X[2] + P[11];
+    u = y0 / z;
+    v = y1 / z;
+}
+
+// bilinear sample of channel c, pixel centres at +1/2, clamped to the border
+__device__ __forceinline__ double bilinear(const SeedView& vw, int c, double x, double y)
+{
+    const int W = vw.width, H = vw.height;
+    const double fx = fmin(fmax(x - 0.5, 0.0), (double)(W - 1));
+    const double fy = fmin(fmax(y - 0.5, 0.0), (double)(H - 1));
+    const int x0 = (int)floor(fx), y0 = (int)floor(fy);
+    const int x1 = min(x0 + 1, W - 1), y1 = min(y0 + 1, H - 1);
+    const double ax = fx - x0, ay = fy - y0;
+    const float* p = vw.image + (int64_t)c * W * H;
+    return (double)p[y0 * W + x0] * (1.0 - ax) * (1.0 - ay) + (double)p[y0 * W + x1] * ax * (1.0 - ay) +
+           (double)p[y1 * W + x0] * (1.0 - ax) * ay + (double)p[y1 * W + x1] * ax * ay;
+}
+
+__global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_triangulate(SeedArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x;
+    if (i >= a.n) return;
+    const int K = a.K;
+    const double xr[2] = {(double)a.x_ref[i], (double)a.x_ref[a.n + i]};
+    const SeedView& R = a.views[0];
+
+    // Eq. (conf) and Eq. (app-alpha-init)
+    double ks = 0.0;
+    for (int k = 0; k < K; ++k) ks += (double)a.kappa[(int64_t)k * a.n + i];
+    const double kbar = ks / (double)K;
+    const double alpha = a.alpha_lo + (a.alpha_hi - a.alpha_lo) * kbar;
+    if (a.kappa_bar) a.kappa_bar[i] = (float)kbar;
+    a.opacity_logit[i] = (float)log(alpha / (1.0 - alpha));
+
+    double best_err = INFINITY, best_ang = -1.0, bX[3] = {0.0, 0.0, 0.0};
+    int best = -1;
+    for (int k = 0; k < K; ++k) {
+        const SeedView& N = a.views[1 + k];
+        const double xn[2] = {(double)a.x_nb[(int64_t)(2 * k) * a.n + i], (double)a.x_nb[(int64_t)(2 * k + 1) * a.n + i]};
+        double A[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            A[0][j] = xr[0] * R.P[8 + j] - R.P[j];
+            A[1][j] = xr[1] * R.P[8 + j] - R.P[4 + j];
+            A[2][j] = xn[0] * N.P[8 + j] - N.P[j];
+            A[3][j] = xn[1] * N.P[8 + j] - N.P[4 + j];
+        }
+        double h[4];
+        smallest_right_singular(A, h);
+        if (h[3] == 0.0) continue;
+        const double X[3] = {h[0] / h[3], h[1] / h[3], h[2] / h[3]};
+        double ur, vr, zr, un, vn, zn;
+        project_px(R.P, X, ur, vr, zr);
+        project_px(N.P, X, un, vn, zn);
+        if (!(zr > 0.0 && zn > 0.0)) continue;
+        const double e0 = ur - xr[0], e1 = vr - xr[1], e2 = un - xn[0], e3 = vn - xn[1];
+        const double err = sqrt(0.5 * ((e0 * e0 + e1 * e1) + (e2 * e2 + e3 * e3)));
+        const double ra[3] = {X[0] - R.centre[0], X[1] - R.centre[1], X[2] - R.centre[2]};
+        const double rb[3] = {X[0] - N.centre[0], X[1] - N.centre[1], X[2] - N.centre[2]};
+        const double dot = ra[0] * rb[0] + ra[1] * rb[1] + ra[2] * rb[2];
+        const double na = sqrt(ra[0] * ra[0] + ra[1] * ra[1] + ra[2] * ra[2]);
+        const double nb = sqrt(rb[0] * rb[0] + rb[1] * rb[1] + rb[2] * rb[2]);
+        const double ang = acos(fmin(fmax(dot / (na * nb), -1.0), 1.0));
+        if (best < 0 || err < best_err || (err == best_err && ang > best_ang)) {
+            best_err = err;
+            best_ang = ang;
+            best = k;
+            bX[0] = X[0];
+            bX[1] = X[1];
+            bX[2] = X[2];
+        }
+    }
+    // a point whose float32 position overflows is no usable Gaussian
+    const bool finite = isfinite((float)bX[0]) && isfinite((float)bX[1]) && isfinite((float)bX[2]);
+    const bool ok = best >= 0 && best_err < a.max_reproj && best_ang >= a.min_parallax && finite;
+    a.valid[i] = ok ? 1 : 0;
+    if (a.best) a.best[i] = best;
+    if (a.err) a.err[i] = (float)best_err;
+    if (a.angle) a.angle[i] = best >= 0 ? (float)best_ang : 0.0f;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.mean[(int64_t)c * a.n + i] = (float)bX[c];
+
+    // colour: median of the corrected samples over the supporting views
+    double smp[3][GSR_SEED_MAX_NEIGHBOURS + 1];
+    int m = 0;
+    if (ok) {
+        for (int v = 0; v <= K; ++v) {
+            double px, py;
+            if (v == 0) {
+                px = xr[0];
+                py = xr[1];
+            } else {
+                const double xn0 = (double)a.x_nb[(int64_t)(2 * (v - 1)) * a.n + i];
+                const double xn1 = (double)a.x_nb[(int64_t)(2 * (v - 1) + 1) * a.n + i];
+                double u, w, z;
+                project_px(a.views[v].P, bX, u, w, z);
+                const double du = u - xn0, dv = w - xn1;
+                if (!(sqrt(du * du + dv * dv) < a.max_reproj)) continue;
+                px = xn0;
+                py = xn1;
+            }
+            const SeedView& vw = a.views[v];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) smp[c][m] = (bilinear(vw, c, px, py) - vw.bias) / vw.gain;
+            ++m;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double med = 0.0;
+        if (m > 0) {
+            for (int x = 1; x < m; ++x) {  // insertion sort of at most 9 values
+                const double key = smp[c][x];
+                int y = x - 1;
+                while (y >= 0 && smp[c][y] > key) {
+                    smp[c][y + 1] = smp[c][y];
+                    --y;
+                }
+                smp[c][y + 1] = key;
+            }
+            med = (m & 1) ? smp[c][m / 2] : (smp[c][m / 2 - 1] + smp[c][m / 2]) / 2.0;
+        }
+        a.colour[(int64_t)c * a.n + i] = (float)med;
+    }
+}
+
+hipError_t launch_seed_triangulate(const SeedArgs& a, hipStream_t s)
+{
+    if (a.n == 0) return hipSuccess;
+    const int64_t blocks = (a.n + GSR_SEED_THREADS - 1) / GSR_SEED_THREADS;
+    hipLaunchKernelGGL(k_seed_triangulate, dim3((unsigned)blocks), dim3(GSR_SEED_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// nearest-neighbour scale
+
+// per-block bounds of the kept seeds and their count
+__global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_bbox(KnnArgs a)
+{
+    __shared__ float red[7][GSR_SEED_THREADS / 64];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    float cnt = 0.0f;
+    for (int64_t i = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x; i < a.n;
+         i += (int64_t)GSR_KNN_BLOCKS * GSR_SEED_THREADS) {
+        if (!a.valid[i]) continue;
+        cnt += 1.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float x = a.mean[(int64_t)c * a.n + i];
+            lo[c] = fminf(lo[c], x);
+            hi[c] = fmaxf(hi[c], x);
+        }
+    }
+    // counts reach at most n / GSR_KNN_BLOCKS per block: exact in float for
+    // any n below 2^24 * GSR_KNN_BLOCKS
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = fminf(lo[c], __shfl_xor(lo[c], off, 64));
+            hi[c] = fmaxf(hi[c], __shfl_xor(hi[c], off, 64));
+        }
+        cnt += __shfl_xor(cnt, off, 64);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            red[c][w] = lo[c];
+            red[3 + c][w] = hi[c];
+        }
+        red[6][w] = cnt;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7) {
+        const int k = threadIdx.x;
+        float r = red[k][0];
+        for (int j = 1; j < GSR_SEED_THREADS / 64; ++j)
+            r = k < 3 ? fminf(r, red[k][j]) : (k < 6 ? fmaxf(r, red[k][j]) : r + red[k][j]);
+        a.bpart[(int64_t)blockIdx.x * 8 + k] = r;
+    }
+}
+
+// the grid: origin, cell size and dimensions from the blocks' bounds; one thread
+__global__ void k_seed_grid(KnnArgs a)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double cnt = 0.0;
+    for (int b = 0; b < GSR_KNN_BLOCKS; ++b) {
+        for (int c = 0; c < 3; ++c) {
+            lo[c] = fminf(lo[c], a.bpart[b * 8 + c]);
+            hi[c] = fmaxf(hi[c], a.bpart[b * 8 + 3 + c]);
+        }
+        cnt += a.bpart[b * 8 + 6];
+    }
+    KnnGrid g{};
+    g.count = (int64_t)cnt;
+    if (g.count == 0) {
+        g.dims[0] = g.dims[1] = g.dims[2] = 1;
+        g.cells = 1;
+        g.h = 1.0;
+        *a.grid = g;
+        return;
+    }
+    double ext[3], vol = 1.0;
+    for (int c = 0; c < 3; ++c) {
+        ext[c] = fmax((double)hi[c] - (double)lo[c], 0.0);
+        g.origin[c] = (double)lo[c];
+    }
+    const double maxext = fmax(ext[0], fmax(ext[1], ext[2]));
+    double h = maxext > 0.0 ? maxext : 1.0;
+    for (int c = 0; c < 3; ++c) vol *= fmax(ext[c], 1e-6 * h);
+    h = fmax(cbrt(vol / (double)g.count), 1e-6 * h);
+    // coarsen until the grid fits; non-finite extents (the caller's means
+    // must be finite) end in a single cell
+    g.cells = 0;
+    for (int it = 0; it < 256 && isfinite(h); ++it) {
+        int64_t cells = 1;
+        for (int c = 0; c < 3; ++c) {
+            g.dims[c] = (int)fmin(fmax(floor(ext[c] / h) + 1.0, 1.0), 1e6);
+            cells *= g.dims[c];
+        }
+        if (cells <= a.max_cells) {
+            g.cells = cells;
+            break;
+        }
+        h *= 1.25;
+    }
+    if (g.cells == 0) {
+        g.dims[0] = g.dims[1] = g.dims[2] = 1;
+        g.cells = 1;
+        h = 1.0;
+    }
+    g.h = h;
+    *a.grid = g;
+}
+
+__device__ __forceinline__ int cell_coord(const KnnGrid& g, int c, float x)
+{
+    const double k = floor(((double)x - g.origin[c]) / g.h);
+    if (!(k > 0.0)) return 0;  // also NaN
+    return k >= (double)(g.dims[c] - 1) ? g.dims[c] - 1 : (int)k;
+}
+
+__global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_zero(KnnArgs a)
+{
+    const KnnGrid g = *a.grid;
+    for (int64_t c = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x; c <= g.cells;
+         c += (int64_t)gridDim.x * GSR_SEED_THREADS)
+        a.cell_count[c] = 0u;
+}
+
+__global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_count(KnnArgs a)
+{
+    const KnnGrid g = *a.grid;
+    const int64_t i = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x;
+    if (i >= a.n || !a.valid[i]) return;
+    int cc[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) cc[c] = cell_coord(g, c, a.mean[(int64_t)c * a.n + i]);
+    const uint32_t cell = (uint32_t)(((int64_t)cc[2] * g.dims[1] + cc[1]) * g.dims[0] + cc[0]);
+    a.cell_of[i] = cell;
+    a.rank[i] = atomicAdd(&a.cell_count[cell], 1u);
+}
+
+// exclusive scan of the cell counts into cell_start, by one block in chunks
+__global__ __launch_bounds__(1024) void k_seed_scan(KnnArgs a)
+{
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t carry;
+    const KnnGrid g = *a.grid;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    if (tid == 0) carry = 0u;
+    __syncthreads();
+    for (int64_t base = 0; base <= g.cells; base += 1024) {
+        const int64_t c = base + tid;
+        const uint32_t x = c < g.cells ? a.cell_count[c] : 0u;
+        uint32_t incl = x;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        uint32_t wofs = 0;
+        for (int k = 0; k < w; ++k) wofs += wsum[k];
+        const uint32_t start = carry + wofs + incl - x;
+        if (c <= g.cells) a.cell_start[c] = start;
+        __syncthreads();
+        if (tid == 1023) carry = start + x;
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_place(KnnArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x;
+    if (i >= a.n || !a.valid[i]) return;
+    a.sorted[a.cell_start[a.cell_of[i]] + a.rank[i]] = (uint32_t)i;
+}
+
+__device__ __forceinline__ void knn_insert(double d, double (&best)[3], int& found)
+{
+    if (found < 3) {
+        int j = found++;
+        while (j > 0 && best[j - 1] > d) {
+            best[j] = best[j - 1];
+            --j;
+        }
+        best[j] = d;
+    } else if (d < best[2]) {
+        int j = 2;
+        while (j > 0 && best[j - 1] > d) {
+            best[j] = best[j - 1];
+            --j;
+        }
+        best[j] = d;
+    }
+}
+
+__global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_knn(KnnArgs a)
+{
+    const KnnGrid g = *a.grid;
+    const int64_t i = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x;
+    if (i >= a.n) return;
+    if (!a.valid[i]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.log_scale[(int64_t)c * a.n + i] = 0.0f;
+        return;
+    }
+    const float px = a.mean[i], py = a.mean[a.n + i], pz = a.mean[2 * a.n + i];
+    const int cx = cell_coord(g, 0, px), cy = cell_coord(g, 1, py), cz = cell_coord(g, 2, pz);
+    const int rmax = max(g.dims[0], max(g.dims[1], g.dims[2]));
+    double best[3] = {INFINITY, INFINITY, INFINITY};  // squared distances, ascending
+    int found = 0;
+    for (int r = 0; r <= rmax; ++r) {
+        // the cells of the shell at Chebyshev distance r that lie in the grid
+        const int z0 = max(-r, -cz), z1 = min(r, g.dims[2] - 1 - cz);
+        const int y0 = max(-r, -cy), y1 = min(r, g.dims[1] - 1 - cy);
+        const int x0 = max(-r, -cx), x1 = min(r, g.dims[0] - 1 - cx);
+        for (int dz = z0; dz <= z1; ++dz) {
+            for (int dy = y0; dy <= y1; ++dy) {
+                const bool face = dz == -r || dz == r || dy == -r || dy == r;
+                // on a face every dx, otherwise only the two ends dx = -r, r
+                for (int dx = face ? x0 : -r; dx <= (face ? x1 : r); dx += face ? 1 : max(2 * r, 1)) {
+                    if (dx < x0 || dx > x1) continue;
+                    const uint32_t cell =
+                        (uint32_t)(((int64_t)(cz + dz) * g.dims[1] + (cy + dy)) * g.dims[0] + (cx + dx));
+                    const uint32_t s0 = a.cell_start[cell], s1 = a.cell_start[cell + 1];
+                    for (uint32_t s = s0; s < s1; ++s) {
+                        const uint32_t j = a.sorted[s];
+                        if ((int64_t)j == i) continue;
+                        const double ex = (double)a.mean[j] - (double)px;
+                        const double ey = (double)a.mean[a.n + j] - (double)py;
+                        const double ez = (double)a.mean[2 * a.n + j] - (double)pz;
+                        knn_insert(ex * ex + ey * ey + ez * ez, best, found);
+                    }
+                }
+            }
+        }
+        // every seed in a farther shell lies at least r * h away
+        if (found == 3 && best[2] <= ((double)r * g.h) * ((double)r * g.h)) break;
+    }
+    double mean_d = 0.0;
+    for (int k = 0; k < found; ++k) mean_d += sqrt(best[k]);
+    const double s = found ? fmax(mean_d / (double)found, (double)a.floor_scale) : (double)a.floor_scale;
+    const float ls = (float)log(s);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.log_scale[(int64_t)c * a.n + i] = ls;
+}
+
+hipError_t launch_seed_scale(const KnnArgs& a, hipStream_t s)
+{
+    if (a.n == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((a.n + GSR_SEED_THREADS - 1) / GSR_SEED_THREADS);
+    hipLaunchKernelGGL(k_seed_bbox, dim3(GSR_KNN_BLOCKS), dim3(GSR_SEED_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_seed_grid, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_seed_zero, dim3(1024), dim3(GSR_SEED_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_seed_count, dim3(blocks), dim3(GSR_SEED_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_seed_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_seed_place, dim3(blocks), dim3(GSR_SEED_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_seed_knn, dim3(blocks), dim3(GSR_SEED_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace gsr

@@ -52,6 +52,17 @@ class Layout(ctypes.Structure):
                  "total")]
 
 
+class SeedView(ctypes.Structure):
+    _fields_ = [("P", ctypes.c_double * 12), ("centre", ctypes.c_double * 3), ("width", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("image", ctypes.c_void_p), ("gain", ctypes.c_double),
+                ("bias", ctypes.c_double)]
+
+
+class SeedConfig(ctypes.Structure):
+    _fields_ = [("max_reproj", ctypes.c_double), ("min_parallax", ctypes.c_double),
+                ("alpha_lo", ctypes.c_double), ("alpha_hi", ctypes.c_double)]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("slots", ctypes.c_int64), ("capacity", ctypes.c_int64),
                 ("total_pixels", ctypes.c_int64), ("n_views", ctypes.c_int32),
@@ -82,6 +93,9 @@ def _load():
         "gsr_raster_bwd": (st, [P, P, P, P, P, P]),
         "gsr_project_bwd": (st, [P, P, P, P, P, P, P]),
         "gsr_pair_count": (st, [P, P, P, P]),
+        "gsr_seed_triangulate": (st, [ctypes.c_int64, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P, P, P, P]),
+        "gsr_seed_scale_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
+        "gsr_seed_scale": (st, [ctypes.c_int64, P, P, ctypes.c_float, P, ctypes.c_size_t, P, P]),
         "gsr_plan_set_timing": (st, [P, ctypes.c_int32]),
         "gsr_plan_read_timing": (st, [P, ctypes.c_int32, P, P]),
         "gsr_status_str": (ctypes.c_char_p, [st]),
@@ -98,7 +112,8 @@ _lib = _load()
 EXPORTS = ("gsr_plan_create", "gsr_plan_destroy", "gsr_plan_workspace_bytes", "gsr_plan_bind",
            "gsr_plan_layout", "gsr_plan_get_info", "gsr_project", "gsr_bin", "gsr_render_fwd",
            "gsr_loss_l1", "gsr_loss_track", "gsr_render_bwd", "gsr_raster_bwd", "gsr_project_bwd", "gsr_pair_count",
-           "gsr_plan_set_timing", "gsr_plan_read_timing", "gsr_status_str", "gsr_last_error")
+           "gsr_plan_set_timing", "gsr_plan_read_timing", "gsr_status_str", "gsr_last_error",
+           "gsr_seed_triangulate", "gsr_seed_scale_workspace_bytes", "gsr_seed_scale")
 
 # launch groups of gsr_plan_read_timing (gsr_timer)
 TIMERS = ("project", "bin_emit", "bin_sort", "bin_ranges", "raster_fwd", "loss_l1", "clear_grad2d",
@@ -200,6 +215,36 @@ def gsr_loss_track(plan, rgb, T_final, target, tau_alpha, tau_grad, loss, exposu
     return check(_lib.gsr_loss_track(plan, _p(rgb), _p(T_final), _p(target), ctypes.c_double(tau_alpha),
                                      ctypes.c_double(tau_grad), _p(loss), _p(exposure), _p(dL_drgb), _p(dL_dT),
                                      ctypes.c_void_p(stream)), "gsr_loss_track")
+
+
+def gsr_seed_triangulate(views, cfg, x_ref, x_nb, kappa, mean, colour, opacity_logit, valid, best, err, angle,
+                         kappa_bar, stream):
+    """views: list of dicts (P [3][4], centre [3], width, height, image (device tensor), gain, bias);
+    cfg: dict (max_reproj, min_parallax, alpha_lo, alpha_hi)."""
+    arr = (SeedView * len(views))()
+    for k, v in enumerate(views):
+        arr[k].P = (ctypes.c_double * 12)(*[float(x) for x in list(v["P"].reshape(-1))])
+        arr[k].centre = (ctypes.c_double * 3)(*[float(x) for x in v["centre"]])
+        arr[k].width, arr[k].height = int(v["width"]), int(v["height"])
+        arr[k].image = ctypes.c_void_p(v["image"].data_ptr())
+        arr[k].gain, arr[k].bias = float(v["gain"]), float(v["bias"])
+    c = SeedConfig(float(cfg["max_reproj"]), float(cfg["min_parallax"]), float(cfg["alpha_lo"]),
+                   float(cfg["alpha_hi"]))
+    n = int(x_ref.shape[-1])
+    return check(_lib.gsr_seed_triangulate(n, len(views) - 1, arr, ctypes.byref(c), _p(x_ref), _p(x_nb), _p(kappa),
+                                           _p(mean), _p(colour), _p(opacity_logit), _p(valid), _p(best), _p(err),
+                                           _p(angle), _p(kappa_bar), ctypes.c_void_p(stream)),
+                 "gsr_seed_triangulate")
+
+
+def gsr_seed_scale_workspace_bytes(n):
+    return int(_lib.gsr_seed_scale_workspace_bytes(int(n)))
+
+
+def gsr_seed_scale(n, mean, valid, floor_scale, workspace, log_scale, stream):
+    return check(_lib.gsr_seed_scale(int(n), _p(mean), _p(valid), ctypes.c_float(floor_scale), _p(workspace),
+                                     workspace.numel() * workspace.element_size(), _p(log_scale),
+                                     ctypes.c_void_p(stream)), "gsr_seed_scale")
 
 
 def gsr_render_bwd(plan, g: Gaussians, poses, T_final, n_contrib, dL_drgb, dL_dT, pose_only, grads, d_xi,

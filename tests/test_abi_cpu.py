@@ -106,3 +106,38 @@ def test_track_loss_argument_errors():
         assert raw.gsr_loss_track(None, fake, fake, fake, 0.5, 0.1, fake, fake, fake, None, None) == lib.EINVAL
     finally:
         lib.gsr_plan_destroy(plan)
+
+
+def test_seed_argument_errors():
+    """Seeding arguments are checked on the host: neighbour count, config
+    bounds, views without images, workspace size; n = 0 does nothing."""
+    from paper_2601_00705_amd import lib
+    raw = lib.raw()
+    fake = ctypes.c_void_p(16)
+    views = (lib.SeedView * 3)()
+    for v in views:
+        v.width, v.height, v.image, v.gain, v.bias = 8, 6, 16, 1.0, 0.0
+    good = lib.SeedConfig(2.0, 0.01, 0.05, 0.95)
+    for K in (0, 9):
+        assert raw.gsr_seed_triangulate(10, K, views, ctypes.byref(good), *([fake] * 7), None, None, None, None,
+                                        None) == lib.EINVAL
+    for bad in ((0.0, 0.01, 0.05, 0.95), (2.0, -1.0, 0.05, 0.95), (2.0, 0.01, 0.0, 0.95), (2.0, 0.01, 0.6, 0.5),
+                (2.0, 0.01, 0.05, 1.0)):
+        c = lib.SeedConfig(*bad)
+        assert raw.gsr_seed_triangulate(10, 2, views, ctypes.byref(c), *([fake] * 7), None, None, None, None,
+                                        None) == lib.EINVAL
+    views[1].image = None
+    assert raw.gsr_seed_triangulate(10, 2, views, ctypes.byref(good), *([fake] * 7), None, None, None, None,
+                                    None) == lib.EINVAL
+    views[1].image = 16
+    views[2].gain = 0.0
+    assert raw.gsr_seed_triangulate(10, 2, views, ctypes.byref(good), *([fake] * 7), None, None, None, None,
+                                    None) == lib.EINVAL
+    views[2].gain = 1.0
+    assert raw.gsr_seed_triangulate(0, 2, views, ctypes.byref(good), *([None] * 7), None, None, None, None,
+                                    None) == 0
+    assert raw.gsr_seed_scale_workspace_bytes(-1) == 0
+    need = raw.gsr_seed_scale_workspace_bytes(1000)
+    assert need > 0
+    assert raw.gsr_seed_scale(1000, fake, fake, 1e-4, fake, need - 1, fake, None) == lib.EINVAL
+    assert raw.gsr_seed_scale(1000, fake, fake, 0.0, fake, need, fake, None) == lib.EINVAL
