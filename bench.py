@@ -53,6 +53,13 @@ SLOTS_BWD_PER_EVAL = 25 + 4 + 4
 TRACK_TAU_ALPHA = 0.5
 TRACK_TAU_GRAD = 0.05
 BYTES_TRACK_PER_PIXEL = 24 + 28 + 28 + 16
+# Seeding: FP64 peak of the vector units (published), and the FP64 operations
+# per reference pixel and neighbour: the 4x4 system (16), six sweeps of the
+# one-sided Jacobi SVD (6 rotations x 87: three 4-term dot products, the
+# rotation, both columns of A and V), the singular vector choice (32), the
+# two reprojections, the error and the baseline angle (~80)
+FP64_PEAK_TFLOPS = 78.6
+FLOPS_SEED_PER_HYPOTHESIS = 16 + 6 * 6 * 87 + 32 + 80
 # Algorithmic HBM bytes of one sort pass per pair: key + value read and written
 BYTES_SORT_PASS_PER_PAIR = 2 * (8 + 4)
 # Projection backward: per live slot the geom record and the nine FP64
@@ -82,6 +89,7 @@ def parse():
     ap.add_argument("--tile", type=str, default=None, help="WxH[/batch] (default: autotuned)")
     ap.add_argument("--autotune", action="store_true", help="re-run the tile/batch autotuner")
     ap.add_argument("--copy-probe", action="store_true", help="run a plain device copy of known size first")
+    ap.add_argument("--no-seeding", action="store_true", help="skip the seeding measurement")
     ap.add_argument("--loss", choices=("l1", "track"), default="l1",
                     help="gradient seed of the step: L1 (default) or the tracking loss")
     return ap.parse_args()
@@ -190,6 +198,47 @@ def measured_traffic(kernel, workload, cfg):
         return float(fields["traffic_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def seeding_measurement(torch, reps, log):
+    """Seeding at the mapping workload's shape: 500,000 reference pixels of a
+    1200x680 keyframe with 4 neighbours (synthetic correspondences of the
+    analytic room, 10 % outliers), then the nearest-neighbour scale."""
+    from paper_2601_00705_amd import scenes, seeding
+    d = scenes.seed_inputs(2601, 500_000, width=1200, height=680, f=600.0)
+    views = [dict(P=d["Ps"][v], centre=d["centres"][v], width=d["cams"][v]["width"],
+                  height=d["cams"][v]["height"], image=torch.from_numpy(d["images"][v]).cuda(),
+                  gain=d["expo"][v, 0], bias=d["expo"][v, 1]) for v in range(len(d["images"]))]
+    cfg = dict(max_reproj=2.0, min_parallax=0.5 * 3.141592653589793 / 180.0, alpha_lo=0.05, alpha_hi=0.95)
+    dev = {k: torch.from_numpy(d[k]).cuda() for k in ("xr", "xn", "kappa")}
+    n, K = d["xr"].shape[1], d["xn"].shape[0]
+    sc = seeding.Scaler(n)
+    out = seeding.triangulate(views, cfg, dev["xr"], dev["xn"], dev["kappa"], diagnostics=False)
+    ls = sc(out["mean"], out["valid"])
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    t_tri = t_knn = 0.0
+    for _ in range(reps):
+        ev[0].record()
+        seeding.triangulate(views, cfg, dev["xr"], dev["xn"], dev["kappa"], diagnostics=False)
+        ev[1].record()
+        sc(out["mean"], out["valid"], log_scale=ls)
+        ev[2].record()
+        torch.cuda.synchronize()
+        t_tri += ev[0].elapsed_time(ev[1])
+        t_knn += ev[1].elapsed_time(ev[2])
+    t_tri /= reps
+    t_knn /= reps
+    flops = FLOPS_SEED_PER_HYPOTHESIS * K * n
+    res = {"points": n, "neighbours": K, "kept": int(out["valid"].sum()), "triangulate_ms": t_tri,
+           "scale_ms": t_knn, "points_per_s": n / ((t_tri + t_knn) * 1e-3),
+           "roofline": {"bound": "alu", "kernel": "seed_triangulate",
+                        "achieved": flops / (t_tri * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s (FP64)", "work": f"{FLOPS_SEED_PER_HYPOTHESIS} x {K} x {n}"}}
+    res["roofline"]["frac"] = res["roofline"]["achieved"] / FP64_PEAK_TFLOPS
+    log(f"seeding: {n} px x {K} neighbours: triangulate {t_tri:.3f} ms, scale {t_knn:.3f} ms, "
+        f"{res['kept']} kept; {res['roofline']['achieved']:.1f} TFLOP/s FP64 ({res['roofline']['frac']:.2f})")
+    return res
 
 
 def oracle_sample(w, views, cfg):
@@ -385,6 +434,9 @@ def main():
     roof["frac"] = roof["achieved"] / roof["peak"]
     roof["traffic"] = measured_traffic(dom, w["name"], cfg)
 
+    # ---------------- seeding at the mapping workload's shape ----------
+    seed_res = None if args.no_seeding else seeding_measurement(torch, max(3, args.steps // 4), log)
+
     # ---------------- CPU baseline: the oracle on a bounded sample -----
     cpu = None
     if not args.no_cpu_baseline:
@@ -435,6 +487,7 @@ def main():
         "kernel_ms": kernel_ms,
         "roofline": roof,
         "tracking_loss": track,
+        "seeding": seed_res,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

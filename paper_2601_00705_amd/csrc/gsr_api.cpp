@@ -713,7 +713,9 @@ extern "C" gsr_status gsr_seed_triangulate(int64_t n, int32_t n_neighbours, cons
 namespace {
 struct KnnLayout {
     size_t bpart, grid, cell_count, cell_start, cell_of, rank, sorted, total;
+    size_t opart, fine_count, fine_start, fine_of, fine_rank, fine_sorted, scan_tot, bf_list, bf_count;
     int64_t max_cells;
+    int32_t table_bits;
 };
 
 KnnLayout knn_layout(int64_t n)
@@ -733,6 +735,20 @@ KnnLayout knn_layout(int64_t n)
     L.cell_of = take(sizeof(uint32_t) * (size_t)n);
     L.rank = take(sizeof(uint32_t) * (size_t)n);
     L.sorted = take(sizeof(uint32_t) * (size_t)n);
+    // fine grid: a hash table of at least two buckets per seed
+    L.table_bits = 10;
+    while (((int64_t)1 << L.table_bits) < 2 * n) ++L.table_bits;
+    const int64_t T = (int64_t)1 << L.table_bits;
+    L.opart = take(sizeof(double) * GSR_KNN_BLOCKS);
+    L.fine_count = take(sizeof(uint32_t) * GSR_KNN_LEVELS * (size_t)(T + 1));
+    L.fine_start = take(sizeof(uint32_t) * GSR_KNN_LEVELS * (size_t)(T + 1));
+    L.fine_of = take(sizeof(uint32_t) * GSR_KNN_LEVELS * (size_t)n);
+    L.fine_rank = take(sizeof(uint32_t) * GSR_KNN_LEVELS * (size_t)n);
+    L.fine_sorted = take(sizeof(uint32_t) * GSR_KNN_LEVELS * (size_t)n);
+    const int64_t scan_blocks = std::max((L.max_cells + 1 + 1023) / 1024, (T + 1 + 1023) / 1024);
+    L.scan_tot = take(sizeof(uint32_t) * (size_t)scan_blocks);
+    L.bf_list = take(sizeof(uint32_t) * (size_t)n);
+    L.bf_count = take(sizeof(uint32_t));
     L.total = o;
     return L;
 }
@@ -768,6 +784,16 @@ extern "C" gsr_status gsr_seed_scale(int64_t n, const float* mean, const int32_t
     a.cell_of = (uint32_t*)(ws + L.cell_of);
     a.rank = (uint32_t*)(ws + L.rank);
     a.sorted = (uint32_t*)(ws + L.sorted);
+    a.table_bits = L.table_bits;
+    a.opart = (double*)(ws + L.opart);
+    a.fine_count = (uint32_t*)(ws + L.fine_count);
+    a.fine_start = (uint32_t*)(ws + L.fine_start);
+    a.fine_of = (uint32_t*)(ws + L.fine_of);
+    a.fine_rank = (uint32_t*)(ws + L.fine_rank);
+    a.fine_sorted = (uint32_t*)(ws + L.fine_sorted);
+    a.scan_tot = (uint32_t*)(ws + L.scan_tot);
+    a.bf_list = (uint32_t*)(ws + L.bf_list);
+    a.bf_count = (uint32_t*)(ws + L.bf_count);
     a.log_scale = log_scale;
     hipError_t e = launch_seed_scale(a, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_seed_scale");

@@ -113,6 +113,7 @@ struct TrackArgs {
 
 #define GSR_SEED_MAX_NEIGHBOURS 8
 #define GSR_KNN_BLOCKS 256          // blocks of the seeds' bounding-box pass
+#define GSR_KNN_LEVELS 8            // fine hashed grid levels (cell sizes h1 * 2^l)
 
 struct SeedView {
     double P[12];              // 3x4 projection matrix K [R | t], row-major
@@ -142,10 +143,12 @@ struct SeedArgs {
 
 struct KnnGrid {
     double origin[3];
-    double h;
-    int32_t dims[3];
+    double h;                  // coarse cell size
+    int32_t dims[3];           // coarse grid
     int64_t cells;
-    int64_t count;
+    int64_t count;             // valid seeds
+    double h1, inv_h1;         // fine cell size (when fine)
+    int32_t fine;
 };
 
 struct KnnArgs {
@@ -161,6 +164,16 @@ struct KnnArgs {
     uint32_t* cell_of;         // [n]
     uint32_t* rank;            // [n]
     uint32_t* sorted;          // [n]
+    int32_t table_bits;        // fine grid: hash table of 2^table_bits buckets
+    double* opart;             // [GSR_KNN_BLOCKS]
+    uint32_t* fine_count;      // [GSR_KNN_LEVELS][2^table_bits + 1]
+    uint32_t* fine_start;      // [GSR_KNN_LEVELS][2^table_bits + 1]
+    uint32_t* fine_of;         // [GSR_KNN_LEVELS][n]
+    uint32_t* fine_rank;       // [GSR_KNN_LEVELS][n]
+    uint32_t* fine_sorted;     // [GSR_KNN_LEVELS][n]
+    uint32_t* scan_tot;        // block totals of the scans
+    uint32_t* bf_list;         // [n] queries left to the exhaustive search
+    uint32_t* bf_count;        // their number
     float* log_scale;          // [3][n]
 };
 

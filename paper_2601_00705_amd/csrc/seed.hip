@@ -18,11 +18,23 @@
 //   kept point's projection).
 //
 // k_seed_bbox .. k_seed_knn: isotropic scale from the mean distance to the 3
-//   nearest other kept seeds, through a uniform grid: per-block bounds, the
-//   grid (cell size from the bounding volume and the seed count, at most
-//   ~4 cells per seed), a counting sort of the seeds by cell, then for every
-//   seed a search over cubic shells of cells around its own until the third
-//   distance found cannot be beaten by a farther shell.
+//   nearest other kept seeds, on two uniform grids.  The coarse grid covers
+//   the seeds' bounding box (cell size from its volume and the seed count, at
+//   most ~4 cells per seed).  Seeds concentrate on surfaces, and a few far
+//   seeds inflate the box, so when a seed shares its coarse cell with more
+//   than 8 others on average, a fine grid refines the cell size towards ~4
+//   seeds per cell, with GSR_KNN_LEVELS - 1 levels of 2x coarser cells above
+//   it for sparser regions; their cells are spatially hashed into a table of ~2
+//   slots per seed per level (a bucket may hold several cells; a candidate
+//   counts only for its own cell).  All are counting sorts by cell.  A query
+//   searches cubic shells of cells around its own until the third distance
+//   found cannot be beaten by a farther shell: up to 2 shells on each fine
+//   level, from the level whose cells match the spacing its coarse cell's
+//   count suggests upwards, then up to 2 shells on the coarse grid.  The few
+//   queries still unsettled (seeds far from all others), or that would
+//   examine more than GSR_KNN_BUDGET candidates on one lane (seeds beside
+//   much denser regions), are listed and each is answered exactly by a whole
+//   block scanning every valid seed.
 #include "kernels.h"
 
 namespace gsr {
@@ -275,7 +287,7 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_bbox(KnnArgs a)
     }
 }
 
-// the grid: origin, cell size and dimensions from the blocks' bounds; one thread
+// the coarse grid: origin, cell size and dimensions from the blocks' bounds
 __global__ void k_seed_grid(KnnArgs a)
 {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -288,8 +300,12 @@ __global__ void k_seed_grid(KnnArgs a)
         }
         cnt += a.bpart[b * 8 + 6];
     }
+    *a.bf_count = 0u;
     KnnGrid g{};
     g.count = (int64_t)cnt;
+    g.fine = 0;
+    g.h1 = 1.0;
+    g.inv_h1 = 1.0;
     if (g.count == 0) {
         g.dims[0] = g.dims[1] = g.dims[2] = 1;
         g.cells = 1;
@@ -337,12 +353,29 @@ __device__ __forceinline__ int cell_coord(const KnnGrid& g, int c, float x)
     return k >= (double)(g.dims[c] - 1) ? g.dims[c] - 1 : (int)k;
 }
 
+// cell coordinate on fine level l (unbounded grid, clamped to +-2^30); the
+// level's inverse cell size is inv_h1 / 2^l, exact in binary
+__device__ __forceinline__ int fine_coord(const KnnGrid& g, int l, int c, float x)
+{
+    const double k = floor(((double)x - g.origin[c]) * (g.inv_h1 * ldexp(1.0, -l)));
+    if (!(k > -1073741824.0)) return -1073741824;  // also NaN
+    return k < 1073741824.0 ? (int)k : 1073741824;
+}
+
+__device__ __forceinline__ uint32_t fine_bucket(int x, int y, int z, uint32_t mask)
+{
+    return (((uint32_t)x * 73856093u) ^ ((uint32_t)y * 19349663u) ^ ((uint32_t)z * 83492791u)) & mask;
+}
+
 __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_zero(KnnArgs a)
 {
     const KnnGrid g = *a.grid;
-    for (int64_t c = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x; c <= g.cells;
-         c += (int64_t)gridDim.x * GSR_SEED_THREADS)
-        a.cell_count[c] = 0u;
+    const int64_t T1 = ((int64_t)1 << a.table_bits) + 1;
+    for (int64_t c = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x; c <= g.cells || c < GSR_KNN_LEVELS * T1;
+         c += (int64_t)gridDim.x * GSR_SEED_THREADS) {
+        if (c <= g.cells) a.cell_count[c] = 0u;
+        if (c < GSR_KNN_LEVELS * T1) a.fine_count[c] = 0u;
+    }
 }
 
 __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_count(KnnArgs a)
@@ -358,18 +391,112 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_count(KnnArgs a)
     a.rank[i] = atomicAdd(&a.cell_count[cell], 1u);
 }
 
-// exclusive scan of the cell counts into cell_start, by one block in chunks
-__global__ __launch_bounds__(1024) void k_seed_scan(KnnArgs a)
+// sum over coarse cells of count^2 (per block), the seeds' mean cell sharing
+__global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_occ(KnnArgs a)
+{
+    __shared__ double red[GSR_SEED_THREADS / 64];
+    const KnnGrid g = *a.grid;
+    double s = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x; c < g.cells;
+         c += (int64_t)GSR_KNN_BLOCKS * GSR_SEED_THREADS) {
+        const double k = (double)a.cell_count[c];
+        s += k * k;
+    }
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int j = 0; j < GSR_SEED_THREADS / 64; ++j) t += red[j];
+        a.opart[blockIdx.x] = t;
+    }
+}
+
+// the fine grid's cell size (or none), one thread
+__global__ void k_seed_fine_grid(KnnArgs a)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    KnnGrid g = *a.grid;
+    double s = 0.0;
+    for (int b = 0; b < GSR_KNN_BLOCKS; ++b) s += a.opart[b];
+    const double occ = g.count > 0 ? s / (double)g.count : 0.0;
+    if (g.count >= 8 && occ > 8.0) {
+        g.fine = 1;
+        g.h1 = fmax(g.h * sqrt(4.0 / occ), 1e-3 * g.h);
+        g.inv_h1 = 1.0 / g.h1;
+    }
+    *a.grid = g;
+}
+
+__global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_fcount(KnnArgs a)
+{
+    const KnnGrid g = *a.grid;
+    const int64_t i = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x;
+    if (!g.fine || i >= a.n || !a.valid[i]) return;
+    const int64_t T1 = ((int64_t)1 << a.table_bits) + 1;
+    const uint32_t mask = ((uint32_t)1 << a.table_bits) - 1u;
+    for (int l = 0; l < GSR_KNN_LEVELS; ++l) {
+        const uint32_t b = fine_bucket(fine_coord(g, l, 0, a.mean[i]), fine_coord(g, l, 1, a.mean[a.n + i]),
+                                       fine_coord(g, l, 2, a.mean[2 * a.n + i]), mask);
+        a.fine_of[l * a.n + i] = b;
+        a.fine_rank[l * a.n + i] = atomicAdd(&a.fine_count[l * T1 + b], 1u);
+    }
+}
+
+// exclusive scan of len counts (len = coarse cells + 1, or table size + 1):
+// per 1024-entry block, then the block totals, then their offsets
+__device__ __forceinline__ int64_t scan_len(const KnnArgs& a, int which)
+{
+    return which == 0 ? a.grid->cells + 1 : ((int64_t)1 << a.table_bits) + 1;
+}
+
+__device__ __forceinline__ const uint32_t* scan_in(const KnnArgs& a, int which)
+{
+    return which == 0 ? a.cell_count : a.fine_count + (int64_t)(which - 1) * (((int64_t)1 << a.table_bits) + 1);
+}
+
+__device__ __forceinline__ uint32_t* scan_out(const KnnArgs& a, int which)
+{
+    return which == 0 ? a.cell_start : a.fine_start + (int64_t)(which - 1) * (((int64_t)1 << a.table_bits) + 1);
+}
+
+__global__ __launch_bounds__(1024) void k_scan_local(KnnArgs a, int which)
+{
+    __shared__ uint32_t wsum[16];
+    const int64_t len = scan_len(a, which);
+    if (which > 0 && !a.grid->fine) return;
+    const int64_t base = (int64_t)blockIdx.x * 1024;
+    if (base >= len) return;
+    const uint32_t* cnt = scan_in(a, which);
+    uint32_t* out = scan_out(a, which);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t c = base + tid;
+    const uint32_t x = c < len ? cnt[c] : 0u;
+    uint32_t incl = x;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t wofs = 0;
+    for (int k = 0; k < w; ++k) wofs += wsum[k];
+    if (c < len) out[c] = wofs + incl - x;
+    if (tid == 1023) a.scan_tot[blockIdx.x] = wofs + incl;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_totals(KnnArgs a, int which)
 {
     __shared__ uint32_t wsum[16];
     __shared__ uint32_t carry;
-    const KnnGrid g = *a.grid;
+    if (which > 0 && !a.grid->fine) return;
+    const int64_t nb = (scan_len(a, which) + 1023) / 1024;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     if (tid == 0) carry = 0u;
     __syncthreads();
-    for (int64_t base = 0; base <= g.cells; base += 1024) {
+    for (int64_t base = 0; base < nb; base += 1024) {
         const int64_t c = base + tid;
-        const uint32_t x = c < g.cells ? a.cell_count[c] : 0u;
+        const uint32_t x = c < nb ? a.scan_tot[c] : 0u;
         uint32_t incl = x;
         for (int off = 1; off < 64; off <<= 1) {
             const uint32_t y = __shfl_up(incl, off, 64);
@@ -380,18 +507,40 @@ __global__ __launch_bounds__(1024) void k_seed_scan(KnnArgs a)
         uint32_t wofs = 0;
         for (int k = 0; k < w; ++k) wofs += wsum[k];
         const uint32_t start = carry + wofs + incl - x;
-        if (c <= g.cells) a.cell_start[c] = start;
+        if (c < nb) a.scan_tot[c] = start;
         __syncthreads();
         if (tid == 1023) carry = start + x;
         __syncthreads();
     }
 }
 
+__global__ __launch_bounds__(1024) void k_scan_add(KnnArgs a, int which)
+{
+    if (which > 0 && !a.grid->fine) return;
+    const int64_t len = scan_len(a, which);
+    const int64_t c = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    if (c >= len) return;
+    uint32_t* out = scan_out(a, which);
+    out[c] += a.scan_tot[blockIdx.x];
+}
+
 __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_place(KnnArgs a)
 {
+    const KnnGrid g = *a.grid;
     const int64_t i = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x;
-    if (i >= a.n || !a.valid[i]) return;
+    if (i >= a.n) return;
+    if (!a.valid[i]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.log_scale[(int64_t)c * a.n + i] = 0.0f;
+        return;
+    }
     a.sorted[a.cell_start[a.cell_of[i]] + a.rank[i]] = (uint32_t)i;
+    if (g.fine) {
+        const int64_t T1 = ((int64_t)1 << a.table_bits) + 1;
+        for (int l = 0; l < GSR_KNN_LEVELS; ++l)
+            a.fine_sorted[l * a.n + a.fine_start[l * T1 + a.fine_of[l * a.n + i]] + a.fine_rank[l * a.n + i]] =
+                (uint32_t)i;
+    }
 }
 
 __device__ __forceinline__ void knn_insert(double d, double (&best)[3], int& found)
@@ -413,68 +562,174 @@ __device__ __forceinline__ void knn_insert(double d, double (&best)[3], int& fou
     }
 }
 
+__device__ __forceinline__ void knn_candidate(const KnnArgs& a, uint32_t j, int64_t i, float px, float py, float pz,
+                                              double (&best)[3], int& found)
+{
+    if ((int64_t)j == i) return;
+    const double ex = (double)a.mean[j] - (double)px;
+    const double ey = (double)a.mean[a.n + j] - (double)py;
+    const double ez = (double)a.mean[2 * a.n + j] - (double)pz;
+    knn_insert(ex * ex + ey * ey + ez * ez, best, found);
+}
+
+#define GSR_KNN_FINE_SHELLS 2
+#define GSR_KNN_COARSE_SHELLS 2
+#define GSR_KNN_BUDGET 2048
+
+// one thread per valid seed, taken in coarse-cell order so that a wave's
+// queries are spatial neighbours with similar search costs
 __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_knn(KnnArgs a)
 {
     const KnnGrid g = *a.grid;
-    const int64_t i = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x;
-    if (i >= a.n) return;
-    if (!a.valid[i]) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) a.log_scale[(int64_t)c * a.n + i] = 0.0f;
-        return;
-    }
+    const int64_t t = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x;
+    if (t >= g.count) return;
+    const int64_t i = a.sorted[t];
     const float px = a.mean[i], py = a.mean[a.n + i], pz = a.mean[2 * a.n + i];
-    const int cx = cell_coord(g, 0, px), cy = cell_coord(g, 1, py), cz = cell_coord(g, 2, pz);
-    const int rmax = max(g.dims[0], max(g.dims[1], g.dims[2]));
     double best[3] = {INFINITY, INFINITY, INFINITY};  // squared distances, ascending
     int found = 0;
-    for (int r = 0; r <= rmax; ++r) {
-        // the cells of the shell at Chebyshev distance r that lie in the grid
-        const int z0 = max(-r, -cz), z1 = min(r, g.dims[2] - 1 - cz);
-        const int y0 = max(-r, -cy), y1 = min(r, g.dims[1] - 1 - cy);
-        const int x0 = max(-r, -cx), x1 = min(r, g.dims[0] - 1 - cx);
-        for (int dz = z0; dz <= z1; ++dz) {
-            for (int dy = y0; dy <= y1; ++dy) {
-                const bool face = dz == -r || dz == r || dy == -r || dy == r;
-                // on a face every dx, otherwise only the two ends dx = -r, r
-                for (int dx = face ? x0 : -r; dx <= (face ? x1 : r); dx += face ? 1 : max(2 * r, 1)) {
-                    if (dx < x0 || dx > x1) continue;
-                    const uint32_t cell =
-                        (uint32_t)(((int64_t)(cz + dz) * g.dims[1] + (cy + dy)) * g.dims[0] + (cx + dx));
-                    const uint32_t s0 = a.cell_start[cell], s1 = a.cell_start[cell + 1];
-                    for (uint32_t s = s0; s < s1; ++s) {
-                        const uint32_t j = a.sorted[s];
-                        if ((int64_t)j == i) continue;
-                        const double ex = (double)a.mean[j] - (double)px;
-                        const double ey = (double)a.mean[a.n + j] - (double)py;
-                        const double ez = (double)a.mean[2 * a.n + j] - (double)pz;
-                        knn_insert(ex * ex + ey * ey + ez * ez, best, found);
+    bool settled = false;
+    uint32_t work = 0;  // candidates examined on this lane
+    if (g.fine) {
+        // shells of each fine level, finest first; a bucket's entries count
+        // only for their own cell
+        const uint32_t mask = ((uint32_t)1 << a.table_bits) - 1u;
+        const int64_t T1 = ((int64_t)1 << a.table_bits) + 1;
+        // seeds of the coarse cell spread over a surface: spacing ~ h / sqrt(count)
+        const double cnt = (double)a.cell_count[a.cell_of[i]];
+        const double lv = floor(log2(g.h / sqrt(fmax(cnt, 1.0)) * g.inv_h1));
+        const int l0 = lv > 0.0 ? (int)fmin(lv, (double)(GSR_KNN_LEVELS - 1)) : 0;
+        for (int l = l0; l < GSR_KNN_LEVELS && !settled; ++l) {
+            found = 0;
+            best[0] = best[1] = best[2] = INFINITY;
+            const uint32_t* start = a.fine_start + l * T1;
+            const uint32_t* sorted = a.fine_sorted + l * a.n;
+            const double hl = g.h1 * ldexp(1.0, l);
+            const int fx = fine_coord(g, l, 0, px), fy = fine_coord(g, l, 1, py), fz = fine_coord(g, l, 2, pz);
+            for (int r = 0; r <= GSR_KNN_FINE_SHELLS && !settled; ++r) {
+                for (int dz = -r; dz <= r; ++dz) {
+                    for (int dy = -r; dy <= r; ++dy) {
+                        const bool face = dz == -r || dz == r || dy == -r || dy == r;
+                        for (int dx = -r; dx <= r; dx += face ? 1 : max(2 * r, 1)) {
+                            const int x = fx + dx, y = fy + dy, z = fz + dz;
+                            const uint32_t b = fine_bucket(x, y, z, mask);
+                            const uint32_t s0 = start[b], s1 = start[b + 1];
+                            work += s1 - s0;
+                            if (work > GSR_KNN_BUDGET) goto exhaustive;
+                            for (uint32_t s = s0; s < s1; ++s) {
+                                const uint32_t j = sorted[s];
+                                if (fine_coord(g, l, 0, a.mean[j]) != x || fine_coord(g, l, 1, a.mean[a.n + j]) != y ||
+                                    fine_coord(g, l, 2, a.mean[2 * a.n + j]) != z)
+                                    continue;
+                                knn_candidate(a, j, i, px, py, pz, best, found);
+                            }
+                        }
+                    }
+                }
+                // every seed in a farther shell lies at least r * hl away
+                settled = found == 3 && best[2] <= ((double)r * hl) * ((double)r * hl);
+            }
+        }
+        if (!settled) {
+            found = 0;
+            best[0] = best[1] = best[2] = INFINITY;
+        }
+    }
+    if (!settled) {
+        const int cx = cell_coord(g, 0, px), cy = cell_coord(g, 1, py), cz = cell_coord(g, 2, pz);
+        const int rmax = max(g.dims[0], max(g.dims[1], g.dims[2]));
+        for (int r = 0; r <= min(rmax, GSR_KNN_COARSE_SHELLS) && !settled; ++r) {
+            // the cells of the shell at Chebyshev distance r that lie in the grid
+            const int z0 = max(-r, -cz), z1 = min(r, g.dims[2] - 1 - cz);
+            const int y0 = max(-r, -cy), y1 = min(r, g.dims[1] - 1 - cy);
+            const int x0 = max(-r, -cx), x1 = min(r, g.dims[0] - 1 - cx);
+            for (int dz = z0; dz <= z1; ++dz) {
+                for (int dy = y0; dy <= y1; ++dy) {
+                    const bool face = dz == -r || dz == r || dy == -r || dy == r;
+                    // on a face every dx, otherwise only the two ends dx = -r, r
+                    for (int dx = face ? x0 : -r; dx <= (face ? x1 : r); dx += face ? 1 : max(2 * r, 1)) {
+                        if (dx < x0 || dx > x1) continue;
+                        const uint32_t cell =
+                            (uint32_t)(((int64_t)(cz + dz) * g.dims[1] + (cy + dy)) * g.dims[0] + (cx + dx));
+                        const uint32_t s0 = a.cell_start[cell], s1 = a.cell_start[cell + 1];
+                        work += s1 - s0;
+                        if (work > GSR_KNN_BUDGET) goto exhaustive;
+                        for (uint32_t s = s0; s < s1; ++s) knn_candidate(a, a.sorted[s], i, px, py, pz, best, found);
                     }
                 }
             }
+            // every seed in a farther shell lies at least r * h away; shell
+            // rmax has covered the whole grid
+            settled = r >= rmax || (found == 3 && best[2] <= ((double)r * g.h) * ((double)r * g.h));
         }
-        // every seed in a farther shell lies at least r * h away
-        if (found == 3 && best[2] <= ((double)r * g.h) * ((double)r * g.h)) break;
+        if (!settled) goto exhaustive;
     }
-    double mean_d = 0.0;
-    for (int k = 0; k < found; ++k) mean_d += sqrt(best[k]);
-    const double s = found ? fmax(mean_d / (double)found, (double)a.floor_scale) : (double)a.floor_scale;
-    const float ls = (float)log(s);
+    {
+        double mean_d = 0.0;
+        for (int k = 0; k < found; ++k) mean_d += sqrt(best[k]);
+        const double sc = found ? fmax(mean_d / (double)found, (double)a.floor_scale) : (double)a.floor_scale;
+        const float ls = (float)log(sc);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) a.log_scale[(int64_t)c * a.n + i] = ls;
+        for (int c = 0; c < 3; ++c) a.log_scale[(int64_t)c * a.n + i] = ls;
+        return;
+    }
+exhaustive:
+    a.bf_list[atomicAdd(a.bf_count, 1u)] = (uint32_t)i;
+}
+
+// the listed queries, one block each (grid-stride over the list): every
+// thread keeps the 3 nearest of its share of the valid seeds, then thread 0
+// merges the block's candidates
+__global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_brute(KnnArgs a)
+{
+    __shared__ double cand[GSR_SEED_THREADS * 3];
+    const KnnGrid g = *a.grid;
+    const uint32_t nq = *a.bf_count;
+    for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
+        const int64_t i = a.bf_list[q];
+        const float px = a.mean[i], py = a.mean[a.n + i], pz = a.mean[2 * a.n + i];
+        double best[3] = {INFINITY, INFINITY, INFINITY};
+        int found = 0;
+        for (int64_t t = threadIdx.x; t < g.count; t += GSR_SEED_THREADS)
+            knn_candidate(a, a.sorted[t], i, px, py, pz, best, found);
+        for (int k = 0; k < 3; ++k) cand[threadIdx.x * 3 + k] = k < found ? best[k] : INFINITY;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double b[3] = {INFINITY, INFINITY, INFINITY};
+            int f = 0;
+            for (int k = 0; k < GSR_SEED_THREADS * 3; ++k)
+                if (cand[k] < INFINITY) knn_insert(cand[k], b, f);
+            double mean_d = 0.0;
+            for (int k = 0; k < f; ++k) mean_d += sqrt(b[k]);
+            const double sc = f ? fmax(mean_d / (double)f, (double)a.floor_scale) : (double)a.floor_scale;
+            const float ls = (float)log(sc);
+            for (int c = 0; c < 3; ++c) a.log_scale[(int64_t)c * a.n + i] = ls;
+        }
+        __syncthreads();
+    }
 }
 
 hipError_t launch_seed_scale(const KnnArgs& a, hipStream_t s)
 {
     if (a.n == 0) return hipSuccess;
     const unsigned blocks = (unsigned)((a.n + GSR_SEED_THREADS - 1) / GSR_SEED_THREADS);
+    const unsigned coarse_scan = (unsigned)((a.max_cells + 1 + 1023) / 1024);
+    const unsigned fine_scan = (unsigned)((((int64_t)1 << a.table_bits) + 1 + 1023) / 1024);
     hipLaunchKernelGGL(k_seed_bbox, dim3(GSR_KNN_BLOCKS), dim3(GSR_SEED_THREADS), 0, s, a);
     hipLaunchKernelGGL(k_seed_grid, dim3(1), dim3(64), 0, s, a);
     hipLaunchKernelGGL(k_seed_zero, dim3(1024), dim3(GSR_SEED_THREADS), 0, s, a);
     hipLaunchKernelGGL(k_seed_count, dim3(blocks), dim3(GSR_SEED_THREADS), 0, s, a);
-    hipLaunchKernelGGL(k_seed_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_seed_occ, dim3(GSR_KNN_BLOCKS), dim3(GSR_SEED_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_seed_fine_grid, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_seed_fcount, dim3(blocks), dim3(GSR_SEED_THREADS), 0, s, a);
+    for (int which = 0; which <= GSR_KNN_LEVELS; ++which) {
+        const unsigned nb = which == 0 ? coarse_scan : fine_scan;
+        hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(1024), 0, s, a, which);
+        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, a, which);
+        hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(1024), 0, s, a, which);
+    }
     hipLaunchKernelGGL(k_seed_place, dim3(blocks), dim3(GSR_SEED_THREADS), 0, s, a);
     hipLaunchKernelGGL(k_seed_knn, dim3(blocks), dim3(GSR_SEED_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_seed_brute, dim3(1024), dim3(GSR_SEED_THREADS), 0, s, a);
     return hipGetLastError();
 }
 
