@@ -367,13 +367,26 @@ def main():
     }
     log("kernel ms: " + ", ".join(f"{k}={v:.3f}" for k, v in kernel_ms.items()))
 
-    # ---------------- tracking loss: its three kernels, eager, HBM bound -----
-    R.set_timing(True)
-    for _ in range(K):
+    # ---------------- tracking loss: its three kernels, HBM bound -----------
+    # (tens of microseconds each, so they are replayed from a graph of 20
+    # calls: eager launches would time the host's launch gaps)
+    tgraph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(cap):
         st.track()
-    t_ms, t_cnt = R.read_timing()["loss_track"]
-    R.set_timing(False)
-    t_ms /= max(t_cnt, 1)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(tgraph, stream=cap):
+            for _ in range(20):
+                st.track()
+    torch.cuda.synchronize()
+    tgraph.replay()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(3, args.steps // 4)
+    ev0.record()
+    for _ in range(reps):
+        tgraph.replay()
+    ev1.record()
+    torch.cuda.synchronize()
+    t_ms = ev0.elapsed_time(ev1) / (20 * reps)
     t_bytes = BYTES_TRACK_PER_PIXEL * total_px
     track = {"ms": t_ms, "bound": "hbm", "achieved": t_bytes / (t_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
              "unit": "GB/s", "work": f"{BYTES_TRACK_PER_PIXEL} B x {total_px} px",
