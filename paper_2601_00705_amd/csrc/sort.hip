@@ -22,16 +22,22 @@
 
 namespace gsr {
 
+// lanes of the wave (valid ones) holding the same 8-bit digit as this lane:
+// for every bit, keep the ballot of that bit where this lane's bit is 1 and
+// its complement where it is 0, i.e. m &= ~(ballot ^ sign-extended bit), on
+// the two 32-bit halves
 __device__ __forceinline__ unsigned long long match_digit(uint32_t d, bool valid)
 {
-    unsigned long long m = __ballot(valid);
+    const unsigned long long v = __ballot(valid);
+    uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
-        bool bit = (d >> b) & 1u;
-        unsigned long long bb = __ballot(bit);
-        m &= bit ? bb : ~bb;
+        const uint32_t s = (uint32_t)((int32_t)(d << (31 - b)) >> 31);  // 0 or ~0
+        const unsigned long long bb = __ballot(s != 0u);
+        lo &= ~((uint32_t)bb ^ s);
+        hi &= ~((uint32_t)(bb >> 32) ^ s);
     }
-    return m;
+    return ((unsigned long long)hi << 32) | lo;
 }
 
 template <int WAVES, int ITEMS>
