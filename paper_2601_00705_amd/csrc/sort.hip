@@ -63,7 +63,6 @@ __device__ __forceinline__ void rank_items(const unsigned long long* key, int R,
                                            SegLds<WAVES, ITEMS>& L)
 {
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const unsigned long long lt = (1ull << lane) - 1ull;
     for (int k = tid; k < WAVES * 256; k += WAVES * 64) (&L.wcnt[0][0])[k] = 0u;
     __syncthreads();
     uint32_t dig[MAXR];
@@ -74,7 +73,8 @@ __device__ __forceinline__ void rank_items(const unsigned long long* key, int R,
         const bool valid = li < m;
         const uint32_t d = valid ? (uint32_t)(key[r] >> shift) & 255u : 0u;
         const unsigned long long mk = match_digit(d, valid);
-        const uint32_t below = (uint32_t)__popcll(mk & lt);
+        // set bits of mk in the lanes below this one
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
         const uint32_t start = valid ? L.wcnt[w][d] : 0u;
         // every lane has read its counter before a leader updates it
         __builtin_amdgcn_wave_barrier();
