@@ -87,13 +87,18 @@ template <int PPT>
 struct TileCtx {
     int tile;                 // global tile of this workgroup
     int px, py0, rs;          // column, first row, row stride
-    bool inside[PPT];
-    int64_t pix[PPT];         // index into the concatenated [H][W] planes
-    int64_t rgb0[PPT];        // channel-0 index into the concatenated images
+    int width, height, pix_base;
+    int64_t base;             // index of row py0 into the concatenated [H][W] planes
     int64_t plane;            // H * W of the view
     double xc, yc;            // tile centre in view pixel coordinates
     float dx;                 // this lane's pixel-centre offset from it (column)
     float dy[PPT];            // and its rows'
+    // the lane's k-th pixel: inside the view, its [H][W] index, and its
+    // channel-0 index into the concatenated [3][H][W] images (derived when
+    // needed rather than held in registers)
+    __device__ __forceinline__ bool inside(int k) const { return px < width && py0 + k * rs < height; }
+    __device__ __forceinline__ int64_t pix(int k) const { return base + (int64_t)(k * rs) * width; }
+    __device__ __forceinline__ int64_t rgb0(int k) const { return pix(k) + 2 * (int64_t)pix_base; }
 };
 
 template <int PPT>
@@ -116,14 +121,13 @@ __device__ __forceinline__ TileCtx<PPT> tile_ctx(const RasterArgs& a)
     c.xc = (double)(tx * a.cfg.tile_w) + 0.5 * a.cfg.tile_w;
     c.yc = (double)(ty * a.cfg.tile_h) + 0.5 * a.cfg.tile_h;
     c.dx = (float)(lane & (a.cfg.tile_w - 1)) + 0.5f - 0.5f * (float)a.cfg.tile_w;
+    c.width = vw.width;
+    c.height = vw.height;
+    c.pix_base = vw.pix_base;
+    c.base = (int64_t)vw.pix_base + (int64_t)c.py0 * vw.width + c.px;
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int py = c.py0 + k * c.rs;
-        c.inside[k] = c.px < vw.width && py < vw.height;
+    for (int k = 0; k < PPT; ++k)
         c.dy[k] = (float)((lane >> l2) + k * c.rs) + 0.5f - 0.5f * (float)a.cfg.tile_h;
-        c.pix[k] = (int64_t)vw.pix_base + (int64_t)py * vw.width + c.px;
-        c.rgb0[k] = 3 * (int64_t)vw.pix_base + (int64_t)py * vw.width + c.px;
-    }
     return c;
 }
 
@@ -191,7 +195,9 @@ __device__ __forceinline__ void fwd_batch(const LdsRec* rec, int cnt, uint32_t p
     }
 }
 
-template <int PPT, int GSR_BATCH>
+// COUNT: also count the blended entries per pixel (into a.n_blend); a
+// separate instantiation, so that the plain forward carries no counters
+template <int PPT, int GSR_BATCH, bool COUNT>
 __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
 {
     __shared__ LdsRec rec[GSR_BATCH];
@@ -200,7 +206,6 @@ __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
     const bool overflow = a.counters->overflow != 0u;
     const uint2 range = overflow ? make_uint2(0u, 0u) : a.ranges[c.tile];
     const float amax = a.cfg.alpha_max, tmin = a.cfg.T_min;
-    const bool count = a.n_blend != nullptr;
     float T[PPT], C0[PPT], C1[PPT], C2[PPT], dy[PPT];
     uint32_t last[PPT], nb[PPT];
 #pragma unroll
@@ -208,7 +213,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
         T[k] = 1.0f;
         C0[k] = C1[k] = C2[k] = 0.0f;
         last[k] = nb[k] = 0u;
-        dy[k] = c.inside[k] ? c.dy[k] : __builtin_nanf("");
+        dy[k] = c.inside(k) ? c.dy[k] : __builtin_nanf("");
     }
     for (uint32_t base = range.x; base < range.y; base += GSR_BATCH) {
         uint64_t live = 0;
@@ -222,31 +227,28 @@ __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)GSR_BATCH, range.y - base);
-        if (count)
-            fwd_batch<PPT, true>(rec, cnt, base - range.x, amax, tmin, c.dx, dy, T, C0, C1, C2, last, nb);
-        else
-            fwd_batch<PPT, false>(rec, cnt, base - range.x, amax, tmin, c.dx, dy, T, C0, C1, C2, last, nb);
+        fwd_batch<PPT, COUNT>(rec, cnt, base - range.x, amax, tmin, c.dx, dy, T, C0, C1, C2, last, nb);
         __syncthreads();
     }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        if (!c.inside[k]) continue;
+        if (!c.inside(k)) continue;
         if (overflow) {
             const float q = __builtin_nanf("");
-            a.rgb[c.rgb0[k]] = q;
-            a.rgb[c.rgb0[k] + c.plane] = q;
-            a.rgb[c.rgb0[k] + 2 * c.plane] = q;
-            a.T_final[c.pix[k]] = q;
-            a.n_contrib[c.pix[k]] = 0;
-            if (a.n_blend) a.n_blend[c.pix[k]] = 0;
+            a.rgb[c.rgb0(k)] = q;
+            a.rgb[c.rgb0(k) + c.plane] = q;
+            a.rgb[c.rgb0(k) + 2 * c.plane] = q;
+            a.T_final[c.pix(k)] = q;
+            a.n_contrib[c.pix(k)] = 0;
+            if (COUNT) a.n_blend[c.pix(k)] = 0;
             continue;
         }
-        a.rgb[c.rgb0[k]] = __builtin_fmaf(T[k], a.cfg.bg0, C0[k]);
-        a.rgb[c.rgb0[k] + c.plane] = __builtin_fmaf(T[k], a.cfg.bg1, C1[k]);
-        a.rgb[c.rgb0[k] + 2 * c.plane] = __builtin_fmaf(T[k], a.cfg.bg2, C2[k]);
-        a.T_final[c.pix[k]] = T[k];
-        a.n_contrib[c.pix[k]] = (int32_t)last[k];
-        if (a.n_blend) a.n_blend[c.pix[k]] = (int32_t)nb[k];
+        a.rgb[c.rgb0(k)] = __builtin_fmaf(T[k], a.cfg.bg0, C0[k]);
+        a.rgb[c.rgb0(k) + c.plane] = __builtin_fmaf(T[k], a.cfg.bg1, C1[k]);
+        a.rgb[c.rgb0(k) + 2 * c.plane] = __builtin_fmaf(T[k], a.cfg.bg2, C2[k]);
+        a.T_final[c.pix(k)] = T[k];
+        a.n_contrib[c.pix(k)] = (int32_t)last[k];
+        if (COUNT) a.n_blend[c.pix(k)] = (int32_t)nb[k];
     }
 }
 
@@ -280,13 +282,13 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
         g0[k] = g1[k] = g2[k] = 0.0f;
         float gT = 0.0f;
         my_n[k] = 0u;
-        if (c.inside[k]) {
-            Tf[k] = a.T_final_in[c.pix[k]];
-            my_n[k] = (uint32_t)a.n_contrib_in[c.pix[k]];
-            g0[k] = a.dL_drgb[c.rgb0[k]];
-            g1[k] = a.dL_drgb[c.rgb0[k] + c.plane];
-            g2[k] = a.dL_drgb[c.rgb0[k] + 2 * c.plane];
-            if (a.dL_dT) gT = a.dL_dT[c.pix[k]];
+        if (c.inside(k)) {
+            Tf[k] = a.T_final_in[c.pix(k)];
+            my_n[k] = (uint32_t)a.n_contrib_in[c.pix(k)];
+            g0[k] = a.dL_drgb[c.rgb0(k)];
+            g1[k] = a.dL_drgb[c.rgb0(k) + c.plane];
+            g2[k] = a.dL_drgb[c.rgb0(k) + 2 * c.plane];
+            if (a.dL_dT) gT = a.dL_dT[c.pix(k)];
         }
         T[k] = Tf[k];
         dy2[k] = c.dy[k] * c.dy[k];
@@ -373,16 +375,22 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
     }
 }
 
-template <int PPT>
-static hipError_t launch_fwd_t(const RasterArgs& a, int tiles, int batch, hipStream_t s)
+template <int PPT, bool COUNT>
+static hipError_t launch_fwd_c(const RasterArgs& a, int tiles, int batch, hipStream_t s)
 {
     switch (batch) {
-    case 64: hipLaunchKernelGGL((k_raster_fwd<PPT, 64>), dim3(tiles), dim3(64), 0, s, a); break;
-    case 128: hipLaunchKernelGGL((k_raster_fwd<PPT, 128>), dim3(tiles), dim3(64), 0, s, a); break;
-    case 256: hipLaunchKernelGGL((k_raster_fwd<PPT, 256>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 64: hipLaunchKernelGGL((k_raster_fwd<PPT, 64, COUNT>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 128: hipLaunchKernelGGL((k_raster_fwd<PPT, 128, COUNT>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 256: hipLaunchKernelGGL((k_raster_fwd<PPT, 256, COUNT>), dim3(tiles), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipSuccess;
+}
+
+template <int PPT>
+static hipError_t launch_fwd_t(const RasterArgs& a, int tiles, int batch, hipStream_t s)
+{
+    return a.n_blend ? launch_fwd_c<PPT, true>(a, tiles, batch, s) : launch_fwd_c<PPT, false>(a, tiles, batch, s);
 }
 
 template <int PPT>
