@@ -47,7 +47,7 @@ struct gsr_plan {
     size_t off_counters = 0, off_views = 0, off_geom = 0, off_conic = 0, off_rgbd = 0, off_qthr = 0, off_grad2d = 0;
     size_t off_stage = 0;
     size_t off_keys = 0, off_vals = 0, off_seg = 0, off_ranges = 0, off_cnt = 0;
-    size_t off_xip = 0, off_order = 0, off_buckets = 0, off_track = 0, total = 0;
+    size_t off_xip = 0, off_xip_sh = 0, off_order = 0, off_buckets = 0, off_track = 0, total = 0;
     char* ws = nullptr;
     Counters host_counters{};
     std::vector<uint32_t> identity_order;
@@ -244,6 +244,7 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->off_buckets = take(sizeof(uint32_t) * 64);
     p->off_cnt = take(sizeof(uint32_t) * (size_t)p->chunks * (size_t)tiles);
     p->off_xip = take(sizeof(double) * 6 * (size_t)n_views * p->bwd_blocks);
+    p->off_xip_sh = take(sizeof(double) * 6 * (size_t)n_views * p->bwd_blocks);
     p->off_track = take(sizeof(double) * GSR_TRACK_SLOTS * GSR_TRACK_BLOCKS * (size_t)n_views);
     p->total = o;
     p->host_counters = Counters{};
@@ -561,6 +562,7 @@ extern "C" gsr_status gsr_project_bwd(gsr_plan* plan, const gsr_gaussians* g, co
     b.d_opacity_logit = grads ? grads->d_opacity_logit : nullptr;
     b.d_colour = grads ? grads->d_colour : nullptr;
     b.xi_partial = at<double>(plan, plan->off_xip);
+    b.xi_partial_sh = at<double>(plan, plan->off_xip_sh);
     b.blocks = plan->bwd_blocks;
     Timed t(plan, GSR_T_PROJECT_BWD, (hipStream_t)stream);
     hipError_t e = launch_project_bwd(b, plan->cfg.sh_degree, d_xi, plan->V, (hipStream_t)stream);

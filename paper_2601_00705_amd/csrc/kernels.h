@@ -87,6 +87,7 @@ struct ProjectBwdArgs {
     unsigned long long pose_only;   // bit v set: view v updates the pose only
     float *d_mean, *d_quat, *d_log_scale, *d_opacity_logit, *d_colour;
     double* xi_partial;             // [V][blocks][6]
+    double* xi_partial_sh;          // [V][blocks][6], the SH chain's (degree >= 1)
     int32_t blocks;
 };
 

@@ -45,13 +45,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
     const bool live_thread = i < n;
     const int64_t S = (int64_t)a.views->n * n;
-    constexpr int K = DEG < 0 ? 1 : (DEG + 1) * (DEG + 1);
+    // SH of degree 1-3 is differentiated by k_sh_bwd (its own registers); the
+    // geometry chain here then carries no colour state
+    constexpr int K = DEG <= 0 ? 1 : 1;
 
     Activated<T> g;
     T col[K][3];
     if (live_thread) {
         activate<T>(a.mean, a.quat, a.log_scale, a.opacity_logit, n, i, g);
-        if (DEG >= 0) {
+        if (DEG == 0) {
 #pragma unroll
             for (int k = 0; k < K; ++k)
 #pragma unroll
@@ -142,7 +144,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
             xi[5] = x * dmc1 - y * dmc0 + (P[3] - P[1]);
             T dm[3];
             for (int q = 0; q < 3; ++q) dm[q] = R[q] * dmc0 + R[3 + q] * dmc1 + R[6 + q] * dmc2;
-            if (DEG >= 0) {
+            if (DEG == 0) {
                 T oc[3];
                 camera_centre<T>(pose, oc);
                 T ddv[3] = {g.mw[0] - oc[0], g.mw[1] - oc[1], g.mw[2] - oc[2]};
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
 #pragma unroll
                         for (int c = 0; c < 3; ++c) dcol[k][c] += gc[c] * Y[k];
                 }
-            } else if (params) {
+            } else if (DEG < 0 && params) {
                 dcol[0][0] += gc[0];
                 dcol[0][1] += gc[1];
                 dcol[0][2] += gc[2];
@@ -236,20 +238,117 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
     a.d_mean[n + i] = (float)dmw[1];
     a.d_mean[2 * n + i] = (float)dmw[2];
     a.d_opacity_logit[i] = (float)(d_o * g.o * ((T)1 - g.o));
+    if (DEG <= 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a.d_colour[(k * 3 + c) * n + i] = (float)dcol[k][c];
+    }
+}
+
+// SH colour of degree DEG >= 1, after k_project_bwd: the colour gradients
+// (dL/dc_k = sum over the parameter views of dL/dcolour Y_k(n)), and the
+// view-direction term: with n = (mu_W - o_c) / |mu_W - o_c|, the colour's
+// gradient in n projected off n and divided by the distance is added to
+// dL/dmu_W (parameter views) and, through the camera centre o_c = -R^T t
+// (which moves by -R^T rho under the left update), R times it to d rho of
+// every view.  This chain is well conditioned (no 1/z), so it runs in FP32.
+template <int DEG>
+__global__ __launch_bounds__(256) void k_sh_bwd(ProjectBwdArgs a)
+{
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    __shared__ double red[4][4];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t n = a.n;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
+    const bool live_thread = i < n;
+    float col[K][3], dcol[K][3], mw[3] = {0.0f, 0.0f, 0.0f}, dm[3] = {0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int k = 0; k < K; ++k)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) a.d_colour[(k * 3 + c) * n + i] = (float)dcol[k][c];
+        for (int c = 0; c < 3; ++c) {
+            col[k][c] = live_thread ? a.colour[(k * 3 + c) * n + i] : 0.0f;
+            dcol[k][c] = 0.0f;
+        }
+    if (live_thread)
+        for (int c = 0; c < 3; ++c) mw[c] = a.mean[c * n + i];
+    const float inv_tw = 1.0f / (float)a.cfg.tile_w, inv_th = 1.0f / (float)a.cfg.tile_h;
+    for (int v = 0; v < a.views->n; ++v) {
+        const ViewInfo vw = a.views->v[v];
+        const float* pose = a.poses + 12 * v;
+        const bool params = ((a.pose_only >> v) & 1ull) == 0ull;
+        double xe[3] = {0.0, 0.0, 0.0};
+        const int64_t slot = (int64_t)v * n + i;
+        bool live = false;
+        if (live_thread) {
+            const float4 gm = a.geom[slot];
+            int x0, y0, x1, y1;
+            live = tile_rect(gm.x, gm.y, gm.z, gm.w, inv_tw, inv_th, vw.tiles_x, vw.tiles_y, x0, y0, x1, y1);
+        }
+        if (live) {
+            const double* g2 = a.grad2d + GSR_G2 * slot;
+            const float gc[3] = {(float)g2[6], (float)g2[7], (float)g2[8]};
+            float oc[3];
+            camera_centre<float>(pose, oc);
+            const float d0 = mw[0] - oc[0], d1 = mw[1] - oc[1], d2 = mw[2] - oc[2];
+            const float inv = 1.0f / sqrtf(d0 * d0 + d1 * d1 + d2 * d2);
+            const float nx = d0 * inv, ny = d1 * inv, nz = d2 * inv;
+            float Y[16], wk[16];
+            sh_eval<DEG, float>(nx, ny, nz, Y);
+#pragma unroll
+            for (int k = 0; k < K; ++k) wk[k] = gc[0] * col[k][0] + gc[1] * col[k][1] + gc[2] * col[k][2];
+            float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+            sh_grad_acc<DEG, float>(nx, ny, nz, wk, gx, gy, gz);
+            const float dot = gx * nx + gy * ny + gz * nz;
+            const float e0 = (gx - nx * dot) * inv, e1 = (gy - ny * dot) * inv, e2 = (gz - nz * dot) * inv;
+            xe[0] = (double)(pose[0] * e0 + pose[1] * e1 + pose[2] * e2);
+            xe[1] = (double)(pose[3] * e0 + pose[4] * e1 + pose[5] * e2);
+            xe[2] = (double)(pose[6] * e0 + pose[7] * e1 + pose[8] * e2);
+            if (params) {
+                dm[0] += e0;
+                dm[1] += e1;
+                dm[2] += e2;
+#pragma unroll
+                for (int k = 0; k < K; ++k)
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) dcol[k][c] += gc[c] * Y[k];
+            }
+        }
+        // block sums of the three rho partials, fixed order (uniform control flow)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            double t = xe[k];
+            for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+            if (lane == 0) red[wv][k] = t;
+        }
+        __syncthreads();
+        if (tid < 6) {
+            const double t = tid < 3 ? red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid] : 0.0;
+            a.xi_partial_sh[((int64_t)v * a.blocks + blockIdx.x) * 6 + tid] = t;
+        }
+        __syncthreads();
+    }
+    if (!live_thread || !a.d_mean) return;
+    for (int c = 0; c < 3; ++c) a.d_mean[c * n + i] += dm[c];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.d_colour[(k * 3 + c) * n + i] = dcol[k][c];
 }
 
-// sum of the per-block tangent partials, fixed order: one block per view
-__global__ __launch_bounds__(256) void k_xi_reduce(const double* partial, int blocks, float* d_xi)
+// sum of the per-block tangent partials (and those of the SH chain, when
+// given), fixed order: one block per view
+__global__ __launch_bounds__(256) void k_xi_reduce(const double* partial, const double* partial_sh, int blocks,
+                                                   float* d_xi)
 {
     __shared__ double red[6][256];
     const int v = blockIdx.x, tid = threadIdx.x;
     double s[6] = {0, 0, 0, 0, 0, 0};
     for (int b = tid; b < blocks; b += 256)
-        for (int k = 0; k < 6; ++k) s[k] += partial[((int64_t)v * blocks + b) * 6 + k];
+        for (int k = 0; k < 6; ++k) {
+            s[k] += partial[((int64_t)v * blocks + b) * 6 + k];
+            if (partial_sh) s[k] += partial_sh[((int64_t)v * blocks + b) * 6 + k];
+        }
     for (int k = 0; k < 6; ++k) red[k][tid] = s[k];
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
@@ -273,9 +372,16 @@ hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, float* d_x
         case 3: hipLaunchKernelGGL(k_project_bwd<3>, grid, block, 0, s, a); break;
         default: return hipErrorInvalidValue;
         }
+        switch (sh_degree) {
+        case 1: hipLaunchKernelGGL(k_sh_bwd<1>, grid, block, 0, s, a); break;
+        case 2: hipLaunchKernelGGL(k_sh_bwd<2>, grid, block, 0, s, a); break;
+        case 3: hipLaunchKernelGGL(k_sh_bwd<3>, grid, block, 0, s, a); break;
+        default: break;
+        }
     }
     if (d_xi && n_views > 0)
-        hipLaunchKernelGGL(k_xi_reduce, dim3(n_views), dim3(256), 0, s, a.xi_partial, a.blocks, d_xi);
+        hipLaunchKernelGGL(k_xi_reduce, dim3(n_views), dim3(256), 0, s, a.xi_partial,
+                           sh_degree >= 1 ? a.xi_partial_sh : (const double*)nullptr, a.blocks, d_xi);
     return hipGetLastError();
 }
 
