@@ -145,7 +145,10 @@ size_t gsr_plan_workspace_bytes(const gsr_plan *plan);
 
 /* Binds a caller-owned device workspace of at least gsr_plan_workspace_bytes
  * bytes, uploads the view table and capacity into it, and synchronises
- * `stream` once.  The workspace must stay alive while the plan is used. */
+ * `stream` once.  The workspace must stay alive while the plan is used.  The
+ * first bind also creates the plan's own second stream (non-blocking,
+ * default priority) and two ordering events, released by
+ * gsr_plan_destroy. */
 gsr_status gsr_plan_bind(gsr_plan *plan, void *workspace, size_t bytes, void *stream);
 
 gsr_status gsr_plan_layout(const gsr_plan *plan, gsr_layout *out);
@@ -163,7 +166,11 @@ gsr_status gsr_project(gsr_plan *plan, const gsr_gaussians *g, const float *pose
  * pair emission, stable LSD radix sort of (tile | depth) keys with slot
  * values, tile ranges.  When the pair count exceeds the capacity, a device
  * flag is set, no pair is written, gsr_render_fwd writes NaN images and
- * gsr_render_bwd writes NaN gradients; gsr_pair_count reports it. */
+ * gsr_render_bwd writes NaN gradients; gsr_pair_count reports it.  The sort
+ * of segments longer than 8192 pairs runs on the plan's second stream,
+ * forked from `stream` after the tile ranges and joined back before gsr_bin
+ * returns its work to `stream` (the fork and join are recorded too when
+ * `stream` is being captured into a graph). */
 gsr_status gsr_bin(gsr_plan *plan, void *stream);
 
 /* Eq. (alpha) for every view.  rgb, T_final, n_contrib required; n_blend

@@ -57,9 +57,17 @@ struct gsr_plan {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[GSR_T_COUNT];
     double timed_ms[GSR_T_COUNT] = {};
     int64_t timed_launches[GSR_T_COUNT] = {};
+    // the long-segment sort runs on a second stream of the plan, forked from
+    // and joined back to the caller's stream by two events (host objects,
+    // created when the plan is bound; default stream priority)
+    hipStream_t side = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
 
     ~gsr_plan()
     {
+        if (fork_ev) (void)hipEventDestroy(fork_ev);
+        if (join_ev) (void)hipEventDestroy(join_ev);
+        if (side) (void)hipStreamDestroy(side);
         for (auto& v : pending)
             for (auto& pr : v) {
                 (void)hipEventDestroy(pr.first);
@@ -279,6 +287,9 @@ extern "C" gsr_status gsr_plan_bind(gsr_plan* plan, void* workspace, size_t byte
                            sizeof(uint32_t) * (size_t)plan->total_tiles, hipMemcpyHostToDevice, s);
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess && !plan->side) e = hipStreamCreateWithFlags(&plan->side, hipStreamNonBlocking);
+    if (e == hipSuccess && !plan->fork_ev) e = hipEventCreateWithFlags(&plan->fork_ev, hipEventDisableTiming);
+    if (e == hipSuccess && !plan->join_ev) e = hipEventCreateWithFlags(&plan->join_ev, hipEventDisableTiming);
     if (e != hipSuccess) {
         plan->ws = nullptr;
         return hip_fail(e, "gsr_plan_bind");
@@ -419,7 +430,7 @@ extern "C" gsr_status gsr_bin(gsr_plan* plan, void* stream)
     if (e != hipSuccess) return hip_fail(e, "gsr_bin: order");
     {
         Timed t(plan, GSR_T_BIN_SORT, s);
-        e = launch_seg_sort(g, plan->total_tiles, s);
+        e = launch_seg_sort(g, plan->total_tiles, plan->capacity, s, plan->side, plan->fork_ev, plan->join_ev);
     }
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_bin: sort");
 }

@@ -184,13 +184,16 @@ struct KnnArgs {
 #define GSR_BIN_LDS_TILES 16384     // views with more tiles count and place with global atomics
 #define GSR_SEG_THREADS 512
 #define GSR_SEG_ITEMS 8192          // segments up to this size are sorted in LDS
+#define GSR_SEG_LONG_THREADS 1024   // longer segments: one 1024-thread block each
+#define GSR_SEG_LONG_ITEMS 16384    // ... holding this many keys in LDS
 
 hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t s);
 // pair counting, offsets, emission into per-tile segments; max_tiles_view is
 // the largest tile count of one view
 hipError_t launch_bin(const BinArgs& a, int max_tiles_view, hipStream_t s);
 hipError_t launch_order(const RangeArgs& a, hipStream_t s);
-hipError_t launch_seg_sort(const SegArgs& a, int total_tiles, hipStream_t s);
+hipError_t launch_seg_sort(const SegArgs& a, int total_tiles, int64_t capacity, hipStream_t s, hipStream_t side,
+                           hipEvent_t fork, hipEvent_t join);
 hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s);
 hipError_t launch_clear_grad2d(const RasterArgs& a, hipStream_t s);
 hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s);

@@ -1,6 +1,6 @@
 // sort.hip -- per-tile ordering of the emitted pairs, and the tiles' order.
 //
-// k_seg_sort   one 512-thread block per tile (longest first): sorts the
+// k_seg_sort   one block per tile (longest first): sorts the
 //              segment's unique 64-bit keys (depth bits << 32 | Gaussian
 //              index) ascending with a stable LSD radix sort of 8-bit digits,
 //              skipping every digit that is the same for all keys of the
@@ -19,6 +19,7 @@
 // round, lane) with wave-private digit counters; equal digits inside a round
 // are found with 8 ballots.
 #include "kernels.h"
+
 
 namespace gsr {
 
@@ -335,21 +336,45 @@ __device__ void sort_segment(const SegArgs& a, uint32_t tile, uint2 rg, SegLds<W
 }
 
 // one block per tile, in the tiles' processing order (longest first)
-__global__ __launch_bounds__(GSR_SEG_THREADS) void k_seg_sort(SegArgs a)
+// LONG = false: segments of up to GSR_SEG_ITEMS keys, with GSR_SEG_THREADS
+// threads; LONG = true: the longer ones, with GSR_SEG_LONG_THREADS threads
+// and GSR_SEG_LONG_ITEMS keys in LDS (through global memory in chunks of
+// that size beyond it).  Block b takes the b-th tile of the processing
+// order; a block whose tile belongs to the other class returns at once.
+template <int THREADS, int ITEMS, bool LONG>
+__global__ __launch_bounds__(THREADS) void k_seg_sort(SegArgs a)
 {
-    __shared__ SegLds<GSR_SEG_THREADS / 64, GSR_SEG_ITEMS> L;
+    __shared__ SegLds<THREADS / 64, ITEMS> L;
     if (a.counters->overflow) return;
     const uint32_t tile = a.order[blockIdx.x];
     const uint2 rg = a.ranges[tile];
-    if (rg.y == rg.x) return;
-    sort_segment(a, tile, rg, L);
+    const uint32_t m = rg.y - rg.x;
+    if (m == 0 || LONG != (m > (uint32_t)GSR_SEG_ITEMS)) return;
+    sort_segment<THREADS / 64, ITEMS>(a, tile, rg, L);
 }
 
-hipError_t launch_seg_sort(const SegArgs& a, int total_tiles, hipStream_t s)
+// The two classes run concurrently: the long segments on `side`, forked
+// from `s` after the tile ranges and joined back before anything later on
+// `s` (the fork and join are recorded into a graph when `s` is captured).
+hipError_t launch_seg_sort(const SegArgs& a, int total_tiles, int64_t capacity, hipStream_t s, hipStream_t side,
+                           hipEvent_t fork, hipEvent_t join)
 {
     if (total_tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_seg_sort, dim3((unsigned)total_tiles), dim3(GSR_SEG_THREADS), 0, s, a);
-    return hipGetLastError();
+    hipError_t e = hipEventRecord(fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+    if (e != hipSuccess) return e;
+    // the long segments lead the processing order (longest first), and at
+    // most capacity / (GSR_SEG_ITEMS + 1) of them fit in the pair buffer
+    const int64_t longs = capacity / (GSR_SEG_ITEMS + 1) + 1;
+    const unsigned long_grid = (unsigned)(longs < total_tiles ? longs : total_tiles);
+    hipLaunchKernelGGL((k_seg_sort<GSR_SEG_LONG_THREADS, GSR_SEG_LONG_ITEMS, true>), dim3(long_grid),
+                       dim3(GSR_SEG_LONG_THREADS), 0, side, a);
+    hipLaunchKernelGGL((k_seg_sort<GSR_SEG_THREADS, GSR_SEG_ITEMS, false>), dim3((unsigned)total_tiles),
+                       dim3(GSR_SEG_THREADS), 0, s, a);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(join, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+    return e;
 }
 
 // ---------------------------------------------------------------------------
