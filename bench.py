@@ -53,6 +53,16 @@ SLOTS_BWD_PER_EVAL = 25 + 4 + 4
 TRACK_TAU_ALPHA = 0.5
 TRACK_TAU_GRAD = 0.05
 BYTES_TRACK_PER_PIXEL = 24 + 28 + 28 + 16
+# Mapping loss (L1 + lambda D-SSIM, lambda_dssim = 0.2 in the appendix's
+# optimisation settings): algorithmic VALU issue slots per pixel and channel
+# of the separable filtering without aprons: the five products along rows
+# (11 taps x 7 operations), along columns (11 x 5 FMA), SSIM and its three
+# partials (~50, two divisions at ~12 slots each), the partials along rows
+# (11 x 3 FMA) and columns (11 x 3 FMA) and the gradient (5); its
+# algorithmic HBM bytes per pixel: render and target read, gradient written
+MAP_LAMBDA = 0.2
+SLOTS_MAP_PER_PIXEL = 3 * (77 + 55 + 50 + 33 + 38)
+BYTES_MAP_PER_PIXEL = 12 + 12 + 12
 # Seeding: FP64 peak of the vector units (published), and the FP64 operations
 # per reference pixel and neighbour: the 4x4 system (16), six sweeps of the
 # one-sided Jacobi SVD (6 rotations x 87: three 4-term dot products, the
@@ -90,8 +100,8 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="re-run the tile/batch autotuner")
     ap.add_argument("--copy-probe", action="store_true", help="run a plain device copy of known size first")
     ap.add_argument("--no-seeding", action="store_true", help="skip the seeding measurement")
-    ap.add_argument("--loss", choices=("l1", "track"), default="l1",
-                    help="gradient seed of the step: L1 (default) or the tracking loss")
+    ap.add_argument("--loss", choices=("l1", "track", "mapping"), default="l1",
+                    help="gradient seed of the step: L1 (default), the tracking loss or the mapping loss")
     return ap.parse_args()
 
 
@@ -129,6 +139,7 @@ class Step:
         self.dL = torch.empty(3 * P, device=dev)
         self.dT = torch.empty(P, device=dev)
         self.loss_v = torch.empty(len(R.cams), dtype=torch.float64, device=dev)
+        self.loss_m = torch.empty(1, dtype=torch.float64, device=dev)
         self.expo = torch.empty(len(R.cams), 2, dtype=torch.float64, device=dev)
         self.grads = {k: torch.empty_like(v) for k, v in params.items()}
         self.d_xi = torch.empty(len(R.cams), 6, device=dev)
@@ -147,12 +158,17 @@ class Step:
     def seed(self):
         if self.loss == "track":
             self.track()
+        elif self.loss == "mapping":
+            self.mapping()
         else:
             self.R.loss_l1(self.rgb, self.target, self.dL)
 
     def track(self):
         self.R.loss_track(self.rgb, self.T, self.target, TRACK_TAU_ALPHA, TRACK_TAU_GRAD, self.loss_v, self.expo,
                           self.dL, self.dT)
+
+    def mapping(self):
+        self.R.loss_mapping(self.rgb, self.target, MAP_LAMBDA, self.loss_m, self.dL)
 
     def run(self):
         for _, f in self.stages():
@@ -356,7 +372,7 @@ def main():
     timing = R.read_timing()
     R.set_timing(False)
     kernel_ms = {g: ms / cnt for g, (ms, cnt) in timing.items() if cnt}
-    loss_group = "loss_track" if args.loss == "track" else "loss_l1"
+    loss_group = {"track": "loss_track", "mapping": "loss_mapping"}.get(args.loss, "loss_l1")
     stage_ms = {
         "project": kernel_ms["project"],
         "bin": kernel_ms["bin_emit"] + kernel_ms["bin_sort"] + kernel_ms["bin_ranges"],
@@ -393,6 +409,30 @@ def main():
              "tau_alpha": TRACK_TAU_ALPHA, "tau_grad": TRACK_TAU_GRAD}
     track["frac"] = track["achieved"] / track["peak"]
     log(f"tracking loss: {t_ms:.4f} ms, {track['achieved']:.0f} GB/s ({track['frac']:.2f} of HBM)")
+
+    # ---------------- mapping loss: one fused kernel, VALU bound ------------
+    mgraph = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(cap):
+        st.mapping()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(mgraph, stream=cap):
+            for _ in range(20):
+                st.mapping()
+    torch.cuda.synchronize()
+    mgraph.replay()
+    ev0.record()
+    for _ in range(reps):
+        mgraph.replay()
+    ev1.record()
+    torch.cuda.synchronize()
+    m_ms = ev0.elapsed_time(ev1) / (20 * reps)
+    m_slots = SLOTS_MAP_PER_PIXEL * total_px
+    mapl = {"ms": m_ms, "bound": "alu", "achieved": m_slots / (m_ms * 1e-3) / 1e12, "peak": VALU_PEAK_TSLOTS,
+            "unit": "T VALU slots/s", "work": f"{SLOTS_MAP_PER_PIXEL} slots x {total_px} px",
+            "hbm_GBs": BYTES_MAP_PER_PIXEL * total_px / (m_ms * 1e-3) / 1e9, "lambda": MAP_LAMBDA}
+    mapl["frac"] = mapl["achieved"] / mapl["peak"]
+    log(f"mapping loss: {m_ms:.4f} ms, {mapl['achieved']:.1f} T slots/s ({mapl['frac']:.2f} of VALU issue), "
+        f"{mapl['hbm_GBs']:.0f} GB/s")
 
     # ---------------- blends / evaluations (untimed counting pass) -----
     nb = torch.empty(total_px, dtype=torch.int32, device=dev)
@@ -500,6 +540,7 @@ def main():
         "kernel_ms": kernel_ms,
         "roofline": roof,
         "tracking_loss": track,
+        "mapping_loss": mapl,
         "seeding": seed_res,
         "cpu_baseline": cpu,
     }

@@ -17,6 +17,8 @@
  *   - gsr_loss_track: the tracking loss of the appendix (Tracking and Camera
  *     Pose Optimization), Eqs. (app-bright), (app-ls), (app-trackloss),
  *     (app-weight), and its gradient seed for gsr_render_bwd.
+ *   - gsr_loss_mapping: the mapping loss of the appendix's optimisation
+ *     settings, L1 plus lambda_dssim (1 - SSIM), and its gradient seed.
  *   - gsr_seed_triangulate, gsr_seed_scale: the one-shot Gaussian seeding of
  *     Sec. "Dense Feature Matching" (Eq. (conf), two-view linear
  *     triangulation) and the appendix's initialisation (Eq.
@@ -207,6 +209,20 @@ gsr_status gsr_loss_track(gsr_plan *plan, const float *rgb, const float *T_final
                           double tau_alpha, double tau_grad, double *loss, double *exposure, float *dL_drgb,
                           float *dL_dT, void *stream);
 
+/* Mapping loss of the appendix's optimisation settings (an L1 term and an
+ * SSIM term weighted by lambda_dssim = 0.2 there), over every pixel and
+ * channel of every view, x the render (rgb) and y the target:
+ *   loss = (1 - lambda) mean |x - y| + lambda (1 - mean SSIM(x, y)).
+ * SSIM per channel (Wang et al. 2004): 11 x 11 Gaussian window of standard
+ * deviation 1.5 (weights summing to 1), C1 = 0.01^2, C2 = 0.03^2, zeros
+ * outside the image.  Outputs: loss (device, one double) and dL_drgb (like
+ * rgb, overwritten) = d loss / d rgb (d|r|/dr = 0 at r = 0), which feeds
+ * gsr_render_bwd.  lambda outside [0, 1]: GSR_EINVAL.  Uses the plan's
+ * workspace; deterministic (fixed-order sums); the arithmetic is FP32 with
+ * the loss summed in double. */
+gsr_status gsr_loss_mapping(gsr_plan *plan, const float *rgb, const float *target, double lambda, double *loss,
+                            float *dL_drgb, void *stream);
+
 /* Backward of gsr_render_fwd (call after it, on the same plan, without an
  * intervening gsr_project or gsr_bin).  T_final and n_contrib are the buffers
  * the forward wrote (read only).  dL_dT may be NULL (zero).  pose_only: HOST array
@@ -311,6 +327,7 @@ typedef enum {
     GSR_T_RASTER_BWD,   /* compositing backward kernel */
     GSR_T_PROJECT_BWD,  /* projection backward and the pose reduction */
     GSR_T_LOSS_TRACK,   /* gsr_loss_track's kernels */
+    GSR_T_LOSS_MAP,     /* gsr_loss_mapping's kernels */
     GSR_T_COUNT
 } gsr_timer;
 

@@ -43,11 +43,11 @@ struct gsr_plan {
     int64_t capacity = 0;
     int64_t total_pixels = 0;
     int32_t total_tiles = 0, tile_bits = 0, passes = 0, chunks = 0, chunk_mult = 1, max_tiles_view = 0;
-    int32_t bwd_blocks = 0;
+    int32_t bwd_blocks = 0, map_tiles = 0;
     size_t off_counters = 0, off_views = 0, off_geom = 0, off_conic = 0, off_rgbd = 0, off_qthr = 0, off_grad2d = 0;
     size_t off_stage = 0;
     size_t off_keys = 0, off_vals = 0, off_seg = 0, off_ranges = 0, off_cnt = 0;
-    size_t off_xip = 0, off_xip_sh = 0, off_order = 0, off_buckets = 0, off_track = 0, total = 0;
+    size_t off_xip = 0, off_xip_sh = 0, off_order = 0, off_buckets = 0, off_track = 0, off_map = 0, total = 0;
     char* ws = nullptr;
     Counters host_counters{};
     std::vector<uint32_t> identity_order;
@@ -254,6 +254,9 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->off_xip = take(sizeof(double) * 6 * (size_t)n_views * p->bwd_blocks);
     p->off_xip_sh = take(sizeof(double) * 6 * (size_t)n_views * p->bwd_blocks);
     p->off_track = take(sizeof(double) * GSR_TRACK_SLOTS * GSR_TRACK_BLOCKS * (size_t)n_views);
+    for (int v = 0; v < n_views; ++v)
+        p->map_tiles = std::max(p->map_tiles, ((p->vt.v[v].width + 31) / 32) * ((p->vt.v[v].height + 31) / 32));
+    p->off_map = take(sizeof(double) * 2 * (size_t)p->map_tiles * (size_t)n_views);
     p->total = o;
     p->host_counters = Counters{};
     p->host_counters.capacity = (unsigned long long)pair_capacity;
@@ -512,6 +515,44 @@ extern "C" gsr_status gsr_loss_track(gsr_plan* plan, const float* rgb, const flo
     Timed t(plan, GSR_T_LOSS_TRACK, (hipStream_t)stream);
     hipError_t e = launch_loss_track(a, plan->V, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_loss_track");
+}
+
+extern "C" gsr_status gsr_loss_mapping(gsr_plan* plan, const float* rgb, const float* target, double lambda,
+                                       double* loss, float* dL_drgb, void* stream)
+{
+    g_err.clear();
+    if (!plan) return fail(GSR_EINVAL, "null plan");
+    if (!rgb || !target || !loss || !dL_drgb) return fail(GSR_EINVAL, "null buffer");
+    if (!(lambda >= 0.0 && lambda <= 1.0)) return fail(GSR_EINVAL, "lambda must lie in [0, 1]");
+    gsr_status st = check_bound(plan);
+    if (st != GSR_OK) return st;
+    MapLossArgs a{};
+    a.views = at<ViewTable>(plan, plan->off_views);
+    a.rgb = rgb;
+    a.target = target;
+    // the Gaussian window of standard deviation 1.5 over offsets -5..5,
+    // normalised to sum 1
+    double w[11], wsum = 0.0;
+    for (int i = 0; i < 11; ++i) {
+        const double d = (double)(i - 5);
+        w[i] = std::exp(-d * d / (2.0 * 1.5 * 1.5));
+        wsum += w[i];
+    }
+    for (int i = 0; i < 11; ++i) a.w[i] = (float)(w[i] / wsum);
+    a.c1 = (float)(0.01 * 0.01);
+    a.c2 = (float)(0.03 * 0.03);
+    const double n = 3.0 * (double)plan->total_pixels;
+    a.lambda = lambda;
+    a.inv_n = 1.0 / n;
+    a.scale_ssim = (float)(-lambda / n);
+    a.scale_l1 = (float)((1.0 - lambda) / n);
+    a.max_tiles = plan->map_tiles;
+    a.part = at<double>(plan, plan->off_map);
+    a.loss = loss;
+    a.dL_drgb = dL_drgb;
+    Timed t(plan, GSR_T_LOSS_MAP, (hipStream_t)stream);
+    hipError_t e = launch_loss_mapping(a, plan->V, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_loss_mapping");
 }
 
 extern "C" gsr_status gsr_raster_bwd(gsr_plan* plan, const float* T_final, const int32_t* n_contrib,

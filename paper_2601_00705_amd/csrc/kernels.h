@@ -112,6 +112,21 @@ struct TrackArgs {
     float* dL_dT;              // like T_final, nullable
 };
 
+struct MapLossArgs {
+    const ViewTable* views;
+    const float* rgb;          // render [3][H][W] per view, concatenated
+    const float* target;       // like rgb
+    float w[11];               // window weights of offsets -5..5
+    float c1, c2;              // SSIM stabilisers
+    float scale_ssim;          // -lambda / (3 P), P = pixels of all views
+    float scale_l1;            // (1 - lambda) / (3 P)
+    double lambda, inv_n;      // lambda, 1 / (3 P)
+    int32_t max_tiles;         // most 32 x 32 tiles of one view
+    double* part;              // [views][max_tiles][2]: sum SSIM, sum |x - y| per block
+    double* loss;              // [1]
+    float* dL_drgb;            // like rgb
+};
+
 #define GSR_SEED_MAX_NEIGHBOURS 8
 #define GSR_KNN_BLOCKS 256          // blocks of the seeds' bounding-box pass
 #define GSR_KNN_LEVELS 8            // fine hashed grid levels (cell sizes h1 * 2^l)
@@ -201,6 +216,7 @@ hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, float* d_x
                               hipStream_t s);
 hipError_t launch_loss_l1(const LossArgs& a, hipStream_t s);
 hipError_t launch_loss_track(const TrackArgs& a, int n_views, hipStream_t s);
+hipError_t launch_loss_mapping(const MapLossArgs& a, int n_views, hipStream_t s);
 hipError_t launch_seed_triangulate(const SeedArgs& a, hipStream_t s);
 hipError_t launch_seed_scale(const KnnArgs& a, hipStream_t s);
 

@@ -89,6 +89,7 @@ def _load():
         "gsr_render_fwd": (st, [P, P, P, P, P, P]),
         "gsr_loss_l1": (st, [P, P, P, P, P]),
         "gsr_loss_track": (st, [P, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P, P, P]),
+        "gsr_loss_mapping": (st, [P, P, P, ctypes.c_double, P, P, P]),
         "gsr_render_bwd": (st, [P, P, P, P, P, P, P, P, P, P, P]),
         "gsr_raster_bwd": (st, [P, P, P, P, P, P]),
         "gsr_project_bwd": (st, [P, P, P, P, P, P, P]),
@@ -111,13 +112,13 @@ def _load():
 _lib = _load()
 EXPORTS = ("gsr_plan_create", "gsr_plan_destroy", "gsr_plan_workspace_bytes", "gsr_plan_bind",
            "gsr_plan_layout", "gsr_plan_get_info", "gsr_project", "gsr_bin", "gsr_render_fwd",
-           "gsr_loss_l1", "gsr_loss_track", "gsr_render_bwd", "gsr_raster_bwd", "gsr_project_bwd", "gsr_pair_count",
+           "gsr_loss_l1", "gsr_loss_track", "gsr_loss_mapping", "gsr_render_bwd", "gsr_raster_bwd", "gsr_project_bwd", "gsr_pair_count",
            "gsr_plan_set_timing", "gsr_plan_read_timing", "gsr_status_str", "gsr_last_error",
            "gsr_seed_triangulate", "gsr_seed_scale_workspace_bytes", "gsr_seed_scale")
 
 # launch groups of gsr_plan_read_timing (gsr_timer)
 TIMERS = ("project", "bin_emit", "bin_sort", "bin_ranges", "raster_fwd", "loss_l1", "clear_grad2d",
-          "raster_bwd", "project_bwd", "loss_track")
+          "raster_bwd", "project_bwd", "loss_track", "loss_mapping")
 
 
 def raw():
@@ -215,6 +216,11 @@ def gsr_loss_track(plan, rgb, T_final, target, tau_alpha, tau_grad, loss, exposu
     return check(_lib.gsr_loss_track(plan, _p(rgb), _p(T_final), _p(target), ctypes.c_double(tau_alpha),
                                      ctypes.c_double(tau_grad), _p(loss), _p(exposure), _p(dL_drgb), _p(dL_dT),
                                      ctypes.c_void_p(stream)), "gsr_loss_track")
+
+
+def gsr_loss_mapping(plan, rgb, target, lam, loss, dL_drgb, stream):
+    return check(_lib.gsr_loss_mapping(plan, _p(rgb), _p(target), ctypes.c_double(lam), _p(loss), _p(dL_drgb),
+                                       ctypes.c_void_p(stream)), "gsr_loss_mapping")
 
 
 def gsr_seed_triangulate(views, cfg, x_ref, x_nb, kappa, mean, colour, opacity_logit, valid, best, err, angle,

@@ -125,6 +125,11 @@ class Renderer:
         lib.gsr_loss_track(self.plan, rgb, T_final, target, tau_alpha, tau_grad, loss, exposure, dL_drgb, dL_dT,
                            _stream(self.device))
 
+    def loss_mapping(self, rgb, target, lam, loss, dL_drgb):
+        """Mapping loss (1 - lam) L1 + lam (1 - SSIM) over all views (loss [1]
+        float64) and its gradient seed dL_drgb for render_bwd."""
+        lib.gsr_loss_mapping(self.plan, rgb, target, lam, loss, dL_drgb, _stream(self.device))
+
     def render_bwd(self, params, poses, T_final, n_contrib, dL_drgb, dL_dT=None, pose_only=None, grads=None,
                    d_xi=None):
         g = None if grads is None else lib.Grads(*(lib._p(grads[k]) for k in PARAM_KEYS))

@@ -92,6 +92,22 @@ def test_timing_switch_without_device_work():
         lib.gsr_plan_destroy(plan)
 
 
+def test_mapping_loss_argument_errors():
+    """gsr_loss_mapping rejects lambda outside [0, 1] and null buffers before
+    touching the device (the pointers are never read)."""
+    from paper_2601_00705_amd import lib
+    raw = lib.raw()
+    plan = lib.gsr_plan_create(100, CAM, _cfg(), 10000)
+    fake = ctypes.c_void_p(16)
+    try:
+        for lam in (-0.1, 1.5, float("nan")):
+            assert raw.gsr_loss_mapping(plan, fake, fake, lam, fake, fake, None) == lib.EINVAL
+        assert raw.gsr_loss_mapping(plan, fake, None, 0.2, fake, fake, None) == lib.EINVAL
+        assert raw.gsr_loss_mapping(None, fake, fake, 0.2, fake, fake, None) == lib.EINVAL
+    finally:
+        lib.gsr_plan_destroy(plan)
+
+
 def test_track_loss_argument_errors():
     """gsr_loss_track rejects non-positive or non-finite thresholds and null
     buffers before touching the device (the pointers are never read)."""

@@ -109,11 +109,13 @@ def test_kernel_timing_eager_only():
             {k: torch.empty_like(v) for k, v in P.items()}, torch.empty(1, 6, device="cuda"))
     R.set_timing(True)
     _step(R, P, poses, target, bufs)
-    # the tracking-loss group, outside the L1 step
+    # the tracking-loss and mapping-loss groups, outside the L1 step
     loss = torch.empty(1, dtype=torch.float64, device="cuda")
     expo = torch.empty(1, 2, dtype=torch.float64, device="cuda")
     R.loss_track(bufs[0], bufs[1], target, 0.5, 0.05, loss, expo, torch.empty_like(bufs[0]),
                  torch.empty_like(bufs[1]))
+    R.loss_mapping(bufs[0], target, 0.2, torch.empty(1, dtype=torch.float64, device="cuda"),
+                   torch.empty_like(bufs[0]))
     t = R.read_timing()
     assert set(t) == set(lib.TIMERS)
     for name, (ms, cnt) in t.items():
