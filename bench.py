@@ -100,6 +100,8 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="re-run the tile/batch autotuner")
     ap.add_argument("--copy-probe", action="store_true", help="run a plain device copy of known size first")
     ap.add_argument("--no-seeding", action="store_true", help="skip the seeding measurement")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="bitwise-reproducible backward (fixed-point accumulation)")
     ap.add_argument("--loss", choices=("l1", "track", "mapping"), default="l1",
                     help="gradient seed of the step: L1 (default), the tracking loss or the mapping loss")
     return ap.parse_args()
@@ -313,7 +315,8 @@ def main():
         if tile is None:
             tuned = autotune.tune(params, cams, poses, target, w["sh_degree"], pose_only, log=log)
             tile = tuned["best"]
-    cfg = Config(tile_w=tile[0], tile_h=tile[1], batch=tile[2], sh_degree=w["sh_degree"])
+    cfg = Config(tile_w=tile[0], tile_h=tile[1], batch=tile[2], sh_degree=w["sh_degree"],
+                 deterministic=args.deterministic)
     log(f"tile {tile[0]}x{tile[1]}, LDS batch {tile[2]}")
     total_px = sum(c["width"] * c["height"] for c in cams)
 
@@ -526,7 +529,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "gaussians": n, "views": V, "pixels": total_px,
                    "tile": f"{cfg.tile_w}x{cfg.tile_h}", "batch": cfg.batch, "sh_degree": cfg.sh_degree,
-                   "mode": "batched-graph", "loss": args.loss},
+                   "mode": "batched-graph", "loss": args.loss, "deterministic": bool(args.deterministic)},
         "autotune_ms": None if tuned is None else tuned["ms"],
         "ms_per_step_p10_p50_p90": [pct[10], pct[50], pct[90]],
         "blends_per_s": blends / (ms_step * 1e-3),

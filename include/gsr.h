@@ -95,6 +95,13 @@ typedef struct {
     float alpha_max;        /* upper clamp, in (0, 1] */
     float T_min;            /* early-stop transmittance (0 disables it) */
     float bg[3];            /* background colour weighted by T_final */
+    int32_t deterministic;  /* 1: the backward accumulates the screen-space
+                               gradients exactly in fixed point (integer
+                               atomics), so that every backward output is
+                               bitwise reproducible whatever the order in
+                               which tiles run; 0: FP64 atomics (reproducible
+                               to ~1e-16 relative).  1 adds 288 bytes of
+                               workspace per slot. */
 } gsr_config;
 
 /* Gaussian parameters (device planes, see above). */

@@ -44,7 +44,7 @@ struct gsr_plan {
     int64_t total_pixels = 0;
     int32_t total_tiles = 0, tile_bits = 0, passes = 0, chunks = 0, chunk_mult = 1, max_tiles_view = 0;
     int32_t bwd_blocks = 0, map_tiles = 0;
-    size_t off_counters = 0, off_views = 0, off_geom = 0, off_conic = 0, off_rgbd = 0, off_qthr = 0, off_grad2d = 0;
+    size_t off_counters = 0, off_views = 0, off_geom = 0, off_conic = 0, off_rgbd = 0, off_qthr = 0, off_grad2d = 0, off_acc = 0;
     size_t off_stage = 0;
     size_t off_keys = 0, off_vals = 0, off_seg = 0, off_ranges = 0, off_cnt = 0;
     size_t off_xip = 0, off_xip_sh = 0, off_order = 0, off_buckets = 0, off_track = 0, off_map = 0, total = 0;
@@ -156,6 +156,7 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
         !(cfg->alpha_min <= cfg->alpha_max))
         return fail(GSR_EINVAL, "alpha bounds");
     if (!(cfg->T_min >= 0.0f) || !(cfg->T_min < 1.0f)) return fail(GSR_EINVAL, "T_min");
+    if (cfg->deterministic != 0 && cfg->deterministic != 1) return fail(GSR_EINVAL, "deterministic not 0 or 1");
     if (!(cfg->dilation >= 0.0f) || !std::isfinite(cfg->z_near)) return fail(GSR_EINVAL, "dilation / z_near");
 
     gsr_plan* p = new (std::nothrow) gsr_plan();
@@ -244,6 +245,7 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->off_qthr = take(sizeof(float) * S);
     p->off_stage = take(sizeof(StageRec) * S);
     p->off_grad2d = take(sizeof(double) * GSR_G2 * S);
+    p->off_acc = take(cfg->deterministic ? sizeof(unsigned long long) * GSR_G2 * GSR_FIX_LIMBS * S : 0);
     p->off_keys = take(sizeof(unsigned long long) * pair_capacity);
     p->off_vals = take(sizeof(uint32_t) * pair_capacity);
     p->off_seg = take(sizeof(unsigned long long) * pair_capacity);
@@ -377,6 +379,7 @@ extern "C" gsr_status gsr_project(gsr_plan* plan, const gsr_gaussians* g, const 
     a.qthr = at<float>(plan, plan->off_qthr);
     a.stage = at<StageRec>(plan, plan->off_stage);
     a.grad2d = at<double>(plan, plan->off_grad2d);
+    a.acc = plan->cfg.deterministic ? at<unsigned long long>(plan, plan->off_acc) : nullptr;
     a.counters = at<Counters>(plan, plan->off_counters);
     Timed t(plan, GSR_T_PROJECT, (hipStream_t)stream);
     hipError_t e = launch_project(a, plan->cfg.sh_degree, (hipStream_t)stream);
@@ -450,6 +453,7 @@ static RasterArgs raster_args(const gsr_plan* plan)
     a.geom = at<float4>(plan, plan->off_geom);
     a.stage = at<StageRec>(plan, plan->off_stage);
     a.grad2d = at<double>(plan, plan->off_grad2d);
+    a.acc = plan->cfg.deterministic ? at<unsigned long long>(plan, plan->off_acc) : nullptr;
     a.slots = plan->n * plan->V;
     return a;
 }

@@ -19,6 +19,10 @@
 
 #define GSR_MAX_VIEWS 64
 #define GSR_G2 9  // screen-space gradient fields per slot
+// deterministic backward: each field is a fixed-point number in 4 signed
+// 64-bit limbs of 32 significant bits each; the lowest bit weighs 2^-96
+#define GSR_FIX_LIMBS 4
+#define GSR_FIX_UNIT 96
 
 namespace gsr {
 

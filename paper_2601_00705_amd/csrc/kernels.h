@@ -14,6 +14,7 @@ struct ProjectArgs {
     float* qthr;
     StageRec* stage;
     double* grad2d;            // [slots][9], zeroed for live slots
+    unsigned long long* acc;   // [slots][GSR_FIX_LIMBS][9] (deterministic mode) or null, zeroed for live slots
     Counters* counters;
 };
 
@@ -73,6 +74,7 @@ struct RasterArgs {
     const float* dL_drgb;
     const float* dL_dT;        // nullable
     double* grad2d;            // [slots][9]
+    unsigned long long* acc;   // [slots][GSR_FIX_LIMBS][9] in deterministic mode, else null
     int64_t slots;
 };
 

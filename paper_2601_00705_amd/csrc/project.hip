@@ -89,6 +89,11 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
         a.stage[slot] = sr;
 #pragma unroll
         for (int f = 0; f < GSR_G2; ++f) a.grad2d[GSR_G2 * slot + f] = 0.0;
+        if (a.acc) {
+            ulonglong2* z = reinterpret_cast<ulonglong2*>(a.acc + GSR_G2 * GSR_FIX_LIMBS * slot);
+#pragma unroll
+            for (int k = 0; k < GSR_G2 * GSR_FIX_LIMBS / 2; ++k) z[k] = make_ulonglong2(0ull, 0ull);
+        }
         // binning level of d^T conic d: the alpha_min ellipse 2 ln(o / alpha_min)
         // widened by 5% + 0.01 so that rounding never drops a tile the
         // compositing would reach

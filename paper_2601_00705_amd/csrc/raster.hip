@@ -260,7 +260,75 @@ __device__ __forceinline__ float field_scale(int f)
     return f < 2 ? -GSR_LN2 : (f == 3 ? -1.0f : (f < 5 ? -0.5f : 1.0f));
 }
 
-template <int PPT, int GSR_BATCH>
+// Deterministic mode: the tile totals are added exactly, as fixed-point
+// numbers, so that the sums do not depend on the order in which tiles run.
+// A field is held in GSR_FIX_LIMBS signed 64-bit limbs; limb k collects the
+// bits [32 k, 32 k + 32) of every addend (the lowest bit weighing
+// 2^-GSR_FIX_UNIT) with its sign, without carries, which leaves 31 bits of
+// headroom for the count of addends.  A float addend M 2^(E - 150) (M its
+// 24-bit significand) spans at most two limbs: two integer atomics, no
+// return value.  A slot's limbs are stored limb-major ([limb][field], 72
+// bytes per limb), so that the 9 lanes of an entry's first atomic mostly
+// hit one 72-byte block, as the FP64 path's do.  Bits below 2^-96 are
+// dropped (truncation toward zero); magnitudes of 2^32 and beyond,
+// infinities and NaN saturate to just below 2^32.
+__device__ __forceinline__ void fixed_add(unsigned long long* limbs, int stride, float v)
+{
+    const uint32_t bits = __float_as_uint(v);
+    const int E = (int)((bits >> 23) & 0xffu);
+    if (E == 0) return;  // zero or subnormal: below the lowest bit
+    uint32_t M = (bits & 0x7fffffu) | 0x800000u;
+    int p = E - 150 + GSR_FIX_UNIT;  // weight 2^(p - 96) of M's lowest bit
+    if (p > 32 * (GSR_FIX_LIMBS - 1) + 8) {
+        M = 0xffffffu;
+        p = 32 * (GSR_FIX_LIMBS - 1) + 8;
+    }
+    if (p < 0) {
+        if (p <= -24) return;
+        M >>= -p;
+        p = 0;
+    }
+    const int k = p >> 5;
+    const unsigned long long wide = (unsigned long long)M << (p & 31);
+    const unsigned long long c0 = wide & 0xffffffffull, c1 = wide >> 32;
+    const bool neg = (bits >> 31) != 0u;
+    atomicAdd(&limbs[k * stride], neg ? 0ull - c0 : c0);
+    if (c1 != 0ull && k + 1 < GSR_FIX_LIMBS) atomicAdd(&limbs[(k + 1) * stride], neg ? 0ull - c1 : c1);
+}
+
+// the value of a fixed-point field: carries propagated upwards (limbs 0..2
+// end in [0, 2^32), the top limb keeps the sign); a negative total is
+// negated and normalised again, so that the magnitude is summed from the
+// top without cancellation
+__device__ __forceinline__ double fixed_value(const unsigned long long* limbs, int stride)
+{
+    long long c[GSR_FIX_LIMBS];
+#pragma unroll
+    for (int k = 0; k < GSR_FIX_LIMBS; ++k) c[k] = (long long)limbs[k * stride];
+#pragma unroll
+    for (int k = 0; k + 1 < GSR_FIX_LIMBS; ++k) {
+        c[k + 1] += c[k] >> 32;
+        c[k] &= 0xffffffffll;
+    }
+    const bool neg = c[GSR_FIX_LIMBS - 1] < 0;
+    if (neg) {
+#pragma unroll
+        for (int k = 0; k < GSR_FIX_LIMBS; ++k) c[k] = -c[k];
+#pragma unroll
+        for (int k = 0; k + 1 < GSR_FIX_LIMBS; ++k) {
+            c[k + 1] += c[k] >> 32;
+            c[k] &= 0xffffffffll;
+        }
+    }
+    // the top limb's lowest bit weighs 2^(32 (limbs - 1) - unit) = 1
+    static_assert(32 * (GSR_FIX_LIMBS - 1) == GSR_FIX_UNIT, "the top limb counts units of 1");
+    double v = (double)c[0];
+#pragma unroll
+    for (int k = 1; k < GSR_FIX_LIMBS; ++k) v = (double)c[k] + v * 0x1p-32;
+    return neg ? -v : v;
+}
+
+template <int PPT, int GSR_BATCH, bool DET>
 __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
 {
     __shared__ LdsRec rec[GSR_BATCH];
@@ -367,7 +435,8 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
             if ((lane & 7) == 0 || lane == 1) {
                 const int f = lane == 1 ? 8 : lane >> 3;
                 const float scale = f == 5 ? r.p3.z : field_scale(f);
-                atomic_add_f64(&a.grad2d[GSR_G2 * (int64_t)slot + f], (double)(s * scale));
+                if (DET) fixed_add(a.acc + GSR_G2 * GSR_FIX_LIMBS * (int64_t)slot + f, GSR_G2, s * scale);
+                else atomic_add_f64(&a.grad2d[GSR_G2 * (int64_t)slot + f], (double)(s * scale));
             }
         }
         __syncthreads();
@@ -393,16 +462,22 @@ static hipError_t launch_fwd_t(const RasterArgs& a, int tiles, int batch, hipStr
     return a.n_blend ? launch_fwd_c<PPT, true>(a, tiles, batch, s) : launch_fwd_c<PPT, false>(a, tiles, batch, s);
 }
 
-template <int PPT>
-static hipError_t launch_bwd_t(const RasterArgs& a, int tiles, int batch, hipStream_t s)
+template <int PPT, bool DET>
+static hipError_t launch_bwd_d(const RasterArgs& a, int tiles, int batch, hipStream_t s)
 {
     switch (batch) {
-    case 64: hipLaunchKernelGGL((k_raster_bwd<PPT, 64>), dim3(tiles), dim3(64), 0, s, a); break;
-    case 128: hipLaunchKernelGGL((k_raster_bwd<PPT, 128>), dim3(tiles), dim3(64), 0, s, a); break;
-    case 256: hipLaunchKernelGGL((k_raster_bwd<PPT, 256>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 64: hipLaunchKernelGGL((k_raster_bwd<PPT, 64, DET>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 128: hipLaunchKernelGGL((k_raster_bwd<PPT, 128, DET>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 256: hipLaunchKernelGGL((k_raster_bwd<PPT, 256, DET>), dim3(tiles), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipSuccess;
+}
+
+template <int PPT>
+static hipError_t launch_bwd_t(const RasterArgs& a, int tiles, int batch, hipStream_t s)
+{
+    return a.acc ? launch_bwd_d<PPT, true>(a, tiles, batch, s) : launch_bwd_d<PPT, false>(a, tiles, batch, s);
 }
 
 hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s)
@@ -434,13 +509,44 @@ __global__ void k_clear_grad2d(const Counters* counters, const float4* geom, dou
     }
 }
 
+// deterministic mode: the same for the fixed-point accumulators
+__global__ void k_clear_acc(const Counters* counters, const float4* geom, unsigned long long* acc, int64_t slots)
+{
+    if (!counters->grad_dirty) return;
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        if (geom[s].z >= 0.0f) {
+            ulonglong2* p = reinterpret_cast<ulonglong2*>(acc + GSR_G2 * GSR_FIX_LIMBS * s);
+#pragma unroll
+            for (int k = 0; k < GSR_G2 * GSR_FIX_LIMBS / 2; ++k) p[k] = make_ulonglong2(0ull, 0ull);
+        }
+    }
+}
+
+// deterministic mode: the accumulators of every projected slot into grad2d
+__global__ void k_fix_to_grad2d(const float4* geom, const unsigned long long* acc, double* grad2d, int64_t slots)
+{
+    for (int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; s < slots;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        if (geom[s].z >= 0.0f) {
+#pragma unroll
+            for (int f = 0; f < GSR_G2; ++f)
+                grad2d[GSR_G2 * s + f] = fixed_value(acc + GSR_G2 * GSR_FIX_LIMBS * s + f, GSR_G2);
+        }
+    }
+}
+
 hipError_t launch_clear_grad2d(const RasterArgs& a, hipStream_t s)
 {
     if (a.slots <= 0) return hipSuccess;
     int64_t blocks = (a.slots + 255) / 256;
     if (blocks > 8192) blocks = 8192;
-    hipLaunchKernelGGL(k_clear_grad2d, dim3((unsigned)blocks), dim3(256), 0, s, a.counters, a.geom, a.grad2d,
-                       a.slots);
+    if (a.acc)
+        hipLaunchKernelGGL(k_clear_acc, dim3((unsigned)blocks), dim3(256), 0, s, a.counters, a.geom, a.acc,
+                           a.slots);
+    else
+        hipLaunchKernelGGL(k_clear_grad2d, dim3((unsigned)blocks), dim3(256), 0, s, a.counters, a.geom, a.grad2d,
+                           a.slots);
     return hipGetLastError();
 }
 
@@ -453,6 +559,12 @@ hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, 
     case 128: e = launch_bwd_t<2>(a, total_tiles, batch, s); break;
     case 256: e = launch_bwd_t<4>(a, total_tiles, batch, s); break;
     default: return hipErrorInvalidValue;
+    }
+    if (e == hipSuccess && a.acc && a.slots > 0) {
+        int64_t blocks = (a.slots + 255) / 256;
+        if (blocks > 8192) blocks = 8192;
+        hipLaunchKernelGGL(k_fix_to_grad2d, dim3((unsigned)blocks), dim3(256), 0, s, a.geom, a.acc, a.grad2d,
+                           a.slots);
     }
     return e != hipSuccess ? e : hipGetLastError();
 }

@@ -32,7 +32,7 @@ class Config(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("sh_degree", ctypes.c_int32), ("z_near", ctypes.c_float), ("dilation", ctypes.c_float),
                 ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("T_min", ctypes.c_float),
-                ("bg", ctypes.c_float * 3)]
+                ("bg", ctypes.c_float * 3), ("deterministic", ctypes.c_int32)]
 
 
 class Gaussians(ctypes.Structure):
@@ -152,6 +152,7 @@ def make_config(cfg):
     c.alpha_min, c.alpha_max, c.T_min = cfg.alpha_min, cfg.alpha_max, cfg.T_min
     for k in range(3):
         c.bg[k] = float(cfg.bg[k])
+    c.deterministic = 1 if getattr(cfg, "deterministic", False) else 0
     return c
 
 

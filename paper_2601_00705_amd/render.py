@@ -21,7 +21,8 @@ PARAM_KEYS = ("mean", "quat", "log_scale", "opacity_logit", "colour")
 class Config:
     """Renderer settings.  Defaults: 16x16 tiles, near plane 0.2, screen
     covariance dilation 0.3 px^2, alpha in [1/255, 0.99], early stop at
-    T < 1e-4, black background, RGB colour."""
+    T < 1e-4, black background, RGB colour, FP64-atomic backward (set
+    deterministic for the bitwise-reproducible fixed-point one)."""
     tile_w: int = 16
     tile_h: int = 16
     batch: int = 128
@@ -32,6 +33,7 @@ class Config:
     alpha_max: float = 0.99
     T_min: float = 1e-4
     bg: tuple = (0.0, 0.0, 0.0)
+    deterministic: bool = False
 
 
 def _stream(device):
