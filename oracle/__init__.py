@@ -236,3 +236,4 @@ def sh_basis(deg, direction):
 from .track import track_loss, track_view, grad_norm as track_grad_norm, exposure as track_exposure  # noqa: E402
 from . import seed as seeding  # noqa: E402
 from . import ssim  # noqa: E402,F401
+from . import optim  # noqa: E402,F401

@@ -1,0 +1,89 @@
+"""FP64 oracle of the map-maintenance steps: the Adam update with gradient
+clipping and the EMA anchor, the co-visibility score, and pruning.
+
+TEST INFRASTRUCTURE ONLY.  The test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers; the product path never imports it.
+
+Follows:
+  - the appendix's optimisation settings: Adam (Kingma and Ba, Algorithm 1)
+    with (beta1, beta2) = (0.9, 0.999), per-group learning rates (2e-3 for
+    colour and opacity, 1e-3 for positions and rotations) and gradient norm
+    clipping at 1.0;
+  - Eq. (app-ema): after each mapping step the anchor of every mean moves to
+    (1 - eta) anchor + eta mean;
+  - Eq. (iou): IoU of the visible-pixel sets of two frames, a pixel visible
+    when its accumulated opacity exceeds a threshold;
+  - the pruning rule of Sec. "Insertion, Lightweight Merging, and Pruning":
+    a Gaussian is removed when m_i < m_min, v_i < v_min,
+    tr(Sigma_i^W) > sigma_max^2 or alpha_i < alpha_min.
+
+Readings where the paper is silent:
+  - epsilon = 1e-8 and the bias-corrected step of Algorithm 1; the log-scales
+    take the positions' learning rate (the geometry group); every rate is an
+    argument, the scheduled value of the call;
+  - clipping is on the global L2 norm of all parameter gradients of the call,
+    scale min(1, max_norm / (norm + 1e-6)), applied before the moments;
+  - the EMA runs on the updated means;
+  - accumulated opacity is 1 - T_final; the comparison 1 - T > tau is taken
+    in float32, the renderer's precision; an empty union scores IoU 0;
+  - tr(Sigma^W) = sum_k exp(2 log_scale_k) (Sigma = R diag(s^2) R^T), alpha =
+    sigmoid(opacity_logit); the kept Gaussians keep their order.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+PLANES = ("mean", "quat", "log_scale", "opacity_logit", "colour")
+
+
+def clip_scale(grads, max_norm):
+    """min(1, max_norm / (norm + 1e-6)) over all planes (1 if max_norm <= 0),
+    and the norm."""
+    norm = np.sqrt(sum(float((np.asarray(g, np.float64) ** 2).sum()) for g in grads.values()))
+    if max_norm <= 0:
+        return 1.0, norm
+    return min(1.0, max_norm / (norm + 1e-6)), norm
+
+
+def adam_step(params, grads, m, v, anchor, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, max_norm=1.0, ema=0.0):
+    """One step.  params, grads, m, v: dicts of arrays over PLANES; lr: dict
+    of rates per plane; anchor: [3][n] or None.  Returns new (params, m, v,
+    anchor, norm) in float64."""
+    c, norm = clip_scale(grads, max_norm)
+    out_p, out_m, out_v = {}, {}, {}
+    for k in PLANES:
+        g = c * np.asarray(grads[k], np.float64)
+        mk = beta1 * np.asarray(m[k], np.float64) + (1.0 - beta1) * g
+        vk = beta2 * np.asarray(v[k], np.float64) + (1.0 - beta2) * g * g
+        mhat = mk / (1.0 - beta1 ** step)
+        vhat = vk / (1.0 - beta2 ** step)
+        out_p[k] = np.asarray(params[k], np.float64) - lr[k] * mhat / (np.sqrt(vhat) + eps)
+        out_m[k], out_v[k] = mk, vk
+    new_anchor = None
+    if anchor is not None:
+        new_anchor = (1.0 - ema) * np.asarray(anchor, np.float64) + ema * out_p["mean"]
+    return out_p, out_m, out_v, new_anchor, norm
+
+
+def covis(T_key, T_frames, tau):
+    """T_key [P] and T_frames [F][P] (float32 transmittance): per frame
+    (intersection, union, IoU)."""
+    t = np.float32(tau)
+    a = (np.float32(1.0) - np.asarray(T_key, np.float32)) > t
+    out = []
+    for T in np.asarray(T_frames, np.float32):
+        b = (np.float32(1.0) - T) > t
+        inter = int(np.count_nonzero(a & b))
+        uni = int(np.count_nonzero(a | b))
+        out.append((inter, uni, inter / uni if uni else 0.0))
+    return out
+
+
+def prune_keep(m_obs, v_vis, log_scale, opacity_logit, m_min, v_min, sigma_max, alpha_min):
+    """Boolean keep mask of the pruning rule."""
+    ls = np.asarray(log_scale, np.float64)
+    tr = np.exp(2.0 * ls).sum(axis=0)
+    alpha = 1.0 / (1.0 + np.exp(-np.asarray(opacity_logit, np.float64)))
+    drop = ((np.asarray(m_obs) < m_min) | (np.asarray(v_vis, np.float64) < v_min) |
+            (tr > sigma_max * sigma_max) | (alpha < alpha_min))
+    return ~drop
