@@ -218,6 +218,75 @@ def measured_traffic(kernel, workload, cfg):
         return None
 
 
+def _graph_ms(torch, fn, reps, calls=20):
+    """Average device time of fn() replayed from a graph of `calls` calls."""
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        fn()
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            for _ in range(calls):
+                fn()
+    torch.cuda.synchronize()
+    g.replay()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.replay()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / (calls * reps)
+
+
+def maintenance_measurement(torch, w, params, T_final, cams, reps, log):
+    """Map maintenance at the workload's size: one optimiser step over every
+    Gaussian parameter (with the anchor), the co-visibility of every view
+    against the first one of its size, and pruning with the compaction of
+    the log-scales.  All bound by HBM traffic; bytes per unit:
+      Adam: per float, read p, g, m, v and write p, m, v (28 B), plus the
+            norm pass reading g (4 B); per mean float the anchor (8 B);
+      co-visibility: per frame pixel, T of the frame and of the key (8 B);
+      pruning: per Gaussian, two passes reading m, v, three log-scales and
+            the opacity logit (2 x 24 B), the kept index (4 B), and the
+            compaction of 3 log-scale rows (read + write 24 B)."""
+    import numpy as np
+    from paper_2601_00705_amd import maintain
+    n = int(params["opacity_logit"].shape[0])
+    P = {k: v.clone() for k, v in params.items()}
+    G = {k: torch.randn_like(v) * 1e-3 for k, v in P.items()}
+    opt = maintain.Adam(P, ema=0.05)
+    floats = sum(v.numel() for v in P.values())
+    t_adam = _graph_ms(torch, lambda: opt.step(P, G), reps)
+    b_adam = 32 * floats + 8 * P["mean"].numel()
+    # co-visibility: views of the key's size
+    sizes = [(c["width"], c["height"]) for c in cams]
+    key = sizes[0]
+    idx = [v for v, s in enumerate(sizes) if s == key]
+    offs = np.cumsum([0] + [wd * ht for wd, ht in sizes])
+    frames = torch.stack([T_final[offs[v]:offs[v + 1]] for v in idx]).contiguous()
+    t_cov = _graph_ms(torch, lambda: maintain.covis(frames[0], frames, 0.05), reps)
+    b_cov = 8 * frames.numel()
+    m_obs = torch.randint(0, 6, (n,), dtype=torch.int32, device=P["mean"].device)
+    v_vis = torch.rand(n, device=P["mean"].device) * 2
+    state = {}
+
+    def prune_and_compact():
+        keep, kept = maintain.prune(m_obs, v_vis, P["log_scale"], P["opacity_logit"], 2, 0.3, 1.5, 0.05)
+        state["ls"] = maintain.compact(P["log_scale"], keep, kept)
+
+    t_pr = _graph_ms(torch, prune_and_compact, reps)
+    b_pr = (2 * 24 + 4 + 24) * n
+    out = {}
+    for name, t, b, unit in (("adam", t_adam, b_adam, f"{floats} floats"),
+                             ("covis", t_cov, b_cov, f"{len(idx)} frames x {key[0]}x{key[1]}"),
+                             ("prune_compact", t_pr, b_pr, f"{n} Gaussians")):
+        out[name] = {"ms": t, "bound": "hbm", "achieved": b / (t * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, "work": unit}
+        log(f"maintenance {name}: {t:.4f} ms, {out[name]['achieved']:.0f} GB/s ({out[name]['frac']:.2f} of HBM)")
+    return out
+
+
 def seeding_measurement(torch, reps, log):
     """Seeding at the mapping workload's shape: 500,000 reference pixels of a
     1200x680 keyframe with 4 neighbours (synthetic correspondences of the
@@ -492,6 +561,7 @@ def main():
 
     # ---------------- seeding at the mapping workload's shape ----------
     seed_res = None if args.no_seeding else seeding_measurement(torch, max(3, args.steps // 4), log)
+    maint = maintenance_measurement(torch, w, params, st.T, R.cams, max(3, args.steps // 4), log)
 
     # ---------------- CPU baseline: the oracle on a bounded sample -----
     cpu = None
@@ -545,6 +615,7 @@ def main():
         "tracking_loss": track,
         "mapping_loss": mapl,
         "seeding": seed_res,
+        "maintenance": maint,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

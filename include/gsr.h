@@ -19,6 +19,10 @@
  *     (app-weight), and its gradient seed for gsr_render_bwd.
  *   - gsr_loss_mapping: the mapping loss of the appendix's optimisation
  *     settings, L1 plus lambda_dssim (1 - SSIM), and its gradient seed.
+ *   - gsr_adam_step, gsr_covis, gsr_prune, gsr_compact: map maintenance,
+ *     the optimiser step of the appendix's settings with the anchor of Eq.
+ *     (app-ema), the co-visibility score of Eq. (iou), and the pruning rule
+ *     of Sec. "Insertion, Lightweight Merging, and Pruning".
  *   - gsr_seed_triangulate, gsr_seed_scale: the one-shot Gaussian seeding of
  *     Sec. "Dense Feature Matching" (Eq. (conf), two-view linear
  *     triangulation) and the appendix's initialisation (Eq.
@@ -309,6 +313,85 @@ gsr_status gsr_seed_triangulate(int64_t n, int32_t n_neighbours, const gsr_seed_
 size_t gsr_seed_scale_workspace_bytes(int64_t n);
 gsr_status gsr_seed_scale(int64_t n, const float *mean, const int32_t *valid, float floor_scale, void *workspace,
                           size_t workspace_bytes, float *log_scale, void *stream);
+
+/* ---- map maintenance (independent of any plan) ----------------------- */
+
+/* Five parameter planes in the layout of gsr_gaussians: mean [3][n],
+ * quat [4][n], log_scale [3][n], opacity_logit [n], colour [colour_rows][n]
+ * (3 for RGB, 3 (d+1)^2 for SH); device pointers. */
+typedef struct {
+    float *mean, *quat, *log_scale, *opacity_logit, *colour;
+} gsr_planes;
+
+typedef struct {
+    float lr[5];           /* learning rate of each plane (mean, quat, log_scale,
+                              opacity_logit, colour): the scheduled value of this
+                              step; the appendix's settings are 1e-3 for
+                              positions and rotations, 2e-3 for colour and
+                              opacity */
+    double beta1, beta2;   /* in [0, 1); the appendix's 0.9, 0.999 (double, so
+                              that 1 - beta is formed exactly before rounding
+                              to the FP32 arithmetic) */
+    float eps;             /* > 0; 1e-8 */
+    float max_grad_norm;   /* global L2 clipping norm (the appendix's 1.0); <= 0:
+                              no clipping */
+    float ema;             /* eta of Eq. (app-ema) in [0, 1] */
+    int32_t step;          /* t >= 1, for the bias corrections */
+} gsr_adam_config;
+
+#define GSR_ADAM_WORKSPACE_BYTES 16384
+
+/* One optimiser step of the appendix's optimisation settings (Adam, Kingma
+ * and Ba, Algorithm 1, with per-plane learning rates and gradient norm
+ * clipping), then the anchor update of Eq. (app-ema) on the new means:
+ *   c = min(1, max_grad_norm / (||g||_2 + 1e-6)) over all planes,
+ *   m = b1 m + (1 - b1) c g,  v = b2 v + (1 - b2) (c g)^2,
+ *   p -= lr / (1 - b1^t) * m / (sqrt(v) / sqrt(1 - b2^t) + eps),
+ *   anchor = (1 - ema) anchor + ema mean.
+ * params, m, v are updated in place; grads are read only (their planes given
+ * through the same struct).  anchor: device [3][n] or NULL.  workspace:
+ * device, GSR_ADAM_WORKSPACE_BYTES, 8-byte aligned.  norm: device double [1]
+ * or NULL, receives ||g||_2 before clipping.  FP32 state and arithmetic, the
+ * norm in double and in a fixed order (deterministic).  Invalid settings or
+ * a null plane: GSR_EINVAL, nothing enqueued. */
+gsr_status gsr_adam_step(int64_t n, int32_t colour_rows, const gsr_planes *params, const gsr_planes *grads,
+                         const gsr_planes *m, const gsr_planes *v, float *anchor, const gsr_adam_config *cfg,
+                         void *workspace, double *norm, void *stream);
+
+/* Co-visibility score of Eq. (iou) between a key frame and n_frames frames
+ * of the same size: a pixel is visible when its accumulated opacity 1 - T
+ * exceeds tau (compared in float32).  T_key [pixels], T_frames
+ * [n_frames][pixels] (device, e.g. T_final of gsr_render_fwd).  Outputs
+ * (device): counts [n_frames][2] = (|V_key & V_f|, |V_key | V_f|), exact;
+ * iou [n_frames] = intersection / union (0 for an empty union). */
+gsr_status gsr_covis(int64_t pixels, int32_t n_frames, const float *T_key, const float *T_frames, float tau,
+                     uint64_t *counts, double *iou, void *stream);
+
+typedef struct {
+    int32_t m_min;         /* observation count below which a Gaussian goes */
+    float v_min;           /* cumulative visibility below which it goes */
+    float sigma_max;       /* trace of the world covariance above sigma_max^2 */
+    float alpha_min;       /* opacity below which it goes */
+} gsr_prune_config;
+
+/* Pruning rule of Sec. "Insertion, Lightweight Merging, and Pruning": the
+ * Gaussian i is dropped when m_obs[i] < m_min, v_vis[i] < v_min,
+ * exp(2 s0) + exp(2 s1) + exp(2 s2) > sigma_max^2 (the trace of
+ * R diag(s^2) R^T) or sigmoid(opacity_logit[i]) < alpha_min, decided in
+ * double.  m_obs, v_vis: the caller's statistics [n]; log_scale [3][n],
+ * opacity_logit [n].  Outputs (device): keep_index [n], the kept indices in
+ * increasing order in its first *kept entries, and kept [1].  workspace:
+ * device, gsr_prune_workspace_bytes(n) bytes. */
+size_t gsr_prune_workspace_bytes(int64_t n);
+gsr_status gsr_prune(int64_t n, const int32_t *m_obs, const float *v_vis, const float *log_scale,
+                     const float *opacity_logit, const gsr_prune_config *cfg, int32_t *keep_index, int64_t *kept,
+                     void *workspace, void *stream);
+
+/* Compaction after gsr_prune: dst[r][j] = src[r][keep_index[j]] for
+ * j < *kept (device value), r < rows; src and dst [rows][n] (device, not
+ * overlapping); columns from *kept on are left as they are. */
+gsr_status gsr_compact(int64_t n, int32_t rows, const float *src, const int32_t *keep_index, const int64_t *kept,
+                       float *dst, void *stream);
 
 /* Synchronises `stream`, then reports the pair count of the last binning
  * and whether it exceeded the capacity. */

@@ -856,3 +856,130 @@ extern "C" gsr_status gsr_seed_scale(int64_t n, const float* mean, const int32_t
     hipError_t e = launch_seed_scale(a, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_seed_scale");
 }
+
+// ---- map maintenance ------------------------------------------------------
+
+extern "C" gsr_status gsr_adam_step(int64_t n, int32_t colour_rows, const gsr_planes* params,
+                                    const gsr_planes* grads, const gsr_planes* m, const gsr_planes* v, float* anchor,
+                                    const gsr_adam_config* cfg, void* workspace, double* norm, void* stream)
+{
+    g_err.clear();
+    if (!params || !grads || !m || !v || !cfg || !workspace) return fail(GSR_EINVAL, "null argument");
+    if (n < 0 || n > (1ll << 36) || colour_rows < 1 || colour_rows > 48) return fail(GSR_EINVAL, "n or colour_rows");
+    if (((uintptr_t)workspace & 7) != 0) return fail(GSR_EINVAL, "workspace not 8-byte aligned");
+    if (cfg->step < 1) return fail(GSR_EINVAL, "step must be at least 1");
+    if (!(cfg->beta1 >= 0.0 && cfg->beta1 < 1.0) || !(cfg->beta2 >= 0.0 && cfg->beta2 < 1.0) ||
+        !(cfg->eps > 0.0f) || !(cfg->ema >= 0.0f && cfg->ema <= 1.0f) || !std::isfinite(cfg->max_grad_norm))
+        return fail(GSR_EINVAL, "adam settings");
+    for (int k = 0; k < 5; ++k)
+        if (!std::isfinite(cfg->lr[k])) return fail(GSR_EINVAL, "learning rate");
+    if (n == 0) return GSR_OK;
+    const gsr_planes* sets[4] = {params, grads, m, v};
+    const int rows[5] = {3, 4, 3, 1, colour_rows};
+    AdamArgs a{};
+    bool vec = true;
+    for (int k = 0; k < 5; ++k) {
+        float* ptr[4];
+        for (int j = 0; j < 4; ++j) {
+            const gsr_planes* q = sets[j];
+            ptr[j] = k == 0 ? q->mean : k == 1 ? q->quat : k == 2 ? q->log_scale : k == 3 ? q->opacity_logit : q->colour;
+            if (!ptr[j]) return fail(GSR_EINVAL, "null plane");
+            if (((uintptr_t)ptr[j] & 15) != 0) vec = false;
+        }
+        a.p[k] = ptr[0];
+        a.g[k] = ptr[1];
+        a.m[k] = ptr[2];
+        a.v[k] = ptr[3];
+        a.len[k] = rows[k] * n;
+        if (a.len[k] % 4 != 0) vec = false;
+        a.step_size[k] = (float)((double)cfg->lr[k] / (1.0 - std::pow(cfg->beta1, cfg->step)));
+    }
+    if (anchor && ((uintptr_t)anchor & 15) != 0) vec = false;
+    a.inv_sqrt_bc2 = (float)(1.0 / std::sqrt(1.0 - std::pow(cfg->beta2, cfg->step)));
+    a.beta1 = (float)cfg->beta1;
+    a.beta2 = (float)cfg->beta2;
+    a.omb1 = (float)(1.0 - cfg->beta1);
+    a.omb2 = (float)(1.0 - cfg->beta2);
+    a.eps = cfg->eps;
+    a.max_norm = cfg->max_grad_norm;
+    a.ema = cfg->ema;
+    a.anchor = anchor;
+    a.part = (double*)workspace;
+    a.norm = norm;
+    hipError_t e = launch_adam(a, vec, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_adam_step");
+}
+
+extern "C" gsr_status gsr_covis(int64_t pixels, int32_t n_frames, const float* T_key, const float* T_frames,
+                                float tau, uint64_t* counts, double* iou, void* stream)
+{
+    g_err.clear();
+    if (!T_key || !T_frames || !counts || !iou) return fail(GSR_EINVAL, "null argument");
+    if (pixels < 0 || n_frames < 0 || n_frames > 65535 || !std::isfinite(tau))
+        return fail(GSR_EINVAL, "pixels, n_frames or tau");
+    if (n_frames == 0) return GSR_OK;
+    CovisArgs a{};
+    a.pixels = pixels;
+    a.frames = n_frames;
+    a.tau = tau;
+    a.T_key = T_key;
+    a.T_frames = T_frames;
+    a.counts = (unsigned long long*)counts;
+    a.iou = iou;
+    hipError_t e = launch_covis(a, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_covis");
+}
+
+extern "C" size_t gsr_prune_workspace_bytes(int64_t n)
+{
+    if (n < 0 || n > (1ll << 31) - 1) return 0;
+    return sizeof(uint32_t) * (size_t)((n + GSR_PRUNE_CHUNK - 1) / GSR_PRUNE_CHUNK + 1);
+}
+
+extern "C" gsr_status gsr_prune(int64_t n, const int32_t* m_obs, const float* v_vis, const float* log_scale,
+                                const float* opacity_logit, const gsr_prune_config* cfg, int32_t* keep_index,
+                                int64_t* kept, void* workspace, void* stream)
+{
+    g_err.clear();
+    if (!m_obs || !v_vis || !log_scale || !opacity_logit || !cfg || !keep_index || !kept || !workspace)
+        return fail(GSR_EINVAL, "null argument");
+    if (n <= 0 || n > (1ll << 31) - 1) return fail(GSR_EINVAL, "n must lie in [1, 2^31)");
+    if (!std::isfinite(cfg->v_min) || !std::isfinite(cfg->sigma_max) || !std::isfinite(cfg->alpha_min))
+        return fail(GSR_EINVAL, "prune settings");
+    PruneArgs a{};
+    a.n = n;
+    a.blocks = (int32_t)((n + GSR_PRUNE_CHUNK - 1) / GSR_PRUNE_CHUNK);
+    a.m_obs = m_obs;
+    a.v_vis = v_vis;
+    a.log_scale = log_scale;
+    a.opacity_logit = opacity_logit;
+    a.m_min = cfg->m_min;
+    a.v_min = cfg->v_min;
+    a.sigma_max2 = (double)cfg->sigma_max * (double)cfg->sigma_max;
+    a.alpha_min = cfg->alpha_min;
+    a.block_count = (uint32_t*)workspace;
+    a.keep_index = keep_index;
+    a.kept = (long long*)kept;
+    hipError_t e = launch_prune(a, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_prune");
+}
+
+extern "C" gsr_status gsr_compact(int64_t n, int32_t rows, const float* src, const int32_t* keep_index,
+                                  const int64_t* kept, float* dst, void* stream)
+{
+    g_err.clear();
+    if (!src || !keep_index || !kept || !dst) return fail(GSR_EINVAL, "null argument");
+    if (n <= 0 || n > (1ll << 31) - 1 || rows < 1 || rows > 65535) return fail(GSR_EINVAL, "n or rows");
+    const size_t span = sizeof(float) * (size_t)rows * (size_t)n;
+    if ((uintptr_t)src < (uintptr_t)dst + span && (uintptr_t)dst < (uintptr_t)src + span)
+        return fail(GSR_EINVAL, "src and dst overlap");
+    CompactArgs a{};
+    a.n = n;
+    a.rows = rows;
+    a.src = src;
+    a.keep_index = keep_index;
+    a.kept = (const long long*)kept;
+    a.dst = dst;
+    hipError_t e = launch_compact(a, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_compact");
+}

@@ -129,6 +129,57 @@ struct MapLossArgs {
     float* dL_drgb;            // like rgb
 };
 
+#define GSR_ADAM_BLOCKS 1024         // blocks of the gradient-norm pass
+#define GSR_PRUNE_CHUNK 2048         // Gaussians per block of the pruning scan
+
+struct AdamArgs {
+    float* p[5];               // planes: mean, quat, log_scale, opacity_logit, colour
+    const float* g[5];
+    float* m[5];
+    float* v[5];
+    int64_t len[5];            // floats per plane
+    float step_size[5];        // lr / (1 - beta1^t) per plane
+    float inv_sqrt_bc2;        // 1 / sqrt(1 - beta2^t)
+    float beta1, beta2, omb1, omb2;  // beta and 1 - beta, each rounded once from double
+    float eps, max_norm, ema;
+    float* anchor;             // [3][n] or null
+    double* part;              // [GSR_ADAM_BLOCKS + 1]: norm partials, then the clip factor
+    double* norm;              // [1] or null
+};
+
+struct CovisArgs {
+    int64_t pixels;
+    int32_t frames;
+    float tau;
+    const float* T_key;        // [pixels]
+    const float* T_frames;     // [frames][pixels]
+    unsigned long long* counts;  // [frames][2]: intersection, union
+    double* iou;               // [frames]
+};
+
+struct PruneArgs {
+    int64_t n;
+    int32_t blocks;            // ceil(n / GSR_PRUNE_CHUNK)
+    const int32_t* m_obs;
+    const float* v_vis;
+    const float* log_scale;    // [3][n]
+    const float* opacity_logit;
+    int32_t m_min;
+    double v_min, sigma_max2, alpha_min;
+    uint32_t* block_count;     // [blocks]: kept per block, then offsets
+    int32_t* keep_index;       // [n]: kept indices in order
+    long long* kept;           // [1]
+};
+
+struct CompactArgs {
+    int64_t n;
+    int32_t rows;
+    const float* src;          // [rows][n]
+    const int32_t* keep_index;
+    const long long* kept;
+    float* dst;                // [rows][n], columns < kept written
+};
+
 #define GSR_SEED_MAX_NEIGHBOURS 8
 #define GSR_KNN_BLOCKS 256          // blocks of the seeds' bounding-box pass
 #define GSR_KNN_LEVELS 8            // fine hashed grid levels (cell sizes h1 * 2^l)
@@ -219,6 +270,10 @@ hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, float* d_x
 hipError_t launch_loss_l1(const LossArgs& a, hipStream_t s);
 hipError_t launch_loss_track(const TrackArgs& a, int n_views, hipStream_t s);
 hipError_t launch_loss_mapping(const MapLossArgs& a, int n_views, hipStream_t s);
+hipError_t launch_adam(const AdamArgs& a, bool vec, hipStream_t s);
+hipError_t launch_covis(const CovisArgs& a, hipStream_t s);
+hipError_t launch_prune(const PruneArgs& a, hipStream_t s);
+hipError_t launch_compact(const CompactArgs& a, hipStream_t s);
 hipError_t launch_seed_triangulate(const SeedArgs& a, hipStream_t s);
 hipError_t launch_seed_scale(const KnnArgs& a, hipStream_t s);
 

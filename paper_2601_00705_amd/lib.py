@@ -63,6 +63,24 @@ class SeedConfig(ctypes.Structure):
                 ("alpha_lo", ctypes.c_double), ("alpha_hi", ctypes.c_double)]
 
 
+class Planes(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in ("mean", "quat", "log_scale", "opacity_logit", "colour")]
+
+
+class AdamConfig(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float * 5), ("beta1", ctypes.c_double), ("beta2", ctypes.c_double),
+                ("eps", ctypes.c_float), ("max_grad_norm", ctypes.c_float), ("ema", ctypes.c_float),
+                ("step", ctypes.c_int32)]
+
+
+class PruneConfig(ctypes.Structure):
+    _fields_ = [("m_min", ctypes.c_int32), ("v_min", ctypes.c_float), ("sigma_max", ctypes.c_float),
+                ("alpha_min", ctypes.c_float)]
+
+
+ADAM_WORKSPACE_BYTES = 16384
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("slots", ctypes.c_int64), ("capacity", ctypes.c_int64),
                 ("total_pixels", ctypes.c_int64), ("n_views", ctypes.c_int32),
@@ -97,6 +115,11 @@ def _load():
         "gsr_seed_triangulate": (st, [ctypes.c_int64, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P, P, P, P]),
         "gsr_seed_scale_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
         "gsr_seed_scale": (st, [ctypes.c_int64, P, P, ctypes.c_float, P, ctypes.c_size_t, P, P]),
+        "gsr_adam_step": (st, [ctypes.c_int64, ctypes.c_int32, P, P, P, P, P, P, P, P, P]),
+        "gsr_covis": (st, [ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_float, P, P, P]),
+        "gsr_prune_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
+        "gsr_prune": (st, [ctypes.c_int64, P, P, P, P, P, P, P, P, P]),
+        "gsr_compact": (st, [ctypes.c_int64, ctypes.c_int32, P, P, P, P, P]),
         "gsr_plan_set_timing": (st, [P, ctypes.c_int32]),
         "gsr_plan_read_timing": (st, [P, ctypes.c_int32, P, P]),
         "gsr_status_str": (ctypes.c_char_p, [st]),
@@ -114,7 +137,8 @@ EXPORTS = ("gsr_plan_create", "gsr_plan_destroy", "gsr_plan_workspace_bytes", "g
            "gsr_plan_layout", "gsr_plan_get_info", "gsr_project", "gsr_bin", "gsr_render_fwd",
            "gsr_loss_l1", "gsr_loss_track", "gsr_loss_mapping", "gsr_render_bwd", "gsr_raster_bwd", "gsr_project_bwd", "gsr_pair_count",
            "gsr_plan_set_timing", "gsr_plan_read_timing", "gsr_status_str", "gsr_last_error",
-           "gsr_seed_triangulate", "gsr_seed_scale_workspace_bytes", "gsr_seed_scale")
+           "gsr_seed_triangulate", "gsr_seed_scale_workspace_bytes", "gsr_seed_scale",
+           "gsr_adam_step", "gsr_covis", "gsr_prune_workspace_bytes", "gsr_prune", "gsr_compact")
 
 # launch groups of gsr_plan_read_timing (gsr_timer)
 TIMERS = ("project", "bin_emit", "bin_sort", "bin_ranges", "raster_fwd", "loss_l1", "clear_grad2d",
@@ -252,6 +276,40 @@ def gsr_seed_scale(n, mean, valid, floor_scale, workspace, log_scale, stream):
     return check(_lib.gsr_seed_scale(int(n), _p(mean), _p(valid), ctypes.c_float(floor_scale), _p(workspace),
                                      workspace.numel() * workspace.element_size(), _p(log_scale),
                                      ctypes.c_void_p(stream)), "gsr_seed_scale")
+
+
+PLANES = ("mean", "quat", "log_scale", "opacity_logit", "colour")
+
+
+def _planes(d):
+    return Planes(*(d[k].data_ptr() for k in PLANES))
+
+
+def gsr_adam_step(n, colour_rows, params, grads, m, v, anchor, cfg: AdamConfig, workspace, norm, stream):
+    """params, grads, m, v: dicts of device tensors over PLANES."""
+    pp, gg, mm, vv = _planes(params), _planes(grads), _planes(m), _planes(v)
+    return check(_lib.gsr_adam_step(int(n), int(colour_rows), ctypes.byref(pp), ctypes.byref(gg), ctypes.byref(mm),
+                                    ctypes.byref(vv), _p(anchor), ctypes.byref(cfg), _p(workspace), _p(norm),
+                                    ctypes.c_void_p(stream)), "gsr_adam_step")
+
+
+def gsr_covis(pixels, n_frames, T_key, T_frames, tau, counts, iou, stream):
+    return check(_lib.gsr_covis(int(pixels), int(n_frames), _p(T_key), _p(T_frames), ctypes.c_float(tau),
+                                _p(counts), _p(iou), ctypes.c_void_p(stream)), "gsr_covis")
+
+
+def gsr_prune_workspace_bytes(n):
+    return int(_lib.gsr_prune_workspace_bytes(int(n)))
+
+
+def gsr_prune(n, m_obs, v_vis, log_scale, opacity_logit, cfg: PruneConfig, keep_index, kept, workspace, stream):
+    return check(_lib.gsr_prune(int(n), _p(m_obs), _p(v_vis), _p(log_scale), _p(opacity_logit), ctypes.byref(cfg),
+                                _p(keep_index), _p(kept), _p(workspace), ctypes.c_void_p(stream)), "gsr_prune")
+
+
+def gsr_compact(n, rows, src, keep_index, kept, dst, stream):
+    return check(_lib.gsr_compact(int(n), int(rows), _p(src), _p(keep_index), _p(kept), _p(dst),
+                                  ctypes.c_void_p(stream)), "gsr_compact")
 
 
 def gsr_render_bwd(plan, g: Gaussians, poses, T_final, n_contrib, dL_drgb, dL_dT, pose_only, grads, d_xi,

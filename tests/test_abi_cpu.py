@@ -108,6 +108,36 @@ def test_mapping_loss_argument_errors():
         lib.gsr_plan_destroy(plan)
 
 
+def test_maintenance_argument_errors():
+    """gsr_adam_step, gsr_covis, gsr_prune and gsr_compact reject bad
+    settings, null buffers and overlapping compaction before touching the
+    device (the pointers are never read)."""
+    from paper_2601_00705_amd import lib
+    raw = lib.raw()
+    fake = ctypes.c_void_p(4096)
+    planes = lib.Planes(4096, 4096, 4096, 4096, 4096)
+    cfg = lib.AdamConfig()
+    for i in range(5):
+        cfg.lr[i] = 1e-3
+    cfg.beta1, cfg.beta2, cfg.eps, cfg.max_grad_norm, cfg.ema, cfg.step = 0.9, 0.999, 1e-8, 1.0, 0.1, 0
+    args = (10, 3, ctypes.byref(planes), ctypes.byref(planes), ctypes.byref(planes), ctypes.byref(planes), None,
+            ctypes.byref(cfg), fake, None, None)
+    assert raw.gsr_adam_step(*args) == lib.EINVAL  # step 0
+    cfg.step = 1
+    cfg.beta2 = 1.0
+    assert raw.gsr_adam_step(*args) == lib.EINVAL
+    cfg.beta2 = 0.999
+    bad = lib.Planes(4096, 0, 4096, 4096, 4096)
+    assert raw.gsr_adam_step(10, 3, ctypes.byref(planes), ctypes.byref(bad), ctypes.byref(planes),
+                             ctypes.byref(planes), None, ctypes.byref(cfg), fake, None, None) == lib.EINVAL
+    assert raw.gsr_covis(100, 2, fake, None, 0.1, fake, fake, None) == lib.EINVAL
+    assert raw.gsr_covis(100, 2, fake, fake, float("nan"), fake, fake, None) == lib.EINVAL
+    pc = lib.PruneConfig(1, 0.1, 1.0, 0.05)
+    assert raw.gsr_prune(0, fake, fake, fake, fake, ctypes.byref(pc), fake, fake, fake, None) == lib.EINVAL
+    assert raw.gsr_prune_workspace_bytes(-1) == 0
+    assert raw.gsr_compact(100, 3, ctypes.c_void_p(4096), fake, fake, ctypes.c_void_p(4096 + 400), None) == lib.EINVAL
+
+
 def test_track_loss_argument_errors():
     """gsr_loss_track rejects non-positive or non-finite thresholds and null
     buffers before touching the device (the pointers are never read)."""
