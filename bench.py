@@ -434,6 +434,23 @@ def main():
     log(f"batched (graph): {ms_step:.3f} ms/step (p10 {pct[10]:.3f}, p50 {pct[50]:.3f}, p90 {pct[90]:.3f}), "
         f"pairs {need}")
 
+    # ---------------- per-view latency: device wall-clock stamps -----------
+    # (each replay, the projection stamps the step's start and the last
+    # backward tile of each view stamps that view's end; over at least 100
+    # replays, the pose-only views when there are any, else every view)
+    lat_reps = max(100, args.steps)
+    lat = []
+    po_views = [v for v in range(V) if pose_only is not None and pose_only[v]]
+    sel = po_views or list(range(V))
+    for _ in range(lat_reps):
+        graph.replay()
+        lat.extend(R.view_latency_ms()[sel].tolist())
+    view_latency = {"views": "pose-only" if po_views else "all", "count": len(sel), "replays": lat_reps,
+                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                    "max_ms": float(np.max(lat))}
+    log(f"view latency ({view_latency['views']}, {len(sel)} views x {lat_reps} replays): "
+        f"p50 {view_latency['p50_ms']:.3f} ms, p99 {view_latency['p99_ms']:.3f} ms")
+
     # ---------------- per-kernel device time: library HIP events ----------
     # (eager launches of the same step on the same inputs, right after the
     # timed replays; every group is bracketed on the stream it runs on)
@@ -612,6 +629,7 @@ def main():
         "stage_ms": stage_ms,
         "kernel_ms": kernel_ms,
         "roofline": roof,
+        "view_latency": view_latency,
         "tracking_loss": track,
         "mapping_loss": mapl,
         "seeding": seed_res,

@@ -133,6 +133,10 @@ typedef struct {
     size_t keys;      /* uint64 [capacity]: sorted (tile << 32 | depth bits) */
     size_t vals;      /* uint32 [capacity]: sorted slot = view * n + index */
     size_t ranges;    /* uint32 [tiles][2]: [first, last + 1) per global tile */
+    size_t stamps;    /* uint64 [V + 1]: device wall-clock ticks (see
+                         gsr_device_clock_hz) at which the last backward tile
+                         of view v finished, for v < V, and at which the last
+                         gsr_project began, at [V]: per-view latency of a step */
     size_t total;     /* workspace bytes */
 } gsr_layout;
 
@@ -392,6 +396,10 @@ gsr_status gsr_prune(int64_t n, const int32_t *m_obs, const float *v_vis, const 
  * overlapping); columns from *kept on are left as they are. */
 gsr_status gsr_compact(int64_t n, int32_t rows, const float *src, const int32_t *keep_index, const int64_t *kept,
                        float *dst, void *stream);
+
+/* Rate of the device wall clock of the current device (the clock of the
+ * layout's stamps), in ticks per second. */
+gsr_status gsr_device_clock_hz(double *hz);
 
 /* Synchronises `stream`, then reports the pair count of the last binning
  * and whether it exceeded the capacity. */

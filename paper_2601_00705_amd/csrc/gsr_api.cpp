@@ -47,7 +47,7 @@ struct gsr_plan {
     size_t off_counters = 0, off_views = 0, off_geom = 0, off_conic = 0, off_rgbd = 0, off_qthr = 0, off_grad2d = 0, off_acc = 0;
     size_t off_stage = 0;
     size_t off_keys = 0, off_vals = 0, off_seg = 0, off_ranges = 0, off_cnt = 0;
-    size_t off_xip = 0, off_xip_sh = 0, off_order = 0, off_buckets = 0, off_track = 0, off_map = 0, total = 0;
+    size_t off_xip = 0, off_xip_sh = 0, off_order = 0, off_buckets = 0, off_track = 0, off_map = 0, off_stamps = 0, off_left = 0, total = 0;
     char* ws = nullptr;
     Counters host_counters{};
     std::vector<uint32_t> identity_order;
@@ -259,6 +259,8 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     for (int v = 0; v < n_views; ++v)
         p->map_tiles = std::max(p->map_tiles, ((p->vt.v[v].width + 31) / 32) * ((p->vt.v[v].height + 31) / 32));
     p->off_map = take(sizeof(double) * 2 * (size_t)p->map_tiles * (size_t)n_views);
+    p->off_stamps = take(sizeof(unsigned long long) * ((size_t)n_views + 1));
+    p->off_left = take(sizeof(uint32_t) * (size_t)n_views);
     p->total = o;
     p->host_counters = Counters{};
     p->host_counters.capacity = (unsigned long long)pair_capacity;
@@ -316,6 +318,7 @@ extern "C" gsr_status gsr_plan_layout(const gsr_plan* plan, gsr_layout* out)
     out->keys = plan->off_keys;
     out->vals = plan->off_vals;
     out->ranges = plan->off_ranges;
+    out->stamps = plan->off_stamps;
     out->total = plan->total;
     return GSR_OK;
 }
@@ -380,6 +383,7 @@ extern "C" gsr_status gsr_project(gsr_plan* plan, const gsr_gaussians* g, const 
     a.stage = at<StageRec>(plan, plan->off_stage);
     a.grad2d = at<double>(plan, plan->off_grad2d);
     a.acc = plan->cfg.deterministic ? at<unsigned long long>(plan, plan->off_acc) : nullptr;
+    a.stamps = at<unsigned long long>(plan, plan->off_stamps);
     a.counters = at<Counters>(plan, plan->off_counters);
     Timed t(plan, GSR_T_PROJECT, (hipStream_t)stream);
     hipError_t e = launch_project(a, plan->cfg.sh_degree, (hipStream_t)stream);
@@ -455,6 +459,8 @@ static RasterArgs raster_args(const gsr_plan* plan)
     a.grad2d = at<double>(plan, plan->off_grad2d);
     a.acc = plan->cfg.deterministic ? at<unsigned long long>(plan, plan->off_acc) : nullptr;
     a.slots = plan->n * plan->V;
+    a.tiles_left = at<uint32_t>(plan, plan->off_left);
+    a.stamps = at<unsigned long long>(plan, plan->off_stamps);
     return a;
 }
 
@@ -982,4 +988,16 @@ extern "C" gsr_status gsr_compact(int64_t n, int32_t rows, const float* src, con
     a.dst = dst;
     hipError_t e = launch_compact(a, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_compact");
+}
+
+extern "C" gsr_status gsr_device_clock_hz(double* hz)
+{
+    g_err.clear();
+    if (!hz) return fail(GSR_EINVAL, "null argument");
+    int dev = 0, khz = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev);
+    if (e != hipSuccess) return hip_fail(e, "gsr_device_clock_hz");
+    *hz = 1000.0 * (double)khz;
+    return GSR_OK;
 }

@@ -16,6 +16,7 @@ struct ProjectArgs {
     double* grad2d;            // [slots][9], zeroed for live slots
     unsigned long long* acc;   // [slots][GSR_FIX_LIMBS][9] (deterministic mode) or null, zeroed for live slots
     Counters* counters;
+    unsigned long long* stamps;  // [V + 1]: [V] = device wall clock when the projection starts
 };
 
 struct BinArgs {
@@ -76,6 +77,8 @@ struct RasterArgs {
     double* grad2d;            // [slots][9]
     unsigned long long* acc;   // [slots][GSR_FIX_LIMBS][9] in deterministic mode, else null
     int64_t slots;
+    uint32_t* tiles_left;      // [V]: backward tiles of each view still running
+    unsigned long long* stamps;  // [V + 1]: wall clock when a view's last backward tile ends
 };
 
 struct ProjectBwdArgs {

@@ -18,7 +18,10 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     // the accumulators of the live slots are zeroed below: the next backward
     // needs no clearing pass
-    if (i == 0) a.counters->grad_dirty = 0u;
+    if (i == 0) {
+        a.counters->grad_dirty = 0u;
+        a.stamps[a.views->n] = (unsigned long long)wall_clock64();
+    }
     if (i >= a.n) return;
     const int64_t n = a.n;
     // the geometry is computed in double (the chip's FP64 vector rate equals

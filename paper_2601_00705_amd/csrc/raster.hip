@@ -442,6 +442,11 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
         __syncthreads();
         hi_ = lo_;
     }
+    // the last tile of a view to finish stamps the view's completion time
+    if (lane == 0) {
+        const int v = view_of_tile(a.views, c.tile);
+        if (atomicSub(&a.tiles_left[v], 1u) == 1u) a.stamps[v] = (unsigned long long)wall_clock64();
+    }
 }
 
 template <int PPT, bool COUNT>
@@ -536,9 +541,17 @@ __global__ void k_fix_to_grad2d(const float4* geom, const unsigned long long* ac
     }
 }
 
+// the backward's per-view tile counters, before each backward
+__global__ void k_stamp_reset(const ViewTable* views, uint32_t* tiles_left)
+{
+    for (int v = threadIdx.x; v < views->n; v += blockDim.x)
+        tiles_left[v] = (uint32_t)(views->v[v].tiles_x * views->v[v].tiles_y);
+}
+
 hipError_t launch_clear_grad2d(const RasterArgs& a, hipStream_t s)
 {
-    if (a.slots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_stamp_reset, dim3(1), dim3(64), 0, s, a.views, a.tiles_left);
+    if (a.slots <= 0) return hipGetLastError();
     int64_t blocks = (a.slots + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     if (a.acc)

@@ -49,7 +49,7 @@ class Grads(ctypes.Structure):
 class Layout(ctypes.Structure):
     _fields_ = [(k, ctypes.c_size_t) for k in
                 ("counters", "geom", "conic_o", "rgb_d", "qthr", "stage", "grad2d", "keys", "vals", "ranges",
-                 "total")]
+                 "stamps", "total")]
 
 
 class SeedView(ctypes.Structure):
@@ -120,6 +120,7 @@ def _load():
         "gsr_prune_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
         "gsr_prune": (st, [ctypes.c_int64, P, P, P, P, P, P, P, P, P]),
         "gsr_compact": (st, [ctypes.c_int64, ctypes.c_int32, P, P, P, P, P]),
+        "gsr_device_clock_hz": (st, [P]),
         "gsr_plan_set_timing": (st, [P, ctypes.c_int32]),
         "gsr_plan_read_timing": (st, [P, ctypes.c_int32, P, P]),
         "gsr_status_str": (ctypes.c_char_p, [st]),
@@ -138,7 +139,8 @@ EXPORTS = ("gsr_plan_create", "gsr_plan_destroy", "gsr_plan_workspace_bytes", "g
            "gsr_loss_l1", "gsr_loss_track", "gsr_loss_mapping", "gsr_render_bwd", "gsr_raster_bwd", "gsr_project_bwd", "gsr_pair_count",
            "gsr_plan_set_timing", "gsr_plan_read_timing", "gsr_status_str", "gsr_last_error",
            "gsr_seed_triangulate", "gsr_seed_scale_workspace_bytes", "gsr_seed_scale",
-           "gsr_adam_step", "gsr_covis", "gsr_prune_workspace_bytes", "gsr_prune", "gsr_compact")
+           "gsr_adam_step", "gsr_covis", "gsr_prune_workspace_bytes", "gsr_prune", "gsr_compact",
+           "gsr_device_clock_hz")
 
 # launch groups of gsr_plan_read_timing (gsr_timer)
 TIMERS = ("project", "bin_emit", "bin_sort", "bin_ranges", "raster_fwd", "loss_l1", "clear_grad2d",
@@ -283,6 +285,12 @@ PLANES = ("mean", "quat", "log_scale", "opacity_logit", "colour")
 
 def _planes(d):
     return Planes(*(d[k].data_ptr() for k in PLANES))
+
+
+def gsr_device_clock_hz():
+    hz = ctypes.c_double()
+    check(_lib.gsr_device_clock_hz(ctypes.byref(hz)), "gsr_device_clock_hz")
+    return hz.value
 
 
 def gsr_adam_step(n, colour_rows, params, grads, m, v, anchor, cfg: AdamConfig, workspace, norm, stream):

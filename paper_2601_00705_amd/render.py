@@ -90,6 +90,20 @@ class Renderer:
             "grad2d": self._view(L.grad2d, 9 * S, torch.float64).view(S, 9),
         }
 
+    def stamps(self):
+        """Device wall-clock ticks [V + 1]: when the last backward tile of
+        each view finished, then when the last projection began (int64 view
+        into the workspace; read after a synchronisation)."""
+        V = len(self.cams)
+        return self._view(self.layout.stamps, V + 1, torch.int64)
+
+    def view_latency_ms(self):
+        """Per-view latency of the last step in ms: completion of the view's
+        backward minus the start of the projection (synchronises)."""
+        torch.cuda.synchronize(self.device)
+        s = self.stamps().cpu().double()
+        return ((s[:-1] - s[-1]) / lib.gsr_device_clock_hz() * 1e3)
+
     def sorted_pairs(self, count):
         L = self.layout
         return (self._view(L.keys, count, torch.int64), self._view(L.vals, count, torch.int32),
