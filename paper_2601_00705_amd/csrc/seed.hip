@@ -65,7 +65,11 @@ __device__ void smallest_right_singular(double A[4][4], double out[4])
                     be += A[i][q] * A[i][q];
                     ga += A[i][p] * A[i][q];
                 }
-                if (ga == 0.0 || fabs(ga) <= 1e-17 * sqrt(al * be)) continue;
+                // a pair counts as orthogonal at ~4.5 machine epsilons of
+                // its norms: below that the rounding of the dot products
+                // themselves dominates, and a stricter test never settles
+                // (every system would run to the sweep cap)
+                if (ga == 0.0 || fabs(ga) <= 1e-15 * sqrt(al * be)) continue;
                 rotated = true;
                 const double zeta = (be - al) / (2.0 * ga);
                 const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
@@ -186,46 +190,56 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_triangulate(SeedArgs 
 #pragma unroll
     for (int c = 0; c < 3; ++c) a.mean[(int64_t)c * a.n + i] = (float)bX[c];
 
-    // colour: median of the corrected samples over the supporting views
-    double smp[3][GSR_SEED_MAX_NEIGHBOURS + 1];
-    int m = 0;
+    // colour: median of the corrected samples over the supporting views.
+    // The supporting views form a bit mask; per channel the samples sit in a
+    // fixed register array (absent views as +inf), sorted by an unrolled
+    // odd-even transposition network, and the median is picked by index
+    // compares, so that nothing is indexed dynamically (no scratch memory).
+    uint32_t support = 0u;
     if (ok) {
-        for (int v = 0; v <= K; ++v) {
-            double px, py;
-            if (v == 0) {
-                px = xr[0];
-                py = xr[1];
-            } else {
-                const double xn0 = (double)a.x_nb[(int64_t)(2 * (v - 1)) * a.n + i];
-                const double xn1 = (double)a.x_nb[(int64_t)(2 * (v - 1) + 1) * a.n + i];
-                double u, w, z;
-                project_px(a.views[v].P, bX, u, w, z);
-                const double du = u - xn0, dv = w - xn1;
-                if (!(sqrt(du * du + dv * dv) < a.max_reproj)) continue;
-                px = xn0;
-                py = xn1;
-            }
-            const SeedView& vw = a.views[v];
+        support = 1u;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) smp[c][m] = (bilinear(vw, c, px, py) - vw.bias) / vw.gain;
-            ++m;
+        for (int v = 1; v <= GSR_SEED_MAX_NEIGHBOURS; ++v) {
+            if (v > K) break;
+            const double xn0 = (double)a.x_nb[(int64_t)(2 * (v - 1)) * a.n + i];
+            const double xn1 = (double)a.x_nb[(int64_t)(2 * (v - 1) + 1) * a.n + i];
+            double u, w, z;
+            project_px(a.views[v].P, bX, u, w, z);
+            const double du = u - xn0, dv = w - xn1;
+            if (sqrt(du * du + dv * dv) < a.max_reproj) support |= 1u << v;
         }
     }
+    const int m = __popc(support);
+    constexpr int NS = GSR_SEED_MAX_NEIGHBOURS + 1;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        double med = 0.0;
-        if (m > 0) {
-            for (int x = 1; x < m; ++x) {  // insertion sort of at most 9 values
-                const double key = smp[c][x];
-                int y = x - 1;
-                while (y >= 0 && smp[c][y] > key) {
-                    smp[c][y + 1] = smp[c][y];
-                    --y;
-                }
-                smp[c][y + 1] = key;
+        double smp[NS];
+#pragma unroll
+        for (int v = 0; v < NS; ++v) {
+            smp[v] = INFINITY;
+            if ((support >> v) & 1u) {
+                const double px = v == 0 ? xr[0] : (double)a.x_nb[(int64_t)(2 * (v - 1)) * a.n + i];
+                const double py = v == 0 ? xr[1] : (double)a.x_nb[(int64_t)(2 * (v - 1) + 1) * a.n + i];
+                const SeedView& vw = a.views[v];
+                smp[v] = (bilinear(vw, c, px, py) - vw.bias) / vw.gain;
             }
-            med = (m & 1) ? smp[c][m / 2] : (smp[c][m / 2 - 1] + smp[c][m / 2]) / 2.0;
         }
+#pragma unroll
+        for (int round = 0; round < NS; ++round) {
+#pragma unroll
+            for (int j = round & 1; j + 1 < NS; j += 2) {
+                const double lo = fmin(smp[j], smp[j + 1]), hi = fmax(smp[j], smp[j + 1]);
+                smp[j] = lo;
+                smp[j + 1] = hi;
+            }
+        }
+        double lo_mid = 0.0, hi_mid = 0.0;
+#pragma unroll
+        for (int j = 0; j < NS; ++j) {
+            if (j == (m - 1) / 2) lo_mid = smp[j];
+            if (j == m / 2) hi_mid = smp[j];
+        }
+        const double med = m == 0 ? 0.0 : ((m & 1) ? hi_mid : (lo_mid + hi_mid) / 2.0);
         a.colour[(int64_t)c * a.n + i] = (float)med;
     }
 }
