@@ -777,7 +777,7 @@ extern "C" gsr_status gsr_seed_triangulate(int64_t n, int32_t n_neighbours, cons
 namespace {
 struct KnnLayout {
     size_t bpart, grid, cell_count, cell_start, cell_of, rank, sorted, total;
-    size_t opart, fine_count, fine_start, fine_of, fine_rank, fine_sorted, scan_tot, bf_list, bf_count;
+    size_t opart, fine_count, fine_start, fine_of, fine_rank, fine_pts, cell_pts, scan_tot, bf_list, bf_count;
     int64_t max_cells;
     int32_t table_bits;
 };
@@ -808,7 +808,8 @@ KnnLayout knn_layout(int64_t n)
     L.fine_start = take(sizeof(uint32_t) * GSR_KNN_LEVELS * (size_t)(T + 1));
     L.fine_of = take(sizeof(uint32_t) * GSR_KNN_LEVELS * (size_t)n);
     L.fine_rank = take(sizeof(uint32_t) * GSR_KNN_LEVELS * (size_t)n);
-    L.fine_sorted = take(sizeof(uint32_t) * GSR_KNN_LEVELS * (size_t)n);
+    L.fine_pts = take(sizeof(float) * 4 * GSR_KNN_LEVELS * (size_t)n);
+    L.cell_pts = take(sizeof(float) * 4 * (size_t)n);
     const int64_t scan_blocks = std::max((L.max_cells + 1 + 1023) / 1024, (T + 1 + 1023) / 1024);
     L.scan_tot = take(sizeof(uint32_t) * (size_t)scan_blocks);
     L.bf_list = take(sizeof(uint32_t) * (size_t)n);
@@ -854,7 +855,8 @@ extern "C" gsr_status gsr_seed_scale(int64_t n, const float* mean, const int32_t
     a.fine_start = (uint32_t*)(ws + L.fine_start);
     a.fine_of = (uint32_t*)(ws + L.fine_of);
     a.fine_rank = (uint32_t*)(ws + L.fine_rank);
-    a.fine_sorted = (uint32_t*)(ws + L.fine_sorted);
+    a.fine_pts = (float4*)(ws + L.fine_pts);
+    a.cell_pts = (float4*)(ws + L.cell_pts);
     a.scan_tot = (uint32_t*)(ws + L.scan_tot);
     a.bf_list = (uint32_t*)(ws + L.bf_list);
     a.bf_count = (uint32_t*)(ws + L.bf_count);

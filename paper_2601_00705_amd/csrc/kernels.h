@@ -242,7 +242,8 @@ struct KnnArgs {
     uint32_t* fine_start;      // [GSR_KNN_LEVELS][2^table_bits + 1]
     uint32_t* fine_of;         // [GSR_KNN_LEVELS][n]
     uint32_t* fine_rank;       // [GSR_KNN_LEVELS][n]
-    uint32_t* fine_sorted;     // [GSR_KNN_LEVELS][n]
+    float4* fine_pts;          // [GSR_KNN_LEVELS][n]: (x, y, z, index bits) in fine-bucket order
+    float4* cell_pts;          // [n]: the same in coarse-cell order
     uint32_t* scan_tot;        // block totals of the scans
     uint32_t* bf_list;         // [n] queries left to the exhaustive search
     uint32_t* bf_count;        // their number

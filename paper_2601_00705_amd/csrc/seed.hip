@@ -548,12 +548,16 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_place(KnnArgs a)
         for (int c = 0; c < 3; ++c) a.log_scale[(int64_t)c * a.n + i] = 0.0f;
         return;
     }
-    a.sorted[a.cell_start[a.cell_of[i]] + a.rank[i]] = (uint32_t)i;
+    // the seed's position travels with its index, so that a query reads one
+    // 16-byte record per candidate, in bucket order
+    const float4 q = make_float4(a.mean[i], a.mean[a.n + i], a.mean[2 * a.n + i], __uint_as_float((uint32_t)i));
+    const int64_t pos = a.cell_start[a.cell_of[i]] + a.rank[i];
+    a.sorted[pos] = (uint32_t)i;
+    a.cell_pts[pos] = q;
     if (g.fine) {
         const int64_t T1 = ((int64_t)1 << a.table_bits) + 1;
         for (int l = 0; l < GSR_KNN_LEVELS; ++l)
-            a.fine_sorted[l * a.n + a.fine_start[l * T1 + a.fine_of[l * a.n + i]] + a.fine_rank[l * a.n + i]] =
-                (uint32_t)i;
+            a.fine_pts[l * a.n + a.fine_start[l * T1 + a.fine_of[l * a.n + i]] + a.fine_rank[l * a.n + i]] = q;
     }
 }
 
@@ -576,13 +580,13 @@ __device__ __forceinline__ void knn_insert(double d, double (&best)[3], int& fou
     }
 }
 
-__device__ __forceinline__ void knn_candidate(const KnnArgs& a, uint32_t j, int64_t i, float px, float py, float pz,
+__device__ __forceinline__ void knn_candidate(const float4& q, int64_t i, float px, float py, float pz,
                                               double (&best)[3], int& found)
 {
-    if ((int64_t)j == i) return;
-    const double ex = (double)a.mean[j] - (double)px;
-    const double ey = (double)a.mean[a.n + j] - (double)py;
-    const double ez = (double)a.mean[2 * a.n + j] - (double)pz;
+    if ((int64_t)__float_as_uint(q.w) == i) return;
+    const double ex = (double)q.x - (double)px;
+    const double ey = (double)q.y - (double)py;
+    const double ez = (double)q.z - (double)pz;
     knn_insert(ex * ex + ey * ey + ez * ez, best, found);
 }
 
@@ -616,7 +620,7 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_knn(KnnArgs a)
             found = 0;
             best[0] = best[1] = best[2] = INFINITY;
             const uint32_t* start = a.fine_start + l * T1;
-            const uint32_t* sorted = a.fine_sorted + l * a.n;
+            const float4* pts = a.fine_pts + l * a.n;
             const double hl = g.h1 * ldexp(1.0, l);
             const int fx = fine_coord(g, l, 0, px), fy = fine_coord(g, l, 1, py), fz = fine_coord(g, l, 2, pz);
             for (int r = 0; r <= GSR_KNN_FINE_SHELLS && !settled; ++r) {
@@ -630,11 +634,11 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_knn(KnnArgs a)
                             work += s1 - s0;
                             if (work > GSR_KNN_BUDGET) goto exhaustive;
                             for (uint32_t s = s0; s < s1; ++s) {
-                                const uint32_t j = sorted[s];
-                                if (fine_coord(g, l, 0, a.mean[j]) != x || fine_coord(g, l, 1, a.mean[a.n + j]) != y ||
-                                    fine_coord(g, l, 2, a.mean[2 * a.n + j]) != z)
+                                const float4 q = pts[s];
+                                if (fine_coord(g, l, 0, q.x) != x || fine_coord(g, l, 1, q.y) != y ||
+                                    fine_coord(g, l, 2, q.z) != z)
                                     continue;
-                                knn_candidate(a, j, i, px, py, pz, best, found);
+                                knn_candidate(q, i, px, py, pz, best, found);
                             }
                         }
                     }
@@ -667,7 +671,7 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_knn(KnnArgs a)
                         const uint32_t s0 = a.cell_start[cell], s1 = a.cell_start[cell + 1];
                         work += s1 - s0;
                         if (work > GSR_KNN_BUDGET) goto exhaustive;
-                        for (uint32_t s = s0; s < s1; ++s) knn_candidate(a, a.sorted[s], i, px, py, pz, best, found);
+                        for (uint32_t s = s0; s < s1; ++s) knn_candidate(a.cell_pts[s], i, px, py, pz, best, found);
                     }
                 }
             }
@@ -704,7 +708,7 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_brute(KnnArgs a)
         double best[3] = {INFINITY, INFINITY, INFINITY};
         int found = 0;
         for (int64_t t = threadIdx.x; t < g.count; t += GSR_SEED_THREADS)
-            knn_candidate(a, a.sorted[t], i, px, py, pz, best, found);
+            knn_candidate(a.cell_pts[t], i, px, py, pz, best, found);
         for (int k = 0; k < 3; ++k) cand[threadIdx.x * 3 + k] = k < found ? best[k] : INFINITY;
         __syncthreads();
         if (threadIdx.x == 0) {
