@@ -623,7 +623,34 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_knn(KnnArgs a)
             const float4* pts = a.fine_pts + l * a.n;
             const double hl = g.h1 * ldexp(1.0, l);
             const int fx = fine_coord(g, l, 0, px), fy = fine_coord(g, l, 1, py), fz = fine_coord(g, l, 2, pz);
-            for (int r = 0; r <= GSR_KNN_FINE_SHELLS && !settled; ++r) {
+            // shells 0 and 1 together (shell 0 alone never settles): the 27
+            // cells around the seed's, a z-slab of 9 at a time with their
+            // bucket bounds loaded together, so that the loads overlap
+            // instead of forming a chain of dependent round trips
+            for (int dz = -1; dz <= 1; ++dz) {
+                uint32_t lo[9], hi[9];
+#pragma unroll
+                for (int c = 0; c < 9; ++c) {
+                    const uint32_t b = fine_bucket(fx + c % 3 - 1, fy + c / 3 - 1, fz + dz, mask);
+                    lo[c] = start[b];
+                    hi[c] = start[b + 1];
+                }
+#pragma unroll
+                for (int c = 0; c < 9; ++c) {
+                    const int x = fx + c % 3 - 1, y = fy + c / 3 - 1, z = fz + dz;
+                    work += hi[c] - lo[c];
+                    if (work > GSR_KNN_BUDGET) goto exhaustive;
+                    for (uint32_t s = lo[c]; s < hi[c]; ++s) {
+                        const float4 q = pts[s];
+                        if (fine_coord(g, l, 0, q.x) != x || fine_coord(g, l, 1, q.y) != y ||
+                            fine_coord(g, l, 2, q.z) != z)
+                            continue;
+                        knn_candidate(q, i, px, py, pz, best, found);
+                    }
+                }
+            }
+            settled = found == 3 && best[2] <= hl * hl;
+            for (int r = 2; r <= GSR_KNN_FINE_SHELLS && !settled; ++r) {
                 for (int dz = -r; dz <= r; ++dz) {
                     for (int dy = -r; dy <= r; ++dy) {
                         const bool face = dz == -r || dz == r || dy == -r || dy == r;
