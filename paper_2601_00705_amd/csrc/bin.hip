@@ -21,9 +21,9 @@
 //                 the order inside a chunk's group is arbitrary, and the
 //                 per-tile sort of the unique keys makes it exact)
 //
-// Candidates of a staged group of Gaussians are expanded cooperatively: one
-// candidate per thread and step, its owner found by binary search over the
-// rectangle-area prefix.
+// Candidates of a staged group of Gaussians are expanded cooperatively: each
+// thread walks a contiguous run of them, its first owner found by binary
+// search over the rectangle-area prefix.
 #include "kernels.h"
 
 namespace gsr {
@@ -117,21 +117,58 @@ __device__ uint32_t stage_chunk(const BinArgs& a, const ViewInfo& vw, const Chun
     return total;
 }
 
-// candidate j of the staged group: owner (largest s with excl[s] <= j) and tile
-__device__ __forceinline__ bool candidate(const ChunkLds& L, uint32_t j, const BinArgs& a, int& s, int& tx,
-                                          int& ty)
+// Walks the staged group's candidates: thread t takes the contiguous run
+// [t per, (t + 1) per) of them, finds the run's first owner (largest s with
+// excl[s] <= j) by one binary search, then advances tile by tile along the
+// owner's rectangle and owner by owner, with no search or division per
+// candidate and the owner's ellipse held in registers.  hit(s, tx, ty) is
+// called for every candidate the tile test keeps.
+template <class Hit>
+__device__ __forceinline__ void walk_candidates(const ChunkLds& L, uint32_t total, const BinArgs& a, Hit&& hit)
 {
+    const uint32_t per = (total + 255u) / 256u;
+    uint32_t j = threadIdx.x * per;
+    const uint32_t j1 = min(j + per, total);
+    if (j >= j1) return;
     int lo = 0, hi = GSR_BIN_CHUNK - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (L.excl[mid] <= j) lo = mid; else hi = mid - 1;
     }
-    s = lo;
-    const uint32_t r = j - L.excl[lo];
-    const uint32_t wdt = (uint32_t)L.rw[lo];
-    ty = L.ry0[lo] + (int)(r / wdt);
-    tx = L.rx0[lo] + (int)(r % wdt);
-    return tile_hit(L.u[lo], L.v[lo], L.A[lo], L.B[lo], L.C[lo], L.q[lo], tx, ty, a.cfg.tile_w, a.cfg.tile_h);
+    int s = lo;
+    // candidates left in s's rectangle (at least 1: excl[s + 1] > j)
+    uint32_t left = L.excl[s + 1] - j;
+    const uint32_t r = j - L.excl[s];
+    int w = L.rw[s];
+    int dx = (int)(r % (uint32_t)w), dy = (int)(r / (uint32_t)w);
+    float u = L.u[s], v = L.v[s], A = L.A[s], B = L.B[s], C = L.C[s], q = L.q[s];
+    int x0 = L.rx0[s], y0 = L.ry0[s];
+    for (; j < j1; ++j) {
+        if (left == 0u) {
+            // the next owner with a non-empty rectangle (one exists: j < total)
+            do {
+                ++s;
+                left = L.excl[s + 1] - L.excl[s];
+            } while (left == 0u);
+            w = L.rw[s];
+            dx = dy = 0;
+            u = L.u[s];
+            v = L.v[s];
+            A = L.A[s];
+            B = L.B[s];
+            C = L.C[s];
+            q = L.q[s];
+            x0 = L.rx0[s];
+            y0 = L.ry0[s];
+        }
+        const int tx = x0 + dx, ty = y0 + dy;
+        if (tile_hit(u, v, A, B, C, q, tx, ty, a.cfg.tile_w, a.cfg.tile_h)) hit(s, tx, ty);
+        --left;
+        if (++dx == w) {
+            dx = 0;
+            ++dy;
+        }
+    }
 }
 
 // row of the count matrix of (view, chunk)
@@ -160,14 +197,11 @@ __global__ __launch_bounds__(256) void k_bin_count(BinArgs a)
         cur = nxt;
         if (sub + 1 < a.chunk_mult) fetch_chunk(a, v, base + GSR_BIN_CHUNK, false, nxt);
         const uint32_t total = stage_chunk(a, vw, cur, L);
-        for (uint32_t j = threadIdx.x; j < total; j += 256) {
-            int s, tx, ty;
-            if (candidate(L, j, a, s, tx, ty)) {
-                const int tt = ty * vw.tiles_x + tx;
-                if (LDS_HIST) atomicAdd(&hist[tt], 1u);
-                else atomicAdd(&row[tt], 1u);
-            }
-        }
+        walk_candidates(L, total, a, [&](int, int tx, int ty) {
+            const int tt = ty * vw.tiles_x + tx;
+            if (LDS_HIST) atomicAdd(&hist[tt], 1u);
+            else atomicAdd(&row[tt], 1u);
+        });
     }
     if (LDS_HIST) {
         __syncthreads();
@@ -266,14 +300,11 @@ __global__ __launch_bounds__(256) void k_bin_emit(BinArgs a)
         cur = nxt;
         if (sub + 1 < a.chunk_mult) fetch_chunk(a, v, base + GSR_BIN_CHUNK, true, nxt);
         const uint32_t total = stage_chunk(a, vw, cur, L);
-        for (uint32_t j = threadIdx.x; j < total; j += 256) {
-            int s, tx, ty;
-            if (candidate(L, j, a, s, tx, ty)) {
-                const int tt = ty * vw.tiles_x + tx;
-                const uint32_t pos = LDS_HIST ? atomicAdd(&cursor[tt], 1u) : rng[tt].x + atomicAdd(&row[tt], 1u);
-                a.seg[pos] = ((unsigned long long)L.dbits[s] << 32) | (unsigned long long)(base + s);
-            }
-        }
+        walk_candidates(L, total, a, [&](int s, int tx, int ty) {
+            const int tt = ty * vw.tiles_x + tx;
+            const uint32_t pos = LDS_HIST ? atomicAdd(&cursor[tt], 1u) : rng[tt].x + atomicAdd(&row[tt], 1u);
+            a.seg[pos] = ((unsigned long long)L.dbits[s] << 32) | (unsigned long long)(base + s);
+        });
     }
 }
 
