@@ -121,7 +121,7 @@ __device__ uint32_t stage_chunk(const BinArgs& a, const ViewInfo& vw, const Chun
 // [t per, (t + 1) per) of them, finds the run's first owner (largest s with
 // excl[s] <= j) by one binary search, then advances tile by tile along the
 // owner's rectangle and owner by owner, with no search or division per
-// candidate and the owner's ellipse held in registers.  hit(s, tx, ty) is
+// candidate and the owner's ellipse (with 1/A and 1/C) held in registers.  hit(s, tx, ty) is
 // called for every candidate the tile test keeps.
 template <class Hit>
 __device__ __forceinline__ void walk_candidates(const ChunkLds& L, uint32_t total, const BinArgs& a, Hit&& hit)
@@ -142,6 +142,7 @@ __device__ __forceinline__ void walk_candidates(const ChunkLds& L, uint32_t tota
     int w = L.rw[s];
     int dx = (int)(r % (uint32_t)w), dy = (int)(r / (uint32_t)w);
     float u = L.u[s], v = L.v[s], A = L.A[s], B = L.B[s], C = L.C[s], q = L.q[s];
+    float iA = 1.0f / A, iC = 1.0f / C;
     int x0 = L.rx0[s], y0 = L.ry0[s];
     for (; j < j1; ++j) {
         if (left == 0u) {
@@ -158,11 +159,13 @@ __device__ __forceinline__ void walk_candidates(const ChunkLds& L, uint32_t tota
             B = L.B[s];
             C = L.C[s];
             q = L.q[s];
+            iA = 1.0f / A;
+            iC = 1.0f / C;
             x0 = L.rx0[s];
             y0 = L.ry0[s];
         }
         const int tx = x0 + dx, ty = y0 + dy;
-        if (tile_hit(u, v, A, B, C, q, tx, ty, a.cfg.tile_w, a.cfg.tile_h)) hit(s, tx, ty);
+        if (tile_hit(u, v, A, B, C, iA, iC, q, tx, ty, a.cfg.tile_w, a.cfg.tile_h)) hit(s, tx, ty);
         --left;
         if (++dx == w) {
             dx = 0;

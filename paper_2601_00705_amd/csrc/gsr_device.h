@@ -94,15 +94,17 @@ __device__ __forceinline__ bool tile_rect(float u, float v, float rx, float ry, 
 // reaches qthr on the box spanned by the tile's pixel centres.  Inside the
 // box the minimum is 0; otherwise it lies on an edge, at the edge's
 // unconstrained minimiser clamped to the edge.  Float32, this exact order.
-__device__ __forceinline__ bool tile_hit(float u, float v, float A, float B, float C, float qthr, int tx, int ty,
-                                         int tw, int th)
+// iA = 1 / A and iC = 1 / C (float32 divisions) are passed in, so that a
+// caller testing many tiles of one ellipse divides once.
+__device__ __forceinline__ bool tile_hit(float u, float v, float A, float B, float C, float iA, float iC, float qthr,
+                                         int tx, int ty, int tw, int th)
 {
     const float x0 = ((float)(tx * tw) + 0.5f) - u;
     const float x1 = ((float)(tx * tw + tw - 1) + 0.5f) - u;
     const float y0 = ((float)(ty * th) + 0.5f) - v;
     const float y1 = ((float)(ty * th + th - 1) + 0.5f) - v;
     if (x0 <= 0.0f && x1 >= 0.0f && y0 <= 0.0f && y1 >= 0.0f) return true;
-    const float iA = 1.0f / A, iC = 1.0f / C, B2 = 2.0f * B;
+    const float B2 = 2.0f * B;
     float m = INFINITY;
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
