@@ -28,9 +28,11 @@
 //   slots per seed per level (a bucket may hold several cells; a candidate
 //   counts only for its own cell).  All are counting sorts by cell.  A query
 //   searches cubic shells of cells around its own until the third distance
-//   found cannot be beaten by a farther shell: up to 2 shells on each fine
-//   level, from the level whose cells match the spacing its coarse cell's
-//   count suggests upwards, then up to 2 shells on the coarse grid.  The few
+//   found cannot be beaten by a farther shell (a seed beyond shell r lies at
+//   least r + its distance to its own cell's nearer face, in cells, away):
+//   up to 2 shells on each fine level, from the level whose cells match the
+//   spacing its coarse cell's count suggests upwards, then up to 2 shells on
+//   the coarse grid.  The few
 //   queries still unsettled (seeds far from all others), or that would
 //   examine more than GSR_KNN_BUDGET candidates on one lane (seeds beside
 //   much denser regions), are listed and each is answered exactly by a whole
@@ -649,7 +651,21 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_knn(KnnArgs a)
                     }
                 }
             }
-            settled = found == 3 && best[2] <= hl * hl;
+            // a seed beyond shell r lies, along some axis, at least
+            // (r + the query's distance to its own cell's nearer face, in
+            // cells) cell sizes away
+            double mrg = 0.5;
+            {
+                const float pc[3] = {px, py, pz};
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double t = ((double)pc[c] - g.origin[c]) * (g.inv_h1 * ldexp(1.0, -l));
+                    const double f = t - floor(t);
+                    mrg = fmin(mrg, fmin(f, 1.0 - f));
+                }
+                const double lim = (1.0 + mrg) * hl * (1.0 - 1e-12);
+                settled = found == 3 && best[2] <= lim * lim;
+            }
             for (int r = 2; r <= GSR_KNN_FINE_SHELLS && !settled; ++r) {
                 for (int dz = -r; dz <= r; ++dz) {
                     for (int dy = -r; dy <= r; ++dy) {
@@ -670,8 +686,8 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_knn(KnnArgs a)
                         }
                     }
                 }
-                // every seed in a farther shell lies at least r * hl away
-                settled = found == 3 && best[2] <= ((double)r * hl) * ((double)r * hl);
+                const double lim = ((double)r + mrg) * hl * (1.0 - 1e-12);
+                settled = found == 3 && best[2] <= lim * lim;
             }
         }
         if (!settled) {
