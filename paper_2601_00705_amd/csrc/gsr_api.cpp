@@ -260,7 +260,7 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
         p->map_tiles = std::max(p->map_tiles, ((p->vt.v[v].width + 31) / 32) * ((p->vt.v[v].height + 31) / 32));
     p->off_map = take(sizeof(double) * 2 * (size_t)p->map_tiles * (size_t)n_views);
     p->off_stamps = take(sizeof(unsigned long long) * ((size_t)n_views + 1));
-    p->off_left = take(sizeof(uint32_t) * (size_t)n_views);
+    p->off_left = take(sizeof(unsigned long long) * (size_t)n_views);
     p->total = o;
     p->host_counters = Counters{};
     p->host_counters.capacity = (unsigned long long)pair_capacity;
@@ -287,6 +287,9 @@ extern "C" gsr_status gsr_plan_bind(gsr_plan* plan, void* workspace, size_t byte
     // empty tile ranges and an identity tile order until the first binning
     if (e == hipSuccess)
         e = hipMemsetAsync(plan->ws + plan->off_ranges, 0, sizeof(uint2) * (size_t)plan->total_tiles, s);
+    // the per-view tile counters of the completion stamps start at zero
+    if (e == hipSuccess)
+        e = hipMemsetAsync(plan->ws + plan->off_left, 0, sizeof(unsigned long long) * (size_t)plan->V, s);
     if (e == hipSuccess) {
         plan->identity_order.resize((size_t)plan->total_tiles);
         for (int32_t t = 0; t < plan->total_tiles; ++t) plan->identity_order[(size_t)t] = (uint32_t)t;
@@ -459,7 +462,7 @@ static RasterArgs raster_args(const gsr_plan* plan)
     a.grad2d = at<double>(plan, plan->off_grad2d);
     a.acc = plan->cfg.deterministic ? at<unsigned long long>(plan, plan->off_acc) : nullptr;
     a.slots = plan->n * plan->V;
-    a.tiles_left = at<uint32_t>(plan, plan->off_left);
+    a.tiles_done = at<unsigned long long>(plan, plan->off_left);
     a.stamps = at<unsigned long long>(plan, plan->off_stamps);
     return a;
 }

@@ -77,7 +77,7 @@ struct RasterArgs {
     double* grad2d;            // [slots][9]
     unsigned long long* acc;   // [slots][GSR_FIX_LIMBS][9] in deterministic mode, else null
     int64_t slots;
-    uint32_t* tiles_left;      // [V]: backward tiles of each view still running
+    unsigned long long* tiles_done;  // [V]: backward tiles of each view completed, over all calls
     unsigned long long* stamps;  // [V + 1]: wall clock when a view's last backward tile ends
 };
 

@@ -328,6 +328,19 @@ __device__ __forceinline__ double fixed_value(const unsigned long long* limbs, i
     return neg ? -v : v;
 }
 
+// Counts the tile as done for its view; the tile completing a whole
+// backward of the view (the view's count reaching a multiple of its tiles:
+// the count runs on across backward calls, so it needs no reset) stamps the
+// view's completion time.
+__device__ __forceinline__ void view_done(const RasterArgs& a, int tile, int lane)
+{
+    if (lane != 0) return;
+    const int v = view_of_tile(a.views, tile);
+    const unsigned long long tiles = (unsigned long long)(a.views->v[v].tiles_x * a.views->v[v].tiles_y);
+    const unsigned long long old = atomicAdd(&a.tiles_done[v], 1ull);
+    if ((old + 1ull) % tiles == 0ull) a.stamps[v] = (unsigned long long)wall_clock64();
+}
+
 template <int PPT, int GSR_BATCH, bool DET>
 __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
 {
@@ -336,9 +349,12 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
     // the accumulators are in use from here on (the clearing kernel, which
     // reads the flag, has completed before this kernel starts)
     if (blockIdx.x == 0 && threadIdx.x == 0) a.counters->grad_dirty = 1u;
-    if (a.counters->overflow) return;
-    const uint2 range = a.ranges[c.tile];
     const int lane = threadIdx.x;
+    if (a.counters->overflow) {
+        view_done(a, c.tile, lane);
+        return;
+    }
+    const uint2 range = a.ranges[c.tile];
     const float amax = a.cfg.alpha_max;
 
     float T[PPT], Tf[PPT], gsk[PPT], g0[PPT], g1[PPT], g2[PPT], dy2[PPT];
@@ -442,11 +458,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
         __syncthreads();
         hi_ = lo_;
     }
-    // the last tile of a view to finish stamps the view's completion time
-    if (lane == 0) {
-        const int v = view_of_tile(a.views, c.tile);
-        if (atomicSub(&a.tiles_left[v], 1u) == 1u) a.stamps[v] = (unsigned long long)wall_clock64();
-    }
+    view_done(a, c.tile, lane);
 }
 
 template <int PPT, bool COUNT>
@@ -541,17 +553,9 @@ __global__ void k_fix_to_grad2d(const float4* geom, const unsigned long long* ac
     }
 }
 
-// the backward's per-view tile counters, before each backward
-__global__ void k_stamp_reset(const ViewTable* views, uint32_t* tiles_left)
-{
-    for (int v = threadIdx.x; v < views->n; v += blockDim.x)
-        tiles_left[v] = (uint32_t)(views->v[v].tiles_x * views->v[v].tiles_y);
-}
-
 hipError_t launch_clear_grad2d(const RasterArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_stamp_reset, dim3(1), dim3(64), 0, s, a.views, a.tiles_left);
-    if (a.slots <= 0) return hipGetLastError();
+    if (a.slots <= 0) return hipSuccess;
     int64_t blocks = (a.slots + 255) / 256;
     if (blocks > 8192) blocks = 8192;
     if (a.acc)
