@@ -90,7 +90,8 @@ typedef struct {
 
 /* Renderer settings (host struct). */
 typedef struct {
-    int32_t tile_w, tile_h; /* powers of two; tile_w * tile_h in {64, 128, 256} */
+    int32_t tile_w, tile_h; /* powers of two, tile_w <= 64; tile_w * tile_h in
+                               {64, 128, 256, 512} (1, 2, 4 or 8 pixels per lane) */
     int32_t batch;          /* records staged in LDS per step: 64, 128 or 256 (0 = 128) */
     int32_t sh_degree;      /* -1: RGB colour; 0..3: SH degree */
     float z_near;           /* cull mu_C.z <= z_near */

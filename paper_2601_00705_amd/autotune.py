@@ -18,7 +18,7 @@ import statistics
 HERE = os.path.dirname(os.path.abspath(__file__))
 SHIPPED_CACHE = os.path.join(HERE, "autotune_cache.json")
 CANDIDATES = [(8, 8, 128), (16, 8, 128), (8, 16, 128), (16, 16, 64), (16, 16, 128), (16, 16, 256),
-              (32, 8, 128)]
+              (32, 8, 128), (32, 16, 64), (32, 16, 128), (16, 32, 128)]
 
 
 def _user_cache_path():

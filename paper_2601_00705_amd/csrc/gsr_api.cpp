@@ -148,7 +148,10 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
         return fail(GSR_EINVAL, "pair_capacity out of range");
     if (!pow2(cfg->tile_w) || !pow2(cfg->tile_h)) return fail(GSR_EINVAL, "tile sizes must be powers of two");
     int tpx = cfg->tile_w * cfg->tile_h;
-    if (tpx != 64 && tpx != 128 && tpx != 256) return fail(GSR_EUNSUPPORTED, "tile pixel count not in {64,128,256}");
+    if (tpx != 64 && tpx != 128 && tpx != 256 && tpx != 512)
+        return fail(GSR_EUNSUPPORTED, "tile pixel count not in {64,128,256,512}");
+    // the 64 lanes of a tile's wavefront own whole columns
+    if (cfg->tile_w > 64) return fail(GSR_EUNSUPPORTED, "tile_w above 64");
     if (cfg->batch != 0 && cfg->batch != 64 && cfg->batch != 128 && cfg->batch != 256)
         return fail(GSR_EUNSUPPORTED, "batch must be 0 (default 128), 64, 128 or 256");
     if (cfg->sh_degree < -1 || cfg->sh_degree > 3) return fail(GSR_EINVAL, "sh_degree not in -1..3");

@@ -505,6 +505,7 @@ hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, 
     case 64: e = launch_fwd_t<1>(a, total_tiles, batch, s); break;
     case 128: e = launch_fwd_t<2>(a, total_tiles, batch, s); break;
     case 256: e = launch_fwd_t<4>(a, total_tiles, batch, s); break;
+    case 512: e = launch_fwd_t<8>(a, total_tiles, batch, s); break;
     default: return hipErrorInvalidValue;
     }
     return e != hipSuccess ? e : hipGetLastError();
@@ -575,6 +576,7 @@ hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, 
     case 64: e = launch_bwd_t<1>(a, total_tiles, batch, s); break;
     case 128: e = launch_bwd_t<2>(a, total_tiles, batch, s); break;
     case 256: e = launch_bwd_t<4>(a, total_tiles, batch, s); break;
+    case 512: e = launch_bwd_t<8>(a, total_tiles, batch, s); break;
     default: return hipErrorInvalidValue;
     }
     if (e == hipSuccess && a.acc && a.slots > 0) {

@@ -109,7 +109,7 @@ def _fill_and_bin(R, rec_arrays):
     return R.pair_count()
 
 
-@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8), (16, 8)])
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 8), (16, 8), (32, 16)])
 def test_bin_bitexact_shared_records(tile):
     """Keys (tile | depth bits), slot values and tile ranges equal the
     oracle's comparator sort bit for bit on the same float32 records."""
@@ -303,7 +303,8 @@ def test_forward_parity_cloud_2k():
 
 @pytest.mark.parametrize("seed,size,tile", [(1, (37, 29), (16, 16)), (2, (70, 41), (8, 8)),
                                             (3, (33, 65), (32, 8)), (4, (64, 64), (16, 8)),
-                                            (5, (1, 1), (16, 16)), (6, (17, 3), (8, 8))])
+                                            (5, (1, 1), (16, 16)), (6, (17, 3), (8, 8)),
+                                            (7, (70, 41), (32, 16)), (8, (33, 65), (16, 32))])
 def test_forward_parity_ragged(seed, size, tile):
     """Ragged image sizes (partial edge tiles) and every tile shape."""
     params, cam = scenes.cloud(100 + seed, 400, size[0], size[1], 40.0)
@@ -455,6 +456,14 @@ def test_backward_parity_smooth_setting():
     pose = scenes.left_perturb(scenes.identity_pose(), np.array([0.03, -0.02, 0.05, 0.04, -0.03, 0.02]))
     cfg = Config(alpha_min=0.0, T_min=0.0, alpha_max=1.0)
     _check_backward("smooth", params, [cam], pose[None], cfg, 17, with_dT=True)
+
+
+def test_backward_parity_512_pixel_tiles():
+    """Eight pixels per lane (32x16 and 16x32 tiles)."""
+    w = scenes.workload(0)
+    for tw, th in ((32, 16), (16, 32)):
+        _check_backward(f"cloud-2k {tw}x{th}", w["params"], w["cams"], w["poses"], Config(tile_w=tw, tile_h=th), 5,
+                        frac_max=0.01)
 
 
 def test_backward_parity_cloud_2k():
