@@ -9,9 +9,9 @@
 //              transposition (falling back to every digit when a run does
 //              not settle in 8 rounds).  Then it writes the final pairs: key (tile << 32 | depth
 //              bits), value slot = view * n + index.  Segments of up to
-//              GSR_SEG_ITEMS keys are sorted in LDS; longer ones by the block
-//              through global memory, GSR_SEG_ITEMS keys at a time,
-//              ping-ponging between the segment and the output key array.
+//              the block's LDS capacity are sorted in LDS; longer ones in
+//              chunks of that size, then merged pairwise through global
+//              memory.
 // k_order_*    processing order of the tiles: descending pair count, bucketed
 //              by floor(log2(count)), for the segment sort and compositing.
 //
@@ -48,8 +48,6 @@ struct SegLds {
     unsigned long long sk[ITEMS];          // keys in digit order (LDS path)
     uint32_t wcnt[WAVES][256];             // per-wave digit counters, then wave offsets
     uint32_t dstart[256];                  // block-local start of each digit
-    uint32_t run[256];                     // global path: running output offset per digit
-    uint32_t hist[256];
     uint32_t wsum[4];
     unsigned long long red[2][WAVES];
 };
@@ -146,8 +144,143 @@ __device__ __forceinline__ void write_pair(const SegArgs& a, uint32_t at, unsign
     a.vals[at] = vbase + (uint32_t)k;
 }
 
+// Sorts the m <= ITEMS keys src[0, m) with the whole block in LDS; on return
+// key[r] of thread (w, lane) holds the key of sorted position
+// w * R * 64 + r * 64 + lane (R = ceil(m / THREADS)) when that is below m.
+template <int WAVES, int ITEMS>
+__device__ void lds_sort(const unsigned long long* src, int m, unsigned long long (&key)[ITEMS / (WAVES * 64)],
+                         SegLds<WAVES, ITEMS>& L)
+{
+    constexpr int THREADS = WAVES * 64;
+    constexpr int MAXR = ITEMS / THREADS;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int R = (m + THREADS - 1) / THREADS;
+    uint32_t pos[MAXR];
+    unsigned long long o = 0ull, an = ~0ull;
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) {
+        if (r >= R) break;
+        const int li = w * R * 64 + r * 64 + lane;
+        key[r] = li < m ? src[li] : 0ull;
+        if (li < m) {
+            o |= key[r];
+            an &= key[r];
+        }
+    }
+    unsigned long long bor, band;
+    block_or_and(o, an, L, bor, band);
+    const unsigned long long diff = bor ^ band;
+    // depth digits first.  Keys that share a depth then stand in runs in
+    // emission order; odd-even transposition inside those runs puts them in
+    // index order (a few rounds: runs are short).  Runs that do not settle
+    // within 8 rounds fall back to sorting every digit, LSD from the index.
+    bool sorted = false, in_lds = false;
+    for (int d = 4; d < 8; ++d) {
+        if (((diff >> (8 * d)) & 255ull) == 0ull) continue;
+        rank_items<WAVES, ITEMS, MAXR>(key, R, m, 8 * d, pos, L);
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r) {
+            if (r >= R) break;
+            if (pos[r] != 0xffffffffu) L.sk[pos[r]] = key[r];
+        }
+        __syncthreads();
+        in_lds = true;
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r) {
+            if (r >= R) break;
+            const int li = w * R * 64 + r * 64 + lane;
+            if (li < m) key[r] = L.sk[li];
+        }
+        __syncthreads();
+    }
+    if ((diff & 0xffffffffull) == 0ull) {
+        sorted = true;  // a single key
+    } else if (diff >> 32) {
+        if (!in_lds) {
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+                if (r >= R) break;
+                const int li = w * R * 64 + r * 64 + lane;
+                if (li < m) L.sk[li] = key[r];
+            }
+            __syncthreads();
+        }
+        for (int round = 0; round < 8 && !sorted; ++round) {
+            bool swapped = false;
+            for (int par = 0; par < 2; ++par) {
+                for (int i = par + 2 * tid; i + 1 < m; i += 2 * THREADS) {
+                    const unsigned long long x = L.sk[i], y = L.sk[i + 1];
+                    if ((x >> 32) == (y >> 32) && x > y) {
+                        L.sk[i] = y;
+                        L.sk[i + 1] = x;
+                        swapped = true;
+                    }
+                }
+                __syncthreads();
+            }
+            sorted = __syncthreads_or(swapped) == 0;
+        }
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r) {
+            if (r >= R) break;
+            const int li = w * R * 64 + r * 64 + lane;
+            if (li < m) key[r] = L.sk[li];
+        }
+        __syncthreads();
+    }
+    if (!sorted) {
+        for (int d = 0; d < 8; ++d) {
+            if (((diff >> (8 * d)) & 255ull) == 0ull) continue;
+            rank_items<WAVES, ITEMS, MAXR>(key, R, m, 8 * d, pos, L);
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+                if (r >= R) break;
+                if (pos[r] != 0xffffffffu) L.sk[pos[r]] = key[r];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) {
+                if (r >= R) break;
+                const int li = w * R * 64 + r * 64 + lane;
+                if (li < m) key[r] = L.sk[li];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Merges the sorted runs A[0, na) and B[0, nb) (unique keys) with the whole
+// block: thread t produces the outputs [t per, (t + 1) per), per =
+// ceil((na + nb) / THREADS), finding how many of them come from A by a
+// binary search along its first diagonal (merge path), then merging
+// sequentially.  out(d, key) receives output position d.
+template <int THREADS, class Out>
+__device__ __forceinline__ void merge_runs(const unsigned long long* A, int na, const unsigned long long* B, int nb,
+                                           Out&& out)
+{
+    const int n = na + nb;
+    const int per = (n + THREADS - 1) / THREADS;
+    const int d0 = min(n, (int)threadIdx.x * per), d1 = min(n, d0 + per);
+    if (d0 >= d1) return;
+    int lo = max(0, d0 - nb), hi = min(d0, na);
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (A[mid] < B[d0 - 1 - mid]) lo = mid + 1;
+        else hi = mid;
+    }
+    int i = lo, j = d0 - lo;
+    for (int d = d0; d < d1; ++d) {
+        const bool take_a = j >= nb || (i < na && A[i] < B[j]);
+        out(d, take_a ? A[i++] : B[j++]);
+    }
+}
+
 // Sorts the segment of one tile with the whole block (WAVES * 64 threads,
-// ITEMS = 16 keys per thread fit in LDS).
+// ITEMS keys fit in LDS).  A longer segment is cut into chunks of ITEMS
+// keys, each sorted in LDS, and the sorted chunks are merged pairwise
+// (merge path) through global memory, ping-ponging between the segment's
+// emission buffer and its output key array; the last merge reads the
+// emission buffer and writes the final pairs.
 template <int WAVES, int ITEMS>
 __device__ void sort_segment(const SegArgs& a, uint32_t tile, uint2 rg, SegLds<WAVES, ITEMS>& L)
 {
@@ -157,102 +290,11 @@ __device__ void sort_segment(const SegArgs& a, uint32_t tile, uint2 rg, SegLds<W
     const int v = view_of_tile(a.views, (int)tile);
     const uint32_t vbase = (uint32_t)((int64_t)v * a.n);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    unsigned long long key[MAXR];
 
     if (m <= ITEMS) {
+        lds_sort<WAVES, ITEMS>(a.seg + rg.x, m, key, L);
         const int R = (m + THREADS - 1) / THREADS;
-        unsigned long long key[MAXR];
-        uint32_t pos[MAXR];
-        unsigned long long o = 0ull, an = ~0ull;
-#pragma unroll
-        for (int r = 0; r < MAXR; ++r) {
-            if (r >= R) break;
-            const int li = w * R * 64 + r * 64 + lane;
-            key[r] = li < m ? a.seg[rg.x + li] : 0ull;
-            if (li < m) {
-                o |= key[r];
-                an &= key[r];
-            }
-        }
-        unsigned long long bor, band;
-        block_or_and(o, an, L, bor, band);
-        const unsigned long long diff = bor ^ band;
-        // depth digits first.  Keys that share a depth then stand in runs in
-        // emission order; odd-even transposition inside those runs puts them in
-        // index order (a few rounds: runs are short).  Runs that do not settle
-        // within 8 rounds fall back to sorting every digit, LSD from the index.
-        bool sorted = false, in_lds = false;
-        for (int d = 4; d < 8; ++d) {
-            if (((diff >> (8 * d)) & 255ull) == 0ull) continue;
-            rank_items<WAVES, ITEMS, MAXR>(key, R, m, 8 * d, pos, L);
-#pragma unroll
-            for (int r = 0; r < MAXR; ++r) {
-                if (r >= R) break;
-                if (pos[r] != 0xffffffffu) L.sk[pos[r]] = key[r];
-            }
-            __syncthreads();
-            in_lds = true;
-#pragma unroll
-            for (int r = 0; r < MAXR; ++r) {
-                if (r >= R) break;
-                const int li = w * R * 64 + r * 64 + lane;
-                if (li < m) key[r] = L.sk[li];
-            }
-            __syncthreads();
-        }
-        if ((diff & 0xffffffffull) == 0ull) {
-            sorted = true;  // a single key
-        } else if (diff >> 32) {
-            if (!in_lds) {
-#pragma unroll
-                for (int r = 0; r < MAXR; ++r) {
-                    if (r >= R) break;
-                    const int li = w * R * 64 + r * 64 + lane;
-                    if (li < m) L.sk[li] = key[r];
-                }
-                __syncthreads();
-            }
-            for (int round = 0; round < 8 && !sorted; ++round) {
-                bool swapped = false;
-                for (int par = 0; par < 2; ++par) {
-                    for (int i = par + 2 * tid; i + 1 < m; i += 2 * THREADS) {
-                        const unsigned long long x = L.sk[i], y = L.sk[i + 1];
-                        if ((x >> 32) == (y >> 32) && x > y) {
-                            L.sk[i] = y;
-                            L.sk[i + 1] = x;
-                            swapped = true;
-                        }
-                    }
-                    __syncthreads();
-                }
-                sorted = __syncthreads_or(swapped) == 0;
-            }
-#pragma unroll
-            for (int r = 0; r < MAXR; ++r) {
-                if (r >= R) break;
-                const int li = w * R * 64 + r * 64 + lane;
-                if (li < m) key[r] = L.sk[li];
-            }
-            __syncthreads();
-        }
-        if (!sorted) {
-            for (int d = 0; d < 8; ++d) {
-                if (((diff >> (8 * d)) & 255ull) == 0ull) continue;
-                rank_items<WAVES, ITEMS, MAXR>(key, R, m, 8 * d, pos, L);
-#pragma unroll
-                for (int r = 0; r < MAXR; ++r) {
-                    if (r >= R) break;
-                    if (pos[r] != 0xffffffffu) L.sk[pos[r]] = key[r];
-                }
-                __syncthreads();
-#pragma unroll
-                for (int r = 0; r < MAXR; ++r) {
-                    if (r >= R) break;
-                    const int li = w * R * 64 + r * 64 + lane;
-                    if (li < m) key[r] = L.sk[li];
-                }
-                __syncthreads();
-            }
-        }
 #pragma unroll
         for (int r = 0; r < MAXR; ++r) {
             if (r >= R) break;
@@ -262,77 +304,41 @@ __device__ void sort_segment(const SegArgs& a, uint32_t tile, uint2 rg, SegLds<W
         return;
     }
 
-    // longer segment: LSD passes through global memory, ITEMS keys at a time
     unsigned long long* bufA = a.seg + rg.x;
     unsigned long long* bufB = a.keys + rg.x;  // output keys double as scratch
-    unsigned long long o = 0ull, an = ~0ull;
-    for (int i = tid; i < m; i += THREADS) {
-        const unsigned long long k = bufA[i];
-        o |= k;
-        an &= k;
-    }
-    unsigned long long bor, band;
-    block_or_and(o, an, L, bor, band);
-    const unsigned long long diff = bor ^ band;
-    unsigned long long* src = bufA;
-    unsigned long long* dst = bufB;
-    for (int d = 0; d < 8; ++d) {
-        if (((diff >> (8 * d)) & 255ull) == 0ull) continue;
-        const int shift = 8 * d;
-        if (tid < 256) L.hist[tid] = 0u;
-        __syncthreads();
-        for (int i = tid; i < m; i += THREADS) atomicAdd(&L.hist[(uint32_t)(src[i] >> shift) & 255u], 1u);
-        __syncthreads();
-        uint32_t x = 0, incl = 0;
-        if (tid < 256) {
-            x = L.hist[tid];
-            incl = x;
-            for (int off = 1; off < 64; off <<= 1) {
-                const uint32_t y = __shfl_up(incl, off, 64);
-                if (lane >= off) incl += y;
-            }
-            if (lane == 63) L.wsum[w] = incl;
-        }
-        __syncthreads();
-        if (tid < 256) {
-            uint32_t wofs = 0;
-            for (int k = 0; k < w; ++k) wofs += L.wsum[k];
-            L.run[tid] = wofs + incl - x;
-        }
-        for (int cb = 0; cb < m; cb += ITEMS) {
-            const int cm = min(ITEMS, m - cb);
-            const int R = (cm + THREADS - 1) / THREADS;
-            unsigned long long key[MAXR];
-            uint32_t pos[MAXR];
+    const int chunks = (m + ITEMS - 1) / ITEMS;
+    int passes = 0;
+    while ((1 << passes) < chunks) ++passes;
+    // the sorted chunks go where the last merge will read from bufA
+    unsigned long long* cur = (passes & 1) ? bufA : bufB;
+    for (int cb = 0; cb < m; cb += ITEMS) {
+        const int cm = min(ITEMS, m - cb);
+        lds_sort<WAVES, ITEMS>(bufA + cb, cm, key, L);
+        const int R = (cm + THREADS - 1) / THREADS;
 #pragma unroll
-            for (int r = 0; r < MAXR; ++r) {
-                if (r >= R) break;
-                const int li = w * R * 64 + r * 64 + lane;
-                key[r] = li < cm ? src[cb + li] : 0ull;
-            }
-            rank_items<WAVES, ITEMS, MAXR>(key, R, cm, shift, pos, L);
-#pragma unroll
-            for (int r = 0; r < MAXR; ++r) {
-                if (r >= R) break;
-                if (pos[r] != 0xffffffffu) {
-                    const uint32_t dg = (uint32_t)(key[r] >> shift) & 255u;
-                    dst[L.run[dg] + (pos[r] - L.dstart[dg])] = key[r];
-                }
-            }
-            __syncthreads();
-            // advance the running offsets by this chunk's digit counts
-            if (tid < 256) {
-                const uint32_t next = tid < 255 ? L.dstart[tid + 1] : (uint32_t)cm;
-                L.run[tid] += next - L.dstart[tid];
-            }
-            __syncthreads();
+        for (int r = 0; r < MAXR; ++r) {
+            if (r >= R) break;
+            const int li = w * R * 64 + r * 64 + lane;
+            if (li < cm) cur[cb + li] = key[r];
         }
-        unsigned long long* t = src;
-        src = dst;
-        dst = t;
+        __syncthreads();
     }
-    // src holds the sorted keys (in place when it is the output array)
-    for (int i = tid; i < m; i += THREADS) write_pair(a, rg.x + (uint32_t)i, src[i], tile, vbase);
+    for (int p = 1, width = ITEMS; p <= passes; ++p, width *= 2) {
+        unsigned long long* nxt = cur == bufA ? bufB : bufA;
+        for (int a0 = 0; a0 < m; a0 += 2 * width) {
+            const int na = min(width, m - a0);
+            const int nb = max(0, min(width, m - a0 - width));
+            if (p == passes)
+                merge_runs<THREADS>(cur + a0, na, cur + a0 + na, nb, [&](int d, unsigned long long k) {
+                    write_pair(a, rg.x + (uint32_t)(a0 + d), k, tile, vbase);
+                });
+            else
+                merge_runs<THREADS>(cur + a0, na, cur + a0 + na, nb,
+                                    [&](int d, unsigned long long k) { nxt[a0 + d] = k; });
+        }
+        __syncthreads();
+        cur = nxt;
+    }
 }
 
 // one block per tile, in the tiles' processing order (longest first)

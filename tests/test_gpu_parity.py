@@ -170,10 +170,11 @@ def _disc_records(rng, S, w, h, scale):
 
 
 def test_bin_bitexact_long_segments():
-    """Long tile lists: 6,000 pairs (sorted in LDS) and 9,000 and 20,000
-    (beyond what one block holds: sorted through global memory), one seventh
-    of the keys at one depth."""
-    for n in (6000, 9000, 20000):
+    """Long tile lists, one seventh of the keys at one depth: 6,000 pairs
+    (the short class, in LDS), 9,000 (the long class, in LDS), and 20,000,
+    40,000 and 70,000 (beyond what one block holds: chunks sorted in LDS,
+    then one, two and three merge passes, the last with an odd run)."""
+    for n in (6000, 9000, 20000, 40000, 70000):
         cams = [{"width": 16, "height": 16, "fx": 1, "fy": 1, "cx": 0, "cy": 0}]
         rng = np.random.default_rng(n)
         recs = _disc_records(rng, n, 16, 16, 1.0)
