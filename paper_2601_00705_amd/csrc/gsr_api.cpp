@@ -254,7 +254,7 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->off_seg = take(sizeof(unsigned long long) * pair_capacity);
     p->off_ranges = take(sizeof(uint2) * tiles);
     p->off_order = take(sizeof(uint32_t) * tiles);
-    p->off_buckets = take(sizeof(uint32_t) * 64);
+    p->off_buckets = take(sizeof(uint32_t) * 66);
     p->off_cnt = take(sizeof(uint32_t) * (size_t)p->chunks * (size_t)tiles);
     p->off_xip = take(sizeof(double) * 6 * (size_t)n_views * p->bwd_blocks);
     p->off_xip_sh = take(sizeof(double) * 6 * (size_t)n_views * p->bwd_blocks);
@@ -432,6 +432,7 @@ extern "C" gsr_status gsr_bin(gsr_plan* plan, void* stream)
     g.seg = b.seg;
     g.keys = at<unsigned long long>(plan, plan->off_keys);
     g.vals = at<uint32_t>(plan, plan->off_vals);
+    g.queue = r.buckets + 64;
     g.n = plan->n;
     hipError_t e;
     {

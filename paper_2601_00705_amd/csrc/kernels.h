@@ -45,6 +45,7 @@ struct SegArgs {
     unsigned long long* seg;   // [capacity]: emitted keys, sorted in place per tile (scratch)
     unsigned long long* keys;  // [capacity]: sorted (tile << 32 | depth bits)
     uint32_t* vals;            // [capacity]: sorted slots
+    uint32_t* queue;           // [1]: next list of the short class (zeroed by the ordering)
     int64_t n;
 };
 
@@ -53,7 +54,7 @@ struct RangeArgs {
     const uint2* ranges;
     int32_t total_tiles;
     uint32_t* order;           // [tiles]: tiles by pair count, descending
-    uint32_t* buckets;         // [64]: per log2-bucket counts, then cursors
+    uint32_t* buckets;         // [66]: per log2-bucket counts, cursors, then the sort queue head
 };
 
 struct RasterArgs {
@@ -254,8 +255,10 @@ struct KnnArgs {
 #define GSR_TRACK_SLOTS 8           // partial sums per block (4 exposure sums, 3 loss/sign sums)
 #define GSR_BIN_CHUNK 256           // Gaussians staged in LDS at a time by the binning blocks (x256)
 #define GSR_BIN_LDS_TILES 16384     // views with more tiles count and place with global atomics
+#define GSR_SEG_SMALL_THREADS 256   // segments below GSR_SEG_SMALL_ITEMS keys: 256-thread blocks
+#define GSR_SEG_SMALL_ITEMS 2048
 #define GSR_SEG_THREADS 512
-#define GSR_SEG_ITEMS 8192          // segments up to this size are sorted in LDS
+#define GSR_SEG_ITEMS 8192          // segments below this size are sorted in LDS by 512-thread blocks
 #define GSR_SEG_LONG_THREADS 1024   // longer segments: one 1024-thread block each
 #define GSR_SEG_LONG_ITEMS 16384    // ... holding this many keys in LDS
 

@@ -281,7 +281,7 @@ __device__ __forceinline__ void merge_runs(const unsigned long long* A, int na, 
 // (merge path) through global memory, ping-ponging between the segment's
 // emission buffer and its output key array; the last merge reads the
 // emission buffer and writes the final pairs.
-template <int WAVES, int ITEMS>
+template <int WAVES, int ITEMS, bool CHUNKED>
 __device__ void sort_segment(const SegArgs& a, uint32_t tile, uint2 rg, SegLds<WAVES, ITEMS>& L)
 {
     constexpr int THREADS = WAVES * 64;
@@ -303,6 +303,7 @@ __device__ void sort_segment(const SegArgs& a, uint32_t tile, uint2 rg, SegLds<W
         }
         return;
     }
+    if (!CHUNKED) return;  // not reached: the class's lists fit in LDS
 
     unsigned long long* bufA = a.seg + rg.x;
     unsigned long long* bufB = a.keys + rg.x;  // output keys double as scratch
@@ -341,27 +342,71 @@ __device__ void sort_segment(const SegArgs& a, uint32_t tile, uint2 rg, SegLds<W
     }
 }
 
-// one block per tile, in the tiles' processing order (longest first)
-// LONG = false: segments of up to GSR_SEG_ITEMS keys, with GSR_SEG_THREADS
-// threads; LONG = true: the longer ones, with GSR_SEG_LONG_THREADS threads
-// and GSR_SEG_LONG_ITEMS keys in LDS (through global memory in chunks of
-// that size beyond it).  Block b takes the b-th tile of the processing
-// order; a block whose tile belongs to the other class returns at once.
-template <int THREADS, int ITEMS, bool LONG>
-__global__ __launch_bounds__(THREADS) void k_seg_sort(SegArgs a)
+// first position of the processing order whose tile has fewer than `below`
+// pairs (the order is grouped by floor(log2(count)), longest first, and
+// `below` is a power of two, so the predicate is monotone along it)
+__device__ __forceinline__ int first_below(const SegArgs& a, int total_tiles, uint32_t below)
+{
+    int lo = 0, hi = total_tiles;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const uint2 r = a.ranges[a.order[mid]];
+        if (r.y - r.x < below) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+// Three classes of segments, each a contiguous stretch of the processing
+// order (longest first).  CLASS 2, lists of GSR_SEG_ITEMS keys or more, and
+// CLASS 1, from GSR_SEG_SMALL_ITEMS up to GSR_SEG_ITEMS: block b takes
+// position b and returns at once if that tile belongs to another class (the
+// middle class's blocks retire tile by tile, which lets the long class's
+// blocks in; persistent middle blocks measured slower where long lists are
+// many).  CLASS 0, below GSR_SEG_SMALL_ITEMS: persistent 256-thread blocks
+// take tiles from a work queue over their stretch (found by binary search),
+// so no block is spent on another class's tile; the small blocks keep more
+// short lists in flight per CU.
+template <int THREADS, int ITEMS, int CLASS>
+__global__ __launch_bounds__(THREADS) void k_seg_sort(SegArgs a, int total_tiles)
 {
     __shared__ SegLds<THREADS / 64, ITEMS> L;
     if (a.counters->overflow) return;
-    const uint32_t tile = a.order[blockIdx.x];
-    const uint2 rg = a.ranges[tile];
-    const uint32_t m = rg.y - rg.x;
-    if (m == 0 || LONG != (m > (uint32_t)GSR_SEG_ITEMS)) return;
-    sort_segment<THREADS / 64, ITEMS>(a, tile, rg, L);
+    if (CLASS == 2) {
+        const uint32_t tile = a.order[blockIdx.x];
+        const uint2 rg = a.ranges[tile];
+        if (rg.y - rg.x < (uint32_t)GSR_SEG_ITEMS) return;
+        sort_segment<THREADS / 64, ITEMS, true>(a, tile, rg, L);
+        return;
+    }
+    if (CLASS == 1) {
+        const uint32_t tile = a.order[blockIdx.x];
+        const uint2 rg = a.ranges[tile];
+        const uint32_t m = rg.y - rg.x;
+        if (m < (uint32_t)GSR_SEG_SMALL_ITEMS || m >= (uint32_t)GSR_SEG_ITEMS) return;
+        sort_segment<THREADS / 64, ITEMS, false>(a, tile, rg, L);
+        return;
+    }
+    const int begin = first_below(a, total_tiles, GSR_SEG_SMALL_ITEMS);
+    const int end = total_tiles;
+    __shared__ int next;
+    for (;;) {
+        if (threadIdx.x == 0) next = begin + (int)atomicAdd(&a.queue[CLASS], 1u);
+        __syncthreads();
+        const int p = next;
+        __syncthreads();
+        if (p >= end) break;
+        const uint32_t tile = a.order[p];
+        const uint2 rg = a.ranges[tile];
+        if (rg.y == rg.x) break;  // empty tiles end the order
+        sort_segment<THREADS / 64, ITEMS, false>(a, tile, rg, L);
+    }
 }
 
-// The two classes run concurrently: the long segments on `side`, forked
-// from `s` after the tile ranges and joined back before anything later on
-// `s` (the fork and join are recorded into a graph when `s` is captured).
+// The long segments run on `side`, forked from `s` after the tile ranges,
+// followed there by the short ones; the middle class runs on `s`; `side` is
+// joined back before anything later on `s` (the fork and join are recorded
+// into a graph when `s` is captured).
 hipError_t launch_seg_sort(const SegArgs& a, int total_tiles, int64_t capacity, hipStream_t s, hipStream_t side,
                            hipEvent_t fork, hipEvent_t join)
 {
@@ -369,14 +414,19 @@ hipError_t launch_seg_sort(const SegArgs& a, int total_tiles, int64_t capacity, 
     hipError_t e = hipEventRecord(fork, s);
     if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
     if (e != hipSuccess) return e;
-    // the long segments lead the processing order (longest first), and at
-    // most capacity / (GSR_SEG_ITEMS + 1) of them fit in the pair buffer
-    const int64_t longs = capacity / (GSR_SEG_ITEMS + 1) + 1;
+    // the long segments lead the processing order, and at most
+    // capacity / GSR_SEG_ITEMS of them fit in the pair buffer
+    const int64_t longs = capacity / GSR_SEG_ITEMS + 1;
     const unsigned long_grid = (unsigned)(longs < total_tiles ? longs : total_tiles);
-    hipLaunchKernelGGL((k_seg_sort<GSR_SEG_LONG_THREADS, GSR_SEG_LONG_ITEMS, true>), dim3(long_grid),
-                       dim3(GSR_SEG_LONG_THREADS), 0, side, a);
-    hipLaunchKernelGGL((k_seg_sort<GSR_SEG_THREADS, GSR_SEG_ITEMS, false>), dim3((unsigned)total_tiles),
-                       dim3(GSR_SEG_THREADS), 0, s, a);
+    hipLaunchKernelGGL((k_seg_sort<GSR_SEG_LONG_THREADS, GSR_SEG_LONG_ITEMS, 2>), dim3(long_grid),
+                       dim3(GSR_SEG_LONG_THREADS), 0, side, a, total_tiles);
+    // the small class: four persistent blocks per CU (what their registers
+    // allow)
+    const unsigned small_grid = (unsigned)(total_tiles < 1024 ? total_tiles : 1024);
+    hipLaunchKernelGGL((k_seg_sort<GSR_SEG_SMALL_THREADS, GSR_SEG_SMALL_ITEMS, 0>), dim3(small_grid),
+                       dim3(GSR_SEG_SMALL_THREADS), 0, side, a, total_tiles);
+    hipLaunchKernelGGL((k_seg_sort<GSR_SEG_THREADS, GSR_SEG_ITEMS, 1>), dim3((unsigned)total_tiles),
+                       dim3(GSR_SEG_THREADS), 0, s, a, total_tiles);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipEventRecord(join, side);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
@@ -395,7 +445,7 @@ __device__ __forceinline__ uint32_t count_bucket(uint2 r)
 
 __global__ void k_order_zero(RangeArgs a)
 {
-    if (threadIdx.x < 64) a.buckets[threadIdx.x] = 0u;
+    if (threadIdx.x < 66) a.buckets[threadIdx.x] = 0u;
 }
 
 __global__ void k_order_count(RangeArgs a)
@@ -439,7 +489,7 @@ hipError_t launch_order(const RangeArgs& a, hipStream_t s)
 {
     if (a.total_tiles == 0) return hipSuccess;
     const int tb = (a.total_tiles + 255) / 256;
-    hipLaunchKernelGGL(k_order_zero, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_order_zero, dim3(1), dim3(128), 0, s, a);
     hipLaunchKernelGGL(k_order_count, dim3(tb), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_order_place, dim3(tb), dim3(256), 0, s, a);
     return hipGetLastError();
