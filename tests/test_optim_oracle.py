@@ -2,7 +2,8 @@
 own Adam and gradient clipping (a library routine), its closed-form first
 step, the EMA anchor's limits; the co-visibility counts against scikit-learn's
 Jaccard score and set identities; the pruning rule against a per-Gaussian
-evaluation through the explicit covariance R diag(s^2) R^T."""
+evaluation through the explicit covariance R diag(s^2) R^T; merging against
+a copy of itself, a closed-form weighted covariance and its conditions."""
 import numpy as np
 import pytest
 import torch
@@ -124,3 +125,68 @@ def test_prune_rule_against_explicit_covariance():
         want = not (m_obs[i] < 2 or v_vis[i] < 0.3 or np.trace(S) > 1.5 ** 2 or alpha < 0.05)
         assert keep[i] == want, i
     assert 0 < keep.sum() < n
+
+
+def _pair_params(rng, n=6):
+    p = {"mean": rng.normal(size=(3, n)) * 10.0, "quat": rng.normal(size=(4, n)),
+         "log_scale": rng.uniform(-1, 0, size=(3, n)), "opacity_logit": rng.normal(size=n),
+         "colour": rng.uniform(size=(3, n))}
+    return p
+
+
+def test_merging_a_gaussian_with_its_copy_returns_it():
+    rng = np.random.default_rng(10)
+    p = _pair_params(rng)
+    for k in p:
+        p[k][..., 1] = p[k][..., 0]
+    p["mean"][:, 1] += 1e-6  # not identical positions: a unique nearest neighbour
+    out, keep = O.merge(p, np.ones(6), radius=0.5, colour_tol=0.1)
+    assert keep.tolist() == [True, False, True, True, True, True]
+    S0 = O.covariance(p["quat"][:, 0], p["log_scale"][:, 0])
+    assert np.allclose(O.covariance(out["quat"][:, 0], out["log_scale"][:, 0]), S0, rtol=1e-10, atol=1e-14)
+    assert np.allclose(out["colour"][:, 0], p["colour"][:, 0]) and np.isclose(out["opacity_logit"][0],
+                                                                               p["opacity_logit"][0])
+    for k in p:  # the others untouched
+        assert np.array_equal(out[k][..., 2:], p[k][..., 2:])
+
+
+def test_merged_covariance_and_weights():
+    """Two axis-aligned Gaussians, visibilities 1 and 3: every merged
+    quantity is the 1:3 weighted mean (covariance through R diag(s^2) R^T,
+    opacity as alpha)."""
+    rng = np.random.default_rng(11)
+    p = _pair_params(rng, 4)
+    p["mean"][:, 1] = p["mean"][:, 0] + np.array([0.01, 0.0, 0.0])
+    p["quat"][:, :2] = np.array([[1.0, 0, 0, 0], [1.0, 0, 0, 0]]).T
+    p["log_scale"][:, 0] = np.log([0.1, 0.2, 0.3])
+    p["log_scale"][:, 1] = np.log([0.3, 0.2, 0.1])
+    p["colour"][:, 1] = p["colour"][:, 0] + 0.01
+    out, keep = O.merge(p, np.array([1.0, 3.0, 1.0, 1.0]), radius=1.0, colour_tol=0.05)
+    assert keep.tolist() == [True, False, True, True]
+    want = np.diag((np.array([0.1, 0.2, 0.3]) ** 2 + 3 * np.array([0.3, 0.2, 0.1]) ** 2) / 4)
+    assert np.allclose(O.covariance(out["quat"][:, 0], out["log_scale"][:, 0]), want, rtol=1e-12, atol=1e-15)
+    assert np.allclose(out["mean"][:, 0], (p["mean"][:, 0] + 3 * p["mean"][:, 1]) / 4)
+    a = lambda z: 1 / (1 + np.exp(-z))  # noqa: E731
+    assert np.isclose(a(out["opacity_logit"][0]), (a(p["opacity_logit"][0]) + 3 * a(p["opacity_logit"][1])) / 4)
+
+
+def test_merge_conditions():
+    rng = np.random.default_rng(12)
+    p = _pair_params(rng, 3)
+    p["mean"][:, 1] = p["mean"][:, 0] + 0.05
+    p["log_scale"][:, :2] = np.log(0.1)
+    p["colour"][:, 1] = p["colour"][:, 0]
+    # distance 0.0866 vs radius 0.5 x 0.1: too far
+    assert O.merge(p, np.ones(3), radius=0.5, colour_tol=0.1)[1].all()
+    assert not O.merge(p, np.ones(3), radius=1.0, colour_tol=0.1)[1].all()
+    p["colour"][0, 1] += 0.2  # colours too different
+    assert O.merge(p, np.ones(3), radius=1.0, colour_tol=0.1)[1].all()
+    # a nearest neighbour that is not mutual merges nothing
+    q = {k: v.copy() for k, v in _pair_params(rng, 3).items()}
+    q["mean"][:, 0] = 0.0
+    q["mean"][:, 1] = [1.0, 0, 0]
+    q["mean"][:, 2] = [1.5, 0, 0]   # 0 -> 1, 1 -> 2, 2 -> 1: only (1, 2) is mutual
+    q["log_scale"][:] = np.log(10.0)
+    q["colour"][:] = 0.5
+    _, keep = O.merge(q, np.ones(3), radius=1.0, colour_tol=0.1)
+    assert keep.tolist() == [True, True, False]
