@@ -249,7 +249,13 @@ def maintenance_measurement(torch, w, params, T_final, cams, reps, log):
       co-visibility: per frame pixel, T of the frame and of the key (8 B);
       pruning: per Gaussian, two passes reading m, v, three log-scales and
             the opacity logit (2 x 24 B), the kept index (4 B), and the
-            compaction of 3 log-scale rows (read + write 24 B)."""
+            compaction of 3 log-scale rows (read + write 24 B);
+      merging: per Gaussian, read its neighbour index, the neighbour's
+            index, its visibility and every parameter row, write every row
+            and the keep flag (8 + 4 + 2 x 4 x rows + 4 B), then the keep
+            list (two passes over the flags, 8 B, and the index, 4 B).
+    The nearest-neighbour search before merging is a grid search, reported
+    by its time only."""
     import numpy as np
     from paper_2601_00705_amd import maintain
     n = int(params["opacity_logit"].shape[0])
@@ -277,10 +283,22 @@ def maintenance_measurement(torch, w, params, T_final, cams, reps, log):
 
     t_pr = _graph_ms(torch, prune_and_compact, reps)
     b_pr = (2 * 24 + 4 + 24) * n
-    out = {}
+    t_nn = _graph_ms(torch, lambda: maintain.nearest(P["mean"]), max(reps // 4, 2), calls=2)
+    nn = maintain.nearest(P["mean"])
+
+    def merge_and_list():
+        _, keep, _ = maintain.merge(P, v_vis, 1.0, 0.05, nn=nn)
+        state["list"] = maintain.keep_list(keep)
+
+    t_mg = _graph_ms(torch, merge_and_list, reps)
+    rows = floats // n
+    b_mg = (8 + 4 + 8 * rows + 4 + 8 + 4) * n
+    out = {"nearest": {"ms": t_nn, "work": f"{n} Gaussians"}}
+    log(f"maintenance nearest: {t_nn:.4f} ms")
     for name, t, b, unit in (("adam", t_adam, b_adam, f"{floats} floats"),
                              ("covis", t_cov, b_cov, f"{len(idx)} frames x {key[0]}x{key[1]}"),
-                             ("prune_compact", t_pr, b_pr, f"{n} Gaussians")):
+                             ("prune_compact", t_pr, b_pr, f"{n} Gaussians"),
+                             ("merge_list", t_mg, b_mg, f"{n} Gaussians, {rows} rows")):
         out[name] = {"ms": t, "bound": "hbm", "achieved": b / (t * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, "work": unit}
         log(f"maintenance {name}: {t:.4f} ms, {out[name]['achieved']:.0f} GB/s ({out[name]['frac']:.2f} of HBM)")

@@ -19,10 +19,11 @@
  *     (app-weight), and its gradient seed for gsr_render_bwd.
  *   - gsr_loss_mapping: the mapping loss of the appendix's optimisation
  *     settings, L1 plus lambda_dssim (1 - SSIM), and its gradient seed.
- *   - gsr_adam_step, gsr_covis, gsr_prune, gsr_compact: map maintenance,
+ *   - gsr_adam_step, gsr_covis, gsr_prune, gsr_compact, gsr_nearest,
+ *     gsr_merge, gsr_keep_list: map maintenance,
  *     the optimiser step of the appendix's settings with the anchor of Eq.
  *     (app-ema), the co-visibility score of Eq. (iou), and the pruning rule
- *     of Sec. "Insertion, Lightweight Merging, and Pruning".
+ *     and merging of Sec. "Insertion, Lightweight Merging, and Pruning".
  *   - gsr_seed_triangulate, gsr_seed_scale: the one-shot Gaussian seeding of
  *     Sec. "Dense Feature Matching" (Eq. (conf), two-view linear
  *     triangulation) and the appendix's initialisation (Eq.
@@ -319,6 +320,17 @@ size_t gsr_seed_scale_workspace_bytes(int64_t n);
 gsr_status gsr_seed_scale(int64_t n, const float *mean, const int32_t *valid, float floor_scale, void *workspace,
                           size_t workspace_bytes, float *log_scale, void *stream);
 
+/* Nearest other valid Gaussian of each valid Gaussian (Euclidean distance of
+ * the centres; ties go to the lower index), the neighbour search behind the
+ * merging of Sec. "Insertion, Lightweight Merging, and Pruning".  mean
+ * [3][n], valid [n] (device; 0 excludes a Gaussian both as a query and as a
+ * neighbour).  Output nn_index [n] (device): the neighbour's index, -1 for
+ * an invalid Gaussian or one with no valid other.  workspace: device,
+ * gsr_seed_scale_workspace_bytes(n) bytes (the same search).  n out of
+ * [0, 2^31) or a null buffer: GSR_EINVAL, nothing enqueued. */
+gsr_status gsr_nearest(int64_t n, const float *mean, const int32_t *valid, void *workspace, size_t workspace_bytes,
+                       int32_t *nn_index, void *stream);
+
 /* ---- map maintenance (independent of any plan) ----------------------- */
 
 /* Five parameter planes in the layout of gsr_gaussians: mean [3][n],
@@ -397,6 +409,33 @@ gsr_status gsr_prune(int64_t n, const int32_t *m_obs, const float *v_vis, const 
  * overlapping); columns from *kept on are left as they are. */
 gsr_status gsr_compact(int64_t n, int32_t rows, const float *src, const int32_t *keep_index, const int64_t *kept,
                        float *dst, void *stream);
+
+/* Merging of Sec. "Insertion, Lightweight Merging, and Pruning" (readings
+ * where the paper is silent): i and j = nn_index[i] merge when they are
+ * mutual nearest neighbours (nn_index[j] == i), their centres lie within
+ * radius * min(sbar_i, sbar_j), sbar = exp(mean of the three log_scales)
+ * (highly overlapping footprints), and the first three colour rows differ
+ * by at most colour_tol each (similar colours).  The pair becomes one
+ * Gaussian at the lower index with the v_vis-weighted mean (equal weights
+ * when both are 0) of mean, colour rows, opacity (as sigmoid) and world
+ * covariance R diag(s^2) R^T, split back into a unit quaternion and
+ * log-scales by its eigen-decomposition (FP64 arithmetic); the higher index
+ * is marked dropped.  params: the input planes; out: separate output planes
+ * of the same shapes, not overlapping the input (every column written: a
+ * copy for Gaussians not merged).  nn_index [n] from gsr_nearest; v_vis [n].
+ * keep [n] (device): 1 kept, 0 merged away, for gsr_keep_list.  Errors:
+ * GSR_EINVAL for null planes, aliasing planes, colour_rows out of [3, 48] or
+ * a negative or non-finite radius or colour_tol; nothing enqueued. */
+gsr_status gsr_merge(int64_t n, int32_t colour_rows, const gsr_planes *params, const float *v_vis,
+                     const int32_t *nn_index, double radius, double colour_tol, gsr_planes *out, int32_t *keep,
+                     void *stream);
+
+/* Ordered list of the set entries of a 0/1 mask [n] (device): keep_index
+ * receives the indices i with mask[i] != 0 in increasing order in its first
+ * *kept entries, for gsr_compact.  workspace: device,
+ * gsr_prune_workspace_bytes(n) bytes.  n must lie in [1, 2^31). */
+gsr_status gsr_keep_list(int64_t n, const int32_t *mask, int32_t *keep_index, int64_t *kept, void *workspace,
+                         void *stream);
 
 /* Rate of the device wall clock of the current device (the clock of the
  * layout's stamps), in ticks per second. */

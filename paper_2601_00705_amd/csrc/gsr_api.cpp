@@ -832,14 +832,9 @@ extern "C" size_t gsr_seed_scale_workspace_bytes(int64_t n)
     return knn_layout(n).total;
 }
 
-extern "C" gsr_status gsr_seed_scale(int64_t n, const float* mean, const int32_t* valid, float floor_scale,
-                                     void* workspace, size_t workspace_bytes, float* log_scale, void* stream)
+static gsr_status knn_run(int64_t n, const float* mean, const int32_t* valid, float floor_scale, void* workspace,
+                          size_t workspace_bytes, float* log_scale, int32_t* nn_index, void* stream, const char* who)
 {
-    g_err.clear();
-    if (n < 0 || n >= (1ll << 31)) return fail(GSR_EINVAL, "n out of range");
-    if (!(floor_scale > 0.0f) || !std::isfinite(floor_scale)) return fail(GSR_EINVAL, "floor_scale must be positive");
-    if (n == 0) return GSR_OK;
-    if (!mean || !valid || !log_scale || !workspace) return fail(GSR_EINVAL, "null buffer");
     const KnnLayout L = knn_layout(n);
     if (workspace_bytes < L.total) return fail(GSR_EINVAL, "workspace too small");
     char* ws = (char*)workspace;
@@ -868,8 +863,31 @@ extern "C" gsr_status gsr_seed_scale(int64_t n, const float* mean, const int32_t
     a.bf_list = (uint32_t*)(ws + L.bf_list);
     a.bf_count = (uint32_t*)(ws + L.bf_count);
     a.log_scale = log_scale;
+    a.nn_index = nn_index;
     hipError_t e = launch_seed_scale(a, (hipStream_t)stream);
-    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_seed_scale");
+    return e == hipSuccess ? GSR_OK : hip_fail(e, who);
+}
+
+extern "C" gsr_status gsr_seed_scale(int64_t n, const float* mean, const int32_t* valid, float floor_scale,
+                                     void* workspace, size_t workspace_bytes, float* log_scale, void* stream)
+{
+    g_err.clear();
+    if (n < 0 || n >= (1ll << 31)) return fail(GSR_EINVAL, "n out of range");
+    if (!(floor_scale > 0.0f) || !std::isfinite(floor_scale)) return fail(GSR_EINVAL, "floor_scale must be positive");
+    if (n == 0) return GSR_OK;
+    if (!mean || !valid || !log_scale || !workspace) return fail(GSR_EINVAL, "null buffer");
+    return knn_run(n, mean, valid, floor_scale, workspace, workspace_bytes, log_scale, nullptr, stream,
+                   "gsr_seed_scale");
+}
+
+extern "C" gsr_status gsr_nearest(int64_t n, const float* mean, const int32_t* valid, void* workspace,
+                                  size_t workspace_bytes, int32_t* nn_index, void* stream)
+{
+    g_err.clear();
+    if (n < 0 || n >= (1ll << 31)) return fail(GSR_EINVAL, "n out of range");
+    if (n == 0) return GSR_OK;
+    if (!mean || !valid || !nn_index || !workspace) return fail(GSR_EINVAL, "null buffer");
+    return knn_run(n, mean, valid, 1.0f, workspace, workspace_bytes, nullptr, nn_index, stream, "gsr_nearest");
 }
 
 // ---- map maintenance ------------------------------------------------------
@@ -1009,4 +1027,56 @@ extern "C" gsr_status gsr_device_clock_hz(double* hz)
     if (e != hipSuccess) return hip_fail(e, "gsr_device_clock_hz");
     *hz = 1000.0 * (double)khz;
     return GSR_OK;
+}
+
+extern "C" gsr_status gsr_merge(int64_t n, int32_t colour_rows, const gsr_planes* params, const float* v_vis,
+                                const int32_t* nn_index, double radius, double colour_tol, gsr_planes* out,
+                                int32_t* keep, void* stream)
+{
+    g_err.clear();
+    if (!params || !out || !v_vis || !nn_index || !keep) return fail(GSR_EINVAL, "null argument");
+    if (n < 0 || n > (1ll << 31) - 1 || colour_rows < 3 || colour_rows > 48)
+        return fail(GSR_EINVAL, "n or colour_rows");
+    if (!(radius >= 0.0) || !std::isfinite(radius) || !(colour_tol >= 0.0) || !std::isfinite(colour_tol))
+        return fail(GSR_EINVAL, "radius and colour_tol must be finite and non-negative");
+    if (n == 0) return GSR_OK;
+    MergeArgs a{};
+    a.n = n;
+    a.colour_rows = colour_rows;
+    const gsr_planes* sets[2] = {params, out};
+    for (int k = 0; k < 5; ++k) {
+        for (int s = 0; s < 2; ++s) {
+            const gsr_planes* q = sets[s];
+            float* ptr = k == 0 ? q->mean : k == 1 ? q->quat : k == 2 ? q->log_scale : k == 3 ? q->opacity_logit
+                                                                                           : q->colour;
+            if (!ptr) return fail(GSR_EINVAL, "null plane");
+            if (s == 0) a.in[k] = ptr;
+            else a.out[k] = ptr;
+        }
+        if (a.in[k] == a.out[k]) return fail(GSR_EINVAL, "merge output planes must not alias the input");
+    }
+    a.v_vis = v_vis;
+    a.nn = nn_index;
+    a.radius = radius;
+    a.colour_tol = colour_tol;
+    a.keep = keep;
+    hipError_t e = launch_merge(a, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_merge");
+}
+
+extern "C" gsr_status gsr_keep_list(int64_t n, const int32_t* mask, int32_t* keep_index, int64_t* kept,
+                                    void* workspace, void* stream)
+{
+    g_err.clear();
+    if (!mask || !keep_index || !kept || !workspace) return fail(GSR_EINVAL, "null argument");
+    if (n <= 0 || n > (1ll << 31) - 1) return fail(GSR_EINVAL, "n must lie in [1, 2^31)");
+    PruneArgs a{};
+    a.n = n;
+    a.blocks = (int32_t)((n + GSR_PRUNE_CHUNK - 1) / GSR_PRUNE_CHUNK);
+    a.mask = mask;
+    a.block_count = (uint32_t*)workspace;
+    a.keep_index = keep_index;
+    a.kept = (long long*)kept;
+    hipError_t e = launch_prune(a, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_keep_list");
 }

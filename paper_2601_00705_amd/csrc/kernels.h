@@ -168,11 +168,23 @@ struct PruneArgs {
     const float* v_vis;
     const float* log_scale;    // [3][n]
     const float* opacity_logit;
+    const int32_t* mask;       // null: the pruning rule; else keep where mask != 0
     int32_t m_min;
     double v_min, sigma_max2, alpha_min;
     uint32_t* block_count;     // [blocks]: kept per block, then offsets
     int32_t* keep_index;       // [n]: kept indices in order
     long long* kept;           // [1]
+};
+
+struct MergeArgs {
+    int64_t n;
+    int32_t colour_rows;
+    const float* in[5];        // planes: mean, quat, log_scale, opacity_logit, colour
+    float* out[5];             // the same layout
+    const float* v_vis;        // [n] merge weights
+    const int32_t* nn;         // [n] nearest other Gaussian (-1: none)
+    double radius, colour_tol;
+    int32_t* keep;             // [n] 1 kept, 0 merged into its partner
 };
 
 struct CompactArgs {
@@ -245,6 +257,7 @@ struct KnnArgs {
     uint32_t* fine_rank;       // [GSR_KNN_LEVELS][n]
     float4* fine_pts;          // [GSR_KNN_LEVELS][n]: (x, y, z, index bits) in fine-bucket order
     float4* cell_pts;          // [n]: the same in coarse-cell order
+    int32_t* nn_index;         // [n] or null: each seed's nearest other seed (-1: none)
     uint32_t* scan_tot;        // block totals of the scans
     uint32_t* bf_list;         // [n] queries left to the exhaustive search
     uint32_t* bf_count;        // their number
@@ -281,6 +294,7 @@ hipError_t launch_adam(const AdamArgs& a, bool vec, hipStream_t s);
 hipError_t launch_covis(const CovisArgs& a, hipStream_t s);
 hipError_t launch_prune(const PruneArgs& a, hipStream_t s);
 hipError_t launch_compact(const CompactArgs& a, hipStream_t s);
+hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
 hipError_t launch_seed_triangulate(const SeedArgs& a, hipStream_t s);
 hipError_t launch_seed_scale(const KnnArgs& a, hipStream_t s);
 

@@ -1,7 +1,7 @@
 // maintain.hip -- map maintenance: the optimiser step of the appendix's
 // optimisation settings with the anchor of Eq. (app-ema), the co-visibility
-// score of Eq. (iou), and the pruning rule of Sec. "Insertion, Lightweight
-// Merging, and Pruning".  All three are bound by memory traffic.
+// score of Eq. (iou), and the pruning and merging of Sec. "Insertion,
+// Lightweight Merging, and Pruning".  All are bound by memory traffic.
 //
 // Adam step (Kingma and Ba, Algorithm 1) over the five parameter planes,
 // each with its own learning rate, after clipping the global L2 norm of all
@@ -25,7 +25,19 @@
 // sum_k exp(2 log_scale_k) > sigma_max^2 (the trace of R diag(s^2) R^T) or
 // sigmoid(opacity_logit) < alpha_min, decided in double; the kept indices are
 // listed in order by a three-pass scan (block counts, one-block scan of the
-// counts, block-local ranks).
+// counts, block-local ranks).  The same scan lists the entries of a caller's
+// keep mask (after merging).
+//
+// Merging: the planes are copied to the output in 16-byte vectors
+// (k_merge_copy); then one thread per Gaussian (k_merge) reads its nearest
+// neighbour j and j's; for a mutual pair the thread of the lower index
+// decides for both (centre distance within radius times the smaller
+// geometric-mean scale, first three colour rows within colour_tol, in
+// double), writes both keep flags and, when they merge, the merged column:
+// visibility-weighted means of mean, colour rows and opacity (as sigmoid),
+// and of the two world covariances, split back by a cyclic Jacobi
+// eigen-decomposition (double) into a unit quaternion of the eigenvector
+// rotation and the log-scales.
 #include "kernels.h"
 
 namespace gsr {
@@ -217,6 +229,7 @@ hipError_t launch_covis(const CovisArgs& a, hipStream_t s)
 
 __device__ __forceinline__ bool prune_keep(const PruneArgs& a, int64_t i)
 {
+    if (a.mask) return a.mask[i] != 0;
     const double tr = exp(2.0 * (double)a.log_scale[i]) + exp(2.0 * (double)a.log_scale[a.n + i]) +
                       exp(2.0 * (double)a.log_scale[2 * a.n + i]);
     const double alpha = 1.0 / (1.0 + exp(-(double)a.opacity_logit[i]));
@@ -315,6 +328,224 @@ hipError_t launch_compact(const CompactArgs& a, hipStream_t s)
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_compact, dim3((unsigned)blocks, (unsigned)a.rows), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// merging: mutual nearest neighbours with overlapping footprints and similar
+// colours become one Gaussian (at the lower index) carrying the
+// visibility-weighted mean of mean, colour, opacity (as alpha) and world
+// covariance, the covariance split back into rotation and scales by a
+// cyclic Jacobi eigen-decomposition; all in double
+
+__device__ __forceinline__ void quat_rot(double w, double x, double y, double z, double (&R)[3][3])
+{
+    const double s = 1.0 / sqrt(w * w + x * x + y * y + z * z);
+    w *= s;
+    x *= s;
+    y *= s;
+    z *= s;
+    R[0][0] = 1 - 2 * (y * y + z * z);
+    R[0][1] = 2 * (x * y - w * z);
+    R[0][2] = 2 * (x * z + w * y);
+    R[1][0] = 2 * (x * y + w * z);
+    R[1][1] = 1 - 2 * (x * x + z * z);
+    R[1][2] = 2 * (y * z - w * x);
+    R[2][0] = 2 * (x * z - w * y);
+    R[2][1] = 2 * (y * z + w * x);
+    R[2][2] = 1 - 2 * (x * x + y * y);
+}
+
+// world covariance of Gaussian i of the input planes, weighted, added to S
+__device__ __forceinline__ void add_cov(const MergeArgs& a, int64_t i, double wgt, double (&S)[3][3])
+{
+    double R[3][3];
+    quat_rot(a.in[1][i], a.in[1][a.n + i], a.in[1][2 * a.n + i], a.in[1][3 * a.n + i], R);
+    double s2[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) s2[k] = exp(2.0 * (double)a.in[2][(int64_t)k * a.n + i]);
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            S[r][c] += wgt * (R[r][0] * s2[0] * R[c][0] + R[r][1] * s2[1] * R[c][1] + R[r][2] * s2[2] * R[c][2]);
+}
+
+// symmetric 3x3 eigen-decomposition S = V diag(lam) V^T by cyclic Jacobi
+// rotations (S is overwritten)
+__device__ __forceinline__ void eig3(double (&S)[3][3], double (&V)[3][3], double (&lam)[3])
+{
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) V[r][c] = r == c ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        const double off = S[0][1] * S[0][1] + S[0][2] * S[0][2] + S[1][2] * S[1][2];
+        const double on = S[0][0] * S[0][0] + S[1][1] * S[1][1] + S[2][2] * S[2][2];
+        if (!(off > 1e-32 * on)) break;
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+#pragma unroll
+            for (int q = p + 1; q < 3; ++q) {
+                if (S[p][q] == 0.0) continue;
+                const double th = (S[q][q] - S[p][p]) / (2.0 * S[p][q]);
+                const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+                // S <- J^T S J, V <- V J, J the rotation in the (p, q) plane
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const double skp = S[k][p], skq = S[k][q];
+                    S[k][p] = c * skp - s * skq;
+                    S[k][q] = s * skp + c * skq;
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const double spk = S[p][k], sqk = S[q][k];
+                    S[p][k] = c * spk - s * sqk;
+                    S[q][k] = s * spk + c * sqk;
+                }
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const double vkp = V[k][p], vkq = V[k][q];
+                    V[k][p] = c * vkp - s * vkq;
+                    V[k][q] = s * vkp + c * vkq;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) lam[k] = S[k][k];
+}
+
+// a unit quaternion (w, x, y, z) of the rotation matrix R (largest of the
+// four squared components first, for accuracy)
+__device__ __forceinline__ void rot_quat(const double (&R)[3][3], double (&q)[4])
+{
+    const double tr = R[0][0] + R[1][1] + R[2][2];
+    if (tr >= R[0][0] && tr >= R[1][1] && tr >= R[2][2]) {
+        const double s = 2.0 * sqrt(1.0 + tr);
+        q[0] = 0.25 * s;
+        q[1] = (R[2][1] - R[1][2]) / s;
+        q[2] = (R[0][2] - R[2][0]) / s;
+        q[3] = (R[1][0] - R[0][1]) / s;
+    } else if (R[0][0] >= R[1][1] && R[0][0] >= R[2][2]) {
+        const double s = 2.0 * sqrt(1.0 + R[0][0] - R[1][1] - R[2][2]);
+        q[0] = (R[2][1] - R[1][2]) / s;
+        q[1] = 0.25 * s;
+        q[2] = (R[0][1] + R[1][0]) / s;
+        q[3] = (R[0][2] + R[2][0]) / s;
+    } else if (R[1][1] >= R[2][2]) {
+        const double s = 2.0 * sqrt(1.0 + R[1][1] - R[0][0] - R[2][2]);
+        q[0] = (R[0][2] - R[2][0]) / s;
+        q[1] = (R[0][1] + R[1][0]) / s;
+        q[2] = 0.25 * s;
+        q[3] = (R[1][2] + R[2][1]) / s;
+    } else {
+        const double s = 2.0 * sqrt(1.0 + R[2][2] - R[0][0] - R[1][1]);
+        q[0] = (R[1][0] - R[0][1]) / s;
+        q[1] = (R[0][2] + R[2][0]) / s;
+        q[2] = (R[1][2] + R[2][1]) / s;
+        q[3] = 0.25 * s;
+    }
+}
+
+// whether the mutual pair (lo, hi) merges
+__device__ __forceinline__ bool merge_test(const MergeArgs& a, int64_t lo, int64_t hi)
+{
+    double d2 = 0.0, sl = 0.0, sh = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double e = (double)a.in[0][(int64_t)k * a.n + lo] - (double)a.in[0][(int64_t)k * a.n + hi];
+        d2 += e * e;
+        sl += (double)a.in[2][(int64_t)k * a.n + lo];
+        sh += (double)a.in[2][(int64_t)k * a.n + hi];
+    }
+    const double sbar = fmin(exp(sl / 3.0), exp(sh / 3.0));
+    if (!(sqrt(d2) <= a.radius * sbar)) return false;
+    double cd = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+        cd = fmax(cd, fabs((double)a.in[4][(int64_t)k * a.n + lo] - (double)a.in[4][(int64_t)k * a.n + hi]));
+    return cd <= a.colour_tol;
+}
+
+// out = in, plane blockIdx.y, in 16-byte vectors where both planes allow
+__global__ __launch_bounds__(256) void k_merge_copy(MergeArgs a)
+{
+    const int k = blockIdx.y;
+    const int rows = k == 0 || k == 2 ? 3 : k == 1 ? 4 : k == 3 ? 1 : a.colour_rows;
+    const float* src = a.in[k];
+    float* dst = a.out[k];
+    const int64_t len = (int64_t)rows * a.n;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int64_t done = 0;
+    if ((((uintptr_t)src | (uintptr_t)dst) & 15) == 0) {
+        const int64_t len4 = len / 4;
+        for (int64_t q = t; q < len4; q += stride)
+            reinterpret_cast<float4*>(dst)[q] = reinterpret_cast<const float4*>(src)[q];
+        done = len4 * 4;
+    }
+    for (int64_t q = done + t; q < len; q += stride) dst[q] = src[q];
+}
+
+// the merge proper, after k_merge_copy: keep flags, and the merged columns
+// of the survivors
+__global__ __launch_bounds__(256) void k_merge(MergeArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= a.n) return;
+    const int64_t j = a.nn[i];
+    const bool mutual = j >= 0 && j < a.n && j != i && (int64_t)a.nn[j] == i;
+    if (!mutual) {
+        a.keep[i] = 1;
+        return;
+    }
+    if (j < i) return;  // the lower index of the pair decides and writes both flags
+    const bool merged = merge_test(a, i, j);
+    a.keep[i] = 1;
+    a.keep[j] = merged ? 0 : 1;
+    if (!merged) return;
+    double wi = (double)a.v_vis[i], wj = (double)a.v_vis[j];
+    if (!(wi + wj > 0.0)) wi = wj = 1.0;
+    const double W = wi + wj;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+        a.out[0][(int64_t)r * a.n + i] =
+            (float)((wi * (double)a.in[0][(int64_t)r * a.n + i] + wj * (double)a.in[0][(int64_t)r * a.n + j]) / W);
+    for (int r = 0; r < a.colour_rows; ++r)
+        a.out[4][(int64_t)r * a.n + i] =
+            (float)((wi * (double)a.in[4][(int64_t)r * a.n + i] + wj * (double)a.in[4][(int64_t)r * a.n + j]) / W);
+    const double ai = 1.0 / (1.0 + exp(-(double)a.in[3][i])), aj = 1.0 / (1.0 + exp(-(double)a.in[3][j]));
+    const double al = (wi * ai + wj * aj) / W;
+    a.out[3][i] = (float)log(al / (1.0 - al));
+    double S[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
+    add_cov(a, i, wi / W, S);
+    add_cov(a, j, wj / W, S);
+    double V[3][3], lam[3];
+    eig3(S, V, lam);
+    const double det = V[0][0] * (V[1][1] * V[2][2] - V[1][2] * V[2][1]) -
+                       V[0][1] * (V[1][0] * V[2][2] - V[1][2] * V[2][0]) +
+                       V[0][2] * (V[1][0] * V[2][1] - V[1][1] * V[2][0]);
+    if (det < 0.0)
+#pragma unroll
+        for (int r = 0; r < 3; ++r) V[r][0] = -V[r][0];
+    double q[4];
+    rot_quat(V, q);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.out[1][(int64_t)k * a.n + i] = (float)q[k];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.out[2][(int64_t)k * a.n + i] = (float)(0.5 * log(fmax(lam[k], 1e-300)));
+}
+
+hipError_t launch_merge(const MergeArgs& a, hipStream_t s)
+{
+    if (a.n == 0) return hipSuccess;
+    int64_t blocks = ((int64_t)a.colour_rows * a.n / 4 + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_merge_copy, dim3((unsigned)blocks, 5), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_merge, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -546,8 +546,10 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_place(KnnArgs a)
     const int64_t i = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x;
     if (i >= a.n) return;
     if (!a.valid[i]) {
+        if (a.log_scale)
 #pragma unroll
-        for (int c = 0; c < 3; ++c) a.log_scale[(int64_t)c * a.n + i] = 0.0f;
+            for (int c = 0; c < 3; ++c) a.log_scale[(int64_t)c * a.n + i] = 0.0f;
+        if (a.nn_index) a.nn_index[i] = -1;
         return;
     }
     // the seed's position travels with its index, so that a query reads one
@@ -563,33 +565,58 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_place(KnnArgs a)
     }
 }
 
-__device__ __forceinline__ void knn_insert(double d, double (&best)[3], int& found)
+// (distance, index) pairs ordered by distance, then index: the 3 nearest
+// are unique even among equal distances
+__device__ __forceinline__ bool knn_before(double d, uint32_t j, double bd, uint32_t bj)
 {
+    return d < bd || (d == bd && j < bj);
+}
+
+__device__ __forceinline__ void knn_insert(double d, uint32_t idx, double (&best)[3], uint32_t (&bidx)[3],
+                                           int& found)
+{
+    int j;
     if (found < 3) {
-        int j = found++;
-        while (j > 0 && best[j - 1] > d) {
-            best[j] = best[j - 1];
-            --j;
-        }
-        best[j] = d;
-    } else if (d < best[2]) {
-        int j = 2;
-        while (j > 0 && best[j - 1] > d) {
-            best[j] = best[j - 1];
-            --j;
-        }
-        best[j] = d;
+        j = found++;
+    } else if (knn_before(d, idx, best[2], bidx[2])) {
+        j = 2;
+    } else {
+        return;
     }
+    while (j > 0 && knn_before(d, idx, best[j - 1], bidx[j - 1])) {
+        best[j] = best[j - 1];
+        bidx[j] = bidx[j - 1];
+        --j;
+    }
+    best[j] = d;
+    bidx[j] = idx;
 }
 
 __device__ __forceinline__ void knn_candidate(const float4& q, int64_t i, float px, float py, float pz,
-                                              double (&best)[3], int& found)
+                                              double (&best)[3], uint32_t (&bidx)[3], int& found)
 {
-    if ((int64_t)__float_as_uint(q.w) == i) return;
+    const uint32_t j = __float_as_uint(q.w);
+    if ((int64_t)j == i) return;
     const double ex = (double)q.x - (double)px;
     const double ey = (double)q.y - (double)py;
     const double ez = (double)q.z - (double)pz;
-    knn_insert(ex * ex + ey * ey + ez * ez, best, found);
+    knn_insert(ex * ex + ey * ey + ez * ez, j, best, bidx, found);
+}
+
+// the query's outputs: its log-scale (when asked for) and its nearest
+// other seed (when asked for; -1 for none)
+__device__ __forceinline__ void knn_write(const KnnArgs& a, int64_t i, const double (&best)[3],
+                                          const uint32_t (&bidx)[3], int found)
+{
+    if (a.log_scale) {
+        double mean_d = 0.0;
+        for (int k = 0; k < found; ++k) mean_d += sqrt(best[k]);
+        const double sc = found ? fmax(mean_d / (double)found, (double)a.floor_scale) : (double)a.floor_scale;
+        const float ls = (float)log(sc);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) a.log_scale[(int64_t)c * a.n + i] = ls;
+    }
+    if (a.nn_index) a.nn_index[i] = found ? (int32_t)bidx[0] : -1;
 }
 
 #define GSR_KNN_FINE_SHELLS 2
@@ -606,6 +633,7 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_knn(KnnArgs a)
     const int64_t i = a.sorted[t];
     const float px = a.mean[i], py = a.mean[a.n + i], pz = a.mean[2 * a.n + i];
     double best[3] = {INFINITY, INFINITY, INFINITY};  // squared distances, ascending
+    uint32_t bidx[3] = {0u, 0u, 0u};
     int found = 0;
     bool settled = false;
     uint32_t work = 0;  // candidates examined on this lane
@@ -647,7 +675,7 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_knn(KnnArgs a)
                         if (fine_coord(g, l, 0, q.x) != x || fine_coord(g, l, 1, q.y) != y ||
                             fine_coord(g, l, 2, q.z) != z)
                             continue;
-                        knn_candidate(q, i, px, py, pz, best, found);
+                        knn_candidate(q, i, px, py, pz, best, bidx, found);
                     }
                 }
             }
@@ -681,7 +709,7 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_knn(KnnArgs a)
                                 if (fine_coord(g, l, 0, q.x) != x || fine_coord(g, l, 1, q.y) != y ||
                                     fine_coord(g, l, 2, q.z) != z)
                                     continue;
-                                knn_candidate(q, i, px, py, pz, best, found);
+                                knn_candidate(q, i, px, py, pz, best, bidx, found);
                             }
                         }
                     }
@@ -714,7 +742,8 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_knn(KnnArgs a)
                         const uint32_t s0 = a.cell_start[cell], s1 = a.cell_start[cell + 1];
                         work += s1 - s0;
                         if (work > GSR_KNN_BUDGET) goto exhaustive;
-                        for (uint32_t s = s0; s < s1; ++s) knn_candidate(a.cell_pts[s], i, px, py, pz, best, found);
+                        for (uint32_t s = s0; s < s1; ++s)
+                            knn_candidate(a.cell_pts[s], i, px, py, pz, best, bidx, found);
                     }
                 }
             }
@@ -724,15 +753,8 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_knn(KnnArgs a)
         }
         if (!settled) goto exhaustive;
     }
-    {
-        double mean_d = 0.0;
-        for (int k = 0; k < found; ++k) mean_d += sqrt(best[k]);
-        const double sc = found ? fmax(mean_d / (double)found, (double)a.floor_scale) : (double)a.floor_scale;
-        const float ls = (float)log(sc);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) a.log_scale[(int64_t)c * a.n + i] = ls;
-        return;
-    }
+    knn_write(a, i, best, bidx, found);
+    return;
 exhaustive:
     a.bf_list[atomicAdd(a.bf_count, 1u)] = (uint32_t)i;
 }
@@ -743,27 +765,29 @@ exhaustive:
 __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_brute(KnnArgs a)
 {
     __shared__ double cand[GSR_SEED_THREADS * 3];
+    __shared__ uint32_t cand_i[GSR_SEED_THREADS * 3];
     const KnnGrid g = *a.grid;
     const uint32_t nq = *a.bf_count;
     for (uint32_t q = blockIdx.x; q < nq; q += gridDim.x) {
         const int64_t i = a.bf_list[q];
         const float px = a.mean[i], py = a.mean[a.n + i], pz = a.mean[2 * a.n + i];
         double best[3] = {INFINITY, INFINITY, INFINITY};
+        uint32_t bidx[3] = {0u, 0u, 0u};
         int found = 0;
         for (int64_t t = threadIdx.x; t < g.count; t += GSR_SEED_THREADS)
-            knn_candidate(a.cell_pts[t], i, px, py, pz, best, found);
-        for (int k = 0; k < 3; ++k) cand[threadIdx.x * 3 + k] = k < found ? best[k] : INFINITY;
+            knn_candidate(a.cell_pts[t], i, px, py, pz, best, bidx, found);
+        for (int k = 0; k < 3; ++k) {
+            cand[threadIdx.x * 3 + k] = k < found ? best[k] : INFINITY;
+            cand_i[threadIdx.x * 3 + k] = bidx[k];
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             double b[3] = {INFINITY, INFINITY, INFINITY};
+            uint32_t bi[3] = {0u, 0u, 0u};
             int f = 0;
             for (int k = 0; k < GSR_SEED_THREADS * 3; ++k)
-                if (cand[k] < INFINITY) knn_insert(cand[k], b, f);
-            double mean_d = 0.0;
-            for (int k = 0; k < f; ++k) mean_d += sqrt(b[k]);
-            const double sc = f ? fmax(mean_d / (double)f, (double)a.floor_scale) : (double)a.floor_scale;
-            const float ls = (float)log(sc);
-            for (int c = 0; c < 3; ++c) a.log_scale[(int64_t)c * a.n + i] = ls;
+                if (cand[k] < INFINITY) knn_insert(cand[k], cand_i[k], b, bi, f);
+            knn_write(a, i, b, bi, f);
         }
         __syncthreads();
     }

@@ -120,6 +120,9 @@ def _load():
         "gsr_prune_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
         "gsr_prune": (st, [ctypes.c_int64, P, P, P, P, P, P, P, P, P]),
         "gsr_compact": (st, [ctypes.c_int64, ctypes.c_int32, P, P, P, P, P]),
+        "gsr_nearest": (st, [ctypes.c_int64, P, P, P, ctypes.c_size_t, P, P]),
+        "gsr_merge": (st, [ctypes.c_int64, ctypes.c_int32, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P]),
+        "gsr_keep_list": (st, [ctypes.c_int64, P, P, P, P, P]),
         "gsr_device_clock_hz": (st, [P]),
         "gsr_plan_set_timing": (st, [P, ctypes.c_int32]),
         "gsr_plan_read_timing": (st, [P, ctypes.c_int32, P, P]),
@@ -140,7 +143,7 @@ EXPORTS = ("gsr_plan_create", "gsr_plan_destroy", "gsr_plan_workspace_bytes", "g
            "gsr_plan_set_timing", "gsr_plan_read_timing", "gsr_status_str", "gsr_last_error",
            "gsr_seed_triangulate", "gsr_seed_scale_workspace_bytes", "gsr_seed_scale",
            "gsr_adam_step", "gsr_covis", "gsr_prune_workspace_bytes", "gsr_prune", "gsr_compact",
-           "gsr_device_clock_hz")
+           "gsr_nearest", "gsr_merge", "gsr_keep_list", "gsr_device_clock_hz")
 
 # launch groups of gsr_plan_read_timing (gsr_timer)
 TIMERS = ("project", "bin_emit", "bin_sort", "bin_ranges", "raster_fwd", "loss_l1", "clear_grad2d",
@@ -375,3 +378,21 @@ def gsr_plan_read_timing(plan):
         check(_lib.gsr_plan_read_timing(plan, k, ctypes.byref(ms), ctypes.byref(cnt)), "gsr_plan_read_timing")
         out[name] = (ms.value, cnt.value)
     return out
+
+
+def gsr_nearest(n, mean, valid, workspace, nn_index, stream):
+    return check(_lib.gsr_nearest(int(n), _p(mean), _p(valid), _p(workspace),
+                                  workspace.numel() * workspace.element_size(), _p(nn_index),
+                                  ctypes.c_void_p(stream)), "gsr_nearest")
+
+
+def gsr_merge(n, colour_rows, params, v_vis, nn_index, radius, colour_tol, out, keep, stream):
+    pin, pout = _planes(params), _planes(out)
+    return check(_lib.gsr_merge(int(n), int(colour_rows), ctypes.byref(pin), _p(v_vis), _p(nn_index),
+                                ctypes.c_double(radius), ctypes.c_double(colour_tol), ctypes.byref(pout), _p(keep),
+                                ctypes.c_void_p(stream)), "gsr_merge")
+
+
+def gsr_keep_list(n, mask, keep_index, kept, workspace, stream):
+    return check(_lib.gsr_keep_list(int(n), _p(mask), _p(keep_index), _p(kept), _p(workspace),
+                                    ctypes.c_void_p(stream)), "gsr_keep_list")

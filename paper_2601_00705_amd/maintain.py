@@ -1,6 +1,7 @@
 """Map maintenance on the GPU: the optimiser step with the anchor of
-Eq. (app-ema), the co-visibility score of Eq. (iou), and pruning with
-compaction (the C ABI's gsr_adam_step, gsr_covis, gsr_prune, gsr_compact).
+Eq. (app-ema), the co-visibility score of Eq. (iou), pruning and merging
+with compaction (the C ABI's gsr_adam_step, gsr_covis, gsr_prune,
+gsr_compact, gsr_nearest, gsr_merge, gsr_keep_list).
 Argument marshalling only; every step runs in the library's kernels."""
 from __future__ import annotations
 
@@ -76,3 +77,43 @@ def compact(src, keep, kept):
     dst = torch.empty_like(src)
     lib.gsr_compact(n, rows, src, keep, kept, dst, _stream(src.device))
     return dst
+
+
+def nearest(mean, valid=None):
+    """Index of each Gaussian's nearest other one (-1 where none); mean
+    [3][n] device, valid [n] int32 (all valid by default)."""
+    n = int(mean.shape[1])
+    dev = mean.device
+    if valid is None:
+        valid = torch.ones(n, dtype=torch.int32, device=dev)
+    ws = torch.empty(max(lib.gsr_seed_scale_workspace_bytes(n), 8), dtype=torch.uint8, device=dev)
+    nn = torch.empty(n, dtype=torch.int32, device=dev)
+    lib.gsr_nearest(n, mean, valid, ws, nn, _stream(dev))
+    return nn
+
+
+def merge(params, v_vis, radius, colour_tol, nn=None):
+    """Merging of mutual nearest neighbours with overlapping footprints and
+    similar colours.  Returns (merged planes, keep mask [n] int32, nn):
+    columns with keep 0 were merged into their partner."""
+    n = int(params["opacity_logit"].shape[0])
+    colour_rows = int(params["colour"].numel() // max(n, 1))
+    dev = params["mean"].device
+    if nn is None:
+        nn = nearest(params["mean"])
+    out = {k: torch.empty_like(params[k]) for k in PLANES}
+    keep = torch.empty(n, dtype=torch.int32, device=dev)
+    lib.gsr_merge(n, colour_rows, params, v_vis, nn, radius, colour_tol, out, keep, _stream(dev))
+    return out, keep, nn
+
+
+def keep_list(mask):
+    """Ordered indices of the set entries of an int32 mask, and their count
+    [1] (device)."""
+    n = int(mask.shape[0])
+    dev = mask.device
+    ws = torch.empty(max(lib.gsr_prune_workspace_bytes(n), 4), dtype=torch.uint8, device=dev)
+    keep = torch.empty(n, dtype=torch.int32, device=dev)
+    kept = torch.empty(1, dtype=torch.int64, device=dev)
+    lib.gsr_keep_list(n, mask, keep, kept, ws, _stream(dev))
+    return keep, kept

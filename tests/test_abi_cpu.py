@@ -138,6 +138,35 @@ def test_maintenance_argument_errors():
     assert raw.gsr_compact(100, 3, ctypes.c_void_p(4096), fake, fake, ctypes.c_void_p(4096 + 400), None) == lib.EINVAL
 
 
+def test_merge_argument_errors():
+    """gsr_nearest, gsr_merge and gsr_keep_list reject bad arguments before
+    touching the device (the pointers are never read)."""
+    from paper_2601_00705_amd import lib
+    raw = lib.raw()
+    fake = ctypes.c_void_p(4096)
+    need = raw.gsr_seed_scale_workspace_bytes(1000)
+    assert raw.gsr_nearest(1000, fake, fake, fake, need - 1, fake, None) == lib.EINVAL
+    assert raw.gsr_nearest(1000, fake, fake, fake, need, None, None) == lib.EINVAL
+    assert raw.gsr_nearest(-1, fake, fake, fake, need, fake, None) == lib.EINVAL
+    assert raw.gsr_nearest(0, None, None, None, 0, None, None) == 0
+    pin = lib.Planes(4096, 8192, 12288, 16384, 20480)
+    pout = lib.Planes(40960, 81920, 122880, 163840, 204800)
+    alias = lib.Planes(40960, 81920, 12288, 163840, 204800)
+    hole = lib.Planes(40960, 0, 122880, 163840, 204800)
+    good = (ctypes.byref(pin), fake, fake, 1.0, 0.1)
+    assert raw.gsr_merge(10, 3, *good, ctypes.byref(alias), fake, None) == lib.EINVAL
+    assert raw.gsr_merge(10, 3, *good, ctypes.byref(hole), fake, None) == lib.EINVAL
+    assert raw.gsr_merge(10, 2, *good, ctypes.byref(pout), fake, None) == lib.EINVAL
+    assert raw.gsr_merge(10, 49, *good, ctypes.byref(pout), fake, None) == lib.EINVAL
+    for r, c in ((-1.0, 0.1), (float("nan"), 0.1), (1.0, float("inf")), (1.0, -0.5)):
+        assert raw.gsr_merge(10, 3, ctypes.byref(pin), fake, fake, r, c, ctypes.byref(pout), fake,
+                             None) == lib.EINVAL
+    assert raw.gsr_merge(10, 3, *good, ctypes.byref(pout), None, None) == lib.EINVAL
+    assert raw.gsr_merge(0, 3, *good, ctypes.byref(pout), fake, None) == 0
+    assert raw.gsr_keep_list(0, fake, fake, fake, fake, None) == lib.EINVAL
+    assert raw.gsr_keep_list(10, None, fake, fake, fake, None) == lib.EINVAL
+
+
 def test_track_loss_argument_errors():
     """gsr_loss_track rejects non-positive or non-finite thresholds and null
     buffers before touching the device (the pointers are never read)."""
