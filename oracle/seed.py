@@ -34,10 +34,23 @@ Readings where the paper is silent:
   - the median of an even number of samples is the mean of the two middle
     ones;
   - opacity_logit = log(alpha / (1 - alpha));
-  - scale (the workload's stated recipe, standing in for the plane-fit
-    anisotropic initialisation): isotropic, the mean distance to the 3
-    nearest other kept seeds (fewer if fewer exist; 0 neighbours gives the
-    floor); log_scale = log(max(that, floor)) on all three axes.
+  - scale (the workload's stated recipe): isotropic, the mean distance to
+    the 3 nearest other kept seeds (fewer if fewer exist; 0 neighbours gives
+    the floor); log_scale = log(max(that, floor)) on all three axes;
+  - the anisotropic initialisation of Eq. (app-sigma-init), frame_init:
+    the plane is fitted to the kept seeds within `radius` of the seed (the
+    seed included) by the eigen-decomposition of their scatter about their
+    mean: the normal v is the eigenvector of the smallest eigenvalue, t1
+    that of the largest, t2 = v x t1; with fewer than three such seeds the
+    normal is the reference viewing ray (X - c) / |X - c|.  The tangential
+    scale is the radius of the circle of equal area to the one-pixel
+    footprint back-projected through the reference projection's Jacobian J
+    (2 x 3, world to pixels, at X): s_perp = det(J J^T)^(-1/4).  The axial
+    scale is s_par = c_par s_perp max(1, err) / max(sin angle, 1e-6) (err
+    the kept hypothesis' reprojection error in pixels, angle its baseline
+    angle, c_par the calibration): the lateral uncertainty of one pixel, or
+    of the residual when larger, stretched by the inverse parallax.  Both
+    scales are floored like the isotropic one.
 """
 from __future__ import annotations
 
@@ -168,3 +181,58 @@ def knn_scale(mean, valid, k=3, floor=1e-4):
     d = np.asarray(d).reshape(idx.size, m + 1)
     out[idx] = np.log(np.maximum(d[:, 1:].mean(axis=1), floor))
     return out
+
+
+def projection_jacobian(P, X):
+    """2 x 3 Jacobian of the pixel position under P [3][4] with respect to
+    the world point X [3]."""
+    Xh = np.append(np.asarray(X, np.float64), 1.0)
+    w = P[2] @ Xh
+    u, v = (P[0] @ Xh) / w, (P[1] @ Xh) / w
+    return np.stack([(P[0, :3] - u * P[2, :3]) / w, (P[1, :3] - v * P[2, :3]) / w])
+
+
+def _completion(v):
+    """A unit vector perpendicular to the unit vector v."""
+    a = np.zeros(3)
+    a[np.argmin(np.abs(v))] = 1.0
+    t = np.cross(v, a)
+    return t / np.linalg.norm(t)
+
+
+def frame_init(mean, valid, P_ref, centre_ref, err, angle, radius, c_par=1.0, floor=1e-4):
+    """Eq. (app-sigma-init) for every kept seed: returns (Sigma [n][3][3],
+    frame [n][3][3] with columns (t1, t2, v), log_scale [3][n]) in float64;
+    zeros for invalid seeds.  mean [3][n], valid [n], err and angle [n] as
+    written by the triangulation; P_ref [3][4] and centre_ref [3] of the
+    reference keyframe."""
+    from scipy.spatial import cKDTree
+    X = np.asarray(mean, np.float64)
+    n = X.shape[1]
+    keep = np.asarray(valid) != 0
+    idx = np.nonzero(keep)[0]
+    pts = X[:, idx].T
+    tree = cKDTree(pts) if idx.size else None
+    P = np.asarray(P_ref, np.float64)
+    Sigma = np.zeros((n, 3, 3))
+    frame = np.zeros((n, 3, 3))
+    ls = np.zeros((3, n))
+    for k, i in enumerate(idx):
+        nb = tree.query_ball_point(pts[k], radius)
+        if len(nb) >= 3:
+            Q = pts[nb]
+            D = Q - Q.mean(axis=0)
+            lam, V = np.linalg.eigh(D.T @ D)
+            v, t1 = V[:, 0], V[:, 2]
+        else:
+            v = X[:, i] - np.asarray(centre_ref, np.float64)
+            v = v / np.linalg.norm(v)
+            t1 = _completion(v)
+        U = np.stack([t1, np.cross(v, t1), v], axis=1)
+        J = projection_jacobian(P, X[:, i])
+        s_perp = max(np.linalg.det(J @ J.T) ** -0.25, floor)
+        s_par = max(c_par * s_perp * max(1.0, float(err[i])) / max(np.sin(float(angle[i])), 1e-6), floor)
+        Sigma[i] = U @ np.diag([s_perp ** 2, s_perp ** 2, s_par ** 2]) @ U.T
+        frame[i] = U
+        ls[:, i] = np.log([s_perp, s_perp, s_par])
+    return Sigma, frame, ls
