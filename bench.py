@@ -334,14 +334,27 @@ def seeding_measurement(torch, reps, log):
         t_knn += ev[1].elapsed_time(ev[2])
     t_tri /= reps
     t_knn /= reps
+    # the anisotropic initialisation (plane fit within 1 cm, about 60 seeds)
+    diag = seeding.triangulate(views, cfg, dev["xr"], dev["xn"], dev["kappa"], diagnostics=True)
+    fr = dict(P_ref=d["Ps"][0].reshape(-1), centre_ref=d["centres"][0], radius=0.01)
+    quat, fls = sc.frame(diag["mean"], diag["valid"], diag["err"], diag["angle"], **fr)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        sc.frame(diag["mean"], diag["valid"], diag["err"], diag["angle"], quat=quat, log_scale=fls, **fr)
+    ev[1].record()
+    torch.cuda.synchronize()
+    t_frame = ev[0].elapsed_time(ev[1]) / reps
     flops = FLOPS_SEED_PER_HYPOTHESIS * K * n
     res = {"points": n, "neighbours": K, "kept": int(out["valid"].sum()), "triangulate_ms": t_tri,
-           "scale_ms": t_knn, "points_per_s": n / ((t_tri + t_knn) * 1e-3),
+           "scale_ms": t_knn, "frame_ms": t_frame, "frame_radius": fr["radius"],
+           "points_per_s": n / ((t_tri + t_knn) * 1e-3),
            "roofline": {"bound": "alu", "kernel": "seed_triangulate",
                         "achieved": flops / (t_tri * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
                         "unit": "TFLOP/s (FP64)", "work": f"{FLOPS_SEED_PER_HYPOTHESIS} x {K} x {n}"}}
     res["roofline"]["frac"] = res["roofline"]["achieved"] / FP64_PEAK_TFLOPS
     log(f"seeding: {n} px x {K} neighbours: triangulate {t_tri:.3f} ms, scale {t_knn:.3f} ms, "
+        f"anisotropic frame {t_frame:.3f} ms, "
         f"{res['kept']} kept; {res['roofline']['achieved']:.1f} TFLOP/s FP64 ({res['roofline']['frac']:.2f})")
     return res
 

@@ -24,11 +24,11 @@
  *     the optimiser step of the appendix's settings with the anchor of Eq.
  *     (app-ema), the co-visibility score of Eq. (iou), and the pruning rule
  *     and merging of Sec. "Insertion, Lightweight Merging, and Pruning".
- *   - gsr_seed_triangulate, gsr_seed_scale: the one-shot Gaussian seeding of
- *     Sec. "Dense Feature Matching" (Eq. (conf), two-view linear
- *     triangulation) and the appendix's initialisation (Eq.
- *     (app-alpha-init), colour median), producing Gaussians in the layout
- *     gsr_project reads.
+ *   - gsr_seed_triangulate, gsr_seed_scale, gsr_seed_frame: the one-shot
+ *     Gaussian seeding of Sec. "Dense Feature Matching" (Eq. (conf),
+ *     two-view linear triangulation) and the appendix's initialisation
+ *     (Eqs. (app-sigma-init), (app-alpha-init), colour median), producing
+ *     Gaussians in the layout gsr_project reads.
  *   - gsr_render_bwd: gradients for colour, opacity, mean, covariance
  *     parameters (the differentiability statement after Eq. (alpha)) and for
  *     the pose twist of Eq. (leftupdate), via Eqs. (muCjac), (muIjac),
@@ -319,6 +319,35 @@ gsr_status gsr_seed_triangulate(int64_t n, int32_t n_neighbours, const gsr_seed_
 size_t gsr_seed_scale_workspace_bytes(int64_t n);
 gsr_status gsr_seed_scale(int64_t n, const float *mean, const int32_t *valid, float floor_scale, void *workspace,
                           size_t workspace_bytes, float *log_scale, void *stream);
+
+/* Anisotropic initial covariance of the valid seeds, Eq. (app-sigma-init):
+ * Sigma = U diag(s_perp^2, s_perp^2, s_par^2) U^T with U = [t1 t2 v].
+ * Readings where the paper is silent: the plane is fitted to the valid
+ * seeds within `radius` of the seed (itself included; distances of the FP32
+ * positions compared in double) by the eigen-decomposition of their scatter
+ * about their mean, v the eigenvector of the smallest eigenvalue (the
+ * normal), t1 that of the largest, t2 = v x t1; fewer than three seeds in
+ * the radius: v = the unit ray from centre_ref to the seed, t1 any unit
+ * perpendicular.  s_perp = det(J J^T)^(-1/4), J the 2 x 3 Jacobian of the
+ * pixel position under P_ref with respect to the world point (the radius of
+ * the circle of equal area to the back-projected one-pixel footprint);
+ * s_par = c_par s_perp max(1, err) / max(sin(angle), 1e-6); both at least
+ * floor_scale (s_par from the floored s_perp).  FP64 arithmetic.
+ * Inputs: mean [3][n], valid [n], err [n] and angle [n] as written by
+ * gsr_seed_triangulate (device); P_ref (3 x 4, row-major) and centre_ref [3]
+ * of the reference keyframe (host).  Outputs (device): quat [4][n], the
+ * unit quaternion (w, x, y, z) of U, and log_scale [3][n] = (log s_perp,
+ * log s_perp, log s_par); the identity and zeros for invalid seeds.
+ * workspace: gsr_seed_scale_workspace_bytes(n) bytes of device memory.
+ * The search hashes the seeds by cells of `radius` and visits the 3 x 3 x 3
+ * cells around each seed, so its cost grows with the number of seeds within
+ * about two radii.  Bad arguments (n out of range, a non-positive or non-finite
+ * radius, c_par or floor_scale, a non-finite P_ref or centre_ref, a null
+ * buffer, a small workspace): GSR_EINVAL, nothing enqueued. */
+gsr_status gsr_seed_frame(int64_t n, const float *mean, const int32_t *valid, const float *err, const float *angle,
+                          const double *P_ref, const double *centre_ref, double radius, double c_par,
+                          float floor_scale, void *workspace, size_t workspace_bytes, float *quat, float *log_scale,
+                          void *stream);
 
 /* Nearest other valid Gaussian of each valid Gaussian (Euclidean distance of
  * the centres; ties go to the lower index), the neighbour search behind the

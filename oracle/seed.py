@@ -200,12 +200,13 @@ def _completion(v):
     return t / np.linalg.norm(t)
 
 
-def frame_init(mean, valid, P_ref, centre_ref, err, angle, radius, c_par=1.0, floor=1e-4):
-    """Eq. (app-sigma-init) for every kept seed: returns (Sigma [n][3][3],
-    frame [n][3][3] with columns (t1, t2, v), log_scale [3][n]) in float64;
-    zeros for invalid seeds.  mean [3][n], valid [n], err and angle [n] as
-    written by the triangulation; P_ref [3][4] and centre_ref [3] of the
-    reference keyframe."""
+def frame_init(mean, valid, P_ref, centre_ref, err, angle, radius, c_par=1.0, floor=1e-4, only=None):
+    """Eq. (app-sigma-init) for every kept seed (or the kept seeds among the
+    indices `only`): returns (Sigma [n][3][3], frame [n][3][3] with columns
+    (t1, t2, v), log_scale [3][n]) in float64; zeros for the others.
+    mean [3][n], valid [n], err and angle [n] as written by the
+    triangulation; P_ref [3][4] and centre_ref [3] of the reference
+    keyframe."""
     from scipy.spatial import cKDTree
     X = np.asarray(mean, np.float64)
     n = X.shape[1]
@@ -217,7 +218,10 @@ def frame_init(mean, valid, P_ref, centre_ref, err, angle, radius, c_par=1.0, fl
     Sigma = np.zeros((n, 3, 3))
     frame = np.zeros((n, 3, 3))
     ls = np.zeros((3, n))
+    ask = np.ones(n, bool) if only is None else np.isin(np.arange(n), only)
     for k, i in enumerate(idx):
+        if not ask[i]:
+            continue
         nb = tree.query_ball_point(pts[k], radius)
         if len(nb) >= 3:
             Q = pts[nb]

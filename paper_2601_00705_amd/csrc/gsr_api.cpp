@@ -832,11 +832,9 @@ extern "C" size_t gsr_seed_scale_workspace_bytes(int64_t n)
     return knn_layout(n).total;
 }
 
-static gsr_status knn_run(int64_t n, const float* mean, const int32_t* valid, float floor_scale, void* workspace,
-                          size_t workspace_bytes, float* log_scale, int32_t* nn_index, void* stream, const char* who)
+static KnnArgs knn_args(int64_t n, const float* mean, const int32_t* valid, float floor_scale, void* workspace,
+                        const KnnLayout& L)
 {
-    const KnnLayout L = knn_layout(n);
-    if (workspace_bytes < L.total) return fail(GSR_EINVAL, "workspace too small");
     char* ws = (char*)workspace;
     KnnArgs a{};
     a.n = n;
@@ -862,10 +860,54 @@ static gsr_status knn_run(int64_t n, const float* mean, const int32_t* valid, fl
     a.scan_tot = (uint32_t*)(ws + L.scan_tot);
     a.bf_list = (uint32_t*)(ws + L.bf_list);
     a.bf_count = (uint32_t*)(ws + L.bf_count);
+    return a;
+}
+
+static gsr_status knn_run(int64_t n, const float* mean, const int32_t* valid, float floor_scale, void* workspace,
+                          size_t workspace_bytes, float* log_scale, int32_t* nn_index, void* stream, const char* who)
+{
+    const KnnLayout L = knn_layout(n);
+    if (workspace_bytes < L.total) return fail(GSR_EINVAL, "workspace too small");
+    KnnArgs a = knn_args(n, mean, valid, floor_scale, workspace, L);
     a.log_scale = log_scale;
     a.nn_index = nn_index;
     hipError_t e = launch_seed_scale(a, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, who);
+}
+
+extern "C" gsr_status gsr_seed_frame(int64_t n, const float* mean, const int32_t* valid, const float* err,
+                                     const float* angle, const double* P_ref, const double* centre_ref, double radius,
+                                     double c_par, float floor_scale, void* workspace, size_t workspace_bytes,
+                                     float* quat, float* log_scale, void* stream)
+{
+    g_err.clear();
+    if (n < 0 || n >= (1ll << 31)) return fail(GSR_EINVAL, "n out of range");
+    if (!P_ref || !centre_ref) return fail(GSR_EINVAL, "null reference view");
+    if (!(radius > 0.0) || !std::isfinite(radius)) return fail(GSR_EINVAL, "radius must be positive and finite");
+    if (!(c_par > 0.0) || !std::isfinite(c_par)) return fail(GSR_EINVAL, "c_par must be positive and finite");
+    if (!(floor_scale > 0.0f) || !std::isfinite(floor_scale)) return fail(GSR_EINVAL, "floor_scale must be positive");
+    for (int k = 0; k < 12; ++k)
+        if (!std::isfinite(P_ref[k])) return fail(GSR_EINVAL, "non-finite projection");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(centre_ref[k])) return fail(GSR_EINVAL, "non-finite centre");
+    if (n == 0) return GSR_OK;
+    if (!mean || !valid || !err || !angle || !quat || !log_scale || !workspace) return fail(GSR_EINVAL, "null buffer");
+    const KnnLayout L = knn_layout(n);
+    if (workspace_bytes < L.total) return fail(GSR_EINVAL, "workspace too small");
+    KnnArgs a = knn_args(n, mean, valid, floor_scale, workspace, L);
+    a.fine_levels = 1;  // only the level of cells of the radius
+    FrameArgs f{};
+    for (int k = 0; k < 12; ++k) f.P[k] = P_ref[k];
+    for (int k = 0; k < 3; ++k) f.centre[k] = centre_ref[k];
+    f.radius = radius;
+    f.c_par = c_par;
+    f.floor_scale = floor_scale;
+    f.err = err;
+    f.angle = angle;
+    f.quat = quat;
+    f.log_scale = log_scale;
+    hipError_t e = launch_seed_frame(a, f, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_seed_frame");
 }
 
 extern "C" gsr_status gsr_seed_scale(int64_t n, const float* mean, const int32_t* valid, float floor_scale,

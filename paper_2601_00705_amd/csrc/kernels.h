@@ -262,6 +262,20 @@ struct KnnArgs {
     uint32_t* bf_list;         // [n] queries left to the exhaustive search
     uint32_t* bf_count;        // their number
     float* log_scale;          // [3][n]
+    int32_t fine_levels;       // fine levels built (0: all GSR_KNN_LEVELS)
+};
+
+// anisotropic initialisation of the seeds (after the coarse grid of KnnArgs)
+struct FrameArgs {
+    double P[12];              // reference projection, row-major 3 x 4
+    double centre[3];          // reference camera centre
+    double radius;             // plane-fit neighbourhood
+    double c_par;              // calibration of the axial scale
+    double floor_scale;
+    const float* err;          // [n] reprojection error of the kept hypothesis (px)
+    const float* angle;        // [n] its baseline angle (rad)
+    float* quat;               // [4][n] out
+    float* log_scale;          // [3][n] out
 };
 
 #define GSR_TRACK_BLOCKS 256        // blocks per view of the tracking-loss kernels
@@ -297,5 +311,6 @@ hipError_t launch_compact(const CompactArgs& a, hipStream_t s);
 hipError_t launch_merge(const MergeArgs& a, hipStream_t s);
 hipError_t launch_seed_triangulate(const SeedArgs& a, hipStream_t s);
 hipError_t launch_seed_scale(const KnnArgs& a, hipStream_t s);
+hipError_t launch_seed_frame(const KnnArgs& a, const FrameArgs& f, hipStream_t s);
 
 }  // namespace gsr

@@ -38,6 +38,7 @@
 //   much denser regions), are listed and each is answered exactly by a whole
 //   block scanning every valid seed.
 #include "kernels.h"
+#include "mat3.h"
 
 namespace gsr {
 
@@ -451,7 +452,8 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_fcount(KnnArgs a)
     if (!g.fine || i >= a.n || !a.valid[i]) return;
     const int64_t T1 = ((int64_t)1 << a.table_bits) + 1;
     const uint32_t mask = ((uint32_t)1 << a.table_bits) - 1u;
-    for (int l = 0; l < GSR_KNN_LEVELS; ++l) {
+    const int levels = a.fine_levels > 0 ? a.fine_levels : GSR_KNN_LEVELS;
+    for (int l = 0; l < levels; ++l) {
         const uint32_t b = fine_bucket(fine_coord(g, l, 0, a.mean[i]), fine_coord(g, l, 1, a.mean[a.n + i]),
                                        fine_coord(g, l, 2, a.mean[2 * a.n + i]), mask);
         a.fine_of[l * a.n + i] = b;
@@ -560,7 +562,8 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_place(KnnArgs a)
     a.cell_pts[pos] = q;
     if (g.fine) {
         const int64_t T1 = ((int64_t)1 << a.table_bits) + 1;
-        for (int l = 0; l < GSR_KNN_LEVELS; ++l)
+        const int levels = a.fine_levels > 0 ? a.fine_levels : GSR_KNN_LEVELS;
+        for (int l = 0; l < levels; ++l)
             a.fine_pts[l * a.n + a.fine_start[l * T1 + a.fine_of[l * a.n + i]] + a.fine_rank[l * a.n + i]] = q;
     }
 }
@@ -791,6 +794,191 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_brute(KnnArgs a)
         }
         __syncthreads();
     }
+}
+
+// ---- anisotropic initialisation, Eq. (app-sigma-init) ----------------------
+// One thread per seed.  The seeds are hashed by cells of exactly `radius`
+// (the first level of the fine grid, unbounded), so the seeds within the
+// radius lie in the 3 x 3 x 3 cells around the seed's own; a candidate counts
+// only in its own cell, so buckets shared by two of those cells count once.
+// Their first and second moments about the seed (double) give
+// the scatter about their mean; its eigenvector of the smallest eigenvalue
+// is the plane normal v, that of the largest t1, and t2 = v x t1 (with fewer
+// than three seeds: v the reference viewing ray, t1 any perpendicular).
+// s_perp = det(J J^T)^(-1/4), J the reference projection's 2 x 3 Jacobian
+// at the seed (the equal-area radius of the back-projected one-pixel
+// footprint); s_par = c_par s_perp max(1, err) / max(sin angle, 1e-6); both
+// floored.  Output: the unit quaternion of [t1 t2 v] and the log-scales
+// (s_perp, s_perp, s_par).
+
+// the frame's hash grid: fine cells of exactly the radius
+__global__ void k_seed_frame_grid(KnnArgs a, double radius)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    KnnGrid g = *a.grid;
+    if (g.count > 0) {
+        g.fine = 1;
+        g.h1 = radius;
+        g.inv_h1 = 1.0 / radius;
+    }
+    *a.grid = g;
+}
+
+__global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_frame(KnnArgs a, FrameArgs f)
+{
+    const int64_t t = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x;
+    const int64_t n = a.n;
+    if (t < n && !a.valid[t]) {
+        f.quat[t] = 1.0f;
+#pragma unroll
+        for (int k = 1; k < 4; ++k) f.quat[k * n + t] = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) f.log_scale[k * n + t] = 0.0f;
+    }
+    // thread t takes the t-th valid seed in cell order: the lanes of a wave
+    // read the same buckets and have neighbourhoods of similar size
+    const KnnGrid g = *a.grid;
+    if (t >= g.count) return;
+    const float4 self = a.fine_pts[t];
+    const int64_t i = (int64_t)__float_as_uint(self.w);
+    const float p[3] = {self.x, self.y, self.z};
+    const double r2 = f.radius * f.radius;
+    const uint32_t mask = ((uint32_t)1 << a.table_bits) - 1u;
+    int c0[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) c0[c] = fine_coord(g, 0, c, p[c]);
+    double cnt = 0.0, m1[3] = {0.0, 0.0, 0.0}, m2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) {
+                const int cx = c0[0] + dx, cy = c0[1] + dy, cz = c0[2] + dz;
+                const uint32_t b = fine_bucket(cx, cy, cz, mask);
+                const uint32_t e = a.fine_start[b + 1];
+                for (uint32_t k = a.fine_start[b]; k < e; ++k) {
+                    const float4 q = a.fine_pts[k];
+                    if (fine_coord(g, 0, 0, q.x) != cx || fine_coord(g, 0, 1, q.y) != cy ||
+                        fine_coord(g, 0, 2, q.z) != cz)
+                        continue;
+                    const double ex = (double)q.x - (double)p[0];
+                    const double ey = (double)q.y - (double)p[1];
+                    const double ez = (double)q.z - (double)p[2];
+                    if (ex * ex + ey * ey + ez * ez <= r2) {
+                        cnt += 1.0;
+                        m1[0] += ex;
+                        m1[1] += ey;
+                        m1[2] += ez;
+                        m2[0] += ex * ex;
+                        m2[1] += ex * ey;
+                        m2[2] += ex * ez;
+                        m2[3] += ey * ey;
+                        m2[4] += ey * ez;
+                        m2[5] += ez * ez;
+                    }
+                }
+            }
+    double v[3], t1[3];
+    if (cnt >= 3.0) {
+        const double ic = 1.0 / cnt;
+        double S[3][3], V[3][3], lam[3];
+        S[0][0] = m2[0] - m1[0] * m1[0] * ic;
+        S[0][1] = S[1][0] = m2[1] - m1[0] * m1[1] * ic;
+        S[0][2] = S[2][0] = m2[2] - m1[0] * m1[2] * ic;
+        S[1][1] = m2[3] - m1[1] * m1[1] * ic;
+        S[1][2] = S[2][1] = m2[4] - m1[1] * m1[2] * ic;
+        S[2][2] = m2[5] - m1[2] * m1[2] * ic;
+        eig3(S, V, lam);
+        int kmin = 0, kmax = 1;
+        if (lam[1] < lam[kmin]) kmin = 1;
+        if (lam[2] < lam[kmin]) kmin = 2;
+        kmax = kmin == 0 ? 1 : 0;
+        for (int k = 0; k < 3; ++k)
+            if (k != kmin && lam[k] > lam[kmax]) kmax = k;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v[c] = V[c][kmin];
+            t1[c] = V[c][kmax];
+        }
+    } else {
+        double nv = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v[c] = (double)p[c] - f.centre[c];
+            nv += v[c] * v[c];
+        }
+        nv = 1.0 / sqrt(nv);
+        int am = 0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            v[c] *= nv;
+            if (fabs(v[c]) < fabs(v[am])) am = c;
+        }
+        // t1 = v x e_am, normalised
+        double e[3] = {0.0, 0.0, 0.0};
+        e[am] = 1.0;
+        t1[0] = v[1] * e[2] - v[2] * e[1];
+        t1[1] = v[2] * e[0] - v[0] * e[2];
+        t1[2] = v[0] * e[1] - v[1] * e[0];
+        const double nt = 1.0 / sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) t1[c] *= nt;
+    }
+    const double t2[3] = {v[1] * t1[2] - v[2] * t1[1], v[2] * t1[0] - v[0] * t1[2], v[0] * t1[1] - v[1] * t1[0]};
+    double U[3][3], q[4];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        U[c][0] = t1[c];
+        U[c][1] = t2[c];
+        U[c][2] = v[c];
+    }
+    rot_quat(U, q);
+    // tangential scale from the reference projection's Jacobian
+    const double X[3] = {(double)p[0], (double)p[1], (double)p[2]};
+    const double* P = f.P;
+    const double w = P[8] * X[0] + P[9] * X[1] + P[10] * X[2] + P[11];
+    const double u = (P[0] * X[0] + P[1] * X[1] + P[2] * X[2] + P[3]) / w;
+    const double vv = (P[4] * X[0] + P[5] * X[1] + P[6] * X[2] + P[7]) / w;
+    double j1[3], j2[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        j1[c] = (P[c] - u * P[8 + c]) / w;
+        j2[c] = (P[4 + c] - vv * P[8 + c]) / w;
+    }
+    const double A = j1[0] * j1[0] + j1[1] * j1[1] + j1[2] * j1[2];
+    const double B = j1[0] * j2[0] + j1[1] * j2[1] + j1[2] * j2[2];
+    const double D = j2[0] * j2[0] + j2[1] * j2[1] + j2[2] * j2[2];
+    const double s_perp = fmax(pow(A * D - B * B, -0.25), f.floor_scale);
+    const double s_par =
+        fmax(f.c_par * s_perp * fmax(1.0, (double)f.err[i]) / fmax(sin((double)f.angle[i]), 1e-6), f.floor_scale);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) f.quat[k * n + i] = (float)q[k];
+    f.log_scale[i] = (float)log(s_perp);
+    f.log_scale[n + i] = (float)log(s_perp);
+    f.log_scale[2 * n + i] = (float)log(s_par);
+}
+
+hipError_t launch_seed_frame(const KnnArgs& a, const FrameArgs& f, hipStream_t s)
+{
+    if (a.n == 0 || a.fine_levels != 1) return a.n == 0 ? hipSuccess : hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)((a.n + GSR_SEED_THREADS - 1) / GSR_SEED_THREADS);
+    const unsigned coarse_scan = (unsigned)((a.max_cells + 1 + 1023) / 1024);
+    const unsigned fine_scan = (unsigned)((((int64_t)1 << a.table_bits) + 1 + 1023) / 1024);
+    // the grid build of the nearest-neighbour search, with the fine levels
+    // set to cells of the radius instead of the occupancy rule
+    hipLaunchKernelGGL(k_seed_bbox, dim3(GSR_KNN_BLOCKS), dim3(GSR_SEED_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_seed_grid, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_seed_zero, dim3(1024), dim3(GSR_SEED_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_seed_count, dim3(blocks), dim3(GSR_SEED_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_seed_frame_grid, dim3(1), dim3(64), 0, s, a, f.radius);
+    hipLaunchKernelGGL(k_seed_fcount, dim3(blocks), dim3(GSR_SEED_THREADS), 0, s, a);
+    for (int which = 0; which <= 1; ++which) {
+        const unsigned nb = which == 0 ? coarse_scan : fine_scan;
+        hipLaunchKernelGGL(k_scan_local, dim3(nb), dim3(1024), 0, s, a, which);
+        hipLaunchKernelGGL(k_scan_totals, dim3(1), dim3(1024), 0, s, a, which);
+        hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(1024), 0, s, a, which);
+    }
+    hipLaunchKernelGGL(k_seed_place, dim3(blocks), dim3(GSR_SEED_THREADS), 0, s, a);
+    hipLaunchKernelGGL(k_seed_frame, dim3(blocks), dim3(GSR_SEED_THREADS), 0, s, a, f);
+    return hipGetLastError();
 }
 
 hipError_t launch_seed_scale(const KnnArgs& a, hipStream_t s)

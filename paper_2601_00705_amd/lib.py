@@ -120,6 +120,8 @@ def _load():
         "gsr_prune_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
         "gsr_prune": (st, [ctypes.c_int64, P, P, P, P, P, P, P, P, P]),
         "gsr_compact": (st, [ctypes.c_int64, ctypes.c_int32, P, P, P, P, P]),
+        "gsr_seed_frame": (st, [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_float,
+                                P, ctypes.c_size_t, P, P, P]),
         "gsr_nearest": (st, [ctypes.c_int64, P, P, P, ctypes.c_size_t, P, P]),
         "gsr_merge": (st, [ctypes.c_int64, ctypes.c_int32, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P]),
         "gsr_keep_list": (st, [ctypes.c_int64, P, P, P, P, P]),
@@ -143,7 +145,7 @@ EXPORTS = ("gsr_plan_create", "gsr_plan_destroy", "gsr_plan_workspace_bytes", "g
            "gsr_plan_set_timing", "gsr_plan_read_timing", "gsr_status_str", "gsr_last_error",
            "gsr_seed_triangulate", "gsr_seed_scale_workspace_bytes", "gsr_seed_scale",
            "gsr_adam_step", "gsr_covis", "gsr_prune_workspace_bytes", "gsr_prune", "gsr_compact",
-           "gsr_nearest", "gsr_merge", "gsr_keep_list", "gsr_device_clock_hz")
+           "gsr_nearest", "gsr_merge", "gsr_keep_list", "gsr_seed_frame", "gsr_device_clock_hz")
 
 # launch groups of gsr_plan_read_timing (gsr_timer)
 TIMERS = ("project", "bin_emit", "bin_sort", "bin_ranges", "raster_fwd", "loss_l1", "clear_grad2d",
@@ -396,3 +398,13 @@ def gsr_merge(n, colour_rows, params, v_vis, nn_index, radius, colour_tol, out, 
 def gsr_keep_list(n, mask, keep_index, kept, workspace, stream):
     return check(_lib.gsr_keep_list(int(n), _p(mask), _p(keep_index), _p(kept), _p(workspace),
                                     ctypes.c_void_p(stream)), "gsr_keep_list")
+
+
+def gsr_seed_frame(n, mean, valid, err, angle, P_ref, centre_ref, radius, c_par, floor_scale, workspace, quat,
+                   log_scale, stream):
+    P = (ctypes.c_double * 12)(*[float(x) for x in P_ref])
+    c = (ctypes.c_double * 3)(*[float(x) for x in centre_ref])
+    return check(_lib.gsr_seed_frame(int(n), _p(mean), _p(valid), _p(err), _p(angle), P, c, ctypes.c_double(radius),
+                                     ctypes.c_double(c_par), ctypes.c_float(floor_scale), _p(workspace),
+                                     workspace.numel() * workspace.element_size(), _p(quat), _p(log_scale),
+                                     ctypes.c_void_p(stream)), "gsr_seed_frame")

@@ -1,5 +1,6 @@
 """One-shot Gaussian seeding on the GPU (argument marshalling for the C ABI's
-gsr_seed_triangulate and gsr_seed_scale; every step runs in the library)."""
+gsr_seed_triangulate, gsr_seed_scale and gsr_seed_frame; every step runs in
+the library)."""
 from __future__ import annotations
 
 import torch
@@ -49,14 +50,34 @@ class Scaler:
         lib.gsr_seed_scale(n, mean, valid, floor_scale, self.workspace, log_scale, _stream(mean.device))
         return log_scale
 
+    def frame(self, mean, valid, err, angle, P_ref, centre_ref, radius, c_par=1.0, floor_scale=1e-4,
+              quat=None, log_scale=None):
+        """Anisotropic initialisation of Eq. (app-sigma-init): (quat [4][n],
+        log_scale [3][n]) of the seeds, from the plane fitted to the seeds
+        within `radius` and the reference view P_ref (3x4), centre_ref."""
+        n = int(mean.shape[-1])
+        if n > self.n:
+            raise ValueError(f"{n} seeds exceed the workspace's {self.n}")
+        if quat is None:
+            quat = torch.empty(4, n, device=mean.device)
+        if log_scale is None:
+            log_scale = torch.empty(3, n, device=mean.device)
+        P = [float(x) for row in P_ref for x in row] if hasattr(P_ref[0], "__len__") else list(P_ref)
+        lib.gsr_seed_frame(n, mean, valid, err, angle, P, centre_ref, radius, c_par, floor_scale, self.workspace,
+                           quat, log_scale, _stream(mean.device))
+        return quat, log_scale
 
-def gaussians(seeds, log_scale):
+
+def gaussians(seeds, log_scale, quat=None):
     """The valid seeds as Gaussian parameters in the renderer's layout
-    (identity rotation)."""
+    (identity rotation unless quat [4][n] is given)."""
     keep = seeds["valid"] != 0
     m = int(keep.sum())
-    quat = torch.zeros(4, m, device=seeds["mean"].device)
-    quat[0] = 1.0
+    if quat is None:
+        quat = torch.zeros(4, m, device=seeds["mean"].device)
+        quat[0] = 1.0
+    else:
+        quat = quat[:, keep].contiguous()
     return {"mean": seeds["mean"][:, keep].contiguous(), "quat": quat,
             "log_scale": log_scale[:, keep].contiguous(),
             "opacity_logit": seeds["opacity_logit"][keep].contiguous(),

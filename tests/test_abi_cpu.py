@@ -216,3 +216,14 @@ def test_seed_argument_errors():
     assert need > 0
     assert raw.gsr_seed_scale(1000, fake, fake, 1e-4, fake, need - 1, fake, None) == lib.EINVAL
     assert raw.gsr_seed_scale(1000, fake, fake, 0.0, fake, need, fake, None) == lib.EINVAL
+    P = (ctypes.c_double * 12)(*([1.0] * 12))
+    c = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    frame = lambda n, r=0.1, cp=1.0, fl=1e-4, ws=need, PP=P: raw.gsr_seed_frame(  # noqa: E731
+        n, fake, fake, fake, fake, PP, c, r, cp, fl, fake, ws, fake, fake, None)
+    assert frame(1000, ws=need - 1) == lib.EINVAL
+    assert frame(1000, r=0.0) == lib.EINVAL and frame(1000, r=float("inf")) == lib.EINVAL
+    assert frame(1000, cp=-1.0) == lib.EINVAL and frame(1000, fl=0.0) == lib.EINVAL
+    assert frame(1000, PP=(ctypes.c_double * 12)(*([float("nan")] + [1.0] * 11))) == lib.EINVAL
+    assert frame(-1) == lib.EINVAL and frame(0) == 0
+    assert raw.gsr_seed_frame(10, fake, fake, None, fake, P, c, 0.1, 1.0, 1e-4, fake, need, fake, fake,
+                              None) == lib.EINVAL

@@ -1,0 +1,129 @@
+"""Parity of the GPU anisotropic seed initialisation (gsr_seed_frame through
+the C ABI) with the FP64 oracle, Eq. (app-sigma-init).
+
+Inputs: seeds at the raycast points of the analytic room seen from the
+reference keyframe, moved by N(0, 2 mm^2) and rounded to FP32, 10 % marked
+invalid, reprojection errors ~ U[0, 2.5] px and baseline angles
+~ U[0.005, 0.4] rad, plus a few isolated seeds far from the rest (the
+viewing-ray fallback).
+
+Bar.  Both sides compare the same FP32 positions in double, so the plane-fit
+neighbourhoods are equal except for a seed lying within 1e-9 relative of
+another's radius; such seeds, and seeds whose scatter has no clear smallest
+eigenvalue (gap below 1e-6 of the largest: the normal is not unique), are
+left out (fewer than 1 %).  The log-scales (one FP32 rounding of FP64
+values) agree within 2e-6; the normal (third column of the rotation of the
+FP32 quaternion) within 1e-6 in |cos|; the covariance rebuilt from the FP32
+quaternion and log-scales within 1e-5 of its largest entry; quaternions are
+unit.  Invalid seeds get the identity and zeros.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import optim as O
+from paper_2601_00705_amd import scenes
+
+pytestmark = pytest.mark.gpu
+
+S = oracle.seeding
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def _inputs(seed, n, far=0, **kw):
+    d = scenes.seed_inputs(seed, n, **kw)
+    rng = np.random.default_rng(seed + 100)
+    X = d["X_true"] + rng.normal(0, 0.002, size=d["X_true"].shape)
+    if far:
+        X[:, :far] = rng.uniform(-40, 40, size=(3, far)) + np.array([[0.0], [0.0], [60.0]])
+    mean = X.astype(np.float32)
+    valid = (rng.uniform(size=n) < 0.9).astype(np.int32)
+    valid[:far] = 1
+    err = rng.uniform(0, 2.5, n).astype(np.float32)
+    angle = rng.uniform(0.005, 0.4, n).astype(np.float32)
+    return mean, valid, err, angle, d["Ps"][0], d["centres"][0]
+
+
+def _unclear(mean, valid, radius, sample):
+    """Seeds of `sample` whose neighbourhood or normal is not decided to
+    the bar's margin."""
+    from scipy.spatial import cKDTree
+    idx = np.nonzero(valid)[0]
+    pts = mean[:, idx].astype(np.float64).T
+    tree = cKDTree(pts)
+    pos = {int(i): k for k, i in enumerate(idx)}
+    bad = set()
+    for i in sample:
+        if not valid[i]:
+            continue
+        p = pts[pos[int(i)]]
+        a = tree.query_ball_point(p, radius * (1 - 1e-9))
+        b = tree.query_ball_point(p, radius * (1 + 1e-9))
+        if len(a) != len(b):
+            bad.add(int(i))
+            continue
+        if len(b) >= 3:
+            D = pts[b] - pts[b].mean(axis=0)
+            lam = np.linalg.eigvalsh(D.T @ D)
+            if lam[1] - lam[0] < 1e-6 * lam[2]:
+                bad.add(int(i))
+    return bad
+
+
+def _check(mean, valid, err, angle, P, c, radius, c_par, q, ls, sample):
+    Sig, U, ref_ls = S.frame_init(mean.astype(np.float64), valid, P, c, err.astype(np.float64),
+                                  angle.astype(np.float64), radius, c_par=c_par, only=sample)
+    bad = _unclear(mean, valid, radius, sample)
+    checked = 0
+    worst = 0.0
+    for i in sample:
+        if not valid[i]:
+            assert q[:, i].tolist() == [1.0, 0.0, 0.0, 0.0] and ls[:, i].tolist() == [0.0, 0.0, 0.0]
+            continue
+        assert abs(np.linalg.norm(q[:, i].astype(np.float64)) - 1.0) < 1e-6
+        assert np.all(np.abs(ls[:, i] - ref_ls[:, i]) <= 2e-6), (i, ls[:, i], ref_ls[:, i])
+        if i in bad:
+            continue
+        R = O.quat_to_rot(q[:, i].astype(np.float64))
+        assert abs(abs(R[:, 2] @ U[i][:, 2]) - 1.0) <= 1e-6, i
+        G = O.covariance(q[:, i].astype(np.float64), ls[:, i].astype(np.float64))
+        e = np.abs(G - Sig[i]).max() / np.abs(Sig[i]).max()
+        worst = max(worst, e)
+        checked += 1
+    assert worst <= 1e-5, worst
+    assert len(bad) <= 0.01 * len(sample)
+    return checked, len(bad), worst
+
+
+def _run(mean, valid, err, angle, P, c, radius, c_par):
+    from paper_2601_00705_amd import seeding
+    n = mean.shape[1]
+    dev = [torch.from_numpy(np.ascontiguousarray(x)).cuda() for x in (mean, valid, err, angle)]
+    q, ls = seeding.Scaler(n).frame(*dev, P, c, radius, c_par=c_par)
+    torch.cuda.synchronize()
+    return q.cpu().numpy(), ls.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,far,radius,c_par", [(20000, 0, 0.04, 1.0), (5003, 25, 0.08, 0.4)])
+def test_frame_parity(n, far, radius, c_par):
+    say(f"[seed_frame] n={n} far={far} radius={radius}")
+    mean, valid, err, angle, P, c = _inputs(n, n, far=far)
+    q, ls = _run(mean, valid, err, angle, P, c, radius, c_par)
+    checked, bad, worst = _check(mean, valid, err, angle, P, c, radius, c_par, q, ls, np.arange(n))
+    say(f"  checked {checked}, left out {bad}, covariance error {worst:.2e}")
+
+
+def test_frame_at_full_size():
+    """500,000 seeds of a 1200x680 keyframe (the mapping workload's seeding
+    shape), 2,000 sampled seeds against the oracle."""
+    n = 500_000
+    say(f"[seed_frame] n={n}")
+    mean, valid, err, angle, P, c = _inputs(7, n, width=1200, height=680, f=600.0)
+    q, ls = _run(mean, valid, err, angle, P, c, 0.01, 1.0)
+    sample = np.random.default_rng(8).choice(n, 2000, replace=False)
+    checked, bad, worst = _check(mean, valid, err, angle, P, c, 0.01, 1.0, q, ls, sample)
+    say(f"  checked {checked}, left out {bad}, covariance error {worst:.2e}")
