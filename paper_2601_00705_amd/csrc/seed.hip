@@ -799,8 +799,8 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_brute(KnnArgs a)
 // ---- anisotropic initialisation, Eq. (app-sigma-init) ----------------------
 // One thread per seed.  The seeds are hashed by cells of exactly `radius`
 // (the first level of the fine grid, unbounded), so the seeds within the
-// radius lie in the 3 x 3 x 3 cells around the seed's own; a candidate counts
-// only in its own cell, so buckets shared by two of those cells count once.
+// radius lie in the 3 x 3 x 3 cells around the seed's own, whose distinct
+// buckets are scanned once each.
 // Their first and second moments about the seed (double) give
 // the scatter about their mean; its eigenvector of the smallest eigenvalue
 // is the plane normal v, that of the largest t1, and t2 = v x t1 (with fewer
@@ -848,34 +848,43 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_frame(KnnArgs a, Fram
 #pragma unroll
     for (int c = 0; c < 3; ++c) c0[c] = fine_coord(g, 0, c, p[c]);
     double cnt = 0.0, m1[3] = {0.0, 0.0, 0.0}, m2[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int dz = -1; dz <= 1; ++dz)
-        for (int dy = -1; dy <= 1; ++dy)
-            for (int dx = -1; dx <= 1; ++dx) {
-                const int cx = c0[0] + dx, cy = c0[1] + dy, cz = c0[2] + dz;
-                const uint32_t b = fine_bucket(cx, cy, cz, mask);
-                const uint32_t e = a.fine_start[b + 1];
-                for (uint32_t k = a.fine_start[b]; k < e; ++k) {
-                    const float4 q = a.fine_pts[k];
-                    if (fine_coord(g, 0, 0, q.x) != cx || fine_coord(g, 0, 1, q.y) != cy ||
-                        fine_coord(g, 0, 2, q.z) != cz)
-                        continue;
-                    const double ex = (double)q.x - (double)p[0];
-                    const double ey = (double)q.y - (double)p[1];
-                    const double ez = (double)q.z - (double)p[2];
-                    if (ex * ex + ey * ey + ez * ez <= r2) {
-                        cnt += 1.0;
-                        m1[0] += ex;
-                        m1[1] += ey;
-                        m1[2] += ez;
-                        m2[0] += ex * ex;
-                        m2[1] += ex * ey;
-                        m2[2] += ex * ez;
-                        m2[3] += ey * ey;
-                        m2[4] += ey * ez;
-                        m2[5] += ez * ez;
-                    }
-                }
+    // the buckets of the 27 cells, each visited once: a seed within the
+    // radius lies in one of the cells, and seeds of other cells that share
+    // a bucket fail the distance test
+    uint32_t bk[27];
+#pragma unroll
+    for (int c = 0; c < 27; ++c) bk[c] = fine_bucket(c0[0] + c % 3 - 1, c0[1] + (c / 3) % 3 - 1, c0[2] + c / 9 - 1, mask);
+    // FP32 prefilter: its squared distance is within 3e-7 relative of the
+    // double one, so a candidate beyond r^2 (1 + 1e-5) in FP32 is beyond r^2
+    const float cut = (float)(r2 * (1.0 + 1e-5));
+#pragma unroll
+    for (int c = 0; c < 27; ++c) {
+        bool dup = false;
+#pragma unroll
+        for (int j = 0; j < c; ++j) dup |= bk[j] == bk[c];
+        if (dup) continue;
+        const uint32_t e = a.fine_start[bk[c] + 1];
+        for (uint32_t k = a.fine_start[bk[c]]; k < e; ++k) {
+            const float4 q = a.fine_pts[k];
+            const float fx = q.x - p[0], fy = q.y - p[1], fz = q.z - p[2];
+            if (fx * fx + fy * fy + fz * fz > cut) continue;
+            const double ex = (double)q.x - (double)p[0];
+            const double ey = (double)q.y - (double)p[1];
+            const double ez = (double)q.z - (double)p[2];
+            if (ex * ex + ey * ey + ez * ez <= r2) {
+                cnt += 1.0;
+                m1[0] += ex;
+                m1[1] += ey;
+                m1[2] += ez;
+                m2[0] += ex * ex;
+                m2[1] += ex * ey;
+                m2[2] += ex * ez;
+                m2[3] += ey * ey;
+                m2[4] += ey * ez;
+                m2[5] += ez * ez;
             }
+        }
+    }
     double v[3], t1[3];
     if (cnt >= 3.0) {
         const double ic = 1.0 / cnt;
