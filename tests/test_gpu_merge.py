@@ -186,3 +186,27 @@ def test_merge_degenerate_cases():
     # zero radius: nothing merges
     _, keep, _ = maintain.merge(_dev(p), torch.from_numpy(v).cuda(), 0.0, 0.05)
     assert keep.cpu().tolist() == [1, 1]
+
+
+def test_nearest_with_a_validity_mask():
+    """Invalid Gaussians are neither queried nor found: -1 for them, and the
+    valid ones' neighbours are the k-d tree's over the valid set."""
+    from scipy.spatial import cKDTree
+    p, _ = _cloud(31, 6000, 1500)
+    n = p["mean"].shape[1]
+    valid = (np.random.default_rng(32).uniform(size=n) < 0.7).astype(np.int32)
+    nn = maintain.nearest(torch.from_numpy(p["mean"]).cuda(), torch.from_numpy(valid).cuda())
+    torch.cuda.synchronize()
+    got = nn.cpu().numpy()
+    idx = np.nonzero(valid)[0]
+    pts = p["mean"][:, idx].astype(np.float64).T
+    dist, j = cKDTree(pts).query(pts, k=3)
+    unique = dist[:, 2] - dist[:, 1] > 1e-9 * dist[:, 1]
+    assert np.all(got[valid == 0] == -1)
+    assert np.array_equal(got[idx][unique], idx[j[unique, 1]])
+    assert unique.sum() > 0.99 * idx.size
+    # no valid pair at all
+    one = np.zeros(n, np.int32)
+    one[5] = 1
+    nn = maintain.nearest(torch.from_numpy(p["mean"]).cuda(), torch.from_numpy(one).cuda())
+    assert nn.cpu().numpy().tolist() == [-1] * n

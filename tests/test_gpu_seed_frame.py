@@ -127,3 +127,16 @@ def test_frame_at_full_size():
     sample = np.random.default_rng(8).choice(n, 2000, replace=False)
     checked, bad, worst = _check(mean, valid, err, angle, P, c, 0.01, 1.0, q, ls, sample)
     say(f"  checked {checked}, left out {bad}, covariance error {worst:.2e}")
+
+
+def test_frame_degenerate_cases():
+    """No valid seed: the identity and zeros everywhere.  One valid seed: the
+    viewing-ray normal with the footprint scales."""
+    mean, valid, err, angle, P, c = _inputs(11, 300)
+    q, ls = _run(mean, np.zeros(300, np.int32), err, angle, P, c, 0.05, 1.0)
+    assert np.all(q[0] == 1.0) and np.all(q[1:] == 0.0) and np.all(ls == 0.0)
+    one = np.zeros(300, np.int32)
+    one[17] = 1
+    q, ls = _run(mean, one, err, angle, P, c, 0.05, 1.0)
+    checked, bad, worst = _check(mean, one, err, angle, P, c, 0.05, 1.0, q, ls, np.arange(300))
+    assert checked == 1 and bad == 0
