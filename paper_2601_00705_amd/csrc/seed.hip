@@ -395,6 +395,28 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_zero(KnnArgs a)
     }
 }
 
+// rank of this lane's entry in counters[key], with one atomic per distinct
+// key of the wave (its lanes of equal key take consecutive ranks): many
+// seeds share a cell of a coarse level, and one atomic each would serialise
+// on its counter
+__device__ __forceinline__ uint32_t wave_rank_add(uint32_t* counters, uint32_t key)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t pending = __ballot(1);
+    uint32_t rank = 0u;
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const uint32_t lead_key = __shfl(key, leader, 64);
+        const uint64_t same = __ballot(key == lead_key);
+        uint32_t base = 0u;
+        if (lane == leader) base = atomicAdd(&counters[lead_key], (uint32_t)__popcll(same));
+        base = __shfl(base, leader, 64);
+        if (key == lead_key) rank = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+        pending &= ~same;
+    }
+    return rank;
+}
+
 __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_count(KnnArgs a)
 {
     const KnnGrid g = *a.grid;
@@ -405,7 +427,7 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_count(KnnArgs a)
     for (int c = 0; c < 3; ++c) cc[c] = cell_coord(g, c, a.mean[(int64_t)c * a.n + i]);
     const uint32_t cell = (uint32_t)(((int64_t)cc[2] * g.dims[1] + cc[1]) * g.dims[0] + cc[0]);
     a.cell_of[i] = cell;
-    a.rank[i] = atomicAdd(&a.cell_count[cell], 1u);
+    a.rank[i] = wave_rank_add(a.cell_count, cell);
 }
 
 // sum over coarse cells of count^2 (per block), the seeds' mean cell sharing
@@ -457,7 +479,7 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_fcount(KnnArgs a)
         const uint32_t b = fine_bucket(fine_coord(g, l, 0, a.mean[i]), fine_coord(g, l, 1, a.mean[a.n + i]),
                                        fine_coord(g, l, 2, a.mean[2 * a.n + i]), mask);
         a.fine_of[l * a.n + i] = b;
-        a.fine_rank[l * a.n + i] = atomicAdd(&a.fine_count[l * T1 + b], 1u);
+        a.fine_rank[l * a.n + i] = wave_rank_add(a.fine_count + l * T1, b);
     }
 }
 
