@@ -622,6 +622,13 @@ __device__ __forceinline__ void knn_candidate(const float4& q, int64_t i, float 
 {
     const uint32_t j = __float_as_uint(q.w);
     if ((int64_t)j == i) return;
+    if (found == 3) {
+        // FP32 prefilter: its squared distance is within 3e-7 relative of
+        // the double one, so beyond the third-best by 1e-5 relative it is
+        // strictly farther in double and could not be inserted
+        const float fx = q.x - px, fy = q.y - py, fz = q.z - pz;
+        if (fx * fx + fy * fy + fz * fz > (float)best[2] * 1.00001f) return;
+    }
     const double ex = (double)q.x - (double)px;
     const double ey = (double)q.y - (double)py;
     const double ez = (double)q.z - (double)pz;
