@@ -838,7 +838,8 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_brute(KnnArgs a)
 // at the seed (the equal-area radius of the back-projected one-pixel
 // footprint); s_par = c_par s_perp max(1, err) / max(sin angle, 1e-6); both
 // floored.  Output: the unit quaternion of [t1 t2 v] and the log-scales
-// (s_perp, s_perp, s_par).
+// (s_perp, s_perp, s_par).  The neighbour moments and the fit run in two
+// kernels, so that the latency-bound search keeps few registers.
 
 // the frame's hash grid: fine cells of exactly the radius
 __global__ void k_seed_frame_grid(KnnArgs a, double radius)
@@ -852,6 +853,8 @@ __global__ void k_seed_frame_grid(KnnArgs a, double radius)
     }
     *a.grid = g;
 }
+
+static_assert(16 * (GSR_KNN_LEVELS - 1) >= 80, "the frame's moments need 80 bytes per seed in fine levels 1..");
 
 __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_frame(KnnArgs a, FrameArgs f)
 {
@@ -869,7 +872,6 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_frame(KnnArgs a, Fram
     const KnnGrid g = *a.grid;
     if (t >= g.count) return;
     const float4 self = a.fine_pts[t];
-    const int64_t i = (int64_t)__float_as_uint(self.w);
     const float p[3] = {self.x, self.y, self.z};
     const double r2 = f.radius * f.radius;
     const uint32_t mask = ((uint32_t)1 << a.table_bits) - 1u;
@@ -914,6 +916,36 @@ __global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_frame(KnnArgs a, Fram
             }
         }
     }
+    // the moments go to the unused fine levels 1.. of the record buffer
+    // ([10][count] doubles; levels 1 to 7 hold 112 bytes per seed)
+    double* mom = reinterpret_cast<double*>(a.fine_pts + a.n);
+    const int64_t cnt_all = g.count;
+    mom[t] = cnt;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) mom[(1 + c) * cnt_all + t] = m1[c];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) mom[(4 + c) * cnt_all + t] = m2[c];
+}
+
+// the plane fit and the scales of the t-th valid seed in cell order, from
+// the moments k_seed_frame left
+__global__ __launch_bounds__(GSR_SEED_THREADS) void k_seed_frame_fit(KnnArgs a, FrameArgs f)
+{
+    const int64_t t = (int64_t)blockIdx.x * GSR_SEED_THREADS + threadIdx.x;
+    const int64_t n = a.n;
+    const KnnGrid g = *a.grid;
+    if (t >= g.count) return;
+    const float4 self = a.fine_pts[t];
+    const int64_t i = (int64_t)__float_as_uint(self.w);
+    const float p[3] = {self.x, self.y, self.z};
+    const double* mom = reinterpret_cast<const double*>(a.fine_pts + a.n);
+    const int64_t cnt_all = g.count;
+    const double cnt = mom[t];
+    double m1[3], m2[6];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) m1[c] = mom[(1 + c) * cnt_all + t];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) m2[c] = mom[(4 + c) * cnt_all + t];
     double v[3], t1[3];
     if (cnt >= 3.0) {
         const double ic = 1.0 / cnt;
@@ -1016,6 +1048,7 @@ hipError_t launch_seed_frame(const KnnArgs& a, const FrameArgs& f, hipStream_t s
     }
     hipLaunchKernelGGL(k_seed_place, dim3(blocks), dim3(GSR_SEED_THREADS), 0, s, a);
     hipLaunchKernelGGL(k_seed_frame, dim3(blocks), dim3(GSR_SEED_THREADS), 0, s, a, f);
+    hipLaunchKernelGGL(k_seed_frame_fit, dim3(blocks), dim3(GSR_SEED_THREADS), 0, s, a, f);
     return hipGetLastError();
 }
 
