@@ -153,10 +153,7 @@ def merge(params, v_vis, radius, colour_tol, nn=None):
         out["mean"][:, i] = (wi * p["mean"][:, i] + wj * p["mean"][:, j]) / W
         oc = out["colour"].reshape(-1, n)
         oc[:, i] = (wi * col[:, i] + wj * col[:, j]) / W
-        ai = 1.0 / (1.0 + np.exp(-p["opacity_logit"][i]))
-        aj = 1.0 / (1.0 + np.exp(-p["opacity_logit"][j]))
-        a = (wi * ai + wj * aj) / W
-        out["opacity_logit"][i] = np.log(a / (1.0 - a))
+        out["opacity_logit"][i] = merged_logit(p["opacity_logit"][i], p["opacity_logit"][j], wi, wj)
         S = (wi * covariance(p["quat"][:, i], p["log_scale"][:, i]) +
              wj * covariance(p["quat"][:, j], p["log_scale"][:, j])) / W
         lam, V = np.linalg.eigh(S)
@@ -166,6 +163,20 @@ def merge(params, v_vis, radius, colour_tol, nn=None):
         out["quat"][:, i] = rot_to_quat(V)
         keep[j] = False
     return out, keep
+
+
+def merged_logit(xi, xj, wi, wj):
+    """logit of the weighted mean (wi sigmoid(xi) + wj sigmoid(xj)) / (wi + wj).
+    The mean a and its complement 1 - a are both formed as weighted sums of
+    sigmoids (1 - sigmoid(x) = sigmoid(-x)) in the log domain, so that
+    saturated opacities (|logit| beyond ~37, where a rounds to 1 in double)
+    keep a finite logit log(a) - log(1 - a)."""
+    with np.errstate(divide="ignore"):
+        lw = np.log(np.array([wi, wj], np.float64))  # a zero weight gives -inf
+    x = np.array([xi, xj], np.float64)
+    log_sig = -np.logaddexp(0.0, -x)      # log sigmoid(x)
+    log_sig_neg = -np.logaddexp(0.0, x)   # log sigmoid(-x) = log(1 - sigmoid(x))
+    return float(np.logaddexp.reduce(lw + log_sig) - np.logaddexp.reduce(lw + log_sig_neg))
 
 
 def rot_to_quat(R):

@@ -412,6 +412,30 @@ __global__ __launch_bounds__(256) void k_merge_copy(MergeArgs a)
     for (int64_t q = done + t; q < len; q += stride) dst[q] = src[q];
 }
 
+// log(exp(x) + exp(y)), -inf when both are -inf
+__device__ __forceinline__ double log_add_exp(double x, double y)
+{
+    const double hi = fmax(x, y), lo = fmin(x, y);
+    return hi == -INFINITY ? hi : hi + log1p(exp(lo - hi));
+}
+
+// log sigmoid(x) = -log(1 + exp(-x)), without overflow for large |x|
+__device__ __forceinline__ double log_sigmoid(double x)
+{
+    return -(fmax(-x, 0.0) + log1p(exp(-fabs(x))));
+}
+
+// logit of the weighted mean a = (wi sigmoid(xi) + wj sigmoid(xj)) / (wi + wj):
+// a and 1 - a are both weighted sums of sigmoids (1 - sigmoid(x) =
+// sigmoid(-x)), summed in the log domain, so that saturated opacities keep a
+// finite logit where a itself rounds to 1
+__device__ __forceinline__ double merged_logit(double xi, double xj, double wi, double wj)
+{
+    const double li = wi > 0.0 ? log(wi) : -INFINITY, lj = wj > 0.0 ? log(wj) : -INFINITY;
+    return log_add_exp(li + log_sigmoid(xi), lj + log_sigmoid(xj)) -
+           log_add_exp(li + log_sigmoid(-xi), lj + log_sigmoid(-xj));
+}
+
 // the merge proper, after k_merge_copy: keep flags, and the merged columns
 // of the survivors
 __global__ __launch_bounds__(256) void k_merge(MergeArgs a)
@@ -439,9 +463,7 @@ __global__ __launch_bounds__(256) void k_merge(MergeArgs a)
     for (int r = 0; r < a.colour_rows; ++r)
         a.out[4][(int64_t)r * a.n + i] =
             (float)((wi * (double)a.in[4][(int64_t)r * a.n + i] + wj * (double)a.in[4][(int64_t)r * a.n + j]) / W);
-    const double ai = 1.0 / (1.0 + exp(-(double)a.in[3][i])), aj = 1.0 / (1.0 + exp(-(double)a.in[3][j]));
-    const double al = (wi * ai + wj * aj) / W;
-    a.out[3][i] = (float)log(al / (1.0 - al));
+    a.out[3][i] = (float)merged_logit((double)a.in[3][i], (double)a.in[3][j], wi, wj);
     double S[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};
     add_cov(a, i, wi / W, S);
     add_cov(a, j, wj / W, S);

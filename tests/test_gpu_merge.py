@@ -186,6 +186,16 @@ def test_merge_degenerate_cases():
     # zero radius: nothing merges
     _, keep, _ = maintain.merge(_dev(p), torch.from_numpy(v).cuda(), 0.0, 0.05)
     assert keep.cpu().tolist() == [1, 1]
+    # saturated opacities (logits 40 and 45, alpha rounds to 1 in double):
+    # the merged logit stays finite and equals the oracle's
+    p["opacity_logit"][:] = [40.0, 45.0]
+    v[:] = [1.0, 3.0]
+    out, keep, _ = maintain.merge(_dev(p), torch.from_numpy(v).cuda(), 1.0, 0.05)
+    torch.cuda.synchronize()
+    ref, _ = O.merge(p, v, 1.0, 0.05, nn=np.array([1, 0]))
+    got = float(out["opacity_logit"][0].cpu())
+    assert keep.cpu().tolist() == [1, 0] and np.isfinite(got)
+    assert abs(got - ref["opacity_logit"][0]) <= 1e-6 * abs(ref["opacity_logit"][0])
 
 
 def test_nearest_with_a_validity_mask():

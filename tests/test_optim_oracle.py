@@ -190,3 +190,25 @@ def test_merge_conditions():
     q["colour"][:] = 0.5
     _, keep = O.merge(q, np.ones(3), radius=1.0, colour_tol=0.1)
     assert keep.tolist() == [True, True, False]
+
+
+def test_merged_opacity_of_saturated_logits_is_finite():
+    """Opacity logits of 40 and 45 (alpha rounds to 1 in double): the merged
+    logit is log(a / (1 - a)) with 1 - a = (e^-40 + 3 e^-45) / 4 to double
+    precision, not +inf; two logits of -40 merge to -40 + log((1 + 3) / 4);
+    a zero weight returns the other Gaussian's logit."""
+    rng = np.random.default_rng(13)
+    p = _pair_params(rng, 3)
+    p["mean"][:, 1] = p["mean"][:, 0] + 0.001
+    p["colour"][:, 1] = p["colour"][:, 0]
+    p["log_scale"][:, :2] = np.log(0.1)
+    p["opacity_logit"][:2] = [40.0, 45.0]
+    out, keep = O.merge(p, np.array([1.0, 3.0, 1.0]), radius=1.0, colour_tol=0.1)
+    assert keep.tolist() == [True, False, True]
+    want = -np.log((np.exp(-40.0) + 3 * np.exp(-45.0)) / 4)  # 1 - a, with a within 1e-17 of 1
+    assert np.isfinite(out["opacity_logit"][0]) and abs(out["opacity_logit"][0] - want) <= 1e-12 * want
+    p["opacity_logit"][:2] = [-40.0, -40.0]
+    out, _ = O.merge(p, np.array([1.0, 3.0, 1.0]), radius=1.0, colour_tol=0.1)
+    assert abs(out["opacity_logit"][0] + 40.0) <= 1e-12
+    assert O.merged_logit(40.0, -3.0, 2.0, 0.0) == 40.0
+    assert abs(O.merged_logit(0.7, -0.2, 0.0, 5.0) + 0.2) <= 1e-15
