@@ -45,9 +45,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
     const bool live_thread = i < n;
     const int64_t S = (int64_t)a.views->n * n;
-    // SH of degree 1-3 is differentiated by k_sh_bwd (its own registers); the
-    // geometry chain here then carries no colour state
-    constexpr int K = DEG <= 0 ? 1 : 1;
+    // one colour row here (RGB, or the single coefficient of SH degree 0);
+    // SH of degree 1-3 is differentiated by k_sh_bwd (its own registers), and
+    // the geometry chain here then carries no colour state
+    constexpr int K = 1;
 
     Activated<T> g;
     T col[K][3];
