@@ -53,9 +53,14 @@ class Renderer:
             # a first guess; forward_all grows it to the measured need
             pair_capacity = min(max(1 << 16, 8 * self.n * len(cams)), 1 << 26)
         self.plan = None
+        # bumped whenever the workspace's records, pair lists or capacity
+        # change (projection, plan growth); the autograd Function compares it
+        # to decide whether its forward's state is still in the workspace
+        self.generation = 0
         self._make(int(min(pair_capacity, (1 << 32) - 1)))
 
     def _make(self, capacity):
+        self.generation += 1
         if self.plan is not None:
             lib.gsr_plan_destroy(self.plan)
         self.plan = lib.gsr_plan_create(self.n, self.cams, self.cfg, capacity)
@@ -114,6 +119,7 @@ class Renderer:
         return lib.make_gaussians(self.n, *(params[k] for k in PARAM_KEYS))
 
     def project(self, params, poses):
+        self.generation += 1
         lib.gsr_project(self.plan, self.gaussians(params), poses, _stream(self.device))
 
     def bin(self):
@@ -202,6 +208,7 @@ class _RenderFn(torch.autograd.Function):
         poses = poses.contiguous()
         rgb, T, nc, _ = renderer.forward_all(params, poses)
         ctx.renderer = renderer
+        ctx.generation = renderer.generation
         ctx.pose_only = pose_only
         ctx.save_for_backward(poses, T, nc, *(params[k] for k in PARAM_KEYS))
         ctx.mark_non_differentiable(nc)
@@ -212,6 +219,14 @@ class _RenderFn(torch.autograd.Function):
         r = ctx.renderer
         poses, T, nc, *tensors = ctx.saved_tensors
         params = dict(zip(PARAM_KEYS, tensors))
+        if r.generation != ctx.generation:
+            # another forward (or a plan growth) has run on this renderer since
+            # this one: its sorted lists and staging records are gone from the
+            # workspace.  Projection and binning are deterministic, so running
+            # them again on the saved inputs restores exactly this forward's
+            # state (the capacity only grows, so it still fits).
+            r.project(params, poses)
+            r.bin()
         grads = {k: torch.empty_like(v) for k, v in params.items()}
         d_xi = torch.empty(len(r.cams), 6, device=poses.device)
         d_rgb = torch.zeros(3 * r.total_pixels, device=poses.device) if d_rgb is None else d_rgb.contiguous()

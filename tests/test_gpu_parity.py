@@ -491,6 +491,44 @@ def test_backward_parity_room_100k():
     _check_backward("room-100k", w["params"], w["cams"], w["poses"], Config(), 21, frac_max=0.01)
 
 
+def test_autograd_backward_after_a_second_forward():
+    """Two differentiable renders on one Renderer (different parameters and
+    poses, the second larger so that the plan grows), then the first graph's
+    backward: its gradients are the oracle's for the first render, not the
+    second's (the workspace state is re-derived when another forward has run
+    since)."""
+    params1, cam = scenes.cloud(511, 60, 48, 40, 40.0)
+    params2, _ = scenes.cloud(512, 600, 48, 40, 40.0)
+    pose1 = scenes.left_perturb(scenes.identity_pose(), np.array([0.03, -0.02, 0.05, 0.04, -0.03, 0.02]))
+    pose2 = scenes.left_perturb(scenes.identity_pose(), np.array([-0.05, 0.01, 0.02, -0.02, 0.03, 0.01]))
+    cfg = Config()
+    R = Renderer(60, [cam], cfg, pair_capacity=64)
+    say("[autograd] two forwards, first backward")
+    P1 = {k: v.clone().requires_grad_(True) for k, v in to_dev(params1).items()}
+    xi1 = torch.zeros(1, 6, device="cuda", requires_grad=True)
+    poses1 = torch.from_numpy(pose1[None].astype(np.float32)).cuda()
+    rgb1, T1, _ = render(R, P1, poses1, xi1)
+    gen1 = R.generation
+    # a second forward on the same renderer with other parameters (60 of the
+    # 600 Gaussians, a different pose); the 64-pair capacity grows again
+    sub = {k: np.ascontiguousarray(v[..., :60]) for k, v in params2.items()}
+    sub["log_scale"] = sub["log_scale"] + np.float32(0.7)
+    P2 = {k: v.clone().requires_grad_(True) for k, v in to_dev(sub).items()}
+    rgb2, _, _ = render(R, P2, torch.from_numpy(pose2[None].astype(np.float32)).cuda())
+    assert R.generation != gen1
+    w = torch.from_numpy(scenes.upstream_grad(3, rgb1.numel())).cuda()
+    wT = torch.from_numpy(scenes.upstream_grad(4, T1.numel())).cuda()
+    ((rgb1 * w).sum() + (T1 * wT).sum()).backward()
+    ref = oracle.backward(params1, [cam], pose1[None].astype(np.float32), oracle_cfg(cfg),
+                          w.cpu().double().numpy(), wT.cpu().double().numpy())
+    for k in ("mean", "quat", "log_scale", "opacity_logit", "colour"):
+        frac, ratio = grad_violations(P1[k].grad.cpu().numpy(), ref[k])
+        say(f"  {k}: violating={frac:.3%} worst={ratio:.3g}")
+        assert frac == 0.0, (k, frac, ratio)
+    frac, ratio = grad_violations(xi1.grad.cpu().numpy(), ref["xi"])
+    assert frac == 0.0, ratio
+
+
 def test_autograd_function_matches_oracle():
     """torch.autograd.Function: L = <w, rgb> + <wT, T_final> backpropagates to
     every parameter and to the twist placeholder xi."""
