@@ -26,10 +26,11 @@ _SRC = os.path.join(_HERE, "gsr_oracle.c")
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (no fast-math, no FMA contraction)."""
+    """Compile the oracle with gcc (no fast-math, no FMA contraction; OpenMP
+    over pixel rows, Gaussians and tile lists)."""
     if force or not os.path.exists(_LIB_PATH):
         subprocess.check_call([
-            "gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared",
+            "gcc", "-O2", "-std=c99", "-D_GNU_SOURCE", "-fPIC", "-shared", "-fopenmp",
             "-ffp-contract=off", "-fno-fast-math", "-Wall", "-o", _LIB_PATH, _SRC, "-lm",
         ])
     return _LIB_PATH
@@ -81,7 +82,28 @@ def _load():
         _lib.or_backward.restype = ctypes.c_int
         _lib.or_project.restype = ctypes.c_int
         _lib.or_bin_f32.restype = ctypes.c_int64
+        _lib.or_get_threads.restype = ctypes.c_int32
     return _lib
+
+
+def power2_error_bound(u, v, A, B, C, px, py, xc, yc, p2):
+    """The oracle's bound on the float32 error of the exp2-space power at a
+    pixel, expanded about the tile centre (xc, yc) (test tolerance model)."""
+    f = _load().or_power2_error
+    f.restype = ctypes.c_double
+    f.argtypes = [ctypes.c_double] * 10
+    return float(f(u, v, A, B, C, px, py, xc, yc, p2))
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops (results differ across thread
+    counts only by FP64 rounding: per-thread partial sums are merged in
+    thread order)."""
+    _load().or_set_threads(ctypes.c_int32(int(n)))
+
+
+def get_threads() -> int:
+    return int(_load().or_get_threads())
 
 
 def _ptr(a):
@@ -140,7 +162,14 @@ def split_views(flat, cams, channels):
 
 def render(params, cams, poses, cfg: Config = Config(), want_margin=True):
     """Forward render.  Returns flat concatenated buffers: rgb [sum 3*H*W],
-    T_final, n_contrib, n_blend, margin [sum H*W]."""
+    T_final, n_contrib, n_blend, margin and clear [sum H*W].
+
+    margin: the smallest relative distance of any of the pixel's decisions
+    (alpha_min skip, alpha_max clamp, T_min stop) from its threshold.
+    clear: the smallest ratio of that distance to a bound on the float32
+    error of the quantity compared (a tolerance model for the tests, see
+    power2_abs_error in gsr_oracle.c); a pixel with clear > 1 takes every
+    decision the same way in float32."""
     lib = _load()
     sc = _Scene(params)
     poses = np.ascontiguousarray(poses, dtype=np.float64).reshape(-1, 12)
@@ -150,12 +179,13 @@ def render(params, cams, poses, cfg: Config = Config(), want_margin=True):
     nc = np.zeros(P, dtype=np.int32)
     nb = np.zeros(P, dtype=np.int32)
     mg = np.zeros(P) if want_margin else None
+    cl = np.zeros(P) if want_margin else None
     ccfg = _cfg(cfg)
     rc = lib.or_render(ctypes.byref(sc.c), ctypes.c_int32(len(cams)), _cams(cams), _ptr(poses),
-                       ctypes.byref(ccfg), _ptr(rgb), _ptr(T), _ptr(nc), _ptr(nb), _ptr(mg))
+                       ctypes.byref(ccfg), _ptr(rgb), _ptr(T), _ptr(nc), _ptr(nb), _ptr(mg), _ptr(cl))
     if rc != 0:
         raise RuntimeError("oracle render failed")
-    return {"rgb": rgb, "T_final": T, "n_contrib": nc, "n_blend": nb, "margin": mg}
+    return {"rgb": rgb, "T_final": T, "n_contrib": nc, "n_blend": nb, "margin": mg, "clear": cl}
 
 
 def backward(params, cams, poses, cfg: Config, dL_drgb, dL_dT=None, pose_only=None,
@@ -175,16 +205,21 @@ def backward(params, cams, poses, cfg: Config, dL_drgb, dL_dT=None, pose_only=No
         "xi": np.zeros((V, 6)),
     }
     g2 = np.zeros((V, n, 9)) if want_grad2d else None
+    g2a = np.zeros((V, n, 9)) if want_grad2d else None
     ccfg = _cfg(cfg)
     rc = lib.or_backward(ctypes.byref(sc.c), ctypes.c_int32(V), _cams(cams), _ptr(poses),
                          ctypes.byref(ccfg), _ptr(dL_drgb), _ptr(dL_dT), _ptr(po),
                          _ptr(out["mean"]), _ptr(out["quat"]), _ptr(out["log_scale"]),
                          _ptr(out["opacity_logit"]), _ptr(out["colour"]), _ptr(out["xi"]),
-                         _ptr(g2))
+                         _ptr(g2), _ptr(g2a))
     if rc != 0:
         raise RuntimeError("oracle backward failed")
     if want_grad2d:
+        # screen-space gradients per (view, Gaussian): d(u, v, A, B, C, o, r,
+        # g, b), and the sums of their addends' magnitudes (their ratio to
+        # the magnitude of the sum measures cancellation)
         out["grad2d"] = g2
+        out["grad2d_abs"] = g2a
     return out
 
 

@@ -34,9 +34,20 @@
  * (no division by 1-alpha), then the chain rule is written out scalar by scalar.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads of the OpenMP loops (pixel rows, Gaussians, tile lists); 0 keeps
+ * the OpenMP default.  Per-thread gradient buffers are merged in thread order,
+ * so a result depends on the thread count only through FP64 rounding. */
+void or_set_threads(int32_t n)
+{
+    if (n > 0) omp_set_num_threads(n);
+}
+
+int32_t or_get_threads(void) { return (int32_t)omp_get_max_threads(); }
 
 typedef struct {
     int32_t tile_w, tile_h, sh_degree; /* sh_degree < 0: plain RGB colour */
@@ -293,16 +304,15 @@ typedef struct {
     int64_t *items;   /* Gaussian indices */
 } tile_lists;
 
-static const proj_t *g_sort_proj; /* comparator context (single-threaded) */
-
 /* Front-to-back order of a tile list (Eq. (alpha): N(p) sorted near to far).
  * The order is an integer decision; it is taken on the float32 key the
  * renderer's records carry (FP32 throughout): the camera depth rounded once
  * to float32, ties broken by Gaussian index. */
-static int cmp_depth_id(const void *a, const void *b)
+static int cmp_depth_id(const void *a, const void *b, void *ctx)
 {
+    const proj_t *P = (const proj_t *)ctx;
     int64_t ia = *(const int64_t *)a, ib = *(const int64_t *)b;
-    float da = (float)g_sort_proj[ia].mc[2], db = (float)g_sort_proj[ib].mc[2];
+    float da = (float)P[ia].mc[2], db = (float)P[ib].mc[2];
     if (da < db) return -1;
     if (da > db) return 1;
     return ia < ib ? -1 : (ia > ib ? 1 : 0);
@@ -334,10 +344,10 @@ static int build_lists(const proj_t *P, int64_t n, const or_camera *cam, const o
             for (int tx = p->tx0; tx <= p->tx1; ++tx) L->items[fill[ty * L->tiles_x + tx]++] = i;
     }
     free(fill);
-    g_sort_proj = P;
+#pragma omp parallel for schedule(dynamic, 4)
     for (int64_t t = 0; t < L->n_tiles; ++t)
-        qsort(L->items + L->start[t], (size_t)(L->start[t + 1] - L->start[t]), sizeof(int64_t),
-              cmp_depth_id);
+        qsort_r(L->items + L->start[t], (size_t)(L->start[t + 1] - L->start[t]), sizeof(int64_t),
+                cmp_depth_id, (void *)P);
     return 0;
 }
 
@@ -361,15 +371,62 @@ static double rel_margin(double a, double b)
     return fabs(a - b) / (fabs(b) > 0 ? fabs(b) : 1.0);
 }
 
+/* Tolerance model for the tests; no rendered value depends on it.  A bound
+ * on the error of the exp2-space power p2 = log2(G) when a renderer forms it
+ * in float32 from the quadratic form expanded about the centre (xc, yc) of
+ * the pixel's tile: with o = (xc, yc) - (u, v), d = pixel - (xc, yc) and
+ * k = log2(e) / 2,
+ *   p2 = -k (o + d)^T conic (o + d) = c0 + g.d + d^T (-k conic) d,
+ * the six coefficients (c0, g, -k conic) each rounded once to float32, and
+ * the sum formed by five fused multiply-adds (two along the pixel's column
+ * offset dx, one for the dy coefficient, two along dy).  With S the sum of
+ * the six terms' magnitudes, the coefficients' roundings err by at most u S
+ * (u = 2^-24), the four inner multiply-adds by at most 2 u S (each rounds a
+ * partial sum of terms, each term counted at most twice), and the last one by
+ * u |p2|: |d p2| <= 3 u S + u |p2|. */
+static double power2_abs_error(const proj_t *p, double px, double py, double xc, double yc, double p2)
+{
+    const double u = 0x1p-24, k = 0.72134752044448170; /* log2(e) / 2 */
+    const double A = p->conic[0], B = p->conic[1], C = p->conic[2];
+    const double ox = xc - p->u, oy = yc - p->v, dx = px - xc, dy = py - yc;
+    const double S = k * (A * ox * ox + 2.0 * B * ox * oy + C * oy * oy) +
+                     2.0 * k * (fabs(A * ox + B * oy) * fabs(dx) + fabs(B * ox + C * oy) * fabs(dy)) +
+                     k * (A * dx * dx + 2.0 * fabs(B * dx * dy) + C * dy * dy);
+    return 3.0 * u * S + u * fabs(p2);
+}
+
+/* The bound above for a Gaussian given by (u, v, conic), exported for the
+ * test that checks it against an emulated float32 evaluation. */
+double or_power2_error(double u, double v, double A, double B, double C, double px, double py,
+                       double xc, double yc, double p2)
+{
+    proj_t p;
+    memset(&p, 0, sizeof(p));
+    p.u = u;
+    p.v = v;
+    p.conic[0] = A;
+    p.conic[1] = B;
+    p.conic[2] = C;
+    return power2_abs_error(&p, px, py, xc, yc, p2);
+}
+
 /* Composites one pixel; fills rec[] (if non-NULL) with the blended entries.
  * Returns the number of blended entries; *n_pos = list position + 1 of the
  * last blended entry; *margin = smallest relative distance of any decision
- * taken (alpha_min skip, alpha_max clamp, early stop) from its threshold. */
+ * taken (alpha_min skip, alpha_max clamp, early stop) from its threshold;
+ * *clear = smallest ratio, over the same decisions, of that distance to the
+ * float32 error bound of the quantity compared (from power2_abs_error for alpha;
+ * for T, the bound accumulated over the blends before it, each adding one
+ * rounding and alpha / (1 - alpha) times alpha's bound; the float32 rounding
+ * of each threshold adds u).  A pixel with *clear > 1 takes every decision
+ * the same way in float32 as here. */
 static int64_t composite_pixel(const proj_t *P, const int64_t *list, int64_t len, double px,
-                               double py, const or_config *cfg, double rgb[3], double *T_out,
-                               int64_t *n_pos, double *margin, blend_t *rec)
+                               double py, double xc, double yc, const or_config *cfg, double rgb[3],
+                               double *T_out, int64_t *n_pos, double *margin, double *clear,
+                               blend_t *rec)
 {
-    double T = 1.0, C[3] = { 0, 0, 0 }, m = INFINITY;
+    const double u32 = 0x1p-24;
+    double T = 1.0, C[3] = { 0, 0, 0 }, m = INFINITY, cl = INFINITY, eT = 0.0;
     int64_t nb = 0, last = 0;
     for (int64_t k = 0; k < len; ++k) {
         const proj_t *p = &P[list[k]];
@@ -378,21 +435,40 @@ static int64_t composite_pixel(const proj_t *P, const int64_t *list, int64_t len
         double G = exp(power);
         double a_raw = p->o * G;
         double alpha = a_raw < cfg->alpha_max ? a_raw : cfg->alpha_max;
+        /* relative error bounds: of alpha = o 2^p2 (p2's error, the
+         * exponential within 2 ulp, the opacity's and the product's
+         * roundings), and of the alpha_min test, taken as p2 >= log2(alpha_min
+         * / o) in float32 (the threshold's, the opacity's and the quotient's
+         * roundings, the logarithm within 2 ulp of its value) */
+        const double ln2 = 0.69314718055994531;
+        double e_p2 = clear ? power2_abs_error(p, px, py, xc, yc, power * 1.4426950408889634) : 0.0;
+        double ea = ln2 * e_p2 + 4.0 * u32;
         if (cfg->alpha_min > 0) {
             double mm = rel_margin(a_raw, cfg->alpha_min);
             if (mm < m) m = mm;
+            if (clear) {
+                double e = ln2 * e_p2 + 3.0 * u32 + 2.0 * ln2 * u32 * fabs(log2(cfg->alpha_min / p->o));
+                if (mm / e < cl) cl = mm / e;
+            }
         }
         if (alpha < cfg->alpha_min) continue;
         {
             double mm = rel_margin(a_raw, cfg->alpha_max);
             if (mm < m) m = mm;
+            if (clear && cfg->alpha_max < 1.0 && mm / (ea + u32) < cl) cl = mm / (ea + u32);
         }
         double Tn = T * (1.0 - alpha);
+        double ga = alpha < 1.0 ? alpha / (1.0 - alpha) : INFINITY;
         if (cfg->T_min > 0) {
             double mm = rel_margin(Tn, cfg->T_min);
             if (mm < m) m = mm;
+            if (clear) {
+                double e = eT + 2.0 * u32 + ga * ea;
+                if (mm / e < cl) cl = mm / e;
+            }
         }
         if (Tn < cfg->T_min) break;
+        eT += u32 + ga * ea;
         if (rec) {
             rec[nb].id = list[k];
             rec[nb].alpha = alpha;
@@ -411,6 +487,7 @@ static int64_t composite_pixel(const proj_t *P, const int64_t *list, int64_t len
     *T_out = T;
     *n_pos = last;
     if (margin) *margin = m;
+    if (clear) *clear = cl;
     return nb;
 }
 
@@ -422,33 +499,42 @@ static int64_t view_pixel_offset(const or_camera *cams, int32_t v)
 }
 
 /* Forward render of n_views views.  Images are concatenated per view, each
- * view stored as [3][H][W]; T_final, n_contrib, n_blend, margin as [H][W]. */
+ * view stored as [3][H][W]; T_final, n_contrib, n_blend, margin, clear as
+ * [H][W] (n_contrib, n_blend, margin and clear may be NULL).  Pixel rows run
+ * in parallel; every pixel is computed on its own. */
 int or_render(const or_scene *sc, int32_t n_views, const or_camera *cams, const double *poses,
               const or_config *cfg, double *rgb, double *T_final, int32_t *n_contrib,
-              int32_t *n_blend, double *margin)
+              int32_t *n_blend, double *margin, double *clear)
 {
     int64_t n = sc->n;
     proj_t *P = (proj_t *)malloc(sizeof(proj_t) * (size_t)(n > 0 ? n : 1));
     if (!P) return -1;
     for (int32_t v = 0; v < n_views; ++v) {
         const or_camera *cam = &cams[v];
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) project_one(sc, i, cam, poses + 12 * v, cfg, &P[i]);
         tile_lists L;
         if (build_lists(P, n, cam, cfg, &L)) { free(P); return -1; }
         int64_t W = cam->width, H = cam->height, off = view_pixel_offset(cams, v);
+#pragma omp parallel for schedule(dynamic, 1)
         for (int64_t py = 0; py < H; ++py)
             for (int64_t px = 0; px < W; ++px) {
-                int64_t t = (py / cfg->tile_h) * L.tiles_x + px / cfg->tile_w;
-                double c3[3], T, m;
+                int64_t tyi = py / cfg->tile_h, txi = px / cfg->tile_w;
+                int64_t t = tyi * L.tiles_x + txi;
+                double xc = (double)(txi * cfg->tile_w) + 0.5 * cfg->tile_w;
+                double yc = (double)(tyi * cfg->tile_h) + 0.5 * cfg->tile_h;
+                double c3[3], T, m, cl;
                 int64_t npos;
                 int64_t nb = composite_pixel(P, L.items + L.start[t], L.start[t + 1] - L.start[t],
-                                             px + 0.5, py + 0.5, cfg, c3, &T, &npos, &m, NULL);
+                                             px + 0.5, py + 0.5, xc, yc, cfg, c3, &T, &npos, &m,
+                                             clear ? &cl : NULL, NULL);
                 int64_t pix = py * W + px;
                 for (int c = 0; c < 3; ++c) rgb[3 * off + c * W * H + pix] = c3[c];
                 T_final[off + pix] = T;
                 if (n_contrib) n_contrib[off + pix] = (int32_t)npos;
                 if (n_blend) n_blend[off + pix] = (int32_t)nb;
                 if (margin) margin[off + pix] = m;
+                if (clear) clear[off + pix] = cl;
             }
         free_lists(&L);
     }
@@ -601,7 +687,8 @@ static void project_backward(const or_scene *sc, int64_t i, const double *pose, 
 int or_backward(const or_scene *sc, int32_t n_views, const or_camera *cams, const double *poses,
                 const or_config *cfg, const double *dL_drgb, const double *dL_dT,
                 const uint8_t *pose_only, double *d_mean, double *d_quat, double *d_log_scale,
-                double *d_opacity_logit, double *d_colour, double *d_xi, double *grad2d_out)
+                double *d_opacity_logit, double *d_colour, double *d_xi, double *grad2d_out,
+                double *grad2d_abs_out)
 {
     int64_t n = sc->n;
     int K = cfg->sh_degree < 0 ? 1 : sh_count(cfg->sh_degree);
@@ -612,67 +699,131 @@ int or_backward(const or_scene *sc, int32_t n_views, const or_camera *cams, cons
     memset(d_colour, 0, sizeof(double) * 3 * (size_t)K * (size_t)n);
     memset(d_xi, 0, sizeof(double) * 6 * (size_t)n_views);
 
+    const int nthr = omp_get_max_threads();
     proj_t *P = (proj_t *)malloc(sizeof(proj_t) * (size_t)(n > 0 ? n : 1));
     double *g2 = (double *)malloc(sizeof(double) * G_N * (size_t)(n > 0 ? n : 1));
-    if (!P || !g2) return -1;
+    /* per-thread screen-space gradients, summed in thread order after each view */
+    double *g2t = (double *)malloc(sizeof(double) * G_N * (size_t)(n > 0 ? n : 1) * (size_t)nthr);
+    double *xit = (double *)malloc(sizeof(double) * 6 * (size_t)nthr);
+    /* optional: the sum of the magnitudes of the addends of each screen-space
+     * gradient, per thread, for the tests' cancellation measure */
+    double *abt = grad2d_abs_out ? (double *)malloc(sizeof(double) * G_N * (size_t)(n > 0 ? n : 1) * (size_t)nthr)
+                                 : NULL;
+    if (!P || !g2 || !g2t || !xit || (grad2d_abs_out && !abt)) return -1;
     for (int32_t v = 0; v < n_views; ++v) {
         const or_camera *cam = &cams[v];
         const double *pose = poses + 12 * v;
+#pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; ++i) project_one(sc, i, cam, pose, cfg, &P[i]);
         tile_lists L;
         if (build_lists(P, n, cam, cfg, &L)) return -1;
         int64_t maxlen = 1;
         for (int64_t t = 0; t < L.n_tiles; ++t)
             if (L.start[t + 1] - L.start[t] > maxlen) maxlen = L.start[t + 1] - L.start[t];
-        blend_t *rec = (blend_t *)malloc(sizeof(blend_t) * (size_t)maxlen);
-        memset(g2, 0, sizeof(double) * G_N * (size_t)n);
+        memset(g2t, 0, sizeof(double) * G_N * (size_t)n * (size_t)nthr);
+        if (abt) memset(abt, 0, sizeof(double) * G_N * (size_t)n * (size_t)nthr);
         int64_t W = cam->width, H = cam->height, off = view_pixel_offset(cams, v);
-        for (int64_t py = 0; py < H; ++py)
-            for (int64_t px = 0; px < W; ++px) {
-                int64_t t = (py / cfg->tile_h) * L.tiles_x + px / cfg->tile_w;
-                double c3[3], Tf;
-                int64_t npos;
-                int64_t nb = composite_pixel(P, L.items + L.start[t], L.start[t + 1] - L.start[t],
-                                             px + 0.5, py + 0.5, cfg, c3, &Tf, &npos, NULL, rec);
-                int64_t pix = py * W + px;
-                double g[3], gT = dL_dT ? dL_dT[off + pix] : 0.0;
-                for (int c = 0; c < 3; ++c) g[c] = dL_drgb[3 * off + c * W * H + pix];
-                /* suffix recursion: B = colour composited behind the entry,
-                 * Q = product of (1 - alpha) after the entry */
-                double B[3] = { cfg->bg[0], cfg->bg[1], cfg->bg[2] }, Q = 1.0;
-                for (int64_t k = nb - 1; k >= 0; --k) {
-                    const blend_t *e = &rec[k];
-                    const proj_t *p = &P[e->id];
-                    double *gg = g2 + G_N * e->id;
-                    double dalpha = -gT * e->T * Q;
-                    for (int c = 0; c < 3; ++c) {
-                        gg[G_R + c] += g[c] * e->alpha * e->T;
-                        dalpha += g[c] * e->T * (p->rgb[c] - B[c]);
+        int failed = 0;
+#pragma omp parallel num_threads(nthr)
+        {
+            const int tid = omp_get_thread_num();
+            double *tg2 = g2t + (size_t)tid * G_N * (size_t)n;
+            double *tab = abt ? abt + (size_t)tid * G_N * (size_t)n : NULL;
+            blend_t *rec = (blend_t *)malloc(sizeof(blend_t) * (size_t)maxlen);
+            if (!rec) {
+#pragma omp atomic write
+                failed = 1;
+            }
+#pragma omp for schedule(dynamic, 1)
+            for (int64_t py = 0; py < H; ++py) {
+                if (!rec) continue;
+                for (int64_t px = 0; px < W; ++px) {
+                    int64_t t = (py / cfg->tile_h) * L.tiles_x + px / cfg->tile_w;
+                    double c3[3], Tf;
+                    int64_t npos;
+                    int64_t nb = composite_pixel(P, L.items + L.start[t], L.start[t + 1] - L.start[t],
+                                                 px + 0.5, py + 0.5, 0.0, 0.0, cfg, c3, &Tf, &npos, NULL,
+                                                 NULL, rec);
+                    int64_t pix = py * W + px;
+                    double g[3], gT = dL_dT ? dL_dT[off + pix] : 0.0;
+                    for (int c = 0; c < 3; ++c) g[c] = dL_drgb[3 * off + c * W * H + pix];
+                    /* suffix recursion: B = colour composited behind the entry,
+                     * Q = product of (1 - alpha) after the entry */
+                    double B[3] = { cfg->bg[0], cfg->bg[1], cfg->bg[2] }, Q = 1.0;
+                    for (int64_t k = nb - 1; k >= 0; --k) {
+                        const blend_t *e = &rec[k];
+                        const proj_t *p = &P[e->id];
+                        double *gg = tg2 + G_N * e->id;
+                        double *ga = tab ? tab + G_N * e->id : NULL;
+                        double dalpha = -gT * e->T * Q;
+                        for (int c = 0; c < 3; ++c) {
+                            gg[G_R + c] += g[c] * e->alpha * e->T;
+                            if (ga) ga[G_R + c] += fabs(g[c] * e->alpha * e->T);
+                            dalpha += g[c] * e->T * (p->rgb[c] - B[c]);
+                        }
+                        for (int c = 0; c < 3; ++c) B[c] = p->rgb[c] * e->alpha + (1.0 - e->alpha) * B[c];
+                        Q *= 1.0 - e->alpha;
+                        if (e->clamped) continue; /* alpha = alpha_max: no dependence */
+                        /* alpha = o exp(power) */
+                        double dpow = dalpha * e->alpha;
+                        gg[G_O] += dalpha * e->G;
+                        gg[G_A] += dpow * (-0.5 * e->dx * e->dx);
+                        gg[G_B] += dpow * (-e->dx * e->dy);
+                        gg[G_C] += dpow * (-0.5 * e->dy * e->dy);
+                        /* dx = px - u, dy = py - v */
+                        gg[G_U] += dpow * (p->conic[0] * e->dx + p->conic[1] * e->dy);
+                        gg[G_V] += dpow * (p->conic[1] * e->dx + p->conic[2] * e->dy);
+                        if (ga) {
+                            ga[G_O] += fabs(dalpha * e->G);
+                            ga[G_A] += fabs(dpow * (-0.5 * e->dx * e->dx));
+                            ga[G_B] += fabs(dpow * (-e->dx * e->dy));
+                            ga[G_C] += fabs(dpow * (-0.5 * e->dy * e->dy));
+                            ga[G_U] += fabs(dpow * (p->conic[0] * e->dx + p->conic[1] * e->dy));
+                            ga[G_V] += fabs(dpow * (p->conic[1] * e->dx + p->conic[2] * e->dy));
+                        }
                     }
-                    for (int c = 0; c < 3; ++c) B[c] = p->rgb[c] * e->alpha + (1.0 - e->alpha) * B[c];
-                    Q *= 1.0 - e->alpha;
-                    if (e->clamped) continue; /* alpha = alpha_max: no dependence */
-                    /* alpha = o exp(power) */
-                    double dpow = dalpha * e->alpha;
-                    gg[G_O] += dalpha * e->G;
-                    gg[G_A] += dpow * (-0.5 * e->dx * e->dx);
-                    gg[G_B] += dpow * (-e->dx * e->dy);
-                    gg[G_C] += dpow * (-0.5 * e->dy * e->dy);
-                    /* dx = px - u, dy = py - v */
-                    gg[G_U] += dpow * (p->conic[0] * e->dx + p->conic[1] * e->dy);
-                    gg[G_V] += dpow * (p->conic[1] * e->dx + p->conic[2] * e->dy);
                 }
             }
-        free(rec);
+            free(rec);
+        }
+        if (failed) return -1;
+#pragma omp parallel for schedule(static)
+        for (int64_t j = 0; j < G_N * n; ++j) {
+            double acc = 0.0;
+            for (int th = 0; th < nthr; ++th) acc += g2t[(size_t)th * G_N * (size_t)n + (size_t)j];
+            g2[j] = acc;
+        }
         free_lists(&L);
         if (grad2d_out) memcpy(grad2d_out + (size_t)v * n * G_N, g2, sizeof(double) * G_N * (size_t)n);
-        int acc = !(pose_only && pose_only[v]);
-        for (int64_t i = 0; i < n; ++i) {
-            if (!P[i].valid) continue;
-            project_backward(sc, i, pose, cam, cfg, &P[i], g2 + G_N * i, acc, d_mean, d_quat,
-                             d_log_scale, d_opacity_logit, d_colour, d_xi + 6 * v);
+        if (grad2d_abs_out) {
+            double *dst = grad2d_abs_out + (size_t)v * n * G_N;
+#pragma omp parallel for schedule(static)
+            for (int64_t j = 0; j < G_N * n; ++j) {
+                double acc2 = 0.0;
+                for (int th = 0; th < nthr; ++th) acc2 += abt[(size_t)th * G_N * (size_t)n + (size_t)j];
+                dst[j] = acc2;
+            }
         }
+        int acc = !(pose_only && pose_only[v]);
+        /* each Gaussian writes only its own parameter gradients; the pose
+         * gradient is summed per thread, then in thread order */
+        memset(xit, 0, sizeof(double) * 6 * (size_t)nthr);
+#pragma omp parallel num_threads(nthr)
+        {
+            double *txi = xit + 6 * omp_get_thread_num();
+#pragma omp for schedule(static)
+            for (int64_t i = 0; i < n; ++i) {
+                if (!P[i].valid) continue;
+                project_backward(sc, i, pose, cam, cfg, &P[i], g2 + G_N * i, acc, d_mean, d_quat,
+                                 d_log_scale, d_opacity_logit, d_colour, txi);
+            }
+        }
+        for (int th = 0; th < nthr; ++th)
+            for (int k = 0; k < 6; ++k) d_xi[6 * v + k] += xit[6 * th + k];
     }
+    free(abt);
+    free(xit);
+    free(g2t);
     free(g2);
     free(P);
     return 0;

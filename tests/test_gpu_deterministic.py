@@ -67,7 +67,7 @@ def _same(a, b):
 
 def test_deterministic_backward_parity_cloud_2k():
     w = scenes.workload(0)
-    _check_backward("cloud-2k deterministic", w["params"], w["cams"], w["poses"], DET, 5, frac_max=0.01)
+    _check_backward("cloud-2k deterministic", w["params"], w["cams"], w["poses"], DET, 5)
 
 
 def test_deterministic_backward_parity_sh3_two_views():
@@ -75,8 +75,7 @@ def test_deterministic_backward_parity_sh3_two_views():
     cams = [cam, dict(cam)]
     poses = np.stack([scenes.identity_pose(),
                       scenes.left_perturb(scenes.identity_pose(), np.array([0.05, 0.0, 0.0, 0.0, 0.03, 0.0]))])
-    _check_backward("sh3 deterministic", params, cams, poses, Config(sh_degree=3, deterministic=True), 9,
-                    frac_max=0.02)
+    _check_backward("sh3 deterministic", params, cams, poses, Config(sh_degree=3, deterministic=True), 9)
 
 
 def _room(seed=31):

@@ -12,20 +12,20 @@ The oracle works on the Gaussians whose FP64 extent reaches a crop (with
 alpha_min lowered a little); no other Gaussian can touch a crop pixel, so
 their GPU gradients must be exactly zero.
 
-Bars.  Images: 1e-4 on pixels whose FP64 decisions are clear of their
-thresholds (relative margin 1e-3); a pixel may differ only if it has a
-near-threshold decision.  Long lists (hundreds of blends per pixel) end near
-T_min on most pixels, so a few such pixels can differ.  Gradients: the
-pose twists within the per-element bar (1e-3 relative + 1e-5 of the tensor's
-largest value) plus the change of the FP64 gradient when alpha_min or T_min
-moves by a relative 2e-4 (the gradient jumps at those decision boundaries and
-FP32 can take decisions that close to them differently); the parameter
-gradients within the plain bar on at least 99.9 % of the elements and every
-element within 50 times bar plus band.  The exceptions are covariance
-gradients of Gaussians just past the near plane whose centres lie tens of
-thousands of pixels from the pixels they reach: their per-pixel partials
-carry weights of (2e4)^2 and of both signs, a cancellation that float32
-per-pixel arithmetic cannot resolve to 1e-3.
+Bars.  Images: 1e-4 on clear pixels (every compositing decision farther
+from its threshold than the float32 error bound of the compared quantity, the
+oracle's clear ratio > 1); a pixel may differ only if it is not clear, and
+unclear pixels stay below 1 % of a crop.  Gradients: the upstream gradient is
+also zero at unclear pixels, on both sides, so no decision float32 takes the
+other way reaches a gradient.  The pose twists must then meet the
+per-element bar (1e-3 relative + 1e-5 of the tensor's largest value) on
+every element.  The parameter gradients meet it on all but a few elements,
+bounded in number and in size: covariance gradients of Gaussians just past
+the near plane whose centres lie tens of thousands of pixels from the pixels
+they reach.  Their per-pixel partials carry weights of (2e4)^2 and of both
+signs, a cancellation that float32 per-pixel arithmetic cannot resolve to
+1e-3.  The caps are about ten times the measured share and twice the
+measured worst ratio.
 """
 import numpy as np
 import pytest
@@ -33,14 +33,19 @@ import torch
 
 import oracle
 from paper_2601_00705_amd import autotune, scenes
-from tests.helpers import IMG_ATOL, grad_violations, oracle_cfg, pixel_mask, to_dev
+from tests.helpers import IMG_ATOL, cancellation, check_grad, oracle_cfg, pixel_mask, to_dev
 
 pytestmark = pytest.mark.gpu
 
 if torch.cuda.is_available():
     from paper_2601_00705_amd.render import Config, Renderer, split_views
 
-DECISION_BAND = 2e-4
+# measured at the three workloads (share of parameter-gradient elements
+# outside the plain bar, and their worst ratio to it) and the caps
+# (seeded-500k and window-1M: none; track-map-3M: 0.0057 % of the elements,
+# worst 7.7 times the bar), each of a cancellation-limited Gaussian
+PARAM_FRAC_CAP = {2: 0.0, 3: 0.0, 4: 6e-4}
+PARAM_RATIO_CAP = {2: 1.0, 3: 1.0, 4: 16.0}
 GRAD_KEYS = ("mean", "quat", "log_scale", "opacity_logit", "colour")
 
 
@@ -61,11 +66,6 @@ def _reaching(params, ccams, poses, cfg):
         r = oracle.project(params, c, p, wide)
         keep |= (r["valid"] > 0) & (r["tx1"] >= r["tx0"]) & (r["ty1"] >= r["ty0"])
     return np.nonzero(keep)[0]
-
-
-def _oracle_cfg_shifted(cfg, da, dt):
-    return oracle_cfg(Config(tile_w=cfg.tile_w, tile_h=cfg.tile_h, sh_degree=cfg.sh_degree,
-                             alpha_min=cfg.alpha_min * (1 + da), T_min=cfg.T_min * (1 + dt)))
 
 
 @pytest.mark.parametrize("index,views,crop", [
@@ -109,17 +109,18 @@ def test_fullsize_sampled_crops(index, views, crop):
                              for v, (x0, y0) in zip(views, origins)])
     d_rgb = np.abs(got_rgb - ref["rgb"]).reshape(len(views), 3, hw).max(axis=1).reshape(-1)
     per_px = np.maximum(d_rgb, np.abs(got_T - ref["T_final"]))
-    ok = pixel_mask(ref["margin"], ccams)
+    ok = pixel_mask(ref["clear"], ccams)
     flipped = (per_px > IMG_ATOL) | (got_nb != ref["n_blend"])
-    say(f"  max|d| on clear pixels={per_px[ok].max():.3g}; near-threshold pixels {1 - ok.mean():.2%}; "
+    say(f"  max|d| on clear pixels={per_px[ok].max():.3g}; unclear pixels {1 - ok.mean():.4%}; "
         f"pixels differing {flipped.mean():.4%} (max |d| {per_px.max():.3g}); blends {int(ref['n_blend'].sum())}")
     assert int(ref["n_blend"].sum()) > 0
     assert not np.any(flipped & ok), "a pixel with clear decisions differs"
-    assert flipped.mean() <= 0.02
+    assert 1 - ok.mean() <= 0.01
 
     # ---- backward seeded inside the crops only
     dL = np.zeros(3 * R.total_pixels, np.float32)
     dL_crops = scenes.upstream_grad(7 + index, 3 * hw * len(views)).astype(np.float32)
+    dL_crops *= pixel_mask(ref["clear"], ccams, 3)   # nothing from unclear pixels
     pix_base = np.cumsum([0] + [c["width"] * c["height"] for c in cams])
     for k, (v, (x0, y0)) in enumerate(zip(views, origins)):
         W, H = cams[v]["width"], cams[v]["height"]
@@ -132,12 +133,8 @@ def test_fullsize_sampled_crops(index, views, crop):
     torch.cuda.synchronize()
     po = np.asarray(w["pose_only"])[views]
     dLc = dL_crops.astype(np.float64)
-    gref = oracle.backward(sub, ccams, cposes, oracle_cfg(cfg), dLc, None, pose_only=po)
-    spread = {k: np.zeros_like(gref[k]) for k in gref}
-    for da, dt in ((DECISION_BAND, 0.0), (-DECISION_BAND, 0.0), (0.0, DECISION_BAND), (0.0, -DECISION_BAND)):
-        gs = oracle.backward(sub, ccams, cposes, _oracle_cfg_shifted(cfg, da, dt), dLc, None, pose_only=po)
-        for k in spread:
-            spread[k] += np.abs(gs[k] - gref[k])
+    gref = oracle.backward(sub, ccams, cposes, oracle_cfg(cfg), dLc, None, pose_only=po, want_grad2d=True)
+    kappa = cancellation(gref["grad2d"], gref["grad2d_abs"])
     say("  oracle backward done")
 
     xi = d_xi.cpu().numpy()
@@ -165,17 +162,12 @@ def test_fullsize_sampled_crops(index, views, crop):
             if not (np.abs(g).max() <= 1e-4 * scale and np.abs(gref[k]).max() <= 1e-6 * scale):
                 failures.append(k)
             continue
-        frac, ratio = grad_violations(g, gref[k])
-        ref_k = gref[k].ravel()
-        tol = 1e-3 * np.abs(ref_k) + 1e-5 * max(np.abs(ref_k).max(), 1e-30) + spread[k].ravel()
-        err = np.abs(g.ravel() - ref_k)
-        beyond = float(np.mean(err > tol))
-        say(f"  {k}: plain bar violated by {frac:.4%} (worst {ratio:.3g}); "
-            f"beyond bar + decision band: {beyond:.4%} (worst {float(np.max(err / tol)):.3g})")
-        if k == "xi":
-            ok_k = beyond == 0.0
-        else:
-            ok_k = frac <= 1e-3 and float(np.max(err / tol)) <= 50.0
-        if not ok_k:
+        try:
+            if k == "xi":
+                check_grad(k, g, gref[k], say=say)
+            else:
+                check_grad(k, g, gref[k], kappa, PARAM_FRAC_CAP[index], PARAM_RATIO_CAP[index], say=say)
+        except AssertionError as e:
+            say(f"  {k}: {e}")
             failures.append(k)
     assert not failures, failures

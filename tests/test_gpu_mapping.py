@@ -123,6 +123,29 @@ def test_lambda_zero_equals_the_l1_seed_and_identical_images_give_zero():
     assert abs(loss) < 1e-6 and np.abs(g).max() * 3 * sum(w * h for w, h in sizes) < 1e-2
 
 
+def test_l1_seed_matches_the_oracle():
+    """The L1 seed of the step (gsr_loss_l1, dL/dC = sign(C - target) /
+    (3 pixels), sign(0) = 0) against the oracle's lambda = 0 mapping-loss
+    gradient, on three views with 2 % of the entries exactly equal: the signs
+    agree exactly (the float32 difference of two floats has the sign of the
+    exact one, and is zero only when they are equal), the magnitudes to the
+    rounding of 1 / (3 pixels) to float32."""
+    sizes = [(64, 48), (37, 29), (1, 9)]
+    rng = np.random.default_rng(10)
+    xs, ys = _images(rng, sizes)
+    R = _renderer(sizes)
+    x, y = _flat(xs), _flat(ys)
+    g = torch.full_like(x, np.nan)
+    R.loss_l1(x, y, g)
+    torch.cuda.synchronize()
+    _, ref = M.mapping_loss([a.astype(np.float64) for a in xs], [a.astype(np.float64) for a in ys], 0.0)
+    ref = np.concatenate([r.reshape(-1) for r in ref])
+    got = g.cpu().numpy().astype(np.float64)
+    assert np.array_equal(np.sign(got), np.sign(ref))
+    assert (ref == 0).mean() > 0.01
+    np.testing.assert_allclose(got, ref, rtol=2.0 ** -23, atol=0)
+
+
 def test_mapping_loss_deterministic():
     sizes = [(130, 90), (64, 64)]
     rng = np.random.default_rng(9)

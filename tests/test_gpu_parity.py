@@ -2,9 +2,12 @@
 
 Bar: binning and sort bit-exact on shared float32 records; images within
 1e-4 absolute; gradients within 1e-3 relative per element (plus a floor of
-1e-5 of the tensor's largest magnitude).  Pixels whose compositing
-decisions lie within 1e-3 (relative) of a threshold in the FP64 oracle are
-excluded from the strict image check and counted.
+1e-5 of the tensor's largest magnitude), on every element.  Pixels with a
+compositing decision closer to its threshold than the float32 error bound of
+the compared quantity (oracle "clear" ratio <= 1) are excluded from the
+strict image check and counted; the backward tests give such pixels a zero
+upstream gradient on both sides, so that no decision taken the other way in
+float32 reaches a gradient.
 """
 import math
 
@@ -14,7 +17,8 @@ import torch
 
 import oracle
 from paper_2601_00705_amd import scenes
-from tests.helpers import (IMG_ATOL, MARGIN, grad_violations, oracle_cfg, pixel_mask, to_dev)
+from tests.helpers import (IMG_ATOL, cancellation, check_grad, grad_violations, oracle_cfg, pixel_mask,
+                           to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -37,14 +41,15 @@ def _gpu_fwd(params, cams, poses, cfg, capacity=None, want_blend=True):
 
 
 def _check_forward(name, params, cams, poses, cfg, capacity=None):
-    """Strict 1e-4 on pixels whose FP64 decisions are clear of their
-    thresholds; elsewhere a pixel may differ only if the oracle records a
-    near-threshold decision for it, and such pixels stay rare."""
+    """Strict 1e-4 on clear pixels (every decision farther from its
+    threshold than float32 can err); elsewhere a pixel may differ only if
+    the oracle records a decision within that bound, and such pixels stay
+    rare (at most 0.1 %)."""
     say(f"[fwd] {name}: n={params['opacity_logit'].shape[0]} views={len(cams)}")
     poses = np.asarray(poses, dtype=np.float32)  # the oracle sees the poses the GPU sees
     R, P, poses_d, rgb, T, nc, nb = _gpu_fwd(params, cams, poses, cfg, capacity)
     ref = oracle.render(params, cams, poses, oracle_cfg(cfg))
-    ok = pixel_mask(ref["margin"], cams)
+    ok = pixel_mask(ref["clear"], cams)
     rgb_g = rgb.cpu().numpy().astype(np.float64)
     T_g = T.cpu().numpy().astype(np.float64)
     nb_g = nb.cpu().numpy()
@@ -58,10 +63,10 @@ def _check_forward(name, params, cams, poses, cfg, capacity=None):
         off += hw
     per_px = np.maximum(per_px, np.abs(T_g - ref["T_final"]))
     flipped = (per_px > IMG_ATOL) | (nb_g != ref["n_blend"])
-    say(f"  max|d| on clear pixels={per_px[ok].max() if ok.any() else 0:.3g}; near-threshold pixels "
-        f"{1 - ok.mean():.2%}; pixels differing {flipped.mean():.4%} (max {per_px.max():.3g})")
+    say(f"  max|d| on clear pixels={per_px[ok].max() if ok.any() else 0:.3g}; unclear pixels "
+        f"{1 - ok.mean():.4%}; pixels differing {flipped.mean():.4%} (max {per_px.max():.3g})")
     assert not np.any(flipped & ok), "a pixel with clear decisions differs"
-    assert flipped.mean() <= 1e-3
+    assert 1 - ok.mean() <= 1e-3 and flipped.mean() <= 1e-3
     return R, P, poses_d, rgb, T, nc, ref, ok
 
 
@@ -398,13 +403,32 @@ def test_forward_identical_across_batches_and_tiles():
 
 
 # --------------------------------------------------------------------------
-def _check_backward(name, params, cams, poses, cfg, seed, pose_only=None, with_dT=False, frac_max=0.0):
+def _masked_upstream(ref_fwd, cams, dL, dT):
+    """Zero the upstream gradient at pixels that are not clear, on both
+    sides: with dL/dC = 0 and dL/dT_final = 0 a pixel adds nothing to any
+    gradient, so a decision float32 may take the other way there cannot
+    reach the comparison.  Returns the masked copies and the masked share."""
+    ok = ref_fwd["clear"] > 1.0
+    dL = dL * pixel_mask(ref_fwd["clear"], cams, 3)
+    dT = None if dT is None else dT * ok
+    return dL.astype(np.float32), None if dT is None else dT.astype(np.float32), float(1 - ok.mean())
+
+
+def _check_backward(name, params, cams, poses, cfg, seed, pose_only=None, with_dT=False, caps=(0.0, 1.0)):
+    """Every element of d_xi, and of every parameter gradient, within the bar
+    (1e-3 relative + 1e-5 of the tensor's largest magnitude), with unclear
+    pixels' upstream gradient zeroed on both sides; caps = (share, ratio)
+    admits that many parameter-gradient elements of cancellation-limited
+    Gaussians (see tests.helpers.check_grad) up to that ratio to the bar."""
     say(f"[bwd] {name}")
     poses = np.asarray(poses, dtype=np.float32)  # the oracle sees the poses the GPU sees
     R, P, poses_d, rgb, T, nc, nb = _gpu_fwd(params, cams, poses, cfg)
     Ptot = sum(c["width"] * c["height"] for c in cams)
-    dL = scenes.upstream_grad(seed, 3 * Ptot)
-    dT = scenes.upstream_grad(seed + 1, Ptot) if with_dT else None
+    ref_fwd = oracle.render(params, cams, poses, oracle_cfg(cfg))
+    dL, dT, masked = _masked_upstream(ref_fwd, cams, scenes.upstream_grad(seed, 3 * Ptot),
+                                      scenes.upstream_grad(seed + 1, Ptot) if with_dT else None)
+    say(f"  upstream gradient zeroed at {masked:.4%} of the pixels (unclear)")
+    assert masked <= 1e-3
     grads = {k: torch.empty_like(v) for k, v in P.items()}
     d_xi = torch.empty(len(cams), 6, device="cuda")
     dL_d = torch.from_numpy(dL).cuda()
@@ -420,34 +444,22 @@ def _check_backward(name, params, cams, poses, cfg, seed, pose_only=None, with_d
         assert float((grads2[k] - grads[k]).abs().max()) <= 1e-5 * scale, k
     assert float((d_xi2 - d_xi).abs().max()) <= 1e-5 * (float(d_xi.abs().max()) + 1e-30)
     ref = oracle.backward(params, cams, poses, oracle_cfg(cfg), dL.astype(np.float64),
-                          None if dT is None else dT.astype(np.float64), pose_only=pose_only)
+                          None if dT is None else dT.astype(np.float64), pose_only=pose_only, want_grad2d=True)
+    kappa = cancellation(ref["grad2d"], ref["grad2d_abs"])
     worst = {}
-    for k in ("mean", "quat", "log_scale", "opacity_logit", "colour", "xi"):
-        g = (d_xi if k == "xi" else grads[k]).cpu().numpy()
-        frac, ratio = grad_violations(g, ref[k])
-        worst[k] = (frac, ratio)
-        say(f"  {k}: violating={frac:.3%} worst={ratio:.3g}")
-        assert np.all(np.isfinite(g))
-    for k, (frac, ratio) in worst.items():
-        assert frac <= frac_max, (k, frac, ratio)
+    for k in ("mean", "quat", "log_scale", "opacity_logit", "colour"):
+        worst[k] = check_grad(k, grads[k].cpu().numpy(), ref[k], kappa, *caps, say=say)
+    worst["xi"] = check_grad("xi", d_xi.cpu().numpy(), ref["xi"], say=say)
     return worst
-
-
-def _min_margin(params, cams, poses, cfg):
-    poses = np.asarray(poses, dtype=np.float32)
-    return float(np.min(oracle.render(params, cams, poses, oracle_cfg(cfg))["margin"]))
 
 
 @pytest.mark.parametrize("seed", [201, 202, 203])
 def test_backward_parity_small_scenes(seed):
-    """All parameter gradients and the pose twist on small scenes whose
-    compositing decisions are far from their thresholds (strict bar)."""
+    """All parameter gradients and the pose twist on small scenes, with an
+    upstream gradient on T_final too."""
     params, cam = scenes.cloud(seed, 60, 48, 40, 40.0)
     pose = scenes.left_perturb(scenes.identity_pose(), np.array([0.03, -0.02, 0.05, 0.04, -0.03, 0.02]))
-    cfg = Config()
-    assert _min_margin(params, [cam], pose[None], cfg) > MARGIN or True
-    _check_backward(f"small{seed}", params, [cam], pose[None], cfg, seed, with_dT=True,
-                    frac_max=0.0 if _min_margin(params, [cam], pose[None], cfg) > MARGIN else 0.02)
+    _check_backward(f"small{seed}", params, [cam], pose[None], Config(), seed, with_dT=True)
 
 
 def test_backward_parity_smooth_setting():
@@ -463,14 +475,13 @@ def test_backward_parity_512_pixel_tiles():
     """Eight pixels per lane (32x16 and 16x32 tiles)."""
     w = scenes.workload(0)
     for tw, th in ((32, 16), (16, 32)):
-        _check_backward(f"cloud-2k {tw}x{th}", w["params"], w["cams"], w["poses"], Config(tile_w=tw, tile_h=th), 5,
-                        frac_max=0.01)
+        _check_backward(f"cloud-2k {tw}x{th}", w["params"], w["cams"], w["poses"], Config(tile_w=tw, tile_h=th), 5)
 
 
 def test_backward_parity_cloud_2k():
     """The 2,000-Gaussian scene with an L1-shaped upstream gradient."""
     w = scenes.workload(0)
-    _check_backward("cloud-2k", w["params"], w["cams"], w["poses"], Config(), 5, frac_max=0.01)
+    _check_backward("cloud-2k", w["params"], w["cams"], w["poses"], Config(), 5)
 
 
 def test_backward_parity_sh3_pose_only():
@@ -481,14 +492,15 @@ def test_backward_parity_sh3_pose_only():
         scenes.left_perturb(scenes.identity_pose(), np.array([0.03, -0.02, 0.05, 0.04, -0.03, 0.02])),
         scenes.left_perturb(scenes.identity_pose(), np.array([-0.1, 0.05, 0.0, -0.02, 0.06, 0.03]))])
     cfg = Config(sh_degree=3, bg=(0.1, 0.2, 0.3))
-    _check_backward("sh3", params, cams, poses, cfg, 9, pose_only=np.array([0, 1], np.uint8), with_dT=True,
-                    frac_max=0.01)
+    _check_backward("sh3", params, cams, poses, cfg, 9, pose_only=np.array([0, 1], np.uint8), with_dT=True)
 
 
 def test_backward_parity_room_100k():
-    """The 100k-Gaussian 640x480 view including the 6-DoF pose twist."""
+    """The 100k-Gaussian 640x480 view including the 6-DoF pose twist.
+    Measured: one log-scale element of 300,000 at 1.11 times the bar, of a
+    cancellation-limited Gaussian; admitted: 10 such elements up to 2.2."""
     w = scenes.workload(1)
-    _check_backward("room-100k", w["params"], w["cams"], w["poses"], Config(), 21, frac_max=0.01)
+    _check_backward("room-100k", w["params"], w["cams"], w["poses"], Config(), 21, caps=(3.3e-5, 2.2))
 
 
 def test_autograd_backward_after_a_second_forward():
@@ -516,8 +528,11 @@ def test_autograd_backward_after_a_second_forward():
     P2 = {k: v.clone().requires_grad_(True) for k, v in to_dev(sub).items()}
     rgb2, _, _ = render(R, P2, torch.from_numpy(pose2[None].astype(np.float32)).cuda())
     assert R.generation != gen1
-    w = torch.from_numpy(scenes.upstream_grad(3, rgb1.numel())).cuda()
-    wT = torch.from_numpy(scenes.upstream_grad(4, T1.numel())).cuda()
+    ref_fwd = oracle.render(params1, [cam], pose1[None].astype(np.float32), oracle_cfg(cfg))
+    w_np, wT_np, masked = _masked_upstream(ref_fwd, [cam], scenes.upstream_grad(3, rgb1.numel()),
+                                           scenes.upstream_grad(4, T1.numel()))
+    assert masked <= 1e-3
+    w, wT = torch.from_numpy(w_np).cuda(), torch.from_numpy(wT_np).cuda()
     ((rgb1 * w).sum() + (T1 * wT).sum()).backward()
     ref = oracle.backward(params1, [cam], pose1[None].astype(np.float32), oracle_cfg(cfg),
                           w.cpu().double().numpy(), wT.cpu().double().numpy())
@@ -540,15 +555,18 @@ def test_autograd_function_matches_oracle():
     xi = torch.zeros(1, 6, device="cuda", requires_grad=True)
     poses = torch.from_numpy(pose[None].astype(np.float32)).cuda()
     rgb, T, nc = render(R, P, poses, xi)
-    w = torch.from_numpy(scenes.upstream_grad(1, rgb.numel())).cuda()
-    wT = torch.from_numpy(scenes.upstream_grad(2, T.numel())).cuda()
+    ref_fwd = oracle.render(params, [cam], pose[None].astype(np.float32), oracle_cfg(cfg))
+    w_np, wT_np, masked = _masked_upstream(ref_fwd, [cam], scenes.upstream_grad(1, rgb.numel()),
+                                           scenes.upstream_grad(2, T.numel()))
+    assert masked <= 1e-3
+    w, wT = torch.from_numpy(w_np).cuda(), torch.from_numpy(wT_np).cuda()
     loss = (rgb * w).sum() + (T * wT).sum()
     loss.backward()
     ref = oracle.backward(params, [cam], pose[None].astype(np.float32), oracle_cfg(cfg), w.cpu().double().numpy(),
                           wT.cpu().double().numpy())
     for k in ("mean", "quat", "log_scale", "opacity_logit", "colour"):
         frac, ratio = grad_violations(P[k].grad.cpu().numpy(), ref[k])
-        assert frac <= 0.02, (k, frac, ratio)
+        assert frac == 0.0, (k, frac, ratio)
     frac, ratio = grad_violations(xi.grad.cpu().numpy(), ref["xi"])
     assert frac == 0.0, ratio
     # first-order check of the pose twist in FP32 on the GPU itself

@@ -169,6 +169,9 @@ def test_track_seeds_backward_end_to_end():
     torch.cuda.synchronize()
 
     ref = oracle.render(params, cams, poses, oracle_cfg(cfg))
+    # every pixel of this scene takes its compositing decisions the same way
+    # in float32 (clear ratio above 1), so the strict bar applies throughout
+    assert ref["clear"].min() > 1.0
     r_loss, r_expo, r_dI, r_dT = oracle.track_loss(ref["rgb"], ref["T_final"], target, cams, TA, TG)
     assert np.allclose(loss.cpu().numpy(), r_loss, rtol=1e-4)
     assert np.allclose(expo.cpu().numpy(), r_expo, rtol=1e-5, atol=1e-6)
@@ -178,4 +181,4 @@ def test_track_seeds_backward_end_to_end():
         frac, ratio = grad_violations(g, gref[k])
         say(f"  {k}: violating={frac:.3%} worst={ratio:.3g}")
         assert np.all(np.isfinite(g))
-        assert frac <= 0.02, (k, frac, ratio)
+        assert frac == 0.0, (k, frac, ratio)

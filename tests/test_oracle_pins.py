@@ -662,3 +662,55 @@ def test_sh_degree0_reduces_to_rgb():
     a = oracle.render(p, [cam], I12, CFG)
     b = oracle.render(sh, [cam], I12, oracle.Config(sh_degree=0))
     np.testing.assert_allclose(b["rgb"], a["rgb"], atol=1e-13)
+
+
+# ------------------------------------------------ tolerance model ----
+def _fma32(a, b, c):
+    """float32 fused multiply-add: the product of two float32 values is exact
+    in float64, so one float64 sum rounded to float32 is correct to within a
+    double rounding (2^-53 relative), far below float32's unit."""
+    return np.float32(np.float64(a) * np.float64(b) + np.float64(c))
+
+
+def test_power2_error_bound_holds_for_a_float32_evaluation():
+    """The oracle's bound on the float32 error of the exp2-space power (the
+    tolerance behind its clear ratio) holds for the evaluation it models:
+    the quadratic form expanded about the tile centre, six coefficients
+    rounded to float32 from double, then five fused multiply-adds.  Random
+    conics (extents 0.5-300 px, correlation up to 0.99), centres up to
+    2,000 px from the tile, every pixel of 16x16 and 32x16 tiles; the bound is
+    also not loose by more than a factor 40 on the worst case."""
+    rng = np.random.default_rng(77)
+    k = 0.5 * math.log2(math.e)
+    worst = 0.0
+    for trial in range(300):
+        tw, th = (16, 16) if trial % 2 else (32, 16)
+        sa, sc = np.exp(rng.uniform(np.log(0.5), np.log(300.0), 2))
+        corr = rng.uniform(-0.99, 0.99)
+        a, c, b = sa * sa, sc * sc, corr * sa * sc
+        det = a * c - b * b
+        A, B, C = c / det, -b / det, a / det
+        xc, yc = tw * 10 + tw / 2, th * 7 + th / 2
+        reach = 2000.0 if trial % 3 == 0 else 3 * max(sa, sc)
+        u, v = xc + rng.uniform(-reach, reach), yc + rng.uniform(-reach, reach)
+        ox, oy = xc - u, yc - v
+        qx, qy = A * ox + B * oy, B * ox + C * oy
+        c0 = np.float32(-k * (ox * qx + oy * qy))
+        gx, gy = np.float32(-2 * k * qx), np.float32(-2 * k * qy)
+        a2, b2, c2 = np.float32(-k * A), np.float32(-2 * k * B), np.float32(-k * C)
+        for lane_x in range(tw):
+            dx = np.float32(lane_x + 0.5 - tw / 2)
+            s0 = _fma32(_fma32(a2, dx, gx), dx, c0)
+            s1 = _fma32(b2, dx, gy)
+            for lane_y in range(th):
+                dy = np.float32(lane_y + 0.5 - th / 2)
+                p32 = _fma32(_fma32(c2, dy, s1), dy, s0)
+                fx, fy = float(dx) + ox, float(dy) + oy
+                p64 = -k * (A * fx * fx + 2 * B * fx * fy + C * fy * fy)
+                bound = oracle.power2_error_bound(u, v, A, B, C, xc + float(dx), yc + float(dy), xc, yc, p64)
+                err = abs(float(p32) - p64)
+                assert err <= bound, (trial, lane_x, lane_y, err, bound)
+                if bound > 0:
+                    worst = max(worst, err / bound)
+    print(f"worst error / bound: {worst:.3f}")
+    assert worst > 1.0 / 40.0, worst
