@@ -73,6 +73,7 @@ extern "C" {
 #endif
 
 #define GSR_MAX_VIEWS 64
+#define GSR_MAX_DEVICES 64   /* device indices the no-allocation entry point serves */
 
 typedef enum {
     GSR_OK = 0,
@@ -432,6 +433,22 @@ size_t gsr_prune_workspace_bytes(int64_t n);
 gsr_status gsr_prune(int64_t n, const int32_t *m_obs, const float *v_vis, const float *log_scale,
                      const float *opacity_logit, const gsr_prune_config *cfg, int32_t *keep_index, int64_t *kept,
                      void *workspace, void *stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): gsr_prune
+ * without a workspace.  Same rule, arguments, outputs and errors as
+ * gsr_prune; the pruning scan keeps its per-block counts in a fixed device
+ * array of the library (256 KiB, one per GPU, held until the process ends)
+ * instead, so the call allocates nothing.  n may not exceed
+ * GSR_PRUNE_NOALLOC_MAX_N (2^27): larger n returns GSR_EINVAL with nothing
+ * enqueued.  All calls on one GPU share that array: calls that overlap on one
+ * GPU (different streams or threads) race and must be ordered by the
+ * caller.  The first call on each device looks up the array's address there
+ * (hipGetSymbolAddress) with that device current. */
+#define GSR_PRUNE_NOALLOC_MAX_N (1ll << 27)
+gsr_status gsr_prune_noalloc(int64_t n, const int32_t *m_obs, const float *v_vis, const float *log_scale,
+                             const float *opacity_logit, const gsr_prune_config *cfg, int32_t *keep_index,
+                             int64_t *kept, void *stream);
 
 /* Compaction after gsr_prune: dst[r][j] = src[r][keep_index[j]] for
  * j < *kept (device value), r < rows; src and dst [rows][n] (device, not

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -1011,16 +1012,12 @@ extern "C" size_t gsr_prune_workspace_bytes(int64_t n)
     return sizeof(uint32_t) * (size_t)((n + GSR_PRUNE_CHUNK - 1) / GSR_PRUNE_CHUNK + 1);
 }
 
-extern "C" gsr_status gsr_prune(int64_t n, const int32_t* m_obs, const float* v_vis, const float* log_scale,
-                                const float* opacity_logit, const gsr_prune_config* cfg, int32_t* keep_index,
-                                int64_t* kept, void* workspace, void* stream)
+// the pruning scan over a given block-count buffer (the caller's workspace
+// or the no-allocation scratch); arguments already hold n in range
+static gsr_status prune_run(int64_t n, const int32_t* m_obs, const float* v_vis, const float* log_scale,
+                            const float* opacity_logit, const gsr_prune_config* cfg, int32_t* keep_index,
+                            int64_t* kept, uint32_t* block_count, void* stream, const char* where)
 {
-    g_err.clear();
-    if (!m_obs || !v_vis || !log_scale || !opacity_logit || !cfg || !keep_index || !kept || !workspace)
-        return fail(GSR_EINVAL, "null argument");
-    if (n <= 0 || n > (1ll << 31) - 1) return fail(GSR_EINVAL, "n must lie in [1, 2^31)");
-    if (!std::isfinite(cfg->v_min) || !std::isfinite(cfg->sigma_max) || !std::isfinite(cfg->alpha_min))
-        return fail(GSR_EINVAL, "prune settings");
     PruneArgs a{};
     a.n = n;
     a.blocks = (int32_t)((n + GSR_PRUNE_CHUNK - 1) / GSR_PRUNE_CHUNK);
@@ -1032,11 +1029,84 @@ extern "C" gsr_status gsr_prune(int64_t n, const int32_t* m_obs, const float* v_
     a.v_min = cfg->v_min;
     a.sigma_max2 = (double)cfg->sigma_max * (double)cfg->sigma_max;
     a.alpha_min = cfg->alpha_min;
-    a.block_count = (uint32_t*)workspace;
+    a.block_count = block_count;
     a.keep_index = keep_index;
     a.kept = (long long*)kept;
     hipError_t e = launch_prune(a, (hipStream_t)stream);
-    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_prune");
+    return e == hipSuccess ? GSR_OK : hip_fail(e, where);
+}
+
+static gsr_status prune_args_ok(int64_t n, const int32_t* m_obs, const float* v_vis, const float* log_scale,
+                                const float* opacity_logit, const gsr_prune_config* cfg, const int32_t* keep_index,
+                                const int64_t* kept)
+{
+    if (!m_obs || !v_vis || !log_scale || !opacity_logit || !cfg || !keep_index || !kept)
+        return fail(GSR_EINVAL, "null argument");
+    if (n <= 0 || n > (1ll << 31) - 1) return fail(GSR_EINVAL, "n must lie in [1, 2^31)");
+    if (!std::isfinite(cfg->v_min) || !std::isfinite(cfg->sigma_max) || !std::isfinite(cfg->alpha_min))
+        return fail(GSR_EINVAL, "prune settings");
+    return GSR_OK;
+}
+
+extern "C" gsr_status gsr_prune(int64_t n, const int32_t* m_obs, const float* v_vis, const float* log_scale,
+                                const float* opacity_logit, const gsr_prune_config* cfg, int32_t* keep_index,
+                                int64_t* kept, void* workspace, void* stream)
+{
+    g_err.clear();
+    gsr_status st = prune_args_ok(n, m_obs, v_vis, log_scale, opacity_logit, cfg, keep_index, kept);
+    if (st != GSR_OK) return st;
+    if (!workspace) return fail(GSR_EINVAL, "null argument");
+    return prune_run(n, m_obs, v_vis, log_scale, opacity_logit, cfg, keep_index, kept, (uint32_t*)workspace,
+                     stream, "gsr_prune");
+}
+
+// ---- pruning without allocation --------------------------------------------
+// The block counts of the pruning scan live in this file-scope device array
+// (one copy per GPU, held until the process ends) instead of a caller
+// workspace.  Host code never passes `scratch` itself to a kernel: its name
+// on the host is a stand-in, not a device address.  The address on each
+// device is taken once, with that device current, by hipGetSymbolAddress,
+// and used from then on.  Every call on one GPU shares the array: calls that
+// overlap on one GPU (two streams, two threads) race.  The scan writes every
+// count it later reads, so nothing needs clearing between calls.
+static __device__ __align__(256) uint32_t scratch[(GSR_PRUNE_NOALLOC_MAX_N + GSR_PRUNE_CHUNK - 1) / GSR_PRUNE_CHUNK + 1];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[GSR_MAX_DEVICES];
+
+static gsr_status scratch_address(uint32_t** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "gsr_prune_noalloc: hipGetDevice");
+    if (dev < 0 || dev >= GSR_MAX_DEVICES) return fail(GSR_EUNSUPPORTED, "gsr_prune_noalloc: device index too large");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "gsr_prune_noalloc: hipGetSymbolAddress");
+        if (!ptr) return fail(GSR_EHIP, "gsr_prune_noalloc: null scratch address");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = (uint32_t*)g_scratch_ptr[dev];
+    return GSR_OK;
+}
+
+extern "C" gsr_status gsr_prune_noalloc(int64_t n, const int32_t* m_obs, const float* v_vis, const float* log_scale,
+                                        const float* opacity_logit, const gsr_prune_config* cfg, int32_t* keep_index,
+                                        int64_t* kept, void* stream)
+{
+    g_err.clear();
+    gsr_status st = prune_args_ok(n, m_obs, v_vis, log_scale, opacity_logit, cfg, keep_index, kept);
+    if (st != GSR_OK) return st;
+    if (n > GSR_PRUNE_NOALLOC_MAX_N)
+        return fail(GSR_EINVAL, "gsr_prune_noalloc: n exceeds GSR_PRUNE_NOALLOC_MAX_N (2^27 Gaussians), the size "
+                                "its fixed device scratch covers; use gsr_prune with a workspace");
+    uint32_t* block_count = nullptr;
+    st = scratch_address(&block_count);
+    if (st != GSR_OK) return st;
+    return prune_run(n, m_obs, v_vis, log_scale, opacity_logit, cfg, keep_index, kept, block_count, stream,
+                     "gsr_prune_noalloc");
 }
 
 extern "C" gsr_status gsr_compact(int64_t n, int32_t rows, const float* src, const int32_t* keep_index,

@@ -119,6 +119,7 @@ def _load():
         "gsr_covis": (st, [ctypes.c_int64, ctypes.c_int32, P, P, ctypes.c_float, P, P, P]),
         "gsr_prune_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
         "gsr_prune": (st, [ctypes.c_int64, P, P, P, P, P, P, P, P, P]),
+        "gsr_prune_noalloc": (st, [ctypes.c_int64, P, P, P, P, P, P, P, P]),
         "gsr_compact": (st, [ctypes.c_int64, ctypes.c_int32, P, P, P, P, P]),
         "gsr_seed_frame": (st, [ctypes.c_int64, P, P, P, P, P, P, ctypes.c_double, ctypes.c_double, ctypes.c_float,
                                 P, ctypes.c_size_t, P, P, P]),
@@ -144,7 +145,7 @@ EXPORTS = ("gsr_plan_create", "gsr_plan_destroy", "gsr_plan_workspace_bytes", "g
            "gsr_loss_l1", "gsr_loss_track", "gsr_loss_mapping", "gsr_render_bwd", "gsr_raster_bwd", "gsr_project_bwd", "gsr_pair_count",
            "gsr_plan_set_timing", "gsr_plan_read_timing", "gsr_status_str", "gsr_last_error",
            "gsr_seed_triangulate", "gsr_seed_scale_workspace_bytes", "gsr_seed_scale",
-           "gsr_adam_step", "gsr_covis", "gsr_prune_workspace_bytes", "gsr_prune", "gsr_compact",
+           "gsr_adam_step", "gsr_covis", "gsr_prune_workspace_bytes", "gsr_prune", "gsr_prune_noalloc", "gsr_compact",
            "gsr_nearest", "gsr_merge", "gsr_keep_list", "gsr_seed_frame", "gsr_device_clock_hz")
 
 # launch groups of gsr_plan_read_timing (gsr_timer)
@@ -318,6 +319,17 @@ def gsr_prune_workspace_bytes(n):
 def gsr_prune(n, m_obs, v_vis, log_scale, opacity_logit, cfg: PruneConfig, keep_index, kept, workspace, stream):
     return check(_lib.gsr_prune(int(n), _p(m_obs), _p(v_vis), _p(log_scale), _p(opacity_logit), ctypes.byref(cfg),
                                 _p(keep_index), _p(kept), _p(workspace), ctypes.c_void_p(stream)), "gsr_prune")
+
+
+def gsr_prune_noalloc(n, m_obs, v_vis, log_scale, opacity_logit, cfg: PruneConfig, keep_index, kept, stream):
+    """gsr_prune without a workspace (the library's fixed device scratch;
+    n <= PRUNE_NOALLOC_MAX_N)."""
+    return check(_lib.gsr_prune_noalloc(int(n), _p(m_obs), _p(v_vis), _p(log_scale), _p(opacity_logit),
+                                        ctypes.byref(cfg), _p(keep_index), _p(kept), ctypes.c_void_p(stream)),
+                 "gsr_prune_noalloc")
+
+
+PRUNE_NOALLOC_MAX_N = 1 << 27
 
 
 def gsr_compact(n, rows, src, keep_index, kept, dst, stream):

@@ -135,6 +135,13 @@ def test_maintenance_argument_errors():
     pc = lib.PruneConfig(1, 0.1, 1.0, 0.05)
     assert raw.gsr_prune(0, fake, fake, fake, fake, ctypes.byref(pc), fake, fake, fake, None) == lib.EINVAL
     assert raw.gsr_prune_workspace_bytes(-1) == 0
+    # the no-allocation variant: the same checks, and n beyond its fixed
+    # scratch, all before any device call
+    assert raw.gsr_prune_noalloc(0, fake, fake, fake, fake, ctypes.byref(pc), fake, fake, None) == lib.EINVAL
+    assert raw.gsr_prune_noalloc(10, fake, None, fake, fake, ctypes.byref(pc), fake, fake, None) == lib.EINVAL
+    assert raw.gsr_prune_noalloc(lib.PRUNE_NOALLOC_MAX_N + 1, fake, fake, fake, fake, ctypes.byref(pc), fake, fake,
+                                 None) == lib.EINVAL
+    assert b"GSR_PRUNE_NOALLOC_MAX_N" in raw.gsr_last_error()
     assert raw.gsr_compact(100, 3, ctypes.c_void_p(4096), fake, fake, ctypes.c_void_p(4096 + 400), None) == lib.EINVAL
 
 
