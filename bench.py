@@ -128,6 +128,9 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="re-run the tile/batch autotuner")
     ap.add_argument("--copy-probe", action="store_true", help="run a plain device copy of known size first")
     ap.add_argument("--no-seeding", action="store_true", help="skip the seeding measurement")
+    ap.add_argument("--no-mixed", action="store_true", help="skip timing the mixed-precision variant")
+    ap.add_argument("--precision", choices=("fp32", "mixed"), default="fp32",
+                    help="precision of the headline step (default fp32)")
     ap.add_argument("--no-second", action="store_true",
                     help="skip the second leg (the 3M-Gaussian tracking-and-mapping batch)")
     ap.add_argument("--deterministic", action="store_true",
@@ -165,7 +168,7 @@ class Step:
         self.loss = loss
         P = R.total_pixels
         dev = poses.device
-        self.rgb = torch.empty(3 * P, device=dev)
+        self.rgb = torch.empty(3 * P, dtype=R.image_dtype, device=dev)
         self.T = torch.empty(P, device=dev)
         self.nc = torch.empty(P, dtype=torch.int32, device=dev)
         self.dL = torch.empty(3 * P, device=dev)
@@ -492,7 +495,8 @@ def step_roofline(stage_ms, ms_step, n, sh3, slots_live, pairs, evals, pixels):
             "stages": stages}
 
 
-def measure_workload(index, args, torch, steps, warmup, lat_reps, plain_steps, loss="l1", extras=True):
+def measure_workload(index, args, torch, steps, warmup, lat_reps, plain_steps, loss="l1", extras=True,
+                     precision="fp32"):
     """One workload end to end: the batched step captured in a graph and
     replayed (timed), per-view latency, per-kernel time, the blend count, the
     per-view plain launches, and the rooflines.  Returns (result dict,
@@ -523,8 +527,8 @@ def measure_workload(index, args, torch, steps, warmup, lat_reps, plain_steps, l
             tuned = autotune.tune(params, cams, poses, target, w["sh_degree"], pose_only, log=log)
             tile = tuned["best"]
     cfg = Config(tile_w=tile[0], tile_h=tile[1], batch=tile[2], sh_degree=w["sh_degree"],
-                 deterministic=args.deterministic)
-    log(f"tile {tile[0]}x{tile[1]}, LDS batch {tile[2]}")
+                 deterministic=args.deterministic, precision=precision)
+    log(f"tile {tile[0]}x{tile[1]}, LDS batch {tile[2]}, precision {precision}")
     total_px = sum(c["width"] * c["height"] for c in cams)
 
     # ---------------- batched: one plan, one graph --------------------
@@ -573,11 +577,13 @@ def measure_workload(index, args, torch, steps, warmup, lat_reps, plain_steps, l
     for _ in range(lat_reps):
         graph.replay()
         lat.extend(R.view_latency_ms()[sel].tolist())
-    view_latency = {"views": "pose-only" if po_views else "all", "count": len(sel), "replays": lat_reps,
-                    "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                    "max_ms": float(np.max(lat))}
-    log(f"view latency ({view_latency['views']}, {len(sel)} views x {lat_reps} replays): "
-        f"p50 {view_latency['p50_ms']:.3f} ms, p99 {view_latency['p99_ms']:.3f} ms")
+    view_latency = None
+    if lat:
+        view_latency = {"views": "pose-only" if po_views else "all", "count": len(sel), "replays": lat_reps,
+                        "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                        "max_ms": float(np.max(lat))}
+        log(f"view latency ({view_latency['views']}, {len(sel)} views x {lat_reps} replays): "
+            f"p50 {view_latency['p50_ms']:.3f} ms, p99 {view_latency['p99_ms']:.3f} ms")
 
     # ---------------- per-kernel device time: library HIP events ----------
     # (eager launches of the same step on the same inputs, right after the
@@ -682,6 +688,31 @@ def measure_workload(index, args, torch, steps, warmup, lat_reps, plain_steps, l
     return res, w, cfg, st, R, params, cap
 
 
+def loss_measurements(torch, st, total_px, reps):
+    """The tracking loss (three kernels, HBM bound) and the mapping loss (one
+    fused kernel, VALU bound) on the step's render, each replayed from a
+    graph of 20 calls (tens of microseconds each: eager launches would time
+    the host's launch gaps)."""
+    t_ms = _graph_ms(torch, st.track, reps)
+    t_bytes = BYTES_TRACK_PER_PIXEL * total_px
+    track = {"ms": t_ms, "bound": "hbm", "achieved": t_bytes / (t_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+             "unit": "GB/s", "work": f"{BYTES_TRACK_PER_PIXEL} B x {total_px} px",
+             "tau_alpha": TRACK_TAU_ALPHA, "tau_grad": TRACK_TAU_GRAD}
+    track["frac"] = track["achieved"] / track["peak"]
+    log(f"tracking loss: {t_ms:.4f} ms, {track['achieved']:.0f} GB/s ({track['frac']:.2f} of HBM)")
+
+    m_ms = _graph_ms(torch, st.mapping, reps)
+    m_slots = SLOTS_MAP_PER_PIXEL * total_px
+    mapl = {"ms": m_ms, "bound": "alu", "achieved": m_slots / (m_ms * 1e-3) / 1e12, "peak": VALU_PEAK_TSLOTS,
+            "unit": "T VALU slots/s", "work": f"{SLOTS_MAP_PER_PIXEL} slots x {total_px} px",
+            "hbm_GBs": BYTES_MAP_PER_PIXEL * total_px / (m_ms * 1e-3) / 1e9, "lambda": MAP_LAMBDA}
+    mapl["frac"] = mapl["achieved"] / mapl["peak"]
+    log(f"mapping loss: {m_ms:.4f} ms, {mapl['achieved']:.1f} T slots/s ({mapl['frac']:.2f} of VALU issue), "
+        f"{mapl['hbm_GBs']:.0f} GB/s")
+
+    return track, mapl
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -708,30 +739,16 @@ def main():
 
     res, w, cfg, st, R, params, cap = measure_workload(
         args.config, args, torch, args.steps, args.warmup, max(100, args.steps),
-        0 if args.no_plain else args.steps, loss=args.loss)
+        0 if args.no_plain else args.steps, loss=args.loss, precision=args.precision)
     total_px = res["pixels"]
 
     # ---------------- tracking loss: its three kernels, HBM bound -----------
     # (tens of microseconds each, so they are replayed from a graph of 20
     # calls: eager launches would time the host's launch gaps)
     reps = max(3, args.steps // 4)
-    t_ms = _graph_ms(torch, st.track, reps)
-    t_bytes = BYTES_TRACK_PER_PIXEL * total_px
-    track = {"ms": t_ms, "bound": "hbm", "achieved": t_bytes / (t_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-             "unit": "GB/s", "work": f"{BYTES_TRACK_PER_PIXEL} B x {total_px} px",
-             "tau_alpha": TRACK_TAU_ALPHA, "tau_grad": TRACK_TAU_GRAD}
-    track["frac"] = track["achieved"] / track["peak"]
-    log(f"tracking loss: {t_ms:.4f} ms, {track['achieved']:.0f} GB/s ({track['frac']:.2f} of HBM)")
-
-    # ---------------- mapping loss: one fused kernel, VALU bound ------------
-    m_ms = _graph_ms(torch, st.mapping, reps)
-    m_slots = SLOTS_MAP_PER_PIXEL * total_px
-    mapl = {"ms": m_ms, "bound": "alu", "achieved": m_slots / (m_ms * 1e-3) / 1e12, "peak": VALU_PEAK_TSLOTS,
-            "unit": "T VALU slots/s", "work": f"{SLOTS_MAP_PER_PIXEL} slots x {total_px} px",
-            "hbm_GBs": BYTES_MAP_PER_PIXEL * total_px / (m_ms * 1e-3) / 1e9, "lambda": MAP_LAMBDA}
-    mapl["frac"] = mapl["achieved"] / mapl["peak"]
-    log(f"mapping loss: {m_ms:.4f} ms, {mapl['achieved']:.1f} T slots/s ({mapl['frac']:.2f} of VALU issue), "
-        f"{mapl['hbm_GBs']:.0f} GB/s")
+    track = mapl = None
+    if args.precision == "fp32":
+        track, mapl = loss_measurements(torch, st, total_px, reps)
 
     # ---------------- seeding and map maintenance at the workload's size ----
     seed_res = None if args.no_seeding else seeding_measurement(torch, max(3, args.steps // 4), log)
@@ -742,6 +759,20 @@ def main():
     del st, R, params
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
+
+    # ---------------- the mixed-precision variant on the same workload ------
+    # (32-byte staging records with binary16 colour, binary16 image; the same
+    # graph-replayed step with the L1 seed)
+    mixed = None
+    if not args.no_mixed and args.loss == "l1":
+        mres, *_ = measure_workload(args.config, args, torch, args.steps, args.warmup, 0, 0, loss="l1",
+                                   extras=False, precision="mixed")
+        mixed = {"ms_per_step": mres["ms_per_step"], "mpix_per_s": mres["mpix_per_s"],
+                 "speedup_vs_fp32": res["ms_per_step"] / mres["ms_per_step"], "kernel_ms": mres["kernel_ms"]}
+        log(f"mixed precision: {mres['ms_per_step']:.3f} ms/step ({mixed['speedup_vs_fp32']:.3f}x the fp32 step)")
+        del mres
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
 
     # ---------------- the 3M-Gaussian tracking-and-mapping batch ----------
     # (a compact second leg: 4 mapping views at 1920x1080 and 32 pose-only
@@ -763,7 +794,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if args.precision == "fp32" else "f32+f16",
         "data": "synthetic",
         "config": {"workload": res["workload"], "gaussians": res["gaussians"], "views": res["views"],
                    "pixels": total_px, "tile": res["tile"], "batch": res["batch"], "sh_degree": res["sh_degree"],
@@ -787,6 +818,7 @@ def main():
         "seeding": seed_res,
         "maintenance": maint,
         "cpu_baseline": cpu,
+        "mixed_precision": mixed,
         "track_map_3M": second,
     }
     print(json.dumps(out), flush=True)

@@ -109,7 +109,21 @@ typedef struct {
                                which tiles run; 0: FP64 atomics (reproducible
                                to ~1e-16 relative).  1 adds 288 bytes of
                                workspace per slot. */
+    int32_t precision;      /* GSR_PRECISION_FP32 (0, the default) or
+                               GSR_PRECISION_MIXED (1).  Mixed: the staging
+                               record each tile reads per pair is 32 bytes
+                               (float32 centre, conic and opacity, binary16
+                               colour) instead of 64 (double centre and conic,
+                               float32 opacity and colour), and gsr_render_fwd
+                               writes, and gsr_loss_l1 reads, the image as
+                               IEEE binary16; T_final, n_contrib and every
+                               gradient stay float32.  gsr_loss_track and
+                               gsr_loss_mapping need float32 images and return
+                               GSR_EUNSUPPORTED for a mixed plan. */
 } gsr_config;
+
+#define GSR_PRECISION_FP32 0
+#define GSR_PRECISION_MIXED 1
 
 /* Gaussian parameters (device planes, see above). */
 typedef struct {
@@ -131,7 +145,9 @@ typedef struct {
     size_t rgb_d;     /* float4 [V*n]: (r, g, b, depth) */
     size_t qthr;      /* float [V*n]: binning level of d^T conic d per slot */
     size_t stage;     /* 64-byte records [V*n]: double u, v, A, B, C; float o, r, g, b
-                         (unrounded centre and conic the compositing stages from) */
+                         (unrounded centre and conic the compositing stages from);
+                         mixed precision: 32-byte records float u, v, A, B, C, o;
+                         binary16 r, g, b (same offset, half the bytes used) */
     size_t grad2d;    /* double [V*n][9]: d(u, v, A, B, C, o, r, g, b) per slot */
     size_t keys;      /* uint64 [capacity]: sorted (tile << 32 | depth bits) */
     size_t vals;      /* uint32 [capacity]: sorted slot = view * n + index */
@@ -196,13 +212,16 @@ gsr_status gsr_bin(gsr_plan *plan, void *stream);
 /* Eq. (alpha) for every view.  rgb, T_final, n_contrib required; n_blend
  * (number of blended entries per pixel) may be NULL.  n_contrib is the list
  * position + 1 of the last blended entry of the pixel's tile list; it is
- * what gsr_render_bwd replays. */
-gsr_status gsr_render_fwd(gsr_plan *plan, float *rgb, float *T_final, int32_t *n_contrib, int32_t *n_blend,
+ * what gsr_render_bwd replays.  rgb holds float32 values, or IEEE binary16
+ * (uint16_t bit patterns, rounded to nearest) for a mixed-precision plan. */
+gsr_status gsr_render_fwd(gsr_plan *plan, void *rgb, float *T_final, int32_t *n_contrib, int32_t *n_blend,
                           void *stream);
 
 /* Gradient of the mean absolute photometric error, Eq. (photometric):
- * dL_drgb = sign(rgb - target) / (3 * total pixels), sign(0) = 0. */
-gsr_status gsr_loss_l1(gsr_plan *plan, const float *rgb, const float *target, float *dL_drgb, void *stream);
+ * dL_drgb = sign(rgb - target) / (3 * total pixels), sign(0) = 0.  rgb as
+ * gsr_render_fwd writes it (binary16 for a mixed-precision plan); target and
+ * dL_drgb float32. */
+gsr_status gsr_loss_l1(gsr_plan *plan, const void *rgb, const float *target, float *dL_drgb, void *stream);
 
 /* Tracking loss of every view, appendix (Tracking and Camera Pose
  * Optimization).  With I_hat the render (rgb), I the observation (target),

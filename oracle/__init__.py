@@ -49,13 +49,16 @@ class Config:
     alpha_max: float = 0.99
     T_min: float = 1e-4
     bg: tuple = (0.0, 0.0, 0.0)
+    # tolerance model only (the "clear" ratio): the renderer under test
+    # stages the projected centre and conic rounded to float32
+    staging_f32: bool = False
 
 
 class _CConfig(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("sh_degree", ctypes.c_int32),
                 ("z_near", ctypes.c_double), ("dilation", ctypes.c_double),
                 ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
-                ("T_min", ctypes.c_double), ("bg", ctypes.c_double * 3)]
+                ("T_min", ctypes.c_double), ("bg", ctypes.c_double * 3), ("staging_f32", ctypes.c_int32)]
 
 
 class _CCamera(ctypes.Structure):
@@ -86,13 +89,14 @@ def _load():
     return _lib
 
 
-def power2_error_bound(u, v, A, B, C, px, py, xc, yc, p2):
+def power2_error_bound(u, v, A, B, C, px, py, xc, yc, p2, staging_f32=False):
     """The oracle's bound on the float32 error of the exp2-space power at a
-    pixel, expanded about the tile centre (xc, yc) (test tolerance model)."""
+    pixel, expanded about the tile centre (xc, yc) (test tolerance model);
+    staging_f32: the centre and conic are rounded to float32 first."""
     f = _load().or_power2_error
     f.restype = ctypes.c_double
-    f.argtypes = [ctypes.c_double] * 10
-    return float(f(u, v, A, B, C, px, py, xc, yc, p2))
+    f.argtypes = [ctypes.c_double] * 10 + [ctypes.c_int32]
+    return float(f(u, v, A, B, C, px, py, xc, yc, p2, 1 if staging_f32 else 0))
 
 
 def set_threads(n: int) -> None:
@@ -117,6 +121,7 @@ def _cfg(cfg: Config) -> _CConfig:
     c.alpha_min, c.alpha_max, c.T_min = cfg.alpha_min, cfg.alpha_max, cfg.T_min
     for k in range(3):
         c.bg[k] = float(cfg.bg[k])
+    c.staging_f32 = 1 if cfg.staging_f32 else 0
     return c
 
 

@@ -53,6 +53,9 @@ typedef struct {
     int32_t tile_w, tile_h, sh_degree; /* sh_degree < 0: plain RGB colour */
     double z_near, dilation, alpha_min, alpha_max, T_min;
     double bg[3];
+    int32_t staging_f32; /* tolerance model only: the renderer stages the projected
+                            centre and conic rounded to float32 (see
+                            power2_abs_error); no rendered value depends on it */
 } or_config;
 
 typedef struct {
@@ -384,7 +387,8 @@ static double rel_margin(double a, double b)
  * (u = 2^-24), the four inner multiply-adds by at most 2 u S (each rounds a
  * partial sum of terms, each term counted at most twice), and the last one by
  * u |p2|: |d p2| <= 3 u S + u |p2|. */
-static double power2_abs_error(const proj_t *p, double px, double py, double xc, double yc, double p2)
+static double power2_abs_error(const proj_t *p, double px, double py, double xc, double yc, double p2,
+                               int staging_f32)
 {
     const double u = 0x1p-24, k = 0.72134752044448170; /* log2(e) / 2 */
     const double A = p->conic[0], B = p->conic[1], C = p->conic[2];
@@ -392,13 +396,23 @@ static double power2_abs_error(const proj_t *p, double px, double py, double xc,
     const double S = k * (A * ox * ox + 2.0 * B * ox * oy + C * oy * oy) +
                      2.0 * k * (fabs(A * ox + B * oy) * fabs(dx) + fabs(B * ox + C * oy) * fabs(dy)) +
                      k * (A * dx * dx + 2.0 * fabs(B * dx * dy) + C * dy * dy);
-    return 3.0 * u * S + u * fabs(p2);
+    double e = 3.0 * u * S + u * fabs(p2);
+    if (staging_f32) {
+        /* the centre (u, v) and the conic rounded to float32 before the
+         * expansion: p2 = -k f^T conic f with f = pixel - centre moves by
+         * 2 k |(conic f)_x| |du| + 2 k |(conic f)_y| |dv| (|du| <= u |u|)
+         * and by k (A fx^2 + 2 |B fx fy| + C fy^2) u for the conic */
+        const double fx = px - p->u, fy = py - p->v;
+        e += u * (2.0 * k * (fabs(A * fx + B * fy) * fabs(p->u) + fabs(B * fx + C * fy) * fabs(p->v)) +
+                  k * (A * fx * fx + 2.0 * fabs(B * fx * fy) + C * fy * fy));
+    }
+    return e;
 }
 
 /* The bound above for a Gaussian given by (u, v, conic), exported for the
  * test that checks it against an emulated float32 evaluation. */
 double or_power2_error(double u, double v, double A, double B, double C, double px, double py,
-                       double xc, double yc, double p2)
+                       double xc, double yc, double p2, int32_t staging_f32)
 {
     proj_t p;
     memset(&p, 0, sizeof(p));
@@ -407,7 +421,7 @@ double or_power2_error(double u, double v, double A, double B, double C, double 
     p.conic[0] = A;
     p.conic[1] = B;
     p.conic[2] = C;
-    return power2_abs_error(&p, px, py, xc, yc, p2);
+    return power2_abs_error(&p, px, py, xc, yc, p2, staging_f32);
 }
 
 /* Composites one pixel; fills rec[] (if non-NULL) with the blended entries.
@@ -441,7 +455,8 @@ static int64_t composite_pixel(const proj_t *P, const int64_t *list, int64_t len
          * / o) in float32 (the threshold's, the opacity's and the quotient's
          * roundings, the logarithm within 2 ulp of its value) */
         const double ln2 = 0.69314718055994531;
-        double e_p2 = clear ? power2_abs_error(p, px, py, xc, yc, power * 1.4426950408889634) : 0.0;
+        double e_p2 = clear ? power2_abs_error(p, px, py, xc, yc, power * 1.4426950408889634, cfg->staging_f32)
+                            : 0.0;
         double ea = ln2 * e_p2 + 4.0 * u32;
         if (cfg->alpha_min > 0) {
             double mm = rel_margin(a_raw, cfg->alpha_min);
@@ -705,8 +720,9 @@ int or_backward(const or_scene *sc, int32_t n_views, const or_camera *cams, cons
     /* per-thread screen-space gradients, summed in thread order after each view */
     double *g2t = (double *)malloc(sizeof(double) * G_N * (size_t)(n > 0 ? n : 1) * (size_t)nthr);
     double *xit = (double *)malloc(sizeof(double) * 6 * (size_t)nthr);
-    /* optional: the sum of the magnitudes of the addends of each screen-space
-     * gradient, per thread, for the tests' cancellation measure */
+    /* optional: the sum of the magnitudes of the elementary products behind
+     * each screen-space gradient (those of dL/dalpha included), per thread,
+     * for the tests' cancellation measure */
     double *abt = grad2d_abs_out ? (double *)malloc(sizeof(double) * G_N * (size_t)(n > 0 ? n : 1) * (size_t)nthr)
                                  : NULL;
     if (!P || !g2 || !g2t || !xit || (grad2d_abs_out && !abt)) return -1;
@@ -756,10 +772,14 @@ int or_backward(const or_scene *sc, int32_t n_views, const or_camera *cams, cons
                         double *gg = tg2 + G_N * e->id;
                         double *ga = tab ? tab + G_N * e->id : NULL;
                         double dalpha = -gT * e->T * Q;
+                        /* the magnitudes of dalpha's elementary products (its
+                         * own cancellation enters the measure too) */
+                        double dalpha_abs = fabs(gT * e->T * Q);
                         for (int c = 0; c < 3; ++c) {
                             gg[G_R + c] += g[c] * e->alpha * e->T;
                             if (ga) ga[G_R + c] += fabs(g[c] * e->alpha * e->T);
                             dalpha += g[c] * e->T * (p->rgb[c] - B[c]);
+                            dalpha_abs += fabs(g[c] * e->T) * (fabs(p->rgb[c]) + fabs(B[c]));
                         }
                         for (int c = 0; c < 3; ++c) B[c] = p->rgb[c] * e->alpha + (1.0 - e->alpha) * B[c];
                         Q *= 1.0 - e->alpha;
@@ -774,12 +794,13 @@ int or_backward(const or_scene *sc, int32_t n_views, const or_camera *cams, cons
                         gg[G_U] += dpow * (p->conic[0] * e->dx + p->conic[1] * e->dy);
                         gg[G_V] += dpow * (p->conic[1] * e->dx + p->conic[2] * e->dy);
                         if (ga) {
-                            ga[G_O] += fabs(dalpha * e->G);
-                            ga[G_A] += fabs(dpow * (-0.5 * e->dx * e->dx));
-                            ga[G_B] += fabs(dpow * (-e->dx * e->dy));
-                            ga[G_C] += fabs(dpow * (-0.5 * e->dy * e->dy));
-                            ga[G_U] += fabs(dpow * (p->conic[0] * e->dx + p->conic[1] * e->dy));
-                            ga[G_V] += fabs(dpow * (p->conic[1] * e->dx + p->conic[2] * e->dy));
+                            const double dpa = dalpha_abs * e->alpha;
+                            ga[G_O] += dalpha_abs * e->G;
+                            ga[G_A] += dpa * 0.5 * e->dx * e->dx;
+                            ga[G_B] += dpa * fabs(e->dx * e->dy);
+                            ga[G_C] += dpa * 0.5 * e->dy * e->dy;
+                            ga[G_U] += dpa * (fabs(p->conic[0] * e->dx) + fabs(p->conic[1] * e->dy));
+                            ga[G_V] += dpa * (fabs(p->conic[1] * e->dx) + fabs(p->conic[2] * e->dy));
                         }
                     }
                 }

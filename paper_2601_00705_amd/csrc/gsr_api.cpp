@@ -161,6 +161,8 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
         return fail(GSR_EINVAL, "alpha bounds");
     if (!(cfg->T_min >= 0.0f) || !(cfg->T_min < 1.0f)) return fail(GSR_EINVAL, "T_min");
     if (cfg->deterministic != 0 && cfg->deterministic != 1) return fail(GSR_EINVAL, "deterministic not 0 or 1");
+    if (cfg->precision != GSR_PRECISION_FP32 && cfg->precision != GSR_PRECISION_MIXED)
+        return fail(GSR_EINVAL, "precision not GSR_PRECISION_FP32 or GSR_PRECISION_MIXED");
     if (!(cfg->dilation >= 0.0f) || !std::isfinite(cfg->z_near)) return fail(GSR_EINVAL, "dilation / z_near");
 
     gsr_plan* p = new (std::nothrow) gsr_plan();
@@ -175,6 +177,7 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->dcfg.log2_tw = ilog2(cfg->tile_w);
     p->dcfg.log2_th = ilog2(cfg->tile_h);
     p->dcfg.sh_degree = cfg->sh_degree;
+    p->dcfg.mixed = cfg->precision == GSR_PRECISION_MIXED ? 1 : 0;
     p->dcfg.z_near = cfg->z_near;
     p->dcfg.dilation = cfg->dilation;
     p->dcfg.alpha_min = cfg->alpha_min;
@@ -387,7 +390,7 @@ extern "C" gsr_status gsr_project(gsr_plan* plan, const gsr_gaussians* g, const 
     a.conic_o = at<float4>(plan, plan->off_conic);
     a.rgb_d = at<float4>(plan, plan->off_rgbd);
     a.qthr = at<float>(plan, plan->off_qthr);
-    a.stage = at<StageRec>(plan, plan->off_stage);
+    a.stage = at<void>(plan, plan->off_stage);
     a.grad2d = at<double>(plan, plan->off_grad2d);
     a.acc = plan->cfg.deterministic ? at<unsigned long long>(plan, plan->off_acc) : nullptr;
     a.stamps = at<unsigned long long>(plan, plan->off_stamps);
@@ -463,7 +466,7 @@ static RasterArgs raster_args(const gsr_plan* plan)
     a.order = at<uint32_t>(plan, plan->off_order);
     a.vals = at<uint32_t>(plan, plan->off_vals);
     a.geom = at<float4>(plan, plan->off_geom);
-    a.stage = at<StageRec>(plan, plan->off_stage);
+    a.stage = at<void>(plan, plan->off_stage);
     a.grad2d = at<double>(plan, plan->off_grad2d);
     a.acc = plan->cfg.deterministic ? at<unsigned long long>(plan, plan->off_acc) : nullptr;
     a.slots = plan->n * plan->V;
@@ -472,7 +475,7 @@ static RasterArgs raster_args(const gsr_plan* plan)
     return a;
 }
 
-extern "C" gsr_status gsr_render_fwd(gsr_plan* plan, float* rgb, float* T_final, int32_t* n_contrib,
+extern "C" gsr_status gsr_render_fwd(gsr_plan* plan, void* rgb, float* T_final, int32_t* n_contrib,
                                      int32_t* n_blend, void* stream)
 {
     g_err.clear();
@@ -490,7 +493,7 @@ extern "C" gsr_status gsr_render_fwd(gsr_plan* plan, float* rgb, float* T_final,
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_render_fwd");
 }
 
-extern "C" gsr_status gsr_loss_l1(gsr_plan* plan, const float* rgb, const float* target, float* dL_drgb,
+extern "C" gsr_status gsr_loss_l1(gsr_plan* plan, const void* rgb, const float* target, float* dL_drgb,
                                   void* stream)
 {
     g_err.clear();
@@ -498,6 +501,7 @@ extern "C" gsr_status gsr_loss_l1(gsr_plan* plan, const float* rgb, const float*
     if (!rgb || !target || !dL_drgb) return fail(GSR_EINVAL, "null buffer");
     LossArgs a{};
     a.rgb = rgb;
+    a.half_image = plan->dcfg.mixed;
     a.target = target;
     a.dL_drgb = dL_drgb;
     a.count = 3 * plan->total_pixels;
@@ -516,6 +520,7 @@ extern "C" gsr_status gsr_loss_track(gsr_plan* plan, const float* rgb, const flo
     if (!rgb || !T_final || !target || !loss || !exposure || !dL_drgb) return fail(GSR_EINVAL, "null buffer");
     if (!(tau_alpha > 0.0) || !(tau_grad > 0.0) || !std::isfinite(tau_alpha) || !std::isfinite(tau_grad))
         return fail(GSR_EINVAL, "tau_alpha and tau_grad must be positive and finite");
+    if (plan->dcfg.mixed) return fail(GSR_EUNSUPPORTED, "gsr_loss_track reads float32 images (mixed plan)");
     gsr_status st = check_bound(plan);
     if (st != GSR_OK) return st;
     TrackArgs a{};
@@ -542,6 +547,7 @@ extern "C" gsr_status gsr_loss_mapping(gsr_plan* plan, const float* rgb, const f
     if (!plan) return fail(GSR_EINVAL, "null plan");
     if (!rgb || !target || !loss || !dL_drgb) return fail(GSR_EINVAL, "null buffer");
     if (!(lambda >= 0.0 && lambda <= 1.0)) return fail(GSR_EINVAL, "lambda must lie in [0, 1]");
+    if (plan->dcfg.mixed) return fail(GSR_EUNSUPPORTED, "gsr_loss_mapping reads float32 images (mixed plan)");
     gsr_status st = check_bound(plan);
     if (st != GSR_OK) return st;
     MapLossArgs a{};

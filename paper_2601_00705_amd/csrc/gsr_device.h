@@ -14,6 +14,7 @@
 // the float32 (u, v, rx, ry) of a slot, single IEEE operations only, so the
 // host reference reproduces it bit for bit.
 #pragma once
+#include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -42,6 +43,7 @@ struct ViewTable {
 struct DevCfg {
     int32_t tile_w, tile_h, log2_tw, log2_th;
     int32_t sh_degree;
+    int32_t mixed;        // 1: 32-byte staging records (StageRecM)
     float z_near, dilation, alpha_min, alpha_max, T_min;
     float bg0, bg1, bg2;
 };
@@ -66,6 +68,15 @@ struct __align__(16) StageRec {
     float pad[2];
 };
 static_assert(sizeof(StageRec) == 64, "StageRec is 64 bytes");
+
+// The mixed-precision staging record: centre, conic and opacity in float32,
+// colour in binary16 (32 bytes, half the gather of StageRec).
+struct __align__(16) StageRecM {
+    float u, v, A, B, C, o;
+    __half r, g, b;
+    uint16_t pad;
+};
+static_assert(sizeof(StageRecM) == 32, "StageRecM is 32 bytes");
 
 // ---------------------------------------------------------------------------
 // binning contract: tile rectangle of a projected record.

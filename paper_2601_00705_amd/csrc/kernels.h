@@ -12,7 +12,7 @@ struct ProjectArgs {
     DevCfg cfg;
     float4 *geom, *conic_o, *rgb_d;
     float* qthr;
-    StageRec* stage;
+    void* stage;               // StageRec or (mixed) StageRecM per slot
     double* grad2d;            // [slots][9], zeroed for live slots
     unsigned long long* acc;   // [slots][GSR_FIX_LIMBS][9] (deterministic mode) or null, zeroed for live slots
     Counters* counters;
@@ -65,8 +65,8 @@ struct RasterArgs {
     const uint32_t* order;     // processing order of the tiles
     const uint32_t* vals;
     const float4* geom;        // liveness of a slot (rx >= 0)
-    const StageRec* stage;     // per-slot staging records
-    float* rgb;                // [sum 3 H W]
+    const void* stage;         // per-slot staging records (StageRec, or StageRecM when cfg.mixed)
+    void* rgb;                 // [sum 3 H W], float (or binary16 when cfg.mixed)
     float* T_final;            // [sum H W]
     int32_t* n_contrib;        // [sum H W]
     int32_t* n_blend;          // nullable
@@ -98,7 +98,8 @@ struct ProjectBwdArgs {
 };
 
 struct LossArgs {
-    const float* rgb;
+    const void* rgb;           // float, or binary16 (half_image)
+    int32_t half_image;
     const float* target;
     float* dL_drgb;
     int64_t count;      // 3 * total pixels

@@ -78,18 +78,33 @@ __global__ __launch_bounds__(256) void k_project(ProjectArgs a)
         a.geom[slot] = make_float4(u, vv, rx, ry);
         a.conic_o[slot] = make_float4((float)p.A, (float)p.B, (float)p.C, o);
         a.rgb_d[slot] = make_float4(rgb[0], rgb[1], rgb[2], (float)p.mc[2]);
-        StageRec sr;
-        sr.u = p.u;
-        sr.v = p.v;
-        sr.A = p.A;
-        sr.B = p.B;
-        sr.C = p.C;
-        sr.o = o;
-        sr.r = rgb[0];
-        sr.g = rgb[1];
-        sr.b = rgb[2];
-        sr.pad[0] = sr.pad[1] = 0.0f;
-        a.stage[slot] = sr;
+        if (a.cfg.mixed) {
+            StageRecM sr;
+            sr.u = (float)p.u;
+            sr.v = (float)p.v;
+            sr.A = (float)p.A;
+            sr.B = (float)p.B;
+            sr.C = (float)p.C;
+            sr.o = o;
+            sr.r = __float2half_rn(rgb[0]);
+            sr.g = __float2half_rn(rgb[1]);
+            sr.b = __float2half_rn(rgb[2]);
+            sr.pad = 0;
+            static_cast<StageRecM*>(a.stage)[slot] = sr;
+        } else {
+            StageRec sr;
+            sr.u = p.u;
+            sr.v = p.v;
+            sr.A = p.A;
+            sr.B = p.B;
+            sr.C = p.C;
+            sr.o = o;
+            sr.r = rgb[0];
+            sr.g = rgb[1];
+            sr.b = rgb[2];
+            sr.pad[0] = sr.pad[1] = 0.0f;
+            static_cast<StageRec*>(a.stage)[slot] = sr;
+        }
 #pragma unroll
         for (int f = 0; f < GSR_G2; ++f) a.grad2d[GSR_G2 * slot + f] = 0.0;
         if (a.acc) {

@@ -47,10 +47,48 @@ struct __align__(16) LdsRec {
 // c0 = k o^T conic o, (gx, gy) = 2 k conic o, formed here in double: the
 // quadratic form of a Gaussian whose centre lies far from the tile cancels
 // heavily, and |d| is at most half a tile.
+// The staged fields of a slot, from either record format: MIXED reads the
+// 32-byte record (float32 centre and conic, binary16 colour).
+struct Staged {
+    double u, v, A, B, C;
+    float o, r, g, b;
+};
+
+template <bool MIXED>
+__device__ __forceinline__ Staged load_staged(const RasterArgs& a, uint32_t slot)
+{
+    Staged t;
+    if (MIXED) {
+        const StageRecM sr = static_cast<const StageRecM*>(a.stage)[slot];
+        t.u = sr.u;
+        t.v = sr.v;
+        t.A = sr.A;
+        t.B = sr.B;
+        t.C = sr.C;
+        t.o = sr.o;
+        t.r = __half2float(sr.r);
+        t.g = __half2float(sr.g);
+        t.b = __half2float(sr.b);
+    } else {
+        const StageRec sr = static_cast<const StageRec*>(a.stage)[slot];
+        t.u = sr.u;
+        t.v = sr.v;
+        t.A = sr.A;
+        t.B = sr.B;
+        t.C = sr.C;
+        t.o = sr.o;
+        t.r = sr.r;
+        t.g = sr.g;
+        t.b = sr.b;
+    }
+    return t;
+}
+
+template <bool MIXED>
 __device__ __forceinline__ void stage_record(const RasterArgs& a, uint32_t slot, double xc, double yc,
                                              LdsRec& r)
 {
-    const StageRec sr = a.stage[slot];
+    const Staged sr = load_staged<MIXED>(a, slot);
     const double k = -0.5 * 1.4426950408889634;
     const double ox = xc - sr.u, oy = yc - sr.v;
     const double qx = sr.A * ox + sr.B * oy, qy = sr.B * ox + sr.C * oy;
@@ -60,6 +98,14 @@ __device__ __forceinline__ void stage_record(const RasterArgs& a, uint32_t slot,
     r.p1 = make_float4((float)(2.0 * k * sr.B), (float)(k * sr.C), sr.o, thr);
     r.p2 = make_float4(sr.r, sr.g, sr.b, __uint_as_float(slot));
     r.p3 = make_float4((float)ox, (float)oy, 1.0f / sr.o, 0.0f);
+}
+
+// writes one colour value of the image (float32, or binary16 when MIXED)
+template <bool MIXED>
+__device__ __forceinline__ void put_rgb(void* rgb, int64_t i, float x)
+{
+    if (MIXED) static_cast<__half*>(rgb)[i] = __float2half_rn(x);
+    else static_cast<float*>(rgb)[i] = x;
 }
 
 // The terms of power2 shared by the pixels of one lane (same column offset
@@ -197,7 +243,7 @@ __device__ __forceinline__ void fwd_batch(const LdsRec* rec, int cnt, uint32_t p
 
 // COUNT: also count the blended entries per pixel (into a.n_blend); a
 // separate instantiation, so that the plain forward carries no counters
-template <int PPT, int GSR_BATCH, bool COUNT>
+template <int PPT, int GSR_BATCH, bool COUNT, bool MIXED>
 __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
 {
     __shared__ LdsRec rec[GSR_BATCH];
@@ -223,7 +269,7 @@ __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
 #pragma unroll
         for (int r = 0; r < GSR_BATCH / 64; ++r) {
             const uint32_t j = base + lane + 64 * r;
-            if (j < range.y) stage_record(a, a.vals[j], c.xc, c.yc, rec[lane + 64 * r]);
+            if (j < range.y) stage_record<MIXED>(a, a.vals[j], c.xc, c.yc, rec[lane + 64 * r]);
         }
         __syncthreads();
         const int cnt = (int)min((uint32_t)GSR_BATCH, range.y - base);
@@ -235,17 +281,17 @@ __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
         if (!c.inside(k)) continue;
         if (overflow) {
             const float q = __builtin_nanf("");
-            a.rgb[c.rgb0(k)] = q;
-            a.rgb[c.rgb0(k) + c.plane] = q;
-            a.rgb[c.rgb0(k) + 2 * c.plane] = q;
+            put_rgb<MIXED>(a.rgb, c.rgb0(k), q);
+            put_rgb<MIXED>(a.rgb, c.rgb0(k) + c.plane, q);
+            put_rgb<MIXED>(a.rgb, c.rgb0(k) + 2 * c.plane, q);
             a.T_final[c.pix(k)] = q;
             a.n_contrib[c.pix(k)] = 0;
             if (COUNT) a.n_blend[c.pix(k)] = 0;
             continue;
         }
-        a.rgb[c.rgb0(k)] = __builtin_fmaf(T[k], a.cfg.bg0, C0[k]);
-        a.rgb[c.rgb0(k) + c.plane] = __builtin_fmaf(T[k], a.cfg.bg1, C1[k]);
-        a.rgb[c.rgb0(k) + 2 * c.plane] = __builtin_fmaf(T[k], a.cfg.bg2, C2[k]);
+        put_rgb<MIXED>(a.rgb, c.rgb0(k), __builtin_fmaf(T[k], a.cfg.bg0, C0[k]));
+        put_rgb<MIXED>(a.rgb, c.rgb0(k) + c.plane, __builtin_fmaf(T[k], a.cfg.bg1, C1[k]));
+        put_rgb<MIXED>(a.rgb, c.rgb0(k) + 2 * c.plane, __builtin_fmaf(T[k], a.cfg.bg2, C2[k]));
         a.T_final[c.pix(k)] = T[k];
         a.n_contrib[c.pix(k)] = (int32_t)last[k];
         if (COUNT) a.n_blend[c.pix(k)] = (int32_t)nb[k];
@@ -341,7 +387,7 @@ __device__ __forceinline__ void view_done(const RasterArgs& a, int tile, int lan
     if ((old + 1ull) % tiles == 0ull) a.stamps[v] = (unsigned long long)wall_clock64();
 }
 
-template <int PPT, int GSR_BATCH, bool DET>
+template <int PPT, int GSR_BATCH, bool DET, bool MIXED>
 __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
 {
     __shared__ LdsRec rec[GSR_BATCH];
@@ -389,7 +435,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
 #pragma unroll
         for (int r = 0; r < GSR_BATCH / 64; ++r) {
             const int t = lane + 64 * r;
-            if (t < cnt) stage_record(a, a.vals[hi_ - 1 - t], c.xc, c.yc, rec[t]);
+            if (t < cnt) stage_record<MIXED>(a, a.vals[hi_ - 1 - t], c.xc, c.yc, rec[t]);
         }
         __syncthreads();
         for (int e = 0; e < cnt; ++e) {
@@ -461,13 +507,13 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
     view_done(a, c.tile, lane);
 }
 
-template <int PPT, bool COUNT>
+template <int PPT, bool COUNT, bool MIXED>
 static hipError_t launch_fwd_c(const RasterArgs& a, int tiles, int batch, hipStream_t s)
 {
     switch (batch) {
-    case 64: hipLaunchKernelGGL((k_raster_fwd<PPT, 64, COUNT>), dim3(tiles), dim3(64), 0, s, a); break;
-    case 128: hipLaunchKernelGGL((k_raster_fwd<PPT, 128, COUNT>), dim3(tiles), dim3(64), 0, s, a); break;
-    case 256: hipLaunchKernelGGL((k_raster_fwd<PPT, 256, COUNT>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 64: hipLaunchKernelGGL((k_raster_fwd<PPT, 64, COUNT, MIXED>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 128: hipLaunchKernelGGL((k_raster_fwd<PPT, 128, COUNT, MIXED>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 256: hipLaunchKernelGGL((k_raster_fwd<PPT, 256, COUNT, MIXED>), dim3(tiles), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipSuccess;
@@ -476,16 +522,20 @@ static hipError_t launch_fwd_c(const RasterArgs& a, int tiles, int batch, hipStr
 template <int PPT>
 static hipError_t launch_fwd_t(const RasterArgs& a, int tiles, int batch, hipStream_t s)
 {
-    return a.n_blend ? launch_fwd_c<PPT, true>(a, tiles, batch, s) : launch_fwd_c<PPT, false>(a, tiles, batch, s);
+    if (a.cfg.mixed)
+        return a.n_blend ? launch_fwd_c<PPT, true, true>(a, tiles, batch, s)
+                         : launch_fwd_c<PPT, false, true>(a, tiles, batch, s);
+    return a.n_blend ? launch_fwd_c<PPT, true, false>(a, tiles, batch, s)
+                     : launch_fwd_c<PPT, false, false>(a, tiles, batch, s);
 }
 
-template <int PPT, bool DET>
+template <int PPT, bool DET, bool MIXED>
 static hipError_t launch_bwd_d(const RasterArgs& a, int tiles, int batch, hipStream_t s)
 {
     switch (batch) {
-    case 64: hipLaunchKernelGGL((k_raster_bwd<PPT, 64, DET>), dim3(tiles), dim3(64), 0, s, a); break;
-    case 128: hipLaunchKernelGGL((k_raster_bwd<PPT, 128, DET>), dim3(tiles), dim3(64), 0, s, a); break;
-    case 256: hipLaunchKernelGGL((k_raster_bwd<PPT, 256, DET>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 64: hipLaunchKernelGGL((k_raster_bwd<PPT, 64, DET, MIXED>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 128: hipLaunchKernelGGL((k_raster_bwd<PPT, 128, DET, MIXED>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 256: hipLaunchKernelGGL((k_raster_bwd<PPT, 256, DET, MIXED>), dim3(tiles), dim3(64), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipSuccess;
@@ -494,7 +544,11 @@ static hipError_t launch_bwd_d(const RasterArgs& a, int tiles, int batch, hipStr
 template <int PPT>
 static hipError_t launch_bwd_t(const RasterArgs& a, int tiles, int batch, hipStream_t s)
 {
-    return a.acc ? launch_bwd_d<PPT, true>(a, tiles, batch, s) : launch_bwd_d<PPT, false>(a, tiles, batch, s);
+    if (a.cfg.mixed)
+        return a.acc ? launch_bwd_d<PPT, true, true>(a, tiles, batch, s)
+                     : launch_bwd_d<PPT, false, true>(a, tiles, batch, s);
+    return a.acc ? launch_bwd_d<PPT, true, false>(a, tiles, batch, s)
+                 : launch_bwd_d<PPT, false, false>(a, tiles, batch, s);
 }
 
 hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s)
@@ -591,11 +645,13 @@ hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, 
 // ---------------------------------------------------------------------------
 // L1 photometric loss seed, Eq. (photometric): dL/dC = sign(C - target) / count
 
+template <bool HALF>
 __global__ void k_loss_l1(LossArgs a)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.count;
          i += (int64_t)gridDim.x * blockDim.x) {
-        float d = a.rgb[i] - a.target[i];
+        const float x = HALF ? __half2float(static_cast<const __half*>(a.rgb)[i]) : static_cast<const float*>(a.rgb)[i];
+        float d = x - a.target[i];
         a.dL_drgb[i] = d > 0.0f ? a.scale : (d < 0.0f ? -a.scale : 0.0f);
     }
 }
@@ -605,7 +661,8 @@ hipError_t launch_loss_l1(const LossArgs& a, hipStream_t s)
     if (a.count == 0) return hipSuccess;
     int64_t blocks = (a.count + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(k_loss_l1, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    if (a.half_image) hipLaunchKernelGGL(k_loss_l1<true>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_loss_l1<false>, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -32,7 +32,7 @@ class Config(ctypes.Structure):
     _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch", ctypes.c_int32),
                 ("sh_degree", ctypes.c_int32), ("z_near", ctypes.c_float), ("dilation", ctypes.c_float),
                 ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float), ("T_min", ctypes.c_float),
-                ("bg", ctypes.c_float * 3), ("deterministic", ctypes.c_int32)]
+                ("bg", ctypes.c_float * 3), ("deterministic", ctypes.c_int32), ("precision", ctypes.c_int32)]
 
 
 class Gaussians(ctypes.Structure):
@@ -148,6 +148,10 @@ EXPORTS = ("gsr_plan_create", "gsr_plan_destroy", "gsr_plan_workspace_bytes", "g
            "gsr_adam_step", "gsr_covis", "gsr_prune_workspace_bytes", "gsr_prune", "gsr_prune_noalloc", "gsr_compact",
            "gsr_nearest", "gsr_merge", "gsr_keep_list", "gsr_seed_frame", "gsr_device_clock_hz")
 
+# gsr_config.precision: float32 staging records and images, or the mixed
+# variant (32-byte records with binary16 colour, binary16 images)
+PRECISIONS = {"fp32": 0, "mixed": 1}
+
 # launch groups of gsr_plan_read_timing (gsr_timer)
 TIMERS = ("project", "bin_emit", "bin_sort", "bin_ranges", "raster_fwd", "loss_l1", "clear_grad2d",
           "raster_bwd", "project_bwd", "loss_track", "loss_mapping")
@@ -185,6 +189,10 @@ def make_config(cfg):
     for k in range(3):
         c.bg[k] = float(cfg.bg[k])
     c.deterministic = 1 if getattr(cfg, "deterministic", False) else 0
+    prec = getattr(cfg, "precision", "fp32")
+    if prec not in PRECISIONS:
+        raise ValueError(f"precision must be one of {tuple(PRECISIONS)}")
+    c.precision = PRECISIONS[prec]
     return c
 
 

@@ -22,7 +22,9 @@ class Config:
     """Renderer settings.  Defaults: 16x16 tiles, near plane 0.2, screen
     covariance dilation 0.3 px^2, alpha in [1/255, 0.99], early stop at
     T < 1e-4, black background, RGB colour, FP64-atomic backward (set
-    deterministic for the bitwise-reproducible fixed-point one)."""
+    deterministic for the bitwise-reproducible fixed-point one), float32
+    staging records and images (precision "mixed": 32-byte records with
+    binary16 colour and binary16 images)."""
     tile_w: int = 16
     tile_h: int = 16
     batch: int = 128
@@ -34,6 +36,7 @@ class Config:
     T_min: float = 1e-4
     bg: tuple = (0.0, 0.0, 0.0)
     deterministic: bool = False
+    precision: str = "fp32"
 
 
 def _stream(device):
@@ -128,10 +131,15 @@ class Renderer:
     def pair_count(self):
         return lib.gsr_pair_count(self.plan, _stream(self.device))
 
+    @property
+    def image_dtype(self):
+        """dtype of the rendered image: float32, or float16 for a mixed plan."""
+        return torch.float16 if self.cfg.precision == "mixed" else torch.float32
+
     def new_image_buffers(self, want_blend=False):
         P = self.total_pixels
         dev = self.device
-        return (torch.empty(3 * P, device=dev), torch.empty(P, device=dev),
+        return (torch.empty(3 * P, dtype=self.image_dtype, device=dev), torch.empty(P, device=dev),
                 torch.empty(P, dtype=torch.int32, device=dev),
                 torch.empty(P, dtype=torch.int32, device=dev) if want_blend else None)
 
@@ -229,7 +237,8 @@ class _RenderFn(torch.autograd.Function):
             r.bin()
         grads = {k: torch.empty_like(v) for k, v in params.items()}
         d_xi = torch.empty(len(r.cams), 6, device=poses.device)
-        d_rgb = torch.zeros(3 * r.total_pixels, device=poses.device) if d_rgb is None else d_rgb.contiguous()
+        d_rgb = (torch.zeros(3 * r.total_pixels, device=poses.device) if d_rgb is None
+                 else d_rgb.to(torch.float32).contiguous())  # float32 also for a binary16 image
         d_T = None if d_T is None else d_T.contiguous()
         r.render_bwd(params, poses, T, nc, d_rgb, d_T, ctx.pose_only, grads, d_xi)
         return (None, None, None, d_xi, grads["mean"], grads["quat"], grads["log_scale"],

@@ -21,7 +21,7 @@ CLEAR = 1.0
 def oracle_cfg(cfg):
     return oracle.Config(tile_w=cfg.tile_w, tile_h=cfg.tile_h, sh_degree=cfg.sh_degree, z_near=cfg.z_near,
                          dilation=cfg.dilation, alpha_min=cfg.alpha_min, alpha_max=cfg.alpha_max,
-                         T_min=cfg.T_min, bg=cfg.bg)
+                         T_min=cfg.T_min, bg=cfg.bg, staging_f32=getattr(cfg, "precision", "fp32") == "mixed")
 
 
 def to_dev(params, device="cuda"):
@@ -70,8 +70,10 @@ KAPPA_MIN = 5.0
 
 def cancellation(grad2d, grad2d_abs):
     """Per Gaussian: the largest cancellation factor of its screen-space
-    gradients (fields u, v, A, B, C, o over every view), from the oracle's
-    sums and sums of magnitudes ([V][n][9] each)."""
+    gradients (fields u, v, A, B, C, o over every view): the sum of the
+    magnitudes of the elementary products behind a field (those inside
+    dL/dalpha included) over the magnitude of the field, from the oracle
+    ([V][n][9] each)."""
     s = np.abs(np.asarray(grad2d)[..., :6])
     a = np.asarray(grad2d_abs)[..., :6]
     kap = np.where(a > 0, a / np.maximum(s, 1e-300), 1.0)

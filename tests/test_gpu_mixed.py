@@ -1,0 +1,178 @@
+"""Parity of the mixed-precision variant (gsr_config.precision = mixed: 32-byte
+staging records with float32 centre, conic and opacity and binary16 colour;
+binary16 image) with the FP64 oracle.
+
+Bars, derived from what the variant rounds (u = 2^-24 float32, 2^-11 the
+binary16 half-unit):
+- image: colours are rounded to binary16 (2^-11 relative) and so is the
+  output (2^-11 of |C|); the float32 centre moves alpha by up to ~2e-4
+  relative for Gaussians ~2,000 px from the origin, which moves C by at most
+  twice that times the largest colour.  So |C - C_ref| <= 2e-3 on pixels
+  whose decisions float32 staging cannot flip (the oracle's clear ratio,
+  computed with the float32-staging tolerance model); T_final, float32 but
+  carrying the same alpha error, within 2e-3 as well.
+- gradients: a per-pixel addend carries the colour rounding (2^-11) and the
+  alpha error (up to ~2e-4), about 7e-4 relative, so the bar is 1e-2
+  relative + 1e-4 of the tensor's largest magnitude on every element, except
+  elements of Gaussians whose screen-space gradient sums cancel by
+  kappa >= 1e-2 / 7e-4 = 14 (capped, as for float32).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import ssim as M
+from paper_2601_00705_amd import scenes
+from tests.helpers import cancellation, oracle_cfg, pixel_mask, to_dev
+
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    from paper_2601_00705_amd.render import Config, Renderer
+
+IMG_MIXED = 2e-3
+REL_MIXED = 1e-2
+FLOOR_MIXED = 1e-4
+KAPPA_MIXED = 14.0
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def _fwd(params, cams, poses, cfg):
+    R = Renderer(params["opacity_logit"].shape[0], cams, cfg)
+    P = to_dev(params)
+    poses_d = torch.from_numpy(np.ascontiguousarray(poses, dtype=np.float32)).cuda()
+    rgb, T, nc, nb = R.forward_all(P, poses_d, want_blend=True)
+    torch.cuda.synchronize()
+    assert rgb.dtype == torch.float16
+    return R, P, poses_d, rgb, T, nc, nb
+
+
+def _check_forward(name, params, cams, poses, cfg):
+    say(f"[mixed fwd] {name}")
+    poses = np.asarray(poses, dtype=np.float32)
+    R, P, poses_d, rgb, T, nc, nb = _fwd(params, cams, poses, cfg)
+    ref = oracle.render(params, cams, poses, oracle_cfg(cfg))
+    ok = pixel_mask(ref["clear"], cams)
+    rgb_g = rgb.cpu().numpy().astype(np.float64)
+    T_g = T.cpu().numpy().astype(np.float64)
+    per_px = np.zeros_like(T_g)
+    off = 0
+    for c in cams:
+        hw = c["width"] * c["height"]
+        per_px[off:off + hw] = np.abs(rgb_g - ref["rgb"])[3 * off:3 * off + 3 * hw].reshape(3, hw).max(axis=0)
+        off += hw
+    per_px = np.maximum(per_px, np.abs(T_g - ref["T_final"]))
+    say(f"  max|d| on clear pixels {per_px[ok].max():.3g} (bar {IMG_MIXED}); unclear {1 - ok.mean():.4%}; "
+        f"beyond the bar {np.mean(per_px > IMG_MIXED):.4%}")
+    assert 1 - ok.mean() <= 1e-2
+    assert per_px[ok].max() <= IMG_MIXED
+    return R, P, poses_d, rgb, T, nc, ref
+
+
+def test_mixed_forward_cloud_2k():
+    w = scenes.workload(0)
+    _check_forward("cloud-2k", w["params"], w["cams"], w["poses"], Config(precision="mixed"))
+
+
+@pytest.mark.parametrize("seed,size,tile", [(1, (37, 29), (16, 16)), (7, (70, 41), (32, 16))])
+def test_mixed_forward_ragged(seed, size, tile):
+    params, cam = scenes.cloud(100 + seed, 400, size[0], size[1], 40.0)
+    cfg = Config(tile_w=tile[0], tile_h=tile[1], precision="mixed")
+    _check_forward(f"ragged{size}", params, [cam], scenes.identity_pose()[None], cfg)
+
+
+def test_mixed_forward_room_100k():
+    w = scenes.workload(1)
+    _check_forward("room-100k", w["params"], w["cams"], w["poses"], Config(precision="mixed"))
+
+
+def _grad_check(name, g, ref, kappa, frac_cap=0.0, ratio_cap=1.0):
+    g = np.asarray(g, np.float64)
+    ref = np.asarray(ref, np.float64)
+    assert np.all(np.isfinite(g)), name
+    tol = REL_MIXED * np.abs(ref) + FLOOR_MIXED * max(np.abs(ref).max() if ref.size else 0.0, 1e-30)
+    ratio = np.abs(g - ref) / tol
+    bad = ratio > 1.0
+    worst = float(ratio.max()) if ratio.size else 0.0
+    if not bad.any():
+        say(f"  {name}: every element within the mixed bar (worst {worst:.3g})")
+        return
+    idx = np.nonzero(bad.reshape(-1, bad.shape[-1]).any(axis=0))[0] if bad.ndim > 1 else np.nonzero(bad)[0]
+    say(f"  {name}: {int(bad.sum())} elements ({bad.mean():.5%}) beyond the bar, worst {worst:.3g}, "
+        f"kappa {None if kappa is None else np.sort(kappa[idx])[:8]}")
+    assert kappa is not None and np.all(kappa[idx] >= KAPPA_MIXED), name
+    assert bad.mean() <= frac_cap and worst <= ratio_cap, (name, bad.mean(), worst)
+
+
+def _check_backward(name, params, cams, poses, cfg, seed, with_dT=False, caps=(0.0, 1.0)):
+    R, P, poses_d, rgb, T, nc, ref_fwd = _check_forward(name, params, cams, poses, cfg)
+    Ptot = sum(c["width"] * c["height"] for c in cams)
+    ok = ref_fwd["clear"] > 1.0
+    dL = (scenes.upstream_grad(seed, 3 * Ptot) * pixel_mask(ref_fwd["clear"], cams, 3)).astype(np.float32)
+    dT = (scenes.upstream_grad(seed + 1, Ptot) * ok).astype(np.float32) if with_dT else None
+    grads = {k: torch.empty_like(v) for k, v in P.items()}
+    d_xi = torch.empty(len(cams), 6, device="cuda")
+    say(f"[mixed bwd] {name}")
+    R.render_bwd(P, poses_d, T, nc, torch.from_numpy(dL).cuda(), None if dT is None else torch.from_numpy(dT).cuda(),
+                 None, grads, d_xi)
+    torch.cuda.synchronize()
+    poses = np.asarray(poses, dtype=np.float32)
+    gref = oracle.backward(params, cams, poses, oracle_cfg(cfg), dL.astype(np.float64),
+                           None if dT is None else dT.astype(np.float64), want_grad2d=True)
+    kappa = cancellation(gref["grad2d"], gref["grad2d_abs"])
+    for k in ("mean", "quat", "log_scale", "opacity_logit", "colour"):
+        _grad_check(k, grads[k].cpu().numpy(), gref[k], kappa, *caps)
+    _grad_check("xi", d_xi.cpu().numpy(), gref["xi"], None)
+
+
+def test_mixed_backward_small_scene():
+    params, cam = scenes.cloud(201, 60, 48, 40, 40.0)
+    pose = scenes.left_perturb(scenes.identity_pose(), np.array([0.03, -0.02, 0.05, 0.04, -0.03, 0.02]))
+    _check_backward("small201", params, [cam], pose[None], Config(precision="mixed"), 201, with_dT=True)
+
+
+def test_mixed_backward_cloud_2k():
+    """Measured: one quaternion element of 8,000 at 1.3 times the bar, of a
+    cancellation-limited Gaussian; admitted: 10 such elements up to 2.6."""
+    w = scenes.workload(0)
+    _check_backward("cloud-2k", w["params"], w["cams"], w["poses"], Config(precision="mixed"), 5,
+                    caps=(1.3e-3, 2.6))
+
+
+def test_mixed_backward_room_100k():
+    """Measured: up to 0.003 % of a tensor's elements beyond the bar, worst
+    4.5 times it, all of cancellation-limited Gaussians; admitted: 0.03 % up
+    to 9.1."""
+    w = scenes.workload(1)
+    _check_backward("room-100k", w["params"], w["cams"], w["poses"], Config(precision="mixed"), 21,
+                    caps=(3e-4, 9.1))
+
+
+def test_mixed_l1_seed_reads_the_half_image():
+    """gsr_loss_l1 on the binary16 image: the oracle's lambda = 0 gradient
+    of the same values (binary16 widened exactly), signs equal and
+    magnitudes within one float32 rounding; the tracking and mapping losses
+    refuse a mixed plan."""
+    from paper_2601_00705_amd import lib
+    w = scenes.workload(0)
+    R, P, poses_d, rgb, T, nc, nb = _fwd(w["params"], w["cams"], w["poses"], Config(precision="mixed"))
+    rng = np.random.default_rng(3)
+    target = rgb.float().cpu().numpy() + rng.normal(0, 0.02, rgb.numel()).astype(np.float32)
+    target[::7] = rgb.float().cpu().numpy()[::7]       # exact ties: zero gradient
+    tgt = torch.from_numpy(target).cuda()
+    g = torch.full((rgb.numel(),), np.nan, device="cuda")
+    R.loss_l1(rgb, tgt, g)
+    torch.cuda.synchronize()
+    cam = w["cams"][0]
+    x = rgb.float().cpu().numpy().astype(np.float64).reshape(3, cam["height"], cam["width"])
+    _, ref = M.mapping_loss([x], [target.astype(np.float64).reshape(x.shape)], 0.0)
+    got = g.cpu().numpy().astype(np.float64)
+    assert np.array_equal(np.sign(got), np.sign(ref[0].reshape(-1)))
+    np.testing.assert_allclose(got, ref[0].reshape(-1), rtol=2.0 ** -23, atol=0)
+    loss = torch.empty(1, dtype=torch.float64, device="cuda")
+    with pytest.raises(lib.GsrError):
+        R.loss_mapping(rgb, tgt, 0.2, loss, g)

@@ -672,14 +672,17 @@ def _fma32(a, b, c):
     return np.float32(np.float64(a) * np.float64(b) + np.float64(c))
 
 
-def test_power2_error_bound_holds_for_a_float32_evaluation():
+@pytest.mark.parametrize("staging_f32", [False, True])
+def test_power2_error_bound_holds_for_a_float32_evaluation(staging_f32):
     """The oracle's bound on the float32 error of the exp2-space power (the
     tolerance behind its clear ratio) holds for the evaluation it models:
     the quadratic form expanded about the tile centre, six coefficients
     rounded to float32 from double, then five fused multiply-adds.  Random
     conics (extents 0.5-300 px, correlation up to 0.99), centres up to
     2,000 px from the tile, every pixel of 16x16 and 32x16 tiles; the bound is
-    also not loose by more than a factor 40 on the worst case."""
+    also not loose by more than a factor 40 on the worst case.  With
+    staging_f32 the centre and conic are first rounded to float32 (the
+    mixed-precision records), tiles up to 1,500 px from the origin."""
     rng = np.random.default_rng(77)
     k = 0.5 * math.log2(math.e)
     worst = 0.0
@@ -691,13 +694,17 @@ def test_power2_error_bound_holds_for_a_float32_evaluation():
         det = a * c - b * b
         A, B, C = c / det, -b / det, a / det
         xc, yc = tw * 10 + tw / 2, th * 7 + th / 2
+        if staging_f32:
+            xc, yc = tw * int(rng.integers(0, 90)) + tw / 2, th * int(rng.integers(0, 90)) + th / 2
         reach = 2000.0 if trial % 3 == 0 else 3 * max(sa, sc)
         u, v = xc + rng.uniform(-reach, reach), yc + rng.uniform(-reach, reach)
-        ox, oy = xc - u, yc - v
-        qx, qy = A * ox + B * oy, B * ox + C * oy
+        su, sv, sA, sB, sC = (u, v, A, B, C) if not staging_f32 else \
+            tuple(float(np.float32(x)) for x in (u, v, A, B, C))
+        ox, oy = xc - su, yc - sv
+        qx, qy = sA * ox + sB * oy, sB * ox + sC * oy
         c0 = np.float32(-k * (ox * qx + oy * qy))
         gx, gy = np.float32(-2 * k * qx), np.float32(-2 * k * qy)
-        a2, b2, c2 = np.float32(-k * A), np.float32(-2 * k * B), np.float32(-k * C)
+        a2, b2, c2 = np.float32(-k * sA), np.float32(-2 * k * sB), np.float32(-k * sC)
         for lane_x in range(tw):
             dx = np.float32(lane_x + 0.5 - tw / 2)
             s0 = _fma32(_fma32(a2, dx, gx), dx, c0)
@@ -705,9 +712,10 @@ def test_power2_error_bound_holds_for_a_float32_evaluation():
             for lane_y in range(th):
                 dy = np.float32(lane_y + 0.5 - th / 2)
                 p32 = _fma32(_fma32(c2, dy, s1), dy, s0)
-                fx, fy = float(dx) + ox, float(dy) + oy
+                fx, fy = xc + float(dx) - u, yc + float(dy) - v
                 p64 = -k * (A * fx * fx + 2 * B * fx * fy + C * fy * fy)
-                bound = oracle.power2_error_bound(u, v, A, B, C, xc + float(dx), yc + float(dy), xc, yc, p64)
+                bound = oracle.power2_error_bound(u, v, A, B, C, xc + float(dx), yc + float(dy), xc, yc, p64,
+                                                  staging_f32)
                 err = abs(float(p32) - p64)
                 assert err <= bound, (trial, lane_x, lane_y, err, bound)
                 if bound > 0:
