@@ -152,10 +152,12 @@ __device__ __forceinline__ int view_of_tile(const ViewTable* vt, int tile)
 // 15 - i of its row, row_half_mirror with 7 - i of its half-row, quad_perm
 // permutes within quads.
 
+// (every lane's source lies inside the wave for these patterns; bound_ctrl
+// lets the compiler fold the move into the consuming add as a DPP operand)
 template <int CTRL>
 __device__ __forceinline__ float dpp(float x)
 {
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, false));
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 #define GSR_DPP_QUAD_XOR1 0xB1
 #define GSR_DPP_QUAD_XOR2 0x4E
@@ -177,30 +179,39 @@ __device__ __forceinline__ float swap_sum16(float a, float b)
     return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Transposed reduction of 9 values over the wave.  Afterwards lane 8k
-// (k < 8) holds the 64-lane total of v[k] and lane 1 the total of v[8].
-// Each exchange keeps half of the values and adds the partner lane's copy
-// of that half; v[8] rides along paired with zeros into lanes 0-15 and is
-// finished inside row 0.
-__device__ __forceinline__ float wave_sum9_transposed(const float (&v)[9], int lane)
+// Transposed reduction of 8 values over the wave.  Afterwards lane 8k holds
+// the 64-lane total of v[k].  Each exchange keeps half of the values and adds
+// the partner lane's copy of that half.
+__device__ __forceinline__ float wave_sum8_transposed(const float (&v)[9], int lane)
 {
     float a[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) a[j] = swap_sum32(v[j], v[4 + j]);  // lane ^ 32
-    float w = swap_sum32(v[8], 0.0f);
-    float b0 = swap_sum16(a[0], a[2]), b1 = swap_sum16(a[1], a[3]);  // lane ^ 16
-    w = swap_sum16(w, 0.0f);
+    const float b0 = swap_sum16(a[0], a[2]), b1 = swap_sum16(a[1], a[3]);  // lane ^ 16
     // mirror partner in the row (bit 3 complemented)
     const bool hi = lane & 8;
     float s = (hi ? b1 : b0) + dpp<GSR_DPP_ROW_MIRROR>(hi ? b0 : b1);
     s += dpp<GSR_DPP_ROW_HALF_MIRROR>(s);
     s += dpp<GSR_DPP_QUAD_XOR2>(s);
     s += dpp<GSR_DPP_QUAD_XOR1>(s);
+    return s;
+}
+
+// Totals of two values over the wave in one chain: afterwards every lane of
+// rows 0 and 1 holds the total of x, every lane of rows 2 and 3 that of y
+// (lanes 1 and 33, say).  The exchange at distance 32 folds x into the lower
+// half and y into the upper; the one at distance 16, of that result with
+// itself, leaves each half's two rows with their sum; four DPP adds finish
+// inside each row.
+__device__ __forceinline__ float wave_sum_pair(float x, float y)
+{
+    float w = swap_sum32(x, y);
+    w = swap_sum16(w, w);
     w += dpp<GSR_DPP_QUAD_XOR1>(w);
     w += dpp<GSR_DPP_QUAD_XOR2>(w);
     w += dpp<GSR_DPP_ROW_HALF_MIRROR>(w);
     w += dpp<GSR_DPP_ROW_MIRROR>(w);
-    return lane == 1 ? w : s;
+    return w;
 }
 
 __device__ __forceinline__ void atomic_add_f64(double* p, double v)

@@ -177,6 +177,15 @@ __device__ __forceinline__ TileCtx<PPT> tile_ctx(const RasterArgs& a)
     return c;
 }
 
+// Whether an entry of opacity o can have a clamped alpha anywhere (alpha =
+// o G with G <= 1): o >= alpha_max.  Both are positive floats, whose order is
+// their bit patterns' order, so the test runs on the scalar unit with the
+// first lane's o (the staged record is the same for every lane).
+__device__ __forceinline__ bool may_clamp(float o, float amax)
+{
+    return __builtin_amdgcn_readfirstlane(__float_as_int(o)) >= __float_as_int(amax);
+}
+
 // Walks the batch in LDS for the lane's pixels.  A pixel that has stopped
 // (or lies outside the view) carries a NaN row offset, so every later test
 // power2 >= thr fails for it without a per-pixel flag.  Reaching T_min is
@@ -387,6 +396,98 @@ __device__ __forceinline__ void view_done(const RasterArgs& a, int tile, int lan
     if ((old + 1ull) % tiles == 0ull) a.stamps[v] = (unsigned long long)wall_clock64();
 }
 
+// Adds a tile's total of screen-space field f to slot's accumulator: an FP64
+// atomic, or (deterministic mode) the exact fixed-point limbs.
+template <bool DET>
+__device__ __forceinline__ void add_field(const RasterArgs& a, uint32_t slot, int f, float value)
+{
+    if (DET) fixed_add(a.acc + GSR_G2 * GSR_FIX_LIMBS * (int64_t)slot + f, GSR_G2, value);
+    else atomic_add_f64(&a.grad2d[GSR_G2 * (int64_t)slot + f], (double)value);
+}
+
+// The ninth field (the blue colour partial) of a reduced entry waits for the
+// next reduced entry's, and the two are summed over the wave in one chain
+// (wave_sum_pair); slot is wave-uniform.
+struct PendingField {
+    bool have;
+    uint32_t slot;
+    float w;
+};
+
+// One entry of the backward replay for the lane's pixels, then the wave's
+// reduction of the entry's nine screen-space partials and their addition to
+// the slot's accumulators.  Per pixel, with rcp = 1 / (1 - alpha), T_j = T
+// rcp the transmittance before the entry, gcol = g . c and gsk the running
+// g . (colour behind) + dL/dT_final T_final:
+//   dL/dalpha = T_j gcol - gsk rcp,
+//   gsk'      = gsk + alpha T_j gcol,
+//   dd        = alpha dL/dalpha = gsk' - gsk rcp   (one FMA);
+// a pixel the entry does not reach takes alpha = 0, for which rcp(1) = 1
+// exactly, so T, gsk and every partial stay unchanged without selects.
+// CLAMP: the entry may clamp at alpha_max (o >= alpha_max), where alpha has
+// no gradient (dd = 0) but still attenuates.
+template <int PPT, bool CLAMP, bool DET>
+__device__ __forceinline__ void bwd_entry(const RasterArgs& a, const LdsRec& r, const ColTerms& ct,
+                                          const float (&p2)[PPT], const bool (&on)[PPT], float amax,
+                                          const TileCtx<PPT>& c, const float (&g0)[PPT], const float (&g1)[PPT],
+                                          const float (&g2)[PPT], const float (&dy2)[PPT], float (&T)[PPT],
+                                          float (&gsk)[PPT], int lane, PendingField& pend)
+{
+    float c0s = 0.0f, c1s = 0.0f, c2s = 0.0f, D = 0.0f, Dy = 0.0f, Dyy = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const float a_raw = r.p1.z * __builtin_amdgcn_exp2f(p2[k]);
+        const float alpha = on[k] ? (CLAMP ? fminf(a_raw, amax) : a_raw) : 0.0f;
+        const float rcp = __builtin_amdgcn_rcpf(1.0f - alpha);
+        const float Tb = T[k] * rcp;
+        const float gcol = __builtin_fmaf(g0[k], r.p2.x, __builtin_fmaf(g1[k], r.p2.y, g2[k] * r.p2.z));
+        const float wgt = alpha * Tb;
+        c0s = __builtin_fmaf(g0[k], wgt, c0s);
+        c1s = __builtin_fmaf(g1[k], wgt, c1s);
+        c2s = __builtin_fmaf(g2[k], wgt, c2s);
+        const float gsk_new = __builtin_fmaf(wgt, gcol, gsk[k]);
+        float dd = __builtin_fmaf(-gsk[k], rcp, gsk_new);
+        if (CLAMP) dd = a_raw < amax ? dd : 0.0f;
+        gsk[k] = gsk_new;
+        T[k] = Tb;
+        D += dd;
+        Dy = __builtin_fmaf(dd, c.dy[k], Dy);
+        Dyy = __builtin_fmaf(dd, dy2[k], Dyy);
+    }
+    // power2 partials per pixel: d/du = -(2 a2 dx + b2 dy + gx),
+    // d/dv = -(b2 dx + 2 c2 dy + gy) (d = pixel - tile centre), and
+    // d/d(A, B, C) = k (fx^2, 2 fx fy, fy^2) with (fx, fy) = d + o the
+    // offset from the projected centre; d alpha / d o = alpha / o
+    const float fx = c.dx + r.p3.x;
+    const float Fy = __builtin_fmaf(r.p3.y, D, Dy);  // sum dd fy
+    float v[9];
+    v[0] = __builtin_fmaf(__builtin_fmaf(2.0f * r.p0.w, c.dx, r.p0.y), D, r.p1.x * Dy);
+    v[1] = __builtin_fmaf(ct.s1, D, 2.0f * r.p1.y * Dy);
+    v[2] = fx * (fx * D);
+    v[3] = fx * Fy;
+    v[4] = __builtin_fmaf(r.p3.y, Fy + Dy, Dyy);
+    v[5] = D;
+    v[6] = c0s;
+    v[7] = c1s;
+    v[8] = c2s;
+    const float s = wave_sum8_transposed(v, lane);
+    const uint32_t slot = __builtin_amdgcn_readfirstlane(__float_as_uint(r.p2.w));
+    if ((lane & 7) == 0) {
+        const int f = lane >> 3;
+        add_field<DET>(a, slot, f, s * (f == 5 ? r.p3.z : field_scale(f)));
+    }
+    if (pend.have) {
+        const float w = wave_sum_pair(pend.w, v[8]);
+        if (lane == 1) add_field<DET>(a, pend.slot, 8, w);
+        if (lane == 33) add_field<DET>(a, slot, 8, w);
+        pend.have = false;
+    } else {
+        pend.w = v[8];
+        pend.slot = slot;
+        pend.have = true;
+    }
+}
+
 template <int PPT, int GSR_BATCH, bool DET, bool MIXED>
 __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
 {
@@ -429,6 +530,7 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
     for (int off = 32; off > 0; off >>= 1) lane_max = max(lane_max, (uint32_t)__shfl_xor((int)lane_max, off, 64));
     const uint32_t end = range.x + min(lane_max, range.y - range.x);
 
+    PendingField pend{false, 0u, 0.0f};
     for (uint32_t hi_ = end; hi_ > range.x;) {
         const uint32_t lo_ = hi_ - range.x > (uint32_t)GSR_BATCH ? hi_ - GSR_BATCH : range.x;
         const int cnt = (int)(hi_ - lo_);
@@ -451,58 +553,19 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
                 any |= on[k];
             }
             if (!__any(any)) continue;
-            // colour partials, and the pixel moments of dd = alpha dL/dalpha
-            // (zero where alpha is clamped): D = sum dd, Dy = sum dd dy,
-            // Dyy = sum dd dy^2 over the lane's pixels (dx is common to them)
-            float c0s = 0.0f, c1s = 0.0f, c2s = 0.0f, D = 0.0f, Dy = 0.0f, Dyy = 0.0f;
-#pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                const float G = __builtin_amdgcn_exp2f(p2[k]);
-                const float a_raw = r.p1.z * G;
-                const bool clamped = !(a_raw < amax);
-                const float alpha = clamped ? amax : a_raw;
-                const float rcp = __builtin_amdgcn_rcpf(1.0f - alpha);
-                const float Tb = T[k] * rcp;
-                const float gcol = __builtin_fmaf(g0[k], r.p2.x, __builtin_fmaf(g1[k], r.p2.y, g2[k] * r.p2.z));
-                const float dalpha = __builtin_fmaf(Tb, gcol, -rcp * gsk[k]);
-                const float wgt = on[k] ? alpha * Tb : 0.0f;
-                c0s = __builtin_fmaf(g0[k], wgt, c0s);
-                c1s = __builtin_fmaf(g1[k], wgt, c1s);
-                c2s = __builtin_fmaf(g2[k], wgt, c2s);
-                gsk[k] = __builtin_fmaf(wgt, gcol, gsk[k]);
-                T[k] = on[k] ? Tb : T[k];
-                const float dd = (on[k] & !clamped) ? dalpha * alpha : 0.0f;
-                D += dd;
-                Dy = __builtin_fmaf(dd, c.dy[k], Dy);
-                Dyy = __builtin_fmaf(dd, dy2[k], Dyy);
-            }
-            // power2 partials per pixel: d/du = -(2 a2 dx + b2 dy + gx),
-            // d/dv = -(b2 dx + 2 c2 dy + gy) (d = pixel - tile centre), and
-            // d/d(A, B, C) = k (fx^2, 2 fx fy, fy^2) with (fx, fy) = d + o the
-            // offset from the projected centre; d alpha / d o = alpha / o
-            const float fx = c.dx + r.p3.x;
-            const float Fy = __builtin_fmaf(r.p3.y, D, Dy);  // sum dd fy
-            float v[9];
-            v[0] = __builtin_fmaf(__builtin_fmaf(2.0f * r.p0.w, c.dx, r.p0.y), D, r.p1.x * Dy);
-            v[1] = __builtin_fmaf(ct.s1, D, 2.0f * r.p1.y * Dy);
-            v[2] = fx * (fx * D);
-            v[3] = fx * Fy;
-            v[4] = __builtin_fmaf(r.p3.y, Fy + Dy, Dyy);
-            v[5] = D;
-            v[6] = c0s;
-            v[7] = c1s;
-            v[8] = c2s;
-            const float s = wave_sum9_transposed(v, lane);
-            const uint32_t slot = __float_as_uint(r.p2.w);
-            if ((lane & 7) == 0 || lane == 1) {
-                const int f = lane == 1 ? 8 : lane >> 3;
-                const float scale = f == 5 ? r.p3.z : field_scale(f);
-                if (DET) fixed_add(a.acc + GSR_G2 * GSR_FIX_LIMBS * (int64_t)slot + f, GSR_G2, s * scale);
-                else atomic_add_f64(&a.grad2d[GSR_G2 * (int64_t)slot + f], (double)(s * scale));
-            }
+            // alpha = o G <= o: only an entry with o >= alpha_max can clamp,
+            // a test uniform over the wave
+            if (may_clamp(r.p1.z, amax))
+                bwd_entry<PPT, true, DET>(a, r, ct, p2, on, amax, c, g0, g1, g2, dy2, T, gsk, lane, pend);
+            else
+                bwd_entry<PPT, false, DET>(a, r, ct, p2, on, amax, c, g0, g1, g2, dy2, T, gsk, lane, pend);
         }
         __syncthreads();
         hi_ = lo_;
+    }
+    if (pend.have) {  // the last reduced entry's ninth field, alone
+        const float w = wave_sum_pair(pend.w, 0.0f);
+        if (lane == 1) add_field<DET>(a, pend.slot, 8, w);
     }
     view_done(a, c.tile, lane);
 }
