@@ -156,6 +156,9 @@ typedef struct {
                          gsr_device_clock_hz) at which the last backward tile
                          of view v finished, for v < V, and at which the last
                          gsr_project began, at [V]: per-view latency of a step */
+    size_t live_mask; /* uint64 [ceil(n / 64)][V]: bit k of word [w][v] set
+                         when slot (v, 64 w + k) is live: its tile rectangle
+                         is not empty (written by gsr_project, read by gsr_bin) */
     size_t total;     /* workspace bytes */
 } gsr_layout;
 
@@ -197,8 +200,11 @@ gsr_status gsr_plan_get_info(const gsr_plan *plan, gsr_plan_info *out);
 gsr_status gsr_project(gsr_plan *plan, const gsr_gaussians *g, const float *poses, void *stream);
 
 /* Builds the depth-ordered per-tile lists from the geom / conic_o / qthr /
- * rgb_d records (candidate tiles: the slot's rectangle; kept: the tiles whose
- * pixel-centre box reaches d^T conic d <= qthr):
+ * rgb_d records of the slots that live_mask marks (candidate tiles: the
+ * slot's rectangle; kept: the tiles whose pixel-centre box reaches
+ * d^T conic d <= qthr).  gsr_project writes the records and the mask; a
+ * caller that writes records itself also sets the mask bit of every slot
+ * with a non-empty rectangle (other bits add no pair):
  * pair emission, stable LSD radix sort of (tile | depth) keys with slot
  * values, tile ranges.  When the pair count exceeds the capacity, a device
  * flag is set, no pair is written, gsr_render_fwd writes NaN images and

@@ -48,6 +48,8 @@ struct gsr_plan {
     size_t off_counters = 0, off_views = 0, off_geom = 0, off_conic = 0, off_rgbd = 0, off_qthr = 0, off_grad2d = 0, off_acc = 0;
     size_t off_stage = 0;
     size_t off_keys = 0, off_vals = 0, off_seg = 0, off_ranges = 0, off_cnt = 0;
+    size_t off_live = 0, off_live_count = 0, off_live_mask = 0;
+    int64_t mask_words = 0;     // ceil(n / 64): liveness ballot words per view
     size_t off_xip = 0, off_xip_sh = 0, off_order = 0, off_buckets = 0, off_track = 0, off_map = 0, off_stamps = 0, off_left = 0, total = 0;
     char* ws = nullptr;
     Counters host_counters{};
@@ -222,18 +224,16 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->passes = 4 + (n > 1 ? (ilog2((int)std::min<int64_t>(n, 1ll << 30)) + 7) / 8 : 0);
     for (int v = 0; v < n_views; ++v)
         p->max_tiles_view = std::max(p->max_tiles_view, p->vt.v[v].tiles_x * p->vt.v[v].tiles_y);
-    // binning chunks of GSR_BIN_CHUNK * chunk_mult Gaussians per block: each
-    // block writes a count row of its view's tiles, so views with many tiles
-    // want larger chunks, while enough blocks must remain to keep every CU
-    // busy (measured on MI355X: 1024 Gaussians per block for views of up to
-    // 4096 tiles, 2048 beyond; smaller chunks while fewer than 4096 blocks
-    // would exist)
-    auto chunks_for = [&](int m) {
-        return (int64_t)((n + (int64_t)GSR_BIN_CHUNK * m - 1) / ((int64_t)GSR_BIN_CHUNK * m));
-    };
-    p->chunk_mult = (p->max_tiles_view <= 4096 ? 1024 : 2048) / GSR_BIN_CHUNK;
-    while (p->chunk_mult > 1 && chunks_for(p->chunk_mult) * n_views < 4096) p->chunk_mult /= 2;
-    p->chunks = (int32_t)std::max<int64_t>(1, chunks_for(p->chunk_mult));
+    // binning chunks of GSR_BIN_CHUNK * chunk_mult live slots per block (the
+    // slots of a view whose tile rectangle is not empty, listed by the
+    // binning's first pass).  Each block writes a count row of its view's
+    // tiles; one staged group per block measured best on MI355X (larger
+    // chunks shorten the count matrix but leave fewer, longer blocks).  The
+    // grid is sized for a view whose every slot is live, and blocks past a
+    // view's live count exit at once
+    p->chunk_mult = GSR_BIN_CHUNK_MULT;
+    p->chunks = (int32_t)std::max<int64_t>(
+        1, (n + (int64_t)GSR_BIN_CHUNK * p->chunk_mult - 1) / ((int64_t)GSR_BIN_CHUNK * p->chunk_mult));
     p->bwd_blocks = (int32_t)((n + 255) / 256);
     if (p->bwd_blocks == 0) p->bwd_blocks = 1;
 
@@ -260,6 +260,11 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->off_order = take(sizeof(uint32_t) * tiles);
     p->off_buckets = take(sizeof(uint32_t) * 66);
     p->off_cnt = take(sizeof(uint32_t) * (size_t)p->chunks * (size_t)tiles);
+    p->mask_words = (n + 63) / 64;
+    p->off_live_mask = take(sizeof(uint64_t) * (size_t)n_views * (size_t)p->mask_words);
+    p->off_live = take(sizeof(uint32_t) * S);
+
+    p->off_live_count = take(sizeof(uint32_t) * GSR_LIVE_STRIDE * GSR_MAX_VIEWS);  // one 256-byte line per view
     p->off_xip = take(sizeof(double) * 6 * (size_t)n_views * p->bwd_blocks);
     p->off_xip_sh = take(sizeof(double) * 6 * (size_t)n_views * p->bwd_blocks);
     p->off_track = take(sizeof(double) * GSR_TRACK_SLOTS * GSR_TRACK_BLOCKS * (size_t)n_views);
@@ -294,9 +299,12 @@ extern "C" gsr_status gsr_plan_bind(gsr_plan* plan, void* workspace, size_t byte
     // empty tile ranges and an identity tile order until the first binning
     if (e == hipSuccess)
         e = hipMemsetAsync(plan->ws + plan->off_ranges, 0, sizeof(uint2) * (size_t)plan->total_tiles, s);
-    // the per-view tile counters of the completion stamps start at zero
+    // the per-view tile counters of the completion stamps start at zero, and
+    // the live lists empty until the first projection
     if (e == hipSuccess)
         e = hipMemsetAsync(plan->ws + plan->off_left, 0, sizeof(unsigned long long) * (size_t)plan->V, s);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(plan->ws + plan->off_live_mask, 0, sizeof(uint64_t) * (size_t)plan->V * plan->mask_words, s);
     if (e == hipSuccess) {
         plan->identity_order.resize((size_t)plan->total_tiles);
         for (int32_t t = 0; t < plan->total_tiles; ++t) plan->identity_order[(size_t)t] = (uint32_t)t;
@@ -329,6 +337,7 @@ extern "C" gsr_status gsr_plan_layout(const gsr_plan* plan, gsr_layout* out)
     out->vals = plan->off_vals;
     out->ranges = plan->off_ranges;
     out->stamps = plan->off_stamps;
+    out->live_mask = plan->off_live_mask;
     out->total = plan->total;
     return GSR_OK;
 }
@@ -395,6 +404,8 @@ extern "C" gsr_status gsr_project(gsr_plan* plan, const gsr_gaussians* g, const 
     a.acc = plan->cfg.deterministic ? at<unsigned long long>(plan, plan->off_acc) : nullptr;
     a.stamps = at<unsigned long long>(plan, plan->off_stamps);
     a.counters = at<Counters>(plan, plan->off_counters);
+    a.live_mask = at<uint64_t>(plan, plan->off_live_mask);
+    a.mask_words = plan->mask_words;
     Timed t(plan, GSR_T_PROJECT, (hipStream_t)stream);
     hipError_t e = launch_project(a, plan->cfg.sh_degree, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_project");
@@ -419,6 +430,10 @@ extern "C" gsr_status gsr_bin(gsr_plan* plan, void* stream)
     b.chunk_mult = plan->chunk_mult;
     b.total_tiles = plan->total_tiles;
     b.cnt = at<uint32_t>(plan, plan->off_cnt);
+    b.live_mask = at<uint64_t>(plan, plan->off_live_mask);
+    b.mask_words = plan->mask_words;
+    b.live = at<uint32_t>(plan, plan->off_live);
+    b.live_count = at<uint32_t>(plan, plan->off_live_count);
     b.counters = at<Counters>(plan, plan->off_counters);
     b.ranges = at<uint2>(plan, plan->off_ranges);
     b.seg = at<unsigned long long>(plan, plan->off_seg);

@@ -57,6 +57,7 @@ struct Counters {
     unsigned long long capacity;
     uint32_t pad[10];
 };
+static_assert(sizeof(Counters) == 64, "Counters is 64 bytes");
 
 // Per live slot, the record the compositing kernels stage from: the projected
 // centre and conic in double (each tile expands the quadratic form around its

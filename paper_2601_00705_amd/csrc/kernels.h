@@ -17,6 +17,8 @@ struct ProjectArgs {
     unsigned long long* acc;   // [slots][GSR_FIX_LIMBS][9] (deterministic mode) or null, zeroed for live slots
     Counters* counters;
     unsigned long long* stamps;  // [V + 1]: [V] = device wall clock when the projection starts
+    uint64_t* live_mask;       // [mask_words][views]: bit k of word [w][v] set when slot (v, 64 w + k) is live
+    int64_t mask_words;        // ceil(n / 64)
 };
 
 struct BinArgs {
@@ -28,8 +30,12 @@ struct BinArgs {
     const float4* conic_o;
     const float* qthr;
     const float4* rgb_d;
-    int32_t chunks;            // chunks of GSR_BIN_CHUNK * chunk_mult Gaussians per view
+    int32_t chunks;            // most chunks of GSR_BIN_CHUNK * chunk_mult live slots a view can have
     int32_t chunk_mult;
+    const uint64_t* live_mask; // [mask_words][views]: the projection's liveness ballots
+    int64_t mask_words;
+    uint32_t* live;            // [views][n]: per view, the live Gaussians (built by the binning)
+    uint32_t* live_count;      // their number, view v's at [GSR_LIVE_STRIDE v]
     int32_t total_tiles;
     uint32_t* cnt;             // per view: [chunks][tiles of the view] pair counts, then offsets
     Counters* counters;
@@ -283,6 +289,11 @@ struct FrameArgs {
 #define GSR_TRACK_SLOTS 8           // partial sums per block (4 exposure sums, 3 loss/sign sums)
 #define GSR_BIN_CHUNK 256           // Gaussians staged in LDS at a time by the binning blocks (x256)
 #define GSR_BIN_LDS_TILES 16384     // views with more tiles count and place with global atomics
+#ifndef GSR_BIN_CHUNK_MULT
+#define GSR_BIN_CHUNK_MULT 1        // live slots per binning chunk, in units of GSR_BIN_CHUNK
+#endif
+#define GSR_LIVE_STRIDE 64          // uint32 between two views' live counters (one 256-byte line each)
+#define GSR_XCDS 8                  // accelerator dies; workgroups are dealt to them in turn
 #define GSR_SEG_SMALL_THREADS 256   // segments below GSR_SEG_SMALL_ITEMS keys: 256-thread blocks
 #define GSR_SEG_SMALL_ITEMS 2048
 #define GSR_SEG_THREADS 512

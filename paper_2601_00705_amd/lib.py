@@ -49,7 +49,7 @@ class Grads(ctypes.Structure):
 class Layout(ctypes.Structure):
     _fields_ = [(k, ctypes.c_size_t) for k in
                 ("counters", "geom", "conic_o", "rgb_d", "qthr", "stage", "grad2d", "keys", "vals", "ranges",
-                 "stamps", "total")]
+                 "stamps", "live_mask", "total")]
 
 
 class SeedView(ctypes.Structure):

@@ -96,6 +96,9 @@ class Renderer:
             "rgb_d": self._view(L.rgb_d, 4 * S, torch.float32).view(S, 4),
             "qthr": self._view(L.qthr, S, torch.float32),
             "grad2d": self._view(L.grad2d, 9 * S, torch.float64).view(S, 9),
+            # bit k of word [w][v] set when slot (v, 64 w + k) is live
+            "live_mask": self._view(L.live_mask, len(self.cams) * ((self.n + 63) // 64),
+                                    torch.int64).view(-1, len(self.cams)),
         }
 
     def stamps(self):

@@ -63,7 +63,7 @@ def test_plan_info_and_layout():
         assert info.slots == 2000 and info.total_pixels == 64 * 48 + 1200 * 680
         assert info.tile_bits == 12 and info.sort_passes == 6
         lay = lib.gsr_plan_layout(plan)
-        offs = [lay.counters, lay.geom, lay.conic_o, lay.rgb_d, lay.grad2d, lay.ranges]
+        offs = [lay.counters, lay.geom, lay.conic_o, lay.rgb_d, lay.grad2d, lay.ranges, lay.live_mask]
         assert all(o % 256 == 0 for o in offs)
         assert lay.total == lib.gsr_plan_workspace_bytes(plan) and lay.total > 2000 * 48
         # calls on an unbound plan fail before touching the device

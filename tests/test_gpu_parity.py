@@ -110,6 +110,8 @@ def _fill_and_bin(R, rec_arrays):
     rec["conic_o"][:, :3].copy_(torch.from_numpy(np.stack([A, B, C], 1)))
     rec["qthr"].copy_(torch.from_numpy(qthr))
     rec["rgb_d"][:, 3].copy_(torch.from_numpy(depth))
+    # every slot marked live: those with an empty rectangle add no pair
+    rec["live_mask"].fill_(-1)
     R.bin()
     return R.pair_count()
 
