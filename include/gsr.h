@@ -269,7 +269,11 @@ gsr_status gsr_loss_mapping(gsr_plan *plan, const float *rgb, const float *targe
 /* Backward of gsr_render_fwd (call after it, on the same plan, without an
  * intervening gsr_project or gsr_bin).  T_final and n_contrib are the buffers
  * the forward wrote (read only).  dL_dT may be NULL (zero).  pose_only: HOST array
- * [n_views] of 0/1 or NULL; views flagged 1 contribute to d_xi only.  grads
+ * [n_views] of 0/1 or NULL; views flagged 1 contribute to d_xi only.  It is
+ * read when the call is made and passed to the kernels by value, so a call
+ * captured into a graph keeps the flags it was captured with: replays see
+ * later changes to the poses and parameters (device memory) but not to
+ * pose_only (capture again to change which views are pose-only).  grads
  * may be NULL (pose gradients only); d_xi: device [n_views][6] or NULL.
  * g and poses must be the values given to gsr_project. */
 gsr_status gsr_render_bwd(gsr_plan *plan, const gsr_gaussians *g, const float *poses, const float *T_final,
