@@ -117,6 +117,8 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="re-run the tile/batch autotuner")
     ap.add_argument("--copy-probe", action="store_true", help="run a plain device copy of known size first")
     ap.add_argument("--no-seeding", action="store_true", help="skip the seeding measurement")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the loss and map-maintenance measurements (short profiler runs)")
     ap.add_argument("--no-mixed", action="store_true", help="skip timing the mixed-precision variant")
     ap.add_argument("--precision", choices=("fp32", "mixed"), default="fp32",
                     help="precision of the headline step (default fp32)")
@@ -731,12 +733,13 @@ def main():
     # calls: eager launches would time the host's launch gaps)
     reps = max(3, args.steps // 4)
     track = mapl = None
-    if args.precision == "fp32":
+    if args.precision == "fp32" and not args.no_extras:
         track, mapl = loss_measurements(torch, st, total_px, reps)
 
     # ---------------- seeding and map maintenance at the workload's size ----
     seed_res = None if args.no_seeding else seeding_measurement(torch, max(3, args.steps // 4), log)
-    maint = maintenance_measurement(torch, w, params, st.T, R.cams, max(3, args.steps // 4), log)
+    maint = None if args.no_extras else maintenance_measurement(torch, w, params, st.T, R.cams,
+                                                                max(3, args.steps // 4), log)
 
     # ---------------- CPU baseline: the oracle on a bounded sample -----
     cpu = None if args.no_cpu_baseline else cpu_baseline(w, cfg, args)
