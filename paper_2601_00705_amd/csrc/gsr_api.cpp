@@ -48,7 +48,7 @@ struct gsr_plan {
     size_t off_counters = 0, off_views = 0, off_geom = 0, off_conic = 0, off_rgbd = 0, off_qthr = 0, off_grad2d = 0, off_acc = 0;
     size_t off_stage = 0;
     size_t off_keys = 0, off_vals = 0, off_seg = 0, off_ranges = 0, off_cnt = 0;
-    size_t off_live = 0, off_live_count = 0, off_live_mask = 0;
+    size_t off_live = 0, off_live_count = 0, off_live_mask = 0, off_fwd_queue = 0;
     int64_t mask_words = 0;     // ceil(n / 64): liveness ballot words per view
     size_t off_xip = 0, off_xip_sh = 0, off_order = 0, off_buckets = 0, off_track = 0, off_map = 0, off_stamps = 0, off_left = 0, total = 0;
     char* ws = nullptr;
@@ -259,6 +259,7 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->off_ranges = take(sizeof(uint2) * tiles);
     p->off_order = take(sizeof(uint32_t) * tiles);
     p->off_buckets = take(sizeof(uint32_t) * 66);
+    p->off_fwd_queue = take(sizeof(uint32_t));
     p->off_cnt = take(sizeof(uint32_t) * (size_t)p->chunks * (size_t)tiles);
     p->mask_words = (n + 63) / 64;
     p->off_live_mask = take(sizeof(uint64_t) * (size_t)n_views * (size_t)p->mask_words);
@@ -487,6 +488,7 @@ static RasterArgs raster_args(const gsr_plan* plan)
     a.slots = plan->n * plan->V;
     a.tiles_done = at<unsigned long long>(plan, plan->off_left);
     a.stamps = at<unsigned long long>(plan, plan->off_stamps);
+    a.fwd_queue = at<uint32_t>(plan, plan->off_fwd_queue);
     return a;
 }
 
@@ -504,7 +506,7 @@ extern "C" gsr_status gsr_render_fwd(gsr_plan* plan, void* rgb, float* T_final, 
     a.n_blend = n_blend;
     Timed t(plan, GSR_T_RASTER_FWD, (hipStream_t)stream);
     hipError_t e = launch_raster_fwd(a, plan->total_tiles, plan->cfg.tile_w * plan->cfg.tile_h, plan->cfg.batch,
-                                     (hipStream_t)stream);
+                                     (hipStream_t)stream, plan->side, plan->fork_ev, plan->join_ev);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_render_fwd");
 }
 

@@ -76,6 +76,7 @@ struct RasterArgs {
     float* T_final;            // [sum H W]
     int32_t* n_contrib;        // [sum H W]
     int32_t* n_blend;          // nullable
+    uint32_t* fwd_queue;       // [1]: next (long tile, part) item of the split forward
     // backward only
     const float* T_final_in;   // forward outputs, read by the backward
     const int32_t* n_contrib_in;
@@ -300,6 +301,12 @@ struct FrameArgs {
 #define GSR_SEG_ITEMS 8192          // segments below this size are sorted in LDS by 512-thread blocks
 #define GSR_SEG_LONG_THREADS 1024   // longer segments: one 1024-thread block each
 #define GSR_SEG_LONG_ITEMS 16384    // ... holding this many keys in LDS
+#define GSR_FWD_LONG 4096           // least list length of a tile composited in parts (power of 2)
+#define GSR_FWD_WAVES 5120          // resident compositing waves (256 CUs x 4 SIMDs x 5)
+#ifndef GSR_FWD_SPLIT
+#define GSR_FWD_SPLIT 2             // parts of a long tile (at most the pixels per lane)
+#endif
+#define GSR_FWD_LONG_WAVES 1024     // persistent waves of the long tiles' parts
 
 hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t s);
 // pair counting, offsets, emission into per-tile segments; max_tiles_view is
@@ -308,7 +315,8 @@ hipError_t launch_bin(const BinArgs& a, int max_tiles_view, hipStream_t s);
 hipError_t launch_order(const RangeArgs& a, hipStream_t s);
 hipError_t launch_seg_sort(const SegArgs& a, int total_tiles, int64_t capacity, hipStream_t s, hipStream_t side,
                            hipEvent_t fork, hipEvent_t join);
-hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s);
+hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s,
+                             hipStream_t side, hipEvent_t fork, hipEvent_t join);
 hipError_t launch_clear_grad2d(const RasterArgs& a, hipStream_t s);
 hipError_t launch_raster_bwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s);
 hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, float* d_xi, int n_views,

@@ -147,12 +147,14 @@ struct TileCtx {
     __device__ __forceinline__ int64_t rgb0(int k) const { return pix(k) + 2 * (int64_t)pix_base; }
 };
 
+// The lane's PPT pixels of `tile`, starting at pixel k0 of the lane's
+// column in the tile (rows (lane >> log2 tw) + (k0 + k) * rs); k0 = 0 and the
+// tile's full PPT for a whole tile, a sub-range for a part of a split tile.
 template <int PPT>
-__device__ __forceinline__ TileCtx<PPT> tile_ctx(const RasterArgs& a)
+__device__ __forceinline__ TileCtx<PPT> tile_ctx_at(const RasterArgs& a, int tile, int k0)
 {
     TileCtx<PPT> c;
-    c.tile = (int)a.order[blockIdx.x];
-    const int tile = c.tile;
+    c.tile = tile;
     const int v = view_of_tile(a.views, tile);
     const ViewInfo& vw = a.views->v[v];
     const int lt = tile - vw.tile_base;
@@ -161,8 +163,8 @@ __device__ __forceinline__ TileCtx<PPT> tile_ctx(const RasterArgs& a)
     const int lane = threadIdx.x;
     const int l2 = a.cfg.log2_tw;
     c.px = tx * a.cfg.tile_w + (lane & (a.cfg.tile_w - 1));
-    c.py0 = ty * a.cfg.tile_h + (lane >> l2);
     c.rs = 64 >> l2;
+    c.py0 = ty * a.cfg.tile_h + (lane >> l2) + k0 * c.rs;
     c.plane = (int64_t)vw.width * vw.height;
     c.xc = (double)(tx * a.cfg.tile_w) + 0.5 * a.cfg.tile_w;
     c.yc = (double)(ty * a.cfg.tile_h) + 0.5 * a.cfg.tile_h;
@@ -173,8 +175,15 @@ __device__ __forceinline__ TileCtx<PPT> tile_ctx(const RasterArgs& a)
     c.base = (int64_t)vw.pix_base + (int64_t)c.py0 * vw.width + c.px;
 #pragma unroll
     for (int k = 0; k < PPT; ++k)
-        c.dy[k] = (float)((lane >> l2) + k * c.rs) + 0.5f - 0.5f * (float)a.cfg.tile_h;
+        c.dy[k] = (float)((lane >> l2) + (k0 + k) * c.rs) + 0.5f - 0.5f * (float)a.cfg.tile_h;
     return c;
+}
+
+// the workgroup's tile (processing order) and all of its pixels
+template <int PPT>
+__device__ __forceinline__ TileCtx<PPT> tile_ctx(const RasterArgs& a)
+{
+    return tile_ctx_at<PPT>(a, (int)a.order[blockIdx.x], 0);
 }
 
 // Whether an entry of opacity o can have a clamped alpha anywhere (alpha =
@@ -253,10 +262,8 @@ __device__ __forceinline__ void fwd_batch(const LdsRec* rec, int cnt, uint32_t p
 // COUNT: also count the blended entries per pixel (into a.n_blend); a
 // separate instantiation, so that the plain forward carries no counters
 template <int PPT, int GSR_BATCH, bool COUNT, bool MIXED>
-__global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
+__device__ __forceinline__ void fwd_tile(const RasterArgs& a, const TileCtx<PPT>& c, LdsRec* rec)
 {
-    __shared__ LdsRec rec[GSR_BATCH];
-    const TileCtx<PPT> c = tile_ctx<PPT>(a);
     const int lane = threadIdx.x;
     const bool overflow = a.counters->overflow != 0u;
     const uint2 range = overflow ? make_uint2(0u, 0u) : a.ranges[c.tile];
@@ -305,6 +312,82 @@ __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
         a.n_contrib[c.pix(k)] = (int32_t)last[k];
         if (COUNT) a.n_blend[c.pix(k)] = (int32_t)nb[k];
     }
+}
+
+// The longest tiles are split: a wave's time is its tile's list, and the
+// few longest lists would otherwise run alone at the end of the launch
+// (measured: emptying the longest 1 % of the tiles at window-1M-10views,
+// 5 % of the pairs, shortened the forward by 16 %).  A tile is long when
+// its list holds at least half the pairs a resident wave would composite
+// with the step's pairs spread evenly (GSR_FWD_WAVES resident waves), and
+// at least GSR_FWD_LONG, rounded up to a power of two.  The processing
+// order puts such tiles first (it is bucketed by floor(log2 length)), so
+// they are the order's first K tiles, found by binary search.  Each is
+// composited as FWD_SPLIT(PPT) parts, every part a wave with PPT / split of
+// the lane's pixels and the whole list; a pixel's arithmetic is the same
+// either way.  Splitting costs each part the whole list's per-entry work,
+// so it pays only for the tail: where most tiles' lists are long (the
+// 3M-Gaussian mapping views) the threshold rises with the pair count.
+template <int PPT>
+struct FwdSplit {
+    static constexpr int parts = PPT < GSR_FWD_SPLIT ? PPT : GSR_FWD_SPLIT;
+    static constexpr int ppt = PPT / parts;
+};
+
+__device__ __forceinline__ uint32_t long_threshold(const RasterArgs& a)
+{
+    const unsigned long long even = a.counters->pairs / (2ull * GSR_FWD_WAVES);
+    uint32_t t = GSR_FWD_LONG;
+    while ((unsigned long long)t < even && t < (1u << 30)) t <<= 1;
+    return t;
+}
+
+__device__ __forceinline__ int long_tiles(const RasterArgs& a, int total_tiles, uint32_t thr)
+{
+    int lo = 0, hi = total_tiles;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const uint2 r = a.ranges[a.order[mid]];
+        if (r.y - r.x < thr) hi = mid;
+        else lo = mid + 1;
+    }
+    return lo;
+}
+
+template <int PPT, int GSR_BATCH, bool COUNT, bool MIXED>
+__global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
+{
+    __shared__ LdsRec rec[GSR_BATCH];
+    const TileCtx<PPT> c = tile_ctx<PPT>(a);
+    if (FwdSplit<PPT>::parts > 1) {
+        const uint2 r = a.ranges[c.tile];
+        if (r.y - r.x >= long_threshold(a)) return;  // composited in parts by k_raster_fwd_long
+    }
+    fwd_tile<PPT, GSR_BATCH, COUNT, MIXED>(a, c, rec);
+}
+
+// Persistent waves that take (long tile, part) items from a queue (zeroed
+// before the launch) until the K long tiles' parts are done.
+template <int PPT, int GSR_BATCH, bool COUNT, bool MIXED>
+__global__ __launch_bounds__(64) void k_raster_fwd_long(RasterArgs a, int total_tiles)
+{
+    constexpr int S = FwdSplit<PPT>::parts, Q = FwdSplit<PPT>::ppt;
+    __shared__ LdsRec rec[GSR_BATCH];
+    const int items = long_tiles(a, total_tiles, long_threshold(a)) * S;
+    for (;;) {
+        uint32_t item = 0u;
+        if (threadIdx.x == 0) item = atomicAdd(a.fwd_queue, 1u);
+        item = (uint32_t)__builtin_amdgcn_readfirstlane((int)item);
+        if ((int)item >= items) break;
+        const int tile = (int)a.order[item / S];
+        const TileCtx<Q> c = tile_ctx_at<Q>(a, tile, (int)(item % S) * Q);
+        fwd_tile<Q, GSR_BATCH, COUNT, MIXED>(a, c, rec);
+    }
+}
+
+__global__ void k_zero_queue(uint32_t* q)
+{
+    *q = 0u;
 }
 
 // scale of field f (du, dv, dA, dB, dC, -, dr, dg, db) from the reduced
@@ -570,26 +653,37 @@ __global__ __launch_bounds__(64) void k_raster_bwd(RasterArgs a)
     view_done(a, c.tile, lane);
 }
 
+template <int PPT, int B, bool COUNT, bool MIXED>
+static void launch_fwd_b(const RasterArgs& a, int tiles, hipStream_t s, hipStream_t side)
+{
+    if (FwdSplit<PPT>::parts > 1) {
+        hipLaunchKernelGGL(k_zero_queue, dim3(1), dim3(1), 0, side, a.fwd_queue);
+        hipLaunchKernelGGL((k_raster_fwd_long<PPT, B, COUNT, MIXED>), dim3(GSR_FWD_LONG_WAVES), dim3(64), 0, side,
+                           a, tiles);
+    }
+    hipLaunchKernelGGL((k_raster_fwd<PPT, B, COUNT, MIXED>), dim3(tiles), dim3(64), 0, s, a);
+}
+
 template <int PPT, bool COUNT, bool MIXED>
-static hipError_t launch_fwd_c(const RasterArgs& a, int tiles, int batch, hipStream_t s)
+static hipError_t launch_fwd_c(const RasterArgs& a, int tiles, int batch, hipStream_t s, hipStream_t side)
 {
     switch (batch) {
-    case 64: hipLaunchKernelGGL((k_raster_fwd<PPT, 64, COUNT, MIXED>), dim3(tiles), dim3(64), 0, s, a); break;
-    case 128: hipLaunchKernelGGL((k_raster_fwd<PPT, 128, COUNT, MIXED>), dim3(tiles), dim3(64), 0, s, a); break;
-    case 256: hipLaunchKernelGGL((k_raster_fwd<PPT, 256, COUNT, MIXED>), dim3(tiles), dim3(64), 0, s, a); break;
+    case 64: launch_fwd_b<PPT, 64, COUNT, MIXED>(a, tiles, s, side); break;
+    case 128: launch_fwd_b<PPT, 128, COUNT, MIXED>(a, tiles, s, side); break;
+    case 256: launch_fwd_b<PPT, 256, COUNT, MIXED>(a, tiles, s, side); break;
     default: return hipErrorInvalidValue;
     }
     return hipSuccess;
 }
 
 template <int PPT>
-static hipError_t launch_fwd_t(const RasterArgs& a, int tiles, int batch, hipStream_t s)
+static hipError_t launch_fwd_t(const RasterArgs& a, int tiles, int batch, hipStream_t s, hipStream_t side)
 {
     if (a.cfg.mixed)
-        return a.n_blend ? launch_fwd_c<PPT, true, true>(a, tiles, batch, s)
-                         : launch_fwd_c<PPT, false, true>(a, tiles, batch, s);
-    return a.n_blend ? launch_fwd_c<PPT, true, false>(a, tiles, batch, s)
-                     : launch_fwd_c<PPT, false, false>(a, tiles, batch, s);
+        return a.n_blend ? launch_fwd_c<PPT, true, true>(a, tiles, batch, s, side)
+                         : launch_fwd_c<PPT, false, true>(a, tiles, batch, s, side);
+    return a.n_blend ? launch_fwd_c<PPT, true, false>(a, tiles, batch, s, side)
+                     : launch_fwd_c<PPT, false, false>(a, tiles, batch, s, side);
 }
 
 template <int PPT, bool DET, bool MIXED>
@@ -614,18 +708,26 @@ static hipError_t launch_bwd_t(const RasterArgs& a, int tiles, int batch, hipStr
                  : launch_bwd_d<PPT, false, false>(a, tiles, batch, s);
 }
 
-hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s)
+// The long tiles' parts run on `side`, forked from `s` and joined back (the
+// fork and join are graph edges when `s` is being captured).
+hipError_t launch_raster_fwd(const RasterArgs& a, int total_tiles, int tile_px, int batch, hipStream_t s,
+                             hipStream_t side, hipEvent_t fork, hipEvent_t join)
 {
     if (total_tiles == 0) return hipSuccess;
-    hipError_t e;
+    hipError_t e = hipEventRecord(fork, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
+    if (e != hipSuccess) return e;
     switch (tile_px) {
-    case 64: e = launch_fwd_t<1>(a, total_tiles, batch, s); break;
-    case 128: e = launch_fwd_t<2>(a, total_tiles, batch, s); break;
-    case 256: e = launch_fwd_t<4>(a, total_tiles, batch, s); break;
-    case 512: e = launch_fwd_t<8>(a, total_tiles, batch, s); break;
+    case 64: e = launch_fwd_t<1>(a, total_tiles, batch, s, side); break;
+    case 128: e = launch_fwd_t<2>(a, total_tiles, batch, s, side); break;
+    case 256: e = launch_fwd_t<4>(a, total_tiles, batch, s, side); break;
+    case 512: e = launch_fwd_t<8>(a, total_tiles, batch, s, side); break;
     default: return hipErrorInvalidValue;
     }
-    return e != hipSuccess ? e : hipGetLastError();
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e == hipSuccess) e = hipEventRecord(join, side);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
+    return e;
 }
 
 // zero the screen-space accumulators of every projected slot (rx >= 0) when
