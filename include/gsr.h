@@ -24,6 +24,9 @@
  *     the optimiser step of the appendix's settings with the anchor of Eq.
  *     (app-ema), the co-visibility score of Eq. (iou), and the pruning rule
  *     and merging of Sec. "Insertion, Lightweight Merging, and Pruning".
+ *   - gsr_spatial_order: a storage order of the map (a layout choice; the
+ *     method's sums do not depend on it) under which projection waves and
+ *     binning chunks hold Gaussians that are neighbours in space.
  *   - gsr_seed_triangulate, gsr_seed_scale, gsr_seed_frame: the one-shot
  *     Gaussian seeding of Sec. "Dense Feature Matching" (Eq. (conf),
  *     two-view linear triangulation) and the appendix's initialisation
@@ -484,6 +487,40 @@ gsr_status gsr_prune_noalloc(int64_t n, const int32_t *m_obs, const float *v_vis
  * overlapping); columns from *kept on are left as they are. */
 gsr_status gsr_compact(int64_t n, int32_t rows, const float *src, const int32_t *keep_index, const int64_t *kept,
                        float *dst, void *stream);
+
+/* Spatial storage order of a map.  The paper fixes no order for the
+ * Gaussians: every sum of Eqs. (alpha) and (color) runs over the
+ * depth-ordered set N(p), whatever the storage order, which only breaks ties
+ * of equal depth (by index).  This order is a layout choice that makes the
+ * Gaussians of a projection wave, and of a binning chunk, neighbours in
+ * space.  index[j] (device, [n]) receives the Gaussian to store at position
+ * j, a permutation of 0 .. n-1 to apply with gsr_compact (kept = n) to every
+ * plane of the map and of its optimiser state.  Definition, for means [3][n]
+ * (device, x, y, z planes):
+ *   1. lo_a, hi_a: the least and greatest coordinate a over the Gaussians
+ *      whose three coordinates are finite; w = max over a of hi_a - lo_a
+ *      (double);
+ *   2. cells: with w = m 2^e, m in [0.5, 1), q_a = min(1023,
+ *      floor((x_a - lo_a) 2^(10 - e))) in double; all 0 when w = 0;
+ *   3. code: the Morton interleave of q_x, q_y, q_z (bit k of q_x at bit
+ *      3k, of q_y at 3k + 1, of q_z at 3k + 2); 2^30 for a Gaussian with a
+ *      non-finite coordinate;
+ *   4. rank: place in the ascending order of (code, index);
+ *   5. with F = floor(n / brick) and P the least integer
+ *      >= max(1, floor(0.6180339887498949 F + 0.5)) coprime with F, position
+ *      j brick + k (j < F, k < brick) holds the Gaussian of rank
+ *      ((j P) mod F) brick + k, and positions from F brick on the Gaussian
+ *      of their own rank.
+ * So a brick of consecutive positions holds neighbours along the curve,
+ * and consecutive bricks come from far apart (brick >= n: the plain curve
+ * order).  The result is deterministic.  workspace: device, 256-byte
+ * aligned, gsr_spatial_order_workspace_bytes(n) bytes (0 for n out of
+ * range), not overlapping mean or index.  Errors: GSR_EINVAL for null
+ * pointers, n outside [1, 2^31), brick < 1, a short or misaligned
+ * workspace or overlapping buffers; nothing enqueued. */
+size_t gsr_spatial_order_workspace_bytes(int64_t n);
+gsr_status gsr_spatial_order(int64_t n, const float *mean, int32_t brick, int32_t *index, void *workspace,
+                             size_t workspace_bytes, void *stream);
 
 /* Merging of Sec. "Insertion, Lightweight Merging, and Pruning" (readings
  * where the paper is silent): i and j = nn_index[i] merge when they are

@@ -18,6 +18,7 @@
 
 #include "gsr.h"
 #include "kernels.h"
+#include "order.h"
 
 using namespace gsr;
 
@@ -1150,6 +1151,84 @@ extern "C" gsr_status gsr_compact(int64_t n, int32_t rows, const float* src, con
     a.dst = dst;
     hipError_t e = launch_compact(a, (hipStream_t)stream);
     return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_compact");
+}
+
+// ---- spatial storage order -------------------------------------------------
+
+// workspace carve-up of gsr_spatial_order: code[2], val[2], hist, box, each
+// on a 256-byte boundary
+static size_t order_layout(int64_t n, size_t off[6])
+{
+    const int64_t blocks = (n + GSR_RADIX_TILE - 1) / GSR_RADIX_TILE;
+    size_t at = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = at;
+        at = (at + bytes + 255) & ~(size_t)255;
+        return o;
+    };
+    for (int k = 0; k < 4; ++k) off[k] = take(sizeof(uint32_t) * (size_t)n);
+    off[4] = take(sizeof(uint32_t) * 256 * (size_t)blocks);
+    off[5] = take(sizeof(uint32_t) * 8);
+    return at;
+}
+
+extern "C" size_t gsr_spatial_order_workspace_bytes(int64_t n)
+{
+    if (n < 1 || n > (1ll << 31) - 1) return 0;
+    size_t off[6];
+    return order_layout(n, off);
+}
+
+// the least P >= max(1, floor(0.618... F + 0.5)) with gcd(P, F) = 1
+static int64_t brick_multiplier(int64_t full)
+{
+    if (full <= 1) return 1;
+    int64_t p = (int64_t)std::floor(0.6180339887498949 * (double)full + 0.5);
+    if (p < 1) p = 1;
+    for (;; ++p) {
+        int64_t x = p, y = full;
+        while (y) {
+            const int64_t t = x % y;
+            x = y;
+            y = t;
+        }
+        if (x == 1) return p;
+    }
+}
+
+extern "C" gsr_status gsr_spatial_order(int64_t n, const float* mean, int32_t brick, int32_t* index, void* workspace,
+                                        size_t workspace_bytes, void* stream)
+{
+    g_err.clear();
+    if (!mean || !index || !workspace) return fail(GSR_EINVAL, "null argument");
+    if (n < 1 || n > (1ll << 31) - 1) return fail(GSR_EINVAL, "n must lie in [1, 2^31)");
+    if (brick < 1) return fail(GSR_EINVAL, "brick must be at least 1");
+    if (((uintptr_t)workspace & 255) != 0) return fail(GSR_EINVAL, "workspace not 256-byte aligned");
+    size_t off[6];
+    const size_t need = order_layout(n, off);
+    if (workspace_bytes < need) return fail(GSR_EINVAL, "workspace smaller than gsr_spatial_order_workspace_bytes(n)");
+    const uintptr_t ws = (uintptr_t)workspace, ix = (uintptr_t)index, mn = (uintptr_t)mean;
+    const size_t ibytes = sizeof(int32_t) * (size_t)n, mbytes = sizeof(float) * 3 * (size_t)n;
+    if ((ix < ws + need && ws < ix + ibytes) || (ix < mn + mbytes && mn < ix + ibytes) ||
+        (mn < ws + need && ws < mn + mbytes))
+        return fail(GSR_EINVAL, "mean, index and workspace must not overlap");
+    OrderArgs a{};
+    a.n = n;
+    a.mean = mean;
+    char* base = (char*)workspace;
+    for (int k = 0; k < 2; ++k) {
+        a.code[k] = (uint32_t*)(base + off[k]);
+        a.val[k] = (uint32_t*)(base + off[2 + k]);
+    }
+    a.hist = (uint32_t*)(base + off[4]);
+    a.box = (uint32_t*)(base + off[5]);
+    a.blocks = (int32_t)((n + GSR_RADIX_TILE - 1) / GSR_RADIX_TILE);
+    a.brick = brick;
+    a.full = n / brick;
+    a.mult = brick_multiplier(a.full);
+    a.index = index;
+    hipError_t e = launch_spatial_order(a, (hipStream_t)stream);
+    return e == hipSuccess ? GSR_OK : hip_fail(e, "gsr_spatial_order");
 }
 
 extern "C" gsr_status gsr_device_clock_hz(double* hz)

@@ -126,6 +126,8 @@ def _load():
         "gsr_nearest": (st, [ctypes.c_int64, P, P, P, ctypes.c_size_t, P, P]),
         "gsr_merge": (st, [ctypes.c_int64, ctypes.c_int32, P, P, P, ctypes.c_double, ctypes.c_double, P, P, P]),
         "gsr_keep_list": (st, [ctypes.c_int64, P, P, P, P, P]),
+        "gsr_spatial_order_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int64]),
+        "gsr_spatial_order": (st, [ctypes.c_int64, P, ctypes.c_int32, P, P, ctypes.c_size_t, P]),
         "gsr_device_clock_hz": (st, [P]),
         "gsr_plan_set_timing": (st, [P, ctypes.c_int32]),
         "gsr_plan_read_timing": (st, [P, ctypes.c_int32, P, P]),
@@ -146,7 +148,8 @@ EXPORTS = ("gsr_plan_create", "gsr_plan_destroy", "gsr_plan_workspace_bytes", "g
            "gsr_plan_set_timing", "gsr_plan_read_timing", "gsr_status_str", "gsr_last_error",
            "gsr_seed_triangulate", "gsr_seed_scale_workspace_bytes", "gsr_seed_scale",
            "gsr_adam_step", "gsr_covis", "gsr_prune_workspace_bytes", "gsr_prune", "gsr_prune_noalloc", "gsr_compact",
-           "gsr_nearest", "gsr_merge", "gsr_keep_list", "gsr_seed_frame", "gsr_device_clock_hz")
+           "gsr_nearest", "gsr_merge", "gsr_keep_list", "gsr_seed_frame", "gsr_device_clock_hz",
+           "gsr_spatial_order_workspace_bytes", "gsr_spatial_order")
 
 # gsr_config.precision: float32 staging records and images, or the mixed
 # variant (32-byte records with binary16 colour, binary16 images)
@@ -418,6 +421,16 @@ def gsr_merge(n, colour_rows, params, v_vis, nn_index, radius, colour_tol, out, 
 def gsr_keep_list(n, mask, keep_index, kept, workspace, stream):
     return check(_lib.gsr_keep_list(int(n), _p(mask), _p(keep_index), _p(kept), _p(workspace),
                                     ctypes.c_void_p(stream)), "gsr_keep_list")
+
+
+def gsr_spatial_order_workspace_bytes(n):
+    return int(_lib.gsr_spatial_order_workspace_bytes(int(n)))
+
+
+def gsr_spatial_order(n, mean, brick, index, workspace, stream):
+    return check(_lib.gsr_spatial_order(int(n), _p(mean), int(brick), _p(index), _p(workspace),
+                                        workspace.numel() * workspace.element_size(), ctypes.c_void_p(stream)),
+                 "gsr_spatial_order")
 
 
 def gsr_seed_frame(n, mean, valid, err, angle, P_ref, centre_ref, radius, c_par, floor_scale, workspace, quat,

@@ -1,7 +1,8 @@
 """Map maintenance on the GPU: the optimiser step with the anchor of
 Eq. (app-ema), the co-visibility score of Eq. (iou), pruning and merging
-with compaction (the C ABI's gsr_adam_step, gsr_covis, gsr_prune,
-gsr_compact, gsr_nearest, gsr_merge, gsr_keep_list).
+with compaction, and the map's spatial storage order (the C ABI's
+gsr_adam_step, gsr_covis, gsr_prune, gsr_compact, gsr_nearest, gsr_merge,
+gsr_keep_list, gsr_spatial_order).
 Argument marshalling only; every step runs in the library's kernels."""
 from __future__ import annotations
 
@@ -117,3 +118,29 @@ def keep_list(mask):
     kept = torch.empty(1, dtype=torch.int64, device=dev)
     lib.gsr_keep_list(n, mask, keep, kept, ws, _stream(dev))
     return keep, kept
+
+
+# Gaussians per brick of the spatial order (see spatial_order)
+SPATIAL_BRICK = 128
+
+
+def spatial_order(mean, brick=SPATIAL_BRICK):
+    """Storage order of a map whose means are [3][n] (device): index [n]
+    int32, the Gaussian to store at each position.  Bricks of `brick`
+    consecutive positions hold neighbours along a Morton curve over the
+    map's box; consecutive bricks come from far apart."""
+    n = int(mean.shape[1])
+    dev = mean.device
+    ws = torch.empty(max(lib.gsr_spatial_order_workspace_bytes(n), 256), dtype=torch.uint8, device=dev)
+    index = torch.empty(n, dtype=torch.int32, device=dev)
+    lib.gsr_spatial_order(n, mean.contiguous(), brick, index, ws, _stream(dev))
+    return index
+
+
+def permute(planes, index):
+    """Every plane [rows][n] or [n] of `planes` (a dict of device float32
+    tensors: the map, or its optimiser state) gathered by index: column j of
+    the result is column index[j] of the input."""
+    n = int(index.shape[0])
+    kept = torch.full((1,), n, dtype=torch.int64, device=index.device)
+    return {k: compact(v.contiguous(), index, kept) for k, v in planes.items()}

@@ -234,3 +234,24 @@ def test_seed_argument_errors():
     assert frame(-1) == lib.EINVAL and frame(0) == 0
     assert raw.gsr_seed_frame(10, fake, fake, None, fake, P, c, 0.1, 1.0, 1e-4, fake, need, fake, fake,
                               None) == lib.EINVAL
+
+
+def test_spatial_order_argument_errors():
+    """gsr_spatial_order rejects bad arguments before touching the device (the
+    pointers are never read); the workspace size follows the layout."""
+    from paper_2601_00705_amd import lib
+    raw = lib.raw()
+    assert raw.gsr_spatial_order_workspace_bytes(0) == 0
+    assert raw.gsr_spatial_order_workspace_bytes(1 << 31) == 0
+    need = raw.gsr_spatial_order_workspace_bytes(10_000)
+    # four key/value buffers, 256 digit counts per 4096 keys, the box
+    assert need >= 4 * 4 * 10_000 + 4 * 256 * 3 + 32
+    ws = ctypes.c_void_p(1 << 30)
+    mean, idx = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 24)
+    ok = (10_000, mean, 128, idx, ws, need, None)
+    for bad in ((0,) + ok[1:], (1 << 31,) + ok[1:], ok[:2] + (0,) + ok[3:], ok[:1] + (None,) + ok[2:],
+                ok[:3] + (None,) + ok[4:], ok[:4] + (None,) + ok[5:], ok[:5] + (need - 1, None),
+                ok[:4] + (ctypes.c_void_p((1 << 30) + 64),) + ok[5:],  # misaligned workspace
+                ok[:3] + (ctypes.c_void_p((1 << 30) + 1024),) + ok[4:],  # index inside the workspace
+                (10_000, ctypes.c_void_p((1 << 24) + 4096)) + ok[2:]):  # mean overlaps index
+        assert raw.gsr_spatial_order(*bad) == lib.EINVAL, bad
