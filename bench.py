@@ -7,6 +7,11 @@ the L1 photometric gradient seed, compositing backward and projection
 backward (all parameters and the pose twists).  Inputs are synthetic and
 seeded (paper_2601_00705_amd.scenes) and resident in HBM before timing.
 
+The map is stored in the library's spatial order (gsr_spatial_order, as
+the map maintenance keeps it; the reorder runs once, outside the timed
+region, and is timed with the maintenance); a comparison leg times the same
+step on the generator's order.
+
 Batched mode: all views of the workload in one plan, the step captured once
 in a HIP graph (torch.cuda.CUDAGraph over the library's stream) and
 replayed.  Plain mode: one plan per view, launched view after view on one
@@ -128,6 +133,12 @@ def parse():
                     help="bitwise-reproducible backward (fixed-point accumulation)")
     ap.add_argument("--loss", choices=("l1", "track", "mapping"), default="l1",
                     help="gradient seed of the step: L1 (default), the tracking loss or the mapping loss")
+    ap.add_argument("--map-order", choices=("spatial", "given"), default="spatial",
+                    help="storage order of the map: the library's spatial order (default) or the generator's")
+    ap.add_argument("--brick", type=int, default=None,
+                    help="Gaussians per brick of the spatial order (default: the library's)")
+    ap.add_argument("--no-given", action="store_true",
+                    help="skip the comparison leg on the generator's order")
     return ap.parse_args()
 
 
@@ -277,7 +288,11 @@ def maintenance_measurement(torch, w, params, T_final, cams, reps, log):
       merging: per Gaussian, read its neighbour index, the neighbour's
             index, its visibility and every parameter row, write every row
             and the keep flag (8 + 4 + 2 x 4 x rows + 4 B), then the keep
-            list (two passes over the flags, 8 B, and the index, 4 B).
+            list (two passes over the flags, 8 B, and the index, 4 B);
+      spatial reorder: per Gaussian, the means twice (24 B), the codes and
+            indices written (8 B), four radix passes each reading them twice
+            and writing them once (4 x 24 B), the brick gather (8 B), then
+            every row gathered (12 B per row: index, read, write).
     The nearest-neighbour search before merging is a grid search, reported
     by its time only."""
     import numpy as np
@@ -317,12 +332,19 @@ def maintenance_measurement(torch, w, params, T_final, cams, reps, log):
     t_mg = _graph_ms(torch, merge_and_list, reps)
     rows = floats // n
     b_mg = (8 + 4 + 8 * rows + 4 + 8 + 4) * n
+
+    def reorder():
+        state["ord"] = maintain.permute(P, maintain.spatial_order(P["mean"]))
+
+    t_or = _graph_ms(torch, reorder, max(reps // 4, 2), calls=2)
+    b_or = (128 + 12 * rows) * n
     out = {"nearest": {"ms": t_nn, "work": f"{n} Gaussians"}}
     log(f"maintenance nearest: {t_nn:.4f} ms")
     for name, t, b, unit in (("adam", t_adam, b_adam, f"{floats} floats"),
                              ("covis", t_cov, b_cov, f"{len(idx)} frames x {key[0]}x{key[1]}"),
                              ("prune_compact", t_pr, b_pr, f"{n} Gaussians"),
-                             ("merge_list", t_mg, b_mg, f"{n} Gaussians, {rows} rows")):
+                             ("merge_list", t_mg, b_mg, f"{n} Gaussians, {rows} rows"),
+                             ("spatial_reorder", t_or, b_or, f"{n} Gaussians, {rows} rows")):
         out[name] = {"ms": t, "bound": "hbm", "achieved": b / (t * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, "work": unit}
         log(f"maintenance {name}: {t:.4f} ms, {out[name]['achieved']:.0f} GB/s ({out[name]['frac']:.2f} of HBM)")
@@ -487,7 +509,7 @@ def step_roofline(stage_ms, ms_step, n, sh3, slots_live, pairs, evals, pixels):
 
 
 def measure_workload(index, args, torch, steps, warmup, lat_reps, plain_steps, loss="l1", extras=True,
-                     precision="fp32"):
+                     precision="fp32", map_order="spatial"):
     """One workload end to end: the batched step captured in a graph and
     replayed (timed), per-view latency, per-kernel time, the blend count, the
     per-view plain launches, and the rooflines.  Returns (result dict,
@@ -505,6 +527,16 @@ def measure_workload(index, args, torch, steps, warmup, lat_reps, plain_steps, l
     V = len(cams)
     pose_only = [int(x) for x in w["pose_only"]]
     params = {k: torch.from_numpy(v).to(dev) for k, v in w["params"].items()}
+    order_desc = "given"
+    if map_order == "spatial":
+        # the order the map maintenance keeps (untimed here; timed with the
+        # maintenance)
+        from paper_2601_00705_amd import maintain
+        brick = args.brick or maintain.SPATIAL_BRICK
+        params = maintain.permute(params, maintain.spatial_order(params["mean"], brick))
+        torch.cuda.synchronize()
+        order_desc = f"spatial (Morton cells, brick {brick})"
+    log(f"map order: {order_desc}")
     poses = torch.from_numpy(w["poses"].astype(np.float32)).to(dev)
     target = target_images(w, params, poses, Config(sh_degree=w["sh_degree"]), Renderer, torch)
     tuned = None
@@ -658,7 +690,7 @@ def measure_workload(index, args, torch, steps, warmup, lat_reps, plain_steps, l
         f"HBM-only {step_roof['hbm_frac']:.3f}")
 
     res = {
-        "workload": w["name"], "gaussians": n, "views": V, "pixels": total_px,
+        "workload": w["name"], "gaussians": n, "views": V, "pixels": total_px, "map_order": order_desc,
         "tile": f"{cfg.tile_w}x{cfg.tile_h}", "batch": cfg.batch, "sh_degree": cfg.sh_degree,
         "ms_per_step": ms_step, "mpix_per_s": total_px / (ms_step * 1e-3) / 1e6,
         "ms_per_step_p10_p50_p90": [pct[10], pct[50], pct[90]],
@@ -725,7 +757,7 @@ def main():
 
     res, w, cfg, st, R, params, cap = measure_workload(
         args.config, args, torch, args.steps, args.warmup, max(100, args.steps),
-        0 if args.no_plain else args.steps, loss=args.loss, precision=args.precision)
+        0 if args.no_plain else args.steps, loss=args.loss, precision=args.precision, map_order=args.map_order)
     total_px = res["pixels"]
 
     # ---------------- tracking loss: its three kernels, HBM bound -----------
@@ -761,12 +793,26 @@ def main():
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
 
+    # ---------------- the same step on the generator's order ---------------
+    given = None
+    if args.map_order == "spatial" and not args.no_given:
+        gres, *_ = measure_workload(args.config, args, torch, args.steps, args.warmup, 0, 0, loss=args.loss,
+                                   extras=False, precision=args.precision, map_order="given")
+        given = {"ms_per_step": gres["ms_per_step"], "mpix_per_s": gres["mpix_per_s"],
+                 "spatial_speedup": gres["ms_per_step"] / res["ms_per_step"], "kernel_ms": gres["kernel_ms"]}
+        log(f"generator's order: {gres['ms_per_step']:.3f} ms/step (the spatial order is "
+            f"{given['spatial_speedup']:.3f}x faster)")
+        del gres
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+
     # ---------------- the 3M-Gaussian tracking-and-mapping batch ----------
     # (a compact second leg: 4 mapping views at 1920x1080 and 32 pose-only
     # solves at 640x480 in one graph, per-solve latency over 100 replays)
     second = None
     if args.config != 4 and not args.no_second:
-        second, *_ = measure_workload(4, args, torch, min(args.steps, 10), 3, 100, 3, loss="l1", extras=False)
+        second, *_ = measure_workload(4, args, torch, min(args.steps, 10), 3, 100, 3, loss="l1", extras=False,
+                                      map_order=args.map_order)
         torch.cuda.synchronize()
         torch.cuda.empty_cache()
 
@@ -785,7 +831,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": res["workload"], "gaussians": res["gaussians"], "views": res["views"],
                    "pixels": total_px, "tile": res["tile"], "batch": res["batch"], "sh_degree": res["sh_degree"],
-                   "mode": "batched-graph", "loss": args.loss, "deterministic": bool(args.deterministic)},
+                   "mode": "batched-graph", "loss": args.loss, "deterministic": bool(args.deterministic),
+                   "map_order": res["map_order"]},
         "autotune_ms": res["autotune_ms"],
         "ms_per_step_p10_p50_p90": res["ms_per_step_p10_p50_p90"],
         "blends_per_s": res["blends_per_s"],
@@ -806,6 +853,7 @@ def main():
         "maintenance": maint,
         "cpu_baseline": cpu,
         "mixed_precision": mixed,
+        "given_order": given,
         "track_map_3M": second,
     }
     print(json.dumps(out), flush=True)

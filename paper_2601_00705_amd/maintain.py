@@ -120,8 +120,9 @@ def keep_list(mask):
     return keep, kept
 
 
-# Gaussians per brick of the spatial order (see spatial_order)
-SPATIAL_BRICK = 128
+# Gaussians per brick of the spatial order (see spatial_order): one
+# projection wave's worth
+SPATIAL_BRICK = 64
 
 
 def spatial_order(mean, brick=SPATIAL_BRICK):
