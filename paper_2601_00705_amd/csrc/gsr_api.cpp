@@ -1155,9 +1155,9 @@ extern "C" gsr_status gsr_compact(int64_t n, int32_t rows, const float* src, con
 
 // ---- spatial storage order -------------------------------------------------
 
-// workspace carve-up of gsr_spatial_order: code[2], val[2], hist, box, each
-// on a 256-byte boundary
-static size_t order_layout(int64_t n, size_t off[6])
+// workspace carve-up of gsr_spatial_order: code[2], val[2], hist, box
+// partials, digit totals, each on a 256-byte boundary
+static size_t order_layout(int64_t n, size_t off[7])
 {
     const int64_t blocks = (n + GSR_RADIX_TILE - 1) / GSR_RADIX_TILE;
     size_t at = 0;
@@ -1168,14 +1168,15 @@ static size_t order_layout(int64_t n, size_t off[6])
     };
     for (int k = 0; k < 4; ++k) off[k] = take(sizeof(uint32_t) * (size_t)n);
     off[4] = take(sizeof(uint32_t) * 256 * (size_t)blocks);
-    off[5] = take(sizeof(uint32_t) * 8);
+    off[5] = take(sizeof(uint32_t) * 8 * GSR_BOX_BLOCKS);
+    off[6] = take(sizeof(uint32_t) * 256);
     return at;
 }
 
 extern "C" size_t gsr_spatial_order_workspace_bytes(int64_t n)
 {
     if (n < 1 || n > (1ll << 31) - 1) return 0;
-    size_t off[6];
+    size_t off[7];
     return order_layout(n, off);
 }
 
@@ -1204,7 +1205,7 @@ extern "C" gsr_status gsr_spatial_order(int64_t n, const float* mean, int32_t br
     if (n < 1 || n > (1ll << 31) - 1) return fail(GSR_EINVAL, "n must lie in [1, 2^31)");
     if (brick < 1) return fail(GSR_EINVAL, "brick must be at least 1");
     if (((uintptr_t)workspace & 255) != 0) return fail(GSR_EINVAL, "workspace not 256-byte aligned");
-    size_t off[6];
+    size_t off[7];
     const size_t need = order_layout(n, off);
     if (workspace_bytes < need) return fail(GSR_EINVAL, "workspace smaller than gsr_spatial_order_workspace_bytes(n)");
     const uintptr_t ws = (uintptr_t)workspace, ix = (uintptr_t)index, mn = (uintptr_t)mean;
@@ -1222,6 +1223,7 @@ extern "C" gsr_status gsr_spatial_order(int64_t n, const float* mean, int32_t br
     }
     a.hist = (uint32_t*)(base + off[4]);
     a.box = (uint32_t*)(base + off[5]);
+    a.tot = (uint32_t*)(base + off[6]);
     a.blocks = (int32_t)((n + GSR_RADIX_TILE - 1) / GSR_RADIX_TILE);
     a.brick = brick;
     a.full = n / brick;

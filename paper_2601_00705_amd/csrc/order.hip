@@ -6,17 +6,20 @@
 // waves whose Gaussians share visibility, and the binning chunks whose pairs
 // fall into few tiles; the brick interleave keeps the chunks' work even.
 //
-//   k_order_init    box accumulators to the identities of min and max
-//   k_order_box     least and greatest coordinates of the finite means
-//   k_order_codes   10-bit cubic cells over the box (FP64: the box's extent
-//                   rounded up to a power of two, so the scaling is exact),
-//                   their Morton code, 2^30 for a non-finite mean
+//   k_order_box     least and greatest coordinates of the finite means,
+//                   one partial box per block (min and max need no order)
+//   k_order_codes   the box from the partials, then 10-bit cubic cells over
+//                   it (FP64: the box's extent rounded up to a power of two,
+//                   so the scaling is exact), their Morton code, 2^30 for a
+//                   non-finite mean
 //   4 radix passes  stable LSD ranking of (code, index), 8 bits a pass:
 //     k_radix_hist    per-block digit counts, digit-major
-//     k_radix_scan    exclusive scan of the counts: each block's offsets
-//     k_radix_scatter each key at its digit's offset plus its rank among
-//                     the block's equal digits (wave ballots, then the
-//                     waves in order), so the pass is stable
+//     k_radix_scan    one block per digit: exclusive scan of the digit's
+//                     counts over the blocks, and the digit's total
+//     k_radix_scatter each key at its digit's start (a scan of the totals)
+//                     plus its block's offset plus its rank among the
+//                     block's equal digits (wave ballots, then the waves in
+//                     order), so the pass is stable
 //   k_order_bricks  position j B + k takes rank ((j P) mod F) B + k
 #include "order.h"
 
@@ -44,12 +47,40 @@ __device__ __forceinline__ uint32_t spread10(uint32_t x)
     return x;
 }
 
-__global__ void k_order_init(uint32_t* box)
+// block-wide min of lo[3] and max of hi[3] (256 threads); thread 0 ends
+// with the block's values
+__device__ __forceinline__ void block_box(uint32_t (&lo)[3], uint32_t (&hi)[3])
 {
-    if (threadIdx.x < 3) box[threadIdx.x] = 0xffffffffu;
-    else if (threadIdx.x < 6) box[threadIdx.x] = 0u;
+    __shared__ uint32_t part[4][6];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        for (int off = 32; off > 0; off >>= 1) {
+            lo[k] = min(lo[k], (uint32_t)__shfl_xor((int)lo[k], off, 64));
+            hi[k] = max(hi[k], (uint32_t)__shfl_xor((int)hi[k], off, 64));
+        }
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            part[w][k] = lo[k];
+            part[w][3 + k] = hi[k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int q = 1; q < 4; ++q) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = min(lo[k], part[q][k]);
+                hi[k] = max(hi[k], part[q][3 + k]);
+            }
+        }
+    }
 }
 
+// partial box of block b's stride of Gaussians at box[8 b .. 8 b + 6) (a
+// block without a finite mean leaves the identities 0xffffffff and 0)
 __global__ __launch_bounds__(256) void k_order_box(OrderArgs a)
 {
     uint32_t lo[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, hi[3] = {0u, 0u, 0u};
@@ -64,30 +95,44 @@ __global__ __launch_bounds__(256) void k_order_box(OrderArgs a)
             }
         }
     }
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        for (int off = 32; off > 0; off >>= 1) {
-            lo[k] = min(lo[k], (uint32_t)__shfl_xor((int)lo[k], off, 64));
-            hi[k] = max(hi[k], (uint32_t)__shfl_xor((int)hi[k], off, 64));
-        }
-    }
-    if ((threadIdx.x & 63) == 0) {
+    block_box(lo, hi);
+    if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            if (lo[k] != 0xffffffffu) atomicMin(&a.box[k], lo[k]);
-            if (hi[k] != 0u) atomicMax(&a.box[3 + k], hi[k]);
+            a.box[8 * blockIdx.x + k] = lo[k];
+            a.box[8 * blockIdx.x + 3 + k] = hi[k];
         }
     }
 }
 
 __global__ __launch_bounds__(256) void k_order_codes(OrderArgs a)
 {
+    __shared__ uint32_t bx[6];
+    {
+        uint32_t blo[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, bhi[3] = {0u, 0u, 0u};
+        for (int b = threadIdx.x; b < GSR_BOX_BLOCKS; b += blockDim.x) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                blo[k] = min(blo[k], a.box[8 * b + k]);
+                bhi[k] = max(bhi[k], a.box[8 * b + 3 + k]);
+            }
+        }
+        block_box(blo, bhi);
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                bx[k] = blo[k];
+                bx[3 + k] = bhi[k];
+            }
+        }
+        __syncthreads();
+    }
     double lo[3], w = 0.0;
-    bool any = a.box[0] != 0xffffffffu;
+    const bool any = bx[0] != 0xffffffffu;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        lo[k] = any ? (double)ord_float(a.box[k]) : 0.0;
-        const double hi = any ? (double)ord_float(a.box[3 + k]) : 0.0;
+        lo[k] = any ? (double)ord_float(bx[k]) : 0.0;
+        const double hi = any ? (double)ord_float(bx[3 + k]) : 0.0;
         w = fmax(w, hi - lo[k]);
     }
     // cells of side 2^e / 1024 with w = m 2^e, m in [0.5, 1): (x - lo) 2^(10 - e)
@@ -134,42 +179,58 @@ __global__ __launch_bounds__(256) void k_radix_hist(OrderArgs a, int src, int sh
     a.hist[(int64_t)tid * a.blocks + blockIdx.x] = h[tid];
 }
 
-// one block: exclusive scan of the [256][blocks] counts in place
-__global__ __launch_bounds__(1024) void k_radix_scan(OrderArgs a)
+// block d: exclusive scan of digit d's counts over the blocks, in place, and
+// the digit's total
+__global__ __launch_bounds__(256) void k_radix_scan(OrderArgs a)
 {
-    __shared__ uint32_t part[1024];
-    const int64_t m = (int64_t)256 * a.blocks;
-    const int64_t per = (m + 1023) / 1024;
-    const int64_t lo = (int64_t)threadIdx.x * per;
-    const int64_t hi = lo + per < m ? lo + per : m;
-    uint32_t s = 0u;
-    for (int64_t k = lo; k < hi; ++k) s += a.hist[k];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t x = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
-        __syncthreads();
-        part[threadIdx.x] += x;
-        __syncthreads();
+    __shared__ uint32_t wsum[4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t* row = a.hist + (int64_t)blockIdx.x * a.blocks;
+    const int per = (a.blocks + 255) / 256;
+    const int lo = min(tid * per, a.blocks), hi = min(lo + per, a.blocks);
+    uint32_t sum = 0u;
+    for (int k = lo; k < hi; ++k) sum += row[k];
+    uint32_t incl = sum;
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += y;
     }
-    uint32_t run = threadIdx.x ? part[threadIdx.x - 1] : 0u;
-    for (int64_t k = lo; k < hi; ++k) {
-        const uint32_t c = a.hist[k];
-        a.hist[k] = run;
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t run = incl - sum;
+    for (int k = 0; k < w; ++k) run += wsum[k];
+    for (int k = lo; k < hi; ++k) {
+        const uint32_t c = row[k];
+        row[k] = run;
         run += c;
     }
+    if (tid == 0) a.tot[blockIdx.x] = wsum[0] + wsum[1] + wsum[2] + wsum[3];
 }
 
-// Each key of block b goes to its digit's offset for b plus its rank among
-// the block's earlier keys of that digit.  The block takes its keys 256 at a
+// Each key of block b goes to its digit's start plus the digit's keys in
+// the earlier blocks plus its rank among the block's earlier keys of that
+// digit.  The block takes its keys 256 at a
 // time, in order; within a wave the keys of one digit are found by matching
 // the digit's 8 bits with ballots, and the waves' counts are added in wave
 // order, so that equal digits keep their input order.
 __global__ __launch_bounds__(256) void k_radix_scatter(OrderArgs a, int src, int shift)
 {
-    __shared__ uint32_t goff[256], run[256], wc[4][256];
+    __shared__ uint32_t goff[256], run[256], wc[4][256], wsum[4];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    goff[tid] = a.hist[(int64_t)tid * a.blocks + blockIdx.x];
+    {
+        // digit tid starts after the keys of the smaller digits
+        const uint32_t t = a.tot[tid];
+        uint32_t incl = t;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) wsum[w] = incl;
+        __syncthreads();
+        uint32_t start = incl - t;
+        for (int k = 0; k < w; ++k) start += wsum[k];
+        goff[tid] = start + a.hist[(int64_t)tid * a.blocks + blockIdx.x];
+    }
     run[tid] = 0u;
     const int64_t base = (int64_t)blockIdx.x * GSR_RADIX_TILE;
     const uint32_t* code_in = a.code[src];
@@ -227,13 +288,12 @@ hipError_t launch_spatial_order(const OrderArgs& a, hipStream_t s)
     int64_t grid = (a.n + 255) / 256;
     if (grid > 2048) grid = 2048;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(k_order_init, dim3(1), dim3(64), 0, s, a.box);
-    hipLaunchKernelGGL(k_order_box, dim3((unsigned)grid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_order_box, dim3(GSR_BOX_BLOCKS), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_order_codes, dim3((unsigned)grid), dim3(256), 0, s, a);
     int src = 0;
     for (int shift = 0; shift < 32; shift += GSR_RADIX_BITS) {
         hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)a.blocks), dim3(256), 0, s, a, src, shift);
-        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, s, a);
+        hipLaunchKernelGGL(k_radix_scan, dim3(256), dim3(256), 0, s, a);
         hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)a.blocks), dim3(256), 0, s, a, src, shift);
         src ^= 1;
     }
