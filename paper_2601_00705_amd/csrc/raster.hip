@@ -328,10 +328,20 @@ __device__ __forceinline__ void fwd_tile(const RasterArgs& a, const TileCtx<PPT>
 // either way.  Splitting costs each part the whole list's per-entry work,
 // so it pays only for the tail: where most tiles' lists are long (the
 // 3M-Gaussian mapping views) the threshold rises with the pair count.
+#ifndef GSR_FWD_SPLIT_MAX
+#define GSR_FWD_SPLIT_MAX 4   // parts of the longest tiles (twice the threshold or more)
+#endif
+#ifndef GSR_FWD_LONG_PRIO
+#define GSR_FWD_LONG_PRIO 2   // issue priority of the long tiles' waves (s_setprio, 0..3)
+#endif
+
 template <int PPT>
 struct FwdSplit {
     static constexpr int parts = PPT < GSR_FWD_SPLIT ? PPT : GSR_FWD_SPLIT;
     static constexpr int ppt = PPT / parts;
+    // tiles of twice the threshold or more: more parts, fewer pixels each
+    static constexpr int parts2 = PPT < GSR_FWD_SPLIT_MAX ? PPT : (GSR_FWD_SPLIT_MAX < parts ? parts : GSR_FWD_SPLIT_MAX);
+    static constexpr int ppt2 = PPT / parts2;
 };
 
 __device__ __forceinline__ uint32_t long_threshold(const RasterArgs& a)
@@ -367,21 +377,37 @@ __global__ __launch_bounds__(64) void k_raster_fwd(RasterArgs a)
 }
 
 // Persistent waves that take (long tile, part) items from a queue (zeroed
-// before the launch) until the K long tiles' parts are done.
+// before the launch) until the long tiles' parts are done.  The K2 tiles of
+// twice the threshold or more (the order's first) come in parts2 parts, the
+// others in parts; items go longest tile first.  The waves raise their issue
+// priority: each carries a whole list and ends the forward, while the short
+// tiles' waves beside them on the same SIMDs can wait a little.
 template <int PPT, int GSR_BATCH, bool COUNT, bool MIXED>
 __global__ __launch_bounds__(64) void k_raster_fwd_long(RasterArgs a, int total_tiles)
 {
-    constexpr int S = FwdSplit<PPT>::parts, Q = FwdSplit<PPT>::ppt;
+    using F = FwdSplit<PPT>;
+    constexpr int S = F::parts, Q = F::ppt, S2 = F::parts2, Q2 = F::ppt2;
     __shared__ LdsRec rec[GSR_BATCH];
-    const int items = long_tiles(a, total_tiles, long_threshold(a)) * S;
+    if (GSR_FWD_LONG_PRIO) __builtin_amdgcn_s_setprio(GSR_FWD_LONG_PRIO);
+    const uint32_t thr = long_threshold(a);
+    const int k2 = S2 > S ? long_tiles(a, total_tiles, 2u * thr) : 0;
+    const int items2 = k2 * S2;
+    const int items = items2 + (long_tiles(a, total_tiles, thr) - k2) * S;
     for (;;) {
         uint32_t item = 0u;
         if (threadIdx.x == 0) item = atomicAdd(a.fwd_queue, 1u);
         item = (uint32_t)__builtin_amdgcn_readfirstlane((int)item);
         if ((int)item >= items) break;
-        const int tile = (int)a.order[item / S];
-        const TileCtx<Q> c = tile_ctx_at<Q>(a, tile, (int)(item % S) * Q);
-        fwd_tile<Q, GSR_BATCH, COUNT, MIXED>(a, c, rec);
+        if ((int)item < items2) {
+            const int tile = (int)a.order[item / S2];
+            const TileCtx<Q2> c = tile_ctx_at<Q2>(a, tile, (int)(item % S2) * Q2);
+            fwd_tile<Q2, GSR_BATCH, COUNT, MIXED>(a, c, rec);
+        } else {
+            const uint32_t j = item - (uint32_t)items2;
+            const int tile = (int)a.order[k2 + (int)(j / S)];
+            const TileCtx<Q> c = tile_ctx_at<Q>(a, tile, (int)(j % S) * Q);
+            fwd_tile<Q, GSR_BATCH, COUNT, MIXED>(a, c, rec);
+        }
     }
 }
 
