@@ -20,6 +20,9 @@
 // are found with 8 ballots.
 #include "kernels.h"
 
+#ifndef GSR_SORT_SMALL_MAIN
+#define GSR_SORT_SMALL_MAIN 512  // small-class blocks also launched on the main stream (0: none)
+#endif
 
 namespace gsr {
 
@@ -427,6 +430,14 @@ hipError_t launch_seg_sort(const SegArgs& a, int total_tiles, int64_t capacity, 
                        dim3(GSR_SEG_SMALL_THREADS), 0, side, a, total_tiles);
     hipLaunchKernelGGL((k_seg_sort<GSR_SEG_THREADS, GSR_SEG_ITEMS, 1>), dim3((unsigned)total_tiles),
                        dim3(GSR_SEG_THREADS), 0, s, a, total_tiles);
+    // more persistent small-class blocks on `s` once the middle class is
+    // done: they take tiles from the same queue as those on `side`, so the
+    // stream that frees up first drains the short lists
+    if (GSR_SORT_SMALL_MAIN > 0) {
+        const unsigned g = (unsigned)(total_tiles < GSR_SORT_SMALL_MAIN ? total_tiles : GSR_SORT_SMALL_MAIN);
+        hipLaunchKernelGGL((k_seg_sort<GSR_SEG_SMALL_THREADS, GSR_SEG_SMALL_ITEMS, 0>), dim3(g),
+                           dim3(GSR_SEG_SMALL_THREADS), 0, s, a, total_tiles);
+    }
     e = hipGetLastError();
     if (e == hipSuccess) e = hipEventRecord(join, side);
     if (e == hipSuccess) e = hipStreamWaitEvent(s, join, 0);
