@@ -13,8 +13,9 @@
 // The arithmetic is double: near the near plane the Jacobians grow like
 // 1/z^2 and would amplify float rounding of the accumulated gradients (the
 // FP64 vector rate of the chip equals its unpacked FP32 rate, and this kernel
-// is a small part of the step).  Per view the block's 6 tangent partials are
-// reduced (transposed wave exchange, then LDS) into a per-block slot; a
+// is a small part of the step).  Per view each wave reduces its 6 tangent
+// partials (transposed wave exchange) into LDS; after the last view the
+// block sums its waves' partials into a per-block slot of each view; a
 // second kernel sums the slots in a fixed order, so the pose gradient is
 // deterministic given the accumulators.  Parameter gradients are summed over
 // the views not flagged pose-only and written once (overwrite).
@@ -39,7 +40,7 @@ template <int DEG>
 __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
 {
     typedef double T;
-    __shared__ double red[4][8];
+    __shared__ double red[GSR_MAX_VIEWS][4][6];  // per view and wave: the 6 tangent partials
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t n = a.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
@@ -191,7 +192,9 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
                 dSw[5] += M[2] * GM0[2] + M[5] * GM1[2];
             }
         }
-        // block reduction of the 6 tangent partials (uniform control flow)
+        // the wave's sums of the 6 tangent partials (uniform control flow),
+        // kept per view: the waves run through the views without waiting for
+        // each other
         xchg_d<4>(xi, lane, 32);
         xchg_d<2>(xi, lane, 16);
         xchg_d<1>(xi, lane, 8);
@@ -199,13 +202,14 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
         s += __shfl_xor(s, 4, 64);
         s += __shfl_xor(s, 2, 64);
         s += __shfl_xor(s, 1, 64);
-        if ((lane & 7) == 0) red[wv][lane >> 3] = s;
-        __syncthreads();
-        if (tid < 6) {
-            T t = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
-            a.xi_partial[((int64_t)v * a.blocks + blockIdx.x) * 6 + tid] = t;
-        }
-        __syncthreads();
+        if ((lane & 7) == 0 && (lane >> 3) < 6) red[v][wv][lane >> 3] = s;
+    }
+    // the block's partials of every view, the waves summed in a fixed order
+    __syncthreads();
+    for (int e = tid; e < a.views->n * 6; e += blockDim.x) {
+        const int v = e / 6, f = e - 6 * (e / 6);
+        const T t = red[v][0][f] + red[v][1][f] + red[v][2][f] + red[v][3][f];
+        a.xi_partial[((int64_t)v * a.blocks + blockIdx.x) * 6 + f] = t;
     }
     if (!live_thread || !a.d_mean) return;
 
@@ -258,7 +262,7 @@ template <int DEG>
 __global__ __launch_bounds__(256) void k_sh_bwd(ProjectBwdArgs a)
 {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    __shared__ double red[4][4];
+    __shared__ double red[GSR_MAX_VIEWS][4][3];  // per view and wave: the 3 rho partials
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int64_t n = a.n;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + tid;
@@ -315,19 +319,25 @@ __global__ __launch_bounds__(256) void k_sh_bwd(ProjectBwdArgs a)
                     for (int c = 0; c < 3; ++c) dcol[k][c] += gc[c] * Y[k];
             }
         }
-        // block sums of the three rho partials, fixed order (uniform control flow)
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            double t = xe[k];
-            for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-            if (lane == 0) red[wv][k] = t;
-        }
-        __syncthreads();
-        if (tid < 6) {
-            const double t = tid < 3 ? red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid] : 0.0;
-            a.xi_partial_sh[((int64_t)v * a.blocks + blockIdx.x) * 6 + tid] = t;
-        }
-        __syncthreads();
+        // the wave's sums of the three rho partials (a transposed exchange
+        // of four values, the fourth zero, then a sum over 16 lanes), kept
+        // per view (uniform control flow)
+        double x4[4] = {xe[0], xe[1], xe[2], 0.0};
+        xchg_d<2>(x4, lane, 32);
+        xchg_d<1>(x4, lane, 16);
+        double t = x4[0];
+        t += __shfl_xor(t, 8, 64);
+        t += __shfl_xor(t, 4, 64);
+        t += __shfl_xor(t, 2, 64);
+        t += __shfl_xor(t, 1, 64);
+        if ((lane & 15) == 0 && (lane >> 4) < 3) red[v][wv][lane >> 4] = t;
+    }
+    // the block's partials of every view, the waves summed in a fixed order
+    __syncthreads();
+    for (int e = tid; e < a.views->n * 6; e += blockDim.x) {
+        const int v = e / 6, f = e - 6 * (e / 6);
+        const double t = f < 3 ? red[v][0][f] + red[v][1][f] + red[v][2][f] + red[v][3][f] : 0.0;
+        a.xi_partial_sh[((int64_t)v * a.blocks + blockIdx.x) * 6 + f] = t;
     }
     if (!live_thread || !a.d_mean) return;
     for (int c = 0; c < 3; ++c) a.d_mean[c * n + i] += dm[c];
