@@ -76,11 +76,61 @@ def _reaching(params, ccams, poses, cfg):
 ])
 def test_fullsize_sampled_crops(index, views, crop):
     w = scenes.workload(index)
+    cams = w["cams"]
+    rng = np.random.default_rng(100 + index)
+    cw, ch = crop
+    origins = [(int(rng.integers(0, cams[v]["width"] - cw + 1)), int(rng.integers(0, cams[v]["height"] - ch + 1)))
+               for v in views]
+    _check_crops(index, w, views, origins, crop, "sampled")
+
+
+def _densest_tile(params, cam, pose, cfg):
+    """(tx, ty) of the tile that the most Gaussians' FP64 tile rectangles
+    (the oracle's projection) cover: where the longest lists are."""
+    r = oracle.project(params, cam, pose, oracle_cfg(cfg))
+    ntx = -(-cam["width"] // cfg.tile_w)
+    nty = -(-cam["height"] // cfg.tile_h)
+    ok = (r["valid"] > 0) & (r["tx1"] >= r["tx0"]) & (r["ty1"] >= r["ty0"])
+    acc = np.zeros((nty + 1, ntx + 1), np.int64)
+    x0, x1 = r["tx0"][ok].astype(int), r["tx1"][ok].astype(int) + 1
+    y0, y1 = r["ty0"][ok].astype(int), r["ty1"][ok].astype(int) + 1
+    np.add.at(acc, (y0, x0), 1)
+    np.add.at(acc, (y0, x1), -1)
+    np.add.at(acc, (y1, x0), -1)
+    np.add.at(acc, (y1, x1), 1)
+    cover = acc.cumsum(0).cumsum(1)[:nty, :ntx]
+    ty, tx = np.unravel_index(int(np.argmax(cover)), cover.shape)
+    return int(tx), int(ty), int(cover[ty, tx])
+
+
+def test_fullsize_crops_on_the_longest_lists():
+    """window-1M-10views, crops centred on the tile of each 1200x680 view
+    that the most Gaussians reach (found from the oracle's projection): the
+    longest lists, which the forward composites in parts (two or four, by
+    length) on its second stream."""
+    index, views, crop = 3, [4, 5, 6, 7], (96, 64)
+    w = scenes.workload(index)
+    cams, n = w["cams"], int(w["params"]["opacity_logit"].shape[0])
+    tuned = autotune.lookup(cams, n, w["sh_degree"])
+    tw, th, _ = tuned if tuned else (16, 16, 128)
+    cfg = Config(tile_w=tw, tile_h=th, sh_degree=w["sh_degree"])
+    cw, ch = crop
+    origins = []
+    for v in views:
+        tx, ty, cover = _densest_tile(w["params"], cams[v], w["poses"][v], cfg)
+        say(f"  view {v}: densest tile ({tx}, {ty}), {cover} rectangles cover it")
+        x0 = min(max(tx * tw + tw // 2 - cw // 2, 0), cams[v]["width"] - cw)
+        y0 = min(max(ty * th + th // 2 - ch // 2, 0), cams[v]["height"] - ch)
+        origins.append((int(x0), int(y0)))
+    _check_crops(index, w, views, origins, crop, "longest lists")
+
+
+def _check_crops(index, w, views, origins, crop, what):
     cams, n = w["cams"], int(w["params"]["opacity_logit"].shape[0])
     tuned = autotune.lookup(cams, n, w["sh_degree"])
     tw, th, batch = tuned if tuned else (16, 16, 128)
     cfg = Config(tile_w=tw, tile_h=th, batch=batch, sh_degree=w["sh_degree"])
-    say(f"[fullsize] {w['name']}: tile {tw}x{th}/{batch}, sampled views {views}, crop {crop}")
+    say(f"[fullsize] {w['name']}: tile {tw}x{th}/{batch}, {what}: views {views}, crop {crop}, origins {origins}")
     P = to_dev(w["params"])
     poses_d = torch.from_numpy(w["poses"]).cuda()
     R = Renderer(n, cams, cfg)
@@ -88,11 +138,8 @@ def test_fullsize_sampled_crops(index, views, crop):
     torch.cuda.synchronize()
     say(f"  pairs {R.pair_count()[0]}")
 
-    rng = np.random.default_rng(100 + index)
     cw, ch = crop
     hw = cw * ch
-    origins = [(int(rng.integers(0, cams[v]["width"] - cw + 1)), int(rng.integers(0, cams[v]["height"] - ch + 1)))
-               for v in views]
     ccams = [_crop_cam(cams[v], x0, y0, cw, ch) for v, (x0, y0) in zip(views, origins)]
     cposes = w["poses"][views]
     ids = _reaching(w["params"], ccams, cposes, cfg)
