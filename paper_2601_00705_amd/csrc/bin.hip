@@ -299,12 +299,22 @@ __global__ __launch_bounds__(256) void k_bin_list(BinArgs a)
     uint32_t pos = base_s + incl - cnt;
     for (int k = 0; k < w; ++k) pos += wsum[k];
     uint32_t* list = a.live + (int64_t)v * a.n;
+    // the wave writes its words' entries together, one word at a time: lane
+    // l keeps bit l of the word, so the set bits go out as one coalesced run
+    // (in index order, as a thread would write them)
+    const uint64_t below = (1ull << lane) - 1ull;
+    for (int j = 0; j < 64; ++j) {
+        uint32_t at = (uint32_t)__builtin_amdgcn_readlane((int)pos, j);
 #pragma unroll
-    for (int k = 0; k < GSR_LIST_WORDS; ++k) {
-        uint64_t b = m[k];
-        while (b) {
-            list[pos++] = (uint32_t)((w0 + k) * 64 + (__ffsll((long long)b) - 1));
-            b &= b - 1ull;
+        for (int k = 0; k < GSR_LIST_WORDS; ++k) {
+            const uint64_t word = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(m[k] >> 32), j) << 32) |
+                                  (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)m[k], j);
+            if (word == 0ull) continue;
+            if ((word >> lane) & 1ull) {
+                const int64_t wd = (int64_t)(blockIdx.x * 256 + w * 64 + j) * GSR_LIST_WORDS + k;
+                list[at + (uint32_t)__popcll(word & below)] = (uint32_t)(wd * 64 + lane);
+            }
+            at += (uint32_t)__popcll(word);
         }
     }
 }
