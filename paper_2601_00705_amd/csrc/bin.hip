@@ -22,7 +22,8 @@
 //                 with more than GSR_BIN_LDS_TILES tiles add straight into
 //                 the row)
 //   k_bin_colscan per tile: exclusive prefix of its column (the chunk's offset
-//                 inside the tile's segment) and the tile's total
+//                 inside the tile's segment) and the tile's total, four
+//                 waves to a column
 //   k_bin_tiles   exclusive scan of the tile totals: the tile ranges, the pair
 //                 count and the capacity flag
 //   k_bin_emit    the chunk's pairs, each at its tile's cursor (LDS atomics:
@@ -365,38 +366,62 @@ __global__ void k_zero_u32(uint32_t* p, int64_t count)
         p[i] = 0u;
 }
 
-// thread per global tile: the column of the tile in its view's count matrix
-// becomes the exclusive prefix over chunks; the total goes to ranges[].y.
-// 32 loads are in flight at a time, so that a long column takes few round
-// trips.
-__global__ __launch_bounds__(256) void k_bin_colscan(BinArgs a)
+// Column scan: a block takes 64 consecutive global tiles; its wave s takes
+// the s-th quarter of every tile's chunks (so a wave reads 64 adjacent
+// counters of one row at a time).  Each wave sums its quarter of the
+// column, the quarters' sums give each quarter its offset, and the wave
+// rewrites its quarter as the exclusive prefix over chunks; the column's
+// total goes to ranges[].y.  32 loads are in flight at a time.
+__device__ __forceinline__ uint32_t colscan_run(uint32_t* col, int64_t stride, int c0, int c1, bool write,
+                                                uint32_t run)
 {
     constexpr int K = 32;
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.total_tiles) return;
-    const int v = view_of_tile(a.views, g);
-    const ViewInfo& vw = a.views->v[v];
-    const int64_t tiles_v = (int64_t)vw.tiles_x * vw.tiles_y;
-    uint32_t* col = a.cnt + (int64_t)a.chunks * vw.tile_base + (g - vw.tile_base);
-    const int chunks_v = view_chunks(a, v);
-    uint32_t run = 0;
-    int c = 0;
-    for (; c + K <= chunks_v; c += K) {
+    int c = c0;
+    for (; c + K <= c1; c += K) {
         uint32_t x[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) x[k] = col[(int64_t)(c + k) * tiles_v];
+        for (int k = 0; k < K; ++k) x[k] = col[(int64_t)(c + k) * stride];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            col[(int64_t)(c + k) * tiles_v] = run;
+            if (write) col[(int64_t)(c + k) * stride] = run;
             run += x[k];
         }
     }
-    for (; c < chunks_v; ++c) {
-        const uint32_t x = col[(int64_t)c * tiles_v];
-        col[(int64_t)c * tiles_v] = run;
+    for (; c < c1; ++c) {
+        const uint32_t x = col[(int64_t)c * stride];
+        if (write) col[(int64_t)c * stride] = run;
         run += x;
     }
-    a.ranges[g] = make_uint2(0u, run);
+    return run;
+}
+
+__global__ __launch_bounds__(256) void k_bin_colscan(BinArgs a)
+{
+    __shared__ uint32_t part[4][64];
+    const int lt = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int g = blockIdx.x * 64 + lt;
+    const bool in = g < a.total_tiles;
+    uint32_t* col = nullptr;
+    int64_t stride = 0;
+    int c0 = 0, c1 = 0;
+    if (in) {
+        const int v = view_of_tile(a.views, g);
+        const ViewInfo& vw = a.views->v[v];
+        stride = (int64_t)vw.tiles_x * vw.tiles_y;
+        col = a.cnt + (int64_t)a.chunks * vw.tile_base + (g - vw.tile_base);
+        const int chunks_v = view_chunks(a, v);
+        const int per = (chunks_v + 3) / 4;
+        c0 = min(q * per, chunks_v);
+        c1 = min(c0 + per, chunks_v);
+    }
+    const uint32_t sum = in ? colscan_run(col, stride, c0, c1, false, 0u) : 0u;
+    part[q][lt] = sum;
+    __syncthreads();
+    uint32_t off = 0u;
+    for (int k = 0; k < q; ++k) off += part[k][lt];
+    if (!in) return;
+    colscan_run(col, stride, c0, c1, true, off);
+    if (q == 3) a.ranges[g] = make_uint2(0u, off + sum);
 }
 
 // one block: exclusive scan of the tile totals into the ranges; pair count
@@ -501,7 +526,7 @@ hipError_t launch_bin(const BinArgs& a, int max_tiles_view, hipStream_t s)
         hipLaunchKernelGGL(k_zero_u32, dim3(2048), dim3(256), 0, s, a.cnt, entries);
         hipLaunchKernelGGL(k_bin_count<false>, grid, dim3(256), 0, s, a);
     }
-    hipLaunchKernelGGL(k_bin_colscan, dim3((unsigned)((a.total_tiles + 255) / 256)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_bin_colscan, dim3((unsigned)((a.total_tiles + 63) / 64)), dim3(256), 0, s, a);
     hipLaunchKernelGGL(k_bin_tiles, dim3(1), dim3(1024), 0, s, a);
     if (lds) hipLaunchKernelGGL(k_bin_emit<true>, grid, dim3(256), dyn, s, a);
     else hipLaunchKernelGGL(k_bin_emit<false>, grid, dim3(256), 0, s, a);
