@@ -24,8 +24,8 @@
 //   k_bin_colscan per tile: exclusive prefix of its column (the chunk's offset
 //                 inside the tile's segment) and the tile's total, four
 //                 waves to a column
-//   k_bin_tiles   exclusive scan of the tile totals: the tile ranges, the pair
-//                 count and the capacity flag
+//   k_bin_tiles   the tile ranges from the column scan's per-block prefixes
+//                 and block sums, the pair count and the capacity flag
 //   k_bin_emit    the chunk's pairs, each at its tile's cursor (LDS atomics:
 //                 the order inside a chunk's group is arbitrary, and the
 //                 per-tile sort of the unique keys makes it exact)
@@ -419,41 +419,62 @@ __global__ __launch_bounds__(256) void k_bin_colscan(BinArgs a)
     __syncthreads();
     uint32_t off = 0u;
     for (int k = 0; k < q; ++k) off += part[k][lt];
-    if (!in) return;
-    colscan_run(col, stride, c0, c1, true, off);
-    if (q == 3) a.ranges[g] = make_uint2(0u, off + sum);
+    if (in) colscan_run(col, stride, c0, c1, true, off);
+    if (q == 3) {
+        // the last wave holds the 64 tiles' totals: their exclusive prefix
+        // within the block goes to ranges[].x, the block's pairs to
+        // tile_blocks (k_bin_tiles adds the earlier blocks')
+        const uint32_t total = off + sum;
+        unsigned long long incl = total;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long y = __shfl_up(incl, o, 64);
+            if (lt >= o) incl += y;
+        }
+        if (in) a.ranges[g] = make_uint2((uint32_t)(incl - total), total);
+        if (lt == 63) a.tile_blocks[blockIdx.x] = incl;
+    }
 }
 
-// one block: exclusive scan of the tile totals into the ranges; pair count
-// and capacity flag
-__global__ __launch_bounds__(1024) void k_bin_tiles(BinArgs a)
+// the tile ranges: each tile's start is the pairs of the earlier 64-tile
+// blocks plus its prefix within its block; the pair count and the capacity
+// flag come from the blocks' sum (every block forms it, so that all decide
+// the overflow alike)
+__global__ __launch_bounds__(256) void k_bin_tiles(BinArgs a)
 {
-    __shared__ unsigned long long part[1024];
-    const int nt = a.total_tiles;
-    const int per = (nt + 1023) / 1024;
-    const int lo = threadIdx.x * per;
-    unsigned long long s = 0;
-    for (int k = 0; k < per && lo + k < nt; ++k) s += a.ranges[lo + k].y;
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        unsigned long long x = threadIdx.x >= off ? part[threadIdx.x - off] : 0ull;
-        __syncthreads();
-        part[threadIdx.x] += x;
-        __syncthreads();
+    __shared__ unsigned long long red[2][4];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int nb = (a.total_tiles + 63) / 64;
+    const int b0 = (int)blockIdx.x * 4;
+    unsigned long long pre = 0ull, tot = 0ull;
+    for (int k = tid; k < nb; k += 256) {
+        const unsigned long long x = a.tile_blocks[k];
+        tot += x;
+        if (k < b0) pre += x;
     }
-    unsigned long long run = threadIdx.x ? part[threadIdx.x - 1] : 0ull;
-    const unsigned long long total = part[1023];
-    const bool over = total > a.counters->capacity;
-    for (int k = 0; k < per && lo + k < nt; ++k) {
-        const uint32_t c = a.ranges[lo + k].y;
+    for (int o = 32; o > 0; o >>= 1) {
+        pre += __shfl_xor(pre, o, 64);
+        tot += __shfl_xor(tot, o, 64);
+    }
+    if (lane == 0) {
+        red[0][w] = pre;
+        red[1][w] = tot;
+    }
+    __syncthreads();
+    pre = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    tot = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    const bool over = tot > a.counters->capacity;
+    const int g = (int)blockIdx.x * 256 + tid;
+    if (g < a.total_tiles) {
+        for (int k = b0; k < b0 + w; ++k) pre += a.tile_blocks[k];
+        const uint2 r = a.ranges[g];
+        const unsigned long long start = pre + r.x;
         // empty tiles get [0, 0); on overflow every range is empty, so that
         // no kernel reads past the capacity
-        a.ranges[lo + k] = (over || c == 0u) ? make_uint2(0u, 0u) : make_uint2((uint32_t)run, (uint32_t)(run + c));
-        run += c;
+        a.ranges[g] = (over || r.y == 0u) ? make_uint2(0u, 0u)
+                                          : make_uint2((uint32_t)start, (uint32_t)(start + r.y));
     }
-    if (threadIdx.x == 1023) {
-        a.counters->pairs = total;
+    if (blockIdx.x == 0 && tid == 0) {
+        a.counters->pairs = tot;
         a.counters->overflow = over ? 1u : 0u;
     }
 }
@@ -527,7 +548,7 @@ hipError_t launch_bin(const BinArgs& a, int max_tiles_view, hipStream_t s)
         hipLaunchKernelGGL(k_bin_count<false>, grid, dim3(256), 0, s, a);
     }
     hipLaunchKernelGGL(k_bin_colscan, dim3((unsigned)((a.total_tiles + 63) / 64)), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_bin_tiles, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_bin_tiles, dim3((unsigned)((a.total_tiles + 255) / 256)), dim3(256), 0, s, a);
     if (lds) hipLaunchKernelGGL(k_bin_emit<true>, grid, dim3(256), dyn, s, a);
     else hipLaunchKernelGGL(k_bin_emit<false>, grid, dim3(256), 0, s, a);
     return hipGetLastError();

@@ -49,7 +49,7 @@ struct gsr_plan {
     size_t off_counters = 0, off_views = 0, off_geom = 0, off_conic = 0, off_rgbd = 0, off_qthr = 0, off_grad2d = 0, off_acc = 0;
     size_t off_stage = 0;
     size_t off_keys = 0, off_vals = 0, off_seg = 0, off_ranges = 0, off_cnt = 0;
-    size_t off_live = 0, off_live_count = 0, off_live_mask = 0, off_fwd_queue = 0;
+    size_t off_live = 0, off_live_count = 0, off_live_mask = 0, off_fwd_queue = 0, off_tile_blocks = 0;
     int64_t mask_words = 0;     // ceil(n / 64): liveness ballot words per view
     size_t off_xip = 0, off_xip_sh = 0, off_order = 0, off_buckets = 0, off_track = 0, off_map = 0, off_stamps = 0, off_left = 0, total = 0;
     char* ws = nullptr;
@@ -267,6 +267,7 @@ extern "C" gsr_status gsr_plan_create(int64_t n, int32_t n_views, const gsr_came
     p->off_live = take(sizeof(uint32_t) * S);
 
     p->off_live_count = take(sizeof(uint32_t) * GSR_LIVE_STRIDE * GSR_MAX_VIEWS);  // one 256-byte line per view
+    p->off_tile_blocks = take(sizeof(unsigned long long) * (size_t)((p->total_tiles + 63) / 64 + 1));
     p->off_xip = take(sizeof(double) * 6 * (size_t)n_views * p->bwd_blocks);
     p->off_xip_sh = take(sizeof(double) * 6 * (size_t)n_views * p->bwd_blocks);
     p->off_track = take(sizeof(double) * GSR_TRACK_SLOTS * GSR_TRACK_BLOCKS * (size_t)n_views);
@@ -436,6 +437,7 @@ extern "C" gsr_status gsr_bin(gsr_plan* plan, void* stream)
     b.mask_words = plan->mask_words;
     b.live = at<uint32_t>(plan, plan->off_live);
     b.live_count = at<uint32_t>(plan, plan->off_live_count);
+    b.tile_blocks = at<unsigned long long>(plan, plan->off_tile_blocks);
     b.counters = at<Counters>(plan, plan->off_counters);
     b.ranges = at<uint2>(plan, plan->off_ranges);
     b.seg = at<unsigned long long>(plan, plan->off_seg);

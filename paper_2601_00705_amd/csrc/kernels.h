@@ -41,6 +41,7 @@ struct BinArgs {
     Counters* counters;
     uint2* ranges;             // [total_tiles]: [first, last + 1) of each tile's pairs
     unsigned long long* seg;   // [capacity]: (depth bits << 32 | Gaussian index), grouped by tile
+    unsigned long long* tile_blocks;  // [ceil(total_tiles / 64)]: pairs of each run of 64 tiles
 };
 
 struct SegArgs {
