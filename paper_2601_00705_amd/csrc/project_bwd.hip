@@ -348,21 +348,24 @@ __global__ __launch_bounds__(256) void k_sh_bwd(ProjectBwdArgs a)
 }
 
 // sum of the per-block tangent partials (and those of the SH chain, when
-// given), fixed order: one block per view
-__global__ __launch_bounds__(256) void k_xi_reduce(const double* partial, const double* partial_sh, int blocks,
-                                                   float* d_xi)
+// given), fixed order: one 1,024-thread block per view (a view's partials
+// number one per 256 Gaussians, so the loads of many threads hide each
+// other's latency)
+#define GSR_XI_THREADS 1024
+__global__ __launch_bounds__(GSR_XI_THREADS) void k_xi_reduce(const double* partial, const double* partial_sh,
+                                                              int blocks, float* d_xi)
 {
-    __shared__ double red[6][256];
+    __shared__ double red[6][GSR_XI_THREADS];
     const int v = blockIdx.x, tid = threadIdx.x;
     double s[6] = {0, 0, 0, 0, 0, 0};
-    for (int b = tid; b < blocks; b += 256)
+    for (int b = tid; b < blocks; b += GSR_XI_THREADS)
         for (int k = 0; k < 6; ++k) {
             s[k] += partial[((int64_t)v * blocks + b) * 6 + k];
             if (partial_sh) s[k] += partial_sh[((int64_t)v * blocks + b) * 6 + k];
         }
     for (int k = 0; k < 6; ++k) red[k][tid] = s[k];
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
+    for (int off = GSR_XI_THREADS / 2; off > 0; off >>= 1) {
         if (tid < off)
             for (int k = 0; k < 6; ++k) red[k][tid] += red[k][tid + off];
         __syncthreads();
@@ -391,7 +394,7 @@ hipError_t launch_project_bwd(const ProjectBwdArgs& a, int sh_degree, float* d_x
         }
     }
     if (d_xi && n_views > 0)
-        hipLaunchKernelGGL(k_xi_reduce, dim3(n_views), dim3(256), 0, s, a.xi_partial,
+        hipLaunchKernelGGL(k_xi_reduce, dim3(n_views), dim3(GSR_XI_THREADS), 0, s, a.xi_partial,
                            sh_degree >= 1 ? a.xi_partial_sh : (const double*)nullptr, a.blocks, d_xi);
     return hipGetLastError();
 }
