@@ -307,7 +307,7 @@ struct FrameArgs {
 #ifndef GSR_FWD_SPLIT
 #define GSR_FWD_SPLIT 2             // parts of a long tile (at most the pixels per lane)
 #endif
-#define GSR_FWD_LONG_WAVES 1024     // persistent waves of the long tiles' parts
+#define GSR_FWD_LONG_WAVES 2048     // persistent waves of the long tiles' parts (two per SIMD)
 
 hipError_t launch_project(const ProjectArgs& a, int sh_degree, hipStream_t s);
 // pair counting, offsets, emission into per-tile segments; max_tiles_view is
