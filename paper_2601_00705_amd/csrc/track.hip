@@ -16,8 +16,10 @@
 // b = mean(I) - mean(I_hat).
 //
 // Three launches over a (GSR_TRACK_BLOCKS, views) grid, each block striding
-// over its view's pixels, all arithmetic in double (the kernels are bound by
-// memory traffic, not by arithmetic):
+// over its view's pixels, all arithmetic in double.  Double division and
+// square root take tens of instructions at half the float rate, so the
+// per-view reciprocals are formed once and the pixel's column and row are
+// stepped, not divided out:
 //   k_track_sums   sum I_hat, sum I, sum I_hat^2, sum I_hat I per block;
 //   k_track_signs  (g, b) from those partials, then per block
 //                  sum w |r|, sum w sign(r), sum w sign(r) I_hat;
@@ -131,6 +133,31 @@ __device__ __forceinline__ double grad_norm_at(const float* img, int W, int H, i
     return sqrt(s);
 }
 
+// A thread's pixels i = i0, i0 + S, ... (S = GSR_TRACK_BLOCKS x threads) of
+// a W-wide view with their column and row, advanced without a division.
+struct PixelWalk {
+    int i, x, y, dx, dy;
+    __device__ PixelWalk(int W)
+    {
+        constexpr int S = GSR_TRACK_BLOCKS * GSR_TRACK_THREADS;
+        i = (int)blockIdx.x * GSR_TRACK_THREADS + (int)threadIdx.x;
+        y = i / W;
+        x = i - y * W;
+        dy = S / W;
+        dx = S - dy * W;
+    }
+    __device__ void next(int W)
+    {
+        i += GSR_TRACK_BLOCKS * GSR_TRACK_THREADS;
+        x += dx;
+        y += dy;
+        if (x >= W) {
+            x -= W;
+            ++y;
+        }
+    }
+};
+
 __device__ __forceinline__ double clip01(double z) { return fmin(fmax(z, 0.0), 1.0); }
 
 __device__ __forceinline__ double sgn(double r) { return r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0); }
@@ -173,12 +200,12 @@ __global__ __launch_bounds__(GSR_TRACK_THREADS) void k_track_signs(TrackArgs a)
     const float* Ih = a.rgb + 3 * (int64_t)vw.pix_base;
     const float* I = a.target + 3 * (int64_t)vw.pix_base;
     const float* T = a.T_final + vw.pix_base;
+    const double inv_tg = 1.0 / a.tau_grad;
     double q[3] = {0.0, 0.0, 0.0};  // sum w |r|, sum w s, sum w s I_hat
-    for (int i = (int)blockIdx.x * GSR_TRACK_THREADS + (int)threadIdx.x; i < (int)hw;
-         i += GSR_TRACK_BLOCKS * GSR_TRACK_THREADS) {
-        const int y = i / W, x = i - y * W;
+    for (PixelWalk p(W); p.i < (int)hw; p.next(W)) {
+        const int i = p.i;
         const double w = clip01((1.0 - (double)T[i]) / a.tau_alpha) *
-                         clip01(grad_norm_at(I, W, H, x, y) / a.tau_grad);
+                         clip01(grad_norm_at(I, W, H, p.x, p.y) * inv_tg);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             const double xh = Ih[c * hw + i];
@@ -215,16 +242,18 @@ __global__ __launch_bounds__(GSR_TRACK_THREADS) void k_track_grad(TrackArgs a)
     // dg/dI_hat_k = (N I_k - Sy - 2 g (N I_hat_k - Sx)) / D,
     // db/dI_hat_k = -(Sx dg/dI_hat_k + g) / N (g fixed at 1 when degenerate)
     const double Q0 = q[1], Q1 = q[2];
+    const double inv_N = 1.0 / e.N, inv_D = e.degenerate ? 0.0 : 1.0 / e.D, inv_tg = 1.0 / a.tau_grad;
+    const double inv_ta = 1.0 / a.tau_alpha;
     const float* Ih = a.rgb + 3 * (int64_t)vw.pix_base;
     const float* I = a.target + 3 * (int64_t)vw.pix_base;
     const float* T = a.T_final + vw.pix_base;
     float* dI = a.dL_drgb + 3 * (int64_t)vw.pix_base;
     float* dT = a.dL_dT ? a.dL_dT + vw.pix_base : nullptr;
-    for (int i = (int)blockIdx.x * GSR_TRACK_THREADS + (int)threadIdx.x; i < (int)hw;
-         i += GSR_TRACK_BLOCKS * GSR_TRACK_THREADS) {
-        const int y = i / W, x = i - y * W;
+    for (PixelWalk p(W); p.i < (int)hw; p.next(W)) {
+        const int i = p.i;
+        // the one division kept: za decides whether dL/dT_final is zero
         const double za = (1.0 - (double)T[i]) / a.tau_alpha;
-        const double wg = clip01(grad_norm_at(I, W, H, x, y) / a.tau_grad);
+        const double wg = clip01(grad_norm_at(I, W, H, p.x, p.y) * inv_tg);
         const double w = clip01(za) * wg;
         double abs_sum = 0.0;
 #pragma unroll
@@ -233,16 +262,16 @@ __global__ __launch_bounds__(GSR_TRACK_THREADS) void k_track_grad(TrackArgs a)
             const double r = yo - (e.g * xh + e.b);
             double d = -w * sgn(r) * e.g;
             if (e.degenerate) {
-                d += Q0 / e.N;
+                d += Q0 * inv_N;
             } else {
-                const double dg = (e.N * yo - e.Sy - 2.0 * e.g * (e.N * xh - e.Sx)) / e.D;
-                const double db = -(e.Sx * dg + e.g) / e.N;
+                const double dg = (e.N * yo - e.Sy - 2.0 * e.g * (e.N * xh - e.Sx)) * inv_D;
+                const double db = -(e.Sx * dg + e.g) * inv_N;
                 d -= Q1 * dg + Q0 * db;
             }
             dI[c * hw + i] = (float)d;
             abs_sum += fabs(r);
         }
-        if (dT) dT[i] = (float)((za > 0.0 && za < 1.0) ? -(wg / a.tau_alpha) * abs_sum : 0.0);
+        if (dT) dT[i] = (float)((za > 0.0 && za < 1.0) ? -(wg * inv_ta) * abs_sum : 0.0);
     }
 }
 
