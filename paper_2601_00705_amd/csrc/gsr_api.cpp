@@ -644,7 +644,7 @@ extern "C" gsr_status gsr_project_bwd(gsr_plan* plan, const gsr_gaussians* g, co
     b.poses = poses;
     b.views = at<ViewTable>(plan, plan->off_views);
     b.cfg = plan->dcfg;
-    b.geom = at<float4>(plan, plan->off_geom);
+    b.live_mask = at<uint64_t>(plan, plan->off_live_mask);
     b.grad2d = at<double>(plan, plan->off_grad2d);
     unsigned long long mask = 0;
     for (int v = 0; v < plan->V; ++v)

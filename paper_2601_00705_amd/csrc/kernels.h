@@ -96,7 +96,7 @@ struct ProjectBwdArgs {
     const float* poses;
     const ViewTable* views;
     DevCfg cfg;
-    const float4* geom;
+    const uint64_t* live_mask;      // [mask_words][views]: the projection's liveness ballots
     const double* grad2d;
     unsigned long long pose_only;   // bit v set: view v updates the pose only
     float *d_mean, *d_quat, *d_log_scale, *d_opacity_logit, *d_colour;

@@ -1,8 +1,10 @@
 // project_bwd.hip -- from screen-space gradients to Gaussian parameters and
 // the SE(3) pose tangent.
 //
-// One thread per Gaussian loops over the views, recomputing the forward
-// projection (project_math.h, in double) and applying the chain rule of
+// One thread per Gaussian loops over the views; for each slot the
+// projection marked live (its liveness ballots: one 64-bit word per wave
+// and view, read through the scalar cache) it recomputes the forward
+// projection (project_math.h, in double) and applies the chain rule of
 // Eq. (proj):
 //   conic (A, B, C) = Sigma_I^-1:   dSigma_I = -Sigma_I^-1 dconic Sigma_I^-1
 //   Sigma_I = M Sigma_W M^T, M = J R:  dSigma_W = M^T G M, dM = 2 G M Sigma_W
@@ -67,7 +69,12 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
 #pragma unroll
     for (int k = 0; k < K; ++k) dcol[k][0] = dcol[k][1] = dcol[k][2] = 0;
 
-    const float inv_tw = 1.0f / (float)a.cfg.tile_w, inv_th = 1.0f / (float)a.cfg.tile_h;
+    // the wave's liveness words, one per view (bit = lane): the projection's
+    // ballots of the same slots; a wave wholly past n (the grid's last block,
+    // or n = 0) has none and reads none
+    const int64_t wword = __builtin_amdgcn_readfirstlane((int)(i >> 6));
+    const bool wave_in = wword < (n + 63) / 64;
+    const uint64_t* lm = a.live_mask + (wave_in ? wword : 0) * a.views->n;
     for (int v = 0; v < a.views->n; ++v) {
         const ViewInfo vw = a.views->v[v];
         const float* pose = a.poses + 12 * v;
@@ -76,12 +83,8 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
         const bool params = ((a.pose_only >> v) & 1ull) == 0ull;
         T xi[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         int64_t slot = (int64_t)v * n + i;
-        bool live = false;
-        if (live_thread) {
-            float4 gm = a.geom[slot];
-            int x0, y0, x1, y1;
-            live = tile_rect(gm.x, gm.y, gm.z, gm.w, inv_tw, inv_th, vw.tiles_x, vw.tiles_y, x0, y0, x1, y1);
-        }
+        const uint64_t word = wave_in ? lm[v] : 0ull;
+        bool live = live_thread && ((word >> lane) & 1ull);
         Projected<T> p;
         if (live) {
             project_gaussian<T>(g, pose, vw, a.cfg, p);
@@ -277,19 +280,20 @@ __global__ __launch_bounds__(256) void k_sh_bwd(ProjectBwdArgs a)
         }
     if (live_thread)
         for (int c = 0; c < 3; ++c) mw[c] = a.mean[c * n + i];
-    const float inv_tw = 1.0f / (float)a.cfg.tile_w, inv_th = 1.0f / (float)a.cfg.tile_h;
+    // the wave's liveness words, one per view (bit = lane): the projection's
+    // ballots of the same slots; a wave wholly past n (the grid's last block,
+    // or n = 0) has none and reads none
+    const int64_t wword = __builtin_amdgcn_readfirstlane((int)(i >> 6));
+    const bool wave_in = wword < (n + 63) / 64;
+    const uint64_t* lm = a.live_mask + (wave_in ? wword : 0) * a.views->n;
     for (int v = 0; v < a.views->n; ++v) {
         const ViewInfo vw = a.views->v[v];
         const float* pose = a.poses + 12 * v;
         const bool params = ((a.pose_only >> v) & 1ull) == 0ull;
         double xe[3] = {0.0, 0.0, 0.0};
         const int64_t slot = (int64_t)v * n + i;
-        bool live = false;
-        if (live_thread) {
-            const float4 gm = a.geom[slot];
-            int x0, y0, x1, y1;
-            live = tile_rect(gm.x, gm.y, gm.z, gm.w, inv_tw, inv_th, vw.tiles_x, vw.tiles_y, x0, y0, x1, y1);
-        }
+        const uint64_t word = wave_in ? lm[v] : 0ull;
+        const bool live = live_thread && ((word >> lane) & 1ull);
         if (live) {
             const double* g2 = a.grad2d + GSR_G2 * slot;
             const float gc[3] = {(float)g2[6], (float)g2[7], (float)g2[8]};
