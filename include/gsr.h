@@ -143,7 +143,7 @@ typedef struct {
 /* Byte offsets of the planes inside a bound workspace. */
 typedef struct {
     size_t counters;  /* struct { uint64 pairs; uint32 overflow; ... } */
-    size_t geom;      /* float4 [V*n]: (u, v, rx, ry); rx < 0 = culled */
+    size_t geom;      /* float4 [V*n]: (u, v, rx, ry); rx < 0 or NaN = culled */
     size_t conic_o;   /* float4 [V*n]: (A, B, C, o), A = (Sigma_I^-1)_00 ... */
     size_t rgb_d;     /* float4 [V*n]: (r, g, b, depth) */
     size_t qthr;      /* float [V*n]: binning level of d^T conic d per slot */
@@ -198,8 +198,12 @@ gsr_status gsr_plan_get_info(const gsr_plan *plan, gsr_plan_info *out);
 
 /* Eq. (proj): projects every Gaussian into every view (poses: device
  * [n_views][12]), in double precision.  Writes the float geom / conic_o /
- * rgb_d / qthr records (correctly rounded) and the staging records, and zeroes
- * the screen-space gradient accumulators of the live slots. */
+ * rgb_d / qthr records (correctly rounded) and the staging records of the
+ * live slots, and zeroes their screen-space gradient accumulators.  A culled
+ * slot's geom holds a culled marker (rx and ry -1, or NaN for a slot not
+ * live at any projection since the workspace was bound); the projection
+ * writes it only where live_mask shows the slot live before, so a caller
+ * that writes geom itself keeps live_mask set for those slots. */
 gsr_status gsr_project(gsr_plan *plan, const gsr_gaussians *g, const float *poses, void *stream);
 
 /* Builds the depth-ordered per-tile lists from the geom / conic_o / qthr /

@@ -308,6 +308,10 @@ extern "C" gsr_status gsr_plan_bind(gsr_plan* plan, void* workspace, size_t byte
         e = hipMemsetAsync(plan->ws + plan->off_left, 0, sizeof(unsigned long long) * (size_t)plan->V, s);
     if (e == hipSuccess)
         e = hipMemsetAsync(plan->ws + plan->off_live_mask, 0, sizeof(uint64_t) * (size_t)plan->V * plan->mask_words, s);
+    // every slot starts culled (NaN geometry): the projection rewrites the
+    // culled marker only where a slot was live at the previous projection
+    if (e == hipSuccess)
+        e = hipMemsetAsync(plan->ws + plan->off_geom, 0xff, sizeof(float4) * (size_t)plan->V * (size_t)plan->n, s);
     if (e == hipSuccess) {
         plan->identity_order.resize((size_t)plan->total_tiles);
         for (int32_t t = 0; t < plan->total_tiles; ++t) plan->identity_order[(size_t)t] = (uint32_t)t;

@@ -6,7 +6,9 @@
 // device memory so that a captured graph sees pose updates.  For every live
 // slot (view, Gaussian) the kernel writes geom/conic_o/rgb_d/qthr (float),
 // the staging record (double centre and conic) and zeroes the slot's
-// screen-space gradient accumulators; a culled slot gets rx = ry = -1.  A
+// screen-space gradient accumulators; a culled slot keeps or gets a culled
+// marker (rx = ry = -1 where it was live before, NaN from the plan's set-up
+// otherwise).  A
 // slot is live when its tile rectangle is not empty; per view, each wave
 // also stores the ballot of its slots' liveness (word [w][v], bit k:
 // Gaussian 64 w + k; lanes past n have left and add 0), from which the
@@ -51,6 +53,10 @@ __global__ __launch_bounds__(256, 3) void k_project(ProjectArgs a)
             for (int c = 0; c < 3; ++c) col[k][c] = a.colour[(k * 3 + c) * n + i];
     }
     const ViewTable* vt = a.views;
+    // the wave's ballot words of the previous projection (a bound plan
+    // starts with all clear and every slot culled); read before this
+    // projection's words replace them below
+    const uint64_t* old_words = a.live_mask + wave_word * vt->n;
     const float inv_tw = 1.0f / (float)a.cfg.tile_w, inv_th = 1.0f / (float)a.cfg.tile_h;
     const float o = (float)g.o;
     for (int v = 0; v < vt->n; ++v) {
@@ -64,7 +70,9 @@ __global__ __launch_bounds__(256, 3) void k_project(ProjectArgs a)
         bool live = p.valid && tile_rect(u, vv, rx, ry, inv_tw, inv_th, vw.tiles_x, vw.tiles_y, x0, y0, x1, y1);
         const uint64_t ballot = __ballot(live);
         if (!live) {
-            a.geom[slot] = make_float4(0.0f, 0.0f, -1.0f, -1.0f);
+            // a slot culled at the previous projection too (its old ballot
+            // bit clear) already holds a culled marker
+            if ((old_words[v] >> lane) & 1ull) a.geom[slot] = make_float4(0.0f, 0.0f, -1.0f, -1.0f);
         } else {
             float rgb[3];
             if (DEG < 0) {
