@@ -374,6 +374,46 @@ def test_forward_deterministic_and_batched_equals_plain():
         assert torch.equal(tparts[v].reshape(-1), T_v), v
 
 
+def _slot_liveness(rec, n, V):
+    """[V * n] booleans from the ballot words (slot v * n + i)."""
+    lm = rec["live_mask"].cpu().numpy().view(np.uint64)  # [words][V]
+    idx = np.arange(n)
+    bits = (lm[idx >> 6, :] >> (idx & 63).astype(np.uint64)[:, None]) & np.uint64(1)
+    return bits.astype(bool).T.reshape(-1)
+
+
+def test_projection_reuse_keeps_culled_markers():
+    """A second projection with other poses on the same plan.  Slots culled
+    at both projections keep their marker without a store, slots live only
+    at the first get one: afterwards a slot's geometry reads live (rx >= 0)
+    exactly where its ballot bit is set, the live records equal those of a
+    freshly bound plan, and so do the image, T_final and n_contrib."""
+    params, _ = scenes.room_scene(57, 20_000, 5_000, avoid=[np.zeros(3)])
+    rng = np.random.default_rng(11)
+    poses_a, _ = scenes.random_room_poses(rng, 3)
+    poses_b, _ = scenes.random_room_poses(rng, 3)
+    cams = [scenes.camera(160, 120, 131.25), scenes.camera(300, 170, 150.0), scenes.camera(80, 60, 65.6)]
+    n, V = params["opacity_logit"].shape[0], len(cams)
+    cfg = Config()
+    say("[projection reuse]")
+    R, P, _, _, _, _, _ = _gpu_fwd(params, cams, np.stack(poses_a), cfg)
+    live_a = _slot_liveness(R.records(), n, V)
+    pb = torch.from_numpy(np.ascontiguousarray(np.stack(poses_b), dtype=np.float32)).cuda()
+    rgb, T, nc, _ = R.forward_all(P, pb)
+    torch.cuda.synchronize()
+    rec = R.records()
+    live_b = _slot_liveness(rec, n, V)
+    R2, _, _, rgb2, T2, nc2, _ = _gpu_fwd(params, cams, np.stack(poses_b), cfg)
+    geom = rec["geom"].cpu().numpy()
+    say(f"  live then culled {int((live_a & ~live_b).sum())}, culled twice {int((~live_a & ~live_b).sum())}, "
+        f"live {int(live_b.sum())} of {V * n}")
+    assert (live_a & ~live_b).any() and (~live_a & ~live_b).any()
+    assert np.array_equal(geom[:, 2] >= 0, live_b)
+    assert np.array_equal(_slot_liveness(R2.records(), n, V), live_b)
+    assert np.array_equal(geom[live_b], R2.records()["geom"].cpu().numpy()[live_b])
+    assert torch.equal(rgb, rgb2) and torch.equal(T, T2) and torch.equal(nc, nc2)
+
+
 def test_forward_identical_across_batches_and_tiles():
     """Binning is conservative and every pixel composites the same
     depth-ordered entries whatever the tile shape or the LDS batch.  For one
