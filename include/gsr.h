@@ -186,7 +186,8 @@ void gsr_plan_destroy(gsr_plan *plan);
 size_t gsr_plan_workspace_bytes(const gsr_plan *plan);
 
 /* Binds a caller-owned device workspace of at least gsr_plan_workspace_bytes
- * bytes, uploads the view table and capacity into it, and synchronises
+ * bytes, uploads the view table and capacity into it, marks every slot
+ * culled (NaN geom, clear live_mask; empty tile ranges), and synchronises
  * `stream` once.  The workspace must stay alive while the plan is used.  The
  * first bind also creates the plan's own second stream (non-blocking,
  * default priority) and two ordering events, released by
