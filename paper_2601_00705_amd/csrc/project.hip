@@ -42,6 +42,7 @@ __global__ __launch_bounds__(256, 3) void k_project(ProjectArgs a)
     // record below is the correctly rounded value of the exact projection
     Activated<double> g;
     activate<double>(a.mean, a.quat, a.log_scale, a.opacity_logit, n, i, g);
+    extent_factor<double>(g, a.cfg);
     constexpr int K = DEG < 0 ? 1 : (DEG + 1) * (DEG + 1);
     float col[K][3];
     if (DEG < 0) {
@@ -59,6 +60,10 @@ __global__ __launch_bounds__(256, 3) void k_project(ProjectArgs a)
     const uint64_t* old_words = a.live_mask + wave_word * vt->n;
     const float inv_tw = 1.0f / (float)a.cfg.tile_w, inv_th = 1.0f / (float)a.cfg.tile_h;
     const float o = (float)g.o;
+    // binning level of d^T conic d, the same in every view: the alpha_min
+    // ellipse 2 ln(o / alpha_min) widened by 5% + 0.01 so that rounding
+    // never drops a tile the compositing would reach
+    const float qthr = a.cfg.alpha_min > 0.0f ? 1.05f * (2.0f * logf(o / a.cfg.alpha_min)) + 0.01f : INFINITY;
     for (int v = 0; v < vt->n; ++v) {
         const ViewInfo vw = vt->v[v];
         const float* pose = a.poses + 12 * v;
@@ -131,10 +136,7 @@ __global__ __launch_bounds__(256, 3) void k_project(ProjectArgs a)
     #pragma unroll
                 for (int k = 0; k < GSR_G2 * GSR_FIX_LIMBS / 2; ++k) z[k] = make_ulonglong2(0ull, 0ull);
             }
-            // binning level of d^T conic d: the alpha_min ellipse 2 ln(o / alpha_min)
-            // widened by 5% + 0.01 so that rounding never drops a tile the
-            // compositing would reach
-            a.qthr[slot] = a.cfg.alpha_min > 0.0f ? 1.05f * (2.0f * logf(o / a.cfg.alpha_min)) + 0.01f : INFINITY;
+            a.qthr[slot] = qthr;
         }
         // after the slot's stores, so that no register of a load in flight
         // is taken for it

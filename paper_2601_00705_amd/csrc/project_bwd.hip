@@ -57,6 +57,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjectBwdArgs a)
     T col[K][3];
     if (live_thread) {
         activate<T>(a.mean, a.quat, a.log_scale, a.opacity_logit, n, i, g);
+        extent_factor<T>(g, a.cfg);
         if (DEG == 0) {
 #pragma unroll
             for (int k = 0; k < K; ++k)

@@ -91,8 +91,16 @@ struct Activated {
     T s2[3];          // squared scales
     T Sw[6];          // Sigma_W: xx, xy, xz, yy, yz, zz
     T o;              // opacity
+    T kext;           // sqrt(2 ln(o / alpha_min)): the extent factor, the same in every view
     bool ok;
 };
+
+// the Gaussian's extent factor, once for all views
+template <class T>
+__device__ __forceinline__ void extent_factor(Activated<T>& g, const DevCfg& cfg)
+{
+    g.kext = (cfg.alpha_min > 0.0f && g.o >= (T)cfg.alpha_min) ? sqrt((T)2 * log(g.o / (T)cfg.alpha_min)) : (T)0;
+}
 
 template <class T>
 __device__ __forceinline__ void activate(const float* mean, const float* quat, const float* log_scale,
@@ -204,7 +212,7 @@ __device__ __forceinline__ void project_gaussian(const Activated<T>& g, const fl
     // extent: alpha >= alpha_min inside d^T Sigma_I^-1 d <= 2 ln(o / alpha_min)
     if (cfg.alpha_min > 0.0f) {
         if (!(g.o >= (T)cfg.alpha_min)) return;
-        T k = sqrt((T)2 * log(g.o / (T)cfg.alpha_min));
+        const T k = g.kext;
         p.rx = k * sqrt(p.a);
         p.ry = k * sqrt(p.c);
     } else {
